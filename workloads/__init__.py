@@ -1,0 +1,137 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+Both the oracle side and the GPU side of every test draw their inputs from
+here.  Nothing in this module computes any part of LSRN: it only builds
+matrices and right-hand sides whose spectra and sparsity the tests need.
+
+Recipes (Sec. 6 of the paper uses random dense matrices with a chosen
+condition number, rank-deficient variants, and sprandn-like sparse matrices):
+
+* dense_problem: A = U diag(sigma) V^T, U (m x k) and V (n x k) Haar-distributed
+  with orthonormal columns (QR of a Gaussian with the signs of diag(R) fixed,
+  Mezzadri 2007), sigma log-spaced from 1 down to sigma_min, k = rank.
+* rhs: b = A x_gen + noise * N(0,1), or b ~ N(0,1).
+* sparse_problem: CSR with `per_row` distinct uniform-random columns per row plus
+  `n_dense` chosen columns each filled with probability `fill`, values N(0,1),
+  column indices sorted in each row.
+* Under-determined inputs are the transpose construction: the row-major array
+  of a tall matrix read as the column-major storage of its transpose.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+
+def haar_columns(rng: np.random.Generator, rows: int, cols: int) -> np.ndarray:
+    """rows x cols with orthonormal columns, Haar-distributed."""
+    Z = rng.standard_normal((rows, cols))
+    Q, R = np.linalg.qr(Z)
+    Q *= np.sign(np.diag(R))
+    return Q
+
+
+def logspaced(k: int, smin: float) -> np.ndarray:
+    if k == 1:
+        return np.ones(1)
+    return 10.0 ** np.linspace(0.0, np.log10(smin), k)
+
+
+@dataclass
+class Dense:
+    A: np.ndarray        # m x n, row-major
+    U: np.ndarray        # m x k
+    sigma: np.ndarray    # k
+    V: np.ndarray        # n x k
+
+
+def dense_problem(m: int, n: int, rank: int | None = None, smin: float = 1e-6,
+                  seed: int = 0) -> Dense:
+    """A = U diag(sigma) V^T (m x n) with the given rank (default min(m, n))."""
+    k = min(m, n) if rank is None else rank
+    rng = np.random.default_rng(seed)
+    U = haar_columns(rng, m, k)
+    V = haar_columns(rng, n, k)
+    sigma = logspaced(k, smin)
+    A = (U * sigma) @ V.T
+    return Dense(np.ascontiguousarray(A), U, sigma, V)
+
+
+def rhs_model(A: np.ndarray, noise: float, seed: int):
+    """b = A x_gen + noise * N(0,1); returns (b, x_gen)."""
+    rng = np.random.default_rng(seed + 7919)
+    xg = rng.standard_normal(A.shape[1])
+    b = A @ xg + noise * rng.standard_normal(A.shape[0])
+    return b, xg
+
+
+def rhs_gauss(m: int, seed: int) -> np.ndarray:
+    return np.random.default_rng(seed + 104729).standard_normal(m)
+
+
+@dataclass
+class Sparse:
+    m: int
+    n: int
+    rowptr: np.ndarray   # int64, m+1
+    colind: np.ndarray   # int32, nnz (sorted within each row)
+    val: np.ndarray      # float64, nnz
+
+    @property
+    def nnz(self) -> int:
+        return int(self.rowptr[-1])
+
+    def to_dense(self) -> np.ndarray:
+        A = np.zeros((self.m, self.n))
+        rows = np.repeat(np.arange(self.m), np.diff(self.rowptr))
+        A[rows, self.colind] = self.val
+        return A
+
+
+def sparse_problem(m: int, n: int, per_row: int = 20, n_dense: int = 10,
+                   fill: float = 0.1, seed: int = 0, chunk: int = 1 << 18) -> Sparse:
+    """CSR m x n: per_row distinct uniform columns per row, plus n_dense fixed
+    columns each present with probability `fill` (a collision keeps one
+    entry); values N(0,1)."""
+    rng = np.random.default_rng(seed)
+    dense_cols = np.sort(rng.choice(n, size=min(n_dense, n), replace=False)).astype(np.int64)
+    counts = np.zeros(m, np.int64)
+    cols_parts, val_parts = [], []
+    for r0 in range(0, m, chunk):
+        r1 = min(m, r0 + chunk)
+        rows = r1 - r0
+        # distinct columns per row: sample with replacement and redraw duplicates
+        c = rng.integers(0, n, size=(rows, per_row), dtype=np.int64)
+        c.sort(axis=1)
+        dup = np.zeros_like(c, dtype=bool)
+        dup[:, 1:] = c[:, 1:] == c[:, :-1]
+        while dup.any():
+            c[dup] = rng.integers(0, n, size=int(dup.sum()), dtype=np.int64)
+            c.sort(axis=1)
+            dup[:] = False
+            dup[:, 1:] = c[:, 1:] == c[:, :-1]
+        hit = rng.random((rows, dense_cols.size)) < fill
+        full = np.concatenate([c, np.where(hit, dense_cols[None, :], -1)], axis=1)
+        full.sort(axis=1)
+        keep = full >= 0
+        keep[:, 1:] &= full[:, 1:] != full[:, :-1]
+        cnt = keep.sum(axis=1)
+        counts[r0:r1] = cnt
+        cols_parts.append(full[keep].astype(np.int32))
+        val_parts.append(rng.standard_normal(int(cnt.sum())))
+    rowptr = np.zeros(m + 1, np.int64)
+    np.cumsum(counts, out=rowptr[1:])
+    return Sparse(m, n, rowptr, np.concatenate(cols_parts), np.concatenate(val_parts))
+
+
+# The five workloads the build is measured on (sizes of the dense, rank-
+# deficient, sparse, precision and serving cases).  Each entry is what the
+# generator needs; solver settings live with the tests and the benchmark.
+WORKLOADS = {
+    "dense_2000x100": dict(m=2000, n=100, rank=100, smin=1e-6, noise=1e-3, seed=11),
+    "rankdef_200000x2000": dict(m=200_000, n=2000, rank=1800, smin=1e-6, seed=12),
+    "sparse_2000000x20000": dict(m=2_000_000, n=20_000, per_row=20, n_dense=10, fill=0.1,
+                                 lam=1e-3, seed=13),
+    "dense_1000000x4000": dict(m=1_000_000, n=4000, rank=4000, smin=1e-8, noise=1e-6, seed=14),
+}
