@@ -1,0 +1,172 @@
+/*
+ * lsrn.h -- C ABI of the MI355X (gfx950) LSRN library, liblsrn.so.
+ *
+ * LSRN (Meng, Saunders, Mahoney, arXiv:1109.5981) computes the min-length
+ * least-squares solution x = A^+ b of a strongly over- or under-determined,
+ * possibly rank-deficient A (Sec. 1, eq. for x*), optionally with Tikhonov
+ * regularisation W = lambda I (Sec. 5):
+ *   1. s = ceil(gamma * min(m, n))                         (Alg. 1/2 step 1)
+ *   2. G: s x m (tall) or n x s (fat) standard normal, generated on the fly
+ *      from Philox4x32-10 counters and never stored       (step 2)
+ *   3. sketch A~ = G A (tall) or A G (fat)                (step 3)
+ *   4. economy SVD of A~, rank r                           (step 4)
+ *   5. N = V~ Sigma~^{-1} (tall) or M = U~ Sigma~^{-1} (fat)  (step 5)
+ *   6. LSQR or the Chebyshev semi-iteration (Alg. 3) on A N or M^T A
+ *   7. x = N y (tall) or x (fat)                          (step 7)
+ *
+ * Conventions for every entry point below:
+ *   - All array arguments are DEVICE pointers (hipMalloc'd or equivalent) on
+ *     the current HIP device, owned by the caller.  The library never frees
+ *     or keeps caller memory beyond the call (a plan keeps its own copies).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is ordered on that stream.  Calls that return sizes or ranks to
+ *     the host synchronise the stream before returning.
+ *   - Workspace is allocated by the library with hipMalloc and freed before
+ *     the call returns (plans keep theirs until lsrn_plan_destroy).
+ *   - No exception crosses the ABI.  On failure the return code says what
+ *     went wrong and lsrn_last_error() (per thread) holds a message.
+ *   - Dense A is FP64 with leading dimension lda >= (columns of the stored
+ *     layout).  LSRN_ROW_MAJOR: A[i][j] = A[i*lda + j];
+ *     LSRN_COL_MAJOR: A[i][j] = A[j*lda + i].  Tall problems (m >= n) run
+ *     from row-major storage and fat ones (m < n) from column-major storage
+ *     without copying A; the other two combinations are transposed once
+ *     into workspace.
+ */
+#ifndef LSRN_H
+#define LSRN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LSRN_OK = 0,
+    LSRN_E_INVALID = 1,       /* bad size, pointer or option                */
+    LSRN_E_NOMEM = 2,         /* device allocation failed                   */
+    LSRN_E_HIP = 3,           /* a HIP runtime call failed                  */
+    LSRN_E_NOT_CONVERGED = 4, /* LSQR hit max_iter; x holds the last iterate */
+    LSRN_E_UNSUPPORTED = 5    /* e.g. Tikhonov on an under-determined A     */
+} lsrn_status;
+
+typedef enum { LSRN_LSQR = 0, LSRN_CHEBYSHEV = 1 } lsrn_method;
+typedef enum { LSRN_ROW_MAJOR = 0, LSRN_COL_MAJOR = 1 } lsrn_layout;
+
+typedef struct lsrn_options {
+    double gamma;      /* oversampling factor gamma > 1 (Alg. 1 step 1); 2     */
+    double lambda;     /* Tikhonov weight, W = lambda I (Sec. 5); 0            */
+    double tol;        /* LSQR atol = btol, or the epsilon of Alg. 3; 1e-14    */
+    double rcond;      /* rank cutoff relative to sigma_1; <= 0 selects
+                          max(s, d) * 2^-52 (d = min(m, n))                     */
+    double t_margin;   /* margin t of Lemma 3 in the Chebyshev bounds
+                          sigma_U = 1/(sqrt s - sqrt r - t),
+                          sigma_L = 1/(sqrt s + sqrt r + t) (Theorem 3); 1     */
+    double refine_tol; /* relative accuracy asked of each refinement
+                          correction; 1e-6                                      */
+    uint64_t seed;     /* Philox key of G; 0                                   */
+    int64_t max_iter;  /* LSQR iteration cap; <= 0 selects the Alg. 3 count
+                          for the same bounds plus 10                           */
+    int32_t method;    /* lsrn_method; LSRN_LSQR                               */
+    int32_t refine;    /* number of refinement steps whose residuals are
+                          formed in double-double arithmetic; 0                 */
+    int32_t reserved[4];
+} lsrn_options;
+
+typedef struct lsrn_info {
+    int64_t s;              /* sketch size ceil(gamma d)                         */
+    int64_t d;              /* min(m, n) of the (augmented) problem              */
+    int64_t rank;           /* r, numerical rank of the sketch                   */
+    int64_t iters;          /* LSQR / Chebyshev iterations of the main solve     */
+    int64_t refine_steps;   /* refinement steps taken                            */
+    int64_t refine_iters;   /* inner iterations summed over refinement steps     */
+    int64_t sweeps;         /* Jacobi sweeps of the sketch SVD                   */
+    int32_t tall;           /* 1: Alg. 1 (m >= n), 0: Alg. 2                     */
+    int32_t converged;      /* stopping rule met (always 1 for Chebyshev)        */
+    double sigma_l, sigma_u;/* Chebyshev bounds used (0 when r is too large)     */
+    double sigma_max;       /* largest singular value of the sketch              */
+    double sigma_min_kept;  /* sigma_r of the sketch                             */
+    double t_sketch_ms;     /* RNG + sketch GEMM                                 */
+    double t_svd_ms;        /* QR + Jacobi + cutoff + N                          */
+    double t_iter_ms;       /* iterations incl. x = N y                          */
+    double t_refine_ms;     /* refinement                                        */
+    double t_total_ms;
+} lsrn_info;
+
+/* Fill *opt with the defaults listed above. */
+void lsrn_default_options(lsrn_options *opt);
+
+/* Short text for a status code (static storage). */
+const char *lsrn_status_string(lsrn_status st);
+
+/* Message describing the last failure of a call made on this thread. */
+const char *lsrn_last_error(void);
+
+/*
+ * Min-length solution x (length n) of min ||A x - b||_2 for dense FP64 A
+ * (m x n) -- Alg. 1 when m >= n (or when lambda > 0), Alg. 2 when m < n;
+ * Tikhonov-regularised (Sec. 5, W = lambda I) when opt->lambda > 0, which
+ * requires m >= n (LSRN_E_UNSUPPORTED otherwise).
+ * b: length m.  x: length n, overwritten.  opt may be NULL (defaults).
+ * info may be NULL.  Errors: LSRN_E_INVALID for m, n <= 0, NULL pointers,
+ * gamma <= 1, tol <= 0, lambda < 0, lda too small, bad layout or method.
+ */
+lsrn_status lsrn_solve_dense(int64_t m, int64_t n, const double *A, int64_t lda,
+                             int32_t layout, const double *b, double *x,
+                             const lsrn_options *opt, lsrn_info *info, void *stream);
+
+/* Bytes of device workspace lsrn_solve_dense allocates for these sizes
+ * (used for HBM admission by callers that batch solves). */
+size_t lsrn_workspace_bytes(int64_t m, int64_t n, int32_t layout, const lsrn_options *opt);
+
+/* ------------------------------------------------------------------------
+ * Step-level entry points.  Each runs one step of the path in the same
+ * kernels lsrn_solve_dense uses, so that every step can be checked alone.
+ * ---------------------------------------------------------------------- */
+
+/* Philox4x32-10 words (Salmon et al., SC'11) behind G:
+ * out[((r * nq) + j) * 4 + w] = word w of the block with counter
+ * (q_lo, q_hi, row_lo, row_hi), q = q0 + j, row = row0 + r, and key
+ * (seed_lo, seed_hi).  out: nrows * nq * 4 uint32. */
+lsrn_status lsrn_philox_words(uint64_t seed, int64_t row0, int64_t nrows, int64_t q0,
+                              int64_t nq, uint32_t *out, void *stream);
+
+/* Entries of G: out[r * ncols + c] = G(row0 + r, col0 + c), where block q
+ * = col / 4 gives words w0..w3 and Box-Muller maps (w0, w1) to columns
+ * 4q, 4q+1 and (w2, w3) to 4q+2, 4q+3 with u = (w + 1/2) 2^-32,
+ * g = sqrt(-2 ln u0) (cos 2 pi u1, sin 2 pi u1). */
+lsrn_status lsrn_gauss_fill(uint64_t seed, int64_t row0, int64_t nrows, int64_t col0,
+                            int64_t ncols, double *out, void *stream);
+
+/* Sketch X = G T (Alg. 1/2 step 3) with T the tall view of A: T = A
+ * (m x n, plus the rows lambda I when lambda > 0) if m >= n, else T = A^T.
+ * X is s x d (d = n if tall else m), written COLUMN-MAJOR: X[i][j] at
+ * X[j * s + i].  G(i, k) as in lsrn_gauss_fill. */
+lsrn_status lsrn_sketch_dense(int64_t m, int64_t n, const double *A, int64_t lda,
+                              int32_t layout, double lambda, int64_t s, uint64_t seed,
+                              double *X, void *stream);
+
+/* Steps 4-5 on a sketch X (s x d, column-major, s >= d): Householder QR,
+ * one-sided Jacobi on R^T, rank r = #{sigma_i > rcond sigma_1} (rcond <= 0
+ * as in lsrn_options), P = V_r Sigma_r^{-1} written row-major d x r with
+ * leading dimension d (P must hold d * d doubles).  sigma (length d)
+ * receives the singular values in descending order.  *rank and *sweeps
+ * are host pointers (sweeps may be NULL).  Synchronises the stream. */
+lsrn_status lsrn_precond(int64_t s, int64_t d, const double *X, double rcond, double *sigma,
+                         double *P, int64_t *rank, int64_t *sweeps, void *stream);
+
+/* Step 6-7 with a given preconditioner: P (d x r, row-major, leading
+ * dimension ldp >= r) is N (tall) or M (fat) for A as in lsrn_solve_dense;
+ * s is the sketch size the Chebyshev bounds use.  Runs LSQR or Chebyshev
+ * (opt->method), opt->refine refinement steps, and writes x.  info->iters
+ * etc. are filled. */
+lsrn_status lsrn_iterate_dense(int64_t m, int64_t n, const double *A, int64_t lda,
+                               int32_t layout, const double *b, const double *P,
+                               int64_t ldp, int64_t r, int64_t s, double *x,
+                               const lsrn_options *opt, lsrn_info *info, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LSRN_H */

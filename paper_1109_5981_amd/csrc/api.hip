@@ -1,0 +1,335 @@
+// api.hip -- the extern "C" entry points declared in include/lsrn.h.
+#include <cfloat>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <exception>
+#include <new>
+#include <string>
+
+#include "internal.hpp"
+
+namespace lsrn {
+
+static thread_local std::string g_last_error;
+
+void fail(lsrn_status st, const std::string &msg) { throw Error{st, msg}; }
+
+void hip_check(hipError_t e, const char *what) {
+    if (e == hipSuccess) return;
+    if (e == hipErrorOutOfMemory) throw Error{LSRN_E_NOMEM, std::string(what) + ": out of device memory"};
+    throw Error{LSRN_E_HIP, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+void DevBuf::alloc(size_t bytes) {
+    release();
+    if (bytes == 0) return;
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error{LSRN_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
+                                      hipGetErrorString(e)};
+    }
+    p_ = p;
+    n_ = bytes;
+}
+
+void DevBuf::release() {
+    if (p_) (void)hipFree(p_);
+    p_ = nullptr;
+    n_ = 0;
+}
+
+int device_cus() {
+    static int cus = 0;
+    if (!cus) {
+        // A host without a device (size queries only) plans for 256 CUs.
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+            (void)hipGetLastError();
+            return 256;
+        }
+        cus = v > 0 ? v : 256;
+    }
+    return cus;
+}
+
+StageTimer::StageTimer(hipStream_t s) : s_(s) {}
+StageTimer::~StageTimer() {
+    for (int i = 0; i < n_; ++i) (void)hipEventDestroy(ev_[i]);
+}
+void StageTimer::mark() {
+    if (n_ >= 16) return;
+    LSRN_HIP(hipEventCreate(&ev_[n_]));
+    LSRN_HIP(hipEventRecord(ev_[n_], s_));
+    ++n_;
+}
+double StageTimer::elapsed_ms(int i, int j) {
+    if (i >= n_ || j >= n_) return 0.0;
+    LSRN_HIP(hipEventSynchronize(ev_[j]));
+    float ms = 0.f;
+    LSRN_HIP(hipEventElapsedTime(&ms, ev_[i], ev_[j]));
+    return ms;
+}
+
+namespace {
+
+lsrn_options defaults() {
+    lsrn_options o;
+    std::memset(&o, 0, sizeof(o));
+    o.gamma = 2.0;
+    o.lambda = 0.0;
+    o.tol = 1e-14;
+    o.rcond = 0.0;
+    o.t_margin = 1.0;
+    o.refine_tol = 1e-6;
+    o.seed = 0;
+    o.max_iter = 0;
+    o.method = LSRN_LSQR;
+    o.refine = 0;
+    return o;
+}
+
+void check_options(const lsrn_options &o) {
+    LSRN_REQUIRE(o.gamma > 1.0 && std::isfinite(o.gamma), "gamma must be > 1");
+    LSRN_REQUIRE(o.tol > 0.0 && o.tol < 1.0, "tol must lie in (0, 1)");
+    LSRN_REQUIRE(o.lambda >= 0.0 && std::isfinite(o.lambda), "lambda must be >= 0");
+    LSRN_REQUIRE(o.method == LSRN_LSQR || o.method == LSRN_CHEBYSHEV, "unknown method");
+    LSRN_REQUIRE(o.refine >= 0 && o.refine <= 100, "refine must lie in [0, 100]");
+    LSRN_REQUIRE(o.refine_tol > 0.0 && o.refine_tol < 1.0, "refine_tol must lie in (0, 1)");
+    LSRN_REQUIRE(std::isfinite(o.t_margin) && o.t_margin >= 0.0, "t_margin must be >= 0");
+}
+
+// The tall view T of A (row-major, K x d): A itself for tall row-major or
+// fat column-major storage, otherwise a transposed copy in `buf`.
+struct TallView {
+    bool tall;
+    int64_t K, d;
+    const double *T;
+    int64_t ldt;
+    DevBuf buf;
+};
+
+void make_view(TallView &v, int64_t m, int64_t n, const double *A, int64_t lda, int32_t layout,
+               double lambda, hipStream_t st) {
+    LSRN_REQUIRE(layout == LSRN_ROW_MAJOR || layout == LSRN_COL_MAJOR, "unknown layout");
+    LSRN_REQUIRE(lda >= (layout == LSRN_ROW_MAJOR ? n : m), "lda too small for the layout");
+    if (lambda > 0.0 && m < n)
+        fail(LSRN_E_UNSUPPORTED, "Tikhonov regularisation needs m >= n (under-determined form not provided)");
+    v.tall = m >= n;
+    v.K = v.tall ? m : n;
+    v.d = v.tall ? n : m;
+    if ((v.tall && layout == LSRN_ROW_MAJOR) || (!v.tall && layout == LSRN_COL_MAJOR)) {
+        v.T = A;
+        v.ldt = lda;
+        return;
+    }
+    // tall column-major: stored array is A^T (n x m, ld lda) -> T = A (m x n)
+    // fat row-major: stored array is A (m x n, ld lda) -> T = A^T (n x m)
+    const int64_t rows = v.tall ? n : m, cols = v.tall ? m : n;
+    v.buf.alloc((size_t)rows * (size_t)cols * sizeof(double));
+    transpose(rows, cols, A, lda, v.buf.as<double>(), st);
+    v.T = v.buf.as<double>();
+    v.ldt = rows;
+}
+
+lsrn_status report(const Error &e) {
+    g_last_error = e.message;
+    return e.status;
+}
+
+#define LSRN_API_BEGIN try {
+#define LSRN_API_END                                                   \
+    }                                                                  \
+    catch (const ::lsrn::Error &e) { return report(e); }               \
+    catch (const std::bad_alloc &) {                                   \
+        g_last_error = "host allocation failed";                       \
+        return LSRN_E_NOMEM;                                           \
+    }                                                                  \
+    catch (const std::exception &e) {                                  \
+        g_last_error = e.what();                                       \
+        return LSRN_E_INVALID;                                         \
+    }                                                                  \
+    return LSRN_OK;
+
+}  // namespace
+}  // namespace lsrn
+
+using namespace lsrn;
+
+extern "C" {
+
+void lsrn_default_options(lsrn_options *opt) {
+    if (opt) *opt = defaults();
+}
+
+const char *lsrn_status_string(lsrn_status st) {
+    switch (st) {
+        case LSRN_OK: return "ok";
+        case LSRN_E_INVALID: return "invalid argument";
+        case LSRN_E_NOMEM: return "out of device memory";
+        case LSRN_E_HIP: return "HIP runtime error";
+        case LSRN_E_NOT_CONVERGED: return "not converged";
+        case LSRN_E_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char *lsrn_last_error(void) { return g_last_error.c_str(); }
+
+lsrn_status lsrn_philox_words(uint64_t seed, int64_t row0, int64_t nrows, int64_t q0, int64_t nq,
+                              uint32_t *out, void *stream) {
+    LSRN_API_BEGIN
+    LSRN_REQUIRE(nrows >= 0 && nq >= 0 && row0 >= 0 && q0 >= 0, "negative size or offset");
+    LSRN_REQUIRE(out || nrows * nq == 0, "out is NULL");
+    launch_philox_words(seed, row0, nrows, q0, nq, out, (hipStream_t)stream);
+    LSRN_API_END
+}
+
+lsrn_status lsrn_gauss_fill(uint64_t seed, int64_t row0, int64_t nrows, int64_t col0, int64_t ncols,
+                            double *out, void *stream) {
+    LSRN_API_BEGIN
+    LSRN_REQUIRE(nrows >= 0 && ncols >= 0 && row0 >= 0 && col0 >= 0, "negative size or offset");
+    LSRN_REQUIRE(out || nrows * ncols == 0, "out is NULL");
+    launch_gauss_fill(seed, row0, nrows, col0, ncols, out, (hipStream_t)stream);
+    LSRN_API_END
+}
+
+lsrn_status lsrn_sketch_dense(int64_t m, int64_t n, const double *A, int64_t lda, int32_t layout,
+                              double lambda, int64_t s, uint64_t seed, double *X, void *stream) {
+    LSRN_API_BEGIN
+    LSRN_REQUIRE(m > 0 && n > 0 && s > 0, "sizes must be positive");
+    LSRN_REQUIRE(A && X, "NULL pointer");
+    LSRN_REQUIRE(lambda >= 0.0, "lambda must be >= 0");
+    hipStream_t st = (hipStream_t)stream;
+    TallView v;
+    make_view(v, m, n, A, lda, layout, lambda, st);
+    sketch_rows(v.K, v.d, v.T, v.ldt, v.tall ? lambda : 0.0, s, seed, X, st);
+    LSRN_HIP(hipStreamSynchronize(st));
+    LSRN_API_END
+}
+
+lsrn_status lsrn_precond(int64_t s, int64_t d, const double *X, double rcond, double *sigma,
+                         double *P, int64_t *rank, int64_t *sweeps, void *stream) {
+    LSRN_API_BEGIN
+    LSRN_REQUIRE(d > 0 && s >= d, "need s >= d > 0");
+    LSRN_REQUIRE(X && sigma && P && rank, "NULL pointer");
+    hipStream_t st = (hipStream_t)stream;
+    DevBuf work((size_t)s * (size_t)d * sizeof(double));
+    LSRN_HIP(hipMemcpyAsync(work.as<double>(), X, (size_t)s * (size_t)d * sizeof(double),
+                            hipMemcpyDeviceToDevice, st));
+    PrecondResult pr = precond(s, d, work.as<double>(), rcond, sigma, P, st);
+    *rank = pr.rank;
+    if (sweeps) *sweeps = pr.sweeps;
+    LSRN_API_END
+}
+
+lsrn_status lsrn_iterate_dense(int64_t m, int64_t n, const double *A, int64_t lda, int32_t layout,
+                               const double *b, const double *P, int64_t ldp, int64_t r, int64_t s,
+                               double *x, const lsrn_options *opt_in, lsrn_info *info,
+                               void *stream) {
+    LSRN_API_BEGIN
+    const lsrn_options opt = opt_in ? *opt_in : defaults();
+    check_options(opt);
+    LSRN_REQUIRE(m > 0 && n > 0, "sizes must be positive");
+    LSRN_REQUIRE(A && b && x && P, "NULL pointer");
+    hipStream_t st = (hipStream_t)stream;
+    TallView v;
+    make_view(v, m, n, A, lda, layout, opt.lambda, st);
+    LSRN_REQUIRE(r > 0 && r <= v.d && ldp >= r && s > 0, "bad preconditioner shape");
+    IterProblem pb;
+    pb.tall = v.tall; pb.rows = v.K; pb.cols = v.d; pb.T = v.T; pb.ldt = v.ldt;
+    pb.lambda = v.tall ? opt.lambda : 0.0; pb.P = P; pb.ldp = ldp; pb.r = r; pb.s = s;
+    IterResult ir = iterate(pb, b, x, opt, st);
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->s = s; info->d = v.d; info->rank = r; info->iters = ir.iters;
+        info->refine_steps = ir.refine_steps; info->refine_iters = ir.refine_iters;
+        info->tall = v.tall; info->converged = ir.converged;
+        info->sigma_l = ir.sigma_l; info->sigma_u = ir.sigma_u;
+        info->t_iter_ms = ir.t_iter_ms; info->t_refine_ms = ir.t_refine_ms;
+        info->t_total_ms = ir.t_iter_ms + ir.t_refine_ms;
+    }
+    if (!ir.converged) {
+        g_last_error = "LSQR reached max_iter";
+        return LSRN_E_NOT_CONVERGED;
+    }
+    LSRN_API_END
+}
+
+lsrn_status lsrn_solve_dense(int64_t m, int64_t n, const double *A, int64_t lda, int32_t layout,
+                             const double *b, double *x, const lsrn_options *opt_in,
+                             lsrn_info *info, void *stream) {
+    LSRN_API_BEGIN
+    const lsrn_options opt = opt_in ? *opt_in : defaults();
+    check_options(opt);
+    LSRN_REQUIRE(m > 0 && n > 0, "sizes must be positive");
+    LSRN_REQUIRE(A && b && x, "NULL pointer");
+    hipStream_t st = (hipStream_t)stream;
+    StageTimer tm(st);
+    tm.mark();
+    TallView v;
+    make_view(v, m, n, A, lda, layout, opt.lambda, st);
+    const int64_t d = v.d;
+    const int64_t s = (int64_t)std::ceil(opt.gamma * (double)d);
+    DevBuf X((size_t)s * (size_t)d * sizeof(double));
+    sketch_rows(v.K, d, v.T, v.ldt, v.tall ? opt.lambda : 0.0, s, opt.seed, X.as<double>(), st);
+    tm.mark();
+    DevBuf sigma((size_t)d * sizeof(double)), P((size_t)d * (size_t)d * sizeof(double));
+    PrecondResult pr = precond(s, d, X.as<double>(), opt.rcond, sigma.as<double>(), P.as<double>(), st);
+    X.release();
+    tm.mark();
+    IterResult ir;
+    if (pr.rank > 0) {
+        IterProblem pb;
+        pb.tall = v.tall; pb.rows = v.K; pb.cols = d; pb.T = v.T; pb.ldt = v.ldt;
+        pb.lambda = v.tall ? opt.lambda : 0.0; pb.P = P.as<double>(); pb.ldp = d;
+        pb.r = pr.rank; pb.s = s;
+        ir = iterate(pb, b, x, opt, st);
+    } else {
+        LSRN_HIP(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), st));
+    }
+    tm.mark();
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->s = s; info->d = d; info->rank = pr.rank; info->iters = ir.iters;
+        info->refine_steps = ir.refine_steps; info->refine_iters = ir.refine_iters;
+        info->sweeps = pr.sweeps; info->tall = v.tall; info->converged = ir.converged;
+        info->sigma_l = ir.sigma_l; info->sigma_u = ir.sigma_u;
+        info->sigma_max = pr.sigma_max; info->sigma_min_kept = pr.sigma_min_kept;
+        info->t_sketch_ms = tm.elapsed_ms(0, 1);
+        info->t_svd_ms = tm.elapsed_ms(1, 2);
+        info->t_iter_ms = ir.t_iter_ms;
+        info->t_refine_ms = ir.t_refine_ms;
+        info->t_total_ms = tm.elapsed_ms(0, 3);
+    }
+    if (!ir.converged) {
+        g_last_error = "LSQR reached max_iter";
+        return LSRN_E_NOT_CONVERGED;
+    }
+    LSRN_API_END
+}
+
+size_t lsrn_workspace_bytes(int64_t m, int64_t n, int32_t layout, const lsrn_options *opt_in) try {
+    const lsrn_options opt = opt_in ? *opt_in : defaults();
+    if (m <= 0 || n <= 0 || !(opt.gamma > 1.0)) return 0;
+    const bool tall = m >= n;
+    const int64_t K = tall ? m : n, d = tall ? n : m;
+    const int64_t s = (int64_t)std::ceil(opt.gamma * (double)d);
+    size_t bytes = 0;
+    if ((tall && layout != LSRN_ROW_MAJOR) || (!tall && layout != LSRN_COL_MAJOR))
+        bytes += (size_t)m * (size_t)n * sizeof(double);
+    bytes += (size_t)s * d * sizeof(double);                 // sketch
+    bytes += sketch_workspace_bytes(K, d, s);
+    bytes += precond_workspace_bytes(s, d);
+    bytes += (size_t)d * d * sizeof(double) * 2 + (size_t)d * sizeof(double);  // P, P^T, sigma
+    bytes += (size_t)(K + d) * sizeof(double) * 3;           // long vectors
+    bytes += (size_t)1024 * d * sizeof(double) * 3;          // sweep partials
+    return bytes;
+} catch (...) {
+    return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,76 @@
+// internal.hpp -- host-side interfaces between the translation units of liblsrn.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "common.hpp"
+
+namespace lsrn {
+
+// ------------------------------------------------------------ rng.hip
+void launch_philox_words(uint64_t seed, int64_t row0, int64_t nrows, int64_t q0, int64_t nq,
+                         uint32_t *out, hipStream_t s);
+void launch_gauss_fill(uint64_t seed, int64_t row0, int64_t nrows, int64_t col0, int64_t ncols,
+                       double *out, hipStream_t s);
+
+// ---------------------------------------------------------- sketch.hip
+// X (s x d, column-major, ld = s) = G T, T row-major K x d with leading
+// dimension ldt (T = A for tall row-major A, T = A^T for fat column-major
+// A).  When lambda > 0, adds lambda * G(i, K + c) to X(i, c) (the rows
+// lambda I of the augmented tall matrix, Sec. 5).
+void sketch_rows(int64_t K, int64_t d, const double *T, int64_t ldt, double lambda, int64_t s,
+                 uint64_t seed, double *X, hipStream_t st);
+size_t sketch_workspace_bytes(int64_t K, int64_t d, int64_t s);
+
+// Out-of-place transpose: out (cols x rows, leading dim rows) = in^T, in
+// row-major rows x cols with leading dim ldin.
+void transpose(int64_t rows, int64_t cols, const double *in, int64_t ldin, double *out,
+               hipStream_t st);
+
+// ------------------------------------------------------------- svd.hip
+struct PrecondResult {
+    int64_t rank = 0;
+    int64_t sweeps = 0;
+    double sigma_max = 0.0;
+    double sigma_min_kept = 0.0;
+};
+// X: s x d column-major (overwritten).  P: d x d row-major (first r columns
+// hold V_r Sigma_r^{-1}); sigma: d values, descending.  Synchronises.
+PrecondResult precond(int64_t s, int64_t d, double *X, double rcond, double *sigma, double *P,
+                      hipStream_t st);
+size_t precond_workspace_bytes(int64_t s, int64_t d);
+
+// --------------------------------------------------------- iterate.hip
+// The operator of the iteration phase.  Tall: T = A row-major (rows = m,
+// cols = n) with optional lambda rows; Fat: T = A^T row-major (rows = n,
+// cols = m).  P is d x r row-major (leading dim ldp), d = cols of T.
+struct IterProblem {
+    bool tall = true;
+    int64_t rows = 0;       // rows of T
+    int64_t cols = 0;       // cols of T (= d)
+    const double *T = nullptr;
+    int64_t ldt = 0;
+    double lambda = 0.0;    // tall only
+    const double *P = nullptr;
+    int64_t ldp = 0;
+    int64_t r = 0;
+    int64_t s = 0;
+};
+
+struct IterResult {
+    int64_t iters = 0;
+    int64_t refine_steps = 0;
+    int64_t refine_iters = 0;
+    bool converged = true;
+    double sigma_l = 0.0, sigma_u = 0.0;
+    double t_iter_ms = 0.0, t_refine_ms = 0.0;
+};
+
+// Runs step 6 (and 7) for b (length m of the original problem) and
+// writes x (length n).  Synchronises.
+IterResult iterate(const IterProblem &pb, const double *b, double *x, const lsrn_options &opt,
+                   hipStream_t st);
+
+}  // namespace lsrn

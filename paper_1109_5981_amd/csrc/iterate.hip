@@ -1,0 +1,1140 @@
+// iterate.hip -- the iteration phase of LSRN (Alg. 1/2 step 6-7).
+//
+// Both shapes are driven through one "row sweep" over a row-major matrix T
+// (the tall view): T = A for m >= n (Alg. 1) and T = A^T, i.e. A stored
+// column-major, for m < n (Alg. 2).  One sweep reads every row T_j once:
+//     q_j = T_j . w                 (w = N v or M u, computed beforehand)
+//     c_j = op(q_j, per-row state)  (the LSQR / Chebyshev update of row j)
+//     z  += c_j T_j                 (the transposed product)
+// so A (x) and A^T (y) of an iteration cost one pass over A in HBM.
+// Partial z vectors per workgroup are summed in a fixed order, which makes
+// every result bitwise reproducible run to run.
+//
+// Tall LSQR runs Paige-Saunders LSQR on K = [A; lambda I] N: the long
+// vector u lives in row space and is kept unnormalised (u~ = beta u), the
+// short vectors v, w, y (length r) and all scalars live in one device
+// workgroup.  Fat LSQR runs on K = M^T A: the long vectors v, w, x live in
+// row space of T, and the x/w update of iteration i is applied during the
+// sweep of iteration i+1, when v_{i+1} is read anyway.  The Chebyshev
+// semi-iteration (Alg. 3) has data-independent scalars, computed on the
+// host.
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace lsrn {
+
+namespace {
+
+constexpr int NT = 256;
+
+// Device-resident scalar state of an iterative solve.
+struct State {
+    double alpha, beta, rhobar, phibar, anorm2, bnorm;
+    double coef;        // tall LSQR: u~_new = q - coef u~
+    double inv_alpha;   // fat LSQR: v = v~ * inv_alpha
+    double phi_rho, theta_rho;
+    double xnorm2;
+    double acc[4];      // reduced sweep accumulators
+    double cg_rs, cg_stop;
+    int32_t done, iters, converged, pending;
+    int32_t maxiter, pad_;
+};
+
+enum Op : int {
+    OP_ATB = 0,        // c = y[j]                       acc0 += c^2
+    OP_LSQR_TALL = 1,  // y[j] = q - coef y[j]; c = y[j]  acc0 += c^2
+    OP_CS_TALL = 2,    // y[j] -= alpha q;    c = y[j]    acc0 += c^2
+    OP_NORMAL = 3,     // c = q                          acc0 += q^2
+    OP_LSQR_FAT = 4,   // see sweep body
+    OP_CS_FAT = 5,     // y[j] = beta y[j] + q; x[j] += alpha y[j]; c = y[j]
+};
+
+struct SweepArgs {
+    const double *T;
+    int64_t ldt, rows;
+    int L;
+    int nblocks;
+    int64_t rows_per_block;
+    const double *w;     // length L
+    double *zpart;       // nblocks x L
+    double *spart;       // nblocks x 4
+    double *y;           // per-row long vector (length rows, + L Tikhonov rows)
+    double *xv, *wv;     // fat LSQR / CS long vectors (length rows)
+    State *st;
+    double lambda;       // Tikhonov rows (tall only)
+    double alpha, beta;  // Chebyshev scalars
+};
+
+template <int CPT>
+__device__ __forceinline__ int col_of(int tid, int e) {
+    return 2 * tid + 512 * (e >> 1) + (e & 1);
+}
+
+template <int CPT, int R, int OP>
+__global__ void __launch_bounds__(NT, 2) sweep_kernel(SweepArgs a) {
+    if (a.st->done) return;
+    __shared__ double red[2][NT / 64][R];
+    __shared__ double accred[NT / 64][4];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int L = a.L;
+
+    double wr[CPT], zr[CPT];
+#pragma unroll
+    for (int e = 0; e < CPT; ++e) {
+        const int col = col_of<CPT>(tid, e);
+        wr[e] = (OP != OP_ATB && col < L) ? a.w[col] : 0.0;
+        zr[e] = 0.0;
+    }
+    // scalars of this sweep
+    double coef = 0.0, inv_alpha = 0.0, beta = 0.0, phi_rho = 0.0, theta_rho = 0.0;
+    int pending = 0;
+    if (OP == OP_LSQR_TALL) coef = a.st->coef;
+    if (OP == OP_CS_TALL) coef = a.alpha;
+    if (OP == OP_LSQR_FAT) {
+        inv_alpha = a.st->inv_alpha;
+        beta = a.st->beta;
+        phi_rho = a.st->phi_rho;
+        theta_rho = a.st->theta_rho;
+        pending = a.st->pending;
+    }
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+
+    const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_block;
+    const int64_t r1 = min(a.rows, r0 + a.rows_per_block);
+    const bool vec2 = ((a.ldt & 1) == 0) && ((reinterpret_cast<uintptr_t>(a.T) & 15) == 0);
+    int parity = 0;
+    for (int64_t j0 = r0; j0 < r1; j0 += R) {
+        double av[R][CPT];
+        double yv[R];
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+            const int64_t row = j0 + rr;
+            const bool valid = row < r1;
+            const double *trow = a.T + row * a.ldt;
+#pragma unroll
+            for (int e = 0; e < CPT; e += 2) {
+                const int col = col_of<CPT>(tid, e);
+                double2 v = make_double2(0.0, 0.0);
+                if (valid) {
+                    if (vec2 && col + 1 < L) {
+                        v = *reinterpret_cast<const double2 *>(trow + col);
+                    } else {
+                        if (col < L) v.x = trow[col];
+                        if (col + 1 < L) v.y = trow[col + 1];
+                    }
+                }
+                av[rr][e] = v.x;
+                av[rr][e + 1] = v.y;
+            }
+            yv[rr] = (valid && OP != OP_NORMAL) ? a.y[row] : 0.0;
+        }
+        double q[R];
+        if (OP != OP_ATB) {
+            double pd[R];
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) {
+                double t = 0.0;
+#pragma unroll
+                for (int e = 0; e < CPT; ++e) t += av[rr][e] * wr[e];
+                pd[rr] = wave_sum(t);
+            }
+            if (lane == 0) {
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr) red[parity][wid][rr] = pd[rr];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) {
+                double t = 0.0;
+#pragma unroll
+                for (int w = 0; w < NT / 64; ++w) t += red[parity][w][rr];
+                q[rr] = t;
+            }
+            parity ^= 1;
+        }
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+            const int64_t row = j0 + rr;
+            if (row >= r1) continue;
+            const bool owner = tid == rr;
+            double c;
+            if (OP == OP_ATB) {
+                c = yv[rr];
+                if (owner) acc0 += c * c;
+            } else if (OP == OP_LSQR_TALL) {
+                c = q[rr] - coef * yv[rr];
+                if (owner) { a.y[row] = c; acc0 += c * c; }
+            } else if (OP == OP_CS_TALL) {
+                c = yv[rr] - coef * q[rr];
+                if (owner) { a.y[row] = c; acc0 += c * c; }
+            } else if (OP == OP_NORMAL) {
+                c = q[rr];
+                if (owner) acc0 += c * c;
+            } else if (OP == OP_LSQR_FAT) {
+                const double v = yv[rr] * inv_alpha;
+                c = q[rr] - beta * v;
+                if (owner) {
+                    if (pending == 1) {
+                        a.wv[row] = v;
+                        acc3 += v * v;
+                    } else if (pending == 2) {
+                        const double xo = a.xv[row] + phi_rho * a.wv[row];
+                        const double wn = v - theta_rho * a.wv[row];
+                        a.xv[row] = xo;
+                        a.wv[row] = wn;
+                        acc1 += xo * xo;
+                        acc2 += xo * wn;
+                        acc3 += wn * wn;
+                    }
+                    a.y[row] = c;
+                    acc0 += c * c;
+                }
+            } else {  // OP_CS_FAT
+                c = a.beta * yv[rr] + q[rr];
+                if (owner) {
+                    a.y[row] = c;
+                    a.xv[row] += a.alpha * c;
+                    acc0 += c * c;
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < CPT; ++e) zr[e] += c * av[rr][e];
+        }
+    }
+
+    // Tikhonov rows m + k (row vector lambda e_k) of the augmented tall
+    // matrix: handled by the thread that owns column k, in block k % nblocks.
+    if (a.lambda > 0.0 && OP != OP_LSQR_FAT && OP != OP_CS_FAT) {
+#pragma unroll
+        for (int e = 0; e < CPT; ++e) {
+            const int col = col_of<CPT>(tid, e);
+            if (col < L && (col % a.nblocks) == (int)blockIdx.x) {
+                const int64_t row = a.rows + col;
+                const double qv = a.lambda * wr[e];
+                double c;
+                if (OP == OP_ATB) c = a.y[row];
+                else if (OP == OP_LSQR_TALL) { c = qv - coef * a.y[row]; a.y[row] = c; }
+                else if (OP == OP_CS_TALL) { c = a.y[row] - coef * qv; a.y[row] = c; }
+                else c = qv;
+                acc0 += c * c;
+                zr[e] += a.lambda * c;
+            }
+        }
+    }
+
+#pragma unroll
+    for (int e = 0; e < CPT; ++e) {
+        const int col = col_of<CPT>(tid, e);
+        if (col < L) a.zpart[(int64_t)blockIdx.x * L + col] = zr[e];
+    }
+    acc0 = wave_sum(acc0);
+    acc1 = wave_sum(acc1);
+    acc2 = wave_sum(acc2);
+    acc3 = wave_sum(acc3);
+    if (lane == 0) {
+        accred[wid][0] = acc0; accred[wid][1] = acc1; accred[wid][2] = acc2; accred[wid][3] = acc3;
+    }
+    __syncthreads();
+    if (tid < 4) {
+        double t = 0.0;
+        for (int w = 0; w < NT / 64; ++w) t += accred[w][tid];
+        a.spart[(int64_t)blockIdx.x * 4 + tid] = t;
+    }
+}
+
+// Stage 1 of the partial-sum reduction: group g of the workgroup partials
+// (rows [g*chunk, (g+1)*chunk) of zpart) summed per column.
+__global__ void __launch_bounds__(256)
+reduce_stage1_kernel(const double *__restrict__ zpart, const double *__restrict__ spart, int nb,
+                     int L, int chunk, double *__restrict__ zred, double *__restrict__ sred,
+                     const State *st) {
+    if (st->done) return;
+    const int g = blockIdx.y;
+    const int b0 = g * chunk, b1 = min(nb, b0 + chunk);
+    const int col = blockIdx.x * 256 + threadIdx.x;
+    if (col < L) {
+        double t = 0.0;
+        for (int b = b0; b < b1; ++b) t += zpart[(int64_t)b * L + col];
+        zred[(int64_t)g * L + col] = t;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < 4) {
+        double t = 0.0;
+        for (int b = b0; b < b1; ++b) t += spart[b * 4 + threadIdx.x];
+        sred[g * 4 + threadIdx.x] = t;
+    }
+}
+
+// Stage 2: z = sum of the group sums; block 0 also reduces the scalar
+// accumulators into st->acc.
+__global__ void __launch_bounds__(256)
+reduce_stage2_kernel(const double *__restrict__ zred, const double *__restrict__ sred, int ng,
+                     int L, double *__restrict__ z, State *st) {
+    if (st->done) return;
+    const int col = blockIdx.x * 256 + threadIdx.x;
+    if (col < L) {
+        double t = 0.0;
+        for (int g = 0; g < ng; ++g) t += zred[(int64_t)g * L + col];
+        z[col] = t;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < 4) {
+        double t = 0.0;
+        for (int g = 0; g < ng; ++g) t += sred[g * 4 + threadIdx.x];
+        st->acc[threadIdx.x] = t;
+    }
+}
+
+// y = M x for row-major M (nrows x ncols, leading dimension ld), one
+// wavefront per row.
+__global__ void __launch_bounds__(256)
+gemv_kernel(const double *__restrict__ M, int64_t ld, int64_t nrows, int64_t ncols,
+            const double *__restrict__ x, double *__restrict__ y, const State *st) {
+    if (st && st->done) return;
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= nrows) return;
+    const int lane = threadIdx.x & 63;
+    const double *mr = M + row * ld;
+    double t = 0.0;
+    for (int64_t c = lane; c < ncols; c += 64) t += mr[c] * x[c];
+    t = wave_sum(t);
+    if (lane == 0) y[row] = t;
+}
+
+// ----------------------------------------------------------- LSQR scalars
+
+constexpr int SNT = 1024;
+
+// Block sum of a length-n vector held in global memory (fixed order).
+__device__ double vec_dot(const double *a, const double *b, int64_t n, double *scratch) {
+    double t = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += SNT) t += a[i] * b[i];
+    return block_sum<SNT>(t, scratch);
+}
+
+// Tall LSQR start: t = K^T b^ (unscaled, from the first sweep), acc0 = ||b^||^2.
+__global__ void __launch_bounds__(SNT)
+lsqr_tall_init_kernel(const double *__restrict__ t, int64_t r, double *__restrict__ v,
+                      double *__restrict__ wdir, double *__restrict__ y, State *st) {
+    __shared__ double scratch[SNT / 64];
+    const double beta = sqrt(st->acc[0]);
+    const double ib = beta > 0.0 ? 1.0 / beta : 0.0;
+    double part = 0.0;
+    for (int64_t i = threadIdx.x; i < r; i += SNT) {
+        const double vi = t[i] * ib;
+        part += vi * vi;
+    }
+    const double alpha = sqrt(block_sum<SNT>(part, scratch));
+    const double ia = alpha > 0.0 ? 1.0 / alpha : 0.0;
+    for (int64_t i = threadIdx.x; i < r; i += SNT) {
+        const double vi = t[i] * ib * ia;
+        v[i] = vi;
+        wdir[i] = vi;
+        y[i] = 0.0;
+    }
+    if (threadIdx.x == 0) {
+        st->alpha = alpha;
+        st->beta = beta;
+        st->bnorm = beta;
+        st->phibar = beta;
+        st->rhobar = alpha;
+        st->anorm2 = 0.0;
+        st->xnorm2 = 0.0;
+        st->coef = beta > 0.0 ? alpha / beta : 0.0;
+        st->iters = 0;
+        st->converged = (beta == 0.0 || alpha == 0.0) ? 1 : 0;
+        st->done = st->converged;
+    }
+}
+
+// One LSQR iteration given t = N^T A^T u~ and acc0 = ||u~||^2 from the sweep
+// that formed u~ = K v - alpha u.  Stopping rules of Paige-Saunders.
+__global__ void __launch_bounds__(SNT)
+lsqr_tall_step_kernel(const double *__restrict__ t, int64_t r, double *__restrict__ v,
+                      double *__restrict__ wdir, double *__restrict__ y, double tol, State *st) {
+    if (st->done) return;
+    __shared__ double scratch[SNT / 64];
+    const double alpha_old = st->alpha;
+    const double beta = sqrt(st->acc[0]);
+    const double anorm2 = st->anorm2 + alpha_old * alpha_old + beta * beta;
+    const double ib = beta > 0.0 ? 1.0 / beta : 0.0;
+    // alpha v = K^T u - beta v, u = u~ / beta
+    double part = 0.0;
+    for (int64_t i = threadIdx.x; i < r; i += SNT) {
+        const double vi = t[i] * ib - beta * v[i];
+        part += vi * vi;
+    }
+    const double alpha = sqrt(block_sum<SNT>(part, scratch));
+    const double ia = alpha > 0.0 ? 1.0 / alpha : 0.0;
+    const double rho = hypot(st->rhobar, beta);
+    const double c = st->rhobar / rho, sn = beta / rho;
+    const double theta = sn * alpha;
+    const double phi = c * st->phibar;
+    const double phibar = sn * st->phibar;
+    const double f1 = phi / rho, f2 = theta / rho;
+    double xpart = 0.0;
+    for (int64_t i = threadIdx.x; i < r; i += SNT) {
+        const double vi = (t[i] * ib - beta * v[i]) * ia;
+        const double yi = y[i] + f1 * wdir[i];
+        y[i] = yi;
+        wdir[i] = vi - f2 * wdir[i];
+        v[i] = vi;
+        xpart += yi * yi;
+    }
+    const double xnorm = sqrt(block_sum<SNT>(xpart, scratch));
+    if (threadIdx.x == 0) {
+        const double anorm = sqrt(anorm2);
+        const double rnorm = phibar;
+        const double arnorm = phibar * alpha * fabs(c);
+        const double test2 = rnorm > 0.0 ? arnorm / (anorm * rnorm) : 0.0;
+        const double test1 = rnorm / st->bnorm;
+        const int it = st->iters + 1;
+        st->iters = it;
+        st->alpha = alpha;
+        st->beta = beta;
+        st->anorm2 = anorm2;
+        st->rhobar = -c * alpha;
+        st->phibar = phibar;
+        st->coef = beta > 0.0 ? alpha / beta : 0.0;
+        const bool conv = test2 <= tol || test1 <= tol + tol * anorm * xnorm / st->bnorm ||
+                          beta == 0.0 || alpha == 0.0;
+        st->converged = conv ? 1 : 0;
+        st->done = (conv || it >= st->maxiter) ? 1 : 0;
+    }
+}
+
+// Fat LSQR start: c = M^T b in t (length r); u = c / beta.
+__global__ void __launch_bounds__(SNT)
+lsqr_fat_init_kernel(const double *__restrict__ t, int64_t r, double *__restrict__ u, State *st) {
+    __shared__ double scratch[SNT / 64];
+    const double beta = sqrt(vec_dot(t, t, r, scratch));
+    const double ib = beta > 0.0 ? 1.0 / beta : 0.0;
+    for (int64_t i = threadIdx.x; i < r; i += SNT) u[i] = t[i] * ib;
+    if (threadIdx.x == 0) {
+        st->beta = beta;
+        st->bnorm = beta;
+        st->phibar = beta;
+        st->anorm2 = 0.0;
+        st->xnorm2 = 0.0;
+        st->inv_alpha = 0.0;
+        st->pending = 0;
+        st->iters = 0;
+        st->alpha = 0.0;
+        st->converged = beta == 0.0 ? 1 : 0;
+        st->done = st->converged;
+    }
+}
+
+// Fat LSQR after a sweep that produced v~_{i+1} (acc0 = ||v~||^2, acc1..3 =
+// ||x_{i-1}||^2, x_{i-1}.w_i, ||w_i||^2) and t = M^T A v~.  first: the sweep
+// was the start sweep (v~_1).  Then: Givens step of iteration i and the
+// stopping test, followed by the u-step of iteration i+1.
+__global__ void __launch_bounds__(SNT)
+lsqr_fat_step_kernel(const double *__restrict__ t, int64_t r, double *__restrict__ u, int first,
+                     double tol, State *st) {
+    if (st->done) return;
+    __shared__ double scratch[SNT / 64];
+    __shared__ int stop;
+    const double alpha = sqrt(st->acc[0]);
+    if (threadIdx.x == 0) {
+        stop = 0;
+        if (first) {
+            st->rhobar = alpha;
+            st->alpha = alpha;
+            st->pending = 1;
+            if (alpha == 0.0) { st->converged = 1; st->done = 1; st->pending = 0; stop = 1; }
+        } else {
+            const double beta = st->beta;  // beta_{i+1}
+            const double rho = hypot(st->rhobar, beta);
+            const double c = st->rhobar / rho, sn = beta / rho;
+            const double theta = sn * alpha;
+            const double phi = c * st->phibar;
+            const double phibar = sn * st->phibar;
+            const double pr = phi / rho;
+            st->phi_rho = pr;
+            st->theta_rho = theta / rho;
+            st->pending = 2;
+            const double xnorm2 = st->acc[1] + 2.0 * pr * st->acc[2] + pr * pr * st->acc[3];
+            st->xnorm2 = xnorm2;
+            st->rhobar = -c * alpha;
+            st->phibar = phibar;
+            st->alpha = alpha;
+            const double anorm = sqrt(st->anorm2);
+            const double rnorm = phibar;
+            const double arnorm = phibar * alpha * fabs(c);
+            const double test2 = rnorm > 0.0 ? arnorm / (anorm * rnorm) : 0.0;
+            const double test1 = rnorm / st->bnorm;
+            const int it = st->iters + 1;
+            st->iters = it;
+            const bool conv = test2 <= tol ||
+                              test1 <= tol + tol * anorm * sqrt(xnorm2) / st->bnorm ||
+                              beta == 0.0 || alpha == 0.0;
+            st->converged = conv ? 1 : 0;
+            if (conv || it >= st->maxiter) { st->done = 1; stop = 1; }
+        }
+    }
+    __syncthreads();
+    if (stop) return;
+    // u-step: beta u = K v - alpha u, K v = t / alpha
+    const double ia = alpha > 0.0 ? 1.0 / alpha : 0.0;
+    double part = 0.0;
+    for (int64_t i = threadIdx.x; i < r; i += SNT) {
+        const double ui = t[i] * ia - alpha * u[i];
+        part += ui * ui;
+    }
+    const double beta = sqrt(block_sum<SNT>(part, scratch));
+    const double ib = beta > 0.0 ? 1.0 / beta : 0.0;
+    for (int64_t i = threadIdx.x; i < r; i += SNT) u[i] = (t[i] * ia - alpha * u[i]) * ib;
+    if (threadIdx.x == 0) {
+        st->anorm2 += alpha * alpha + beta * beta;
+        st->beta = beta;
+        st->inv_alpha = ia;
+    }
+}
+
+// x += phi/rho w after the last fat LSQR iteration.
+__global__ void __launch_bounds__(256)
+lsqr_fat_finish_kernel(int64_t n, double *__restrict__ x, const double *__restrict__ wdir,
+                       const State *st) {
+    if (st->pending != 2) return;
+    const double pr = st->phi_rho;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        x[i] += pr * wdir[i];
+}
+
+// ------------------------------------------------------ Chebyshev / misc
+
+// v = beta v + t; y += alpha v (short vectors of the tall Chebyshev solve).
+__global__ void __launch_bounds__(256)
+cs_short_kernel(int64_t r, double *__restrict__ v, const double *__restrict__ t,
+                double *__restrict__ y, double alpha, double beta) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < r;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double vi = beta * v[i] + t[i];
+        v[i] = vi;
+        y[i] += alpha * vi;
+    }
+}
+
+// y = a x + b y
+__global__ void __launch_bounds__(256)
+axpby_kernel(int64_t n, double a, const double *__restrict__ x, double b, double *__restrict__ y) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = a * x[i] + (b == 0.0 ? 0.0 : b * y[i]);
+}
+
+__global__ void __launch_bounds__(256)
+fill_kernel(int64_t n, double v, double *__restrict__ y) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = v;
+}
+
+__global__ void set_state_kernel(State *st, int maxiter) {
+    State z = {};
+    z.maxiter = maxiter;
+    *st = z;
+}
+
+// -------------------------------------------------------------- refinement
+
+// Tall: h = T^T (b^ - T x) - lambda^2 x in double-double, one pass over T.
+// x (length L) is held per thread like w in the sweep.
+template <int CPT>
+__global__ void __launch_bounds__(NT)
+resid_dd_tall_kernel(const double *__restrict__ T, int64_t ldt, int64_t rows, int L, int nblocks,
+                     int64_t rows_per_block, const double *__restrict__ b,
+                     const double *__restrict__ x, double lambda, double *__restrict__ hpart_hi,
+                     double *__restrict__ hpart_lo) {
+    __shared__ double red_hi[2][NT / 64], red_lo[2][NT / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    double xr[CPT];
+    dd zr[CPT];
+#pragma unroll
+    for (int e = 0; e < CPT; ++e) {
+        const int col = col_of<CPT>(tid, e);
+        xr[e] = col < L ? x[col] : 0.0;
+        zr[e] = {0.0, 0.0};
+    }
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+    const int64_t r1 = min(rows, r0 + rows_per_block);
+    int parity = 0;
+    for (int64_t row = r0; row < r1; ++row) {
+        const double *trow = T + row * ldt;
+        double av[CPT];
+        dd p = {0.0, 0.0};
+#pragma unroll
+        for (int e = 0; e < CPT; ++e) {
+            const int col = col_of<CPT>(tid, e);
+            av[e] = col < L ? trow[col] : 0.0;
+            p = dd_fma(p, av[e], xr[e]);
+        }
+        p = wave_sum_dd(p);
+        if (lane == 0) { red_hi[parity][wid] = p.hi; red_lo[parity][wid] = p.lo; }
+        __syncthreads();
+        dd tx = {0.0, 0.0};
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) tx = dd_add(tx, dd{red_hi[parity][w], red_lo[parity][w]});
+        parity ^= 1;
+        // res = b - T x
+        const dd res = dd_add(dd{b[row], 0.0}, dd{-tx.hi, -tx.lo});
+#pragma unroll
+        for (int e = 0; e < CPT; ++e) zr[e] = dd_fma_dd(zr[e], av[e], res);
+    }
+    if (lambda > 0.0) {
+#pragma unroll
+        for (int e = 0; e < CPT; ++e) {
+            const int col = col_of<CPT>(tid, e);
+            if (col < L && (col % nblocks) == (int)blockIdx.x) {
+                // row m + col: residual 0 - lambda x_col, contributes lambda * residual
+                dd res = two_prod(-lambda, xr[e]);
+                zr[e] = dd_fma_dd(zr[e], lambda, res);
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < CPT; ++e) {
+        const int col = col_of<CPT>(tid, e);
+        if (col < L) {
+            hpart_hi[(int64_t)blockIdx.x * L + col] = zr[e].hi;
+            hpart_lo[(int64_t)blockIdx.x * L + col] = zr[e].lo;
+        }
+    }
+}
+
+// Fat: z = T^T x = A x in double-double (rows of T weighted by x).
+template <int CPT>
+__global__ void __launch_bounds__(NT)
+ax_dd_fat_kernel(const double *__restrict__ T, int64_t ldt, int64_t rows, int L,
+                 int64_t rows_per_block, const double *__restrict__ x,
+                 double *__restrict__ zpart_hi, double *__restrict__ zpart_lo) {
+    const int tid = threadIdx.x;
+    dd zr[CPT];
+#pragma unroll
+    for (int e = 0; e < CPT; ++e) zr[e] = {0.0, 0.0};
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+    const int64_t r1 = min(rows, r0 + rows_per_block);
+    for (int64_t row = r0; row < r1; ++row) {
+        const double *trow = T + row * ldt;
+        const double xv = x[row];
+#pragma unroll
+        for (int e = 0; e < CPT; ++e) {
+            const int col = col_of<CPT>(tid, e);
+            if (col < L) zr[e] = dd_fma(zr[e], trow[col], xv);
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < CPT; ++e) {
+        const int col = col_of<CPT>(tid, e);
+        if (col < L) {
+            zpart_hi[(int64_t)blockIdx.x * L + col] = zr[e].hi;
+            zpart_lo[(int64_t)blockIdx.x * L + col] = zr[e].lo;
+        }
+    }
+}
+
+// out = sum over nb partials (double-double), optionally out = bvec - sum.
+__global__ void __launch_bounds__(256)
+reduce_dd_kernel(const double *__restrict__ phi, const double *__restrict__ plo, int nb, int L,
+                 const double *__restrict__ bvec, double *__restrict__ out_hi,
+                 double *__restrict__ out_lo) {
+    const int col = blockIdx.x * 256 + threadIdx.x;
+    if (col >= L) return;
+    dd t = {0.0, 0.0};
+    for (int b = 0; b < nb; ++b) t = dd_add(t, dd{phi[(int64_t)b * L + col], plo[(int64_t)b * L + col]});
+    if (bvec) t = dd_add(dd{bvec[col], 0.0}, dd{-t.hi, -t.lo});
+    out_hi[col] = t.hi;
+    if (out_lo) out_lo[col] = t.lo;
+}
+
+// y = M^T v for row-major M (nrows x ncols, ld) with v = vhi + vlo in
+// double-double accumulation; one wavefront per output column chunk.
+__global__ void __launch_bounds__(256)
+gemv_t_dd_kernel(const double *__restrict__ M, int64_t ld, int64_t nrows, int64_t ncols,
+                 const double *__restrict__ vhi, const double *__restrict__ vlo,
+                 double *__restrict__ y) {
+    const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= ncols) return;
+    const int lane = threadIdx.x & 63;
+    dd t = {0.0, 0.0};
+    for (int64_t i = lane; i < nrows; i += 64) t = dd_fma_dd(t, M[i * ld + c], dd{vhi[i], vlo[i]});
+    t = wave_sum_dd(t);
+    if (lane == 0) y[c] = t.hi + t.lo;
+}
+
+// CG on K^T K z = c: given t = K^T K p (sweep) and acc0 = ||K p||^2.
+__global__ void __launch_bounds__(SNT)
+cg_step_kernel(const double *__restrict__ t, int64_t r, double *__restrict__ z,
+               double *__restrict__ res, double *__restrict__ p, State *st) {
+    if (st->done) return;
+    __shared__ double scratch[SNT / 64];
+    const double pbp = st->acc[0];
+    const double rs = st->cg_rs;
+    const double a = pbp > 0.0 ? rs / pbp : 0.0;
+    double part = 0.0;
+    for (int64_t i = threadIdx.x; i < r; i += SNT) {
+        z[i] += a * p[i];
+        const double ri = res[i] - a * t[i];
+        res[i] = ri;
+        part += ri * ri;
+    }
+    const double rs_new = block_sum<SNT>(part, scratch);
+    const double bta = rs > 0.0 ? rs_new / rs : 0.0;
+    for (int64_t i = threadIdx.x; i < r; i += SNT) p[i] = res[i] + bta * p[i];
+    if (threadIdx.x == 0) {
+        st->cg_rs = rs_new;
+        const int it = st->iters + 1;
+        st->iters = it;
+        const bool conv = sqrt(rs_new) <= st->cg_stop || pbp <= 0.0;
+        st->converged = conv ? 1 : 0;
+        st->done = (conv || it >= st->maxiter) ? 1 : 0;
+    }
+}
+
+__global__ void __launch_bounds__(SNT)
+cg_init_kernel(const double *__restrict__ c, int64_t r, double *__restrict__ z,
+               double *__restrict__ res, double *__restrict__ p, double rtol, int maxiter,
+               State *st) {
+    __shared__ double scratch[SNT / 64];
+    double part = 0.0;
+    for (int64_t i = threadIdx.x; i < r; i += SNT) {
+        z[i] = 0.0;
+        res[i] = c[i];
+        p[i] = c[i];
+        part += c[i] * c[i];
+    }
+    const double rs = block_sum<SNT>(part, scratch);
+    if (threadIdx.x == 0) {
+        State s0 = {};
+        s0.maxiter = maxiter;
+        s0.cg_rs = rs;
+        s0.cg_stop = rtol * sqrt(rs);
+        s0.done = rs == 0.0 ? 1 : 0;
+        s0.converged = s0.done;
+        *st = s0;
+    }
+}
+
+// ------------------------------------------------------------ host driver
+
+int grid1(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 256), 4096)); }
+
+struct Ctx {
+    const IterProblem &pb;
+    hipStream_t st;
+    int L;
+    int nblocks;
+    int64_t rows_per_block;
+    int cpt, R;
+    int ngroups, chunk;
+    DevBuf zpart, spart, zred, sred, z, stbuf, Pt;
+    State *state;
+    const double *Ptp;  // P^T, r x L row-major (ld L)
+
+    Ctx(const IterProblem &p, hipStream_t s) : pb(p), st(s) {
+        L = (int)pb.cols;
+        if (L <= 512) { cpt = 2; R = 8; }
+        else if (L <= 1024) { cpt = 4; R = 8; }
+        else if (L <= 2048) { cpt = 8; R = 4; }
+        else if (L <= 4096) { cpt = 16; R = 2; }
+        else fail(LSRN_E_UNSUPPORTED, "dense iteration supports min(m, n) <= 4096");
+        const int64_t want = 2 * (int64_t)device_cus();
+        nblocks = (int)std::max<int64_t>(1, std::min<int64_t>(want, ceil_div(pb.rows, R)));
+        rows_per_block = round_up(ceil_div(pb.rows, nblocks), R);
+        nblocks = (int)std::max<int64_t>(1, ceil_div(pb.rows, rows_per_block));
+        chunk = 16;
+        ngroups = (int)ceil_div(nblocks, chunk);
+        zpart.alloc((size_t)nblocks * L * sizeof(double));
+        spart.alloc((size_t)nblocks * 4 * sizeof(double));
+        zred.alloc((size_t)ngroups * L * sizeof(double));
+        sred.alloc((size_t)ngroups * 4 * sizeof(double));
+        z.alloc((size_t)L * sizeof(double));
+        stbuf.alloc(sizeof(State));
+        state = stbuf.as<State>();
+        // P^T (r x L) for the t = P^T z products
+        Pt.alloc((size_t)std::max<int64_t>(pb.r, 1) * L * sizeof(double));
+        transpose(L, pb.r, pb.P, pb.ldp, Pt.as<double>(), st);
+        Ptp = Pt.as<double>();
+    }
+
+    void reset_state(int maxiter) {
+        set_state_kernel<<<1, 1, 0, st>>>(state, maxiter);
+        LSRN_HIP(hipGetLastError());
+    }
+
+    template <int CPT, int RR>
+    void sweep_t(int op, SweepArgs &a) {
+        switch (op) {
+            case OP_ATB: sweep_kernel<CPT, RR, OP_ATB><<<nblocks, NT, 0, st>>>(a); break;
+            case OP_LSQR_TALL: sweep_kernel<CPT, RR, OP_LSQR_TALL><<<nblocks, NT, 0, st>>>(a); break;
+            case OP_CS_TALL: sweep_kernel<CPT, RR, OP_CS_TALL><<<nblocks, NT, 0, st>>>(a); break;
+            case OP_NORMAL: sweep_kernel<CPT, RR, OP_NORMAL><<<nblocks, NT, 0, st>>>(a); break;
+            case OP_LSQR_FAT: sweep_kernel<CPT, RR, OP_LSQR_FAT><<<nblocks, NT, 0, st>>>(a); break;
+            default: sweep_kernel<CPT, RR, OP_CS_FAT><<<nblocks, NT, 0, st>>>(a); break;
+        }
+    }
+
+    // One pass: z = sum_j op_j T_j, st->acc = reduced accumulators.
+    void sweep(int op, const double *w, double *y, double *xv, double *wv, double alpha = 0.0,
+               double beta = 0.0) {
+        SweepArgs a;
+        a.T = pb.T; a.ldt = pb.ldt; a.rows = pb.rows; a.L = L; a.nblocks = nblocks;
+        a.rows_per_block = rows_per_block; a.w = w; a.zpart = zpart.as<double>();
+        a.spart = spart.as<double>(); a.y = y; a.xv = xv; a.wv = wv; a.st = state;
+        a.lambda = pb.tall ? pb.lambda : 0.0; a.alpha = alpha; a.beta = beta;
+        if (cpt == 2) sweep_t<2, 8>(op, a);
+        else if (cpt == 4) sweep_t<4, 8>(op, a);
+        else if (cpt == 8) sweep_t<8, 4>(op, a);
+        else sweep_t<16, 2>(op, a);
+        LSRN_HIP(hipGetLastError());
+        dim3 g1((unsigned)ceil_div(L, 256), (unsigned)ngroups);
+        reduce_stage1_kernel<<<g1, 256, 0, st>>>(zpart.as<double>(), spart.as<double>(), nblocks, L,
+                                                 chunk, zred.as<double>(), sred.as<double>(), state);
+        reduce_stage2_kernel<<<(unsigned)ceil_div(L, 256), 256, 0, st>>>(
+            zred.as<double>(), sred.as<double>(), ngroups, L, z.as<double>(), state);
+        LSRN_HIP(hipGetLastError());
+    }
+
+    // out (length rows_of_M) = M x.
+    void gemv(const double *M, int64_t ld, int64_t nrows, int64_t ncols, const double *x,
+              double *out, bool honour_done = true) {
+        if (nrows <= 0) return;
+        gemv_kernel<<<(unsigned)ceil_div(nrows, 4), 256, 0, st>>>(M, ld, nrows, ncols, x, out,
+                                                                   honour_done ? state : nullptr);
+        LSRN_HIP(hipGetLastError());
+    }
+
+    State host_state() {
+        State h;
+        LSRN_HIP(hipMemcpyAsync(&h, state, sizeof(State), hipMemcpyDeviceToHost, st));
+        LSRN_HIP(hipStreamSynchronize(st));
+        return h;
+    }
+};
+
+int64_t default_maxiter(const IterProblem &pb, const lsrn_options &opt, double &sl, double &su) {
+    const double lo = std::sqrt((double)pb.s) - std::sqrt((double)pb.r) - opt.t_margin;
+    const double hi = std::sqrt((double)pb.s) + std::sqrt((double)pb.r) + opt.t_margin;
+    sl = su = 0.0;
+    int64_t cs = -1;
+    if (lo > 0.0) {
+        su = 1.0 / lo;
+        sl = 1.0 / hi;
+        const double rate = (su - sl) / (su + sl);
+        cs = rate > 0.0 ? (int64_t)std::ceil((std::log(opt.tol) - std::log(2.0)) / std::log(rate)) + 1 : 1;
+    }
+    if (opt.max_iter > 0) return opt.max_iter;
+    return cs > 0 ? cs + 10 : 10 * pb.cols + 100;
+}
+
+// Chebyshev step lengths of Alg. 3 (k = 0 .. K); alpha_1 = 1/(d - c^2/(2d)).
+void cs_schedule(double sl, double su, double eps, std::vector<double> &al, std::vector<double> &be) {
+    const double d = 0.5 * (su * su + sl * sl), c = 0.5 * (su * su - sl * sl);
+    const double rate = (su - sl) / (su + sl);
+    const int64_t iters = rate > 0.0 ? (int64_t)std::ceil((std::log(eps) - std::log(2.0)) / std::log(rate)) + 1 : 1;
+    al.resize((size_t)iters);
+    be.resize((size_t)iters);
+    double alpha = 0.0, beta = 0.0;
+    for (int64_t k = 0; k < iters; ++k) {
+        if (k == 0) { beta = 0.0; alpha = 1.0 / d; }
+        else if (k == 1) { beta = 0.5 * (c / d) * (c / d); alpha = 1.0 / (d - c * c / (2.0 * d)); }
+        else { beta = (alpha * c / 2.0) * (alpha * c / 2.0); alpha = 1.0 / (d - alpha * c * c / 4.0); }
+        al[(size_t)k] = alpha;
+        be[(size_t)k] = beta;
+    }
+}
+
+constexpr int CHUNK = 8;  // iterations enqueued between convergence checks
+
+// ---- tall: K = [A; lambda I] N
+struct TallSolver {
+    Ctx &cx;
+    int64_t M, r;  // long length (rows + Tikhonov rows), short length
+    DevBuf ulong, v, wdir, y, t, wN;
+
+    explicit TallSolver(Ctx &c) : cx(c) {
+        M = cx.pb.rows + (cx.pb.lambda > 0.0 ? cx.pb.cols : 0);
+        r = cx.pb.r;
+        ulong.alloc((size_t)M * sizeof(double));
+        v.alloc((size_t)r * sizeof(double));
+        wdir.alloc((size_t)r * sizeof(double));
+        y.alloc((size_t)r * sizeof(double));
+        t.alloc((size_t)r * sizeof(double));
+        wN.alloc((size_t)cx.L * sizeof(double));
+    }
+
+    void load_rhs(const double *b) {
+        LSRN_HIP(hipMemcpyAsync(ulong.as<double>(), b, (size_t)cx.pb.rows * sizeof(double),
+                                hipMemcpyDeviceToDevice, cx.st));
+        if (M > cx.pb.rows)
+            fill_kernel<<<grid1(M - cx.pb.rows), 256, 0, cx.st>>>(M - cx.pb.rows, 0.0,
+                                                                  ulong.as<double>() + cx.pb.rows);
+    }
+
+    // t = N^T [A; lambda I]^T u
+    void at(const double *ulong_in) {
+        cx.sweep(OP_ATB, nullptr, const_cast<double *>(ulong_in), nullptr, nullptr);
+        cx.gemv(cx.Ptp, cx.L, r, cx.L, cx.z.as<double>(), t.as<double>());
+    }
+
+    int64_t lsqr(int64_t maxiter, double tol, bool &converged) {
+        cx.reset_state((int)maxiter);
+        at(ulong.as<double>());
+        lsqr_tall_init_kernel<<<1, SNT, 0, cx.st>>>(t.as<double>(), r, v.as<double>(),
+                                                    wdir.as<double>(), y.as<double>(), cx.state);
+        LSRN_HIP(hipGetLastError());
+        State h = cx.host_state();
+        while (!h.done) {
+            for (int k = 0; k < CHUNK; ++k) {
+                cx.gemv(cx.pb.P, cx.pb.ldp, cx.L, r, v.as<double>(), wN.as<double>());
+                cx.sweep(OP_LSQR_TALL, wN.as<double>(), ulong.as<double>(), nullptr, nullptr);
+                cx.gemv(cx.Ptp, cx.L, r, cx.L, cx.z.as<double>(), t.as<double>());
+                lsqr_tall_step_kernel<<<1, SNT, 0, cx.st>>>(t.as<double>(), r, v.as<double>(),
+                                                            wdir.as<double>(), y.as<double>(), tol,
+                                                            cx.state);
+            }
+            LSRN_HIP(hipGetLastError());
+            h = cx.host_state();
+        }
+        converged = h.converged != 0;
+        return h.iters;
+    }
+
+    int64_t cs(double sl, double su, double eps) {
+        std::vector<double> al, be;
+        cs_schedule(sl, su, eps, al, be);
+        cx.reset_state(0);
+        // r = b^, t = K^T r; v = 0, y = 0
+        at(ulong.as<double>());
+        fill_kernel<<<grid1(r), 256, 0, cx.st>>>(r, 0.0, v.as<double>());
+        fill_kernel<<<grid1(r), 256, 0, cx.st>>>(r, 0.0, y.as<double>());
+        for (size_t k = 0; k < al.size(); ++k) {
+            cs_short_kernel<<<grid1(r), 256, 0, cx.st>>>(r, v.as<double>(), t.as<double>(),
+                                                         y.as<double>(), al[k], be[k]);
+            cx.gemv(cx.pb.P, cx.pb.ldp, cx.L, r, v.as<double>(), wN.as<double>());
+            const bool last = k + 1 == al.size();
+            cx.sweep(OP_CS_TALL, wN.as<double>(), ulong.as<double>(), nullptr, nullptr, al[k]);
+            if (!last) cx.gemv(cx.Ptp, cx.L, r, cx.L, cx.z.as<double>(), t.as<double>());
+        }
+        LSRN_HIP(hipGetLastError());
+        return (int64_t)al.size();
+    }
+
+    void x_from_y(double *x) { cx.gemv(cx.pb.P, cx.pb.ldp, cx.L, r, y.as<double>(), x, false); }
+};
+
+// ---- fat: K = M^T A, T = A^T (rows = n)
+struct FatSolver {
+    Ctx &cx;
+    int64_t n, r;
+    DevBuf vt, wdir, u, t, wM;
+    double *x;
+
+    FatSolver(Ctx &c, double *xout) : cx(c), x(xout) {
+        n = cx.pb.rows;
+        r = cx.pb.r;
+        vt.alloc((size_t)n * sizeof(double));
+        wdir.alloc((size_t)n * sizeof(double));
+        u.alloc((size_t)r * sizeof(double));
+        t.alloc((size_t)r * sizeof(double));
+        wM.alloc((size_t)cx.L * sizeof(double));
+    }
+
+    // LSQR on M^T A x = c with c given in t.
+    int64_t lsqr(int64_t maxiter, double tol, bool &converged) {
+        fill_kernel<<<grid1(n), 256, 0, cx.st>>>(n, 0.0, x);
+        fill_kernel<<<grid1(n), 256, 0, cx.st>>>(n, 0.0, vt.as<double>());
+        cx.reset_state((int)maxiter);
+        lsqr_fat_init_kernel<<<1, SNT, 0, cx.st>>>(t.as<double>(), r, u.as<double>(), cx.state);
+        // start sweep: v~_1 = A^T M u_1
+        cx.gemv(cx.pb.P, cx.pb.ldp, cx.L, r, u.as<double>(), wM.as<double>());
+        cx.sweep(OP_LSQR_FAT, wM.as<double>(), vt.as<double>(), x, wdir.as<double>());
+        cx.gemv(cx.Ptp, cx.L, r, cx.L, cx.z.as<double>(), t.as<double>());
+        lsqr_fat_step_kernel<<<1, SNT, 0, cx.st>>>(t.as<double>(), r, u.as<double>(), 1, tol, cx.state);
+        LSRN_HIP(hipGetLastError());
+        State h = cx.host_state();
+        while (!h.done) {
+            for (int k = 0; k < CHUNK; ++k) {
+                cx.gemv(cx.pb.P, cx.pb.ldp, cx.L, r, u.as<double>(), wM.as<double>());
+                cx.sweep(OP_LSQR_FAT, wM.as<double>(), vt.as<double>(), x, wdir.as<double>());
+                cx.gemv(cx.Ptp, cx.L, r, cx.L, cx.z.as<double>(), t.as<double>());
+                lsqr_fat_step_kernel<<<1, SNT, 0, cx.st>>>(t.as<double>(), r, u.as<double>(), 0, tol,
+                                                           cx.state);
+            }
+            LSRN_HIP(hipGetLastError());
+            h = cx.host_state();
+        }
+        lsqr_fat_finish_kernel<<<grid1(n), 256, 0, cx.st>>>(n, x, wdir.as<double>(), cx.state);
+        LSRN_HIP(hipGetLastError());
+        converged = h.converged != 0;
+        return h.iters;
+    }
+
+    // Alg. 3 on M^T A x = c (c in t): x, v long; residual short.
+    int64_t cs(double sl, double su, double eps) {
+        std::vector<double> al, be;
+        cs_schedule(sl, su, eps, al, be);
+        cx.reset_state(0);
+        fill_kernel<<<grid1(n), 256, 0, cx.st>>>(n, 0.0, x);
+        fill_kernel<<<grid1(n), 256, 0, cx.st>>>(n, 0.0, vt.as<double>());
+        double *res = u.as<double>();
+        LSRN_HIP(hipMemcpyAsync(res, t.as<double>(), (size_t)r * sizeof(double),
+                                hipMemcpyDeviceToDevice, cx.st));
+        for (size_t k = 0; k < al.size(); ++k) {
+            cx.gemv(cx.pb.P, cx.pb.ldp, cx.L, r, res, wM.as<double>());
+            cx.sweep(OP_CS_FAT, wM.as<double>(), vt.as<double>(), x, nullptr, al[k], be[k]);
+            cx.gemv(cx.Ptp, cx.L, r, cx.L, cx.z.as<double>(), t.as<double>());
+            axpby_kernel<<<grid1(r), 256, 0, cx.st>>>(r, -al[k], t.as<double>(), 1.0, res);
+        }
+        LSRN_HIP(hipGetLastError());
+        return (int64_t)al.size();
+    }
+};
+
+template <int CPT>
+void launch_resid_tall(Ctx &cx, const double *b, const double *x, double *hi, double *lo) {
+    resid_dd_tall_kernel<CPT><<<cx.nblocks, NT, 0, cx.st>>>(
+        cx.pb.T, cx.pb.ldt, cx.pb.rows, cx.L, cx.nblocks, cx.rows_per_block, b, x, cx.pb.lambda, hi, lo);
+}
+
+template <int CPT>
+void launch_ax_fat(Ctx &cx, const double *x, double *hi, double *lo) {
+    ax_dd_fat_kernel<CPT><<<cx.nblocks, NT, 0, cx.st>>>(cx.pb.T, cx.pb.ldt, cx.pb.rows, cx.L,
+                                                        cx.rows_per_block, x, hi, lo);
+}
+
+double host_norm(const double *d, int64_t n, hipStream_t st) {
+    std::vector<double> h((size_t)n);
+    LSRN_HIP(hipMemcpyAsync(h.data(), d, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, st));
+    LSRN_HIP(hipStreamSynchronize(st));
+    double s = 0.0;
+    for (double v : h) s += v * v;
+    return std::sqrt(s);
+}
+
+}  // namespace
+
+IterResult iterate(const IterProblem &pb, const double *b, double *x, const lsrn_options &opt,
+                   hipStream_t st) {
+    IterResult res;
+    Ctx cx(pb, st);
+    double sl = 0.0, su = 0.0;
+    const int64_t maxiter = default_maxiter(pb, opt, sl, su);
+    res.sigma_l = sl;
+    res.sigma_u = su;
+    const bool cs = opt.method == LSRN_CHEBYSHEV;
+    if (cs && su <= 0.0)
+        fail(LSRN_E_UNSUPPORTED, "Chebyshev bounds need sqrt(s) - sqrt(r) - t > 0");
+
+    hipEvent_t e0, e1, e2;
+    LSRN_HIP(hipEventCreate(&e0));
+    LSRN_HIP(hipEventCreate(&e1));
+    LSRN_HIP(hipEventCreate(&e2));
+    LSRN_HIP(hipEventRecord(e0, st));
+    const int64_t L = pb.cols, r = pb.r;
+    bool conv = true;
+
+    if (pb.tall) {
+        TallSolver ts(cx);
+        ts.load_rhs(b);
+        res.iters = cs ? ts.cs(sl, su, opt.tol) : ts.lsqr(maxiter, opt.tol, conv);
+        ts.x_from_y(x);
+        LSRN_HIP(hipEventRecord(e1, st));
+        LSRN_HIP(hipStreamSynchronize(st));
+        // refinement: (A N)^T (A N) dy = N^T h, h = A^T (b - A x) - lambda^2 x in dd
+        if (opt.refine > 0) {
+            DevBuf hhi((size_t)cx.nblocks * L * sizeof(double)), hlo((size_t)cx.nblocks * L * sizeof(double));
+            DevBuf h((size_t)L * sizeof(double)), c((size_t)r * sizeof(double));
+            DevBuf zc((size_t)r * sizeof(double)), rc((size_t)r * sizeof(double)), pc((size_t)r * sizeof(double));
+            DevBuf dx((size_t)L * sizeof(double));
+            for (int step = 0; step < opt.refine; ++step) {
+                if (cx.cpt == 2) launch_resid_tall<2>(cx, b, x, hhi.as<double>(), hlo.as<double>());
+                else if (cx.cpt == 4) launch_resid_tall<4>(cx, b, x, hhi.as<double>(), hlo.as<double>());
+                else if (cx.cpt == 8) launch_resid_tall<8>(cx, b, x, hhi.as<double>(), hlo.as<double>());
+                else launch_resid_tall<16>(cx, b, x, hhi.as<double>(), hlo.as<double>());
+                LSRN_HIP(hipGetLastError());
+                reduce_dd_kernel<<<(unsigned)ceil_div(L, 256), 256, 0, st>>>(
+                    hhi.as<double>(), hlo.as<double>(), cx.nblocks, (int)L, nullptr, h.as<double>(), nullptr);
+                cx.gemv(cx.Ptp, L, r, L, h.as<double>(), c.as<double>(), false);
+                const int cg_max = 200;
+                cg_init_kernel<<<1, SNT, 0, st>>>(c.as<double>(), r, zc.as<double>(), rc.as<double>(),
+                                                  pc.as<double>(), opt.refine_tol, cg_max, cx.state);
+                State hs = cx.host_state();
+                while (!hs.done) {
+                    for (int k = 0; k < CHUNK; ++k) {
+                        cx.gemv(pb.P, pb.ldp, L, r, pc.as<double>(), ts.wN.as<double>());
+                        cx.sweep(OP_NORMAL, ts.wN.as<double>(), nullptr, nullptr, nullptr);
+                        cx.gemv(cx.Ptp, L, r, L, cx.z.as<double>(), ts.t.as<double>());
+                        cg_step_kernel<<<1, SNT, 0, st>>>(ts.t.as<double>(), r, zc.as<double>(),
+                                                          rc.as<double>(), pc.as<double>(), cx.state);
+                    }
+                    LSRN_HIP(hipGetLastError());
+                    hs = cx.host_state();
+                }
+                res.refine_iters += hs.iters;
+                cx.gemv(pb.P, pb.ldp, L, r, zc.as<double>(), dx.as<double>(), false);
+                axpby_kernel<<<grid1(L), 256, 0, st>>>(L, 1.0, dx.as<double>(), 1.0, x);
+                LSRN_HIP(hipGetLastError());
+                ++res.refine_steps;
+                const double dn = host_norm(dx.as<double>(), L, st), xn = host_norm(x, L, st);
+                if (dn <= 1e-15 * xn) break;
+            }
+        }
+        LSRN_HIP(hipStreamSynchronize(st));  // before the solver's buffers are freed
+    } else {
+        FatSolver fs(cx, x);
+        // c = M^T b
+        cx.gemv(cx.Ptp, L, r, L, b, fs.t.as<double>(), false);
+        res.iters = cs ? fs.cs(sl, su, opt.tol) : fs.lsqr(maxiter, opt.tol, conv);
+        LSRN_HIP(hipEventRecord(e1, st));
+        if (opt.refine > 0) {
+            const int64_t n = pb.rows;
+            DevBuf zhi((size_t)cx.nblocks * L * sizeof(double)), zlo((size_t)cx.nblocks * L * sizeof(double));
+            DevBuf thi((size_t)L * sizeof(double)), tlo((size_t)L * sizeof(double));
+            DevBuf xsave((size_t)n * sizeof(double));
+            for (int step = 0; step < opt.refine; ++step) {
+                if (cx.cpt == 2) launch_ax_fat<2>(cx, x, zhi.as<double>(), zlo.as<double>());
+                else if (cx.cpt == 4) launch_ax_fat<4>(cx, x, zhi.as<double>(), zlo.as<double>());
+                else if (cx.cpt == 8) launch_ax_fat<8>(cx, x, zhi.as<double>(), zlo.as<double>());
+                else launch_ax_fat<16>(cx, x, zhi.as<double>(), zlo.as<double>());
+                LSRN_HIP(hipGetLastError());
+                reduce_dd_kernel<<<(unsigned)ceil_div(L, 256), 256, 0, st>>>(
+                    zhi.as<double>(), zlo.as<double>(), cx.nblocks, (int)L, b, thi.as<double>(), tlo.as<double>());
+                // e = M^T (b - A x) with dd accumulation
+                gemv_t_dd_kernel<<<(unsigned)ceil_div(r, 4), 256, 0, st>>>(
+                    pb.P, pb.ldp, L, r, thi.as<double>(), tlo.as<double>(), fs.t.as<double>());
+                LSRN_HIP(hipGetLastError());
+                LSRN_HIP(hipMemcpyAsync(xsave.as<double>(), x, (size_t)n * sizeof(double),
+                                        hipMemcpyDeviceToDevice, st));
+                bool c2 = true;
+                res.refine_iters += cs ? fs.cs(sl, su, opt.tol) : fs.lsqr(maxiter, opt.tol, c2);
+                // fs wrote the correction into x; x = xsave + dx
+                const double dn = host_norm(x, n, st);
+                axpby_kernel<<<grid1(n), 256, 0, st>>>(n, 1.0, xsave.as<double>(), 1.0, x);
+                LSRN_HIP(hipGetLastError());
+                ++res.refine_steps;
+                const double xn = host_norm(x, n, st);
+                if (dn <= 1e-15 * xn) break;
+            }
+        }
+        LSRN_HIP(hipStreamSynchronize(st));  // before the solver's buffers are freed
+    }
+    LSRN_HIP(hipEventRecord(e2, st));
+    LSRN_HIP(hipEventSynchronize(e2));
+    float ms1 = 0.f, ms2 = 0.f;
+    LSRN_HIP(hipEventElapsedTime(&ms1, e0, e1));
+    LSRN_HIP(hipEventElapsedTime(&ms2, e1, e2));
+    res.t_iter_ms = ms1;
+    res.t_refine_ms = ms2;
+    res.converged = conv;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipEventDestroy(e2);
+    return res;
+}
+
+}  // namespace lsrn

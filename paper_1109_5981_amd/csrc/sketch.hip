@@ -1,0 +1,270 @@
+// sketch.hip -- the random normal projection of Alg. 1/2 step 3.
+//
+// X = G T for the tall view T of A (K x d, row-major): X is s x d, written
+// column-major.  G (s x K) is generated on the fly from the Philox stream
+// (rng.hpp) into LDS, one 128 x 16 tile at a time, and never reaches HBM.
+// The product runs on the FP64 matrix cores (v_mfma_f64_16x16x4f64): each
+// 256-thread workgroup owns a 128 x 128 tile of X and one slice of K; the
+// slices are summed in a fixed order by a second kernel.
+#include "internal.hpp"
+#include "rng.hpp"
+
+namespace lsrn {
+
+namespace {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 128;   // rows of X (sketch rows i) per workgroup
+constexpr int BN = 128;   // cols of X per workgroup
+constexpr int KT = 16;    // k per LDS stage (four MFMA k-steps)
+constexpr int LDP = 144;  // LDS row pitch in doubles: 144*2 = 288 = 32 (mod 64)
+                          // dwords, so the four 16-lane groups of a wave read
+                          // two disjoint bank halves
+constexpr int NT = 256;
+
+// One MFMA 16x16x4 f64 step: lane l supplies A[l%16][l/16] (a 16x4 slice of
+// G) and B[l/16][l%16] (a 4x16 slice of T); the 16x16 accumulator holds
+// D[4*(l/16) + v][l%16] in element v of lane l.
+__device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// G(i, k) for the 128 rows of the tile and the 16 k of one stage:
+// 128 rows x 4 Philox blocks; thread t takes row t%128 and blocks
+// (t/128) and (t/128)+2 of the stage.
+__device__ __forceinline__ void gen_g_stage(double (*Gs)[LDP], uint64_t seed, int64_t m0,
+                                            int64_t kstage) {
+    const int t = threadIdx.x;
+    const int row = t & (BM - 1);
+    const int qb = t >> 7;  // 0 or 1
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int qloc = qb + 2 * h;  // 0..3
+        double g[4];
+        gauss4(seed, (uint64_t)(m0 + row), (uint64_t)((kstage >> 2) + qloc), g);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) Gs[qloc * 4 + j][row] = g[j];
+    }
+}
+
+// 16 rows x 128 columns of T for one stage into registers (zero outside
+// [k0, kend) x [0, d)).
+template <bool VEC2>
+__device__ __forceinline__ void load_t_stage(const double *__restrict__ T, int64_t ldt,
+                                             int64_t kstage, int64_t kend, int64_t n0, int64_t d,
+                                             double2 (&reg)[4]) {
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+        const int idx = it * NT + threadIdx.x;
+        const int kk = idx >> 6;          // 0..15
+        const int c2 = (idx & 63) * 2;    // 0..126
+        const int64_t k = kstage + kk, col = n0 + c2;
+        double2 v = make_double2(0.0, 0.0);
+        if (k < kend) {
+            const double *p = T + k * ldt + col;
+            if (VEC2 && col + 1 < d) {
+                v = *reinterpret_cast<const double2 *>(p);
+            } else {
+                if (col < d) v.x = p[0];
+                if (col + 1 < d) v.y = p[1];
+            }
+        }
+        reg[it] = v;
+    }
+}
+
+__device__ __forceinline__ void store_t_stage(double (*Ts)[LDP], const double2 (&reg)[4]) {
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+        const int idx = it * NT + threadIdx.x;
+        const int kk = idx >> 6, c2 = (idx & 63) * 2;
+        Ts[kk][c2] = reg[it].x;
+        Ts[kk][c2 + 1] = reg[it].y;
+    }
+}
+
+template <bool VEC2>
+__global__ void __launch_bounds__(NT, 2)
+sketch_mfma_kernel(const double *__restrict__ T, int64_t ldt, int64_t K, int64_t d, int64_t s,
+                   uint64_t seed, int64_t k_per_split, int tiles_m, double *__restrict__ Xp) {
+    __shared__ double Gs[2][KT][LDP];
+    __shared__ double Ts[2][KT][LDP];
+
+    const int tile = blockIdx.x;
+    const int64_t m0 = (int64_t)(tile % tiles_m) * BM;
+    const int64_t n0 = (int64_t)(tile / tiles_m) * BN;
+    const int64_t kbeg = (int64_t)blockIdx.y * k_per_split;
+    const int64_t kend = min(K, kbeg + k_per_split);
+    double *__restrict__ Xout = Xp + (int64_t)blockIdx.y * s * d;
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int lr = lane & 15, lk = lane >> 4;
+
+    f64x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+    const int64_t nstage = kend > kbeg ? ceil_div(kend - kbeg, KT) : 0;
+    double2 treg[4];
+    if (nstage > 0) {
+        gen_g_stage(Gs[0], seed, m0, kbeg);
+        load_t_stage<VEC2>(T, ldt, kbeg, kend, n0, d, treg);
+        store_t_stage(Ts[0], treg);
+    }
+    __syncthreads();
+
+    for (int64_t st = 0; st < nstage; ++st) {
+        const int buf = (int)(st & 1);
+        const bool more = st + 1 < nstage;
+        const int64_t knext = kbeg + (st + 1) * KT;
+        if (more) load_t_stage<VEC2>(T, ldt, knext, kend, n0, d, treg);
+#pragma unroll
+        for (int kk = 0; kk < KT / 4; ++kk) {
+            double a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = Gs[buf][kk * 4 + lk][wm * 64 + i * 16 + lr];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = Ts[buf][kk * 4 + lk][wn * 64 + j * 16 + lr];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = mfma16(a[i], b[j], acc[i][j]);
+        }
+        if (more) {
+            gen_g_stage(Gs[buf ^ 1], seed, m0, knext);
+            store_t_stage(Ts[buf ^ 1], treg);
+        }
+        __syncthreads();
+    }
+
+    // Column-major store: lane group lk holds rows 4*lk .. 4*lk+3 of each
+    // 16 x 16 block, so a column's 16 rows are 128 contiguous bytes.
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t col = n0 + wn * 64 + j * 16 + lr;
+            const int64_t rbase = m0 + wm * 64 + i * 16 + 4 * lk;
+            if (col < d) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    if (rbase + v < s) Xout[col * s + rbase + v] = acc[i][j][v];
+            }
+        }
+}
+
+// X[idx] = sum over slices of Xp[slice][idx], slices in ascending order.
+__global__ void __launch_bounds__(256)
+sum_slices_kernel(const double *__restrict__ Xp, int nslice, int64_t count, double *__restrict__ X) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        for (int sl = 0; sl < nslice; ++sl) acc += Xp[(int64_t)sl * count + t];
+        X[t] = acc;
+    }
+}
+
+// Rows lambda * I of the augmented matrix (Sec. 5): X(i, c) += lambda G(i, K + c).
+__global__ void __launch_bounds__(256)
+add_identity_rows_kernel(int64_t K, int64_t d, int64_t s, double lambda, uint64_t seed,
+                         double *__restrict__ X) {
+    const int64_t total = s * d;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = t / s, i = t % s;
+        const uint64_t col = (uint64_t)(K + c);
+        double g[4];
+        gauss4(seed, (uint64_t)i, col >> 2, g);
+        X[t] += lambda * g[col & 3];
+    }
+}
+
+__global__ void __launch_bounds__(256)
+transpose_kernel(int64_t rows, int64_t cols, const double *__restrict__ in, int64_t ldin,
+                 double *__restrict__ out) {
+    __shared__ double tile[32][33];
+    const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+    for (int k = ty; k < 32; k += 8) {
+        const int64_t r = r0 + k, c = c0 + tx;
+        tile[k][tx] = (r < rows && c < cols) ? in[r * ldin + c] : 0.0;
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+        const int64_t c = c0 + k, r = r0 + tx;
+        if (c < cols && r < rows) out[c * rows + r] = tile[tx][k];
+    }
+}
+
+struct SketchPlan {
+    int tiles_m, tiles_n, nsplit;
+    int64_t k_per_split;
+};
+
+SketchPlan plan_sketch(int64_t K, int64_t d, int64_t s) {
+    SketchPlan p;
+    p.tiles_m = (int)ceil_div(s, BM);
+    p.tiles_n = (int)ceil_div(d, BN);
+    const int64_t tiles = (int64_t)p.tiles_m * p.tiles_n;
+    const int64_t want = 2 * (int64_t)device_cus();  // two workgroups per CU
+    int64_t nsplit = tiles >= want ? 1 : ceil_div(want, tiles);
+    // keep at least 8 stages per slice and the partial sums under 2 GiB
+    nsplit = std::min<int64_t>(nsplit, std::max<int64_t>(1, K / (8 * KT)));
+    const int64_t cap = std::max<int64_t>(1, (int64_t(1) << 31) / (8 * s * d));
+    nsplit = std::max<int64_t>(1, std::min(nsplit, cap));
+    p.k_per_split = round_up(ceil_div(K, nsplit), KT);
+    p.nsplit = (int)ceil_div(K, p.k_per_split);
+    if (p.nsplit < 1) p.nsplit = 1;
+    return p;
+}
+
+}  // namespace
+
+size_t sketch_workspace_bytes(int64_t K, int64_t d, int64_t s) {
+    SketchPlan p = plan_sketch(K, d, s);
+    return p.nsplit > 1 ? (size_t)p.nsplit * (size_t)s * (size_t)d * sizeof(double) : 0;
+}
+
+void sketch_rows(int64_t K, int64_t d, const double *T, int64_t ldt, double lambda, int64_t s,
+                 uint64_t seed, double *X, hipStream_t st) {
+    SketchPlan p = plan_sketch(K, d, s);
+    DevBuf part;
+    double *Xp = X;
+    if (p.nsplit > 1) {
+        part.alloc((size_t)p.nsplit * (size_t)s * (size_t)d * sizeof(double));
+        Xp = part.as<double>();
+    }
+    dim3 grid((unsigned)(p.tiles_m * p.tiles_n), (unsigned)p.nsplit);
+    const bool vec2 = (ldt % 2 == 0) && ((reinterpret_cast<uintptr_t>(T) & 15) == 0);
+    if (vec2)
+        sketch_mfma_kernel<true><<<grid, NT, 0, st>>>(T, ldt, K, d, s, seed, p.k_per_split,
+                                                      p.tiles_m, Xp);
+    else
+        sketch_mfma_kernel<false><<<grid, NT, 0, st>>>(T, ldt, K, d, s, seed, p.k_per_split,
+                                                       p.tiles_m, Xp);
+    LSRN_HIP(hipGetLastError());
+    const int64_t count = s * d;
+    const int blocks = (int)std::min<int64_t>(ceil_div(count, 256), 8192);
+    if (p.nsplit > 1) {
+        sum_slices_kernel<<<blocks, 256, 0, st>>>(Xp, p.nsplit, count, X);
+        LSRN_HIP(hipGetLastError());
+    }
+    if (lambda > 0.0) {
+        add_identity_rows_kernel<<<blocks, 256, 0, st>>>(K, d, s, lambda, seed, X);
+        LSRN_HIP(hipGetLastError());
+    }
+    if (p.nsplit > 1) LSRN_HIP(hipStreamSynchronize(st));  // before `part` is freed
+}
+
+void transpose(int64_t rows, int64_t cols, const double *in, int64_t ldin, double *out,
+               hipStream_t st) {
+    dim3 grid((unsigned)ceil_div(cols, 32), (unsigned)ceil_div(rows, 32));
+    transpose_kernel<<<grid, 256, 0, st>>>(rows, cols, in, ldin, out);
+    LSRN_HIP(hipGetLastError());
+}
+
+}  // namespace lsrn

@@ -1,0 +1,202 @@
+"""ctypes binding of liblsrn.so (include/lsrn.h) for torch device tensors.
+
+Argument marshalling only: every step of LSRN runs in the HIP kernels of the
+library.  Arrays are torch float64 tensors on the current HIP device; work
+is ordered on torch's current stream.  If the library has not been built
+this module raises at first use (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, fields
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblsrn.so")
+
+LSQR, CHEBYSHEV = 0, 1
+ROW_MAJOR, COL_MAJOR = 0, 1
+STATUS = {0: "ok", 1: "invalid argument", 2: "out of device memory", 3: "HIP runtime error",
+          4: "not converged", 5: "unsupported"}
+
+
+class LSRNError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class Options(C.Structure):
+    _fields_ = [("gamma", C.c_double), ("lambda_", C.c_double), ("tol", C.c_double),
+                ("rcond", C.c_double), ("t_margin", C.c_double), ("refine_tol", C.c_double),
+                ("seed", C.c_uint64), ("max_iter", C.c_int64), ("method", C.c_int32),
+                ("refine", C.c_int32), ("reserved", C.c_int32 * 4)]
+
+
+class Info(C.Structure):
+    _fields_ = [("s", C.c_int64), ("d", C.c_int64), ("rank", C.c_int64), ("iters", C.c_int64),
+                ("refine_steps", C.c_int64), ("refine_iters", C.c_int64), ("sweeps", C.c_int64),
+                ("tall", C.c_int32), ("converged", C.c_int32), ("sigma_l", C.c_double),
+                ("sigma_u", C.c_double), ("sigma_max", C.c_double), ("sigma_min_kept", C.c_double),
+                ("t_sketch_ms", C.c_double), ("t_svd_ms", C.c_double), ("t_iter_ms", C.c_double),
+                ("t_refine_ms", C.c_double), ("t_total_ms", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+
+EXPORTS = ["lsrn_default_options", "lsrn_status_string", "lsrn_last_error", "lsrn_solve_dense",
+           "lsrn_workspace_bytes", "lsrn_philox_words", "lsrn_gauss_fill", "lsrn_sketch_dense",
+           "lsrn_precond", "lsrn_iterate_dense"]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1109_5981_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        P, I64, I32, U64, D = C.c_void_p, C.c_int64, C.c_int32, C.c_uint64, C.c_double
+        L.lsrn_default_options.argtypes = [C.POINTER(Options)]
+        L.lsrn_status_string.argtypes = [C.c_int]
+        L.lsrn_status_string.restype = C.c_char_p
+        L.lsrn_last_error.restype = C.c_char_p
+        L.lsrn_solve_dense.argtypes = [I64, I64, P, I64, I32, P, P, C.POINTER(Options),
+                                       C.POINTER(Info), P]
+        L.lsrn_workspace_bytes.argtypes = [I64, I64, I32, C.POINTER(Options)]
+        L.lsrn_workspace_bytes.restype = C.c_size_t
+        L.lsrn_philox_words.argtypes = [U64, I64, I64, I64, I64, P, P]
+        L.lsrn_gauss_fill.argtypes = [U64, I64, I64, I64, I64, P, P]
+        L.lsrn_sketch_dense.argtypes = [I64, I64, P, I64, I32, D, I64, U64, P, P]
+        L.lsrn_precond.argtypes = [I64, I64, P, D, P, P, C.POINTER(C.c_int64),
+                                   C.POINTER(C.c_int64), P]
+        L.lsrn_iterate_dense.argtypes = [I64, I64, P, I64, I32, P, P, I64, I64, I64, P,
+                                         C.POINTER(Options), C.POINTER(Info), P]
+        for name in EXPORTS:
+            if name not in ("lsrn_default_options", "lsrn_status_string", "lsrn_last_error",
+                            "lsrn_workspace_bytes"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(st: int):
+    if st != 0:
+        raise LSRNError(st, lib().lsrn_last_error().decode())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_f64(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64):
+        raise TypeError(f"{name} must be a float64 tensor on the GPU")
+    return t
+
+
+def options(**kw) -> Options:
+    o = Options()
+    lib().lsrn_default_options(C.byref(o))
+    alias = {"lam": "lambda_", "lambda": "lambda_"}
+    for k, v in kw.items():
+        k = alias.get(k, k)
+        if k == "method" and isinstance(v, str):
+            v = {"lsqr": LSQR, "chebyshev": CHEBYSHEV, "cs": CHEBYSHEV}[v.lower()]
+        setattr(o, k, v)
+    return o
+
+
+def _layout_dims(A: torch.Tensor, layout: int):
+    """(m, n, lda) of the least-squares matrix stored in A.  Row-major: A has
+    shape (m, n).  Column-major: A holds A^T with shape (n, m)."""
+    if A.dim() != 2 or A.stride(1) != 1:
+        raise ValueError("A must be a 2-D tensor with unit stride in its last dimension")
+    rows, cols = A.shape
+    lda = A.stride(0) if rows > 1 else cols
+    return (rows, cols, lda) if layout == ROW_MAJOR else (cols, rows, lda)
+
+
+def solve_dense(A: torch.Tensor, b: torch.Tensor, x: torch.Tensor | None = None, *,
+                layout: int = ROW_MAJOR, **opts):
+    """Min-length least-squares solution of min ||A x - b|| (Alg. 1 / Alg. 2).
+    Returns (x, info dict)."""
+    _dev_f64(A, "A")
+    _dev_f64(b, "b")
+    m, n, lda = _layout_dims(A, layout)
+    if b.numel() != m or not b.is_contiguous():
+        raise ValueError("b must be contiguous with m entries")
+    if x is None:
+        x = torch.empty(n, dtype=torch.float64, device=A.device)
+    o, info = options(**opts), Info()
+    st = lib().lsrn_solve_dense(m, n, A.data_ptr(), lda, layout, b.data_ptr(), x.data_ptr(),
+                                C.byref(o), C.byref(info), _stream())
+    _check(st)
+    return x, info.as_dict()
+
+
+def workspace_bytes(m: int, n: int, layout: int = ROW_MAJOR, **opts) -> int:
+    o = options(**opts)
+    return int(lib().lsrn_workspace_bytes(m, n, layout, C.byref(o)))
+
+
+def philox_words(seed: int, row0: int, nrows: int, q0: int, nq: int, device="cuda") -> torch.Tensor:
+    """int32 tensor (nrows, nq, 4) holding the uint32 Philox words bit for bit."""
+    out = torch.empty((nrows, nq, 4), dtype=torch.int32, device=device)
+    _check(lib().lsrn_philox_words(seed, row0, nrows, q0, nq, out.data_ptr(), _stream()))
+    return out
+
+
+def gauss_fill(seed: int, row0: int, nrows: int, col0: int, ncols: int, device="cuda"):
+    out = torch.empty((nrows, ncols), dtype=torch.float64, device=device)
+    _check(lib().lsrn_gauss_fill(seed, row0, nrows, col0, ncols, out.data_ptr(), _stream()))
+    return out
+
+
+def sketch_dense(A: torch.Tensor, s: int, seed: int = 0, lam: float = 0.0,
+                 layout: int = ROW_MAJOR) -> torch.Tensor:
+    """The sketch X = G T (s x d) of Alg. 1/2 step 3, returned as a (d, s)
+    tensor holding X column-major (so `.T` is X)."""
+    _dev_f64(A, "A")
+    m, n, lda = _layout_dims(A, layout)
+    d = n if (m >= n or lam > 0) else m
+    X = torch.empty((d, s), dtype=torch.float64, device=A.device)
+    _check(lib().lsrn_sketch_dense(m, n, A.data_ptr(), lda, layout, lam, s, seed, X.data_ptr(),
+                                   _stream()))
+    return X
+
+
+def precond(Xcm: torch.Tensor, rcond: float = 0.0):
+    """Steps 4-5 on a sketch given column-major as a (d, s) tensor.
+    Returns (rank, sigma (d,), P (d, r), sweeps)."""
+    _dev_f64(Xcm, "X")
+    d, s = Xcm.shape
+    Xcm = Xcm.contiguous()
+    sigma = torch.empty(d, dtype=torch.float64, device=Xcm.device)
+    P = torch.empty((d, d), dtype=torch.float64, device=Xcm.device)
+    r, sw = C.c_int64(), C.c_int64()
+    _check(lib().lsrn_precond(s, d, Xcm.data_ptr(), rcond, sigma.data_ptr(), P.data_ptr(),
+                              C.byref(r), C.byref(sw), _stream()))
+    return int(r.value), sigma, P[:, : r.value], int(sw.value)
+
+
+def iterate_dense(A: torch.Tensor, b: torch.Tensor, P: torch.Tensor, s: int, *,
+                  layout: int = ROW_MAJOR, **opts):
+    """Steps 6-7 with a given preconditioner P (d x r, row-major rows)."""
+    _dev_f64(A, "A")
+    _dev_f64(b, "b")
+    _dev_f64(P, "P")
+    if P.stride(1) != 1:
+        raise ValueError("P must have unit stride in its last dimension")
+    m, n, lda = _layout_dims(A, layout)
+    x = torch.empty(n, dtype=torch.float64, device=A.device)
+    o, info = options(**opts), Info()
+    r = P.shape[1]
+    _check(lib().lsrn_iterate_dense(m, n, A.data_ptr(), lda, layout, b.data_ptr(), P.data_ptr(),
+                                    P.stride(0), r, s, x.data_ptr(), C.byref(o), C.byref(info),
+                                    _stream()))
+    return x, info.as_dict()

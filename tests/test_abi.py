@@ -1,0 +1,52 @@
+"""The C-ABI library loads and exports every entry point include/lsrn.h
+declares (no GPU needed: nothing is called except host-only queries)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lsrn.h")
+LIB = os.path.join(ROOT, "paper_1109_5981_amd", "liblsrn.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lsrn_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("lsrn_solve_dense", "lsrn_sketch_dense", "lsrn_precond",
+                     "lsrn_iterate_dense", "lsrn_philox_words", "lsrn_gauss_fill",
+                     "lsrn_default_options", "lsrn_last_error", "lsrn_workspace_bytes"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(LIB):
+        pytest.skip("liblsrn.so not built")
+    L = C.CDLL(LIB)
+    for name in declared_functions():
+        assert hasattr(L, name), f"{name} missing from liblsrn.so"
+
+
+def test_binding_lists_every_export():
+    from paper_1109_5981_amd import lsrn
+    assert sorted(lsrn.EXPORTS) == declared_functions()
+
+
+def test_default_options_and_struct_layout():
+    if not os.path.exists(LIB):
+        pytest.skip("liblsrn.so not built")
+    from paper_1109_5981_amd import lsrn
+    o = lsrn.options()
+    assert o.gamma == 2.0 and o.tol == 1e-14 and o.t_margin == 1.0 and o.method == 0
+    assert o.refine == 0 and o.lambda_ == 0.0 and o.refine_tol == 1e-6
+    assert C.sizeof(lsrn.Options) == 6 * 8 + 8 + 8 + 4 + 4 + 16
+    L = lsrn.lib()
+    assert L.lsrn_status_string(5) == b"unsupported"
+    # host-only size query
+    assert lsrn.workspace_bytes(200000, 2000) > 200000 * 8
