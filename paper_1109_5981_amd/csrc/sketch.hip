@@ -25,7 +25,7 @@ constexpr int NT = 256;
 
 // One MFMA 16x16x4 f64 step: lane l supplies A[l%16][l/16] (a 16x4 slice of
 // G) and B[l/16][l%16] (a 4x16 slice of T); the 16x16 accumulator holds
-// D[4*(l/16) + v][l%16] in element v of lane l.
+// D[l/16 + 4 v][l%16] in element v of lane l.
 __device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
@@ -141,18 +141,18 @@ sketch_mfma_kernel(const double *__restrict__ T, int64_t ldt, int64_t K, int64_t
         __syncthreads();
     }
 
-    // Column-major store: lane group lk holds rows 4*lk .. 4*lk+3 of each
-    // 16 x 16 block, so a column's 16 rows are 128 contiguous bytes.
+    // Column-major store: element v of lane group lk is row lk + 4 v of its
+    // 16 x 16 block, so for each v the four groups write 4 consecutive rows.
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int64_t col = n0 + wn * 64 + j * 16 + lr;
-            const int64_t rbase = m0 + wm * 64 + i * 16 + 4 * lk;
+            const int64_t rbase = m0 + wm * 64 + i * 16 + lk;
             if (col < d) {
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
-                    if (rbase + v < s) Xout[col * s + rbase + v] = acc[i][j][v];
+                    if (rbase + 4 * v < s) Xout[col * s + rbase + 4 * v] = acc[i][j][v];
             }
         }
 }
