@@ -1,0 +1,246 @@
+"""Benchmark: LSRN least-squares solves on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+One step is one complete LSRN solve (Alg. 1 or 2): Philox G + FP64 MFMA
+sketch, QR + Jacobi SVD, rank cutoff and N, LSQR (or Chebyshev) with fused
+one-pass sweeps, x = N y, and double-double refinement to reach relative
+error 1e-10.  The default workload is the rank-deficient over-determined
+problem m = 200000, n = 2000, rank 1800, sigma log-spaced 1 .. 1e-6,
+b ~ N(0, 1), gamma = 2, tolerance 1e-14 (synthetic, seeded; built on the
+GPU before timing).  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+FP64_MFMA_PEAK_TFS = 78.6    # MI355X dense FP64 matrix
+
+WORKLOADS = {
+    "rankdef_200000x2000": dict(m=200_000, n=2000, rank=1800, smin=1e-6, seed=12, fat=False),
+    "rankdef_2000x200000": dict(m=200_000, n=2000, rank=1800, smin=1e-6, seed=112, fat=True),
+    "dense_2000x100": dict(m=2000, n=100, rank=100, smin=1e-6, seed=11, fat=False),
+}
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return float("nan")
+    k = (len(xs) - 1) * q / 100.0
+    f, c = math.floor(k), math.ceil(k)
+    return xs[f] if f == c else xs[f] + (xs[c] - xs[f]) * (k - f)
+
+
+def cpu_baseline(A_np, b_np, s, d, r, iters_per_solve, sweeps, tall, budget_s=20.0):
+    """The oracle as it stands, timed on a bounded sample of the same solve and
+    scaled to solves/s: sketch rows, a QR and one Jacobi sweep of reduced
+    order scaled by their flop counts, and two iterations on the full A."""
+    import numpy as np
+
+    import oracle
+
+    t_start = time.perf_counter()
+    threads = oracle.num_threads()
+    M = oracle.Matrix.dense(A_np) if tall else oracle.Matrix.dense_colmajor(A_np)
+    # 1) sketch: the first `rows` rows of G times A (each row costs the same)
+    rows = max(2, threads)
+    t0 = time.perf_counter()
+    oracle.sketch(M, rows, 0)
+    t_sketch = (time.perf_counter() - t0) * s / rows
+    # 2) QR of an (s' x d') Gaussian with the same aspect, scaled by flops
+    rng = np.random.default_rng(0)
+    dq = min(d, 400)
+    sq = int(round(dq * s / d))
+    Xq = rng.standard_normal((sq, dq))
+    t0 = time.perf_counter()
+    Rq = oracle.qr_r(Xq)
+    tq = time.perf_counter() - t0
+    flops = lambda ss, dd: 2.0 * ss * dd * dd - 2.0 * dd ** 3 / 3.0
+    t_qr = tq * flops(s, d) / flops(sq, dq)
+    # 3) one Jacobi sweep of order d', scaled by d^3 and the sweep count
+    t0 = time.perf_counter()
+    oracle.jacobi_rt(Rq, max_sweeps=1)
+    t_jac = (time.perf_counter() - t0) * (d / dq) ** 3 * max(1, sweeps)
+    # 4) two LSQR iterations on the full problem with a preconditioner of the
+    #    right shape (the iteration's cost does not depend on its values)
+    P = rng.standard_normal((d, r)) / math.sqrt(d)
+    b_use = b_np
+    t0 = time.perf_counter()
+    oracle.lsrn_iterate(M, b_use, P, s, max_iter=2, tol=1e-300)
+    # the sample makes 5 products with A or A^T (start: A^T b; each iteration:
+    # A v and A^T u); an iteration costs 2
+    t_it = (time.perf_counter() - t0) * 2.0 / 5.0 * iters_per_solve
+    total = t_sketch + t_qr + t_jac + t_it
+    return {
+        "value": 1.0 / total,
+        "unit": "solves/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"oracle stages timed on samples and scaled: sketch of {rows} of {s} rows "
+                   f"(x{s / rows:.0f}); Householder QR of a {sq}x{dq} Gaussian (x flops); one "
+                   f"Jacobi sweep of order {dq} (x (d/{dq})^3 x {sweeps} sweeps); LSQR start + 2 "
+                   f"iterations on the full A (x 2/5 x {iters_per_solve})"),
+        "stage_s": {"sketch": t_sketch, "qr": t_qr, "jacobi": t_jac, "iterations": t_it},
+        "sample_wall_s": time.perf_counter() - t_start,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rankdef_200000x2000", choices=sorted(WORKLOADS))
+    ap.add_argument("--method", default="lsqr", choices=["lsqr", "chebyshev"])
+    ap.add_argument("--refine", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="do not time individual kernels with HIP events")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_1109_5981_amd import lsrn
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    wl = WORKLOADS[args.workload]
+    t_gen = time.perf_counter()
+    A, U, sigma, V = workloads.dense_problem_device(wl["m"], wl["n"], wl["rank"], wl["smin"],
+                                                    wl["seed"], device=dev)
+    if wl["fat"]:
+        # under-determined n x m problem stored column-major: the array of the
+        # tall generator read as A^T
+        m_ls, n_ls, layout = wl["n"], wl["m"], lsrn.COL_MAJOR
+        Ufat, Vfat = V, U
+    else:
+        m_ls, n_ls, layout = wl["m"], wl["n"], lsrn.ROW_MAJOR
+        Ufat, Vfat = U, V
+    b = workloads.rhs_gauss_device(m_ls, wl["seed"], device=dev)
+    # min-length solution of the generating (unrounded) matrix U diag(sigma) V^T
+    x_gen = Vfat @ ((Ufat.T @ b) / sigma)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t_gen
+
+    opts = dict(method=args.method, refine=args.refine, seed=2024, tol=1e-14,
+                profile=0 if args.no_profile else 1)
+    for _ in range(args.warmup):
+        x, info = lsrn.solve_dense(A, b, layout=layout, **opts)
+    torch.cuda.synchronize()
+
+    lat, infos = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        x, info = lsrn.solve_dense(A, b, layout=layout, **opts)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - ts) * 1e3)
+        infos.append(info)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+
+    # accuracy of the last solve
+    err_gen = (torch.linalg.norm(x - x_gen) / torch.linalg.norm(x_gen)).item()
+    if layout == lsrn.ROW_MAJOR:
+        res = b - A @ x
+        ne = torch.linalg.norm(A.T @ res) / (sigma[0] * torch.linalg.norm(res))
+    else:
+        res = b - A.T @ x
+        ne = torch.linalg.norm(A @ res) / (sigma[0] * torch.linalg.norm(res))
+    ne = ne.item()
+
+    info = infos[-1]
+    s, d, r = info["s"], info["d"], info["rank"]
+    K = wl["m"]                              # rows of the tall view
+    sketch_flop = 2.0 * s * K * d
+    sweeps_per_solve = info["sweep_kernels"] if info["sweep_kernels"] else None
+    bytes_per_sweep = 8.0 * K * d + 16.0 * K  # one read of A + long vector read/write
+    mean = lambda key: sum(i[key] for i in infos) / len(infos)
+    t_sketch_k = mean("t_sketch_kernel_ms")
+    t_sweep_k = mean("t_sweep_kernel_ms")
+    n_sweep = mean("sweep_kernels")
+
+    kernels = {}
+    if t_sketch_k > 0:
+        kernels["sketch_mfma_f64"] = {
+            "avg_ms": t_sketch_k, "launches_per_step": 1, "bound": "mfma",
+            "achieved": sketch_flop / (t_sketch_k * 1e-3) / 1e12, "unit": "TFLOP/s",
+            "peak": FP64_MFMA_PEAK_TFS}
+    if t_sweep_k > 0 and n_sweep > 0:
+        avg = t_sweep_k / n_sweep
+        kernels["row_sweep"] = {
+            "avg_ms": avg, "launches_per_step": n_sweep, "bound": "hbm",
+            "achieved": bytes_per_sweep / (avg * 1e-3) / 1e9, "unit": "GB/s",
+            "peak": HBM_PEAK_GBS}
+    roofline = None
+    if kernels:
+        dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches_per_step"])
+        kk = kernels[dom]
+        roofline = {"kernel": dom, "bound": kk["bound"], "achieved": round(kk["achieved"], 3),
+                    "peak": kk["peak"], "unit": kk["unit"],
+                    "frac": round(kk["achieved"] / kk["peak"], 4), "traffic": None}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        A_np = A.cpu().numpy()
+        b_np = b.cpu().numpy()
+        iters_total = info["iters"] + info["refine_iters"] + 2 * info["refine_steps"]
+        cpu = cpu_baseline(A_np, b_np, s, d, r, iters_total, info["sweeps"], not wl["fat"])
+
+    value = args.steps / elapsed
+    line = {
+        "metric": "LS solves/s + p99 latency at rel err 1e-10; sketch GEMM TFLOP/s, iter GB/s",
+        "value": round(value, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded; U, V Haar, sigma log-spaced, b ~ N(0,1))",
+        "config": {"workload": args.workload, "m": m_ls, "n": n_ls, "rank": wl["rank"],
+                   "gamma": 2.0, "tol": 1e-14, "method": args.method, "refine": args.refine},
+        "latency_ms": {"p50": round(percentile(lat, 50), 3), "p99": round(percentile(lat, 99), 3)},
+        "sketch_tflops": round(sketch_flop / (mean("t_sketch_ms") * 1e-3) / 1e12, 3),
+        "iter_gbs": (round(bytes_per_sweep * n_sweep / (mean("t_iter_ms") + mean("t_refine_ms"))
+                           / 1e6, 1) if n_sweep else None),
+        "stages_ms": {k: round(mean(k), 3) for k in
+                      ("t_sketch_ms", "t_svd_ms", "t_iter_ms", "t_refine_ms", "t_total_ms")},
+        "iters": info["iters"], "refine_iters": info["refine_iters"], "rank": r, "s": s,
+        "jacobi_sweeps": info["sweeps"],
+        "rel_err_vs_generator": err_gen,
+        "rel_normal_residual": ne,
+        "kernels": kernels,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "setup_s": round(t_gen, 2),
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -71,7 +71,10 @@ typedef struct lsrn_options {
     int32_t method;    /* lsrn_method; LSRN_LSQR                               */
     int32_t refine;    /* number of refinement steps whose residuals are
                           formed in double-double arithmetic; 0                 */
-    int32_t reserved[4];
+    int32_t profile;   /* nonzero: time every sketch and sweep kernel launch
+                          with HIP events on `stream` (lsrn_info fields
+                          t_*_kernel_ms); 0                                     */
+    int32_t reserved[3];
 } lsrn_options;
 
 typedef struct lsrn_info {
@@ -92,6 +95,12 @@ typedef struct lsrn_info {
     double t_iter_ms;       /* iterations incl. x = N y                          */
     double t_refine_ms;     /* refinement                                        */
     double t_total_ms;
+    /* with opt->profile: summed durations of the sketch GEMM kernel and of
+     * the row-sweep kernels (each sweep = one pass over A), and their counts */
+    double t_sketch_kernel_ms;
+    double t_sweep_kernel_ms;
+    int64_t sketch_kernels;
+    int64_t sweep_kernels;
 } lsrn_info;
 
 /* Fill *opt with the defaults listed above. */

@@ -94,6 +94,7 @@ def lib():
         L.orc_cs_iterations.restype = C.c_int64
         L.orc_cs_bounds.argtypes = [C.c_int64, C.c_int64, C.c_double, P, P]
         L.orc_lsrn_solve.argtypes = [P, P, P, P, P, P, P]
+        L.orc_lsrn_iterate.argtypes = [P, P, P, C.c_int64, C.c_int64, C.c_int64, P, P, P]
         L.orc_pinv_solve.argtypes = [P, P, C.c_double, P]
         L.orc_pinv_solve.restype = C.c_int64
         L.orc_num_threads.restype = C.c_int
@@ -353,6 +354,26 @@ def lsrn_solve(M: Matrix, b, *, gamma=2.0, tol=1e-14, method=LSQR, seed=0, rcond
                   info.sigma_l, info.sigma_u, info.t_sketch, info.t_svd, info.t_iter,
                   info.t_refine, bool(info.tall), bool(info.converged), sigma,
                   P[:, :r].copy())
+
+
+def lsrn_iterate(M: Matrix, b, P, s: int, *, tol=1e-14, method=LSQR, t_margin=1.0,
+                 max_iter=0, refine=0):
+    """Steps 6-7 (and refinement) with a given preconditioner P (d x r).
+    Returns (x, iters, converged, info dict of timings)."""
+    b = _f64(b)
+    P = _f64(P)
+    d, r = P.shape
+    o = _Options(2.0, tol, 0.0, t_margin, 0, max_iter, method, refine)
+    info = _Info()
+    x = np.zeros(M.n)
+    st = M._struct()
+    rc = lib().orc_lsrn_iterate(C.byref(st), _ptr(b), _ptr(P), r, r, s, C.byref(o), _ptr(x),
+                                C.byref(info))
+    if rc != 0:
+        raise ValueError(f"orc_lsrn_iterate failed ({rc})")
+    return x, int(info.iters), bool(info.converged), {"t_iter": info.t_iter,
+                                                     "t_refine": info.t_refine,
+                                                     "refine_steps": int(info.refine_steps)}
 
 
 def pinv_solve(M: Matrix, b, rcond: float = 0.0):

@@ -541,6 +541,7 @@ int64_t orc_cs(const orc_linop *K, const double *b, double sigma_l, double sigma
 typedef struct {
     const orc_matrix *A;
     const double *P;
+    int64_t ldp;    /* leading dimension of P */
     int64_t d, r;
     double *tmp_d;  /* length d (n for tall, m for fat) */
     double *tmp_n;  /* length n */
@@ -551,7 +552,7 @@ static void p_times(const precond_ctx *c, const double *y, double *out) /* out =
     for (int64_t i = 0; i < c->d; ++i) {
         double acc = 0.0;
         for (int64_t k = 0; k < c->r; ++k)
-            acc += c->P[i * c->d + k] * y[k];
+            acc += c->P[i * c->ldp + k] * y[k];
         out[i] = acc;
     }
 }
@@ -561,7 +562,7 @@ static void pt_times(const precond_ctx *c, const double *h, double *out) /* out 
     for (int64_t k = 0; k < c->r; ++k) {
         double acc = 0.0;
         for (int64_t i = 0; i < c->d; ++i)
-            acc += c->P[i * c->d + k] * h[i];
+            acc += c->P[i * c->ldp + k] * h[i];
         out[k] = acc;
     }
 }
@@ -636,56 +637,24 @@ static int64_t cg_normal(const orc_linop *K, const double *rhs, double rtol, int
     return it;
 }
 
-int orc_lsrn_solve(const orc_matrix *A, const double *b, const orc_options *opt,
-                   double *x, orc_info *info, double *sigma_out, double *P_out)
+/* Alg. 1/2 steps 6-7 (and reference-mode refinement) with a given
+ * preconditioner P (d x r, row-major, leading dimension ldp): N for tall
+ * problems, M for fat ones; s is the sketch size behind the Chebyshev
+ * bounds.  x (length n) receives the solution.  Returns 0, -3 if the
+ * Chebyshev bounds do not exist for (s, r). */
+int orc_lsrn_iterate(const orc_matrix *A, const double *b, const double *P, int64_t ldp,
+                     int64_t r, int64_t s, const orc_options *opt, double *x, orc_info *info)
 {
-    orc_info local;
-    if (!info)
-        info = &local;
-    memset(info, 0, sizeof(*info));
     const int64_t m = A->m, n = A->n;
-    if (m <= 0 || n <= 0 || !(opt->gamma > 1.0) || !(opt->tol > 0.0) || A->lambda < 0.0)
-        return -1;
-    if (A->lambda > 0.0 && m < n)
-        return -2; /* under-determined Tikhonov form (Sec. 5) not provided */
     const int tall = is_tall(A);
     const int64_t rows = m + (A->lambda > 0.0 ? n : 0);
     const int64_t d = tall ? n : m;
-    /* Alg. 1/2 step 1: s = ceil(gamma * d). */
-    const int64_t s = (int64_t)ceil(opt->gamma * (double)d);
-    info->s = s;
-    info->d = d;
-    info->tall = tall;
-
-    double t0 = now_s();
-    double *X = (double *)malloc(sizeof(double) * (size_t)s * (size_t)d);
-    double *sigma = (double *)malloc(sizeof(double) * (size_t)d);
-    double *P = (double *)malloc(sizeof(double) * (size_t)d * (size_t)d);
-    orc_sketch(A, s, opt->seed, X);
-    double t1 = now_s();
-    int sweeps = 0;
-    const int64_t r = orc_precond(s, d, X, opt->rcond, sigma, P, &sweeps);
-    double t2 = now_s();
-    free(X);
-    info->t_sketch = t1 - t0;
-    info->t_svd = t2 - t1;
-    info->rank = r;
-    info->sweeps = sweeps;
-    if (sigma_out)
-        memcpy(sigma_out, sigma, sizeof(double) * (size_t)d);
-    if (P_out)
-        memcpy(P_out, P, sizeof(double) * (size_t)d * (size_t)d);
     for (int64_t j = 0; j < n; ++j)
         x[j] = 0.0;
-    if (r <= 0) {
-        info->converged = 1;
-        free(sigma); free(P);
-        return 0;
-    }
-
     precond_ctx ctx;
     ctx.A = A;
     ctx.P = P;
+    ctx.ldp = ldp;
     ctx.d = d;
     ctx.r = r;
     ctx.tmp_d = (double *)malloc(sizeof(double) * (size_t)d);
@@ -705,7 +674,12 @@ int orc_lsrn_solve(const orc_matrix *A, const double *b, const orc_options *opt,
     int64_t maxiter = opt->max_iter;
     if (maxiter <= 0)
         maxiter = have_bounds ? orc_cs_iterations(sl, su, opt->tol) + 10 : 10 * d + 100;
+    if (opt->method == ORC_CS && !have_bounds) {
+        free(ctx.tmp_d); free(ctx.tmp_n);
+        return -3;
+    }
 
+    const double t2 = now_s();
     /* Right-hand side of the preconditioned problem: [b; 0] (tall) or M^T b (fat). */
     double *rhs = (double *)calloc((size_t)(tall ? rows : r), sizeof(double));
     if (tall) {
@@ -716,22 +690,17 @@ int orc_lsrn_solve(const orc_matrix *A, const double *b, const orc_options *opt,
     }
     double *sol = (double *)malloc(sizeof(double) * (size_t)(tall ? r : n));
     int64_t it;
-    if (opt->method == ORC_CS) {
-        if (!have_bounds) {
-            free(rhs); free(sol); free(ctx.tmp_d); free(ctx.tmp_n); free(sigma); free(P);
-            return -3;
-        }
+    if (opt->method == ORC_CS)
         it = orc_cs(&K, rhs, sl, su, opt->tol, sol);
-    } else {
+    else
         it = orc_lsqr(&K, rhs, opt->tol, maxiter, sol);
-    }
     info->converged = it >= 0;
     info->iters = it >= 0 ? it : -it;
     if (tall)
         p_times(&ctx, sol, x); /* Alg. 1 step 7: x = N y */
     else
         memcpy(x, sol, sizeof(double) * (size_t)n);
-    double t3 = now_s();
+    const double t3 = now_s();
     info->t_iter = t3 - t2;
 
     /* Reference-mode refinement. */
@@ -769,7 +738,7 @@ int orc_lsrn_solve(const orc_matrix *A, const double *b, const orc_options *opt,
             for (int64_t k = 0; k < r; ++k) {
                 long double acc = 0.0L;
                 for (int64_t i = 0; i < d; ++i)
-                    acc += (long double)P[i * d + k] * h[i];
+                    acc += (long double)P[i * ldp + k] * h[i];
                 c[k] = (double)acc;
             }
             double *z = (double *)malloc(sizeof(double) * (size_t)r);
@@ -781,16 +750,20 @@ int orc_lsrn_solve(const orc_matrix *A, const double *b, const orc_options *opt,
             dxn = nrm2(n, dx);
             free(h); free(c); free(z); free(dx);
         } else {
-            /* e = M^T (b - A x) in long double; solve M^T A dx = e. */
+            /* e = M^T (b - A x) in long double; solve M^T A dx = e with the
+             * same method as the main solve. */
             double *e = (double *)malloc(sizeof(double) * (size_t)r);
             for (int64_t k = 0; k < r; ++k) {
                 long double acc = 0.0L;
                 for (int64_t i = 0; i < m; ++i)
-                    acc += (long double)P[i * d + k] * res[i];
+                    acc += (long double)P[i * ldp + k] * res[i];
                 e[k] = (double)acc;
             }
             double *dx = (double *)malloc(sizeof(double) * (size_t)n);
-            orc_lsqr(&K, e, opt->tol, maxiter, dx);
+            if (opt->method == ORC_CS)
+                orc_cs(&K, e, sl, su, opt->tol, dx);
+            else
+                orc_lsqr(&K, e, opt->tol, maxiter, dx);
             for (int64_t j = 0; j < n; ++j)
                 x[j] += dx[j];
             dxn = nrm2(n, dx);
@@ -804,8 +777,59 @@ int orc_lsrn_solve(const orc_matrix *A, const double *b, const orc_options *opt,
     info->refine_steps = steps;
     info->t_refine = now_s() - t3;
 
-    free(rhs); free(sol); free(ctx.tmp_d); free(ctx.tmp_n); free(sigma); free(P);
+    free(rhs); free(sol); free(ctx.tmp_d); free(ctx.tmp_n);
     return 0;
+}
+
+int orc_lsrn_solve(const orc_matrix *A, const double *b, const orc_options *opt,
+                   double *x, orc_info *info, double *sigma_out, double *P_out)
+{
+    orc_info local;
+    if (!info)
+        info = &local;
+    memset(info, 0, sizeof(*info));
+    const int64_t m = A->m, n = A->n;
+    if (m <= 0 || n <= 0 || !(opt->gamma > 1.0) || !(opt->tol > 0.0) || A->lambda < 0.0)
+        return -1;
+    if (A->lambda > 0.0 && m < n)
+        return -2; /* under-determined Tikhonov form (Sec. 5) not provided */
+    const int tall = is_tall(A);
+    const int64_t d = tall ? n : m;
+    /* Alg. 1/2 step 1: s = ceil(gamma * d). */
+    const int64_t s = (int64_t)ceil(opt->gamma * (double)d);
+    info->s = s;
+    info->d = d;
+    info->tall = tall;
+
+    double t0 = now_s();
+    double *X = (double *)malloc(sizeof(double) * (size_t)s * (size_t)d);
+    double *sigma = (double *)malloc(sizeof(double) * (size_t)d);
+    double *P = (double *)malloc(sizeof(double) * (size_t)d * (size_t)d);
+    orc_sketch(A, s, opt->seed, X);
+    double t1 = now_s();
+    int sweeps = 0;
+    const int64_t r = orc_precond(s, d, X, opt->rcond, sigma, P, &sweeps);
+    double t2 = now_s();
+    free(X);
+    info->t_sketch = t1 - t0;
+    info->t_svd = t2 - t1;
+    info->rank = r;
+    info->sweeps = sweeps;
+    if (sigma_out)
+        memcpy(sigma_out, sigma, sizeof(double) * (size_t)d);
+    if (P_out)
+        memcpy(P_out, P, sizeof(double) * (size_t)d * (size_t)d);
+    for (int64_t j = 0; j < n; ++j)
+        x[j] = 0.0;
+    if (r <= 0) {
+        info->converged = 1;
+        free(sigma); free(P);
+        return 0;
+    }
+
+    const int rc = orc_lsrn_iterate(A, b, P, d, r, s, opt, x, info);
+    free(sigma); free(P);
+    return rc;
 }
 
 /* ====================================================================

@@ -179,6 +179,13 @@ typedef struct {
 int orc_lsrn_solve(const orc_matrix *A, const double *b, const orc_options *opt,
                    double *x, orc_info *info, double *sigma_out, double *P_out);
 
+/* Steps 6-7 (and refinement) of the above with a given preconditioner P
+ * (d x r, row-major, leading dimension ldp): N for tall problems, M for fat
+ * ones; s is the sketch size behind the Chebyshev bounds.  Returns 0, or -3
+ * when method = ORC_CS and the bounds do not exist. */
+int orc_lsrn_iterate(const orc_matrix *A, const double *b, const double *P, int64_t ldp,
+                     int64_t r, int64_t s, const orc_options *opt, double *x, orc_info *info);
+
 /* Brute force x = A^+ b from a one-sided Jacobi SVD of A carried out in long
  * double, singular values below rcond * sigma_1 dropped.  For tiny
  * inputs only (dense A).  Returns the rank. */

@@ -251,6 +251,8 @@ lsrn_status lsrn_iterate_dense(int64_t m, int64_t n, const double *A, int64_t ld
         info->sigma_l = ir.sigma_l; info->sigma_u = ir.sigma_u;
         info->t_iter_ms = ir.t_iter_ms; info->t_refine_ms = ir.t_refine_ms;
         info->t_total_ms = ir.t_iter_ms + ir.t_refine_ms;
+        info->t_sweep_kernel_ms = ir.t_sweep_kernel_ms;
+        info->sweep_kernels = ir.sweep_kernels;
     }
     if (!ir.converged) {
         g_last_error = "LSQR reached max_iter";
@@ -275,7 +277,9 @@ lsrn_status lsrn_solve_dense(int64_t m, int64_t n, const double *A, int64_t lda,
     const int64_t d = v.d;
     const int64_t s = (int64_t)std::ceil(opt.gamma * (double)d);
     DevBuf X((size_t)s * (size_t)d * sizeof(double));
-    sketch_rows(v.K, d, v.T, v.ldt, v.tall ? opt.lambda : 0.0, s, opt.seed, X.as<double>(), st);
+    double sketch_kernel_ms = 0.0;
+    sketch_rows(v.K, d, v.T, v.ldt, v.tall ? opt.lambda : 0.0, s, opt.seed, X.as<double>(), st,
+                opt.profile ? &sketch_kernel_ms : nullptr);
     tm.mark();
     DevBuf sigma((size_t)d * sizeof(double)), P((size_t)d * (size_t)d * sizeof(double));
     PrecondResult pr = precond(s, d, X.as<double>(), opt.rcond, sigma.as<double>(), P.as<double>(), st);
@@ -304,6 +308,12 @@ lsrn_status lsrn_solve_dense(int64_t m, int64_t n, const double *A, int64_t lda,
         info->t_iter_ms = ir.t_iter_ms;
         info->t_refine_ms = ir.t_refine_ms;
         info->t_total_ms = tm.elapsed_ms(0, 3);
+        if (opt.profile) {
+            info->t_sketch_kernel_ms = sketch_kernel_ms;
+            info->sketch_kernels = 1;
+            info->t_sweep_kernel_ms = ir.t_sweep_kernel_ms;
+            info->sweep_kernels = ir.sweep_kernels;
+        }
     }
     if (!ir.converged) {
         g_last_error = "LSQR reached max_iter";

@@ -20,8 +20,9 @@ void launch_gauss_fill(uint64_t seed, int64_t row0, int64_t nrows, int64_t col0,
 // dimension ldt (T = A for tall row-major A, T = A^T for fat column-major
 // A).  When lambda > 0, adds lambda * G(i, K + c) to X(i, c) (the rows
 // lambda I of the augmented tall matrix, Sec. 5).
+// With kernel_ms != NULL the GEMM kernel is timed with HIP events on st.
 void sketch_rows(int64_t K, int64_t d, const double *T, int64_t ldt, double lambda, int64_t s,
-                 uint64_t seed, double *X, hipStream_t st);
+                 uint64_t seed, double *X, hipStream_t st, double *kernel_ms = nullptr);
 size_t sketch_workspace_bytes(int64_t K, int64_t d, int64_t s);
 
 // Out-of-place transpose: out (cols x rows, leading dim rows) = in^T, in
@@ -66,6 +67,8 @@ struct IterResult {
     bool converged = true;
     double sigma_l = 0.0, sigma_u = 0.0;
     double t_iter_ms = 0.0, t_refine_ms = 0.0;
+    double t_sweep_kernel_ms = 0.0;  // opt.profile: summed sweep kernel time
+    int64_t sweep_kernels = 0;
 };
 
 // Runs step 6 (and 7) for b (length m of the original problem) and

@@ -106,10 +106,8 @@ __global__ void __launch_bounds__(NT, 2) sweep_kernel(SweepArgs a) {
     const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_block;
     const int64_t r1 = min(a.rows, r0 + a.rows_per_block);
     const bool vec2 = ((a.ldt & 1) == 0) && ((reinterpret_cast<uintptr_t>(a.T) & 15) == 0);
-    int parity = 0;
-    for (int64_t j0 = r0; j0 < r1; j0 += R) {
-        double av[R][CPT];
-        double yv[R];
+    // R rows of T (and of the per-row vector) starting at j0 into registers
+    auto load_rows = [&](int64_t j0, double (&av)[R][CPT], double (&yv)[R]) {
 #pragma unroll
         for (int rr = 0; rr < R; ++rr) {
             const int64_t row = j0 + rr;
@@ -132,6 +130,22 @@ __global__ void __launch_bounds__(NT, 2) sweep_kernel(SweepArgs a) {
             }
             yv[rr] = (valid && OP != OP_NORMAL) ? a.y[row] : 0.0;
         }
+    };
+    // software pipeline: the loads of step k+1 are in flight while step k
+    // reduces and updates
+    double avn[R][CPT], yvn[R];
+    if (r0 < r1) load_rows(r0, avn, yvn);
+    int parity = 0;
+    for (int64_t j0 = r0; j0 < r1; j0 += R) {
+        double av[R][CPT];
+        double yv[R];
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+            yv[rr] = yvn[rr];
+#pragma unroll
+            for (int e = 0; e < CPT; ++e) av[rr][e] = avn[rr][e];
+        }
+        if (j0 + R < r1) load_rows(j0 + R, avn, yvn);
         double q[R];
         if (OP != OP_ATB) {
             double pd[R];
@@ -734,11 +748,29 @@ struct Ctx {
     DevBuf zpart, spart, zred, sred, z, stbuf, Pt;
     State *state;
     const double *Ptp;  // P^T, r x L row-major (ld L)
+    // optional per-launch timing of the sweep kernel
+    bool profile = false;
+    std::vector<hipEvent_t> ev;
+
+    ~Ctx() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+
+    double sweep_kernel_ms() {
+        double t = 0.0;
+        for (size_t i = 0; i + 1 < ev.size(); i += 2) {
+            LSRN_HIP(hipEventSynchronize(ev[i + 1]));
+            float ms = 0.f;
+            LSRN_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+            t += ms;
+        }
+        return t;
+    }
 
     Ctx(const IterProblem &p, hipStream_t s) : pb(p), st(s) {
         L = (int)pb.cols;
         if (L <= 512) { cpt = 2; R = 8; }
-        else if (L <= 1024) { cpt = 4; R = 8; }
+        else if (L <= 1024) { cpt = 4; R = 4; }
         else if (L <= 2048) { cpt = 8; R = 4; }
         else if (L <= 4096) { cpt = 16; R = 2; }
         else fail(LSRN_E_UNSUPPORTED, "dense iteration supports min(m, n) <= 4096");
@@ -786,11 +818,20 @@ struct Ctx {
         a.rows_per_block = rows_per_block; a.w = w; a.zpart = zpart.as<double>();
         a.spart = spart.as<double>(); a.y = y; a.xv = xv; a.wv = wv; a.st = state;
         a.lambda = pb.tall ? pb.lambda : 0.0; a.alpha = alpha; a.beta = beta;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (profile) {
+            LSRN_HIP(hipEventCreate(&e0));
+            LSRN_HIP(hipEventCreate(&e1));
+            ev.push_back(e0);
+            ev.push_back(e1);
+            LSRN_HIP(hipEventRecord(e0, st));
+        }
         if (cpt == 2) sweep_t<2, 8>(op, a);
-        else if (cpt == 4) sweep_t<4, 8>(op, a);
+        else if (cpt == 4) sweep_t<4, 4>(op, a);
         else if (cpt == 8) sweep_t<8, 4>(op, a);
         else sweep_t<16, 2>(op, a);
         LSRN_HIP(hipGetLastError());
+        if (profile) LSRN_HIP(hipEventRecord(e1, st));
         dim3 g1((unsigned)ceil_div(L, 256), (unsigned)ngroups);
         reduce_stage1_kernel<<<g1, 256, 0, st>>>(zpart.as<double>(), spart.as<double>(), nblocks, L,
                                                  chunk, zred.as<double>(), sred.as<double>(), state);
@@ -1022,6 +1063,7 @@ IterResult iterate(const IterProblem &pb, const double *b, double *x, const lsrn
                    hipStream_t st) {
     IterResult res;
     Ctx cx(pb, st);
+    cx.profile = opt.profile != 0;
     double sl = 0.0, su = 0.0;
     const int64_t maxiter = default_maxiter(pb, opt, sl, su);
     res.sigma_l = sl;
@@ -1131,6 +1173,10 @@ IterResult iterate(const IterProblem &pb, const double *b, double *x, const lsrn
     res.t_iter_ms = ms1;
     res.t_refine_ms = ms2;
     res.converged = conv;
+    if (cx.profile) {
+        res.t_sweep_kernel_ms = cx.sweep_kernel_ms();
+        res.sweep_kernels = (int64_t)cx.ev.size() / 2;
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipEventDestroy(e2);

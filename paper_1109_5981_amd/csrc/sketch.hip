@@ -230,7 +230,7 @@ size_t sketch_workspace_bytes(int64_t K, int64_t d, int64_t s) {
 }
 
 void sketch_rows(int64_t K, int64_t d, const double *T, int64_t ldt, double lambda, int64_t s,
-                 uint64_t seed, double *X, hipStream_t st) {
+                 uint64_t seed, double *X, hipStream_t st, double *kernel_ms) {
     SketchPlan p = plan_sketch(K, d, s);
     DevBuf part;
     double *Xp = X;
@@ -240,6 +240,12 @@ void sketch_rows(int64_t K, int64_t d, const double *T, int64_t ldt, double lamb
     }
     dim3 grid((unsigned)(p.tiles_m * p.tiles_n), (unsigned)p.nsplit);
     const bool vec2 = (ldt % 2 == 0) && ((reinterpret_cast<uintptr_t>(T) & 15) == 0);
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    if (kernel_ms) {
+        LSRN_HIP(hipEventCreate(&ev[0]));
+        LSRN_HIP(hipEventCreate(&ev[1]));
+        LSRN_HIP(hipEventRecord(ev[0], st));
+    }
     if (vec2)
         sketch_mfma_kernel<true><<<grid, NT, 0, st>>>(T, ldt, K, d, s, seed, p.k_per_split,
                                                       p.tiles_m, Xp);
@@ -247,6 +253,15 @@ void sketch_rows(int64_t K, int64_t d, const double *T, int64_t ldt, double lamb
         sketch_mfma_kernel<false><<<grid, NT, 0, st>>>(T, ldt, K, d, s, seed, p.k_per_split,
                                                        p.tiles_m, Xp);
     LSRN_HIP(hipGetLastError());
+    if (kernel_ms) {
+        LSRN_HIP(hipEventRecord(ev[1], st));
+        LSRN_HIP(hipEventSynchronize(ev[1]));
+        float ms = 0.f;
+        LSRN_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+        *kernel_ms = ms;
+        (void)hipEventDestroy(ev[0]);
+        (void)hipEventDestroy(ev[1]);
+    }
     const int64_t count = s * d;
     const int blocks = (int)std::min<int64_t>(ceil_div(count, 256), 8192);
     if (p.nsplit > 1) {

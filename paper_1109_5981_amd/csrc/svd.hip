@@ -83,6 +83,98 @@ qr_panel_kernel(double *__restrict__ X, int64_t s, int64_t p0, int nb, double *_
     }
 }
 
+// The same panel factorisation with the panel (rows >= p0, NB columns) held
+// in registers: thread t owns rows p0 + t + 1024 e, e < EPT, so each column
+// step costs three block reductions and no global traffic.
+template <int NB, int EPT>
+__global__ void __launch_bounds__(1024)
+qr_panel_reg_kernel(double *__restrict__ X, int64_t s, int64_t p0, int nb, double *__restrict__ V,
+                    double *__restrict__ beta) {
+    __shared__ double red[16][NB];
+    __shared__ double bc[NB + 1];
+    __shared__ double scratch[16];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    double pr[NB][EPT];
+#pragma unroll
+    for (int k = 0; k < NB; ++k)
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int64_t i = p0 + tid + 1024 * e;
+            pr[k][e] = (k < nb && i < s) ? X[(p0 + k) * s + i] : 0.0;
+        }
+    for (int k = 0; k < nb; ++k)
+        for (int64_t i = tid; i < p0; i += 1024) V[(int64_t)k * s + i] = 0.0;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        if (j < nb) {
+            const int64_t c = p0 + j;
+            double acc = 0.0;
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const int64_t i = p0 + tid + 1024 * e;
+                if (i >= c && i < s) acc += pr[j][e] * pr[j][e];
+            }
+            const double nrm2 = block_sum<1024>(acc, scratch);
+            if (tid == j) bc[NB] = pr[j][0];  // row c = p0 + j sits in thread j, e = 0
+            __syncthreads();
+            const double x0 = bc[NB];
+            const double normx = sqrt(nrm2);
+            const double alpha = x0 >= 0.0 ? -normx : normx;
+            const double v0 = x0 - alpha;
+            const double vtv = nrm2 - x0 * x0 + v0 * v0;
+            const double bet = normx == 0.0 ? 0.0 : 2.0 / vtv;
+            double vr[EPT];
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const int64_t i = p0 + tid + 1024 * e;
+                vr[e] = (i < c || i >= s) ? 0.0 : (i == c ? v0 : pr[j][e]);
+            }
+#pragma unroll
+            for (int k = j + 1; k < NB; ++k) {
+                if (k < nb) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int e = 0; e < EPT; ++e) t += vr[e] * pr[k][e];
+                    t = wave_sum(t);
+                    if (lane == 0) red[wid][k] = t;
+                }
+            }
+            __syncthreads();
+            if (tid > j && tid < nb) {
+                double t = 0.0;
+                for (int w = 0; w < 16; ++w) t += red[w][tid];
+                bc[tid] = bet * t;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = j + 1; k < NB; ++k) {
+                if (k < nb) {
+                    const double f = bc[k];
+#pragma unroll
+                    for (int e = 0; e < EPT; ++e) pr[k][e] -= f * vr[e];
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const int64_t i = p0 + tid + 1024 * e;
+                if (i < s) {
+                    V[(int64_t)j * s + i] = vr[e];
+                    if (i >= c) pr[j][e] = i == c ? alpha : 0.0;
+                }
+            }
+            if (tid == 0) beta[j] = bet;
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NB; ++k)
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int64_t i = p0 + tid + 1024 * e;
+            if (k < nb && i < s) X[(p0 + k) * s + i] = pr[k][e];
+        }
+}
+
 // Apply the nb reflectors of a panel, in order, to the trailing columns
 // c >= p0 + nb: one column per workgroup, held in registers.
 template <int NT, int EPT>
@@ -210,46 +302,298 @@ jacobi_small_kernel(double *__restrict__ Y, int d, int max_sweeps, double tol,
 }
 
 // One round of the block round robin: workgroup k takes column blocks
-// (bi, bj) of width bw into LDS and rotates every pair among those 2 bw
-// columns (round robin on 2 bw players), then writes them back.
-__global__ void __launch_bounds__(256)
-jacobi_block_round_kernel(double *__restrict__ Y, int d, int bw, int nblocks, int round,
-                          double tol, int *__restrict__ rot_count) {
-    extern __shared__ double W[];  // 2*bw columns of length d
+// (bi, bj) of width BW into LDS, rotates every pair among those 2 BW
+// columns (round robin on 2 BW players) and writes them back.  The BW pairs of a sub-round are spread over the 8 waves: WPP waves per
+// pair (each owning a contiguous segment of the rows) when BW < 8, PPW
+// pairs per wave when BW > 8.  A pair's three inner products are summed
+// over its waves through LDS in a fixed order.  d <= 512 EPU and
+// ceil(d / WPP) <= 64 EPL.
+template <int BW, int EPU, int EPL>
+__global__ void __launch_bounds__(512)
+jacobi_round_kernel(double *__restrict__ Y, int d, int nblocks, int round, double tol,
+                    int *__restrict__ rot_count) {
+    extern __shared__ double W[];  // 2*BW columns of length d
+    constexpr int NLOC = 2 * BW;
+    constexpr int WPP = BW >= 8 ? 1 : 8 / BW;   // waves per pair
+    constexpr int PPW = BW > 8 ? BW / 8 : 1;    // pairs per wave
+    __shared__ double part[BW][WPP][3];
     const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
     int bi, bj;
     rr_pair(nblocks, round, blockIdx.x, bi, bj);
-    const int nloc = 2 * bw;
-    // load
-    for (int cl = 0; cl < nloc; ++cl) {
-        const int blk = cl < bw ? bi : bj;
-        const int64_t col = (int64_t)blk * bw + (cl % bw);
-        const double *src = Y + col * d;
-        double *dst = W + (int64_t)cl * d;
-        for (int i = tid; i < d; i += 256) dst[i] = src[i];
+    {
+        double reg[NLOC][EPU];
+#pragma unroll
+        for (int cl = 0; cl < NLOC; ++cl) {
+            const int64_t col = (int64_t)(cl < BW ? bi : bj) * BW + (cl % BW);
+            const double *src = Y + col * d;
+#pragma unroll
+            for (int u = 0; u < EPU; ++u) {
+                const int i = tid + 512 * u;
+                reg[cl][u] = i < d ? src[i] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int cl = 0; cl < NLOC; ++cl)
+#pragma unroll
+            for (int u = 0; u < EPU; ++u) {
+                const int i = tid + 512 * u;
+                if (i < d) W[cl * d + i] = reg[cl][u];
+            }
     }
     __syncthreads();
+    const int seg = (d + WPP - 1) / WPP;
+    const int gw = wid % WPP;                   // wave index inside its pair group
+    const int r0 = gw * seg, r1 = min(d, r0 + seg);
     int mine = 0;
-    for (int sub = 0; sub < nloc - 1; ++sub) {
-        for (int k = wid; k < nloc / 2; k += 4) {
+    for (int sub = 0; sub < NLOC - 1; ++sub) {
+#pragma unroll
+        for (int h = 0; h < PPW; ++h) {
+            const int k = (WPP > 1) ? wid / WPP : wid * PPW + h;
             int p, q;
-            rr_pair(nloc, sub, k, p, q);
-            // keep the global column order inside a pair
-            const int64_t gp = (int64_t)(p < bw ? bi : bj) * bw + (p % bw);
-            const int64_t gq = (int64_t)(q < bw ? bi : bj) * bw + (q % bw);
+            rr_pair(NLOC, sub, k, p, q);
+            const int gp = (p < BW ? bi : bj) * BW + (p % BW);
+            const int gq = (q < BW ? bi : bj) * BW + (q % BW);
             if (gp > gq) { const int tmp = p; p = q; q = tmp; }
-            mine += rotate_pair(W + (int64_t)p * d, W + (int64_t)q * d, d, tol);
+            double *wp = W + p * d, *wq = W + q * d;
+            double xp[EPL], xq[EPL];
+            double a = 0.0, b = 0.0, g = 0.0;
+#pragma unroll
+            for (int u = 0; u < EPL; ++u) {
+                const int i = r0 + lane + 64 * u;
+                xp[u] = i < r1 ? wp[i] : 0.0;
+                xq[u] = i < r1 ? wq[i] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < EPL; ++u) {
+                a += xp[u] * xp[u];
+                b += xq[u] * xq[u];
+                g += xp[u] * xq[u];
+            }
+            a = wave_sum(a);
+            b = wave_sum(b);
+            g = wave_sum(g);
+            if (WPP > 1) {
+                if (lane == 0) {
+                    part[k][gw][0] = a;
+                    part[k][gw][1] = b;
+                    part[k][gw][2] = g;
+                }
+                __syncthreads();
+                a = b = g = 0.0;
+#pragma unroll
+                for (int w = 0; w < WPP; ++w) {
+                    a += part[k][w][0];
+                    b += part[k][w][1];
+                    g += part[k][w][2];
+                }
+            }
+            if (g != 0.0 && fabs(g) > tol * sqrt(a) * sqrt(b)) {
+                const double zeta = (b - a) / (2.0 * g);
+                const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
+                const double c = 1.0 / sqrt(1.0 + t * t);
+                const double sn = c * t;
+#pragma unroll
+                for (int u = 0; u < EPL; ++u) {
+                    const int i = r0 + lane + 64 * u;
+                    if (i < r1) {
+                        wp[i] = c * xp[u] - sn * xq[u];
+                        wq[i] = sn * xp[u] + c * xq[u];
+                    }
+                }
+                if (gw == 0) ++mine;
+            }
         }
         __syncthreads();
     }
-    for (int cl = 0; cl < nloc; ++cl) {
-        const int blk = cl < bw ? bi : bj;
-        const int64_t col = (int64_t)blk * bw + (cl % bw);
-        double *dst = Y + col * d;
-        const double *src = W + (int64_t)cl * d;
-        for (int i = tid; i < d; i += 256) dst[i] = src[i];
+    {
+        double reg[NLOC][EPU];
+#pragma unroll
+        for (int cl = 0; cl < NLOC; ++cl)
+#pragma unroll
+            for (int u = 0; u < EPU; ++u) {
+                const int i = tid + 512 * u;
+                reg[cl][u] = i < d ? W[cl * d + i] : 0.0;
+            }
+#pragma unroll
+        for (int cl = 0; cl < NLOC; ++cl) {
+            const int64_t col = (int64_t)(cl < BW ? bi : bj) * BW + (cl % BW);
+            double *dst = Y + col * d;
+#pragma unroll
+            for (int u = 0; u < EPU; ++u) {
+                const int i = tid + 512 * u;
+                if (i < d) dst[i] = reg[cl][u];
+            }
+        }
     }
     if (lane == 0 && mine) atomicAdd(rot_count, mine);
+}
+
+// Compile-time round-robin pair (same schedule as rr_pair).
+template <int N, int T, int K>
+struct RR {
+    static constexpr int a = K == 0 ? N - 1 : (T + K) % (N - 1);
+    static constexpr int b = K == 0 ? T : (T - K + (N - 1)) % (N - 1);
+    static constexpr int p = a < b ? a : b;
+    static constexpr int q = a < b ? b : a;
+};
+
+// Sum each of the 32 values v[0..31] over the 64 lanes of a wavefront by a
+// halving butterfly (reduce-scatter): at each step a lane keeps half of its
+// values and adds its partner's copy of that half.  Afterwards lanes 2j and
+// 2j+1 both hold the total of value j (32 shuffles instead of 192).
+template <int N, int H>
+__device__ __forceinline__ void butterfly_steps(double (&v)[N], int lane) {
+    if constexpr (H >= 1) {
+        const bool upper = (lane & (2 * H)) != 0;
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+            const double send = upper ? v[j] : v[j + H];
+            const double keep = upper ? v[j + H] : v[j];
+            v[j] = keep + __shfl_xor(send, 2 * H, 64);
+        }
+        butterfly_steps<N, H / 2>(v, lane);
+    }
+}
+
+// N (a power of two <= 32) values reduced over the wavefront: the halving
+// steps consume lane bits 1 .. log2 N, plain butterflies the rest; lane l
+// then holds the total of value (l >> 1) & (N - 1).
+template <int N>
+__device__ __forceinline__ double wave_reduce_n(double (&v)[N]) {
+    const int lane = threadIdx.x & 63;
+    butterfly_steps<N, N / 2>(v, lane);
+    double t = v[0] + __shfl_xor(v[0], 1, 64);
+#pragma unroll
+    for (int m = 2 * N; m <= 32; m <<= 1) t += __shfl_xor(t, m, 64);
+    return t;
+}
+
+template <int X>
+constexpr int pow2_at_least() {
+    int p = 1;
+    while (p < X) p <<= 1;
+    return p;
+}
+
+// One round of the block round robin with the 2 BW columns of a block pair
+// held in registers: thread t owns rows t + 512 u (u < EPU) of every column.
+// Per sub-round the 3 BW inner products of its BW disjoint pairs are reduced
+// together (one butterfly per wave, one LDS pass across the 8 waves), the
+// rotation of pair k is computed once by thread k and broadcast through LDS.
+// d <= 512 EPU; 3 BW <= 32.
+template <int BW, int EPU>
+__global__ void __launch_bounds__(512)
+jacobi_reg_round_kernel(double *__restrict__ Y, int d, int nblocks, int round, double tol,
+                        int *__restrict__ rot_count) {
+    constexpr int NLOC = 2 * BW;
+    constexpr int NV = pow2_at_least<3 * BW>();
+    static_assert(NV <= 32, "three inner products per pair must fit one butterfly");
+    __shared__ double part[8][33];
+    __shared__ double rot[BW][2];
+    __shared__ int nrot;
+    const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+    int bi, bj;
+    rr_pair(nblocks, round, blockIdx.x, bi, bj);
+    double x[NLOC][EPU];
+#pragma unroll
+    for (int cl = 0; cl < NLOC; ++cl) {
+        const int64_t col = (int64_t)(cl < BW ? bi : bj) * BW + (cl % BW);
+        const double *src = Y + col * d;
+#pragma unroll
+        for (int u = 0; u < EPU; ++u) {
+            const int i = tid + 512 * u;
+            x[cl][u] = i < d ? src[i] : 0.0;
+        }
+    }
+    if (tid == 0) nrot = 0;
+    // pairs with gp > gq are swapped so the global column order is kept
+    const bool swap_cross = bi > bj;
+    auto sub_round = [&](auto tsub) {
+        constexpr int TS = decltype(tsub)::value;
+        double v[NV];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) v[j] = 0.0;
+        // partial inner products of the BW pairs
+        [&]<int... K>(std::integer_sequence<int, K...>) {
+            ((
+                 [&] {
+                     constexpr int p0 = RR<NLOC, TS, K>::p, q0 = RR<NLOC, TS, K>::q;
+                     const bool cross = (p0 < BW) != (q0 < BW);
+                     const bool sw = cross && swap_cross;
+                     double a = 0.0, b = 0.0, g = 0.0;
+#pragma unroll
+                     for (int u = 0; u < EPU; ++u) {
+                         const double xp = sw ? x[q0][u] : x[p0][u];
+                         const double xq = sw ? x[p0][u] : x[q0][u];
+                         a += xp * xp;
+                         b += xq * xq;
+                         g += xp * xq;
+                     }
+                     v[3 * K] = a;
+                     v[3 * K + 1] = b;
+                     v[3 * K + 2] = g;
+                 }()),
+             ...);
+        }(std::make_integer_sequence<int, BW>{});
+        const double tot = wave_reduce_n<NV>(v);
+        if ((lane & 1) == 0 && (lane >> 1) < 3 * BW) part[wid][lane >> 1] = tot;
+        __syncthreads();
+        if (tid < BW) {
+            double a = 0.0, b = 0.0, g = 0.0;
+#pragma unroll
+            for (int w = 0; w < 8; ++w) {
+                a += part[w][3 * tid];
+                b += part[w][3 * tid + 1];
+                g += part[w][3 * tid + 2];
+            }
+            double c = 1.0, sn = 0.0;
+            if (g != 0.0 && fabs(g) > tol * sqrt(a) * sqrt(b)) {
+                const double zeta = (b - a) / (2.0 * g);
+                const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
+                c = 1.0 / sqrt(1.0 + t * t);
+                sn = c * t;
+                atomicAdd(&nrot, 1);
+            }
+            rot[tid][0] = c;
+            rot[tid][1] = sn;
+        }
+        __syncthreads();
+        [&]<int... K>(std::integer_sequence<int, K...>) {
+            ((
+                 [&] {
+                     constexpr int p0 = RR<NLOC, TS, K>::p, q0 = RR<NLOC, TS, K>::q;
+                     const bool cross = (p0 < BW) != (q0 < BW);
+                     const bool sw = cross && swap_cross;
+                     const double c = rot[K][0], sn = rot[K][1];
+                     if (sn != 0.0) {
+#pragma unroll
+                         for (int u = 0; u < EPU; ++u) {
+                             const double xp = sw ? x[q0][u] : x[p0][u];
+                             const double xq = sw ? x[p0][u] : x[q0][u];
+                             const double np = c * xp - sn * xq, nq = sn * xp + c * xq;
+                             if (sw) { x[q0][u] = np; x[p0][u] = nq; }
+                             else { x[p0][u] = np; x[q0][u] = nq; }
+                         }
+                     }
+                 }()),
+             ...);
+        }(std::make_integer_sequence<int, BW>{});
+    };
+    [&]<int... TS>(std::integer_sequence<int, TS...>) {
+        (sub_round(std::integral_constant<int, TS>{}), ...);
+    }(std::make_integer_sequence<int, NLOC - 1>{});
+#pragma unroll
+    for (int cl = 0; cl < NLOC; ++cl) {
+        const int64_t col = (int64_t)(cl < BW ? bi : bj) * BW + (cl % BW);
+        double *dst = Y + col * d;
+#pragma unroll
+        for (int u = 0; u < EPU; ++u) {
+            const int i = tid + 512 * u;
+            if (i < d) dst[i] = x[cl][u];
+        }
+    }
+    __syncthreads();
+    if (tid == 0 && nrot) atomicAdd(rot_count, nrot);
 }
 
 // sigma_p = ||Y[:, p]||, one wavefront per column.
@@ -331,9 +675,17 @@ PrecondResult precond(int64_t s, int64_t d, double *X, double rcond, double *sig
 
     // ---- Householder QR
     DevBuf Vb((size_t)s * QNB * sizeof(double)), betab(QNB * sizeof(double));
-    for (int64_t p0 = 0; p0 < d; p0 += QNB) {
-        const int nb = (int)std::min<int64_t>(QNB, d - p0);
-        qr_panel_kernel<<<1, 1024, 0, st>>>(X, s, p0, nb, Vb.as<double>(), betab.as<double>());
+    // panel width: 8 (4 when s > 4096) with the register panel kernel, 32
+    // with the global-memory one for taller sketches
+    const int pw = s <= 4096 ? 8 : (s <= 8192 ? 4 : QNB);
+    for (int64_t p0 = 0; p0 < d; p0 += pw) {
+        const int nb = (int)std::min<int64_t>(pw, d - p0);
+        double *Vp = Vb.as<double>(), *bp = betab.as<double>();
+        if (s <= 1024) qr_panel_reg_kernel<8, 1><<<1, 1024, 0, st>>>(X, s, p0, nb, Vp, bp);
+        else if (s <= 2048) qr_panel_reg_kernel<8, 2><<<1, 1024, 0, st>>>(X, s, p0, nb, Vp, bp);
+        else if (s <= 4096) qr_panel_reg_kernel<8, 4><<<1, 1024, 0, st>>>(X, s, p0, nb, Vp, bp);
+        else if (s <= 8192) qr_panel_reg_kernel<4, 8><<<1, 1024, 0, st>>>(X, s, p0, nb, Vp, bp);
+        else qr_panel_kernel<<<1, 1024, 0, st>>>(X, s, p0, nb, Vp, bp);
         LSRN_HIP(hipGetLastError());
         const int64_t ncols = d - p0 - nb;
         if (ncols > 0) {
@@ -353,9 +705,15 @@ PrecondResult precond(int64_t s, int64_t d, double *X, double rcond, double *sig
     const double tol = (double)d * DBL_EPSILON;
     const int max_sweeps = 60;
     const size_t lds = lds_limit();
-    int bw = 1;
-    while ((size_t)(4 * bw) * (size_t)d * sizeof(double) <= lds && bw < 8) bw *= 2;
+    // column-block width and rows per thread of the register round kernel
+    static const int kBW[] = {8, 8, 4, 2, 1}, kDMAX[] = {512, 1024, 2048, 4096, 8192};
+    int variant = -1;
+    for (int v = 0; v < 5 && variant < 0; ++v)
+        if (d <= kDMAX[v]) variant = v;
+    const int bw = variant >= 0 ? kBW[variant] : 1;
     const bool small = (size_t)d * (size_t)d * sizeof(double) <= lds && d <= 128;
+    if (!small && variant < 0)
+        fail(LSRN_E_UNSUPPORTED, "precond: the Jacobi kernels support min(m, n) <= 8192");
     int64_t nblocks = ceil_div(d, bw);
     nblocks += nblocks & 1;
     const int64_t dcols = small ? d : nblocks * bw;
@@ -378,17 +736,17 @@ PrecondResult precond(int64_t s, int64_t d, double *X, double rcond, double *sig
         LSRN_HIP(hipStreamSynchronize(st));
         res.sweeps = sw;
     } else {
-        const size_t bytes = (size_t)(2 * bw) * (size_t)d * sizeof(double);
-        LSRN_REQUIRE(bytes <= lds, "precond: sketch too wide for the LDS Jacobi kernel");
-        if (bytes > 65536)
-            LSRN_HIP(hipFuncSetAttribute((const void *)jacobi_block_round_kernel,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+        typedef void (*RoundFn)(double *, int, int, int, double, int *);
+        static const RoundFn kFn[] = {jacobi_reg_round_kernel<8, 1>, jacobi_reg_round_kernel<8, 2>,
+                                      jacobi_reg_round_kernel<4, 4>, jacobi_reg_round_kernel<2, 8>,
+                                      jacobi_reg_round_kernel<1, 16>};
+        const RoundFn fn = kFn[variant];
         int sweep = 0;
         for (; sweep < max_sweeps; ++sweep) {
             LSRN_HIP(hipMemsetAsync(dcnt, 0, sizeof(int), st));
             for (int round = 0; round < nblocks - 1; ++round) {
-                jacobi_block_round_kernel<<<(unsigned)(nblocks / 2), 256, bytes, st>>>(
-                    Y, (int)d, bw, (int)nblocks, round, tol, dcnt);
+                hipLaunchKernelGGL(fn, dim3((unsigned)(nblocks / 2)), dim3(512), 0, st, Y, (int)d,
+                                   (int)nblocks, round, tol, dcnt);
             }
             LSRN_HIP(hipGetLastError());
             int rot = 0;

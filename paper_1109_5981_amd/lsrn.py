@@ -32,7 +32,7 @@ class Options(C.Structure):
     _fields_ = [("gamma", C.c_double), ("lambda_", C.c_double), ("tol", C.c_double),
                 ("rcond", C.c_double), ("t_margin", C.c_double), ("refine_tol", C.c_double),
                 ("seed", C.c_uint64), ("max_iter", C.c_int64), ("method", C.c_int32),
-                ("refine", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("refine", C.c_int32), ("profile", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class Info(C.Structure):
@@ -41,7 +41,9 @@ class Info(C.Structure):
                 ("tall", C.c_int32), ("converged", C.c_int32), ("sigma_l", C.c_double),
                 ("sigma_u", C.c_double), ("sigma_max", C.c_double), ("sigma_min_kept", C.c_double),
                 ("t_sketch_ms", C.c_double), ("t_svd_ms", C.c_double), ("t_iter_ms", C.c_double),
-                ("t_refine_ms", C.c_double), ("t_total_ms", C.c_double)]
+                ("t_refine_ms", C.c_double), ("t_total_ms", C.c_double),
+                ("t_sketch_kernel_ms", C.c_double), ("t_sweep_kernel_ms", C.c_double),
+                ("sketch_kernels", C.c_int64), ("sweep_kernels", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -58,6 +58,34 @@ def dense_problem(m: int, n: int, rank: int | None = None, smin: float = 1e-6,
     return Dense(np.ascontiguousarray(A), U, sigma, V)
 
 
+def dense_problem_device(m: int, n: int, rank: int | None = None, smin: float = 1e-6,
+                         seed: int = 0, device="cuda"):
+    """The dense_problem recipe built with torch on `device` (for sizes where
+    the host QR would dominate set-up).  Returns (A, U, sigma, V) tensors."""
+    import torch
+    k = min(m, n) if rank is None else rank
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+
+    def haar(rows):
+        Z = torch.randn(rows, k, generator=g, dtype=torch.float64, device=device)
+        Q, R = torch.linalg.qr(Z)
+        return Q * torch.sign(torch.diagonal(R))
+
+    U = haar(m)
+    V = haar(n)
+    sigma = torch.logspace(0.0, float(np.log10(smin)), k, dtype=torch.float64, device=device)
+    A = ((U * sigma) @ V.T).contiguous()
+    return A, U, sigma, V
+
+
+def rhs_gauss_device(m: int, seed: int, device="cuda"):
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed + 104729)
+    return torch.randn(m, generator=g, dtype=torch.float64, device=device)
+
+
 def rhs_model(A: np.ndarray, noise: float, seed: int):
     """b = A x_gen + noise * N(0,1); returns (b, x_gen)."""
     rng = np.random.default_rng(seed + 7919)
