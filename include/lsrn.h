@@ -101,6 +101,10 @@ typedef struct lsrn_info {
     double t_sweep_kernel_ms;
     int64_t sketch_kernels;
     int64_t sweep_kernels;
+    /* with opt->profile: span of the Jacobi round kernels (summed per
+     * sweep) and the number of round launches */
+    double t_jacobi_kernel_ms;
+    int64_t jacobi_kernels;
 } lsrn_info;
 
 /* Fill *opt with the defaults listed above. */

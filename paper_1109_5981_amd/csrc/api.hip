@@ -282,7 +282,8 @@ lsrn_status lsrn_solve_dense(int64_t m, int64_t n, const double *A, int64_t lda,
                 opt.profile ? &sketch_kernel_ms : nullptr);
     tm.mark();
     DevBuf sigma((size_t)d * sizeof(double)), P((size_t)d * (size_t)d * sizeof(double));
-    PrecondResult pr = precond(s, d, X.as<double>(), opt.rcond, sigma.as<double>(), P.as<double>(), st);
+    PrecondResult pr = precond(s, d, X.as<double>(), opt.rcond, sigma.as<double>(), P.as<double>(), st,
+                               opt.profile != 0);
     X.release();
     tm.mark();
     IterResult ir;
@@ -313,6 +314,8 @@ lsrn_status lsrn_solve_dense(int64_t m, int64_t n, const double *A, int64_t lda,
             info->sketch_kernels = 1;
             info->t_sweep_kernel_ms = ir.t_sweep_kernel_ms;
             info->sweep_kernels = ir.sweep_kernels;
+            info->t_jacobi_kernel_ms = pr.t_jacobi_kernel_ms;
+            info->jacobi_kernels = pr.jacobi_kernels;
         }
     }
     if (!ir.converged) {

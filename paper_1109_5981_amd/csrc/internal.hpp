@@ -36,11 +36,13 @@ struct PrecondResult {
     int64_t sweeps = 0;
     double sigma_max = 0.0;
     double sigma_min_kept = 0.0;
+    double t_jacobi_kernel_ms = 0.0;  // with profile: summed per-sweep spans
+    int64_t jacobi_kernels = 0;
 };
 // X: s x d column-major (overwritten).  P: d x d row-major (first r columns
 // hold V_r Sigma_r^{-1}); sigma: d values, descending.  Synchronises.
 PrecondResult precond(int64_t s, int64_t d, double *X, double rcond, double *sigma, double *P,
-                      hipStream_t st);
+                      hipStream_t st, bool profile = false);
 size_t precond_workspace_bytes(int64_t s, int64_t d);
 
 // --------------------------------------------------------- iterate.hip

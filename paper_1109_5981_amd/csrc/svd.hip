@@ -481,10 +481,16 @@ constexpr int pow2_at_least() {
 // together (one butterfly per wave, one LDS pass across the 8 waves), the
 // rotation of pair k is computed once by thread k and broadcast through LDS.
 // d <= 512 EPU; 3 BW <= 32.
+//
+// last_mod[b] is the global round index (sweep * (nblocks - 1) + round) at
+// which a column of block b was last rotated.  Two blocks meet once per
+// sweep; if neither changed since their previous meeting (period rounds
+// ago) then no rotation happened there and none can happen now, so the
+// workgroup returns at once -- an exact shortcut for the converging sweeps.
 template <int BW, int EPU>
 __global__ void __launch_bounds__(512)
 jacobi_reg_round_kernel(double *__restrict__ Y, int d, int nblocks, int round, double tol,
-                        int *__restrict__ rot_count) {
+                        int *__restrict__ rot_count, int *__restrict__ last_mod, int rnow) {
     constexpr int NLOC = 2 * BW;
     constexpr int NV = pow2_at_least<3 * BW>();
     static_assert(NV <= 32, "three inner products per pair must fit one butterfly");
@@ -494,6 +500,8 @@ jacobi_reg_round_kernel(double *__restrict__ Y, int d, int nblocks, int round, d
     const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
     int bi, bj;
     rr_pair(nblocks, round, blockIdx.x, bi, bj);
+    const int prev = rnow - (nblocks - 1);
+    if (prev >= 0 && last_mod[bi] < prev && last_mod[bj] < prev) return;
     double x[NLOC][EPU];
 #pragma unroll
     for (int cl = 0; cl < NLOC; ++cl) {
@@ -593,7 +601,11 @@ jacobi_reg_round_kernel(double *__restrict__ Y, int d, int nblocks, int round, d
         }
     }
     __syncthreads();
-    if (tid == 0 && nrot) atomicAdd(rot_count, nrot);
+    if (tid == 0 && nrot) {
+        atomicAdd(rot_count, nrot);
+        last_mod[bi] = rnow;
+        last_mod[bj] = rnow;
+    }
 }
 
 // sigma_p = ||Y[:, p]||, one wavefront per column.
@@ -669,7 +681,7 @@ size_t precond_workspace_bytes(int64_t s, int64_t d) {
 }
 
 PrecondResult precond(int64_t s, int64_t d, double *X, double rcond, double *sigma, double *P,
-                      hipStream_t st) {
+                      hipStream_t st, bool profile) {
     LSRN_REQUIRE(s >= d && d > 0, "precond: need s >= d > 0");
     PrecondResult res;
 
@@ -736,23 +748,44 @@ PrecondResult precond(int64_t s, int64_t d, double *X, double rcond, double *sig
         LSRN_HIP(hipStreamSynchronize(st));
         res.sweeps = sw;
     } else {
-        typedef void (*RoundFn)(double *, int, int, int, double, int *);
+        typedef void (*RoundFn)(double *, int, int, int, double, int *, int *, int);
         static const RoundFn kFn[] = {jacobi_reg_round_kernel<8, 1>, jacobi_reg_round_kernel<8, 2>,
                                       jacobi_reg_round_kernel<4, 4>, jacobi_reg_round_kernel<2, 8>,
                                       jacobi_reg_round_kernel<1, 16>};
         const RoundFn fn = kFn[variant];
+        DevBuf lastb((size_t)nblocks * sizeof(int));
+        int *last_mod = lastb.as<int>();
+        LSRN_HIP(hipMemsetAsync(last_mod, 0, (size_t)nblocks * sizeof(int), st));
+        const int period = (int)nblocks - 1;
+        hipEvent_t ev[2] = {nullptr, nullptr};
+        if (profile) {
+            LSRN_HIP(hipEventCreate(&ev[0]));
+            LSRN_HIP(hipEventCreate(&ev[1]));
+        }
         int sweep = 0;
         for (; sweep < max_sweeps; ++sweep) {
             LSRN_HIP(hipMemsetAsync(dcnt, 0, sizeof(int), st));
-            for (int round = 0; round < nblocks - 1; ++round) {
+            if (profile) LSRN_HIP(hipEventRecord(ev[0], st));
+            for (int round = 0; round < period; ++round) {
                 hipLaunchKernelGGL(fn, dim3((unsigned)(nblocks / 2)), dim3(512), 0, st, Y, (int)d,
-                                   (int)nblocks, round, tol, dcnt);
+                                   (int)nblocks, round, tol, dcnt, last_mod, sweep * period + round);
             }
             LSRN_HIP(hipGetLastError());
+            if (profile) LSRN_HIP(hipEventRecord(ev[1], st));
             int rot = 0;
             LSRN_HIP(hipMemcpyAsync(&rot, dcnt, sizeof(int), hipMemcpyDeviceToHost, st));
             LSRN_HIP(hipStreamSynchronize(st));
+            if (profile) {
+                float ms = 0.f;
+                LSRN_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+                res.t_jacobi_kernel_ms += ms;
+                res.jacobi_kernels += period;
+            }
             if (rot == 0) break;
+        }
+        if (profile) {
+            (void)hipEventDestroy(ev[0]);
+            (void)hipEventDestroy(ev[1]);
         }
         res.sweeps = sweep + 1;
     }
