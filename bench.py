@@ -106,6 +106,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="do not time individual kernels with HIP events")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many bytes (3 times); "
+                         "its FETCH_SIZE / WRITE_SIZE counters calibrate the traffic figures")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -124,6 +127,14 @@ def main():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if args.copy_bytes > 0:
+        src = torch.ones(args.copy_bytes // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 8, "launches": 3}))
+        return
     wl = WORKLOADS[args.workload]
     t_gen = time.perf_counter()
     A, U, sigma, V = workloads.dense_problem_device(wl["m"], wl["n"], wl["rank"], wl["smin"],
@@ -180,6 +191,10 @@ def main():
     t_sketch_k = mean("t_sketch_kernel_ms")
     t_sweep_k = mean("t_sweep_kernel_ms")
     n_sweep = mean("sweep_kernels")
+    t_jac_k = mean("t_jacobi_kernel_ms")
+    n_jac = mean("jacobi_kernels")
+    # one Jacobi round reads and writes every column of the d x d matrix once
+    bytes_per_round = 16.0 * d * d
 
     kernels = {}
     if t_sketch_k > 0:
@@ -192,6 +207,12 @@ def main():
         kernels["row_sweep"] = {
             "avg_ms": avg, "launches_per_step": n_sweep, "bound": "hbm",
             "achieved": bytes_per_sweep / (avg * 1e-3) / 1e9, "unit": "GB/s",
+            "peak": HBM_PEAK_GBS}
+    if t_jac_k > 0 and n_jac > 0:
+        avg = t_jac_k / n_jac
+        kernels["jacobi_round"] = {
+            "avg_ms": avg, "launches_per_step": n_jac, "bound": "hbm",
+            "achieved": bytes_per_round / (avg * 1e-3) / 1e9, "unit": "GB/s",
             "peak": HBM_PEAK_GBS}
     roofline = None
     if kernels:
