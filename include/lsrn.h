@@ -17,12 +17,12 @@
  * Conventions for every entry point below:
  *   - All array arguments are DEVICE pointers (hipMalloc'd or equivalent) on
  *     the current HIP device, owned by the caller.  The library never frees
- *     or keeps caller memory beyond the call (a plan keeps its own copies).
+ *     or keeps caller memory beyond the call.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *     Work is ordered on that stream.  Calls that return sizes or ranks to
  *     the host synchronise the stream before returning.
  *   - Workspace is allocated by the library with hipMalloc and freed before
- *     the call returns (plans keep theirs until lsrn_plan_destroy).
+ *     the call returns.
  *   - No exception crosses the ABI.  On failure the return code says what
  *     went wrong and lsrn_last_error() (per thread) holds a message.
  *   - Dense A is FP64 with leading dimension lda >= (columns of the stored
@@ -54,6 +54,17 @@ typedef enum {
 typedef enum { LSRN_LSQR = 0, LSRN_CHEBYSHEV = 1 } lsrn_method;
 typedef enum { LSRN_ROW_MAJOR = 0, LSRN_COL_MAJOR = 1 } lsrn_layout;
 
+/* How steps 4-5 form the preconditioner.
+ *   LSRN_PRECOND_SVD: QR + one-sided Jacobi SVD of the sketch, rank cutoff,
+ *     N = V_r Sigma_r^-1 (Alg. 1/2 steps 4-5); min(m, n) <= 8192.
+ *   LSRN_PRECOND_QR: N = R^-1 from the QR of the sketch.  G A R^-1 = Q has
+ *     orthonormal columns, the property the condition-number bound of
+ *     Sec. 4.2 rests on, but no rank is revealed: needs a full-rank sketch
+ *     (guaranteed when lambda > 0) and returns LSRN_E_UNSUPPORTED otherwise.
+ *   LSRN_PRECOND_AUTO: SVD when min(m, n) <= 8192, else QR when lambda > 0,
+ *     else LSRN_E_UNSUPPORTED. */
+typedef enum { LSRN_PRECOND_AUTO = 0, LSRN_PRECOND_SVD = 1, LSRN_PRECOND_QR = 2 } lsrn_precond_kind;
+
 typedef struct lsrn_options {
     double gamma;      /* oversampling factor gamma > 1 (Alg. 1 step 1); 2     */
     double lambda;     /* Tikhonov weight, W = lambda I (Sec. 5); 0            */
@@ -74,7 +85,8 @@ typedef struct lsrn_options {
     int32_t profile;   /* nonzero: time every sketch and sweep kernel launch
                           with HIP events on `stream` (lsrn_info fields
                           t_*_kernel_ms); 0                                     */
-    int32_t reserved[3];
+    int32_t precond;   /* lsrn_precond_kind; LSRN_PRECOND_AUTO                 */
+    int32_t reserved[2];
 } lsrn_options;
 
 typedef struct lsrn_info {
@@ -133,6 +145,23 @@ lsrn_status lsrn_solve_dense(int64_t m, int64_t n, const double *A, int64_t lda,
  * (used for HBM admission by callers that batch solves). */
 size_t lsrn_workspace_bytes(int64_t m, int64_t n, int32_t layout, const lsrn_options *opt);
 
+/*
+ * The same solve for sparse A (m x n) in CSR: rowptr (m + 1 int64, rowptr[0]
+ * = 0, rowptr[m] = nnz, nondecreasing), colind (nnz int32 in [0, n)), val
+ * (nnz FP64); entries of a row in any order (sums follow the given order).
+ * The sketch G T and every iteration read the nonzeros only (Sec. 4.3: the
+ * cost follows nnz); the library builds a transposed copy of the structure
+ * (12 nnz + 8 (n + 1) bytes) for the products with A^T.  Needs nnz, m, n <
+ * 2^31.  Errors as lsrn_solve_dense, plus LSRN_E_INVALID for a malformed
+ * structure (checked on the device before use).
+ */
+lsrn_status lsrn_solve_csr(int64_t m, int64_t n, int64_t nnz, const int64_t *rowptr,
+                           const int32_t *colind, const double *val, const double *b, double *x,
+                           const lsrn_options *opt, lsrn_info *info, void *stream);
+
+/* Device bytes lsrn_solve_csr allocates for these sizes. */
+size_t lsrn_workspace_bytes_csr(int64_t m, int64_t n, int64_t nnz, const lsrn_options *opt);
+
 /* ------------------------------------------------------------------------
  * Step-level entry points.  Each runs one step of the path in the same
  * kernels lsrn_solve_dense uses, so that every step can be checked alone.
@@ -160,6 +189,11 @@ lsrn_status lsrn_sketch_dense(int64_t m, int64_t n, const double *A, int64_t lda
                               int32_t layout, double lambda, int64_t s, uint64_t seed,
                               double *X, void *stream);
 
+/* lsrn_sketch_dense for CSR A (arguments as in lsrn_solve_csr). */
+lsrn_status lsrn_sketch_csr(int64_t m, int64_t n, int64_t nnz, const int64_t *rowptr,
+                            const int32_t *colind, const double *val, double lambda, int64_t s,
+                            uint64_t seed, double *X, void *stream);
+
 /* Steps 4-5 on a sketch X (s x d, column-major, s >= d): Householder QR,
  * one-sided Jacobi on R^T, rank r = #{sigma_i > rcond sigma_1} (rcond <= 0
  * as in lsrn_options), P = V_r Sigma_r^{-1} written row-major d x r with
@@ -168,6 +202,14 @@ lsrn_status lsrn_sketch_dense(int64_t m, int64_t n, const double *A, int64_t lda
  * are host pointers (sweeps may be NULL).  Synchronises the stream. */
 lsrn_status lsrn_precond(int64_t s, int64_t d, const double *X, double rcond, double *sigma,
                          double *P, int64_t *rank, int64_t *sweeps, void *stream);
+
+/* The full-rank alternative (LSRN_PRECOND_QR): Householder QR of X (s x d,
+ * column-major, s >= d) and P = R^-1 (row-major d x d, leading dimension
+ * d); sigma receives |r_ii| in descending order.  LSRN_E_UNSUPPORTED when
+ * min |r_ii| <= rcond max |r_ii| (rcond <= 0: max(s, d) 2^-52).
+ * Synchronises the stream. */
+lsrn_status lsrn_precond_qr(int64_t s, int64_t d, const double *X, double rcond, double *sigma,
+                            double *P, void *stream);
 
 /* Step 6-7 with a given preconditioner: P (d x r, row-major, leading
  * dimension ldp >= r) is N (tall) or M (fat) for A as in lsrn_solve_dense;
@@ -178,6 +220,12 @@ lsrn_status lsrn_iterate_dense(int64_t m, int64_t n, const double *A, int64_t ld
                                int32_t layout, const double *b, const double *P,
                                int64_t ldp, int64_t r, int64_t s, double *x,
                                const lsrn_options *opt, lsrn_info *info, void *stream);
+
+/* lsrn_iterate_dense for CSR A (arguments as in lsrn_solve_csr). */
+lsrn_status lsrn_iterate_csr(int64_t m, int64_t n, int64_t nnz, const int64_t *rowptr,
+                             const int32_t *colind, const double *val, const double *b,
+                             const double *P, int64_t ldp, int64_t r, int64_t s, double *x,
+                             const lsrn_options *opt, lsrn_info *info, void *stream);
 
 #ifdef __cplusplus
 }

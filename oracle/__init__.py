@@ -43,7 +43,8 @@ class _Matrix(C.Structure):
 class _Options(C.Structure):
     _fields_ = [("gamma", C.c_double), ("tol", C.c_double), ("rcond", C.c_double),
                 ("t_margin", C.c_double), ("seed", C.c_uint64), ("max_iter", C.c_int64),
-                ("method", C.c_int32), ("refine", C.c_int32)]
+                ("method", C.c_int32), ("refine", C.c_int32), ("precond", C.c_int32),
+                ("pad_", C.c_int32)]
 
 
 class _Info(C.Structure):
@@ -86,6 +87,8 @@ def lib():
         L.orc_jacobi_rt.argtypes = [C.c_int64, P, P, C.c_int]
         L.orc_precond.argtypes = [C.c_int64, C.c_int64, P, C.c_double, P, P, P]
         L.orc_precond.restype = C.c_int64
+        L.orc_precond_qr.argtypes = [C.c_int64, C.c_int64, P, C.c_double, P, P]
+        L.orc_precond_qr.restype = C.c_int64
         L.orc_lsqr.argtypes = [C.POINTER(_Linop), P, C.c_double, C.c_int64, P]
         L.orc_lsqr.restype = C.c_int64
         L.orc_cs.argtypes = [C.POINTER(_Linop), P, C.c_double, C.c_double, C.c_double, P]
@@ -261,6 +264,19 @@ def precond(X, rcond: float = 0.0):
     return int(r), sigma, P[:, :r].copy(), sw.value
 
 
+def precond_qr(X, rcond: float = 0.0):
+    """(|diag R| descending, P = R^-1 (d x d)) for the sketch X (s x d);
+    raises ValueError when the sketch is numerically rank-deficient."""
+    X = _f64(X)
+    s, d = X.shape
+    dg = np.zeros(d)
+    P = np.zeros((d, d))
+    r = lib().orc_precond_qr(s, d, _ptr(X), rcond, _ptr(dg), _ptr(P))
+    if r < 0:
+        raise ValueError("rank-deficient sketch")
+    return dg, P
+
+
 def cs_iterations(sigma_l: float, sigma_u: float, eps: float) -> int:
     return int(lib().orc_cs_iterations(sigma_l, sigma_u, eps))
 
@@ -332,13 +348,17 @@ class Result:
     P: np.ndarray
 
 
+PRECOND_SVD, PRECOND_QR = 0, 1
+
+
 def lsrn_solve(M: Matrix, b, *, gamma=2.0, tol=1e-14, method=LSQR, seed=0, rcond=0.0,
-               t_margin=1.0, max_iter=0, refine=0) -> Result:
-    """LSRN (Alg. 1 / Alg. 2) in the oracle; refine > 0 selects reference mode."""
+               t_margin=1.0, max_iter=0, refine=0, precond=PRECOND_SVD) -> Result:
+    """LSRN (Alg. 1 / Alg. 2) in the oracle; refine > 0 selects reference mode;
+    precond = PRECOND_QR uses N = R^-1 (full-rank sketches only)."""
     b = _f64(b)
     if b.shape[0] != M.m:
         raise ValueError("b has the wrong length")
-    o = _Options(gamma, tol, rcond, t_margin, seed, max_iter, method, refine)
+    o = _Options(gamma, tol, rcond, t_margin, seed, max_iter, method, refine, precond, 0)
     info = _Info()
     x = np.zeros(M.n)
     d = M.n if is_tall(M) else M.m
@@ -363,7 +383,7 @@ def lsrn_iterate(M: Matrix, b, P, s: int, *, tol=1e-14, method=LSQR, t_margin=1.
     b = _f64(b)
     P = _f64(P)
     d, r = P.shape
-    o = _Options(2.0, tol, 0.0, t_margin, 0, max_iter, method, refine)
+    o = _Options(2.0, tol, 0.0, t_margin, 0, max_iter, method, refine, 0, 0)
     info = _Info()
     x = np.zeros(M.n)
     st = M._struct()

@@ -808,7 +808,16 @@ int orc_lsrn_solve(const orc_matrix *A, const double *b, const orc_options *opt,
     orc_sketch(A, s, opt->seed, X);
     double t1 = now_s();
     int sweeps = 0;
-    const int64_t r = orc_precond(s, d, X, opt->rcond, sigma, P, &sweeps);
+    int64_t r;
+    if (opt->precond == ORC_PRECOND_QR) {
+        r = orc_precond_qr(s, d, X, opt->rcond, sigma, P);
+        if (r < 0) {
+            free(X); free(sigma); free(P);
+            return -4; /* rank-deficient sketch: the QR-inverse path needs full rank */
+        }
+    } else {
+        r = orc_precond(s, d, X, opt->rcond, sigma, P, &sweeps);
+    }
     double t2 = now_s();
     free(X);
     info->t_sketch = t1 - t0;
@@ -830,6 +839,65 @@ int orc_lsrn_solve(const orc_matrix *A, const double *b, const orc_options *opt,
     const int rc = orc_lsrn_iterate(A, b, P, d, r, s, opt, x, info);
     free(sigma); free(P);
     return rc;
+}
+
+/* QR-inverse preconditioner: P = R^{-1}, column j of P by back
+ * substitution on R p_j = e_j (rows j, j-1, ..., 0). */
+int64_t orc_precond_qr(int64_t s, int64_t d, const double *X, double rcond,
+                       double *diag_out, double *P)
+{
+    if (s < d || d <= 0)
+        return -1;
+    double *R = (double *)malloc(sizeof(double) * (size_t)d * (size_t)d);
+    double *dg = (double *)malloc(sizeof(double) * (size_t)d);
+    if (!R || !dg) {
+        free(R);
+        free(dg);
+        return -1;
+    }
+    orc_qr_r(s, d, X, R);
+    double dmax = 0.0, dmin = INFINITY;
+    for (int64_t i = 0; i < d; ++i) {
+        dg[i] = fabs(R[i * d + i]);
+        if (dg[i] > dmax) dmax = dg[i];
+        if (dg[i] < dmin) dmin = dg[i];
+    }
+    const double rc = rcond > 0.0 ? rcond : (double)(s > d ? s : d) * DBL_EPSILON;
+    if (!(dmin > rc * dmax)) {
+        free(R);
+        free(dg);
+        return -1;
+    }
+    if (diag_out) {
+        /* descending order (insertion sort: d is small in the tests) */
+        for (int64_t i = 0; i < d; ++i) {
+            double v = dg[i];
+            int64_t k = i;
+            while (k > 0 && diag_out[k - 1] < v) {
+                diag_out[k] = diag_out[k - 1];
+                --k;
+            }
+            diag_out[k] = v;
+        }
+    }
+#pragma omp parallel for schedule(dynamic)
+    for (int64_t j = 0; j < d; ++j) {
+        for (int64_t i = d - 1; i >= 0; --i) {
+            double v;
+            if (i > j) {
+                v = 0.0;
+            } else {
+                double t = (i == j) ? 1.0 : 0.0;
+                for (int64_t k = i + 1; k <= j; ++k)
+                    t -= R[i * d + k] * P[k * d + j];
+                v = t / R[i * d + i];
+            }
+            P[i * d + j] = v;
+        }
+    }
+    free(R);
+    free(dg);
+    return d;
 }
 
 /* ====================================================================

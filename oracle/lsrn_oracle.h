@@ -23,6 +23,7 @@
  *   orc_qr_r            pinned: R^T R = X^T X, LAPACK |diag R|
  *   orc_jacobi_rt       pinned: LAPACK singular values, W W^T = R^T R
  *   orc_precond         pinned: X N orthonormal, range(N) = range(X^T)
+ *   orc_precond_qr      pinned: X P orthonormal, R P = I, P upper triangular
  *   orc_lsqr / orc_cs   pinned: diagonal problems, Chebyshev closed form,
  *                               SciPy LSQR iterates on the same operator
  *   orc_cs_iterations   pinned: Table 3 of the paper (106 iterations)
@@ -117,6 +118,14 @@ int orc_jacobi_rt(int64_t d, const double *R, double *W, int max_sweeps);
 int64_t orc_precond(int64_t s, int64_t d, const double *X, double rcond,
                     double *sigma, double *P, int *sweeps);
 
+/* Full-rank alternative to steps 4-5: R from the Householder QR of X
+ * (s x d, row-major) and P = R^{-1} (d x d, row-major, upper triangular) by
+ * back substitution, so that X P = Q has orthonormal columns.  diag_out
+ * (length d, may be NULL) receives |r_ii| in descending order.  Returns d,
+ * or -1 when min |r_ii| <= rcond max |r_ii| (rcond <= 0: max(s,d) eps). */
+int64_t orc_precond_qr(int64_t s, int64_t d, const double *X, double rcond,
+                       double *diag_out, double *P);
+
 /* --------------------------------------------------------- iterations */
 
 /* Linear operator K (rows x cols) given by callbacks. */
@@ -159,7 +168,11 @@ typedef struct {
     int64_t max_iter;  /* LSQR cap; <= 0 selects the CS count + 10          */
     int32_t method;    /* ORC_LSQR or ORC_CS                                */
     int32_t refine;    /* reference-mode refinement steps (0 = none)        */
+    int32_t precond;   /* ORC_PRECOND_SVD (0) or ORC_PRECOND_QR (1)         */
+    int32_t pad_;
 } orc_options;
+
+enum { ORC_PRECOND_SVD = 0, ORC_PRECOND_QR = 1 };
 
 typedef struct {
     int64_t s, d, rank, iters, sweeps, refine_steps;

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <exception>
 #include <new>
 #include <string>
@@ -100,6 +101,9 @@ void check_options(const lsrn_options &o) {
     LSRN_REQUIRE(o.refine >= 0 && o.refine <= 100, "refine must lie in [0, 100]");
     LSRN_REQUIRE(o.refine_tol > 0.0 && o.refine_tol < 1.0, "refine_tol must lie in (0, 1)");
     LSRN_REQUIRE(std::isfinite(o.t_margin) && o.t_margin >= 0.0, "t_margin must be >= 0");
+    LSRN_REQUIRE(o.precond == LSRN_PRECOND_AUTO || o.precond == LSRN_PRECOND_SVD ||
+                     o.precond == LSRN_PRECOND_QR,
+                 "unknown preconditioner kind");
 }
 
 // The tall view T of A (row-major, K x d): A itself for tall row-major or
@@ -153,6 +157,94 @@ lsrn_status report(const Error &e) {
         return LSRN_E_INVALID;                                         \
     }                                                                  \
     return LSRN_OK;
+
+void fill_iter_info(lsrn_info *info, int64_t s, int64_t d, int64_t r, bool tall, const IterResult &ir) {
+    if (!info) return;
+    std::memset(info, 0, sizeof(*info));
+    info->s = s; info->d = d; info->rank = r; info->iters = ir.iters;
+    info->refine_steps = ir.refine_steps; info->refine_iters = ir.refine_iters;
+    info->tall = tall; info->converged = ir.converged;
+    info->sigma_l = ir.sigma_l; info->sigma_u = ir.sigma_u;
+    info->t_iter_ms = ir.t_iter_ms; info->t_refine_ms = ir.t_refine_ms;
+    info->t_total_ms = ir.t_iter_ms + ir.t_refine_ms;
+    info->t_sweep_kernel_ms = ir.t_sweep_kernel_ms;
+    info->sweep_kernels = ir.sweep_kernels;
+}
+
+// Largest min(m, n) the Jacobi kernels of the SVD handle.
+constexpr int64_t kSvdMaxD = 8192;
+
+bool use_qr_inverse(const lsrn_options &opt, int64_t d) {
+    if (opt.precond == LSRN_PRECOND_QR) return true;
+    if (opt.precond == LSRN_PRECOND_SVD) return false;
+    if (d <= kSvdMaxD) return false;
+    if (opt.lambda > 0.0) return true;
+    fail(LSRN_E_UNSUPPORTED,
+         "min(m, n) above 8192 needs lambda > 0 (full-rank QR-inverse preconditioner)");
+}
+
+// Steps 1-7 for a dense (dv) or sparse (sv) tall view; tm has its first mark.
+lsrn_status solve_impl(bool tall, int64_t K, int64_t d, int64_t n, const TallView *dv,
+                       const SparseView *sv, const double *b, double *x, const lsrn_options &opt,
+                       lsrn_info *info, hipStream_t st, StageTimer &tm) {
+    const int64_t s = (int64_t)std::ceil(opt.gamma * (double)d);
+    const bool qr_inv = use_qr_inverse(opt, d);
+    DevBuf X((size_t)s * (size_t)d * sizeof(double));
+    double sketch_kernel_ms = 0.0;
+    if (sv)
+        sketch_csr(*sv, tall ? opt.lambda : 0.0, s, opt.seed, X.as<double>(), st,
+                   opt.profile ? &sketch_kernel_ms : nullptr);
+    else
+        sketch_rows(K, d, dv->T, dv->ldt, tall ? opt.lambda : 0.0, s, opt.seed, X.as<double>(), st,
+                    opt.profile ? &sketch_kernel_ms : nullptr);
+    tm.mark();
+    DevBuf sigma((size_t)d * sizeof(double)), P((size_t)d * (size_t)d * sizeof(double));
+    PrecondResult pr = qr_inv ? precond_qr_inverse(s, d, X.as<double>(), opt.rcond, sigma.as<double>(),
+                                                   P.as<double>(), st)
+                              : precond(s, d, X.as<double>(), opt.rcond, sigma.as<double>(),
+                                        P.as<double>(), st, opt.profile != 0);
+    X.release();
+    tm.mark();
+    IterResult ir;
+    if (pr.rank > 0) {
+        IterProblem pb;
+        pb.tall = tall; pb.rows = K; pb.cols = d;
+        if (sv) pb.sp = sv;
+        else { pb.T = dv->T; pb.ldt = dv->ldt; }
+        pb.lambda = tall ? opt.lambda : 0.0; pb.P = P.as<double>(); pb.ldp = d;
+        pb.r = pr.rank; pb.s = s;
+        ir = iterate(pb, b, x, opt, st);
+    } else {
+        LSRN_HIP(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), st));
+    }
+    tm.mark();
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->s = s; info->d = d; info->rank = pr.rank; info->iters = ir.iters;
+        info->refine_steps = ir.refine_steps; info->refine_iters = ir.refine_iters;
+        info->sweeps = pr.sweeps; info->tall = tall; info->converged = ir.converged;
+        info->sigma_l = ir.sigma_l; info->sigma_u = ir.sigma_u;
+        info->sigma_max = pr.sigma_max; info->sigma_min_kept = pr.sigma_min_kept;
+        info->t_sketch_ms = tm.elapsed_ms(0, 1);
+        info->t_svd_ms = tm.elapsed_ms(1, 2);
+        info->t_iter_ms = ir.t_iter_ms;
+        info->t_refine_ms = ir.t_refine_ms;
+        info->t_total_ms = tm.elapsed_ms(0, 3);
+        if (opt.profile) {
+            info->t_sketch_kernel_ms = sketch_kernel_ms;
+            info->sketch_kernels = 1;
+            info->t_sweep_kernel_ms = ir.t_sweep_kernel_ms;
+            info->sweep_kernels = ir.sweep_kernels;
+            info->t_jacobi_kernel_ms = pr.t_jacobi_kernel_ms;
+            info->jacobi_kernels = pr.jacobi_kernels;
+        }
+    }
+    if (!ir.converged) {
+        g_last_error = "LSQR reached max_iter";
+        return LSRN_E_NOT_CONVERGED;
+    }
+    return LSRN_OK;
+}
 
 }  // namespace
 }  // namespace lsrn
@@ -226,6 +318,19 @@ lsrn_status lsrn_precond(int64_t s, int64_t d, const double *X, double rcond, do
     LSRN_API_END
 }
 
+lsrn_status lsrn_precond_qr(int64_t s, int64_t d, const double *X, double rcond, double *sigma,
+                            double *P, void *stream) {
+    LSRN_API_BEGIN
+    LSRN_REQUIRE(d > 0 && s >= d, "need s >= d > 0");
+    LSRN_REQUIRE(X && sigma && P, "NULL pointer");
+    hipStream_t st = (hipStream_t)stream;
+    DevBuf work((size_t)s * (size_t)d * sizeof(double));
+    LSRN_HIP(hipMemcpyAsync(work.as<double>(), X, (size_t)s * (size_t)d * sizeof(double),
+                            hipMemcpyDeviceToDevice, st));
+    precond_qr_inverse(s, d, work.as<double>(), rcond, sigma, P, st);
+    LSRN_API_END
+}
+
 lsrn_status lsrn_iterate_dense(int64_t m, int64_t n, const double *A, int64_t lda, int32_t layout,
                                const double *b, const double *P, int64_t ldp, int64_t r, int64_t s,
                                double *x, const lsrn_options *opt_in, lsrn_info *info,
@@ -243,17 +348,7 @@ lsrn_status lsrn_iterate_dense(int64_t m, int64_t n, const double *A, int64_t ld
     pb.tall = v.tall; pb.rows = v.K; pb.cols = v.d; pb.T = v.T; pb.ldt = v.ldt;
     pb.lambda = v.tall ? opt.lambda : 0.0; pb.P = P; pb.ldp = ldp; pb.r = r; pb.s = s;
     IterResult ir = iterate(pb, b, x, opt, st);
-    if (info) {
-        std::memset(info, 0, sizeof(*info));
-        info->s = s; info->d = v.d; info->rank = r; info->iters = ir.iters;
-        info->refine_steps = ir.refine_steps; info->refine_iters = ir.refine_iters;
-        info->tall = v.tall; info->converged = ir.converged;
-        info->sigma_l = ir.sigma_l; info->sigma_u = ir.sigma_u;
-        info->t_iter_ms = ir.t_iter_ms; info->t_refine_ms = ir.t_refine_ms;
-        info->t_total_ms = ir.t_iter_ms + ir.t_refine_ms;
-        info->t_sweep_kernel_ms = ir.t_sweep_kernel_ms;
-        info->sweep_kernels = ir.sweep_kernels;
-    }
+    fill_iter_info(info, s, v.d, r, v.tall, ir);
     if (!ir.converged) {
         g_last_error = "LSQR reached max_iter";
         return LSRN_E_NOT_CONVERGED;
@@ -274,50 +369,65 @@ lsrn_status lsrn_solve_dense(int64_t m, int64_t n, const double *A, int64_t lda,
     tm.mark();
     TallView v;
     make_view(v, m, n, A, lda, layout, opt.lambda, st);
-    const int64_t d = v.d;
-    const int64_t s = (int64_t)std::ceil(opt.gamma * (double)d);
-    DevBuf X((size_t)s * (size_t)d * sizeof(double));
-    double sketch_kernel_ms = 0.0;
-    sketch_rows(v.K, d, v.T, v.ldt, v.tall ? opt.lambda : 0.0, s, opt.seed, X.as<double>(), st,
-                opt.profile ? &sketch_kernel_ms : nullptr);
+    return solve_impl(v.tall, v.K, v.d, n, &v, nullptr, b, x, opt, info, st, tm);
+    LSRN_API_END
+}
+
+lsrn_status lsrn_solve_csr(int64_t m, int64_t n, int64_t nnz, const int64_t *rowptr,
+                           const int32_t *colind, const double *val, const double *b, double *x,
+                           const lsrn_options *opt_in, lsrn_info *info, void *stream) {
+    LSRN_API_BEGIN
+    const lsrn_options opt = opt_in ? *opt_in : defaults();
+    check_options(opt);
+    LSRN_REQUIRE(m > 0 && n > 0, "sizes must be positive");
+    LSRN_REQUIRE(b && x, "NULL pointer");
+    if (opt.lambda > 0.0 && m < n)
+        fail(LSRN_E_UNSUPPORTED, "Tikhonov regularisation needs m >= n (under-determined form not provided)");
+    hipStream_t st = (hipStream_t)stream;
+    StageTimer tm(st);
     tm.mark();
-    DevBuf sigma((size_t)d * sizeof(double)), P((size_t)d * (size_t)d * sizeof(double));
-    PrecondResult pr = precond(s, d, X.as<double>(), opt.rcond, sigma.as<double>(), P.as<double>(), st,
-                               opt.profile != 0);
-    X.release();
-    tm.mark();
-    IterResult ir;
-    if (pr.rank > 0) {
-        IterProblem pb;
-        pb.tall = v.tall; pb.rows = v.K; pb.cols = d; pb.T = v.T; pb.ldt = v.ldt;
-        pb.lambda = v.tall ? opt.lambda : 0.0; pb.P = P.as<double>(); pb.ldp = d;
-        pb.r = pr.rank; pb.s = s;
-        ir = iterate(pb, b, x, opt, st);
-    } else {
-        LSRN_HIP(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), st));
-    }
-    tm.mark();
-    if (info) {
-        std::memset(info, 0, sizeof(*info));
-        info->s = s; info->d = d; info->rank = pr.rank; info->iters = ir.iters;
-        info->refine_steps = ir.refine_steps; info->refine_iters = ir.refine_iters;
-        info->sweeps = pr.sweeps; info->tall = v.tall; info->converged = ir.converged;
-        info->sigma_l = ir.sigma_l; info->sigma_u = ir.sigma_u;
-        info->sigma_max = pr.sigma_max; info->sigma_min_kept = pr.sigma_min_kept;
-        info->t_sketch_ms = tm.elapsed_ms(0, 1);
-        info->t_svd_ms = tm.elapsed_ms(1, 2);
-        info->t_iter_ms = ir.t_iter_ms;
-        info->t_refine_ms = ir.t_refine_ms;
-        info->t_total_ms = tm.elapsed_ms(0, 3);
-        if (opt.profile) {
-            info->t_sketch_kernel_ms = sketch_kernel_ms;
-            info->sketch_kernels = 1;
-            info->t_sweep_kernel_ms = ir.t_sweep_kernel_ms;
-            info->sweep_kernels = ir.sweep_kernels;
-            info->t_jacobi_kernel_ms = pr.t_jacobi_kernel_ms;
-            info->jacobi_kernels = pr.jacobi_kernels;
-        }
-    }
+    SparseView v;
+    make_sparse_view(v, m, n, nnz, rowptr, colind, val, st);
+    return solve_impl(v.tall, v.K, v.d, n, nullptr, &v, b, x, opt, info, st, tm);
+    LSRN_API_END
+}
+
+lsrn_status lsrn_sketch_csr(int64_t m, int64_t n, int64_t nnz, const int64_t *rowptr,
+                            const int32_t *colind, const double *val, double lambda, int64_t s,
+                            uint64_t seed, double *X, void *stream) {
+    LSRN_API_BEGIN
+    LSRN_REQUIRE(m > 0 && n > 0 && s > 0, "sizes must be positive");
+    LSRN_REQUIRE(X, "NULL pointer");
+    LSRN_REQUIRE(lambda >= 0.0, "lambda must be >= 0");
+    if (lambda > 0.0 && m < n)
+        fail(LSRN_E_UNSUPPORTED, "Tikhonov regularisation needs m >= n (under-determined form not provided)");
+    hipStream_t st = (hipStream_t)stream;
+    SparseView v;
+    make_sparse_view(v, m, n, nnz, rowptr, colind, val, st);
+    sketch_csr(v, lambda, s, seed, X, st);
+    LSRN_API_END
+}
+
+lsrn_status lsrn_iterate_csr(int64_t m, int64_t n, int64_t nnz, const int64_t *rowptr,
+                             const int32_t *colind, const double *val, const double *b,
+                             const double *P, int64_t ldp, int64_t r, int64_t s, double *x,
+                             const lsrn_options *opt_in, lsrn_info *info, void *stream) {
+    LSRN_API_BEGIN
+    const lsrn_options opt = opt_in ? *opt_in : defaults();
+    check_options(opt);
+    LSRN_REQUIRE(m > 0 && n > 0, "sizes must be positive");
+    LSRN_REQUIRE(b && x && P, "NULL pointer");
+    if (opt.lambda > 0.0 && m < n)
+        fail(LSRN_E_UNSUPPORTED, "Tikhonov regularisation needs m >= n (under-determined form not provided)");
+    hipStream_t st = (hipStream_t)stream;
+    SparseView v;
+    make_sparse_view(v, m, n, nnz, rowptr, colind, val, st);
+    LSRN_REQUIRE(r > 0 && r <= v.d && ldp >= r && s > 0, "bad preconditioner shape");
+    IterProblem pb;
+    pb.tall = v.tall; pb.rows = v.K; pb.cols = v.d; pb.sp = &v;
+    pb.lambda = v.tall ? opt.lambda : 0.0; pb.P = P; pb.ldp = ldp; pb.r = r; pb.s = s;
+    IterResult ir = iterate(pb, b, x, opt, st);
+    fill_iter_info(info, s, v.d, r, v.tall, ir);
     if (!ir.converged) {
         g_last_error = "LSQR reached max_iter";
         return LSRN_E_NOT_CONVERGED;
@@ -340,6 +450,24 @@ size_t lsrn_workspace_bytes(int64_t m, int64_t n, int32_t layout, const lsrn_opt
     bytes += (size_t)d * d * sizeof(double) * 2 + (size_t)d * sizeof(double);  // P, P^T, sigma
     bytes += (size_t)(K + d) * sizeof(double) * 3;           // long vectors
     bytes += (size_t)1024 * d * sizeof(double) * 3;          // sweep partials
+    return bytes;
+} catch (...) {
+    return 0;
+}
+
+size_t lsrn_workspace_bytes_csr(int64_t m, int64_t n, int64_t nnz, const lsrn_options *opt_in) try {
+    const lsrn_options opt = opt_in ? *opt_in : defaults();
+    if (m <= 0 || n <= 0 || nnz < 0 || !(opt.gamma > 1.0)) return 0;
+    const bool tall = m >= n;
+    const int64_t K = tall ? m : n, d = tall ? n : m;
+    const int64_t s = (int64_t)std::ceil(opt.gamma * (double)d);
+    const int64_t rows = K + (tall && opt.lambda > 0.0 ? d : 0);
+    size_t bytes = sparse_view_bytes(m, n, nnz);               // transposed structure
+    bytes += (size_t)nnz * 36;                                 // sketch order + sort temporaries
+    bytes += (size_t)s * d * sizeof(double);                   // sketch
+    bytes += precond_workspace_bytes(s, d) + (size_t)d * d * sizeof(double);  // QR-inverse
+    bytes += (size_t)d * d * sizeof(double) * 2 + (size_t)d * sizeof(double);  // P, P^T, sigma
+    bytes += (size_t)rows * sizeof(double) * 5;                // long vectors
     return bytes;
 } catch (...) {
     return 0;

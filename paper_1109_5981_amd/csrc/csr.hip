@@ -1,0 +1,299 @@
+// csr.hip -- sparse A in CSR: validation, the transposed structure, and the
+// sketch X = G T of the tall view T (Alg. 1/2 steps 2-3 for sparse A;
+// Sec. 5 for the Tikhonov rows).
+//
+// The sketch keeps an S x C tile of X in LDS per workgroup (S sketch rows,
+// C columns of T) and walks the nonzeros of T that fall in those C columns
+// in order of their row k.  G(i, 4q .. 4q+3) is one Philox block, so the
+// workgroup generates, batch by batch, the S x 4QB slice of G for the rows
+// kb .. kb + 4QB of T once into LDS; every nonzero (k, c, v) of the batch
+// then adds v G(i, k) to X(i, c) for the S rows.  Nonzeros are grouped by
+// the thread that owns their column (c mod NT), so each column of the tile
+// has one writer and the summation order is fixed: the result is
+// deterministic.  Each slice of G is generated once per column block.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "common.hpp"
+#include "internal.hpp"
+#include "rng.hpp"
+
+namespace lsrn {
+
+namespace {
+
+constexpr int SK_NT = 256;  // threads of the sketch kernel
+constexpr int SK_S = 4;     // sketch rows per workgroup
+constexpr int SK_C = 4096;  // columns of T per workgroup (multiple of SK_NT)
+
+struct SkEntry {
+    int32_t k;  // row of T
+    int32_t c;  // column of T minus the block's first column
+    double v;
+};
+
+__global__ void check_csr_kernel(int64_t m, int64_t n, int64_t nnz, const int64_t *__restrict__ ptr,
+                                 const int32_t *__restrict__ idx, int *__restrict__ bad) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t a = ptr[r], b = ptr[r + 1];
+        if (a < 0 || b < a || b > nnz) {
+            atomicOr(bad, 1);
+            continue;
+        }
+        for (int64_t e = a; e < b; ++e) {
+            const int32_t c = idx[e];
+            if (c < 0 || (int64_t)c >= n) {
+                atomicOr(bad, 2);
+                break;
+            }
+        }
+    }
+}
+
+// out[e] = row of entry e.
+__global__ void expand_rows_kernel(int64_t nrows, const int64_t *__restrict__ ptr,
+                                   int32_t *__restrict__ out) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrows;
+         r += (int64_t)gridDim.x * blockDim.x)
+        for (int64_t e = ptr[r]; e < ptr[r + 1]; ++e) out[e] = (int32_t)r;
+}
+
+__global__ void iota_kernel(int64_t n, int32_t *__restrict__ out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (int32_t)i;
+}
+
+// ptr[g] = first position of key >= g in the sorted keys, g = 0 .. ngroups.
+__global__ void bounds_kernel(int64_t nkeys, const uint32_t *__restrict__ keys, int64_t ngroups,
+                              int64_t *__restrict__ ptr) {
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g <= ngroups;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        int64_t lo = 0, hi = nkeys;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if ((int64_t)keys[mid] < g) lo = mid + 1;
+            else hi = mid;
+        }
+        ptr[g] = lo;
+    }
+}
+
+__global__ void gather_transpose_kernel(int64_t nnz, const int32_t *__restrict__ perm,
+                                        const int32_t *__restrict__ rowof,
+                                        const double *__restrict__ val, int32_t *__restrict__ tidx,
+                                        double *__restrict__ tval) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nnz;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t e = perm[j];
+        tidx[j] = rowof[e];
+        tval[j] = val[e];
+    }
+}
+
+// key of entry e for the sketch order: (column block, owning thread).
+__global__ void sketch_keys_kernel(int64_t nnz, const int32_t *__restrict__ idx, int C,
+                                   uint32_t *__restrict__ keys) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t c = idx[e];
+        keys[e] = (uint32_t)((c / C) * SK_NT + (c % SK_NT));
+    }
+}
+
+__global__ void gather_sketch_kernel(int64_t nnz, const int32_t *__restrict__ perm,
+                                     const int32_t *__restrict__ rowof,
+                                     const int32_t *__restrict__ idx,
+                                     const double *__restrict__ val, int C,
+                                     SkEntry *__restrict__ out) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nnz;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t e = perm[j];
+        const int32_t c = idx[e];
+        out[j] = SkEntry{rowof[e], c % C, val[e]};
+    }
+}
+
+template <int S, int NT>
+__global__ void __launch_bounds__(NT)
+csr_sketch_kernel(const SkEntry *__restrict__ ent, const int64_t *__restrict__ optr, int64_t K,
+                  int64_t d, int C, int64_t s, uint64_t seed, double *__restrict__ X) {
+    constexpr int QB = NT / S;  // Philox blocks (quads of rows of T) per batch per sketch row
+    constexpr int KB = 4 * QB;  // rows of T per batch
+    extern __shared__ double lds[];
+    double *Xs = lds;           // [S][C]
+    double *Gs = lds + S * C;   // [S][KB]
+    const int tid = threadIdx.x;
+    const int b = blockIdx.y;
+    const int64_t i0 = (int64_t)blockIdx.x * S;
+    const int64_t c0 = (int64_t)b * C;
+    const int cw = (int)min<int64_t>((int64_t)C, d - c0);
+    for (int j = tid; j < S * C; j += NT) Xs[j] = 0.0;
+    int64_t e = optr[(int64_t)b * NT + tid];
+    const int64_t e1 = optr[(int64_t)b * NT + tid + 1];
+    const int gi = tid / QB, gq = tid % QB;
+    const uint64_t grow = (uint64_t)min<int64_t>(i0 + gi, s - 1);
+    SkEntry cur = SkEntry{0, 0, 0.0};
+    bool have = e < e1;
+    if (have) cur = ent[e];
+    for (int64_t kb = 0; kb < K; kb += KB) {
+        double g[4];
+        gauss4(seed, grow, (uint64_t)(kb / 4 + gq), g);
+        __syncthreads();  // previous batch done with Gs
+#pragma unroll
+        for (int w = 0; w < 4; ++w) Gs[gi * KB + 4 * gq + w] = g[w];
+        __syncthreads();
+        const int64_t kend = kb + KB;
+        while (have && (int64_t)cur.k < kend) {
+            const int kl = (int)((int64_t)cur.k - kb);
+#pragma unroll
+            for (int i = 0; i < S; ++i) Xs[i * C + cur.c] += cur.v * Gs[i * KB + kl];
+            ++e;
+            have = e < e1;
+            if (have) cur = ent[e];
+        }
+    }
+    __syncthreads();
+    for (int j = tid; j < S * cw; j += NT) {
+        const int c = j / S, i = j % S;
+        if (i0 + i < s) X[(c0 + c) * s + i0 + i] = Xs[i * C + c];
+    }
+}
+
+int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 256), 65535)); }
+
+// Stable sort of (keys, values) by the low `bits` bits of the keys.
+void sort_pairs(const uint32_t *kin, uint32_t *kout, const int32_t *vin, int32_t *vout, int64_t n,
+                int bits, hipStream_t st) {
+    size_t tb = 0;
+    LSRN_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, kin, kout, vin, vout, (int)n, 0, bits, st));
+    DevBuf tmp(std::max<size_t>(tb, 16));
+    LSRN_HIP(hipcub::DeviceRadixSort::SortPairs(tmp.as<void>(), tb, kin, kout, vin, vout, (int)n, 0,
+                                                bits, st));
+    LSRN_HIP(hipStreamSynchronize(st));  // before tmp is freed
+}
+
+int bits_for(int64_t maxkey) {
+    int b = 1;
+    while (b < 32 && ((int64_t)1 << b) <= maxkey) ++b;
+    return b;
+}
+
+}  // namespace
+
+void make_sparse_view(SparseView &v, int64_t m, int64_t n, int64_t nnz, const int64_t *rowptr,
+                      const int32_t *colind, const double *val, hipStream_t st) {
+    LSRN_REQUIRE(m > 0 && n > 0 && nnz >= 0, "sizes must be positive");
+    LSRN_REQUIRE(rowptr && (nnz == 0 || (colind && val)), "NULL pointer");
+    LSRN_REQUIRE(nnz < ((int64_t)1 << 31) && m < ((int64_t)1 << 31) && n < ((int64_t)1 << 31),
+                 "CSR input needs nnz, m, n < 2^31");
+    // structure check before any kernel indexes with it
+    int64_t ends[2] = {0, 0};
+    LSRN_HIP(hipMemcpyAsync(&ends[0], rowptr, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    LSRN_HIP(hipMemcpyAsync(&ends[1], rowptr + m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    LSRN_HIP(hipStreamSynchronize(st));
+    LSRN_REQUIRE(ends[0] == 0 && ends[1] == nnz, "rowptr[0] must be 0 and rowptr[m] must be nnz");
+    {
+        DevBuf flag(sizeof(int));
+        LSRN_HIP(hipMemsetAsync(flag.as<int>(), 0, sizeof(int), st));
+        check_csr_kernel<<<grid_for(m), 256, 0, st>>>(m, n, nnz, rowptr, colind, flag.as<int>());
+        LSRN_HIP(hipGetLastError());
+        int bad = 0;
+        LSRN_HIP(hipMemcpyAsync(&bad, flag.as<int>(), sizeof(int), hipMemcpyDeviceToHost, st));
+        LSRN_HIP(hipStreamSynchronize(st));
+        LSRN_REQUIRE(!(bad & 1), "rowptr must be nondecreasing within [0, nnz]");
+        LSRN_REQUIRE(!(bad & 2), "column index out of range");
+    }
+    v.tall = m >= n;
+    v.K = v.tall ? m : n;
+    v.d = v.tall ? n : m;
+    v.nnz = nnz;
+    const CsrMat a{m, n, nnz, rowptr, colind, val};
+    // A^T, row-compressed: stable sort of the entries by column
+    v.tptr.alloc((size_t)(n + 1) * sizeof(int64_t));
+    v.tidx.alloc((size_t)std::max<int64_t>(nnz, 1) * sizeof(int32_t));
+    v.tval.alloc((size_t)std::max<int64_t>(nnz, 1) * sizeof(double));
+    const CsrMat at{n, m, nnz, v.tptr.as<int64_t>(), v.tidx.as<int32_t>(), v.tval.as<double>()};
+    if (nnz > 0) {
+        DevBuf rowof((size_t)nnz * 4), iota((size_t)nnz * 4), perm((size_t)nnz * 4), ksort((size_t)nnz * 4);
+        expand_rows_kernel<<<grid_for(m), 256, 0, st>>>(m, rowptr, rowof.as<int32_t>());
+        iota_kernel<<<grid_for(nnz), 256, 0, st>>>(nnz, iota.as<int32_t>());
+        LSRN_HIP(hipGetLastError());
+        sort_pairs(reinterpret_cast<const uint32_t *>(colind), ksort.as<uint32_t>(), iota.as<int32_t>(),
+                   perm.as<int32_t>(), nnz, bits_for(n), st);
+        bounds_kernel<<<grid_for(n + 1), 256, 0, st>>>(nnz, ksort.as<uint32_t>(), n, v.tptr.as<int64_t>());
+        gather_transpose_kernel<<<grid_for(nnz), 256, 0, st>>>(nnz, perm.as<int32_t>(), rowof.as<int32_t>(),
+                                                               val, v.tidx.as<int32_t>(), v.tval.as<double>());
+        LSRN_HIP(hipGetLastError());
+        LSRN_HIP(hipStreamSynchronize(st));  // before the temporaries are freed
+    } else {
+        LSRN_HIP(hipMemsetAsync(v.tptr.as<int64_t>(), 0, (size_t)(n + 1) * sizeof(int64_t), st));
+    }
+    v.rows = v.tall ? a : at;
+    v.cols = v.tall ? at : a;
+}
+
+size_t sparse_view_bytes(int64_t m, int64_t n, int64_t nnz) {
+    return (size_t)(n + 1) * 8 + (size_t)nnz * 12 + (size_t)nnz * 16 + (size_t)nnz * 8;
+}
+
+void sketch_csr(const SparseView &v, double lambda, int64_t s, uint64_t seed, double *X,
+                hipStream_t st, double *kernel_ms) {
+    const int64_t K = v.K, d = v.d, nnz = v.nnz;
+    const int C = SK_C;
+    const int64_t nb = ceil_div(d, C);
+    const int64_t ngroups = nb * SK_NT;
+    LSRN_REQUIRE(ngroups < ((int64_t)1 << 31), "too many column blocks");
+    DevBuf ent((size_t)std::max<int64_t>(nnz, 1) * sizeof(SkEntry));
+    DevBuf optr((size_t)(ngroups + 1) * sizeof(int64_t));
+    const CsrMat &t = v.rows;  // CSR(T)
+    if (nnz > 0) {
+        DevBuf rowof((size_t)nnz * 4), keys((size_t)nnz * 4), ksort((size_t)nnz * 4);
+        DevBuf iota((size_t)nnz * 4), perm((size_t)nnz * 4);
+        expand_rows_kernel<<<grid_for(t.nrows), 256, 0, st>>>(t.nrows, t.ptr, rowof.as<int32_t>());
+        sketch_keys_kernel<<<grid_for(nnz), 256, 0, st>>>(nnz, t.idx, C, keys.as<uint32_t>());
+        iota_kernel<<<grid_for(nnz), 256, 0, st>>>(nnz, iota.as<int32_t>());
+        LSRN_HIP(hipGetLastError());
+        sort_pairs(keys.as<uint32_t>(), ksort.as<uint32_t>(), iota.as<int32_t>(), perm.as<int32_t>(),
+                   nnz, bits_for(ngroups), st);
+        bounds_kernel<<<grid_for(ngroups + 1), 256, 0, st>>>(nnz, ksort.as<uint32_t>(), ngroups,
+                                                             optr.as<int64_t>());
+        gather_sketch_kernel<<<grid_for(nnz), 256, 0, st>>>(nnz, perm.as<int32_t>(), rowof.as<int32_t>(),
+                                                            t.idx, t.val, C, ent.as<SkEntry>());
+        LSRN_HIP(hipGetLastError());
+        LSRN_HIP(hipStreamSynchronize(st));
+    } else {
+        LSRN_HIP(hipMemsetAsync(optr.as<int64_t>(), 0, (size_t)(ngroups + 1) * sizeof(int64_t), st));
+    }
+    const size_t lds = sizeof(double) * ((size_t)SK_S * C + 4 * SK_NT);
+    LSRN_HIP(hipFuncSetAttribute((const void *)csr_sketch_kernel<SK_S, SK_NT>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    if (kernel_ms) {
+        LSRN_HIP(hipEventCreate(&ev[0]));
+        LSRN_HIP(hipEventCreate(&ev[1]));
+        LSRN_HIP(hipEventRecord(ev[0], st));
+    }
+    LSRN_REQUIRE(nb <= 65535, "too many column blocks");
+    dim3 grid((unsigned)ceil_div(s, SK_S), (unsigned)nb);
+    csr_sketch_kernel<SK_S, SK_NT><<<grid, SK_NT, lds, st>>>(ent.as<SkEntry>(), optr.as<int64_t>(), K, d,
+                                                             C, s, seed, X);
+    LSRN_HIP(hipGetLastError());
+    if (kernel_ms) {
+        LSRN_HIP(hipEventRecord(ev[1], st));
+        LSRN_HIP(hipEventSynchronize(ev[1]));
+        float ms = 0.f;
+        LSRN_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+        *kernel_ms = ms;
+        (void)hipEventDestroy(ev[0]);
+        (void)hipEventDestroy(ev[1]);
+    }
+    if (v.tall) add_identity_rows(K, d, s, lambda, seed, X, st);
+    LSRN_HIP(hipStreamSynchronize(st));  // before ent / optr are freed
+}
+
+}  // namespace lsrn

@@ -25,10 +25,45 @@ void sketch_rows(int64_t K, int64_t d, const double *T, int64_t ldt, double lamb
                  uint64_t seed, double *X, hipStream_t st, double *kernel_ms = nullptr);
 size_t sketch_workspace_bytes(int64_t K, int64_t d, int64_t s);
 
+// X(i, c) += lambda G(i, K + c): the rows lambda I of the augmented tall
+// matrix (Sec. 5).
+void add_identity_rows(int64_t K, int64_t d, int64_t s, double lambda, uint64_t seed, double *X,
+                       hipStream_t st);
+
 // Out-of-place transpose: out (cols x rows, leading dim rows) = in^T, in
 // row-major rows x cols with leading dim ldin.
 void transpose(int64_t rows, int64_t cols, const double *in, int64_t ldin, double *out,
                hipStream_t st);
+
+// ------------------------------------------------------------- csr.hip
+// Row-compressed structure of a sparse matrix (device arrays).
+struct CsrMat {
+    int64_t nrows = 0, ncols = 0, nnz = 0;
+    const int64_t *ptr = nullptr;  // nrows + 1 offsets
+    const int32_t *idx = nullptr;  // column index of each entry
+    const double *val = nullptr;
+};
+
+// The tall view T (K x d) of a CSR matrix A (m x n): T = A when m >= n,
+// T = A^T otherwise, held row-compressed (rows = CSR of T) and column-
+// compressed (cols = CSR of T^T).  One of the two is the caller's A; the
+// other is the transposed copy the library builds (stable, so entries of a
+// column keep the row order and every sum runs in a fixed order).
+struct SparseView {
+    bool tall = true;
+    int64_t K = 0, d = 0, nnz = 0;
+    CsrMat rows, cols;
+    DevBuf tptr, tidx, tval;
+};
+// Validates the structure (LSRN_E_INVALID on bad offsets or indices) and
+// builds the transposed copy.  Synchronises.
+void make_sparse_view(SparseView &v, int64_t m, int64_t n, int64_t nnz, const int64_t *rowptr,
+                      const int32_t *colind, const double *val, hipStream_t st);
+size_t sparse_view_bytes(int64_t m, int64_t n, int64_t nnz);
+// X (s x d, column-major) = G T (+ lambda G(:, K + c) when tall and
+// lambda > 0).  Synchronises.
+void sketch_csr(const SparseView &v, double lambda, int64_t s, uint64_t seed, double *X,
+                hipStream_t st, double *kernel_ms = nullptr);
 
 // ------------------------------------------------------------- svd.hip
 struct PrecondResult {
@@ -44,6 +79,22 @@ struct PrecondResult {
 PrecondResult precond(int64_t s, int64_t d, double *X, double rcond, double *sigma, double *P,
                       hipStream_t st, bool profile = false);
 size_t precond_workspace_bytes(int64_t s, int64_t d);
+// Householder QR of X (s x d, column-major, in place; R in the upper
+// triangle).  Synchronises.
+void householder_qr(int64_t s, int64_t d, double *X, hipStream_t st);
+// Full-rank alternative to steps 4-5: QR of the sketch and P = R^-1
+// (row-major d x d); sigma receives |diag R| in descending order.
+// LSRN_E_UNSUPPORTED when min |r_ii| <= rcond max |r_ii|.  Synchronises.
+PrecondResult precond_qr_inverse(int64_t s, int64_t d, double *X, double rcond, double *sigma,
+                                 double *P, hipStream_t st);
+
+// ---------------------------------------------------------- linalg.hip
+// C = alpha A B + beta C, all column-major (FP64 MFMA).
+void gemm_nn(int64_t M, int64_t N, int64_t K, double alpha, const double *A, int64_t lda,
+             const double *B, int64_t ldb, double beta, double *C, int64_t ldc, hipStream_t st);
+// Rinv (column-major, ldi) = R^-1 for upper-triangular R (column-major, ldr;
+// entries below the diagonal are ignored).
+void trtri_upper(int64_t d, const double *R, int64_t ldr, double *Rinv, int64_t ldi, hipStream_t st);
 
 // --------------------------------------------------------- iterate.hip
 // The operator of the iteration phase.  Tall: T = A row-major (rows = m,
@@ -60,6 +111,7 @@ struct IterProblem {
     int64_t ldp = 0;
     int64_t r = 0;
     int64_t s = 0;
+    const SparseView *sp = nullptr;  // sparse T (then T and ldt are unused)
 };
 
 struct IterResult {

@@ -733,6 +733,212 @@ cg_init_kernel(const double *__restrict__ c, int64_t r, double *__restrict__ z,
     }
 }
 
+// ------------------------------------------------------------ sparse passes
+//
+// For sparse T a sweep is two passes: a row pass over CSR(T) forms
+// q_j = T_j w and the row-local update of the same operation as the dense
+// sweep, storing c_j in the long vector; a column pass over CSR(T^T) forms
+// z = T^T c by gathering c.  Both run in a fixed order (no atomics).
+
+constexpr int CRP_NT = 256;  // threads of the row pass
+constexpr int CRP_G = 8;     // lanes per row
+constexpr int CCP_NT = 256;  // column pass: one wavefront per column
+
+struct CsrArgs {
+    CsrMat t;                 // CSR(T)
+    int64_t K, total;         // rows of T; rows including the Tikhonov rows
+    int64_t rows_per_block;
+    const double *w;
+    double *y, *xv, *wv;
+    double *spart;            // nblocks x 4
+    State *st;
+    double lambda, alpha, beta;
+};
+
+__device__ __forceinline__ double group8_sum(double v) {
+    v += __shfl_xor(v, 4, CRP_G);
+    v += __shfl_xor(v, 2, CRP_G);
+    v += __shfl_xor(v, 1, CRP_G);
+    return v;
+}
+
+__device__ __forceinline__ dd group8_sum_dd(dd v) {
+#pragma unroll
+    for (int m = 4; m >= 1; m >>= 1) {
+        const dd o{__shfl_xor(v.hi, m, CRP_G), __shfl_xor(v.lo, m, CRP_G)};
+        v = dd_add(v, o);
+    }
+    return v;
+}
+
+template <int OP>
+__global__ void __launch_bounds__(CRP_NT) csr_row_pass_kernel(CsrArgs a) {
+    if (a.st->done) return;
+    __shared__ double red[CRP_NT / 64][4];
+    const int tid = threadIdx.x, g = tid / CRP_G, l = tid % CRP_G;
+    constexpr int NG = CRP_NT / CRP_G;
+    double coef = 0.0, inv_alpha = 0.0, beta = 0.0, phi_rho = 0.0, theta_rho = 0.0;
+    int pending = 0;
+    if (OP == OP_LSQR_TALL) coef = a.st->coef;
+    if (OP == OP_CS_TALL) coef = a.alpha;
+    if (OP == OP_LSQR_FAT) {
+        inv_alpha = a.st->inv_alpha;
+        beta = a.st->beta;
+        phi_rho = a.st->phi_rho;
+        theta_rho = a.st->theta_rho;
+        pending = a.st->pending;
+    }
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+    const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_block;
+    const int64_t r1 = min(a.total, r0 + a.rows_per_block);
+    for (int64_t row = r0 + g; row < r1; row += NG) {
+        double q = 0.0;
+        if (OP != OP_ATB) {
+            if (row < a.K) {
+                const int64_t e0 = a.t.ptr[row], e1 = a.t.ptr[row + 1];
+                for (int64_t e = e0 + l; e < e1; e += CRP_G) q += a.t.val[e] * a.w[a.t.idx[e]];
+                q = group8_sum(q);
+            } else {
+                q = a.lambda * a.w[row - a.K];
+            }
+        }
+        if (l != 0) continue;
+        if (OP == OP_ATB) {
+            const double c = a.y[row];
+            acc0 += c * c;
+        } else if (OP == OP_LSQR_TALL) {
+            const double c = q - coef * a.y[row];
+            a.y[row] = c;
+            acc0 += c * c;
+        } else if (OP == OP_CS_TALL) {
+            const double c = a.y[row] - coef * q;
+            a.y[row] = c;
+            acc0 += c * c;
+        } else if (OP == OP_NORMAL) {
+            a.y[row] = q;
+            acc0 += q * q;
+        } else if (OP == OP_LSQR_FAT) {
+            const double v = a.y[row] * inv_alpha;
+            const double c = q - beta * v;
+            if (pending == 1) {
+                a.wv[row] = v;
+                acc3 += v * v;
+            } else if (pending == 2) {
+                const double xo = a.xv[row] + phi_rho * a.wv[row];
+                const double wn = v - theta_rho * a.wv[row];
+                a.xv[row] = xo;
+                a.wv[row] = wn;
+                acc1 += xo * xo;
+                acc2 += xo * wn;
+                acc3 += wn * wn;
+            }
+            a.y[row] = c;
+            acc0 += c * c;
+        } else {  // OP_CS_FAT
+            const double c = a.beta * a.y[row] + q;
+            a.y[row] = c;
+            a.xv[row] += a.alpha * c;
+            acc0 += c * c;
+        }
+    }
+    acc0 = wave_sum(acc0);
+    acc1 = wave_sum(acc1);
+    acc2 = wave_sum(acc2);
+    acc3 = wave_sum(acc3);
+    const int lane = tid & 63, wid = tid >> 6;
+    if (lane == 0) {
+        red[wid][0] = acc0; red[wid][1] = acc1; red[wid][2] = acc2; red[wid][3] = acc3;
+    }
+    __syncthreads();
+    if (tid < 4) {
+        double t = 0.0;
+        for (int w = 0; w < CRP_NT / 64; ++w) t += red[w][tid];
+        a.spart[(int64_t)blockIdx.x * 4 + tid] = t;
+    }
+}
+
+// z_j = sum over column j of T of T(k, j) y_k (+ lambda y_{K+j}).
+__global__ void __launch_bounds__(CCP_NT)
+csr_col_pass_kernel(CsrMat ct, const double *__restrict__ y, double lambda, int64_t K,
+                    double *__restrict__ z, const State *st) {
+    if (st && st->done) return;
+    const int64_t j = (int64_t)blockIdx.x * (CCP_NT / 64) + (threadIdx.x >> 6);
+    if (j >= ct.nrows) return;
+    const int lane = threadIdx.x & 63;
+    double t = 0.0;
+    const int64_t e0 = ct.ptr[j], e1 = ct.ptr[j + 1];
+    for (int64_t e = e0 + lane; e < e1; e += 64) t += ct.val[e] * y[ct.idx[e]];
+    t = wave_sum(t);
+    if (lane == 0) z[j] = lambda > 0.0 ? t + lambda * y[K + j] : t;
+}
+
+// st->acc = sums of the row-pass partials (fixed order).
+__global__ void __launch_bounds__(256)
+reduce_spart_kernel(const double *__restrict__ spart, int nb, State *st) {
+    if (st->done) return;
+    __shared__ double red[4][4];
+    const int tid = threadIdx.x, k = tid & 3, part = tid >> 2;  // 64 partial sums per accumulator
+    double t = 0.0;
+    for (int b = part; b < nb; b += 64) t += spart[b * 4 + k];
+    // reduce over the 64 threads with the same k: lanes k, k+4, ... within
+    // each wavefront, then across the 4 wavefronts
+    for (int m = 32; m >= 4; m >>= 1) t += __shfl_xor(t, m);
+    if ((tid & 63) < 4) red[tid >> 6][k] = t;
+    __syncthreads();
+    if (tid < 4) st->acc[tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+}
+
+// Tall refinement, rows: res_k = b_k - T_k x (k < K) and res_{K+j} =
+// -lambda x_j, in double-double.
+__global__ void __launch_bounds__(CRP_NT)
+csr_resid_rows_dd_kernel(CsrMat t, int64_t K, int64_t total, int64_t rows_per_block,
+                         const double *__restrict__ b, const double *__restrict__ x,
+                         double lambda, double *__restrict__ rhi, double *__restrict__ rlo) {
+    const int tid = threadIdx.x, g = tid / CRP_G, l = tid % CRP_G;
+    constexpr int NG = CRP_NT / CRP_G;
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+    const int64_t r1 = min(total, r0 + rows_per_block);
+    for (int64_t row = r0 + g; row < r1; row += NG) {
+        dd res;
+        if (row < K) {
+            dd p = {0.0, 0.0};
+            const int64_t e0 = t.ptr[row], e1 = t.ptr[row + 1];
+            for (int64_t e = e0 + l; e < e1; e += CRP_G) p = dd_fma(p, t.val[e], x[t.idx[e]]);
+            p = group8_sum_dd(p);
+            res = dd_add(dd{b[row], 0.0}, dd{-p.hi, -p.lo});
+        } else {
+            res = two_prod(-lambda, x[row - K]);
+        }
+        if (l == 0) {
+            rhi[row] = res.hi;
+            rlo[row] = res.lo;
+        }
+    }
+}
+
+// Column pass in double-double: out_j = sum_k T(k, j) (yhi_k + ylo_k)
+// (+ lambda (yhi + ylo)_{K+j}); ylo may be NULL.
+__global__ void __launch_bounds__(CCP_NT)
+csr_col_pass_dd_kernel(CsrMat ct, const double *__restrict__ yhi, const double *__restrict__ ylo,
+                       double lambda, int64_t K, double *__restrict__ out_hi,
+                       double *__restrict__ out_lo) {
+    const int64_t j = (int64_t)blockIdx.x * (CCP_NT / 64) + (threadIdx.x >> 6);
+    if (j >= ct.nrows) return;
+    const int lane = threadIdx.x & 63;
+    dd t = {0.0, 0.0};
+    const int64_t e0 = ct.ptr[j], e1 = ct.ptr[j + 1];
+    for (int64_t e = e0 + lane; e < e1; e += 64) {
+        const int32_t k = ct.idx[e];
+        t = dd_fma_dd(t, ct.val[e], dd{yhi[k], ylo ? ylo[k] : 0.0});
+    }
+    t = wave_sum_dd(t);
+    if (lane == 0) {
+        if (lambda > 0.0) t = dd_fma_dd(t, lambda, dd{yhi[K + j], ylo ? ylo[K + j] : 0.0});
+        out_hi[j] = t.hi;
+        if (out_lo) out_lo[j] = t.lo;
+    }
+}
+
 // ------------------------------------------------------------ host driver
 
 int grid1(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 256), 4096)); }
@@ -769,6 +975,25 @@ struct Ctx {
 
     Ctx(const IterProblem &p, hipStream_t s) : pb(p), st(s) {
         L = (int)pb.cols;
+        if (pb.sp) {
+            // sparse: row-pass workgroups over the rows of T and the Tikhonov rows
+            cpt = 0; R = 1;
+            const int64_t total = pb.rows + (pb.lambda > 0.0 ? pb.cols : 0);
+            const int64_t want = 4 * (int64_t)device_cus();
+            nblocks = (int)std::max<int64_t>(1, std::min<int64_t>(want, ceil_div(total, CRP_NT / CRP_G)));
+            rows_per_block = ceil_div(total, nblocks);
+            nblocks = (int)std::max<int64_t>(1, ceil_div(total, rows_per_block));
+            chunk = 16;
+            ngroups = 1;
+            spart.alloc((size_t)nblocks * 4 * sizeof(double));
+            z.alloc((size_t)L * sizeof(double));
+            stbuf.alloc(sizeof(State));
+            state = stbuf.as<State>();
+            Pt.alloc((size_t)std::max<int64_t>(pb.r, 1) * L * sizeof(double));
+            transpose(L, pb.r, pb.P, pb.ldp, Pt.as<double>(), st);
+            Ptp = Pt.as<double>();
+            return;
+        }
         if (L <= 512) { cpt = 2; R = 8; }
         else if (L <= 1024) { cpt = 4; R = 4; }
         else if (L <= 2048) { cpt = 8; R = 4; }
@@ -813,6 +1038,10 @@ struct Ctx {
     // One pass: z = sum_j op_j T_j, st->acc = reduced accumulators.
     void sweep(int op, const double *w, double *y, double *xv, double *wv, double alpha = 0.0,
                double beta = 0.0) {
+        if (pb.sp) {
+            sweep_sparse(op, w, y, xv, wv, alpha, beta);
+            return;
+        }
         SweepArgs a;
         a.T = pb.T; a.ldt = pb.ldt; a.rows = pb.rows; a.L = L; a.nblocks = nblocks;
         a.rows_per_block = rows_per_block; a.w = w; a.zpart = zpart.as<double>();
@@ -837,6 +1066,39 @@ struct Ctx {
                                                  chunk, zred.as<double>(), sred.as<double>(), state);
         reduce_stage2_kernel<<<(unsigned)ceil_div(L, 256), 256, 0, st>>>(
             zred.as<double>(), sred.as<double>(), ngroups, L, z.as<double>(), state);
+        LSRN_HIP(hipGetLastError());
+    }
+
+    // Sparse sweep: row pass (q, row-local update, partial norms), column
+    // pass z = T^T c, and the partial norms reduced into st->acc.
+    void sweep_sparse(int op, const double *w, double *y, double *xv, double *wv, double alpha,
+                      double beta) {
+        CsrArgs a;
+        a.t = pb.sp->rows; a.K = pb.rows;
+        a.total = pb.rows + (pb.lambda > 0.0 ? pb.cols : 0);
+        a.rows_per_block = rows_per_block; a.w = w; a.y = y; a.xv = xv; a.wv = wv;
+        a.spart = spart.as<double>(); a.st = state; a.lambda = pb.lambda; a.alpha = alpha; a.beta = beta;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (profile) {
+            LSRN_HIP(hipEventCreate(&e0));
+            LSRN_HIP(hipEventCreate(&e1));
+            ev.push_back(e0);
+            ev.push_back(e1);
+            LSRN_HIP(hipEventRecord(e0, st));
+        }
+        switch (op) {
+            case OP_ATB: csr_row_pass_kernel<OP_ATB><<<nblocks, CRP_NT, 0, st>>>(a); break;
+            case OP_LSQR_TALL: csr_row_pass_kernel<OP_LSQR_TALL><<<nblocks, CRP_NT, 0, st>>>(a); break;
+            case OP_CS_TALL: csr_row_pass_kernel<OP_CS_TALL><<<nblocks, CRP_NT, 0, st>>>(a); break;
+            case OP_NORMAL: csr_row_pass_kernel<OP_NORMAL><<<nblocks, CRP_NT, 0, st>>>(a); break;
+            case OP_LSQR_FAT: csr_row_pass_kernel<OP_LSQR_FAT><<<nblocks, CRP_NT, 0, st>>>(a); break;
+            default: csr_row_pass_kernel<OP_CS_FAT><<<nblocks, CRP_NT, 0, st>>>(a); break;
+        }
+        csr_col_pass_kernel<<<(unsigned)ceil_div(L, CCP_NT / 64), CCP_NT, 0, st>>>(
+            pb.sp->cols, y, pb.lambda, pb.rows, z.as<double>(), state);
+        LSRN_HIP(hipGetLastError());
+        if (profile) LSRN_HIP(hipEventRecord(e1, st));
+        reduce_spart_kernel<<<1, 256, 0, st>>>(spart.as<double>(), nblocks, state);
         LSRN_HIP(hipGetLastError());
     }
 
@@ -1089,18 +1351,33 @@ IterResult iterate(const IterProblem &pb, const double *b, double *x, const lsrn
         LSRN_HIP(hipStreamSynchronize(st));
         // refinement: (A N)^T (A N) dy = N^T h, h = A^T (b - A x) - lambda^2 x in dd
         if (opt.refine > 0) {
-            DevBuf hhi((size_t)cx.nblocks * L * sizeof(double)), hlo((size_t)cx.nblocks * L * sizeof(double));
+            const int64_t total = pb.rows + (pb.lambda > 0.0 ? L : 0);
+            const size_t hlen = pb.sp ? (size_t)total : (size_t)cx.nblocks * L;
+            DevBuf hhi(hlen * sizeof(double)), hlo(hlen * sizeof(double));
             DevBuf h((size_t)L * sizeof(double)), c((size_t)r * sizeof(double));
             DevBuf zc((size_t)r * sizeof(double)), rc((size_t)r * sizeof(double)), pc((size_t)r * sizeof(double));
             DevBuf dx((size_t)L * sizeof(double));
+            // the sparse normal-equation sweep stores T p here for its column pass
+            DevBuf ybuf(pb.sp ? (size_t)(pb.rows + L) * sizeof(double) : 0);
             for (int step = 0; step < opt.refine; ++step) {
-                if (cx.cpt == 2) launch_resid_tall<2>(cx, b, x, hhi.as<double>(), hlo.as<double>());
-                else if (cx.cpt == 4) launch_resid_tall<4>(cx, b, x, hhi.as<double>(), hlo.as<double>());
-                else if (cx.cpt == 8) launch_resid_tall<8>(cx, b, x, hhi.as<double>(), hlo.as<double>());
-                else launch_resid_tall<16>(cx, b, x, hhi.as<double>(), hlo.as<double>());
-                LSRN_HIP(hipGetLastError());
-                reduce_dd_kernel<<<(unsigned)ceil_div(L, 256), 256, 0, st>>>(
-                    hhi.as<double>(), hlo.as<double>(), cx.nblocks, (int)L, nullptr, h.as<double>(), nullptr);
+                if (pb.sp) {
+                    // rows: res = b^ - T^ x (dd); columns: h = T^^T res (dd), rounded
+                    csr_resid_rows_dd_kernel<<<cx.nblocks, CRP_NT, 0, st>>>(
+                        pb.sp->rows, pb.rows, total, cx.rows_per_block, b, x, pb.lambda,
+                        hhi.as<double>(), hlo.as<double>());
+                    csr_col_pass_dd_kernel<<<(unsigned)ceil_div(L, CCP_NT / 64), CCP_NT, 0, st>>>(
+                        pb.sp->cols, hhi.as<double>(), hlo.as<double>(), pb.lambda, pb.rows,
+                        h.as<double>(), nullptr);
+                    LSRN_HIP(hipGetLastError());
+                } else {
+                    if (cx.cpt == 2) launch_resid_tall<2>(cx, b, x, hhi.as<double>(), hlo.as<double>());
+                    else if (cx.cpt == 4) launch_resid_tall<4>(cx, b, x, hhi.as<double>(), hlo.as<double>());
+                    else if (cx.cpt == 8) launch_resid_tall<8>(cx, b, x, hhi.as<double>(), hlo.as<double>());
+                    else launch_resid_tall<16>(cx, b, x, hhi.as<double>(), hlo.as<double>());
+                    LSRN_HIP(hipGetLastError());
+                    reduce_dd_kernel<<<(unsigned)ceil_div(L, 256), 256, 0, st>>>(
+                        hhi.as<double>(), hlo.as<double>(), cx.nblocks, (int)L, nullptr, h.as<double>(), nullptr);
+                }
                 cx.gemv(cx.Ptp, L, r, L, h.as<double>(), c.as<double>(), false);
                 const int cg_max = 200;
                 cg_init_kernel<<<1, SNT, 0, st>>>(c.as<double>(), r, zc.as<double>(), rc.as<double>(),
@@ -1109,7 +1386,7 @@ IterResult iterate(const IterProblem &pb, const double *b, double *x, const lsrn
                 while (!hs.done) {
                     for (int k = 0; k < CHUNK; ++k) {
                         cx.gemv(pb.P, pb.ldp, L, r, pc.as<double>(), ts.wN.as<double>());
-                        cx.sweep(OP_NORMAL, ts.wN.as<double>(), nullptr, nullptr, nullptr);
+                        cx.sweep(OP_NORMAL, ts.wN.as<double>(), ybuf.as<double>(), nullptr, nullptr);
                         cx.gemv(cx.Ptp, L, r, L, cx.z.as<double>(), ts.t.as<double>());
                         cg_step_kernel<<<1, SNT, 0, st>>>(ts.t.as<double>(), r, zc.as<double>(),
                                                           rc.as<double>(), pc.as<double>(), cx.state);
@@ -1135,17 +1412,24 @@ IterResult iterate(const IterProblem &pb, const double *b, double *x, const lsrn
         LSRN_HIP(hipEventRecord(e1, st));
         if (opt.refine > 0) {
             const int64_t n = pb.rows;
-            DevBuf zhi((size_t)cx.nblocks * L * sizeof(double)), zlo((size_t)cx.nblocks * L * sizeof(double));
+            const size_t zlen = pb.sp ? (size_t)L : (size_t)cx.nblocks * L;
+            DevBuf zhi(zlen * sizeof(double)), zlo(zlen * sizeof(double));
             DevBuf thi((size_t)L * sizeof(double)), tlo((size_t)L * sizeof(double));
             DevBuf xsave((size_t)n * sizeof(double));
             for (int step = 0; step < opt.refine; ++step) {
-                if (cx.cpt == 2) launch_ax_fat<2>(cx, x, zhi.as<double>(), zlo.as<double>());
-                else if (cx.cpt == 4) launch_ax_fat<4>(cx, x, zhi.as<double>(), zlo.as<double>());
-                else if (cx.cpt == 8) launch_ax_fat<8>(cx, x, zhi.as<double>(), zlo.as<double>());
-                else launch_ax_fat<16>(cx, x, zhi.as<double>(), zlo.as<double>());
+                if (pb.sp) {
+                    csr_col_pass_dd_kernel<<<(unsigned)ceil_div(L, CCP_NT / 64), CCP_NT, 0, st>>>(
+                        pb.sp->cols, x, nullptr, 0.0, pb.rows, zhi.as<double>(), zlo.as<double>());
+                } else {
+                    if (cx.cpt == 2) launch_ax_fat<2>(cx, x, zhi.as<double>(), zlo.as<double>());
+                    else if (cx.cpt == 4) launch_ax_fat<4>(cx, x, zhi.as<double>(), zlo.as<double>());
+                    else if (cx.cpt == 8) launch_ax_fat<8>(cx, x, zhi.as<double>(), zlo.as<double>());
+                    else launch_ax_fat<16>(cx, x, zhi.as<double>(), zlo.as<double>());
+                }
                 LSRN_HIP(hipGetLastError());
                 reduce_dd_kernel<<<(unsigned)ceil_div(L, 256), 256, 0, st>>>(
-                    zhi.as<double>(), zlo.as<double>(), cx.nblocks, (int)L, b, thi.as<double>(), tlo.as<double>());
+                    zhi.as<double>(), zlo.as<double>(), pb.sp ? 1 : cx.nblocks, (int)L, b,
+                    thi.as<double>(), tlo.as<double>());
                 // e = M^T (b - A x) with dd accumulation
                 gemv_t_dd_kernel<<<(unsigned)ceil_div(r, 4), 256, 0, st>>>(
                     pb.P, pb.ldp, L, r, thi.as<double>(), tlo.as<double>(), fs.t.as<double>());

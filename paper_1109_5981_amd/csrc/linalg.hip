@@ -1,0 +1,209 @@
+// linalg.hip -- dense FP64 building blocks on the matrix cores: a general
+// column-major GEMM and the inverse of an upper-triangular matrix (used for
+// the preconditioner N = R^-1 of a full-rank sketch).
+#include "internal.hpp"
+
+namespace lsrn {
+
+namespace {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int GBM = 128, GBN = 128, GKT = 16, GLDP = 144, GNT = 256;
+
+__device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// A (M x K, column-major, lda): stage kk rows of k, 128 consecutive i.
+__device__ __forceinline__ void load_a(const double *__restrict__ A, int64_t lda, int64_t M,
+                                       int64_t K, int64_t m0, int64_t k0, double (&reg)[8]) {
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+        const int idx = it * GNT + threadIdx.x;  // 0 .. 2047
+        const int kk = idx >> 7, i = idx & 127;
+        const int64_t k = k0 + kk, row = m0 + i;
+        reg[it] = (k < K && row < M) ? A[k * lda + row] : 0.0;
+    }
+}
+
+__device__ __forceinline__ void store_a(double (*As)[GLDP], const double (&reg)[8]) {
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+        const int idx = it * GNT + threadIdx.x;
+        As[idx >> 7][idx & 127] = reg[it];
+    }
+}
+
+// B (K x N, column-major, ldb): 16 consecutive k of column j per 16 lanes.
+__device__ __forceinline__ void load_b(const double *__restrict__ B, int64_t ldb, int64_t K,
+                                       int64_t N, int64_t k0, int64_t n0, double (&reg)[8]) {
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+        const int idx = it * GNT + threadIdx.x;
+        const int kk = idx & 15, j = idx >> 4;  // j 0 .. 127
+        const int64_t k = k0 + kk, col = n0 + j;
+        reg[it] = (k < K && col < N) ? B[col * ldb + k] : 0.0;
+    }
+}
+
+__device__ __forceinline__ void store_b(double (*Bs)[GLDP], const double (&reg)[8]) {
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+        const int idx = it * GNT + threadIdx.x;
+        Bs[idx & 15][idx >> 4] = reg[it];
+    }
+}
+
+// C = alpha A B + beta C; each workgroup one 128 x 128 tile of C (2 x 2
+// wavefronts of 64 x 64, 4 x 4 blocks of v_mfma_f64_16x16x4f64).
+__global__ void __launch_bounds__(GNT, 2)
+gemm_nn_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double *__restrict__ A,
+               int64_t lda, const double *__restrict__ B, int64_t ldb, double beta,
+               double *__restrict__ C, int64_t ldc, int tiles_m) {
+    __shared__ double As[2][GKT][GLDP];
+    __shared__ double Bs[2][GKT][GLDP];
+    const int64_t m0 = (int64_t)(blockIdx.x % tiles_m) * GBM;
+    const int64_t n0 = (int64_t)(blockIdx.x / tiles_m) * GBN;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave >> 1, wn = wave & 1, lr = lane & 15, lk = lane >> 4;
+    f64x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+    const int64_t nstage = ceil_div(K, GKT);
+    double ra[8], rb[8];
+    if (nstage > 0) {
+        load_a(A, lda, M, K, m0, 0, ra);
+        load_b(B, ldb, K, N, 0, n0, rb);
+        store_a(As[0], ra);
+        store_b(Bs[0], rb);
+    }
+    __syncthreads();
+    for (int64_t st = 0; st < nstage; ++st) {
+        const int buf = (int)(st & 1);
+        const bool more = st + 1 < nstage;
+        if (more) {
+            load_a(A, lda, M, K, m0, (st + 1) * GKT, ra);
+            load_b(B, ldb, K, N, (st + 1) * GKT, n0, rb);
+        }
+#pragma unroll
+        for (int kk = 0; kk < GKT / 4; ++kk) {
+            double a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = As[buf][kk * 4 + lk][wm * 64 + i * 16 + lr];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = Bs[buf][kk * 4 + lk][wn * 64 + j * 16 + lr];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = mfma16(a[i], b[j], acc[i][j]);
+        }
+        if (more) {
+            store_a(As[buf ^ 1], ra);
+            store_b(Bs[buf ^ 1], rb);
+        }
+        __syncthreads();
+    }
+    // accumulator element v of lane (lr, lk) is row lk + 4 v, column lr of
+    // its 16 x 16 block
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t col = n0 + wn * 64 + j * 16 + lr;
+            const int64_t rbase = m0 + wm * 64 + i * 16 + lk;
+            if (col < N) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t row = rbase + 4 * v;
+                    if (row < M) {
+                        double *c = C + col * ldc + row;
+                        *c = beta == 0.0 ? alpha * acc[i][j][v] : alpha * acc[i][j][v] + beta * *c;
+                    }
+                }
+            }
+        }
+}
+
+constexpr int TB = 64;  // diagonal block of the triangular inverse
+
+// Inverse of each 64 x 64 diagonal block of upper-triangular R (column-
+// major, ldr) into Rinv (column-major, ldi): thread j back-substitutes
+// column j of the block's inverse.
+__global__ void __launch_bounds__(TB)
+trtri_diag_kernel(int64_t d, const double *__restrict__ R, int64_t ldr, double *__restrict__ Rinv,
+                  int64_t ldi) {
+    __shared__ double Rs[TB][TB + 1];  // Rs[i][k] = R(o + i, o + k)
+    __shared__ double Xs[TB][TB + 1];  // Xs[i][j] = inverse (i, j)
+    const int64_t o = (int64_t)blockIdx.x * TB;
+    const int nb = (int)min<int64_t>(TB, d - o);
+    const int j = threadIdx.x;
+    for (int k = 0; k < nb; ++k)
+        if (j < nb) Rs[j][k] = R[(o + k) * ldr + o + j];
+    __syncthreads();
+    if (j < nb) {
+        for (int i = nb - 1; i >= 0; --i) {
+            double v;
+            if (i > j) {
+                v = 0.0;
+            } else {
+                double t = i == j ? 1.0 : 0.0;
+                for (int k = i + 1; k <= j; ++k) t -= Rs[i][k] * Xs[k][j];
+                v = t / Rs[i][i];
+            }
+            Xs[i][j] = v;
+        }
+    }
+    __syncthreads();
+    for (int k = 0; k < nb; ++k)
+        if (j < nb) Rinv[(o + k) * ldi + o + j] = Xs[j][k];
+}
+
+}  // namespace
+
+void gemm_nn(int64_t M, int64_t N, int64_t K, double alpha, const double *A, int64_t lda,
+             const double *B, int64_t ldb, double beta, double *C, int64_t ldc, hipStream_t st) {
+    if (M <= 0 || N <= 0) return;
+    const int64_t tm = ceil_div(M, GBM), tn = ceil_div(N, GBN);
+    LSRN_REQUIRE(tm * tn < ((int64_t)1 << 31), "gemm: too many tiles");
+    gemm_nn_kernel<<<(unsigned)(tm * tn), GNT, 0, st>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
+                                                       (int)tm);
+    LSRN_HIP(hipGetLastError());
+}
+
+namespace {
+
+// Off-diagonal blocks of the inverse, bottom-up over the halving tree: for
+// the diagonal block [off, off + n) split as [A B; 0 C] with both diagonal
+// inverses already in Rinv, Rinv(top-right) = -A^-1 B C^-1.
+void trtri_rec(int64_t off, int64_t n, const double *R, int64_t ldr, double *Rinv, int64_t ldi,
+               double *W, hipStream_t st) {
+    if (n <= TB) return;
+    const int64_t n1 = TB * ceil_div(ceil_div(n, 2), TB), n2 = n - n1;
+    trtri_rec(off, n1, R, ldr, Rinv, ldi, W, st);
+    trtri_rec(off + n1, n2, R, ldr, Rinv, ldi, W, st);
+    // W (n1 x n2, ld n1) = A^-1 B
+    gemm_nn(n1, n2, n1, 1.0, Rinv + off * ldi + off, ldi, R + (off + n1) * ldr + off, ldr, 0.0, W, n1,
+            st);
+    // top-right = -W C^-1
+    gemm_nn(n1, n2, n2, -1.0, W, n1, Rinv + (off + n1) * ldi + off + n1, ldi, 0.0,
+            Rinv + (off + n1) * ldi + off, ldi, st);
+}
+
+}  // namespace
+
+void trtri_upper(int64_t d, const double *R, int64_t ldr, double *Rinv, int64_t ldi, hipStream_t st) {
+    LSRN_HIP(hipMemsetAsync(Rinv, 0, (size_t)ldi * (size_t)d * sizeof(double), st));
+    trtri_diag_kernel<<<(unsigned)ceil_div(d, TB), TB, 0, st>>>(d, R, ldr, Rinv, ldi);
+    LSRN_HIP(hipGetLastError());
+    if (d > TB) {
+        const int64_t n1 = TB * ceil_div(ceil_div(d, 2), TB);
+        DevBuf W((size_t)n1 * (size_t)(d - n1) * sizeof(double));
+        trtri_rec(0, d, R, ldr, Rinv, ldi, W.as<double>(), st);
+        LSRN_HIP(hipStreamSynchronize(st));  // before W is freed
+    }
+}
+
+}  // namespace lsrn

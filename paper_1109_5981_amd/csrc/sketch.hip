@@ -275,6 +275,14 @@ void sketch_rows(int64_t K, int64_t d, const double *T, int64_t ldt, double lamb
     if (p.nsplit > 1) LSRN_HIP(hipStreamSynchronize(st));  // before `part` is freed
 }
 
+void add_identity_rows(int64_t K, int64_t d, int64_t s, double lambda, uint64_t seed, double *X,
+                       hipStream_t st) {
+    if (!(lambda > 0.0)) return;
+    const int blocks = (int)std::min<int64_t>(ceil_div(s * d, 256), 8192);
+    add_identity_rows_kernel<<<blocks, 256, 0, st>>>(K, d, s, lambda, seed, X);
+    LSRN_HIP(hipGetLastError());
+}
+
 void transpose(int64_t rows, int64_t cols, const double *in, int64_t ldin, double *out,
                hipStream_t st) {
     dim3 grid((unsigned)ceil_div(cols, 32), (unsigned)ceil_div(rows, 32));

@@ -652,6 +652,14 @@ form_p_kernel(const double *__restrict__ Y, int64_t d, int64_t r, const int64_t 
     }
 }
 
+// out[i] = |R(i, i)| (R the upper triangle of X, column-major, ld s).
+__global__ void __launch_bounds__(256)
+diag_abs_kernel(const double *__restrict__ X, int64_t s, int64_t d, double *__restrict__ out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < d;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = fabs(X[i * s + i]);
+}
+
 int grid1d(int64_t total) { return (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(total, 256), 16384)); }
 
 template <int NT, int EPT>
@@ -680,12 +688,9 @@ size_t precond_workspace_bytes(int64_t s, int64_t d) {
            sizeof(int64_t) * (size_t)d + 64;
 }
 
-PrecondResult precond(int64_t s, int64_t d, double *X, double rcond, double *sigma, double *P,
-                      hipStream_t st, bool profile) {
-    LSRN_REQUIRE(s >= d && d > 0, "precond: need s >= d > 0");
-    PrecondResult res;
-
-    // ---- Householder QR
+void householder_qr(int64_t s, int64_t d, double *X, hipStream_t st) {
+    LSRN_REQUIRE(s >= d && d > 0, "qr: need s >= d > 0");
+    if (s > 1024 * 40) fail(LSRN_E_UNSUPPORTED, "precond: the QR kernels support sketches of up to 40960 rows");
     DevBuf Vb((size_t)s * QNB * sizeof(double)), betab(QNB * sizeof(double));
     // panel width: 8 (4 when s > 4096) with the register panel kernel, 32
     // with the global-memory one for taller sketches
@@ -707,11 +712,21 @@ PrecondResult precond(int64_t s, int64_t d, double *X, double rcond, double *sig
             else if (rows <= 256 * 16) launch_apply<256, 16>(X, s, p0, nb, ncols, Vb.as<double>(), betab.as<double>(), st);
             else if (rows <= 256 * 32) launch_apply<256, 32>(X, s, p0, nb, ncols, Vb.as<double>(), betab.as<double>(), st);
             else if (rows <= 1024 * 16) launch_apply<1024, 16>(X, s, p0, nb, ncols, Vb.as<double>(), betab.as<double>(), st);
-            else if (rows <= 1024 * 40) launch_apply<1024, 40>(X, s, p0, nb, ncols, Vb.as<double>(), betab.as<double>(), st);
-            else fail(LSRN_E_UNSUPPORTED, "precond: sketch has too many rows for the QR kernels");
+            else launch_apply<1024, 40>(X, s, p0, nb, ncols, Vb.as<double>(), betab.as<double>(), st);
             LSRN_HIP(hipGetLastError());
         }
     }
+
+    LSRN_HIP(hipStreamSynchronize(st));  // before the panel buffers are freed
+}
+
+PrecondResult precond(int64_t s, int64_t d, double *X, double rcond, double *sigma, double *P,
+                      hipStream_t st, bool profile) {
+    LSRN_REQUIRE(s >= d && d > 0, "precond: need s >= d > 0");
+    PrecondResult res;
+
+    // ---- Householder QR
+    householder_qr(s, d, X, st);
 
     // ---- Jacobi on Y = R^T
     const double tol = (double)d * DBL_EPSILON;
@@ -810,6 +825,35 @@ PrecondResult precond(int64_t s, int64_t d, double *X, double rcond, double *sig
         LSRN_HIP(hipGetLastError());
     }
     LSRN_HIP(hipStreamSynchronize(st));
+    return res;
+}
+
+PrecondResult precond_qr_inverse(int64_t s, int64_t d, double *X, double rcond, double *sigma,
+                                 double *P, hipStream_t st) {
+    LSRN_REQUIRE(s >= d && d > 0, "precond: need s >= d > 0");
+    PrecondResult res;
+    householder_qr(s, d, X, st);
+    // |diag R| in descending order stands in for the singular values; the
+    // path needs a full-rank sketch
+    diag_abs_kernel<<<grid1d(d), 256, 0, st>>>(X, s, d, sigma);
+    LSRN_HIP(hipGetLastError());
+    std::vector<double> h((size_t)d);
+    LSRN_HIP(hipMemcpyAsync(h.data(), sigma, (size_t)d * sizeof(double), hipMemcpyDeviceToHost, st));
+    LSRN_HIP(hipStreamSynchronize(st));
+    std::sort(h.begin(), h.end(), [](double a, double b) { return a > b; });
+    const double rc = rcond > 0.0 ? rcond : (double)std::max(s, d) * DBL_EPSILON;
+    if (!(h[(size_t)d - 1] > rc * h[0]))
+        fail(LSRN_E_UNSUPPORTED, "precond: the QR-inverse preconditioner needs a full-rank sketch");
+    LSRN_HIP(hipMemcpyAsync(sigma, h.data(), (size_t)d * sizeof(double), hipMemcpyHostToDevice, st));
+    // P (row-major d x d) = R^-1: invert column-major, then transpose
+    DevBuf Rinv((size_t)d * (size_t)d * sizeof(double));
+    trtri_upper(d, X, s, Rinv.as<double>(), d, st);
+    transpose(d, d, Rinv.as<double>(), d, P, st);
+    LSRN_HIP(hipStreamSynchronize(st));
+    res.rank = d;
+    res.sweeps = 0;
+    res.sigma_max = h[0];
+    res.sigma_min_kept = h[(size_t)d - 1];
     return res;
 }
 

@@ -32,7 +32,8 @@ class Options(C.Structure):
     _fields_ = [("gamma", C.c_double), ("lambda_", C.c_double), ("tol", C.c_double),
                 ("rcond", C.c_double), ("t_margin", C.c_double), ("refine_tol", C.c_double),
                 ("seed", C.c_uint64), ("max_iter", C.c_int64), ("method", C.c_int32),
-                ("refine", C.c_int32), ("profile", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("refine", C.c_int32), ("profile", C.c_int32), ("precond", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
 
 class Info(C.Structure):
@@ -53,8 +54,12 @@ class Info(C.Structure):
 _lib = None
 
 EXPORTS = ["lsrn_default_options", "lsrn_status_string", "lsrn_last_error", "lsrn_solve_dense",
-           "lsrn_workspace_bytes", "lsrn_philox_words", "lsrn_gauss_fill", "lsrn_sketch_dense",
-           "lsrn_precond", "lsrn_iterate_dense"]
+           "lsrn_workspace_bytes", "lsrn_solve_csr", "lsrn_workspace_bytes_csr",
+           "lsrn_philox_words", "lsrn_gauss_fill", "lsrn_sketch_dense", "lsrn_sketch_csr",
+           "lsrn_precond", "lsrn_precond_qr", "lsrn_iterate_dense", "lsrn_iterate_csr"]
+PRECOND = {"auto": 0, "svd": 1, "qr": 2}
+_SIZE_FNS = ("lsrn_default_options", "lsrn_status_string", "lsrn_last_error",
+             "lsrn_workspace_bytes", "lsrn_workspace_bytes_csr")
 
 
 def lib():
@@ -79,9 +84,16 @@ def lib():
                                    C.POINTER(C.c_int64), P]
         L.lsrn_iterate_dense.argtypes = [I64, I64, P, I64, I32, P, P, I64, I64, I64, P,
                                          C.POINTER(Options), C.POINTER(Info), P]
+        L.lsrn_solve_csr.argtypes = [I64, I64, I64, P, P, P, P, P, C.POINTER(Options),
+                                     C.POINTER(Info), P]
+        L.lsrn_workspace_bytes_csr.argtypes = [I64, I64, I64, C.POINTER(Options)]
+        L.lsrn_workspace_bytes_csr.restype = C.c_size_t
+        L.lsrn_sketch_csr.argtypes = [I64, I64, I64, P, P, P, D, I64, U64, P, P]
+        L.lsrn_precond_qr.argtypes = [I64, I64, P, D, P, P, P]
+        L.lsrn_iterate_csr.argtypes = [I64, I64, I64, P, P, P, P, P, I64, I64, I64, P,
+                                       C.POINTER(Options), C.POINTER(Info), P]
         for name in EXPORTS:
-            if name not in ("lsrn_default_options", "lsrn_status_string", "lsrn_last_error",
-                            "lsrn_workspace_bytes"):
+            if name not in _SIZE_FNS:
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -110,6 +122,8 @@ def options(**kw) -> Options:
         k = alias.get(k, k)
         if k == "method" and isinstance(v, str):
             v = {"lsqr": LSQR, "chebyshev": CHEBYSHEV, "cs": CHEBYSHEV}[v.lower()]
+        if k == "precond" and isinstance(v, str):
+            v = PRECOND[v.lower()]
         setattr(o, k, v)
     return o
 
@@ -202,4 +216,83 @@ def iterate_dense(A: torch.Tensor, b: torch.Tensor, P: torch.Tensor, s: int, *,
     _check(lib().lsrn_iterate_dense(m, n, A.data_ptr(), lda, layout, b.data_ptr(), P.data_ptr(),
                                     P.stride(0), r, s, x.data_ptr(), C.byref(o), C.byref(info),
                                     _stream()))
+    return x, info.as_dict()
+
+
+class Csr:
+    """Device CSR matrix for the sparse entry points: rowptr int64 (m + 1),
+    colind int32 (nnz), val float64 (nnz), all contiguous on the GPU."""
+
+    def __init__(self, m: int, n: int, rowptr: torch.Tensor, colind: torch.Tensor,
+                 val: torch.Tensor):
+        for t, dt, name in ((rowptr, torch.int64, "rowptr"), (colind, torch.int32, "colind"),
+                            (val, torch.float64, "val")):
+            if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dt and t.is_contiguous()):
+                raise TypeError(f"{name} must be a contiguous {dt} tensor on the GPU")
+        if rowptr.numel() != m + 1 or colind.numel() != val.numel():
+            raise ValueError("CSR arrays have inconsistent sizes")
+        self.m, self.n, self.nnz = int(m), int(n), int(val.numel())
+        self.rowptr, self.colind, self.val = rowptr, colind, val
+
+    @classmethod
+    def from_host(cls, m, n, rowptr, colind, val, device="cuda"):
+        import numpy as np
+        return cls(m, n, torch.from_numpy(np.ascontiguousarray(rowptr, dtype=np.int64)).to(device),
+                   torch.from_numpy(np.ascontiguousarray(colind, dtype=np.int32)).to(device),
+                   torch.from_numpy(np.ascontiguousarray(val, dtype=np.float64)).to(device))
+
+    def args(self):
+        return (self.m, self.n, self.nnz, self.rowptr.data_ptr(), self.colind.data_ptr(),
+                self.val.data_ptr())
+
+
+def solve_csr(A: Csr, b: torch.Tensor, x: torch.Tensor | None = None, **opts):
+    """lsrn_solve_csr: min-length LS solution for CSR A.  Returns (x, info)."""
+    _dev_f64(b, "b")
+    if b.numel() != A.m or not b.is_contiguous():
+        raise ValueError("b must be contiguous with m entries")
+    if x is None:
+        x = torch.empty(A.n, dtype=torch.float64, device=b.device)
+    o, info = options(**opts), Info()
+    _check(lib().lsrn_solve_csr(*A.args(), b.data_ptr(), x.data_ptr(), C.byref(o), C.byref(info),
+                                _stream()))
+    return x, info.as_dict()
+
+
+def workspace_bytes_csr(m: int, n: int, nnz: int, **opts) -> int:
+    o = options(**opts)
+    return int(lib().lsrn_workspace_bytes_csr(m, n, nnz, C.byref(o)))
+
+
+def sketch_csr(A: Csr, s: int, seed: int = 0, lam: float = 0.0) -> torch.Tensor:
+    """X = G T for CSR A as a (d, s) tensor holding X column-major."""
+    d = min(A.m, A.n)
+    X = torch.empty((d, s), dtype=torch.float64, device=A.val.device)
+    _check(lib().lsrn_sketch_csr(*A.args(), lam, s, seed, X.data_ptr(), _stream()))
+    return X
+
+
+def precond_qr(Xcm: torch.Tensor, rcond: float = 0.0):
+    """The QR-inverse preconditioner of a sketch given column-major as (d, s).
+    Returns (|diag R| descending, P = R^-1 (d, d))."""
+    _dev_f64(Xcm, "X")
+    d, s = Xcm.shape
+    Xcm = Xcm.contiguous()
+    sigma = torch.empty(d, dtype=torch.float64, device=Xcm.device)
+    P = torch.empty((d, d), dtype=torch.float64, device=Xcm.device)
+    _check(lib().lsrn_precond_qr(s, d, Xcm.data_ptr(), rcond, sigma.data_ptr(), P.data_ptr(),
+                                 _stream()))
+    return sigma, P
+
+
+def iterate_csr(A: Csr, b: torch.Tensor, P: torch.Tensor, s: int, **opts):
+    """Steps 6-7 for CSR A with a given preconditioner P (d x r)."""
+    _dev_f64(b, "b")
+    _dev_f64(P, "P")
+    if P.stride(1) != 1:
+        raise ValueError("P must have unit stride in its last dimension")
+    x = torch.empty(A.n, dtype=torch.float64, device=b.device)
+    o, info = options(**opts), Info()
+    _check(lib().lsrn_iterate_csr(*A.args(), b.data_ptr(), P.data_ptr(), P.stride(0), P.shape[1], s,
+                                  x.data_ptr(), C.byref(o), C.byref(info), _stream()))
     return x, info.as_dict()
