@@ -25,9 +25,11 @@ namespace lsrn {
 
 namespace {
 
-constexpr int SK_NT = 256;  // threads of the sketch kernel
+constexpr int SK_NT = 512;  // threads of the sketch kernel
 constexpr int SK_S = 4;     // sketch rows per workgroup
 constexpr int SK_C = 4096;  // columns of T per workgroup (multiple of SK_NT)
+constexpr int SK_KB = 4 * (SK_NT / SK_S);  // rows of T per batch
+constexpr int SK_PF = 8;    // entries per thread loaded one batch ahead
 
 struct SkEntry {
     int32_t k;  // row of T
@@ -95,13 +97,16 @@ __global__ void gather_transpose_kernel(int64_t nnz, const int32_t *__restrict__
     }
 }
 
-// key of entry e for the sketch order: (column block, owning thread).
-__global__ void sketch_keys_kernel(int64_t nnz, const int32_t *__restrict__ idx, int C,
+// key of entry e for the sketch order: (column block, batch of rows of T,
+// owning thread); the stable sort keeps the rows in order within a key.
+__global__ void sketch_keys_kernel(int64_t nnz, const int32_t *__restrict__ idx,
+                                   const int32_t *__restrict__ rowof, int C, int64_t nbatch,
                                    uint32_t *__restrict__ keys) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz;
          e += (int64_t)gridDim.x * blockDim.x) {
         const int32_t c = idx[e];
-        keys[e] = (uint32_t)((c / C) * SK_NT + (c % SK_NT));
+        const int64_t batch = rowof[e] / SK_KB;
+        keys[e] = (uint32_t)(((int64_t)(c / C) * nbatch + batch) * SK_NT + (c % SK_NT));
     }
 }
 
@@ -121,46 +126,75 @@ __global__ void gather_sketch_kernel(int64_t nnz, const int32_t *__restrict__ pe
 template <int S, int NT>
 __global__ void __launch_bounds__(NT)
 csr_sketch_kernel(const SkEntry *__restrict__ ent, const int64_t *__restrict__ optr, int64_t K,
-                  int64_t d, int C, int64_t s, uint64_t seed, double *__restrict__ X) {
+                  int64_t d, int C, int64_t nbatch, int64_t s, uint64_t seed,
+                  double *__restrict__ X) {
+    static_assert(S == 4, "the LDS tiles hold 4 sketch rows per column as two 16-byte vectors");
     constexpr int QB = NT / S;  // Philox blocks (quads of rows of T) per batch per sketch row
     constexpr int KB = 4 * QB;  // rows of T per batch
     extern __shared__ double lds[];
-    double *Xs = lds;           // [S][C]
-    double *Gs = lds + S * C;   // [S][KB]
+    // Xs[c][i] = X(i0 + i, c0 + c), Gs[kl][i] = G(i0 + i, kb + kl): the S values
+    // an entry touches are contiguous
+    double2 *Xs = reinterpret_cast<double2 *>(lds);                      // [C][S/2]
+    double2 *Gs = reinterpret_cast<double2 *>(lds + (size_t)S * C);      // [KB][S/2]
+    double *Gd = lds + (size_t)S * C;
     const int tid = threadIdx.x;
     const int b = blockIdx.y;
     const int64_t i0 = (int64_t)blockIdx.x * S;
     const int64_t c0 = (int64_t)b * C;
     const int cw = (int)min<int64_t>((int64_t)C, d - c0);
-    for (int j = tid; j < S * C; j += NT) Xs[j] = 0.0;
-    int64_t e = optr[(int64_t)b * NT + tid];
-    const int64_t e1 = optr[(int64_t)b * NT + tid + 1];
+    for (int j = tid; j < S * C; j += NT) lds[j] = 0.0;
     const int gi = tid / QB, gq = tid % QB;
     const uint64_t grow = (uint64_t)min<int64_t>(i0 + gi, s - 1);
-    SkEntry cur = SkEntry{0, 0, 0.0};
-    bool have = e < e1;
-    if (have) cur = ent[e];
-    for (int64_t kb = 0; kb < K; kb += KB) {
+    // this thread's entries of batch j: [optr[g], optr[g + 1]), g = (b nbatch + j) NT + tid
+    const int64_t *op = optr + (int64_t)b * nbatch * NT + tid;
+    int64_t lo = op[0], hi = op[1];
+    SkEntry pf[SK_PF];
+#pragma unroll
+    for (int u = 0; u < SK_PF; ++u)
+        if (lo + u < hi) pf[u] = ent[lo + u];
+    auto apply = [&](const SkEntry &t, int64_t kb) {
+        const int kl = (int)((int64_t)t.k - kb);
+        const double2 g01 = Gs[kl * 2], g23 = Gs[kl * 2 + 1];
+        double2 x01 = Xs[t.c * 2], x23 = Xs[t.c * 2 + 1];
+        x01.x += t.v * g01.x;
+        x01.y += t.v * g01.y;
+        x23.x += t.v * g23.x;
+        x23.y += t.v * g23.y;
+        Xs[t.c * 2] = x01;
+        Xs[t.c * 2 + 1] = x23;
+    };
+    for (int64_t j = 0; j < nbatch; ++j) {
+        const int64_t kb = j * KB;
+        // next batch's range and first entries are loaded while this batch
+        // generates its slice of G and applies its entries
+        int64_t nlo = 0, nhi = 0;
+        if (j + 1 < nbatch) {
+            nlo = op[(j + 1) * NT];
+            nhi = op[(j + 1) * NT + 1];
+        }
+        SkEntry cur[SK_PF];
+#pragma unroll
+        for (int u = 0; u < SK_PF; ++u) cur[u] = pf[u];
         double g[4];
         gauss4(seed, grow, (uint64_t)(kb / 4 + gq), g);
         __syncthreads();  // previous batch done with Gs
 #pragma unroll
-        for (int w = 0; w < 4; ++w) Gs[gi * KB + 4 * gq + w] = g[w];
+        for (int w = 0; w < 4; ++w) Gd[(4 * gq + w) * S + gi] = g[w];
         __syncthreads();
-        const int64_t kend = kb + KB;
-        while (have && (int64_t)cur.k < kend) {
-            const int kl = (int)((int64_t)cur.k - kb);
 #pragma unroll
-            for (int i = 0; i < S; ++i) Xs[i * C + cur.c] += cur.v * Gs[i * KB + kl];
-            ++e;
-            have = e < e1;
-            if (have) cur = ent[e];
-        }
+        for (int u = 0; u < SK_PF; ++u)
+            if (nlo + u < nhi) pf[u] = ent[nlo + u];
+#pragma unroll
+        for (int u = 0; u < SK_PF; ++u)
+            if (lo + u < hi) apply(cur[u], kb);
+        for (int64_t e = lo + SK_PF; e < hi; ++e) apply(ent[e], kb);
+        lo = nlo;
+        hi = nhi;
     }
     __syncthreads();
     for (int j = tid; j < S * cw; j += NT) {
         const int c = j / S, i = j % S;
-        if (i0 + i < s) X[(c0 + c) * s + i0 + i] = Xs[i * C + c];
+        if (i0 + i < s) X[(c0 + c) * s + i0 + i] = lds[c * S + i];
     }
 }
 
@@ -246,8 +280,10 @@ void sketch_csr(const SparseView &v, double lambda, int64_t s, uint64_t seed, do
     const int64_t K = v.K, d = v.d, nnz = v.nnz;
     const int C = SK_C;
     const int64_t nb = ceil_div(d, C);
-    const int64_t ngroups = nb * SK_NT;
-    LSRN_REQUIRE(ngroups < ((int64_t)1 << 31), "too many column blocks");
+    const int64_t nbatch = std::max<int64_t>(1, ceil_div(K, SK_KB));
+    const int64_t ngroups = nb * nbatch * SK_NT;
+    LSRN_REQUIRE(ngroups < ((int64_t)1 << 31), "sparse sketch: too many (column block, batch) groups");
+    LSRN_REQUIRE(nb <= 65535, "sparse sketch: too many column blocks");
     DevBuf ent((size_t)std::max<int64_t>(nnz, 1) * sizeof(SkEntry));
     DevBuf optr((size_t)(ngroups + 1) * sizeof(int64_t));
     const CsrMat &t = v.rows;  // CSR(T)
@@ -255,7 +291,8 @@ void sketch_csr(const SparseView &v, double lambda, int64_t s, uint64_t seed, do
         DevBuf rowof((size_t)nnz * 4), keys((size_t)nnz * 4), ksort((size_t)nnz * 4);
         DevBuf iota((size_t)nnz * 4), perm((size_t)nnz * 4);
         expand_rows_kernel<<<grid_for(t.nrows), 256, 0, st>>>(t.nrows, t.ptr, rowof.as<int32_t>());
-        sketch_keys_kernel<<<grid_for(nnz), 256, 0, st>>>(nnz, t.idx, C, keys.as<uint32_t>());
+        sketch_keys_kernel<<<grid_for(nnz), 256, 0, st>>>(nnz, t.idx, rowof.as<int32_t>(), C, nbatch,
+                                                          keys.as<uint32_t>());
         iota_kernel<<<grid_for(nnz), 256, 0, st>>>(nnz, iota.as<int32_t>());
         LSRN_HIP(hipGetLastError());
         sort_pairs(keys.as<uint32_t>(), ksort.as<uint32_t>(), iota.as<int32_t>(), perm.as<int32_t>(),
@@ -269,7 +306,7 @@ void sketch_csr(const SparseView &v, double lambda, int64_t s, uint64_t seed, do
     } else {
         LSRN_HIP(hipMemsetAsync(optr.as<int64_t>(), 0, (size_t)(ngroups + 1) * sizeof(int64_t), st));
     }
-    const size_t lds = sizeof(double) * ((size_t)SK_S * C + 4 * SK_NT);
+    const size_t lds = sizeof(double) * ((size_t)SK_S * C + (size_t)SK_S * SK_KB);
     LSRN_HIP(hipFuncSetAttribute((const void *)csr_sketch_kernel<SK_S, SK_NT>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipEvent_t ev[2] = {nullptr, nullptr};
@@ -278,10 +315,9 @@ void sketch_csr(const SparseView &v, double lambda, int64_t s, uint64_t seed, do
         LSRN_HIP(hipEventCreate(&ev[1]));
         LSRN_HIP(hipEventRecord(ev[0], st));
     }
-    LSRN_REQUIRE(nb <= 65535, "too many column blocks");
     dim3 grid((unsigned)ceil_div(s, SK_S), (unsigned)nb);
     csr_sketch_kernel<SK_S, SK_NT><<<grid, SK_NT, lds, st>>>(ent.as<SkEntry>(), optr.as<int64_t>(), K, d,
-                                                             C, s, seed, X);
+                                                             C, nbatch, s, seed, X);
     LSRN_HIP(hipGetLastError());
     if (kernel_ms) {
         LSRN_HIP(hipEventRecord(ev[1], st));

@@ -89,6 +89,15 @@ PrecondResult precond_qr_inverse(int64_t s, int64_t d, double *X, double rcond, 
                                  double *P, hipStream_t st);
 
 // ---------------------------------------------------------- linalg.hip
+// C = alpha op(A) B + beta C, column-major (FP64 MFMA); op(A) = A^T when
+// ta (A then K x M); upper: only tiles touching the upper triangle.
+void gemm(bool ta, bool upper, int64_t M, int64_t N, int64_t K, double alpha, const double *A,
+          int64_t lda, const double *B, int64_t ldb, double beta, double *C, int64_t ldc,
+          hipStream_t st);
+// In-place Cholesky C = R^T R of the upper triangle of C (d x d, column-
+// major, ldc), R written over the upper triangle; false on a pivot <= 0.
+// Synchronises.
+bool cholesky_upper(int64_t d, double *C, int64_t ldc, hipStream_t st);
 // C = alpha A B + beta C, all column-major (FP64 MFMA).
 void gemm_nn(int64_t M, int64_t N, int64_t K, double alpha, const double *A, int64_t lda,
              const double *B, int64_t ldb, double beta, double *C, int64_t ldc, hipStream_t st);

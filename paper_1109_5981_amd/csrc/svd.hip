@@ -832,26 +832,46 @@ PrecondResult precond_qr_inverse(int64_t s, int64_t d, double *X, double rcond, 
                                  double *P, hipStream_t st) {
     LSRN_REQUIRE(s >= d && d > 0, "precond: need s >= d > 0");
     PrecondResult res;
-    householder_qr(s, d, X, st);
-    // |diag R| in descending order stands in for the singular values; the
-    // path needs a full-rank sketch
-    diag_abs_kernel<<<grid1d(d), 256, 0, st>>>(X, s, d, sigma);
-    LSRN_HIP(hipGetLastError());
-    std::vector<double> h((size_t)d);
-    LSRN_HIP(hipMemcpyAsync(h.data(), sigma, (size_t)d * sizeof(double), hipMemcpyDeviceToHost, st));
-    LSRN_HIP(hipStreamSynchronize(st));
-    std::sort(h.begin(), h.end(), [](double a, double b) { return a > b; });
     const double rc = rcond > 0.0 ? rcond : (double)std::max(s, d) * DBL_EPSILON;
+    std::vector<double> h((size_t)d);
+    auto sorted_diag = [&](const double *R, int64_t ldr) {
+        diag_abs_kernel<<<grid1d(d), 256, 0, st>>>(R, ldr, d, sigma);
+        LSRN_HIP(hipGetLastError());
+        LSRN_HIP(hipMemcpyAsync(h.data(), sigma, (size_t)d * sizeof(double), hipMemcpyDeviceToHost, st));
+        LSRN_HIP(hipStreamSynchronize(st));
+        std::sort(h.begin(), h.end(), [](double a, double b) { return a > b; });
+    };
+    // Cholesky QR: R^T R = X^T X from the upper triangle of the Gram matrix
+    // (one FP64 MFMA product, then a blocked Cholesky).  X R^-1 is then
+    // orthonormal to about d eps kappa(X)^2, so it is used only while
+    // max r_ii / min r_ii (a lower bound on kappa) keeps that below 1e-3;
+    // otherwise, or when a pivot is not positive, Householder QR of X.
+    DevBuf gram((size_t)d * (size_t)d * sizeof(double));
+    gemm(true, true, d, d, s, 1.0, X, s, X, s, 0.0, gram.as<double>(), d, st);
+    const double *R = gram.as<double>();
+    int64_t ldr = d;
+    bool ok = cholesky_upper(d, gram.as<double>(), d, st);
+    if (ok) {
+        sorted_diag(R, ldr);
+        const double ratio = h[0] / h[(size_t)d - 1];
+        ok = h[(size_t)d - 1] > 0.0 && ratio * ratio * (double)d * DBL_EPSILON <= 1e-3;
+    }
+    if (!ok) {
+        gram.release();
+        householder_qr(s, d, X, st);
+        R = X;
+        ldr = s;
+        sorted_diag(R, ldr);
+    }
     if (!(h[(size_t)d - 1] > rc * h[0]))
         fail(LSRN_E_UNSUPPORTED, "precond: the QR-inverse preconditioner needs a full-rank sketch");
     LSRN_HIP(hipMemcpyAsync(sigma, h.data(), (size_t)d * sizeof(double), hipMemcpyHostToDevice, st));
     // P (row-major d x d) = R^-1: invert column-major, then transpose
     DevBuf Rinv((size_t)d * (size_t)d * sizeof(double));
-    trtri_upper(d, X, s, Rinv.as<double>(), d, st);
+    trtri_upper(d, R, ldr, Rinv.as<double>(), d, st);
     transpose(d, d, Rinv.as<double>(), d, P, st);
     LSRN_HIP(hipStreamSynchronize(st));
     res.rank = d;
-    res.sweeps = 0;
     res.sigma_max = h[0];
     res.sigma_min_kept = h[(size_t)d - 1];
     return res;
