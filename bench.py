@@ -24,11 +24,15 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 FP64_MFMA_PEAK_TFS = 78.6    # MI355X dense FP64 matrix
+BF16_MFMA_PEAK_TFS = 2500.0  # MI355X dense BF16 matrix
 
 WORKLOADS = {
     "rankdef_200000x2000": dict(m=200_000, n=2000, rank=1800, smin=1e-6, seed=12, fat=False),
     "rankdef_2000x200000": dict(m=200_000, n=2000, rank=1800, smin=1e-6, seed=112, fat=True),
-    "dense_2000x100": dict(m=2000, n=100, rank=100, smin=1e-6, seed=11, fat=False),
+    "dense_2000x100": dict(m=2000, n=100, rank=100, smin=1e-6, seed=11, fat=False, noise=1e-3),
+    # the precision-form workload: full rank, sigma 1 .. 1e-8, b = A x + 1e-6 noise
+    "dense_1000000x4000": dict(m=1_000_000, n=4000, rank=4000, smin=1e-8, seed=14, fat=False,
+                               noise=1e-6),
 }
 
 
@@ -103,6 +107,8 @@ def main():
     ap.add_argument("--workload", default="rankdef_200000x2000", choices=sorted(WORKLOADS))
     ap.add_argument("--method", default="lsqr", choices=["lsqr", "chebyshev"])
     ap.add_argument("--refine", type=int, default=1)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--precond", default="auto", choices=["auto", "svd", "qr"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="do not time individual kernels with HIP events")
@@ -147,14 +153,20 @@ def main():
     else:
         m_ls, n_ls, layout = wl["m"], wl["n"], lsrn.ROW_MAJOR
         Ufat, Vfat = U, V
-    b = workloads.rhs_gauss_device(m_ls, wl["seed"], device=dev)
+    if "noise" in wl:
+        b, _ = workloads.rhs_model_device(A, wl["noise"], wl["seed"])
+    else:
+        b = workloads.rhs_gauss_device(m_ls, wl["seed"], device=dev)
     # min-length solution of the generating (unrounded) matrix U diag(sigma) V^T
-    x_gen = Vfat @ ((Ufat.T @ b) / sigma)
+    x_gen = Vfat @ (workloads.matvec_device(Ufat, b, trans=True) / sigma)
+    del U, V, Ufat, Vfat
+    torch.cuda.empty_cache()  # the library allocates with hipMalloc, outside torch's cache
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t_gen
 
     opts = dict(method=args.method, refine=args.refine, seed=2024, tol=1e-14,
-                profile=0 if args.no_profile else 1)
+                profile=0 if args.no_profile else 1, precision=args.precision,
+                precond=args.precond)
     for _ in range(args.warmup):
         x, info = lsrn.solve_dense(A, b, layout=layout, **opts)
     torch.cuda.synchronize()
@@ -173,12 +185,20 @@ def main():
 
     # accuracy of the last solve
     err_gen = (torch.linalg.norm(x - x_gen) / torch.linalg.norm(x_gen)).item()
+    err_fp64 = None
+    if args.precision != "fp64":
+        # the plain FP64 path on the same problem (untimed), refined to convergence
+        ref_opts = dict(opts, precision="fp64", refine=max(args.refine, 6), profile=0)
+        x64, _ = lsrn.solve_dense(A, b, layout=layout, **ref_opts)
+        err_fp64 = (torch.linalg.norm(x - x64) / torch.linalg.norm(x64)).item()
+        del x64
     if layout == lsrn.ROW_MAJOR:
-        res = b - A @ x
-        ne = torch.linalg.norm(A.T @ res) / (sigma[0] * torch.linalg.norm(res))
+        res = b - workloads.matvec_device(A, x)
+        ne = torch.linalg.norm(workloads.matvec_device(A, res, trans=True)) / (
+            sigma[0] * torch.linalg.norm(res))
     else:
-        res = b - A.T @ x
-        ne = torch.linalg.norm(A @ res) / (sigma[0] * torch.linalg.norm(res))
+        res = b - workloads.matvec_device(A, x, trans=True)
+        ne = torch.linalg.norm(workloads.matvec_device(A, res)) / (sigma[0] * torch.linalg.norm(res))
     ne = ne.item()
 
     info = infos[-1]
@@ -186,7 +206,8 @@ def main():
     K = wl["m"]                              # rows of the tall view
     sketch_flop = 2.0 * s * K * d
     sweeps_per_solve = info["sweep_kernels"] if info["sweep_kernels"] else None
-    bytes_per_sweep = 8.0 * K * d + 16.0 * K  # one read of A + long vector read/write
+    # one read of A (FP32 copy in the precision form) + long vector read/write
+    bytes_per_sweep = (8.0 if args.precision == "fp64" else 4.0) * K * d + 16.0 * K
     mean = lambda key: sum(i[key] for i in infos) / len(infos)
     t_sketch_k = mean("t_sketch_kernel_ms")
     t_sweep_k = mean("t_sweep_kernel_ms")
@@ -197,11 +218,17 @@ def main():
     bytes_per_round = 16.0 * d * d
 
     kernels = {}
-    if t_sketch_k > 0:
+    if t_sketch_k > 0 and args.precision == "fp64":
         kernels["sketch_mfma_f64"] = {
             "avg_ms": t_sketch_k, "launches_per_step": 1, "bound": "mfma",
             "achieved": sketch_flop / (t_sketch_k * 1e-3) / 1e12, "unit": "TFLOP/s",
             "peak": FP64_MFMA_PEAK_TFS}
+    elif t_sketch_k > 0:
+        # three BF16 products (the exact split of fl32(A)) per element of G A
+        kernels["sketch_mfma_bf16x3"] = {
+            "avg_ms": t_sketch_k, "launches_per_step": 1, "bound": "mfma",
+            "achieved": 3 * sketch_flop / (t_sketch_k * 1e-3) / 1e12, "unit": "TFLOP/s",
+            "peak": BF16_MFMA_PEAK_TFS}
     if t_sweep_k > 0 and n_sweep > 0:
         avg = t_sweep_k / n_sweep
         kernels["row_sweep"] = {
@@ -223,7 +250,7 @@ def main():
                     "frac": round(kk["achieved"] / kk["peak"], 4), "traffic": None}
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "rankdef_200000x2000":
         A_np = A.cpu().numpy()
         b_np = b.cpu().numpy()
         iters_total = info["iters"] + info["refine_iters"] + 2 * info["refine_steps"]
@@ -241,10 +268,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "bf16 sketch + f32 sweeps + f64",
         "data": "synthetic (seeded; U, V Haar, sigma log-spaced, b ~ N(0,1))",
         "config": {"workload": args.workload, "m": m_ls, "n": n_ls, "rank": wl["rank"],
-                   "gamma": 2.0, "tol": 1e-14, "method": args.method, "refine": args.refine},
+                   "gamma": 2.0, "tol": 1e-14, "method": args.method, "refine": args.refine,
+                   "precision": args.precision, "precond": args.precond},
         "latency_ms": {"p50": round(percentile(lat, 50), 3), "p99": round(percentile(lat, 99), 3)},
         "sketch_tflops": round(sketch_flop / (mean("t_sketch_ms") * 1e-3) / 1e12, 3),
         "iter_gbs": (round(bytes_per_sweep * n_sweep / (mean("t_iter_ms") + mean("t_refine_ms"))
@@ -254,6 +282,8 @@ def main():
         "iters": info["iters"], "refine_iters": info["refine_iters"], "rank": r, "s": s,
         "jacobi_sweeps": info["sweeps"],
         "rel_err_vs_generator": err_gen,
+        "rel_err_vs_fp64_path": err_fp64,
+        "refine_steps": info["refine_steps"],
         "rel_normal_residual": ne,
         "kernels": kernels,
         "roofline": roofline,

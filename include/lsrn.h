@@ -65,6 +65,25 @@ typedef enum { LSRN_ROW_MAJOR = 0, LSRN_COL_MAJOR = 1 } lsrn_layout;
  *     else LSRN_E_UNSUPPORTED. */
 typedef enum { LSRN_PRECOND_AUTO = 0, LSRN_PRECOND_SVD = 1, LSRN_PRECOND_QR = 2 } lsrn_precond_kind;
 
+/* Arithmetic of the solve (dense A only).
+ *   LSRN_PREC_FP64: everything in FP64 (refinement residuals in
+ *     double-double).
+ *   LSRN_PREC_MIXED: the precision form.  The sketch is bf16(G) fl32(A) on
+ *     the BF16 matrix cores (A rounded to FP32 and split exactly into three
+ *     BF16 terms, FP32 accumulation flushed to FP64); the library keeps an
+ *     FP32 copy of A (4 m n bytes) that every LSQR sweep reads, accumulating
+ *     in FP64; the SVD / cutoff / N, the scalar recurrences and the
+ *     refinement residuals (double-double, with the FP64 A) stay FP64.  The
+ *     main LSQR stops at max(tol, 1e-8) and refinement steps (opt->refine, 10
+ *     when 0) bring x to the FP64 solution while kappa(A) * 2^-24 << 1.
+ *     The Chebyshev bounds of Sec. 4.2 hold for the exact sketch only, so
+ *     LSRN_CHEBYSHEV is rejected (LSRN_E_UNSUPPORTED), and so are
+ *     under-determined A: the FP32 sweeps would leave a component of size
+ *     about kappa(A) 2^-24 outside range(A^T) that residual refinement does
+ *     not remove.  Refinement stops when a correction is below 1e-15 ||x||
+ *     or no longer half the previous one. */
+typedef enum { LSRN_PREC_FP64 = 0, LSRN_PREC_MIXED = 1 } lsrn_precision;
+
 typedef struct lsrn_options {
     double gamma;      /* oversampling factor gamma > 1 (Alg. 1 step 1); 2     */
     double lambda;     /* Tikhonov weight, W = lambda I (Sec. 5); 0            */
@@ -86,7 +105,8 @@ typedef struct lsrn_options {
                           with HIP events on `stream` (lsrn_info fields
                           t_*_kernel_ms); 0                                     */
     int32_t precond;   /* lsrn_precond_kind; LSRN_PRECOND_AUTO                 */
-    int32_t reserved[2];
+    int32_t precision; /* lsrn_precision; LSRN_PREC_FP64                       */
+    int32_t reserved[1];
 } lsrn_options;
 
 typedef struct lsrn_info {
@@ -188,6 +208,12 @@ lsrn_status lsrn_gauss_fill(uint64_t seed, int64_t row0, int64_t nrows, int64_t 
 lsrn_status lsrn_sketch_dense(int64_t m, int64_t n, const double *A, int64_t lda,
                               int32_t layout, double lambda, int64_t s, uint64_t seed,
                               double *X, void *stream);
+
+/* The precision form's sketch X = bf16(G) fl32(T) (+ lambda G(:, K + c) in
+ * FP64), arguments and layout as lsrn_sketch_dense. */
+lsrn_status lsrn_sketch_dense_bf16(int64_t m, int64_t n, const double *A, int64_t lda,
+                                   int32_t layout, double lambda, int64_t s, uint64_t seed,
+                                   double *X, void *stream);
 
 /* lsrn_sketch_dense for CSR A (arguments as in lsrn_solve_csr). */
 lsrn_status lsrn_sketch_csr(int64_t m, int64_t n, int64_t nnz, const int64_t *rowptr,

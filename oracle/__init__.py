@@ -69,7 +69,9 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH):
+        hdr = os.path.join(os.path.dirname(_SRC), "lsrn_oracle.h")
+        if (not os.path.exists(_LIB_PATH)
+                or os.path.getmtime(_LIB_PATH) < max(os.path.getmtime(_SRC), os.path.getmtime(hdr))):
             build(force=True)
         L = C.CDLL(_LIB_PATH)
         P = C.c_void_p
@@ -83,6 +85,10 @@ def lib():
         L.orc_matvec_t.argtypes = [P, P, P]
         L.orc_sketch.argtypes = [P, C.c_int64, C.c_uint64, P]
         L.orc_sketch.restype = C.c_int64
+        L.orc_sketch_bf16.argtypes = [P, C.c_int64, C.c_uint64, P]
+        L.orc_sketch_bf16.restype = C.c_int64
+        L.orc_bf16_round.argtypes = [C.c_float]
+        L.orc_bf16_round.restype = C.c_float
         L.orc_qr_r.argtypes = [C.c_int64, C.c_int64, P, P]
         L.orc_jacobi_rt.argtypes = [C.c_int64, P, P, C.c_int]
         L.orc_precond.argtypes = [C.c_int64, C.c_int64, P, C.c_double, P, P, P]
@@ -234,6 +240,19 @@ def sketch(M: Matrix, s: int, seed: int) -> np.ndarray:
     if rc < 0:
         raise ValueError("orc_sketch rejected the input")
     return X
+
+
+def sketch_bf16(M: "Matrix", s: int, seed: int = 0) -> np.ndarray:
+    """The precision form's sketch bf16(G) fl32(T) (s x d), exact products in FP64."""
+    d = M.n if is_tall(M) else M.m
+    X = np.zeros((s, d))
+    st = M._struct()
+    lib().orc_sketch_bf16(C.byref(st), s, seed, _ptr(X))
+    return X
+
+
+def bf16_round(f: float) -> float:
+    return float(lib().orc_bf16_round(f))
 
 
 def qr_r(X) -> np.ndarray:

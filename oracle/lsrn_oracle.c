@@ -175,13 +175,31 @@ static int is_tall(const orc_matrix *A)
  * A~ (tall) or A~^T (fat).  X[i][j] = sum_k G(i,k) T[k][j], k ascending.
  * ==================================================================== */
 
-int64_t orc_sketch(const orc_matrix *A, int64_t s, uint64_t seed, double *X)
+/* Round a float to the nearest BF16 value (8 significant bits), ties to
+ * even, returned as a float. */
+float orc_bf16_round(float f)
+{
+    uint32_t u;
+    memcpy(&u, &f, sizeof(u));
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    u &= 0xFFFF0000u;
+    float r;
+    memcpy(&r, &u, sizeof(r));
+    return r;
+}
+
+/* The sketch; with precision_form the entries of G become bf16(fl32(g))
+ * and those of A fl32(a) (the Tikhonov rows keep FP64 lambda g). */
+static int64_t sketch_impl(const orc_matrix *A, int64_t s, uint64_t seed, double *X,
+                           int precision_form)
 {
     if (s <= 0 || A->m <= 0 || A->n <= 0)
         return -1;
     const int tall = is_tall(A);
     const int64_t d = tall ? A->n : A->m;
     memset(X, 0, sizeof(double) * (size_t)s * (size_t)d);
+#define G_OF(v) (precision_form ? (double)orc_bf16_round((float)(v)) : (v))
+#define A_OF(v) (precision_form ? (double)(float)(v) : (v))
 
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < s; ++i) {
@@ -191,7 +209,7 @@ int64_t orc_sketch(const orc_matrix *A, int64_t s, uint64_t seed, double *X)
             for (int64_t j = 0; j < A->m; ++j) {
                 double acc = 0.0;
                 for (int64_t p = A->rowptr[j]; p < A->rowptr[j + 1]; ++p)
-                    acc += orc_gauss(seed, (uint64_t)i, (uint64_t)A->colind[p]) * A->val[p];
+                    acc += G_OF(orc_gauss(seed, (uint64_t)i, (uint64_t)A->colind[p])) * A_OF(A->val[p]);
                 xi[j] = acc;
             }
             continue;
@@ -204,16 +222,16 @@ int64_t orc_sketch(const orc_matrix *A, int64_t s, uint64_t seed, double *X)
                 cached_q = k / 4;
                 gauss_block(seed, (uint64_t)i, (uint64_t)cached_q, g4);
             }
-            const double g = g4[k % 4];
+            const double g = G_OF(g4[k % 4]);
             if (A->kind == ORC_CSR) {
                 for (int64_t p = A->rowptr[k]; p < A->rowptr[k + 1]; ++p)
-                    xi[A->colind[p]] += g * A->val[p];
+                    xi[A->colind[p]] += g * A_OF(A->val[p]);
             } else if (tall) {
                 for (int64_t j = 0; j < d; ++j)
-                    xi[j] += g * a_at(A, k, j);
+                    xi[j] += g * A_OF(a_at(A, k, j));
             } else {
                 for (int64_t j = 0; j < d; ++j)
-                    xi[j] += g * a_at(A, j, k);
+                    xi[j] += g * A_OF(a_at(A, j, k));
             }
         }
         if (tall && A->lambda > 0.0) {
@@ -223,7 +241,19 @@ int64_t orc_sketch(const orc_matrix *A, int64_t s, uint64_t seed, double *X)
                 xi[c] += orc_gauss(seed, (uint64_t)i, (uint64_t)(A->m + c)) * A->lambda;
         }
     }
+#undef G_OF
+#undef A_OF
     return d;
+}
+
+int64_t orc_sketch(const orc_matrix *A, int64_t s, uint64_t seed, double *X)
+{
+    return sketch_impl(A, s, seed, X, 0);
+}
+
+int64_t orc_sketch_bf16(const orc_matrix *A, int64_t s, uint64_t seed, double *X)
+{
+    return sketch_impl(A, s, seed, X, 1);
 }
 
 /* ====================================================================

@@ -20,6 +20,8 @@
  *   orc_gauss           pinned: Box-Muller identity vs libm, moments, KS test
  *   orc_sketch          pinned: exact rational check on integer-valued A,
  *                               brute force via orc_gauss on tiny inputs
+ *   orc_sketch_bf16     pinned: torch's BF16 rounding of G times fl32(A)
+ *   orc_bf16_round      pinned: torch.bfloat16 conversion, ties to even
  *   orc_qr_r            pinned: R^T R = X^T X, LAPACK |diag R|
  *   orc_jacobi_rt       pinned: LAPACK singular values, W W^T = R^T R
  *   orc_precond         pinned: X N orthonormal, range(N) = range(X^T)
@@ -97,6 +99,14 @@ void orc_matvec_t(const orc_matrix *A, const double *y, double *x);
  * orc_gauss(seed, i, k) for i < s, k < rows(T).
  * X is s x d, row-major.  Returns d, or -1 on bad input. */
 int64_t orc_sketch(const orc_matrix *A, int64_t s, uint64_t seed, double *X);
+
+/* The precision form's sketch: as orc_sketch with G(i, k) replaced by
+ * bf16(fl32(G(i, k))) and A by fl32(A) (exact products summed in FP64);
+ * the Tikhonov rows lambda G(i, K + c) stay FP64. */
+int64_t orc_sketch_bf16(const orc_matrix *A, int64_t s, uint64_t seed, double *X);
+
+/* Nearest BF16 value of a float (ties to even). */
+float orc_bf16_round(float f);
 
 /* ------------------------------------------------------------ SVD */
 

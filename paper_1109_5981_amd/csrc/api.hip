@@ -104,6 +104,10 @@ void check_options(const lsrn_options &o) {
     LSRN_REQUIRE(o.precond == LSRN_PRECOND_AUTO || o.precond == LSRN_PRECOND_SVD ||
                      o.precond == LSRN_PRECOND_QR,
                  "unknown preconditioner kind");
+    LSRN_REQUIRE(o.precision == LSRN_PREC_FP64 || o.precision == LSRN_PREC_MIXED,
+                 "unknown precision");
+    if (o.precision == LSRN_PREC_MIXED && o.method == LSRN_CHEBYSHEV)
+        fail(LSRN_E_UNSUPPORTED, "the Chebyshev bounds do not hold for the precision form's sketch");
 }
 
 // The tall view T of A (row-major, K x d): A itself for tall row-major or
@@ -189,14 +193,28 @@ lsrn_status solve_impl(bool tall, int64_t K, int64_t d, int64_t n, const TallVie
                        lsrn_info *info, hipStream_t st, StageTimer &tm) {
     const int64_t s = (int64_t)std::ceil(opt.gamma * (double)d);
     const bool qr_inv = use_qr_inverse(opt, d);
+    const bool mixed = opt.precision == LSRN_PREC_MIXED;
+    if (mixed && sv) fail(LSRN_E_UNSUPPORTED, "the precision form is provided for dense A");
+    // FP32 sweeps keep the fat iterate in range(fl32(A)^T); residual
+    // refinement cannot remove the part outside range(A^T), so the
+    // min-length solution would be off by about kappa(A) 2^-24
+    if (mixed && !tall)
+        fail(LSRN_E_UNSUPPORTED, "the precision form is provided for over-determined A");
     DevBuf X((size_t)s * (size_t)d * sizeof(double));
     double sketch_kernel_ms = 0.0;
-    if (sv)
+    DevBuf T32;
+    if (sv) {
         sketch_csr(*sv, tall ? opt.lambda : 0.0, s, opt.seed, X.as<double>(), st,
                    opt.profile ? &sketch_kernel_ms : nullptr);
-    else
+    } else if (mixed) {
+        T32.alloc((size_t)K * (size_t)dv->ldt * sizeof(float));
+        to_f32(K, d, dv->T, dv->ldt, T32.as<float>(), st);
+        sketch_rows_bf16(K, d, dv->T, dv->ldt, tall ? opt.lambda : 0.0, s, opt.seed, X.as<double>(),
+                         st, opt.profile ? &sketch_kernel_ms : nullptr);
+    } else {
         sketch_rows(K, d, dv->T, dv->ldt, tall ? opt.lambda : 0.0, s, opt.seed, X.as<double>(), st,
                     opt.profile ? &sketch_kernel_ms : nullptr);
+    }
     tm.mark();
     DevBuf sigma((size_t)d * sizeof(double)), P((size_t)d * (size_t)d * sizeof(double));
     PrecondResult pr = qr_inv ? precond_qr_inverse(s, d, X.as<double>(), opt.rcond, sigma.as<double>(),
@@ -213,7 +231,15 @@ lsrn_status solve_impl(bool tall, int64_t K, int64_t d, int64_t n, const TallVie
         else { pb.T = dv->T; pb.ldt = dv->ldt; }
         pb.lambda = tall ? opt.lambda : 0.0; pb.P = P.as<double>(); pb.ldp = d;
         pb.r = pr.rank; pb.s = s;
-        ir = iterate(pb, b, x, opt, st);
+        if (mixed) {
+            pb.T32 = T32.as<float>();
+            lsrn_options om = opt;
+            om.tol = std::max(opt.tol, 1e-8);
+            if (om.refine == 0) om.refine = 10;
+            ir = iterate(pb, b, x, om, st);
+        } else {
+            ir = iterate(pb, b, x, opt, st);
+        }
     } else {
         LSRN_HIP(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), st));
     }
@@ -300,6 +326,20 @@ lsrn_status lsrn_sketch_dense(int64_t m, int64_t n, const double *A, int64_t lda
     make_view(v, m, n, A, lda, layout, lambda, st);
     sketch_rows(v.K, v.d, v.T, v.ldt, v.tall ? lambda : 0.0, s, seed, X, st);
     LSRN_HIP(hipStreamSynchronize(st));
+    LSRN_API_END
+}
+
+lsrn_status lsrn_sketch_dense_bf16(int64_t m, int64_t n, const double *A, int64_t lda,
+                                   int32_t layout, double lambda, int64_t s, uint64_t seed,
+                                   double *X, void *stream) {
+    LSRN_API_BEGIN
+    LSRN_REQUIRE(m > 0 && n > 0 && s > 0, "sizes must be positive");
+    LSRN_REQUIRE(A && X, "NULL pointer");
+    LSRN_REQUIRE(lambda >= 0.0, "lambda must be >= 0");
+    hipStream_t st = (hipStream_t)stream;
+    TallView v;
+    make_view(v, m, n, A, lda, layout, lambda, st);
+    sketch_rows_bf16(v.K, v.d, v.T, v.ldt, v.tall ? lambda : 0.0, s, seed, X, st);
     LSRN_API_END
 }
 

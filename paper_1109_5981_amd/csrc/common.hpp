@@ -97,12 +97,17 @@ __device__ __forceinline__ double block_sum(double v, double *scratch) {
 }
 
 // Double-double arithmetic (Dekker 1971; Knuth TAOCP vol. 2, 4.2.2):
-// value = hi + lo with |lo| <= ulp(hi)/2.
+// value = hi + lo with |lo| <= ulp(hi)/2.  The error-free transformations
+// below rely on every product and sum being rounded on its own: each body
+// turns floating-point contraction off, or the compiler (HIP contracts by
+// default) would fuse a rounded product into a later sum and the error
+// terms would no longer be exact.
 struct dd {
     double hi, lo;
 };
 
 __device__ __forceinline__ dd two_sum(double a, double b) {
+#pragma clang fp contract(off)
     double s = a + b;
     double bb = s - a;
     double e = (a - (s - bb)) + (b - bb);
@@ -110,16 +115,19 @@ __device__ __forceinline__ dd two_sum(double a, double b) {
 }
 
 __device__ __forceinline__ dd quick_two_sum(double a, double b) {
+#pragma clang fp contract(off)
     double s = a + b;
     return {s, b - (s - a)};
 }
 
 __device__ __forceinline__ dd two_prod(double a, double b) {
+#pragma clang fp contract(off)
     double p = a * b;
     return {p, fma(a, b, -p)};
 }
 
 __device__ __forceinline__ dd dd_add(dd a, dd b) {
+#pragma clang fp contract(off)
     dd s = two_sum(a.hi, b.hi);
     dd t = two_sum(a.lo, b.lo);
     s.lo += t.hi;
@@ -129,10 +137,14 @@ __device__ __forceinline__ dd dd_add(dd a, dd b) {
 }
 
 // a += x * y with x*y formed exactly.
-__device__ __forceinline__ dd dd_fma(dd a, double x, double y) { return dd_add(a, two_prod(x, y)); }
+__device__ __forceinline__ dd dd_fma(dd a, double x, double y) {
+#pragma clang fp contract(off)
+    return dd_add(a, two_prod(x, y));
+}
 
 // a += x * (y.hi + y.lo), the product kept to double-double accuracy.
 __device__ __forceinline__ dd dd_fma_dd(dd a, double x, dd y) {
+#pragma clang fp contract(off)
     dd p = two_prod(x, y.hi);
     p.lo = fma(x, y.lo, p.lo);
     return dd_add(a, p);
@@ -146,6 +158,7 @@ __device__ __forceinline__ dd dd_shfl_xor(dd v, int off) {
 // values in swapped order; dd_add is not commutative bit-for-bit, so the
 // lower lane's value always goes first to keep every lane identical.
 __device__ __forceinline__ dd wave_sum_dd(dd v) {
+#pragma clang fp contract(off)
     const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {

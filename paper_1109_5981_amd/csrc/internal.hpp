@@ -25,6 +25,14 @@ void sketch_rows(int64_t K, int64_t d, const double *T, int64_t ldt, double lamb
                  uint64_t seed, double *X, hipStream_t st, double *kernel_ms = nullptr);
 size_t sketch_workspace_bytes(int64_t K, int64_t d, int64_t s);
 
+// The precision form's sketch: X = bf16(G) fl32(T) on the BF16 matrix
+// cores (FP32 accumulation flushed to FP64), plus the FP64 rows lambda G of
+// the Tikhonov block.  Synchronises.
+void sketch_rows_bf16(int64_t K, int64_t d, const double *T, int64_t ldt, double lambda, int64_t s,
+                      uint64_t seed, double *X, hipStream_t st, double *kernel_ms = nullptr);
+// T32 (rows x cols, leading dimension ldt) = T rounded to FP32.
+void to_f32(int64_t rows, int64_t cols, const double *T, int64_t ldt, float *T32, hipStream_t st);
+
 // X(i, c) += lambda G(i, K + c): the rows lambda I of the augmented tall
 // matrix (Sec. 5).
 void add_identity_rows(int64_t K, int64_t d, int64_t s, double lambda, uint64_t seed, double *X,
@@ -121,6 +129,9 @@ struct IterProblem {
     int64_t r = 0;
     int64_t s = 0;
     const SparseView *sp = nullptr;  // sparse T (then T and ldt are unused)
+    // precision form: FP32 copy of T (leading dimension ldt) read by every
+    // sweep; refinement residuals still use the FP64 T
+    const float *T32 = nullptr;
 };
 
 struct IterResult {

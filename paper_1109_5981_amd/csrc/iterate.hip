@@ -55,6 +55,7 @@ enum Op : int {
 
 struct SweepArgs {
     const double *T;
+    const float *T32;    // FP32 copy of T (precision form), read when F32
     int64_t ldt, rows;
     int L;
     int nblocks;
@@ -74,7 +75,7 @@ __device__ __forceinline__ int col_of(int tid, int e) {
     return 2 * tid + 512 * (e >> 1) + (e & 1);
 }
 
-template <int CPT, int R, int OP>
+template <int CPT, int R, int OP, bool F32>
 __global__ void __launch_bounds__(NT, 2) sweep_kernel(SweepArgs a) {
     if (a.st->done) return;
     __shared__ double red[2][NT / 64][R];
@@ -105,24 +106,37 @@ __global__ void __launch_bounds__(NT, 2) sweep_kernel(SweepArgs a) {
 
     const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_block;
     const int64_t r1 = min(a.rows, r0 + a.rows_per_block);
-    const bool vec2 = ((a.ldt & 1) == 0) && ((reinterpret_cast<uintptr_t>(a.T) & 15) == 0);
+    const bool vec2 = F32 ? (((a.ldt & 1) == 0) && ((reinterpret_cast<uintptr_t>(a.T32) & 7) == 0))
+                          : (((a.ldt & 1) == 0) && ((reinterpret_cast<uintptr_t>(a.T) & 15) == 0));
     // R rows of T (and of the per-row vector) starting at j0 into registers
+    // (FP32 storage is widened to FP64 on load)
     auto load_rows = [&](int64_t j0, double (&av)[R][CPT], double (&yv)[R]) {
 #pragma unroll
         for (int rr = 0; rr < R; ++rr) {
             const int64_t row = j0 + rr;
             const bool valid = row < r1;
-            const double *trow = a.T + row * a.ldt;
 #pragma unroll
             for (int e = 0; e < CPT; e += 2) {
                 const int col = col_of<CPT>(tid, e);
                 double2 v = make_double2(0.0, 0.0);
                 if (valid) {
-                    if (vec2 && col + 1 < L) {
-                        v = *reinterpret_cast<const double2 *>(trow + col);
+                    if (F32) {
+                        const float *trow = a.T32 + row * a.ldt;
+                        if (vec2 && col + 1 < L) {
+                            const float2 f = *reinterpret_cast<const float2 *>(trow + col);
+                            v = make_double2((double)f.x, (double)f.y);
+                        } else {
+                            if (col < L) v.x = (double)trow[col];
+                            if (col + 1 < L) v.y = (double)trow[col + 1];
+                        }
                     } else {
-                        if (col < L) v.x = trow[col];
-                        if (col + 1 < L) v.y = trow[col + 1];
+                        const double *trow = a.T + row * a.ldt;
+                        if (vec2 && col + 1 < L) {
+                            v = *reinterpret_cast<const double2 *>(trow + col);
+                        } else {
+                            if (col < L) v.x = trow[col];
+                            if (col + 1 < L) v.y = trow[col + 1];
+                        }
                     }
                 }
                 av[rr][e] = v.x;
@@ -1023,16 +1037,21 @@ struct Ctx {
         LSRN_HIP(hipGetLastError());
     }
 
+    template <int CPT, int RR, bool F32>
+    void sweep_tf(int op, SweepArgs &a) {
+        switch (op) {
+            case OP_ATB: sweep_kernel<CPT, RR, OP_ATB, F32><<<nblocks, NT, 0, st>>>(a); break;
+            case OP_LSQR_TALL: sweep_kernel<CPT, RR, OP_LSQR_TALL, F32><<<nblocks, NT, 0, st>>>(a); break;
+            case OP_CS_TALL: sweep_kernel<CPT, RR, OP_CS_TALL, F32><<<nblocks, NT, 0, st>>>(a); break;
+            case OP_NORMAL: sweep_kernel<CPT, RR, OP_NORMAL, F32><<<nblocks, NT, 0, st>>>(a); break;
+            case OP_LSQR_FAT: sweep_kernel<CPT, RR, OP_LSQR_FAT, F32><<<nblocks, NT, 0, st>>>(a); break;
+            default: sweep_kernel<CPT, RR, OP_CS_FAT, F32><<<nblocks, NT, 0, st>>>(a); break;
+        }
+    }
     template <int CPT, int RR>
     void sweep_t(int op, SweepArgs &a) {
-        switch (op) {
-            case OP_ATB: sweep_kernel<CPT, RR, OP_ATB><<<nblocks, NT, 0, st>>>(a); break;
-            case OP_LSQR_TALL: sweep_kernel<CPT, RR, OP_LSQR_TALL><<<nblocks, NT, 0, st>>>(a); break;
-            case OP_CS_TALL: sweep_kernel<CPT, RR, OP_CS_TALL><<<nblocks, NT, 0, st>>>(a); break;
-            case OP_NORMAL: sweep_kernel<CPT, RR, OP_NORMAL><<<nblocks, NT, 0, st>>>(a); break;
-            case OP_LSQR_FAT: sweep_kernel<CPT, RR, OP_LSQR_FAT><<<nblocks, NT, 0, st>>>(a); break;
-            default: sweep_kernel<CPT, RR, OP_CS_FAT><<<nblocks, NT, 0, st>>>(a); break;
-        }
+        if (a.T32) sweep_tf<CPT, RR, true>(op, a);
+        else sweep_tf<CPT, RR, false>(op, a);
     }
 
     // One pass: z = sum_j op_j T_j, st->acc = reduced accumulators.
@@ -1043,7 +1062,7 @@ struct Ctx {
             return;
         }
         SweepArgs a;
-        a.T = pb.T; a.ldt = pb.ldt; a.rows = pb.rows; a.L = L; a.nblocks = nblocks;
+        a.T = pb.T; a.T32 = pb.T32; a.ldt = pb.ldt; a.rows = pb.rows; a.L = L; a.nblocks = nblocks;
         a.rows_per_block = rows_per_block; a.w = w; a.zpart = zpart.as<double>();
         a.spart = spart.as<double>(); a.y = y; a.xv = xv; a.wv = wv; a.st = state;
         a.lambda = pb.tall ? pb.lambda : 0.0; a.alpha = alpha; a.beta = beta;
@@ -1359,6 +1378,7 @@ IterResult iterate(const IterProblem &pb, const double *b, double *x, const lsrn
             DevBuf dx((size_t)L * sizeof(double));
             // the sparse normal-equation sweep stores T p here for its column pass
             DevBuf ybuf(pb.sp ? (size_t)(pb.rows + L) * sizeof(double) : 0);
+            double dn_prev = 0.0;
             for (int step = 0; step < opt.refine; ++step) {
                 if (pb.sp) {
                     // rows: res = b^ - T^ x (dd); columns: h = T^^T res (dd), rounded
@@ -1400,7 +1420,10 @@ IterResult iterate(const IterProblem &pb, const double *b, double *x, const lsrn
                 LSRN_HIP(hipGetLastError());
                 ++res.refine_steps;
                 const double dn = host_norm(dx.as<double>(), L, st), xn = host_norm(x, L, st);
-                if (dn <= 1e-15 * xn) break;
+                // stop at convergence, or once the corrections stop shrinking
+                // (the floor of the inner arithmetic is reached)
+                if (dn <= 1e-15 * xn || (step > 0 && dn > 0.5 * dn_prev)) break;
+                dn_prev = dn;
             }
         }
         LSRN_HIP(hipStreamSynchronize(st));  // before the solver's buffers are freed
@@ -1416,6 +1439,7 @@ IterResult iterate(const IterProblem &pb, const double *b, double *x, const lsrn
             DevBuf zhi(zlen * sizeof(double)), zlo(zlen * sizeof(double));
             DevBuf thi((size_t)L * sizeof(double)), tlo((size_t)L * sizeof(double));
             DevBuf xsave((size_t)n * sizeof(double));
+            double dn_prev = 0.0;
             for (int step = 0; step < opt.refine; ++step) {
                 if (pb.sp) {
                     csr_col_pass_dd_kernel<<<(unsigned)ceil_div(L, CCP_NT / 64), CCP_NT, 0, st>>>(
@@ -1444,7 +1468,10 @@ IterResult iterate(const IterProblem &pb, const double *b, double *x, const lsrn
                 LSRN_HIP(hipGetLastError());
                 ++res.refine_steps;
                 const double xn = host_norm(x, n, st);
-                if (dn <= 1e-15 * xn) break;
+                // stop at convergence, or once the corrections stop shrinking
+                // (the floor of the inner arithmetic is reached)
+                if (dn <= 1e-15 * xn || (step > 0 && dn > 0.5 * dn_prev)) break;
+                dn_prev = dn;
             }
         }
         LSRN_HIP(hipStreamSynchronize(st));  // before the solver's buffers are freed

@@ -33,7 +33,7 @@ class Options(C.Structure):
                 ("rcond", C.c_double), ("t_margin", C.c_double), ("refine_tol", C.c_double),
                 ("seed", C.c_uint64), ("max_iter", C.c_int64), ("method", C.c_int32),
                 ("refine", C.c_int32), ("profile", C.c_int32), ("precond", C.c_int32),
-                ("reserved", C.c_int32 * 2)]
+                ("precision", C.c_int32), ("reserved", C.c_int32 * 1)]
 
 
 class Info(C.Structure):
@@ -55,9 +55,11 @@ _lib = None
 
 EXPORTS = ["lsrn_default_options", "lsrn_status_string", "lsrn_last_error", "lsrn_solve_dense",
            "lsrn_workspace_bytes", "lsrn_solve_csr", "lsrn_workspace_bytes_csr",
-           "lsrn_philox_words", "lsrn_gauss_fill", "lsrn_sketch_dense", "lsrn_sketch_csr",
+           "lsrn_philox_words", "lsrn_gauss_fill", "lsrn_sketch_dense", "lsrn_sketch_dense_bf16",
+           "lsrn_sketch_csr",
            "lsrn_precond", "lsrn_precond_qr", "lsrn_iterate_dense", "lsrn_iterate_csr"]
 PRECOND = {"auto": 0, "svd": 1, "qr": 2}
+PRECISION = {"fp64": 0, "mixed": 1}
 _SIZE_FNS = ("lsrn_default_options", "lsrn_status_string", "lsrn_last_error",
              "lsrn_workspace_bytes", "lsrn_workspace_bytes_csr")
 
@@ -80,6 +82,7 @@ def lib():
         L.lsrn_philox_words.argtypes = [U64, I64, I64, I64, I64, P, P]
         L.lsrn_gauss_fill.argtypes = [U64, I64, I64, I64, I64, P, P]
         L.lsrn_sketch_dense.argtypes = [I64, I64, P, I64, I32, D, I64, U64, P, P]
+        L.lsrn_sketch_dense_bf16.argtypes = [I64, I64, P, I64, I32, D, I64, U64, P, P]
         L.lsrn_precond.argtypes = [I64, I64, P, D, P, P, C.POINTER(C.c_int64),
                                    C.POINTER(C.c_int64), P]
         L.lsrn_iterate_dense.argtypes = [I64, I64, P, I64, I32, P, P, I64, I64, I64, P,
@@ -124,6 +127,8 @@ def options(**kw) -> Options:
             v = {"lsqr": LSQR, "chebyshev": CHEBYSHEV, "cs": CHEBYSHEV}[v.lower()]
         if k == "precond" and isinstance(v, str):
             v = PRECOND[v.lower()]
+        if k == "precision" and isinstance(v, str):
+            v = PRECISION[v.lower()]
         setattr(o, k, v)
     return o
 
@@ -184,6 +189,18 @@ def sketch_dense(A: torch.Tensor, s: int, seed: int = 0, lam: float = 0.0,
     X = torch.empty((d, s), dtype=torch.float64, device=A.device)
     _check(lib().lsrn_sketch_dense(m, n, A.data_ptr(), lda, layout, lam, s, seed, X.data_ptr(),
                                    _stream()))
+    return X
+
+
+def sketch_dense_bf16(A: torch.Tensor, s: int, seed: int = 0, lam: float = 0.0,
+                      layout: int = ROW_MAJOR) -> torch.Tensor:
+    """The precision form's sketch bf16(G) fl32(T), as sketch_dense."""
+    _dev_f64(A, "A")
+    m, n, lda = _layout_dims(A, layout)
+    d = n if (m >= n or lam > 0) else m
+    X = torch.empty((d, s), dtype=torch.float64, device=A.device)
+    _check(lib().lsrn_sketch_dense_bf16(m, n, A.data_ptr(), lda, layout, lam, s, seed,
+                                        X.data_ptr(), _stream()))
     return X
 
 

@@ -14,14 +14,16 @@ LIB = os.path.join(ROOT, "paper_1109_5981_amd", "liblsrn.so")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(lsrn_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(lsrn_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_declares_the_boundary():
     names = declared_functions()
     for required in ("lsrn_solve_dense", "lsrn_sketch_dense", "lsrn_precond",
                      "lsrn_iterate_dense", "lsrn_philox_words", "lsrn_gauss_fill",
-                     "lsrn_default_options", "lsrn_last_error", "lsrn_workspace_bytes"):
+                     "lsrn_default_options", "lsrn_last_error", "lsrn_workspace_bytes",
+                     "lsrn_solve_csr", "lsrn_sketch_csr", "lsrn_iterate_csr", "lsrn_precond_qr",
+                     "lsrn_sketch_dense_bf16", "lsrn_workspace_bytes_csr"):
         assert required in names
 
 

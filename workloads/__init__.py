@@ -58,6 +58,39 @@ def dense_problem(m: int, n: int, rank: int | None = None, smin: float = 1e-6,
     return Dense(np.ascontiguousarray(A), U, sigma, V)
 
 
+CHUNK_ELEMS = 1 << 28  # every torch BLAS / solver call stays far below 2^31 elements
+
+
+def _row_chunks(rows: int, cols: int):
+    step = max(1, CHUNK_ELEMS // max(cols, 1))
+    for r0 in range(0, rows, step):
+        yield r0, min(rows, r0 + step)
+
+
+def haar_device(rows: int, k: int, g, device="cuda"):
+    """Haar-distributed rows x k orthonormal columns: Z R^-1 with R the
+    Cholesky factor of Z^T Z, Z Gaussian (the Q factor of Z with positive
+    diag R), formed in row chunks."""
+    import torch
+    Z = torch.empty(rows, k, dtype=torch.float64, device=device)
+    for r0, r1 in _row_chunks(rows, k):
+        Z[r0:r1] = torch.randn(r1 - r0, k, generator=g, dtype=torch.float64, device=device)
+    if rows * k <= CHUNK_ELEMS:
+        Q, R = torch.linalg.qr(Z)
+        return Q * torch.sign(torch.diagonal(R))
+    # kappa(Z) is about (sqrt(rows) + sqrt(k)) / (sqrt(rows) - sqrt(k)), so
+    # one Cholesky QR pass is orthonormal to rounding; a second pass removes
+    # what is left
+    for _ in range(2):
+        C = torch.zeros(k, k, dtype=torch.float64, device=device)
+        for r0, r1 in _row_chunks(rows, k):
+            C += Z[r0:r1].T @ Z[r0:r1]
+        R = torch.linalg.cholesky(C, upper=True)
+        for r0, r1 in _row_chunks(rows, k):
+            Z[r0:r1] = torch.linalg.solve_triangular(R, Z[r0:r1], upper=True, left=False)
+    return Z
+
+
 def dense_problem_device(m: int, n: int, rank: int | None = None, smin: float = 1e-6,
                          seed: int = 0, device="cuda"):
     """The dense_problem recipe built with torch on `device` (for sizes where
@@ -66,17 +99,29 @@ def dense_problem_device(m: int, n: int, rank: int | None = None, smin: float = 
     k = min(m, n) if rank is None else rank
     g = torch.Generator(device=device)
     g.manual_seed(seed)
-
-    def haar(rows):
-        Z = torch.randn(rows, k, generator=g, dtype=torch.float64, device=device)
-        Q, R = torch.linalg.qr(Z)
-        return Q * torch.sign(torch.diagonal(R))
-
-    U = haar(m)
-    V = haar(n)
+    U = haar_device(m, k, g, device)
+    V = haar_device(n, k, g, device)
     sigma = torch.logspace(0.0, float(np.log10(smin)), k, dtype=torch.float64, device=device)
-    A = ((U * sigma) @ V.T).contiguous()
+    A = torch.empty(m, n, dtype=torch.float64, device=device)
+    W = (V * sigma).T.contiguous()                     # k x n
+    for r0, r1 in _row_chunks(m, max(n, k)):
+        A[r0:r1] = U[r0:r1] @ W
     return A, U, sigma, V
+
+
+def matvec_device(A, x, trans: bool = False):
+    """A x (or A^T x) in row chunks."""
+    import torch
+    m, n = A.shape
+    if not trans:
+        out = torch.empty(m, dtype=A.dtype, device=A.device)
+        for r0, r1 in _row_chunks(m, n):
+            out[r0:r1] = A[r0:r1] @ x
+        return out
+    out = torch.zeros(n, dtype=A.dtype, device=A.device)
+    for r0, r1 in _row_chunks(m, n):
+        out += A[r0:r1].T @ x[r0:r1]
+    return out
 
 
 def rhs_gauss_device(m: int, seed: int, device="cuda"):
@@ -84,6 +129,17 @@ def rhs_gauss_device(m: int, seed: int, device="cuda"):
     g = torch.Generator(device=device)
     g.manual_seed(seed + 104729)
     return torch.randn(m, generator=g, dtype=torch.float64, device=device)
+
+
+def rhs_model_device(A, noise: float, seed: int):
+    """rhs_model's recipe with torch on A's device: (b, x_gen) tensors."""
+    import torch
+    g = torch.Generator(device=A.device)
+    g.manual_seed(seed + 7919)
+    xg = torch.randn(A.shape[1], generator=g, dtype=torch.float64, device=A.device)
+    b = matvec_device(A, xg) + noise * torch.randn(A.shape[0], generator=g, dtype=torch.float64,
+                                                   device=A.device)
+    return b, xg
 
 
 def rhs_model(A: np.ndarray, noise: float, seed: int):
