@@ -33,6 +33,10 @@ WORKLOADS = {
     # the precision-form workload: full rank, sigma 1 .. 1e-8, b = A x + 1e-6 noise
     "dense_1000000x4000": dict(m=1_000_000, n=4000, rank=4000, smin=1e-8, seed=14, fat=False,
                                noise=1e-6),
+    # the same shape at kappa = 1e6, where kappa u32 < 1 lets the precision form
+    # reach the FP64 solution
+    "dense_1000000x4000_k1e6": dict(m=1_000_000, n=4000, rank=4000, smin=1e-6, seed=14, fat=False,
+                                    noise=1e-6),
 }
 
 
@@ -168,14 +172,14 @@ def main():
                 profile=0 if args.no_profile else 1, precision=args.precision,
                 precond=args.precond)
     for _ in range(args.warmup):
-        x, info = lsrn.solve_dense(A, b, layout=layout, **opts)
+        x, info = lsrn.solve_dense(A, b, layout=layout, allow_not_converged=True, **opts)
     torch.cuda.synchronize()
 
     lat, infos = [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         ts = time.perf_counter()
-        x, info = lsrn.solve_dense(A, b, layout=layout, **opts)
+        x, info = lsrn.solve_dense(A, b, layout=layout, allow_not_converged=True, **opts)
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - ts) * 1e3)
         infos.append(info)
@@ -284,6 +288,7 @@ def main():
         "rel_err_vs_generator": err_gen,
         "rel_err_vs_fp64_path": err_fp64,
         "refine_steps": info["refine_steps"],
+        "converged": bool(info["converged"]),
         "rel_normal_residual": ne,
         "kernels": kernels,
         "roofline": roofline,

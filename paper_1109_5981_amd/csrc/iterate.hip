@@ -1420,6 +1420,10 @@ IterResult iterate(const IterProblem &pb, const double *b, double *x, const lsrn
                 LSRN_HIP(hipGetLastError());
                 ++res.refine_steps;
                 const double dn = host_norm(dx.as<double>(), L, st), xn = host_norm(x, L, st);
+                // the precision form's main LSQR runs on fl32(A): its answer
+                // is settled by the refinement, whose last correction must
+                // have become negligible
+                if (pb.T32) conv = dn <= 1e-12 * xn;
                 // stop at convergence, or once the corrections stop shrinking
                 // (the floor of the inner arithmetic is reached)
                 if (dn <= 1e-15 * xn || (step > 0 && dn > 0.5 * dn_prev)) break;

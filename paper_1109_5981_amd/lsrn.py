@@ -144,9 +144,10 @@ def _layout_dims(A: torch.Tensor, layout: int):
 
 
 def solve_dense(A: torch.Tensor, b: torch.Tensor, x: torch.Tensor | None = None, *,
-                layout: int = ROW_MAJOR, **opts):
+                layout: int = ROW_MAJOR, allow_not_converged: bool = False, **opts):
     """Min-length least-squares solution of min ||A x - b|| (Alg. 1 / Alg. 2).
-    Returns (x, info dict)."""
+    Returns (x, info dict).  With allow_not_converged, LSRN_E_NOT_CONVERGED
+    returns the last iterate with info["status"] = 4 instead of raising."""
     _dev_f64(A, "A")
     _dev_f64(b, "b")
     m, n, lda = _layout_dims(A, layout)
@@ -157,8 +158,11 @@ def solve_dense(A: torch.Tensor, b: torch.Tensor, x: torch.Tensor | None = None,
     o, info = options(**opts), Info()
     st = lib().lsrn_solve_dense(m, n, A.data_ptr(), lda, layout, b.data_ptr(), x.data_ptr(),
                                 C.byref(o), C.byref(info), _stream())
-    _check(st)
-    return x, info.as_dict()
+    if not (allow_not_converged and st == 4):
+        _check(st)
+    out = info.as_dict()
+    out["status"] = int(st)
+    return x, out
 
 
 def workspace_bytes(m: int, n: int, layout: int = ROW_MAJOR, **opts) -> int:

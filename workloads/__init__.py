@@ -86,8 +86,11 @@ def haar_device(rows: int, k: int, g, device="cuda"):
         for r0, r1 in _row_chunks(rows, k):
             C += Z[r0:r1].T @ Z[r0:r1]
         R = torch.linalg.cholesky(C, upper=True)
+        # kappa(R) ~ 1: multiply by the explicit inverse (a plain GEMM per chunk)
+        Rinv = torch.linalg.solve_triangular(R, torch.eye(k, dtype=R.dtype, device=R.device),
+                                             upper=True)
         for r0, r1 in _row_chunks(rows, k):
-            Z[r0:r1] = torch.linalg.solve_triangular(R, Z[r0:r1], upper=True, left=False)
+            Z[r0:r1] = Z[r0:r1] @ Rinv
     return Z
 
 
