@@ -103,6 +103,125 @@ def cpu_baseline(A_np, b_np, s, d, r, iters_per_solve, sweeps, tall, budget_s=20
     }
 
 
+def serve_main(args):
+    """The serving workload: Poisson arrivals of uneven dense solves, admitted
+    by device-memory footprint onto a pool of streams; reports solves/s and
+    latency percentiles.  Each request's A is built on the GPU when it
+    arrives (the generator's time is reported, not counted in latency)."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_1109_5981_amd import lsrn
+
+    rng = np.random.default_rng(2024)
+    nreq, rate = args.serve_requests, args.serve_rate
+    dev = torch.device("cuda:0")
+    results, lock = {}, threading.Lock()
+    srv = lsrn.Server(hbm_budget_bytes=int(args.serve_budget_gb * (1 << 30)),
+                      streams=args.serve_streams)
+    queue = []           # (ticket, meta, tensors) in submission order
+    cv = threading.Condition()
+    done_flag = [False]
+
+    def waiter():
+        while True:
+            with cv:
+                while not queue and not done_flag[0]:
+                    cv.wait()
+                if not queue:
+                    return
+                ticket, meta, tens = queue.pop(0)
+                cv.notify_all()
+            x, info, tm = srv.wait(ticket, allow_not_converged=True)
+            A, b = tens
+            check = None
+            if meta["i"] % 16 == 0:
+                # accuracy sample: relative normal-equation residual (tall) or
+                # relative residual of the consistent system (fat)
+                with torch.no_grad():
+                    if meta["fat"]:
+                        r = b - A.T @ x
+                        check = (torch.linalg.norm(r) / torch.linalg.norm(b)).item()
+                    else:
+                        r = b - A @ x
+                        check = (torch.linalg.norm(A.T @ r) /
+                                 (torch.linalg.norm(A) * torch.linalg.norm(r))).item()
+            with lock:
+                results[meta["i"]] = dict(meta, latency_ms=tm["latency_ms"], queue_ms=tm["queue_ms"],
+                                          run_ms=tm["run_ms"], status=info["status"],
+                                          iters=info["iters"], check=check)
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    t_gen = 0.0
+    t0 = time.perf_counter()
+    t_next = t0
+    for i in range(nreq):
+        t_next += rng.exponential(1.0 / rate)
+        while True:
+            n = int(rng.integers(16, 513))
+            m = int(rng.integers(1000, 100_001))
+            if m >= 20 * n:
+                break
+        fat = rng.random() < 0.25
+        cond = 10.0 ** rng.uniform(2, 8)
+        tol = 10.0 ** rng.uniform(-14, -8)
+        prec = "mixed" if (not fat and rng.random() < 0.5) else "fp64"
+        g0 = time.perf_counter()
+        A, _, _, _ = workloads.dense_problem_device(m, n, smin=1.0 / cond, seed=10_000 + i, device=dev)
+        b = workloads.rhs_gauss_device(n if fat else m, 10_000 + i, device=dev)
+        torch.cuda.synchronize()
+        t_gen += time.perf_counter() - g0
+        now = time.perf_counter()
+        if now < t_next:
+            time.sleep(t_next - now)
+        with cv:
+            while len(queue) > args.serve_streams * 8:   # back-pressure on the inputs held
+                cv.wait(0.01)
+        # method: LSQR for the precision form, Chebyshev for a quarter of the rest
+        meth = "chebyshev" if (prec == "fp64" and rng.random() < 0.25) else "lsqr"
+        opts = dict(tol=tol, method=meth, precision=prec, seed=i, refine=2 if tol < 1e-12 else 0)
+        ticket = srv.submit_dense(A, b, layout=lsrn.COL_MAJOR if fat else lsrn.ROW_MAJOR, **opts)
+        with cv:
+            queue.append((ticket, dict(i=i, m=n if fat else m, n=m if fat else n, fat=fat,
+                                       cond=cond, tol=tol, precision=prec, method=meth), (A, b)))
+            cv.notify()
+    with cv:
+        done_flag[0] = True
+        cv.notify()
+    th.join()
+    t1 = time.perf_counter()
+    srv.close()
+    lat = [r["latency_ms"] for r in results.values()]
+    checks = [r["check"] for r in results.values() if r["check"] is not None]
+    status = {}
+    for r in results.values():
+        status[r["status"]] = status.get(r["status"], 0) + 1
+    line = {
+        "metric": "serving: LS solves/s with p50/p99 latency (Poisson arrivals, uneven shapes)",
+        "value": round(len(results) / (t1 - t0), 2),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "f64 + precision form",
+        "data": "synthetic (seeded; per request U, V Haar, sigma log-spaced to 1/cond)",
+        "config": {"workload": "serving_uneven", "requests": nreq, "arrival_rate_per_s": rate,
+                   "m": [1000, 100000], "n": [16, 512], "fat_fraction": 0.25,
+                   "streams": args.serve_streams, "budget_gb": args.serve_budget_gb},
+        "latency_ms": {"p50": round(percentile(lat, 50), 3), "p99": round(percentile(lat, 99), 3),
+                       "mean_queue": round(float(np.mean([r["queue_ms"] for r in results.values()])), 3)},
+        "wall_s": round(t1 - t0, 3),
+        "generator_s": round(t_gen, 3),
+        "status_counts": {str(k): v for k, v in status.items()},
+        "accuracy_sample": {"count": len(checks), "max": max(checks) if checks else None,
+                            "median": float(np.median(checks)) if checks else None},
+    }
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +235,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="do not time individual kernels with HIP events")
+    ap.add_argument("--serve", action="store_true",
+                    help="run the serving workload instead of the single-solve benchmark")
+    ap.add_argument("--serve-requests", type=int, default=4096)
+    ap.add_argument("--serve-rate", type=float, default=500.0)
+    ap.add_argument("--serve-streams", type=int, default=8)
+    ap.add_argument("--serve-budget-gb", type=float, default=96.0)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (3 times); "
                          "its FETCH_SIZE / WRITE_SIZE counters calibrate the traffic figures")
@@ -136,6 +261,9 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
+    if args.serve:
+        serve_main(args)
+        return
     dev = torch.device("cuda:0")
     if args.copy_bytes > 0:
         src = torch.ones(args.copy_bytes // 8, dtype=torch.float64, device=dev)

@@ -255,6 +255,59 @@ lsrn_status lsrn_iterate_csr(int64_t m, int64_t n, int64_t nnz, const int64_t *r
                              const double *P, int64_t ldp, int64_t r, int64_t s, double *x,
                              const lsrn_options *opt, lsrn_info *info, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Serving runtime: solves of different shapes submitted as they arrive,
+ * admitted by device-memory footprint onto a pool of streams (not a paper
+ * passage: the serving loop around Alg. 1/2).
+ *
+ * A request is admitted, in arrival order, when one of `streams` worker
+ * streams is free and its footprint (lsrn_workspace_bytes /
+ * lsrn_workspace_bytes_csr, plus the FP32 copy of the precision form) fits
+ * in `hbm_budget_bytes` next to the solves already running; a request
+ * larger than the budget runs alone.  Admitted solves overlap on the device
+ * and each runs exactly the kernels of lsrn_solve_dense / lsrn_solve_csr,
+ * so its result equals that of the same call made alone.  The caller keeps
+ * A, b and x (device memory) alive and unused until lsrn_server_wait
+ * returns for the ticket.  Errors of a request are returned by
+ * lsrn_server_wait (message in lsrn_server_last_error()).
+ * ---------------------------------------------------------------------- */
+typedef struct lsrn_server lsrn_server;
+
+typedef struct lsrn_server_timing {
+    double queue_ms;          /* submit -> admitted                          */
+    double run_ms;            /* admitted -> finished                        */
+    double latency_ms;        /* submit -> finished                          */
+    int64_t footprint_bytes;  /* memory the admission reserved               */
+} lsrn_server_timing;
+
+/* Start the worker threads on the current device.  0 < streams <= 64. */
+lsrn_status lsrn_server_create(int64_t hbm_budget_bytes, int32_t streams, lsrn_server **out);
+
+/* Queue a dense solve (arguments as lsrn_solve_dense); *ticket identifies it. */
+lsrn_status lsrn_server_submit_dense(lsrn_server *srv, int64_t m, int64_t n, const double *A,
+                                     int64_t lda, int32_t layout, const double *b, double *x,
+                                     const lsrn_options *opt, int64_t *ticket);
+
+/* Queue a CSR solve (arguments as lsrn_solve_csr). */
+lsrn_status lsrn_server_submit_csr(lsrn_server *srv, int64_t m, int64_t n, int64_t nnz,
+                                   const int64_t *rowptr, const int32_t *colind, const double *val,
+                                   const double *b, double *x, const lsrn_options *opt,
+                                   int64_t *ticket);
+
+/* Block until the request finishes; returns its status and fills info and
+ * timing (either may be NULL).  A ticket can be waited for once. */
+lsrn_status lsrn_server_wait(lsrn_server *srv, int64_t ticket, lsrn_info *info,
+                             lsrn_server_timing *timing);
+
+/* Requests queued, running, and the footprint admitted right now. */
+lsrn_status lsrn_server_stats(lsrn_server *srv, int64_t *pending, int64_t *running,
+                              int64_t *bytes_in_use);
+
+const char *lsrn_server_last_error(void);
+
+/* Finish every queued request, then stop the workers and free the server. */
+void lsrn_server_destroy(lsrn_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,22 +22,32 @@ void hip_check(hipError_t e, const char *what) {
     throw Error{LSRN_E_HIP, std::string(what) + ": " + hipGetErrorString(e)};
 }
 
+static thread_local hipStream_t g_alloc_stream = nullptr;
+
+void set_alloc_stream(hipStream_t s) { g_alloc_stream = s; }
+
 void DevBuf::alloc(size_t bytes) {
     release();
     if (bytes == 0) return;
     void *p = nullptr;
-    hipError_t e = hipMalloc(&p, bytes);
+    const bool async = g_alloc_stream != nullptr;
+    hipError_t e = async ? hipMallocAsync(&p, bytes, g_alloc_stream) : hipMalloc(&p, bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
-        throw Error{LSRN_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
+        throw Error{LSRN_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed: " +
                                       hipGetErrorString(e)};
     }
     p_ = p;
     n_ = bytes;
+    s_ = g_alloc_stream;
+    async_ = async;
 }
 
 void DevBuf::release() {
-    if (p_) (void)hipFree(p_);
+    if (p_) {
+        if (async_) (void)hipFreeAsync(p_, s_);
+        else (void)hipFree(p_);
+    }
     p_ = nullptr;
     n_ = 0;
 }

@@ -27,7 +27,10 @@ void hip_check(hipError_t e, const char *what);
         if (!(cond)) ::lsrn::fail(LSRN_E_INVALID, (msg));    \
     } while (0)
 
-// Device buffer owned by the library (hipMalloc / hipFree).
+// Device buffer owned by the library.  Allocated with hipMalloc, or with
+// stream-ordered hipMallocAsync on the thread's allocation stream when one
+// is set (the serving runtime does, so that concurrent solves do not
+// synchronise the device on every free).
 class DevBuf {
   public:
     DevBuf() = default;
@@ -35,9 +38,17 @@ class DevBuf {
     ~DevBuf() { release(); }
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
-    DevBuf(DevBuf &&o) noexcept : p_(o.p_), n_(o.n_) { o.p_ = nullptr; o.n_ = 0; }
+    DevBuf(DevBuf &&o) noexcept : p_(o.p_), n_(o.n_), s_(o.s_), async_(o.async_) {
+        o.p_ = nullptr;
+        o.n_ = 0;
+    }
     DevBuf &operator=(DevBuf &&o) noexcept {
-        if (this != &o) { release(); p_ = o.p_; n_ = o.n_; o.p_ = nullptr; o.n_ = 0; }
+        if (this != &o) {
+            release();
+            p_ = o.p_; n_ = o.n_; s_ = o.s_; async_ = o.async_;
+            o.p_ = nullptr;
+            o.n_ = 0;
+        }
         return *this;
     }
     void alloc(size_t bytes);
@@ -48,7 +59,13 @@ class DevBuf {
   private:
     void *p_ = nullptr;
     size_t n_ = 0;
+    hipStream_t s_ = nullptr;
+    bool async_ = false;
 };
+
+// Stream for stream-ordered allocations of DevBufs made on this thread
+// (nullptr: plain hipMalloc / hipFree).
+void set_alloc_stream(hipStream_t s);
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 __host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }

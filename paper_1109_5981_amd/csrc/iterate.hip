@@ -1136,6 +1136,41 @@ struct Ctx {
         LSRN_HIP(hipStreamSynchronize(st));
         return h;
     }
+
+    // A chunk of iterations (kernel launches only, their arguments fixed) is
+    // captured once into a HIP graph and replayed: one launch per chunk
+    // instead of one per kernel.  Per-launch timing needs the eager path.
+    bool use_graphs = false;
+    template <class F>
+    void run_chunk(hipGraphExec_t &exec, F &&body) {
+        if (!use_graphs) {
+            body();
+            return;
+        }
+        if (!exec) {
+            hipGraph_t graph = nullptr;
+            LSRN_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            try {
+                body();
+            } catch (...) {
+                (void)hipStreamEndCapture(st, &graph);
+                if (graph) (void)hipGraphDestroy(graph);
+                throw;
+            }
+            LSRN_HIP(hipStreamEndCapture(st, &graph));
+            const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            LSRN_HIP(e);
+        }
+        LSRN_HIP(hipGraphLaunch(exec, st));
+    }
+};
+
+struct GraphExec {
+    hipGraphExec_t g = nullptr;
+    ~GraphExec() {
+        if (g) (void)hipGraphExecDestroy(g);
+    }
 };
 
 int64_t default_maxiter(const IterProblem &pb, const lsrn_options &opt, double &sl, double &su) {
@@ -1210,16 +1245,19 @@ struct TallSolver {
                                                     wdir.as<double>(), y.as<double>(), cx.state);
         LSRN_HIP(hipGetLastError());
         State h = cx.host_state();
+        GraphExec graph;
         while (!h.done) {
-            for (int k = 0; k < CHUNK; ++k) {
-                cx.gemv(cx.pb.P, cx.pb.ldp, cx.L, r, v.as<double>(), wN.as<double>());
-                cx.sweep(OP_LSQR_TALL, wN.as<double>(), ulong.as<double>(), nullptr, nullptr);
-                cx.gemv(cx.Ptp, cx.L, r, cx.L, cx.z.as<double>(), t.as<double>());
-                lsqr_tall_step_kernel<<<1, SNT, 0, cx.st>>>(t.as<double>(), r, v.as<double>(),
-                                                            wdir.as<double>(), y.as<double>(), tol,
-                                                            cx.state);
-            }
-            LSRN_HIP(hipGetLastError());
+            cx.run_chunk(graph.g, [&] {
+                for (int k = 0; k < CHUNK; ++k) {
+                    cx.gemv(cx.pb.P, cx.pb.ldp, cx.L, r, v.as<double>(), wN.as<double>());
+                    cx.sweep(OP_LSQR_TALL, wN.as<double>(), ulong.as<double>(), nullptr, nullptr);
+                    cx.gemv(cx.Ptp, cx.L, r, cx.L, cx.z.as<double>(), t.as<double>());
+                    lsqr_tall_step_kernel<<<1, SNT, 0, cx.st>>>(t.as<double>(), r, v.as<double>(),
+                                                                wdir.as<double>(), y.as<double>(),
+                                                                tol, cx.state);
+                }
+                LSRN_HIP(hipGetLastError());
+            });
             h = cx.host_state();
         }
         converged = h.converged != 0;
@@ -1279,15 +1317,18 @@ struct FatSolver {
         lsqr_fat_step_kernel<<<1, SNT, 0, cx.st>>>(t.as<double>(), r, u.as<double>(), 1, tol, cx.state);
         LSRN_HIP(hipGetLastError());
         State h = cx.host_state();
+        GraphExec graph;
         while (!h.done) {
-            for (int k = 0; k < CHUNK; ++k) {
-                cx.gemv(cx.pb.P, cx.pb.ldp, cx.L, r, u.as<double>(), wM.as<double>());
-                cx.sweep(OP_LSQR_FAT, wM.as<double>(), vt.as<double>(), x, wdir.as<double>());
-                cx.gemv(cx.Ptp, cx.L, r, cx.L, cx.z.as<double>(), t.as<double>());
-                lsqr_fat_step_kernel<<<1, SNT, 0, cx.st>>>(t.as<double>(), r, u.as<double>(), 0, tol,
-                                                           cx.state);
-            }
-            LSRN_HIP(hipGetLastError());
+            cx.run_chunk(graph.g, [&] {
+                for (int k = 0; k < CHUNK; ++k) {
+                    cx.gemv(cx.pb.P, cx.pb.ldp, cx.L, r, u.as<double>(), wM.as<double>());
+                    cx.sweep(OP_LSQR_FAT, wM.as<double>(), vt.as<double>(), x, wdir.as<double>());
+                    cx.gemv(cx.Ptp, cx.L, r, cx.L, cx.z.as<double>(), t.as<double>());
+                    lsqr_fat_step_kernel<<<1, SNT, 0, cx.st>>>(t.as<double>(), r, u.as<double>(), 0,
+                                                               tol, cx.state);
+                }
+                LSRN_HIP(hipGetLastError());
+            });
             h = cx.host_state();
         }
         lsqr_fat_finish_kernel<<<grid1(n), 256, 0, cx.st>>>(n, x, wdir.as<double>(), cx.state);
@@ -1340,11 +1381,14 @@ double host_norm(const double *d, int64_t n, hipStream_t st) {
 
 }  // namespace
 
-IterResult iterate(const IterProblem &pb, const double *b, double *x, const lsrn_options &opt,
-                   hipStream_t st) {
+namespace {
+
+IterResult iterate_on(const IterProblem &pb, const double *b, double *x, const lsrn_options &opt,
+                      hipStream_t st) {
     IterResult res;
     Ctx cx(pb, st);
     cx.profile = opt.profile != 0;
+    cx.use_graphs = !cx.profile && st != nullptr;
     double sl = 0.0, su = 0.0;
     const int64_t maxiter = default_maxiter(pb, opt, sl, su);
     res.sigma_l = sl;
@@ -1378,6 +1422,7 @@ IterResult iterate(const IterProblem &pb, const double *b, double *x, const lsrn
             DevBuf dx((size_t)L * sizeof(double));
             // the sparse normal-equation sweep stores T p here for its column pass
             DevBuf ybuf(pb.sp ? (size_t)(pb.rows + L) * sizeof(double) : 0);
+            GraphExec cg_graph;  // the CG chunk keeps its buffers across refinement steps
             double dn_prev = 0.0;
             for (int step = 0; step < opt.refine; ++step) {
                 if (pb.sp) {
@@ -1404,14 +1449,17 @@ IterResult iterate(const IterProblem &pb, const double *b, double *x, const lsrn
                                                   pc.as<double>(), opt.refine_tol, cg_max, cx.state);
                 State hs = cx.host_state();
                 while (!hs.done) {
-                    for (int k = 0; k < CHUNK; ++k) {
-                        cx.gemv(pb.P, pb.ldp, L, r, pc.as<double>(), ts.wN.as<double>());
-                        cx.sweep(OP_NORMAL, ts.wN.as<double>(), ybuf.as<double>(), nullptr, nullptr);
-                        cx.gemv(cx.Ptp, L, r, L, cx.z.as<double>(), ts.t.as<double>());
-                        cg_step_kernel<<<1, SNT, 0, st>>>(ts.t.as<double>(), r, zc.as<double>(),
-                                                          rc.as<double>(), pc.as<double>(), cx.state);
-                    }
-                    LSRN_HIP(hipGetLastError());
+                    cx.run_chunk(cg_graph.g, [&] {
+                        for (int k = 0; k < CHUNK; ++k) {
+                            cx.gemv(pb.P, pb.ldp, L, r, pc.as<double>(), ts.wN.as<double>());
+                            cx.sweep(OP_NORMAL, ts.wN.as<double>(), ybuf.as<double>(), nullptr, nullptr);
+                            cx.gemv(cx.Ptp, L, r, L, cx.z.as<double>(), ts.t.as<double>());
+                            cg_step_kernel<<<1, SNT, 0, st>>>(ts.t.as<double>(), r, zc.as<double>(),
+                                                              rc.as<double>(), pc.as<double>(),
+                                                              cx.state);
+                        }
+                        LSRN_HIP(hipGetLastError());
+                    });
                     hs = cx.host_state();
                 }
                 res.refine_iters += hs.iters;
@@ -1496,6 +1544,28 @@ IterResult iterate(const IterProblem &pb, const double *b, double *x, const lsrn
     (void)hipEventDestroy(e1);
     (void)hipEventDestroy(e2);
     return res;
+}
+
+}  // namespace
+
+IterResult iterate(const IterProblem &pb, const double *b, double *x, const lsrn_options &opt,
+                   hipStream_t st) {
+    if (st) return iterate_on(pb, b, x, opt, st);
+    // the null stream cannot be captured into graphs: run on a stream of our
+    // own (default priority) after the caller's work on the null stream
+    LSRN_HIP(hipStreamSynchronize(nullptr));
+    hipStream_t own = nullptr;
+    LSRN_HIP(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+    try {
+        IterResult r = iterate_on(pb, b, x, opt, own);
+        LSRN_HIP(hipStreamSynchronize(own));
+        (void)hipStreamDestroy(own);
+        return r;
+    } catch (...) {
+        (void)hipStreamSynchronize(own);
+        (void)hipStreamDestroy(own);
+        throw;
+    }
 }
 
 }  // namespace lsrn

@@ -58,10 +58,20 @@ EXPORTS = ["lsrn_default_options", "lsrn_status_string", "lsrn_last_error", "lsr
            "lsrn_philox_words", "lsrn_gauss_fill", "lsrn_sketch_dense", "lsrn_sketch_dense_bf16",
            "lsrn_sketch_csr",
            "lsrn_precond", "lsrn_precond_qr", "lsrn_iterate_dense", "lsrn_iterate_csr"]
+SERVER_EXPORTS = ["lsrn_server_create", "lsrn_server_submit_dense", "lsrn_server_submit_csr",
+                  "lsrn_server_wait", "lsrn_server_stats", "lsrn_server_last_error",
+                  "lsrn_server_destroy"]
+EXPORTS = EXPORTS + SERVER_EXPORTS
 PRECOND = {"auto": 0, "svd": 1, "qr": 2}
 PRECISION = {"fp64": 0, "mixed": 1}
 _SIZE_FNS = ("lsrn_default_options", "lsrn_status_string", "lsrn_last_error",
-             "lsrn_workspace_bytes", "lsrn_workspace_bytes_csr")
+             "lsrn_workspace_bytes", "lsrn_workspace_bytes_csr", "lsrn_server_last_error",
+             "lsrn_server_destroy")
+
+
+class ServerTiming(C.Structure):
+    _fields_ = [("queue_ms", C.c_double), ("run_ms", C.c_double), ("latency_ms", C.c_double),
+                ("footprint_bytes", C.c_int64)]
 
 
 def lib():
@@ -95,6 +105,17 @@ def lib():
         L.lsrn_precond_qr.argtypes = [I64, I64, P, D, P, P, P]
         L.lsrn_iterate_csr.argtypes = [I64, I64, I64, P, P, P, P, P, I64, I64, I64, P,
                                        C.POINTER(Options), C.POINTER(Info), P]
+        L.lsrn_server_create.argtypes = [I64, I32, C.POINTER(C.c_void_p)]
+        L.lsrn_server_submit_dense.argtypes = [P, I64, I64, P, I64, I32, P, P, C.POINTER(Options),
+                                               C.POINTER(C.c_int64)]
+        L.lsrn_server_submit_csr.argtypes = [P, I64, I64, I64, P, P, P, P, P, C.POINTER(Options),
+                                             C.POINTER(C.c_int64)]
+        L.lsrn_server_wait.argtypes = [P, I64, C.POINTER(Info), C.POINTER(ServerTiming)]
+        L.lsrn_server_stats.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                        C.POINTER(C.c_int64)]
+        L.lsrn_server_last_error.restype = C.c_char_p
+        L.lsrn_server_destroy.argtypes = [P]
+        L.lsrn_server_destroy.restype = None
         for name in EXPORTS:
             if name not in _SIZE_FNS:
                 getattr(L, name).restype = C.c_int
@@ -317,3 +338,79 @@ def iterate_csr(A: Csr, b: torch.Tensor, P: torch.Tensor, s: int, **opts):
     _check(lib().lsrn_iterate_csr(*A.args(), b.data_ptr(), P.data_ptr(), P.stride(0), P.shape[1], s,
                                   x.data_ptr(), C.byref(o), C.byref(info), _stream()))
     return x, info.as_dict()
+
+
+class Server:
+    """The serving runtime (lsrn_server_*): submit solves as they arrive,
+    wait for them by ticket.  Tensors of a request are kept referenced until
+    it has been waited for."""
+
+    def __init__(self, hbm_budget_bytes: int, streams: int = 8):
+        h = C.c_void_p()
+        st = lib().lsrn_server_create(int(hbm_budget_bytes), int(streams), C.byref(h))
+        if st != 0:
+            raise LSRNError(st, lib().lsrn_server_last_error().decode())
+        self._h = h
+        self._keep = {}
+
+    def submit_dense(self, A: torch.Tensor, b: torch.Tensor, x: torch.Tensor | None = None, *,
+                     layout: int = ROW_MAJOR, **opts) -> int:
+        _dev_f64(A, "A")
+        _dev_f64(b, "b")
+        m, n, lda = _layout_dims(A, layout)
+        if b.numel() != m or not b.is_contiguous():
+            raise ValueError("b must be contiguous with m entries")
+        if x is None:
+            x = torch.empty(n, dtype=torch.float64, device=A.device)
+        o = options(**opts)
+        t = C.c_int64()
+        # the request's inputs must be complete before a worker stream reads them
+        torch.cuda.current_stream().synchronize()
+        st = lib().lsrn_server_submit_dense(self._h, m, n, A.data_ptr(), lda, layout, b.data_ptr(),
+                                            x.data_ptr(), C.byref(o), C.byref(t))
+        if st != 0:
+            raise LSRNError(st, lib().lsrn_server_last_error().decode())
+        self._keep[t.value] = (A, b, x)
+        return t.value
+
+    def submit_csr(self, A: "Csr", b: torch.Tensor, x: torch.Tensor | None = None, **opts) -> int:
+        _dev_f64(b, "b")
+        if x is None:
+            x = torch.empty(A.n, dtype=torch.float64, device=b.device)
+        o = options(**opts)
+        t = C.c_int64()
+        torch.cuda.current_stream().synchronize()
+        st = lib().lsrn_server_submit_csr(self._h, *A.args(), b.data_ptr(), x.data_ptr(),
+                                          C.byref(o), C.byref(t))
+        if st != 0:
+            raise LSRNError(st, lib().lsrn_server_last_error().decode())
+        self._keep[t.value] = (A, b, x)
+        return t.value
+
+    def wait(self, ticket: int, allow_not_converged: bool = False):
+        """(x, info dict, timing dict) of a submitted request."""
+        info, tm = Info(), ServerTiming()
+        st = lib().lsrn_server_wait(self._h, ticket, C.byref(info), C.byref(tm))
+        _, _, x = self._keep.pop(ticket)
+        if st != 0 and not (allow_not_converged and st == 4):
+            raise LSRNError(st, lib().lsrn_server_last_error().decode())
+        out = info.as_dict()
+        out["status"] = int(st)
+        return x, out, {"queue_ms": tm.queue_ms, "run_ms": tm.run_ms,
+                        "latency_ms": tm.latency_ms, "footprint_bytes": tm.footprint_bytes}
+
+    def stats(self):
+        p, r, b = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().lsrn_server_stats(self._h, C.byref(p), C.byref(r), C.byref(b)))
+        return {"pending": p.value, "running": r.value, "bytes_in_use": b.value}
+
+    def close(self):
+        if self._h:
+            lib().lsrn_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -260,3 +260,23 @@ def test_edge_cases(L, orc):
     with pytest.raises(L.LSRNError) as e:
         L.solve_dense(dev(A.T.copy()), dev(np.ones(8)), lam=0.1)
     assert e.value.status == 5
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_graph_replays_match_eager_launches(L, dense_workload, method):
+    """The iteration chunks replayed as HIP graphs (profile off) give the
+    same bits as the eager launches (profile on), on the null stream and on
+    a stream of the caller's, over repeated solves with eager work between."""
+    P, b, _ = dense_workload
+    A_d, b_d = dev(P.A), dev(b)
+    ref, _ = L.solve_dense(A_d, b_d, seed=8, refine=2, method=method, profile=1)
+    ref = host(ref)
+    s = torch.cuda.Stream()
+    for rep in range(3):
+        x0, _ = L.solve_dense(A_d, b_d, seed=8, refine=2, method=method)
+        np.testing.assert_array_equal(host(x0), ref)
+        with torch.cuda.stream(s):
+            x1, _ = L.solve_dense(A_d, b_d, seed=8, refine=2, method=method)
+        s.synchronize()
+        np.testing.assert_array_equal(host(x1), ref)
+        _ = A_d.sum().item()  # eager work between replays

@@ -1,0 +1,110 @@
+"""The serving runtime: every request's result is the same alone and in a
+mix of concurrently running solves, admission respects the memory budget,
+and errors come back per request."""
+import time
+
+import numpy as np
+import pytest
+
+import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1109_5981_amd import lsrn
+    lsrn.lib()  # raises if the library is missing: there is no CPU fallback
+    return lsrn
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def mix(L):
+    """Uneven requests: tall and fat dense, FP64 and the precision form,
+    LSQR and Chebyshev, sparse with Tikhonov."""
+    reqs = []
+    shapes = [(3000, 60, 0, "fp64", "lsqr"), (5000, 200, 0, "mixed", "lsqr"), (80, 4000, 1, "fp64", "lsqr"),
+              (12000, 130, 0, "fp64", "chebyshev"), (2500, 40, 0, "fp64", "lsqr"),
+              (150, 3000, 1, "fp64", "chebyshev"), (7000, 300, 0, "mixed", "lsqr"),
+              (4000, 100, 0, "fp64", "lsqr")]
+    for i, (m, n, layout, prec, meth) in enumerate(shapes):
+        rows, cols = (m, n) if layout == 0 else (n, m)        # stored array
+        P = workloads.dense_problem(max(rows, cols), min(rows, cols), smin=10.0 ** -(3 + i % 4),
+                                    seed=100 + i)
+        A = P.A if layout == 0 else P.A                       # tall storage (rows >= cols)
+        b = workloads.rhs_gauss(m, 100 + i)
+        reqs.append(("dense", dev(A), dev(b), dict(layout=layout, precision=prec, method=meth,
+                                                     seed=7 + i, refine=10 if prec == "mixed" else 3)))
+    S = workloads.sparse_problem(20000, 150, per_row=12, n_dense=3, fill=0.2, seed=9)
+    reqs.append(("csr", L.Csr.from_host(S.m, S.n, S.rowptr, S.colind, S.val),
+                 dev(workloads.rhs_gauss(S.m, 9)), dict(lam=1e-3, seed=3, refine=2)))
+    return reqs
+
+
+def solve_alone(L, kind, A, b, opts):
+    if kind == "dense":
+        x, info = L.solve_dense(A, b, allow_not_converged=True, **opts)
+    else:
+        x, info = L.solve_csr(A, b, **opts)
+    return host(x), info
+
+
+def test_results_alone_equal_results_in_mix(L):
+    reqs = mix(L)
+    alone = [solve_alone(L, *r)[0] for r in reqs]
+    with L.Server(hbm_budget_bytes=64 << 30, streams=4) as srv:
+        for rep in range(2):
+            tickets = []
+            for kind, A, b, opts in reqs:
+                if kind == "dense":
+                    tickets.append(srv.submit_dense(A, b, **opts))
+                else:
+                    tickets.append(srv.submit_csr(A, b, **opts))
+            for t, ref in zip(tickets, alone):
+                x, info, tm = srv.wait(t, allow_not_converged=True)
+                np.testing.assert_array_equal(host(x), ref)
+                assert tm["latency_ms"] >= tm["run_ms"] >= 0.0
+
+
+def test_admission_respects_budget(L):
+    P = workloads.dense_problem(20000, 100, smin=1e-4, seed=5)
+    A, b = dev(P.A), dev(workloads.rhs_gauss(20000, 5))
+    need = L.workspace_bytes(20000, 100)
+    budget = int(1.5 * need)   # one request at a time fits, two do not
+    with L.Server(hbm_budget_bytes=budget, streams=4) as srv:
+        t0 = time.perf_counter()
+        tickets = [srv.submit_dense(A, b, seed=s) for s in range(6)]
+        spans = []
+        for t in tickets:
+            _, _, tm = srv.wait(t)
+            assert tm["footprint_bytes"] == need
+            spans.append((tm["queue_ms"], tm["queue_ms"] + tm["run_ms"]))
+    # admitted one after the other: each request starts after the previous
+    # one finished (submissions were back to back, so queue times grow)
+    spans.sort()
+    for (s0, e0), (s1, e1) in zip(spans, spans[1:]):
+        assert s1 >= e0 - 2.0
+
+
+def test_request_errors_are_per_request(L):
+    P = workloads.dense_problem(500, 20, smin=1e-3, seed=6)
+    A, b = dev(P.A), dev(workloads.rhs_gauss(500, 6))
+    with L.Server(hbm_budget_bytes=1 << 30, streams=2) as srv:
+        good = srv.submit_dense(A, b)
+        bad = srv.submit_dense(A, b, precision="mixed", method="chebyshev")
+        _, info, _ = srv.wait(good)
+        assert info["rank"] == 20
+        with pytest.raises(L.LSRNError) as e:
+            srv.wait(bad)
+        assert e.value.status == 5
