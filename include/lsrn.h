@@ -255,6 +255,26 @@ lsrn_status lsrn_iterate_csr(int64_t m, int64_t n, int64_t nnz, const int64_t *r
                              const double *P, int64_t ldp, int64_t r, int64_t s, double *x,
                              const lsrn_options *opt, lsrn_info *info, void *stream);
 
+/*
+ * Many small over-determined solves at once (Alg. 1 for each problem): A[p]
+ * dense FP64 row-major, m[p] >= n[p], n[p] <= 512, leading dimension
+ * lda[p]; b[p] length m[p]; x[p] length n[p] (arrays of device pointers
+ * held on the host).  Each problem's sketch and SVD run in turn on the
+ * stream; then the LSQR iterations of all problems advance together: every
+ * kernel launch covers the whole batch (one work item per problem row
+ * block, column chunk or problem) and each chunk of iterations is replayed
+ * as a HIP graph, so the number of launches does not grow with the number
+ * of problems.  One option set for all problems; LSQR only, no refinement,
+ * lambda = 0, precision FP64, the SVD preconditioner (LSRN_E_UNSUPPORTED
+ * otherwise).  infos (count entries, may be NULL) report per problem; the
+ * stage times are those of the whole batch.  LSRN_E_NOT_CONVERGED if any
+ * problem reached max_iter (its x holds the last iterate).
+ */
+lsrn_status lsrn_solve_batch(int32_t count, const int64_t *m, const int64_t *n,
+                             const double *const *A, const int64_t *lda, const double *const *b,
+                             double *const *x, const lsrn_options *opt, lsrn_info *infos,
+                             void *stream);
+
 /* ------------------------------------------------------------------------
  * Serving runtime: solves of different shapes submitted as they arrive,
  * admitted by device-memory footprint onto a pool of streams (not a paper

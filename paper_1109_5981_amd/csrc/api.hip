@@ -7,6 +7,7 @@
 #include <exception>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "internal.hpp"
 
@@ -25,6 +26,10 @@ void hip_check(hipError_t e, const char *what) {
 static thread_local hipStream_t g_alloc_stream = nullptr;
 
 void set_alloc_stream(hipStream_t s) { g_alloc_stream = s; }
+
+static thread_local bool g_graphs_allowed = true;
+void set_graphs_allowed(bool on) { g_graphs_allowed = on; }
+bool graphs_allowed() { return g_graphs_allowed; }
 
 void DevBuf::alloc(size_t bytes) {
     release();
@@ -480,6 +485,90 @@ lsrn_status lsrn_iterate_csr(int64_t m, int64_t n, int64_t nnz, const int64_t *r
     fill_iter_info(info, s, v.d, r, v.tall, ir);
     if (!ir.converged) {
         g_last_error = "LSQR reached max_iter";
+        return LSRN_E_NOT_CONVERGED;
+    }
+    LSRN_API_END
+}
+
+lsrn_status lsrn_solve_batch(int32_t count, const int64_t *m, const int64_t *n,
+                             const double *const *A, const int64_t *lda, const double *const *b,
+                             double *const *x, const lsrn_options *opt_in, lsrn_info *infos,
+                             void *stream) {
+    LSRN_API_BEGIN
+    const lsrn_options opt = opt_in ? *opt_in : defaults();
+    check_options(opt);
+    LSRN_REQUIRE(count >= 0, "count must be >= 0");
+    LSRN_REQUIRE(count == 0 || (m && n && A && lda && b && x), "NULL pointer");
+    if (opt.method != LSRN_LSQR || opt.refine != 0 || opt.lambda != 0.0 ||
+        opt.precision != LSRN_PREC_FP64 || opt.precond == LSRN_PRECOND_QR)
+        fail(LSRN_E_UNSUPPORTED, "the batched path runs FP64 LSQR with the SVD preconditioner, "
+                                 "without refinement or lambda");
+    hipStream_t st = (hipStream_t)stream;
+    for (int32_t p = 0; p < count; ++p) {
+        LSRN_REQUIRE(m[p] >= n[p] && n[p] > 0 && n[p] <= 512, "batched problems need m >= n, 0 < n <= 512");
+        LSRN_REQUIRE(A[p] && b[p] && x[p] && lda[p] >= n[p], "bad batched problem");
+    }
+    StageTimer tm(st);
+    tm.mark();
+    std::vector<IterProblem> pbs((size_t)count);
+    std::vector<const double *> bs((size_t)count);
+    std::vector<double *> xs((size_t)count);
+    std::vector<DevBuf> Ps;
+    Ps.reserve((size_t)count);
+    std::vector<PrecondResult> prs((size_t)count);
+    std::vector<int64_t> ss((size_t)count);
+    for (int32_t p = 0; p < count; ++p) {
+        const int64_t d = n[p];
+        const int64_t s = (int64_t)std::ceil(opt.gamma * (double)d);
+        ss[(size_t)p] = s;
+        DevBuf X((size_t)s * (size_t)d * sizeof(double)), sigma((size_t)d * sizeof(double));
+        sketch_rows(m[p], d, A[p], lda[p], 0.0, s, opt.seed, X.as<double>(), st);
+        Ps.emplace_back((size_t)d * (size_t)d * sizeof(double));
+        prs[(size_t)p] = precond(s, d, X.as<double>(), opt.rcond, sigma.as<double>(),
+                                 Ps.back().as<double>(), st);
+        IterProblem &pb = pbs[(size_t)p];
+        pb.tall = true; pb.rows = m[p]; pb.cols = d; pb.T = A[p]; pb.ldt = lda[p];
+        pb.P = Ps.back().as<double>(); pb.ldp = d; pb.r = prs[(size_t)p].rank; pb.s = s;
+        bs[(size_t)p] = b[p];
+        xs[(size_t)p] = x[p];
+    }
+    tm.mark();
+    // rank-0 problems (A = 0) are answered directly; the rest iterate together
+    std::vector<IterProblem> live;
+    std::vector<const double *> lb;
+    std::vector<double *> lx;
+    std::vector<int32_t> idx;
+    for (int32_t p = 0; p < count; ++p) {
+        if (pbs[(size_t)p].r > 0) {
+            live.push_back(pbs[(size_t)p]);
+            lb.push_back(bs[(size_t)p]);
+            lx.push_back(xs[(size_t)p]);
+            idx.push_back(p);
+        } else {
+            LSRN_HIP(hipMemsetAsync(x[p], 0, (size_t)n[p] * sizeof(double), st));
+        }
+    }
+    std::vector<IterResult> irs = iterate_batch_tall(live, lb, lx, opt, st);
+    tm.mark();
+    bool all_conv = true;
+    std::vector<IterResult> full((size_t)count);
+    for (size_t k = 0; k < idx.size(); ++k) full[(size_t)idx[k]] = irs[k];
+    for (int32_t p = 0; p < count; ++p) {
+        all_conv = all_conv && full[(size_t)p].converged;
+        if (!infos) continue;
+        lsrn_info &in = infos[p];
+        std::memset(&in, 0, sizeof(in));
+        in.s = ss[(size_t)p]; in.d = n[p]; in.rank = prs[(size_t)p].rank;
+        in.iters = full[(size_t)p].iters; in.sweeps = prs[(size_t)p].sweeps; in.tall = 1;
+        in.converged = full[(size_t)p].converged;
+        in.sigma_l = full[(size_t)p].sigma_l; in.sigma_u = full[(size_t)p].sigma_u;
+        in.sigma_max = prs[(size_t)p].sigma_max; in.sigma_min_kept = prs[(size_t)p].sigma_min_kept;
+        in.t_svd_ms = tm.elapsed_ms(0, 1);   // sketches + preconditioners of the whole batch
+        in.t_iter_ms = tm.elapsed_ms(1, 2);  // batched iterations of the whole batch
+        in.t_total_ms = tm.elapsed_ms(0, 2);
+    }
+    if (!all_conv) {
+        g_last_error = "LSQR reached max_iter for at least one problem";
         return LSRN_E_NOT_CONVERGED;
     }
     LSRN_API_END

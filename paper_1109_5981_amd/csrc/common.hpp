@@ -67,6 +67,12 @@ class DevBuf {
 // (nullptr: plain hipMalloc / hipFree).
 void set_alloc_stream(hipStream_t s);
 
+// Whether this thread may capture iteration chunks into HIP graphs (the
+// serving workers do not: a capture there can be invalidated by device-wide
+// work other threads issue meanwhile).
+void set_graphs_allowed(bool on);
+bool graphs_allowed();
+
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 __host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 

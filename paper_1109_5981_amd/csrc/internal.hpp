@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 #include "common.hpp"
 
@@ -149,5 +150,12 @@ struct IterResult {
 // writes x (length n).  Synchronises.
 IterResult iterate(const IterProblem &pb, const double *b, double *x, const lsrn_options &opt,
                    hipStream_t st);
+
+// LSQR for many tall dense FP64 problems (cols <= 512, no lambda) at once:
+// each kernel launch covers the whole batch.  No refinement.  Synchronises.
+std::vector<IterResult> iterate_batch_tall(const std::vector<IterProblem> &pbs,
+                                           const std::vector<const double *> &bs,
+                                           const std::vector<double *> &xs, const lsrn_options &opt,
+                                           hipStream_t st);
 
 }  // namespace lsrn

@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "internal.hpp"
@@ -76,7 +77,7 @@ __device__ __forceinline__ int col_of(int tid, int e) {
 }
 
 template <int CPT, int R, int OP, bool F32>
-__global__ void __launch_bounds__(NT, 2) sweep_kernel(SweepArgs a) {
+__device__ __forceinline__ void sweep_body(const SweepArgs &a, const int block) {
     if (a.st->done) return;
     __shared__ double red[2][NT / 64][R];
     __shared__ double accred[NT / 64][4];
@@ -104,7 +105,7 @@ __global__ void __launch_bounds__(NT, 2) sweep_kernel(SweepArgs a) {
     }
     double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
 
-    const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_block;
+    const int64_t r0 = (int64_t)block * a.rows_per_block;
     const int64_t r1 = min(a.rows, r0 + a.rows_per_block);
     const bool vec2 = F32 ? (((a.ldt & 1) == 0) && ((reinterpret_cast<uintptr_t>(a.T32) & 7) == 0))
                           : (((a.ldt & 1) == 0) && ((reinterpret_cast<uintptr_t>(a.T) & 15) == 0));
@@ -240,7 +241,7 @@ __global__ void __launch_bounds__(NT, 2) sweep_kernel(SweepArgs a) {
 #pragma unroll
         for (int e = 0; e < CPT; ++e) {
             const int col = col_of<CPT>(tid, e);
-            if (col < L && (col % a.nblocks) == (int)blockIdx.x) {
+            if (col < L && (col % a.nblocks) == block) {
                 const int64_t row = a.rows + col;
                 const double qv = a.lambda * wr[e];
                 double c;
@@ -257,7 +258,7 @@ __global__ void __launch_bounds__(NT, 2) sweep_kernel(SweepArgs a) {
 #pragma unroll
     for (int e = 0; e < CPT; ++e) {
         const int col = col_of<CPT>(tid, e);
-        if (col < L) a.zpart[(int64_t)blockIdx.x * L + col] = zr[e];
+        if (col < L) a.zpart[(int64_t)block * L + col] = zr[e];
     }
     acc0 = wave_sum(acc0);
     acc1 = wave_sum(acc1);
@@ -270,8 +271,13 @@ __global__ void __launch_bounds__(NT, 2) sweep_kernel(SweepArgs a) {
     if (tid < 4) {
         double t = 0.0;
         for (int w = 0; w < NT / 64; ++w) t += accred[w][tid];
-        a.spart[(int64_t)blockIdx.x * 4 + tid] = t;
+        a.spart[(int64_t)block * 4 + tid] = t;
     }
+}
+
+template <int CPT, int R, int OP, bool F32>
+__global__ void __launch_bounds__(NT, 2) sweep_kernel(SweepArgs a) {
+    sweep_body<CPT, R, OP, F32>(a, (int)blockIdx.x);
 }
 
 // Stage 1 of the partial-sum reduction: group g of the workgroup partials
@@ -343,9 +349,9 @@ __device__ double vec_dot(const double *a, const double *b, int64_t n, double *s
 }
 
 // Tall LSQR start: t = K^T b^ (unscaled, from the first sweep), acc0 = ||b^||^2.
-__global__ void __launch_bounds__(SNT)
-lsqr_tall_init_kernel(const double *__restrict__ t, int64_t r, double *__restrict__ v,
-                      double *__restrict__ wdir, double *__restrict__ y, State *st) {
+__device__ __forceinline__ void lsqr_tall_init_body(const double *__restrict__ t, int64_t r,
+                                                    double *__restrict__ v, double *__restrict__ wdir,
+                                                    double *__restrict__ y, State *st) {
     __shared__ double scratch[SNT / 64];
     const double beta = sqrt(st->acc[0]);
     const double ib = beta > 0.0 ? 1.0 / beta : 0.0;
@@ -377,11 +383,17 @@ lsqr_tall_init_kernel(const double *__restrict__ t, int64_t r, double *__restric
     }
 }
 
+__global__ void __launch_bounds__(SNT)
+lsqr_tall_init_kernel(const double *__restrict__ t, int64_t r, double *__restrict__ v,
+                      double *__restrict__ wdir, double *__restrict__ y, State *st) {
+    lsqr_tall_init_body(t, r, v, wdir, y, st);
+}
+
 // One LSQR iteration given t = N^T A^T u~ and acc0 = ||u~||^2 from the sweep
 // that formed u~ = K v - alpha u.  Stopping rules of Paige-Saunders.
-__global__ void __launch_bounds__(SNT)
-lsqr_tall_step_kernel(const double *__restrict__ t, int64_t r, double *__restrict__ v,
-                      double *__restrict__ wdir, double *__restrict__ y, double tol, State *st) {
+__device__ __forceinline__ void lsqr_tall_step_body(const double *__restrict__ t, int64_t r,
+                                                    double *__restrict__ v, double *__restrict__ wdir,
+                                                    double *__restrict__ y, double tol, State *st) {
     if (st->done) return;
     __shared__ double scratch[SNT / 64];
     const double alpha_old = st->alpha;
@@ -431,6 +443,12 @@ lsqr_tall_step_kernel(const double *__restrict__ t, int64_t r, double *__restric
         st->converged = conv ? 1 : 0;
         st->done = (conv || it >= st->maxiter) ? 1 : 0;
     }
+}
+
+__global__ void __launch_bounds__(SNT)
+lsqr_tall_step_kernel(const double *__restrict__ t, int64_t r, double *__restrict__ v,
+                      double *__restrict__ wdir, double *__restrict__ y, double tol, State *st) {
+    lsqr_tall_step_body(t, r, v, wdir, y, tol, st);
 }
 
 // Fat LSQR start: c = M^T b in t (length r); u = c / beta.
@@ -1388,7 +1406,7 @@ IterResult iterate_on(const IterProblem &pb, const double *b, double *x, const l
     IterResult res;
     Ctx cx(pb, st);
     cx.profile = opt.profile != 0;
-    cx.use_graphs = !cx.profile && st != nullptr;
+    cx.use_graphs = !cx.profile && st != nullptr && graphs_allowed();
     double sl = 0.0, su = 0.0;
     const int64_t maxiter = default_maxiter(pb, opt, sl, su);
     res.sigma_l = sl;
@@ -1566,6 +1584,252 @@ IterResult iterate(const IterProblem &pb, const double *b, double *x, const lsrn
         (void)hipStreamDestroy(own);
         throw;
     }
+}
+
+// ------------------------------------------------------- batched LSQR
+//
+// Many tall problems with min(m, n) <= 512 iterate together: every launch
+// below covers the whole batch, one work item per (problem, row block),
+// (problem, column chunk), (problem, row group) or problem, found from a
+// prefix table; a problem whose done flag is set leaves the work items of
+// its kernels empty.  One chunk of iterations (five launches each) is
+// replayed as a HIP graph.
+
+namespace {
+
+constexpr int BCPT = 2, BR = 8;          // the sweep variant for L <= 512
+constexpr int64_t B_ROWS_PER_BLOCK = 512;
+
+struct BatchItem {
+    SweepArgs sw;  // T, ldt, rows, L, nblocks, rows_per_block, w = wN, zpart, spart, y = u, st
+    const double *P;
+    int64_t ldp;
+    const double *Pt;  // r x L
+    int64_t r, L;
+    double *v, *wdir, *yv, *t, *z, *x;
+    double tol;
+};
+
+__device__ __forceinline__ int find_item(const int *__restrict__ off, int n, int g) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int OP>
+__global__ void __launch_bounds__(NT, 2)
+batch_sweep_kernel(const BatchItem *__restrict__ it, const int *__restrict__ off, int n) {
+    const int p = find_item(off, n, (int)blockIdx.x);
+    sweep_body<BCPT, BR, OP, false>(it[p].sw, (int)blockIdx.x - off[p]);
+}
+
+// z_p = sum of the row-block partials, st_p->acc = sum of the scalar partials.
+__global__ void __launch_bounds__(256)
+batch_reduce_kernel(const BatchItem *__restrict__ it, const int *__restrict__ off, int n) {
+    const int p = find_item(off, n, (int)blockIdx.x);
+    const BatchItem &b = it[p];
+    if (b.sw.st->done) return;
+    const int chunk = (int)blockIdx.x - off[p];
+    const int col = chunk * 256 + threadIdx.x;
+    const int nb = b.sw.nblocks;
+    if (col < b.L) {
+        double t = 0.0;
+        for (int k = 0; k < nb; ++k) t += b.sw.zpart[(int64_t)k * b.L + col];
+        b.z[col] = t;
+    }
+    if (chunk == 0 && threadIdx.x < 4) {
+        double t = 0.0;
+        for (int k = 0; k < nb; ++k) t += b.sw.spart[k * 4 + threadIdx.x];
+        b.sw.st->acc[threadIdx.x] = t;
+    }
+}
+
+// which 0: wN = P v; 1: t = P^T z; 2: x = P y (ignores the done flag).
+__global__ void __launch_bounds__(256)
+batch_gemv_kernel(const BatchItem *__restrict__ it, const int *__restrict__ off, int n, int which) {
+    const int p = find_item(off, n, (int)blockIdx.x);
+    const BatchItem &b = it[p];
+    if (which != 2 && b.sw.st->done) return;
+    const int64_t row = (int64_t)((int)blockIdx.x - off[p]) * 4 + (threadIdx.x >> 6);
+    const double *M;
+    int64_t ld, nrows, ncols;
+    const double *x;
+    double *y;
+    if (which == 1) { M = b.Pt; ld = b.L; nrows = b.r; ncols = b.L; x = b.z; y = b.t; }
+    else { M = b.P; ld = b.ldp; nrows = b.L; ncols = b.r; x = which == 0 ? b.v : b.yv;
+           y = which == 0 ? const_cast<double *>(b.sw.w) : b.x; }
+    if (row >= nrows) return;
+    const int lane = threadIdx.x & 63;
+    const double *mr = M + row * ld;
+    double t = 0.0;
+    for (int64_t c = lane; c < ncols; c += 64) t += mr[c] * x[c];
+    t = wave_sum(t);
+    if (lane == 0) y[row] = t;
+}
+
+__global__ void __launch_bounds__(SNT) batch_init_kernel(const BatchItem *__restrict__ it) {
+    const BatchItem &b = it[blockIdx.x];
+    lsqr_tall_init_body(b.t, b.r, b.v, b.wdir, b.yv, b.sw.st);
+}
+
+__global__ void __launch_bounds__(SNT) batch_step_kernel(const BatchItem *__restrict__ it) {
+    const BatchItem &b = it[blockIdx.x];
+    lsqr_tall_step_body(b.t, b.r, b.v, b.wdir, b.yv, b.tol, b.sw.st);
+}
+
+__global__ void batch_set_state_kernel(const BatchItem *__restrict__ it, const int *__restrict__ maxit) {
+    State z = {};
+    z.maxiter = maxit[blockIdx.x];
+    *it[blockIdx.x].sw.st = z;
+}
+
+}  // namespace
+
+std::vector<IterResult> iterate_batch_tall(const std::vector<IterProblem> &pbs,
+                                           const std::vector<const double *> &bs,
+                                           const std::vector<double *> &xs, const lsrn_options &opt,
+                                           hipStream_t st) {
+    const int n = (int)pbs.size();
+    std::vector<IterResult> res((size_t)n);
+    if (n == 0) return res;
+    for (const IterProblem &pb : pbs)
+        LSRN_REQUIRE(pb.tall && !pb.sp && !pb.T32 && pb.lambda == 0.0 && pb.cols <= 512,
+                     "batched iterations: tall dense FP64 problems with n <= 512");
+    // per-problem buffers, one allocation per kind
+    std::vector<BatchItem> items((size_t)n);
+    std::vector<int> off_sw(n + 1), off_red(n + 1), off_gP(n + 1), off_gPt(n + 1), maxit(n);
+    std::vector<DevBuf> bufs;
+    bufs.reserve((size_t)n * 12);
+    auto buf = [&](size_t elems) {
+        bufs.emplace_back(std::max<size_t>(elems, 1) * sizeof(double));
+        return bufs.back().as<double>();
+    };
+    DevBuf states((size_t)n * sizeof(State));
+    for (int p = 0; p < n; ++p) {
+        const IterProblem &pb = pbs[(size_t)p];
+        BatchItem &b = items[(size_t)p];
+        const int64_t L = pb.cols, r = pb.r;
+        const int nblocks = (int)std::max<int64_t>(1, ceil_div(pb.rows, B_ROWS_PER_BLOCK));
+        std::memset(&b, 0, sizeof(b));
+        b.sw.T = pb.T; b.sw.T32 = nullptr; b.sw.ldt = pb.ldt; b.sw.rows = pb.rows; b.sw.L = (int)L;
+        b.sw.nblocks = nblocks; b.sw.rows_per_block = B_ROWS_PER_BLOCK;
+        b.sw.zpart = buf((size_t)nblocks * L);
+        b.sw.spart = buf((size_t)nblocks * 4);
+        b.sw.y = buf((size_t)pb.rows);
+        b.sw.st = states.as<State>() + p;
+        b.sw.lambda = 0.0;
+        double *wN = buf((size_t)L);
+        b.sw.w = wN;
+        b.P = pb.P; b.ldp = pb.ldp; b.r = r; b.L = L;
+        double *Pt = buf((size_t)r * L);
+        transpose(L, r, pb.P, pb.ldp, Pt, st);
+        b.Pt = Pt;
+        b.v = buf((size_t)r); b.wdir = buf((size_t)r); b.yv = buf((size_t)r); b.t = buf((size_t)r);
+        b.z = buf((size_t)L); b.x = xs[(size_t)p];
+        b.tol = opt.tol;
+        LSRN_HIP(hipMemcpyAsync(b.sw.y, bs[(size_t)p], (size_t)pb.rows * sizeof(double),
+                                hipMemcpyDeviceToDevice, st));
+        double sl = 0.0, su = 0.0;
+        maxit[(size_t)p] = (int)default_maxiter(pb, opt, sl, su);
+        res[(size_t)p].sigma_l = sl;
+        res[(size_t)p].sigma_u = su;
+        off_sw[(size_t)p + 1] = off_sw[(size_t)p] + nblocks;
+        off_red[(size_t)p + 1] = off_red[(size_t)p] + (int)ceil_div(L, 256);
+        off_gP[(size_t)p + 1] = off_gP[(size_t)p] + (int)ceil_div(L, 4);
+        off_gPt[(size_t)p + 1] = off_gPt[(size_t)p] + (int)ceil_div(r, 4);
+    }
+    DevBuf ditems((size_t)n * sizeof(BatchItem)), doffs((size_t)(4 * (n + 1) + n) * sizeof(int));
+    int *o_sw = doffs.as<int>(), *o_red = o_sw + (n + 1), *o_gP = o_red + (n + 1),
+        *o_gPt = o_gP + (n + 1), *o_max = o_gPt + (n + 1);
+    std::vector<int> packed;
+    packed.insert(packed.end(), off_sw.begin(), off_sw.end());
+    packed.insert(packed.end(), off_red.begin(), off_red.end());
+    packed.insert(packed.end(), off_gP.begin(), off_gP.end());
+    packed.insert(packed.end(), off_gPt.begin(), off_gPt.end());
+    packed.insert(packed.end(), maxit.begin(), maxit.end());
+    LSRN_HIP(hipMemcpyAsync(ditems.as<BatchItem>(), items.data(), (size_t)n * sizeof(BatchItem),
+                            hipMemcpyHostToDevice, st));
+    LSRN_HIP(hipMemcpyAsync(o_sw, packed.data(), packed.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    const BatchItem *di = ditems.as<BatchItem>();
+    hipEvent_t e0, e1;
+    LSRN_HIP(hipEventCreate(&e0));
+    LSRN_HIP(hipEventCreate(&e1));
+    LSRN_HIP(hipEventRecord(e0, st));
+    // start: t = N^T A^T b, ||b||
+    batch_set_state_kernel<<<n, 1, 0, st>>>(di, o_max);
+    batch_sweep_kernel<OP_ATB><<<off_sw[(size_t)n], NT, 0, st>>>(di, o_sw, n);
+    batch_reduce_kernel<<<off_red[(size_t)n], 256, 0, st>>>(di, o_red, n);
+    batch_gemv_kernel<<<off_gPt[(size_t)n], 256, 0, st>>>(di, o_gPt, n, 1);
+    batch_init_kernel<<<n, SNT, 0, st>>>(di);
+    LSRN_HIP(hipGetLastError());
+    std::vector<State> hs((size_t)n);
+    auto all_done = [&] {
+        LSRN_HIP(hipMemcpyAsync(hs.data(), states.as<State>(), (size_t)n * sizeof(State),
+                                hipMemcpyDeviceToHost, st));
+        LSRN_HIP(hipStreamSynchronize(st));
+        for (const State &h : hs)
+            if (!h.done) return false;
+        return true;
+    };
+    hipGraphExec_t exec = nullptr;
+    auto chunk = [&] {
+        for (int k = 0; k < CHUNK; ++k) {
+            batch_gemv_kernel<<<off_gP[(size_t)n], 256, 0, st>>>(di, o_gP, n, 0);
+            batch_sweep_kernel<OP_LSQR_TALL><<<off_sw[(size_t)n], NT, 0, st>>>(di, o_sw, n);
+            batch_reduce_kernel<<<off_red[(size_t)n], 256, 0, st>>>(di, o_red, n);
+            batch_gemv_kernel<<<off_gPt[(size_t)n], 256, 0, st>>>(di, o_gPt, n, 1);
+            batch_step_kernel<<<n, SNT, 0, st>>>(di);
+        }
+        LSRN_HIP(hipGetLastError());
+    };
+    try {
+        while (!all_done()) {
+            if (st && graphs_allowed()) {
+                if (!exec) {
+                    hipGraph_t g = nullptr;
+                    LSRN_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+                    try {
+                        chunk();
+                    } catch (...) {
+                        (void)hipStreamEndCapture(st, &g);
+                        if (g) (void)hipGraphDestroy(g);
+                        throw;
+                    }
+                    LSRN_HIP(hipStreamEndCapture(st, &g));
+                    const hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+                    (void)hipGraphDestroy(g);
+                    LSRN_HIP(e);
+                }
+                LSRN_HIP(hipGraphLaunch(exec, st));
+            } else {
+                chunk();
+            }
+        }
+    } catch (...) {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        (void)hipStreamSynchronize(st);
+        throw;
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    batch_gemv_kernel<<<off_gP[(size_t)n], 256, 0, st>>>(di, o_gP, n, 2);
+    LSRN_HIP(hipGetLastError());
+    LSRN_HIP(hipEventRecord(e1, st));
+    LSRN_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    LSRN_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    for (int p = 0; p < n; ++p) {
+        res[(size_t)p].iters = hs[(size_t)p].iters;
+        res[(size_t)p].converged = hs[(size_t)p].converged != 0;
+        res[(size_t)p].t_iter_ms = ms;
+    }
+    LSRN_HIP(hipStreamSynchronize(st));  // before the buffers are freed
+    return res;
 }
 
 }  // namespace lsrn

@@ -70,6 +70,7 @@ struct lsrn_server {
         hipStream_t st = nullptr;
         if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return;
         lsrn::set_alloc_stream(st);
+        lsrn::set_graphs_allowed(false);
         for (;;) {
             Request *r = nullptr;
             {

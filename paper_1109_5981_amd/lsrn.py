@@ -58,6 +58,7 @@ EXPORTS = ["lsrn_default_options", "lsrn_status_string", "lsrn_last_error", "lsr
            "lsrn_philox_words", "lsrn_gauss_fill", "lsrn_sketch_dense", "lsrn_sketch_dense_bf16",
            "lsrn_sketch_csr",
            "lsrn_precond", "lsrn_precond_qr", "lsrn_iterate_dense", "lsrn_iterate_csr"]
+EXPORTS = EXPORTS + ["lsrn_solve_batch"]
 SERVER_EXPORTS = ["lsrn_server_create", "lsrn_server_submit_dense", "lsrn_server_submit_csr",
                   "lsrn_server_wait", "lsrn_server_stats", "lsrn_server_last_error",
                   "lsrn_server_destroy"]
@@ -105,6 +106,7 @@ def lib():
         L.lsrn_precond_qr.argtypes = [I64, I64, P, D, P, P, P]
         L.lsrn_iterate_csr.argtypes = [I64, I64, I64, P, P, P, P, P, I64, I64, I64, P,
                                        C.POINTER(Options), C.POINTER(Info), P]
+        L.lsrn_solve_batch.argtypes = [I32, P, P, P, P, P, P, C.POINTER(Options), P, P]
         L.lsrn_server_create.argtypes = [I64, I32, C.POINTER(C.c_void_p)]
         L.lsrn_server_submit_dense.argtypes = [P, I64, I64, P, I64, I32, P, P, C.POINTER(Options),
                                                C.POINTER(C.c_int64)]
@@ -414,3 +416,31 @@ class Server:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def solve_batch(As, bs, xs=None, allow_not_converged: bool = False, **opts):
+    """lsrn_solve_batch over lists of row-major tall A (n <= 512) and b.
+    Returns (list of x, list of info dicts)."""
+    count = len(As)
+    if len(bs) != count:
+        raise ValueError("As and bs differ in length")
+    ms, ns, ldas = [], [], []
+    for A, b in zip(As, bs):
+        _dev_f64(A, "A")
+        _dev_f64(b, "b")
+        m, n, lda = _layout_dims(A, ROW_MAJOR)
+        if b.numel() != m or not b.is_contiguous():
+            raise ValueError("b must be contiguous with m entries")
+        ms.append(m); ns.append(n); ldas.append(lda)
+    if xs is None:
+        xs = [torch.empty(n, dtype=torch.float64, device=A.device) for A, n in zip(As, ns)]
+    I64A = C.c_int64 * max(count, 1)
+    PA = C.c_void_p * max(count, 1)
+    o = options(**opts)
+    infos = (Info * max(count, 1))()
+    st = lib().lsrn_solve_batch(count, I64A(*ms), I64A(*ns), PA(*[A.data_ptr() for A in As]),
+                                I64A(*ldas), PA(*[b.data_ptr() for b in bs]),
+                                PA(*[x.data_ptr() for x in xs]), C.byref(o), infos, _stream())
+    if not (allow_not_converged and st == 4):
+        _check(st)
+    return xs, [infos[i].as_dict() for i in range(count)]

@@ -1,0 +1,70 @@
+"""Batched LSQR (lsrn_solve_batch): many small tall problems iterating in
+shared launches give the solutions of solving them one by one."""
+import numpy as np
+import pytest
+
+import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1109_5981_amd import lsrn
+    lsrn.lib()  # raises if the library is missing: there is no CPU fallback
+    return lsrn
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def test_batch_matches_single_solves_and_oracle(L, orc):
+    rng = np.random.default_rng(5)
+    As, bs, refs = [], [], []
+    for i in range(24):
+        n = int(rng.integers(4, 513)) if i % 6 else 512
+        m = int(rng.integers(max(2 * n, 300), 9000))
+        P = workloads.dense_problem(m, n, smin=10.0 ** -rng.uniform(1, 4), seed=300 + i)
+        b = workloads.rhs_gauss(m, 300 + i)
+        As.append(dev(P.A)); bs.append(dev(b))
+        if i % 4 == 0:
+            refs.append((i, orc.lsrn_solve(orc.Matrix.dense(P.A), b, seed=1, refine=3).x))
+    # a zero matrix: rank 0, x = 0
+    As.append(torch.zeros(700, 30, dtype=torch.float64, device="cuda"))
+    bs.append(dev(np.ones(700)))
+    xs, infos = L.solve_batch(As, bs, seed=11)
+    for k, (A, b) in enumerate(zip(As[:-1], bs[:-1])):
+        x1, i1 = L.solve_dense(A, b, seed=11)
+        assert infos[k]["rank"] == i1["rank"]
+        assert abs(infos[k]["iters"] - i1["iters"]) <= 1
+        # same sketch and preconditioner; the sweeps sum in other orders
+        assert rel(host(xs[k]), host(x1)) < 1e-11
+    for i, xr in refs:
+        assert rel(host(xs[i]), xr) < 1e-9
+    assert infos[-1]["rank"] == 0 and np.all(host(xs[-1]) == 0.0)
+
+
+def test_batch_rejections(L):
+    P = workloads.dense_problem(500, 20, smin=1e-3, seed=6)
+    A, b = dev(P.A), dev(workloads.rhs_gauss(500, 6))
+    for bad in (dict(refine=1), dict(method="chebyshev"), dict(lam=0.1), dict(precision="mixed")):
+        with pytest.raises(L.LSRNError) as e:
+            L.solve_batch([A], [b], **bad)
+        assert e.value.status == 5
+    Pw = workloads.dense_problem(2000, 600, smin=1e-3, seed=7)
+    with pytest.raises(L.LSRNError) as e:
+        L.solve_batch([dev(Pw.A)], [dev(workloads.rhs_gauss(2000, 7))])
+    assert e.value.status == 1
