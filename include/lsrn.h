@@ -83,7 +83,7 @@ typedef enum { LSRN_PRECOND_AUTO = 0, LSRN_PRECOND_SVD = 1, LSRN_PRECOND_QR = 2 
  *     not remove.  Refinement stops when a correction is below 1e-15 ||x||
  *     or no longer half the previous one; the solve counts as converged
  *     (info->converged, else LSRN_E_NOT_CONVERGED with x the last iterate)
- *     when the last correction is below 1e-12 ||x||. */
+ *     when the last correction is below max(tol, 1e-12) ||x||. */
 typedef enum { LSRN_PREC_FP64 = 0, LSRN_PREC_MIXED = 1 } lsrn_precision;
 
 typedef struct lsrn_options {

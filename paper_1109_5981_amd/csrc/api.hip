@@ -249,7 +249,6 @@ lsrn_status solve_impl(bool tall, int64_t K, int64_t d, int64_t n, const TallVie
         if (mixed) {
             pb.T32 = T32.as<float>();
             lsrn_options om = opt;
-            om.tol = std::max(opt.tol, 1e-8);
             if (om.refine == 0) om.refine = 10;
             ir = iterate(pb, b, x, om, st);
         } else {

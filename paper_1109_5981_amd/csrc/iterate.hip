@@ -1426,7 +1426,10 @@ IterResult iterate_on(const IterProblem &pb, const double *b, double *x, const l
     if (pb.tall) {
         TallSolver ts(cx);
         ts.load_rhs(b);
-        res.iters = cs ? ts.cs(sl, su, opt.tol) : ts.lsqr(maxiter, opt.tol, conv);
+        // the precision form's main solve runs on fl32(A): no point in going
+        // below 1e-8 before the refinement
+        const double tol_main = pb.T32 ? std::max(opt.tol, 1e-8) : opt.tol;
+        res.iters = cs ? ts.cs(sl, su, opt.tol) : ts.lsqr(maxiter, tol_main, conv);
         ts.x_from_y(x);
         LSRN_HIP(hipEventRecord(e1, st));
         LSRN_HIP(hipStreamSynchronize(st));
@@ -1489,7 +1492,7 @@ IterResult iterate_on(const IterProblem &pb, const double *b, double *x, const l
                 // the precision form's main LSQR runs on fl32(A): its answer
                 // is settled by the refinement, whose last correction must
                 // have become negligible
-                if (pb.T32) conv = dn <= 1e-12 * xn;
+                if (pb.T32) conv = dn <= std::max(opt.tol, 1e-12) * xn;
                 // stop at convergence, or once the corrections stop shrinking
                 // (the floor of the inner arithmetic is reached)
                 if (dn <= 1e-15 * xn || (step > 0 && dn > 0.5 * dn_prev)) break;

@@ -112,6 +112,28 @@ def dense_problem_device(m: int, n: int, rank: int | None = None, smin: float = 
     return A, U, sigma, V
 
 
+def reflected_problem_device(m: int, n: int, cond: float, seed: int, device="cuda",
+                             reflectors: int = 4):
+    """An m x n (m >= n) matrix with singular values log-spaced from 1 to
+    1/cond, built in O(m n): A = H_1 ... H_k [Sigma V^T; 0] with V Haar (n x n)
+    and H_i = I - 2 u_i u_i^T for random unit u_i.  The cheap generator of the
+    serving workload (a request's matrix is made when it arrives)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    Z = torch.randn(n, n, generator=g, dtype=torch.float64, device=device)
+    Q, R = torch.linalg.qr(Z)
+    V = Q * torch.sign(torch.diagonal(R))
+    sigma = torch.logspace(0.0, -float(np.log10(cond)), n, dtype=torch.float64, device=device)
+    A = torch.zeros(m, n, dtype=torch.float64, device=device)
+    A[:n] = sigma[:, None] * V.T
+    for _ in range(reflectors):
+        u = torch.randn(m, generator=g, dtype=torch.float64, device=device)
+        u /= torch.linalg.norm(u)
+        A -= 2.0 * torch.outer(u, u @ A)
+    return A
+
+
 def matvec_device(A, x, trans: bool = False):
     """A x (or A^T x) in row chunks."""
     import torch
