@@ -301,133 +301,6 @@ jacobi_small_kernel(double *__restrict__ Y, int d, int max_sweeps, double tol,
     if (tid == 0) *sweeps_out = sweep + 1;
 }
 
-// One round of the block round robin: workgroup k takes column blocks
-// (bi, bj) of width BW into LDS, rotates every pair among those 2 BW
-// columns (round robin on 2 BW players) and writes them back.  The BW pairs of a sub-round are spread over the 8 waves: WPP waves per
-// pair (each owning a contiguous segment of the rows) when BW < 8, PPW
-// pairs per wave when BW > 8.  A pair's three inner products are summed
-// over its waves through LDS in a fixed order.  d <= 512 EPU and
-// ceil(d / WPP) <= 64 EPL.
-template <int BW, int EPU, int EPL>
-__global__ void __launch_bounds__(512)
-jacobi_round_kernel(double *__restrict__ Y, int d, int nblocks, int round, double tol,
-                    int *__restrict__ rot_count) {
-    extern __shared__ double W[];  // 2*BW columns of length d
-    constexpr int NLOC = 2 * BW;
-    constexpr int WPP = BW >= 8 ? 1 : 8 / BW;   // waves per pair
-    constexpr int PPW = BW > 8 ? BW / 8 : 1;    // pairs per wave
-    __shared__ double part[BW][WPP][3];
-    const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
-    int bi, bj;
-    rr_pair(nblocks, round, blockIdx.x, bi, bj);
-    {
-        double reg[NLOC][EPU];
-#pragma unroll
-        for (int cl = 0; cl < NLOC; ++cl) {
-            const int64_t col = (int64_t)(cl < BW ? bi : bj) * BW + (cl % BW);
-            const double *src = Y + col * d;
-#pragma unroll
-            for (int u = 0; u < EPU; ++u) {
-                const int i = tid + 512 * u;
-                reg[cl][u] = i < d ? src[i] : 0.0;
-            }
-        }
-#pragma unroll
-        for (int cl = 0; cl < NLOC; ++cl)
-#pragma unroll
-            for (int u = 0; u < EPU; ++u) {
-                const int i = tid + 512 * u;
-                if (i < d) W[cl * d + i] = reg[cl][u];
-            }
-    }
-    __syncthreads();
-    const int seg = (d + WPP - 1) / WPP;
-    const int gw = wid % WPP;                   // wave index inside its pair group
-    const int r0 = gw * seg, r1 = min(d, r0 + seg);
-    int mine = 0;
-    for (int sub = 0; sub < NLOC - 1; ++sub) {
-#pragma unroll
-        for (int h = 0; h < PPW; ++h) {
-            const int k = (WPP > 1) ? wid / WPP : wid * PPW + h;
-            int p, q;
-            rr_pair(NLOC, sub, k, p, q);
-            const int gp = (p < BW ? bi : bj) * BW + (p % BW);
-            const int gq = (q < BW ? bi : bj) * BW + (q % BW);
-            if (gp > gq) { const int tmp = p; p = q; q = tmp; }
-            double *wp = W + p * d, *wq = W + q * d;
-            double xp[EPL], xq[EPL];
-            double a = 0.0, b = 0.0, g = 0.0;
-#pragma unroll
-            for (int u = 0; u < EPL; ++u) {
-                const int i = r0 + lane + 64 * u;
-                xp[u] = i < r1 ? wp[i] : 0.0;
-                xq[u] = i < r1 ? wq[i] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < EPL; ++u) {
-                a += xp[u] * xp[u];
-                b += xq[u] * xq[u];
-                g += xp[u] * xq[u];
-            }
-            a = wave_sum(a);
-            b = wave_sum(b);
-            g = wave_sum(g);
-            if (WPP > 1) {
-                if (lane == 0) {
-                    part[k][gw][0] = a;
-                    part[k][gw][1] = b;
-                    part[k][gw][2] = g;
-                }
-                __syncthreads();
-                a = b = g = 0.0;
-#pragma unroll
-                for (int w = 0; w < WPP; ++w) {
-                    a += part[k][w][0];
-                    b += part[k][w][1];
-                    g += part[k][w][2];
-                }
-            }
-            if (g != 0.0 && fabs(g) > tol * sqrt(a) * sqrt(b)) {
-                const double zeta = (b - a) / (2.0 * g);
-                const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
-                const double c = 1.0 / sqrt(1.0 + t * t);
-                const double sn = c * t;
-#pragma unroll
-                for (int u = 0; u < EPL; ++u) {
-                    const int i = r0 + lane + 64 * u;
-                    if (i < r1) {
-                        wp[i] = c * xp[u] - sn * xq[u];
-                        wq[i] = sn * xp[u] + c * xq[u];
-                    }
-                }
-                if (gw == 0) ++mine;
-            }
-        }
-        __syncthreads();
-    }
-    {
-        double reg[NLOC][EPU];
-#pragma unroll
-        for (int cl = 0; cl < NLOC; ++cl)
-#pragma unroll
-            for (int u = 0; u < EPU; ++u) {
-                const int i = tid + 512 * u;
-                reg[cl][u] = i < d ? W[cl * d + i] : 0.0;
-            }
-#pragma unroll
-        for (int cl = 0; cl < NLOC; ++cl) {
-            const int64_t col = (int64_t)(cl < BW ? bi : bj) * BW + (cl % BW);
-            double *dst = Y + col * d;
-#pragma unroll
-            for (int u = 0; u < EPU; ++u) {
-                const int i = tid + 512 * u;
-                if (i < d) dst[i] = reg[cl][u];
-            }
-        }
-    }
-    if (lane == 0 && mine) atomicAdd(rot_count, mine);
-}
-
 // Compile-time round-robin pair (same schedule as rr_pair).
 template <int N, int T, int K>
 struct RR {
@@ -475,37 +348,89 @@ constexpr int pow2_at_least() {
     return p;
 }
 
-// One round of the block round robin with the 2 BW columns of a block pair
-// held in registers: thread t owns rows t + 512 u (u < EPU) of every column.
-// Per sub-round the 3 BW inner products of its BW disjoint pairs are reduced
-// together (one butterfly per wave, one LDS pass across the 8 waves), the
-// rotation of pair k is computed once by thread k and broadcast through LDS.
-// d <= 512 EPU; 3 BW <= 32.
+// Packed index of Gram entry (p, q), p <= q, row by row.
+template <int NL>
+__host__ __device__ constexpr int gram_index(int p, int q) {
+    return p * NL - p * (p - 1) / 2 + (q - p);
+}
+
+// 1 / sqrt(x) and 1 / x for normal x > 0 from the hardware estimates; each
+// Newton step roughly squares the relative error.
+template <int STEPS = 1>
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int k = 0; k < STEPS; ++k) y = y * fma(-0.5 * x * y, y, 1.5);
+    return y;
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+    const double y = __builtin_amdgcn_rcp(x);
+    return y * fma(-x, y, 2.0);
+}
+
+// Rotation of the pair (p, q) from its Gram entries a = |x_p|^2,
+// b = |x_q|^2, g = x_p . x_q (Golub & Van Loan Sec. 8.6): x_p <- c x_p - s x_q,
+// x_q <- s x_p + c x_q makes the pair orthogonal.  False (c = 1, s = 0) when
+// |g| <= tol sqrt(a b).  Only c^2 + s^2 = 1 has to hold to rounding (c from
+// t by a refined reciprocal square root); the threshold test and the angle
+// itself may carry a few ulp.
+__device__ __forceinline__ bool jacobi_angle(double a, double b, double g, double tol, double &c,
+                                             double &s) {
+    c = 1.0;
+    s = 0.0;
+    if (!(g != 0.0 && fabs(g) * rsqrt_nr(a) * rsqrt_nr(b) > tol)) return false;
+    const double zeta = (b - a) * rcp_nr(2.0 * g);
+    const double az = fabs(zeta);
+    // 1 / (|zeta| + sqrt(1 + zeta^2)), without overflow for huge |zeta|
+    const double den = az < 1e150 ? az + (1.0 + az * az) * rsqrt_nr(1.0 + az * az) : 2.0 * az;
+    const double t = copysign(rcp_nr(den), zeta);
+    c = rsqrt_nr<2>(fma(t, t, 1.0));
+    s = c * t;
+    return true;
+}
+
+// One round of the block round robin, Gram form.  The 2 BW columns of the
+// block pair stay in registers (thread t owns rows t + 512 u, u < EPU).
+// Their 2 BW x 2 BW Gram matrix G is reduced once; the 2 BW - 1 sub-rounds
+// of rotations are then carried out on G itself, every thread owning one
+// entry of G and of the accumulated rotation J (G <- R^T G R, J <- J R per
+// sub-round, through LDS), and the columns are replaced by x J in a single
+// pass.  Each angle follows the one-sided (Hestenes) formula from the
+// current Gram entries.  The first sub-round tests exact inner products of
+// the columns and a sub-round without rotations leaves G and J bit for bit
+// unchanged (c = 1, s = 0), so "no rotation in the round" is the same exact
+// convergence test as rotating column by column.
 //
 // last_mod[b] is the global round index (sweep * (nblocks - 1) + round) at
 // which a column of block b was last rotated.  Two blocks meet once per
 // sweep; if neither changed since their previous meeting (period rounds
 // ago) then no rotation happened there and none can happen now, so the
 // workgroup returns at once -- an exact shortcut for the converging sweeps.
+// d <= 512 EPU.
 template <int BW, int EPU>
 __global__ void __launch_bounds__(512)
-jacobi_reg_round_kernel(double *__restrict__ Y, int d, int nblocks, int round, double tol,
-                        int *__restrict__ rot_count, int *__restrict__ last_mod, int rnow) {
-    constexpr int NLOC = 2 * BW;
-    constexpr int NV = pow2_at_least<3 * BW>();
-    static_assert(NV <= 32, "three inner products per pair must fit one butterfly");
-    __shared__ double part[8][33];
-    __shared__ double rot[BW][2];
-    __shared__ int nrot;
+jacobi_gram_round_kernel(double *__restrict__ Y, int d, int nblocks, int round, double tol,
+                         int *__restrict__ rot_count, int *__restrict__ last_mod, int rnow) {
+    constexpr int NL = 2 * BW;
+    constexpr int NG = NL * (NL + 1) / 2;
+    constexpr int NFULL = NG / 32;                        // 32-value reduction chunks
+    constexpr int NREST = NG - 32 * NFULL;                // values of the last chunk
+    constexpr int NVREST = NREST ? pow2_at_least<NREST>() : 1;
+    static_assert(NL * NL <= 512, "one thread per Gram entry");
+    __shared__ double part[8][32 * NFULL + NVREST];
+    __shared__ double Gs[2][NL][NL + 1], Js[2][NL][NL + 1];
+    __shared__ int nrot_s;
     const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
     int bi, bj;
     rr_pair(nblocks, round, blockIdx.x, bi, bj);
     const int prev = rnow - (nblocks - 1);
     if (prev >= 0 && last_mod[bi] < prev && last_mod[bj] < prev) return;
-    double x[NLOC][EPU];
+    // local column order follows the global one: block min(bi, bj) first
+    const int blo = bi < bj ? bi : bj, bhi = bi < bj ? bj : bi;
+    double x[NL][EPU];
 #pragma unroll
-    for (int cl = 0; cl < NLOC; ++cl) {
-        const int64_t col = (int64_t)(cl < BW ? bi : bj) * BW + (cl % BW);
+    for (int cl = 0; cl < NL; ++cl) {
+        const int64_t col = (int64_t)(cl < BW ? blo : bhi) * BW + (cl % BW);
         const double *src = Y + col * d;
 #pragma unroll
         for (int u = 0; u < EPU; ++u) {
@@ -513,95 +438,106 @@ jacobi_reg_round_kernel(double *__restrict__ Y, int d, int nblocks, int round, d
             x[cl][u] = i < d ? src[i] : 0.0;
         }
     }
-    if (tid == 0) nrot = 0;
-    // pairs with gp > gq are swapped so the global column order is kept
-    const bool swap_cross = bi > bj;
-    auto sub_round = [&](auto tsub) {
-        constexpr int TS = decltype(tsub)::value;
+    if (tid == 0) nrot_s = 0;
+    // ---- Gram matrix: per-thread partial sums, reduced in chunks of <= 32
+    // values per butterfly, then across the 8 wavefronts
+    auto chunk = [&](auto cidx, auto nv) {
+        constexpr int C = decltype(cidx)::value, NV = decltype(nv)::value;
         double v[NV];
 #pragma unroll
         for (int j = 0; j < NV; ++j) v[j] = 0.0;
-        // partial inner products of the BW pairs
-        [&]<int... K>(std::integer_sequence<int, K...>) {
-            ((
-                 [&] {
-                     constexpr int p0 = RR<NLOC, TS, K>::p, q0 = RR<NLOC, TS, K>::q;
-                     const bool cross = (p0 < BW) != (q0 < BW);
-                     const bool sw = cross && swap_cross;
-                     double a = 0.0, b = 0.0, g = 0.0;
 #pragma unroll
-                     for (int u = 0; u < EPU; ++u) {
-                         const double xp = sw ? x[q0][u] : x[p0][u];
-                         const double xq = sw ? x[p0][u] : x[q0][u];
-                         a += xp * xp;
-                         b += xq * xq;
-                         g += xp * xq;
-                     }
-                     v[3 * K] = a;
-                     v[3 * K + 1] = b;
-                     v[3 * K + 2] = g;
-                 }()),
-             ...);
-        }(std::make_integer_sequence<int, BW>{});
+        for (int p = 0; p < NL; ++p)
+#pragma unroll
+            for (int q = p; q < NL; ++q) {
+                const int k = gram_index<NL>(p, q) - 32 * C;
+                if (k >= 0 && k < NV) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int u = 0; u < EPU; ++u) t += x[p][u] * x[q][u];
+                    v[k] = t;
+                }
+            }
         const double tot = wave_reduce_n<NV>(v);
-        if ((lane & 1) == 0 && (lane >> 1) < 3 * BW) part[wid][lane >> 1] = tot;
-        __syncthreads();
-        if (tid < BW) {
-            double a = 0.0, b = 0.0, g = 0.0;
+        if ((lane & 1) == 0 && (lane >> 1) < NV) part[wid][32 * C + (lane >> 1)] = tot;
+    };
+    [&]<int... C>(std::integer_sequence<int, C...>) {
+        (chunk(std::integral_constant<int, C>{}, std::integral_constant<int, 32>{}), ...);
+    }(std::make_integer_sequence<int, NFULL>{});
+    if constexpr (NREST > 0)
+        chunk(std::integral_constant<int, NFULL>{}, std::integral_constant<int, NVREST>{});
+    __syncthreads();
+    // thread t < NL^2 owns entry (r, c) of G and J
+    const bool owner = tid < NL * NL;
+    const int r = owner ? tid / NL : 0, c = owner ? tid % NL : 0;
+    double gv = 0.0, jv = 0.0;
+    if (owner) {
+        const int k = r <= c ? gram_index<NL>(r, c) : gram_index<NL>(c, r);
 #pragma unroll
-            for (int w = 0; w < 8; ++w) {
-                a += part[w][3 * tid];
-                b += part[w][3 * tid + 1];
-                g += part[w][3 * tid + 2];
-            }
-            double c = 1.0, sn = 0.0;
-            if (g != 0.0 && fabs(g) > tol * sqrt(a) * sqrt(b)) {
-                const double zeta = (b - a) / (2.0 * g);
-                const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
-                c = 1.0 / sqrt(1.0 + t * t);
-                sn = c * t;
-                atomicAdd(&nrot, 1);
-            }
-            rot[tid][0] = c;
-            rot[tid][1] = sn;
+        for (int w = 0; w < 8; ++w) gv += part[w][k];
+        jv = r == c ? 1.0 : 0.0;
+        Gs[0][r][c] = gv;
+        Js[0][r][c] = jv;
+    }
+    __syncthreads();
+    int mine = 0;
+    auto sub_round = [&](auto tsub) {
+        constexpr int TS = decltype(tsub)::value, CUR = TS & 1;
+        if (owner) {
+            // partners of r and c in this sub-round of the round robin
+            auto partner = [](int i) {
+                if (i == NL - 1) return TS;
+                if (i == TS) return NL - 1;
+                return (2 * TS - i + 2 * (NL - 1)) % (NL - 1);
+            };
+            const int r2 = partner(r), c2 = partner(c);
+            const int rp = r < r2 ? r : r2, rq = r < r2 ? r2 : r;
+            const int cp = c < c2 ? c : c2, cq = c < c2 ? c2 : c;
+            double cr, sr, cc, sc;
+            const bool rot_r = jacobi_angle(Gs[CUR][rp][rp], Gs[CUR][rq][rq], Gs[CUR][rp][rq], tol, cr, sr);
+            jacobi_angle(Gs[CUR][cp][cp], Gs[CUR][cq][cq], Gs[CUR][cp][cq], tol, cc, sc);
+            if (rot_r && r == rp && c == rq) ++mine;  // each pair counted once
+            // new column x = alpha x_own + beta x_partner
+            const double ar = cr, br = r == rp ? -sr : sr;
+            const double ac = cc, bc = c == cp ? -sc : sc;
+            const double g_rc2 = Gs[CUR][r][c2], g_r2c = Gs[CUR][r2][c], g_r2c2 = Gs[CUR][r2][c2];
+            const double j_rc2 = Js[CUR][r][c2];
+            gv = ar * (ac * gv + bc * g_rc2) + br * (ac * g_r2c + bc * g_r2c2);
+            jv = ac * jv + bc * j_rc2;
+            Gs[CUR ^ 1][r][c] = gv;
+            Js[CUR ^ 1][r][c] = jv;
         }
         __syncthreads();
-        [&]<int... K>(std::integer_sequence<int, K...>) {
-            ((
-                 [&] {
-                     constexpr int p0 = RR<NLOC, TS, K>::p, q0 = RR<NLOC, TS, K>::q;
-                     const bool cross = (p0 < BW) != (q0 < BW);
-                     const bool sw = cross && swap_cross;
-                     const double c = rot[K][0], sn = rot[K][1];
-                     if (sn != 0.0) {
-#pragma unroll
-                         for (int u = 0; u < EPU; ++u) {
-                             const double xp = sw ? x[q0][u] : x[p0][u];
-                             const double xq = sw ? x[p0][u] : x[q0][u];
-                             const double np = c * xp - sn * xq, nq = sn * xp + c * xq;
-                             if (sw) { x[q0][u] = np; x[p0][u] = nq; }
-                             else { x[p0][u] = np; x[q0][u] = nq; }
-                         }
-                     }
-                 }()),
-             ...);
-        }(std::make_integer_sequence<int, BW>{});
     };
     [&]<int... TS>(std::integer_sequence<int, TS...>) {
         (sub_round(std::integral_constant<int, TS>{}), ...);
-    }(std::make_integer_sequence<int, NLOC - 1>{});
+    }(std::make_integer_sequence<int, NL - 1>{});
+    if (mine) atomicAdd(&nrot_s, mine);
+    __syncthreads();
+    const int nrot = nrot_s;
+    if (nrot == 0) return;
+    constexpr int FIN = (NL - 1) & 1;  // buffer written by the last sub-round
+    // ---- columns <- x J, written straight back
 #pragma unroll
-    for (int cl = 0; cl < NLOC; ++cl) {
-        const int64_t col = (int64_t)(cl < BW ? bi : bj) * BW + (cl % BW);
+    for (int q = 0; q < NL; ++q) {
+        double acc[EPU];
+#pragma unroll
+        for (int u = 0; u < EPU; ++u) acc[u] = 0.0;
+#pragma unroll
+        for (int p = 0; p < NL; ++p) {
+            const double jpq = Js[FIN][p][q];
+#pragma unroll
+            for (int u = 0; u < EPU; ++u) acc[u] += x[p][u] * jpq;
+        }
+        const int64_t col = (int64_t)(q < BW ? blo : bhi) * BW + (q % BW);
         double *dst = Y + col * d;
 #pragma unroll
         for (int u = 0; u < EPU; ++u) {
             const int i = tid + 512 * u;
-            if (i < d) dst[i] = x[cl][u];
+            if (i < d) dst[i] = acc[u];
         }
     }
-    __syncthreads();
-    if (tid == 0 && nrot) {
+    if (tid == 0) {
         atomicAdd(rot_count, nrot);
         last_mod[bi] = rnow;
         last_mod[bj] = rnow;
@@ -732,8 +668,9 @@ PrecondResult precond(int64_t s, int64_t d, double *X, double rcond, double *sig
     const double tol = (double)d * DBL_EPSILON;
     const int max_sweeps = 60;
     const size_t lds = lds_limit();
-    // column-block width and rows per thread of the register round kernel
-    static const int kBW[] = {8, 8, 4, 2, 1}, kDMAX[] = {512, 1024, 2048, 4096, 8192};
+    // column-block width and rows per thread of the Gram round kernel: the
+    // widest block whose 2 BW register columns fit next to the reduction
+    static const int kBW[] = {8, 8, 8, 4, 2}, kDMAX[] = {512, 1024, 2048, 4096, 8192};
     int variant = -1;
     for (int v = 0; v < 5 && variant < 0; ++v)
         if (d <= kDMAX[v]) variant = v;
@@ -764,9 +701,9 @@ PrecondResult precond(int64_t s, int64_t d, double *X, double rcond, double *sig
         res.sweeps = sw;
     } else {
         typedef void (*RoundFn)(double *, int, int, int, double, int *, int *, int);
-        static const RoundFn kFn[] = {jacobi_reg_round_kernel<8, 1>, jacobi_reg_round_kernel<8, 2>,
-                                      jacobi_reg_round_kernel<4, 4>, jacobi_reg_round_kernel<2, 8>,
-                                      jacobi_reg_round_kernel<1, 16>};
+        static const RoundFn kFn[] = {jacobi_gram_round_kernel<8, 1>, jacobi_gram_round_kernel<8, 2>,
+                                      jacobi_gram_round_kernel<8, 4>, jacobi_gram_round_kernel<4, 8>,
+                                      jacobi_gram_round_kernel<2, 16>};
         const RoundFn fn = kFn[variant];
         DevBuf lastb((size_t)nblocks * sizeof(int));
         int *last_mod = lastb.as<int>();

@@ -135,6 +135,32 @@ def test_precond_wide_variants_against_lapack(L, d, rank):
     assert np.linalg.norm(C - np.eye(rank), 2) <= 1e-6
 
 
+@pytest.mark.parametrize("d,rank", [(2500, 2400), (4500, 4500)])
+def test_precond_large_variants_against_lapack(L, d, rank):
+    """The two widest Jacobi round kernels (4 and 2 columns per block);
+    LAPACK's singular values of the same sketch are the reference.  With
+    kappa = 1e3 the FP64 product X N is accurate to ~d eps kappa, far below
+    the 1e-6 bound, so no extended precision is needed."""
+    s = 2 * d
+    A, _, _, _ = workloads.dense_problem_device(3 * s, d, rank=rank, smin=1e-3, seed=d)
+    Xcm = L.sketch_dense(A, s, seed=3)
+    del A
+    X = host(Xcm).T
+    r, sig, N, sweeps = L.precond(Xcm)
+    sig, N = host(sig), host(N)
+    ref = np.linalg.svd(X, compute_uv=False)
+    assert r == rank and 0 < sweeps < 40
+    eps = np.finfo(float).eps
+    np.testing.assert_allclose(sig[:rank], ref[:rank], rtol=0, atol=4 * d * eps * ref[0])
+    Q = X @ N
+    assert np.linalg.norm(Q.T @ Q - np.eye(rank), 2) <= 1e-6
+    # N = V Sigma^-1: the rescaled columns are orthonormal up to the stopping
+    # rule, which leaves every off-diagonal cosine below d eps, so the d x d
+    # deviation has norm at most d * d eps
+    V = N * sig[:rank]
+    assert np.linalg.norm(V.T @ V - np.eye(rank), 2) <= d * d * eps
+
+
 # ---------------------------------------------------------------- steps 6-7
 
 @pytest.mark.parametrize("method", [0, 1])
