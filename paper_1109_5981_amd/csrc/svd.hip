@@ -418,8 +418,8 @@ jacobi_gram_round_kernel(double *__restrict__ Y, int d, int nblocks, int round, 
     constexpr int NVREST = NREST ? pow2_at_least<NREST>() : 1;
     static_assert(NL * NL <= 512, "one thread per Gram entry");
     __shared__ double part[8][32 * NFULL + NVREST];
-    __shared__ double Gs[2][NL][NL + 1], Js[2][NL][NL + 1];
-    __shared__ int nrot_s;
+    __shared__ double Gs[2][NL][NL + 1], Js[2][NL][NL + 1], CSs[BW][2];
+    __shared__ int nrot_s, any_s[NL];
     const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
     int bi, bj;
     rr_pair(nblocks, round, blockIdx.x, bi, bj);
@@ -439,6 +439,7 @@ jacobi_gram_round_kernel(double *__restrict__ Y, int d, int nblocks, int round, 
         }
     }
     if (tid == 0) nrot_s = 0;
+    if (tid < NL) any_s[tid] = 0;
     // ---- Gram matrix: per-thread partial sums, reduced in chunks of <= 32
     // values per butterfly, then across the 8 wavefronts
     auto chunk = [&](auto cidx, auto nv) {
@@ -480,33 +481,50 @@ jacobi_gram_round_kernel(double *__restrict__ Y, int d, int nblocks, int round, 
         Js[0][r][c] = jv;
     }
     __syncthreads();
-    int mine = 0;
+    int mine = 0, cur = 0;
     auto sub_round = [&](auto tsub) {
-        constexpr int TS = decltype(tsub)::value, CUR = TS & 1;
+        constexpr int TS = decltype(tsub)::value;
+        // (a) the angle of pair k, once, by thread k
+        if (tid < BW) {
+            const int k = tid;
+            const int a = k == 0 ? NL - 1 : (TS + k) % (NL - 1);
+            const int b = k == 0 ? TS : (TS - k + (NL - 1)) % (NL - 1);
+            const int pp = a < b ? a : b, qq = a < b ? b : a;
+            double cs, sn;
+            if (jacobi_angle(Gs[cur][pp][pp], Gs[cur][qq][qq], Gs[cur][pp][qq], tol, cs, sn)) {
+                ++mine;
+                any_s[TS] = 1;
+            }
+            CSs[k][0] = cs;
+            CSs[k][1] = sn;
+        }
+        __syncthreads();
+        if (!any_s[TS]) return;  // uniform: G and J stay as they are
+        // (b) G <- R^T G R and J <- J R entry by entry
         if (owner) {
-            // partners of r and c in this sub-round of the round robin
+            // partner of i in this sub-round and the index of their pair
             auto partner = [](int i) {
                 if (i == NL - 1) return TS;
                 if (i == TS) return NL - 1;
                 return (2 * TS - i + 2 * (NL - 1)) % (NL - 1);
             };
-            const int r2 = partner(r), c2 = partner(c);
-            const int rp = r < r2 ? r : r2, rq = r < r2 ? r2 : r;
-            const int cp = c < c2 ? c : c2, cq = c < c2 ? c2 : c;
-            double cr, sr, cc, sc;
-            const bool rot_r = jacobi_angle(Gs[CUR][rp][rp], Gs[CUR][rq][rq], Gs[CUR][rp][rq], tol, cr, sr);
-            jacobi_angle(Gs[CUR][cp][cp], Gs[CUR][cq][cq], Gs[CUR][cp][cq], tol, cc, sc);
-            if (rot_r && r == rp && c == rq) ++mine;  // each pair counted once
+            auto pair_of = [](int i) {
+                if (i == NL - 1 || i == TS) return 0;
+                const int u = (i - TS + (NL - 1)) % (NL - 1), v = (TS - i + (NL - 1)) % (NL - 1);
+                return u < v ? u : v;
+            };
+            const int r2 = partner(r), c2 = partner(c), kr = pair_of(r), kc = pair_of(c);
             // new column x = alpha x_own + beta x_partner
-            const double ar = cr, br = r == rp ? -sr : sr;
-            const double ac = cc, bc = c == cp ? -sc : sc;
-            const double g_rc2 = Gs[CUR][r][c2], g_r2c = Gs[CUR][r2][c], g_r2c2 = Gs[CUR][r2][c2];
-            const double j_rc2 = Js[CUR][r][c2];
+            const double ar = CSs[kr][0], br = r < r2 ? -CSs[kr][1] : CSs[kr][1];
+            const double ac = CSs[kc][0], bc = c < c2 ? -CSs[kc][1] : CSs[kc][1];
+            const double g_rc2 = Gs[cur][r][c2], g_r2c = Gs[cur][r2][c], g_r2c2 = Gs[cur][r2][c2];
+            const double j_rc2 = Js[cur][r][c2];
             gv = ar * (ac * gv + bc * g_rc2) + br * (ac * g_r2c + bc * g_r2c2);
             jv = ac * jv + bc * j_rc2;
-            Gs[CUR ^ 1][r][c] = gv;
-            Js[CUR ^ 1][r][c] = jv;
+            Gs[cur ^ 1][r][c] = gv;
+            Js[cur ^ 1][r][c] = jv;
         }
+        cur ^= 1;
         __syncthreads();
     };
     [&]<int... TS>(std::integer_sequence<int, TS...>) {
@@ -516,7 +534,6 @@ jacobi_gram_round_kernel(double *__restrict__ Y, int d, int nblocks, int round, 
     __syncthreads();
     const int nrot = nrot_s;
     if (nrot == 0) return;
-    constexpr int FIN = (NL - 1) & 1;  // buffer written by the last sub-round
     // ---- columns <- x J, written straight back
 #pragma unroll
     for (int q = 0; q < NL; ++q) {
@@ -525,7 +542,7 @@ jacobi_gram_round_kernel(double *__restrict__ Y, int d, int nblocks, int round, 
         for (int u = 0; u < EPU; ++u) acc[u] = 0.0;
 #pragma unroll
         for (int p = 0; p < NL; ++p) {
-            const double jpq = Js[FIN][p][q];
+            const double jpq = Js[cur][p][q];
 #pragma unroll
             for (int u = 0; u < EPU; ++u) acc[u] += x[p][u] * jpq;
         }
