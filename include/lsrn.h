@@ -139,6 +139,9 @@ typedef struct lsrn_info {
      * sweep) and the number of round launches */
     double t_jacobi_kernel_ms;
     int64_t jacobi_kernels;
+    /* precision form: refinement steps whose sweeps read the FP64 A because
+     * the FP32 ones had stopped shrinking the corrections                   */
+    int64_t fp64_refine_steps;
 } lsrn_info;
 
 /* Fill *opt with the defaults listed above. */

@@ -182,6 +182,7 @@ void fill_iter_info(lsrn_info *info, int64_t s, int64_t d, int64_t r, bool tall,
     std::memset(info, 0, sizeof(*info));
     info->s = s; info->d = d; info->rank = r; info->iters = ir.iters;
     info->refine_steps = ir.refine_steps; info->refine_iters = ir.refine_iters;
+    info->fp64_refine_steps = ir.fp64_refine_steps;
     info->tall = tall; info->converged = ir.converged;
     info->sigma_l = ir.sigma_l; info->sigma_u = ir.sigma_u;
     info->t_iter_ms = ir.t_iter_ms; info->t_refine_ms = ir.t_refine_ms;
@@ -262,6 +263,7 @@ lsrn_status solve_impl(bool tall, int64_t K, int64_t d, int64_t n, const TallVie
         std::memset(info, 0, sizeof(*info));
         info->s = s; info->d = d; info->rank = pr.rank; info->iters = ir.iters;
         info->refine_steps = ir.refine_steps; info->refine_iters = ir.refine_iters;
+        info->fp64_refine_steps = ir.fp64_refine_steps;
         info->sweeps = pr.sweeps; info->tall = tall; info->converged = ir.converged;
         info->sigma_l = ir.sigma_l; info->sigma_u = ir.sigma_u;
         info->sigma_max = pr.sigma_max; info->sigma_min_kept = pr.sigma_min_kept;

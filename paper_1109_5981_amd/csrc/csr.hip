@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <vector>
 
 #include "common.hpp"
 #include "internal.hpp"
@@ -269,10 +270,37 @@ void make_sparse_view(SparseView &v, int64_t m, int64_t n, int64_t nnz, const in
     }
     v.rows = v.tall ? a : at;
     v.cols = v.tall ? at : a;
+    // segments of the column pass (host table from the d + 1 offsets)
+    {
+        const int64_t d = v.cols.nrows;
+        std::vector<int64_t> ptr((size_t)d + 1);
+        LSRN_HIP(hipMemcpyAsync(ptr.data(), v.cols.ptr, (size_t)(d + 1) * sizeof(int64_t),
+                                hipMemcpyDeviceToHost, st));
+        LSRN_HIP(hipStreamSynchronize(st));
+        std::vector<int32_t> rseg((size_t)d + 1), srow;
+        srow.reserve((size_t)d + (size_t)(nnz / SparseView::kColSeg) + 1);
+        for (int64_t j = 0; j < d; ++j) {
+            rseg[(size_t)j] = (int32_t)srow.size();
+            const int64_t len = ptr[(size_t)j + 1] - ptr[(size_t)j];
+            const int64_t ns = std::max<int64_t>(1, ceil_div(len, SparseView::kColSeg));
+            for (int64_t g = 0; g < ns; ++g) srow.push_back((int32_t)j);
+        }
+        rseg[(size_t)d] = (int32_t)srow.size();
+        v.nseg = (int64_t)srow.size();
+        v.seg_row.alloc(srow.size() * sizeof(int32_t));
+        v.row_seg.alloc(rseg.size() * sizeof(int32_t));
+        LSRN_HIP(hipMemcpyAsync(v.seg_row.as<int32_t>(), srow.data(), srow.size() * sizeof(int32_t),
+                                hipMemcpyHostToDevice, st));
+        LSRN_HIP(hipMemcpyAsync(v.row_seg.as<int32_t>(), rseg.data(), rseg.size() * sizeof(int32_t),
+                                hipMemcpyHostToDevice, st));
+        LSRN_HIP(hipStreamSynchronize(st));  // before the host tables go out of scope
+    }
 }
 
 size_t sparse_view_bytes(int64_t m, int64_t n, int64_t nnz) {
-    return (size_t)(n + 1) * 8 + (size_t)nnz * 12 + (size_t)nnz * 16 + (size_t)nnz * 8;
+    const int64_t d = std::min(m, n);
+    const size_t seg = (size_t)(d + 1 + nnz / SparseView::kColSeg + d) * 4;
+    return (size_t)(n + 1) * 8 + (size_t)nnz * 12 + (size_t)nnz * 16 + (size_t)nnz * 8 + seg;
 }
 
 void sketch_csr(const SparseView &v, double lambda, int64_t s, uint64_t seed, double *X,

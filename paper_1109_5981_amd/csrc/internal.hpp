@@ -63,6 +63,13 @@ struct SparseView {
     int64_t K = 0, d = 0, nnz = 0;
     CsrMat rows, cols;
     DevBuf tptr, tidx, tval;
+    // the rows of `cols` cut into segments of at most kColSeg entries, so a
+    // few long columns of T do not serialise the column pass: segment g
+    // belongs to row seg_row[g] of `cols`, whose segments start at
+    // row_seg[row] (d + 1 offsets)
+    static constexpr int64_t kColSeg = 512;
+    int64_t nseg = 0;
+    DevBuf seg_row, row_seg;
 };
 // Validates the structure (LSRN_E_INVALID on bad offsets or indices) and
 // builds the transposed copy.  Synchronises.
@@ -139,6 +146,7 @@ struct IterResult {
     int64_t iters = 0;
     int64_t refine_steps = 0;
     int64_t refine_iters = 0;
+    int64_t fp64_refine_steps = 0;  // precision form: steps whose sweeps read the FP64 A
     bool converged = true;
     double sigma_l = 0.0, sigma_u = 0.0;
     double t_iter_ms = 0.0, t_refine_ms = 0.0;

@@ -22,6 +22,7 @@
 #include <cfloat>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <vector>
 
 #include "internal.hpp"
@@ -889,19 +890,37 @@ __global__ void __launch_bounds__(CRP_NT) csr_row_pass_kernel(CsrArgs a) {
     }
 }
 
-// z_j = sum over column j of T of T(k, j) y_k (+ lambda y_{K+j}).
+// Column pass over segments: zseg_g = sum of T(k, j) y_k over segment g
+// (at most SparseView::kColSeg entries of column j of T), one wavefront per
+// segment.
 __global__ void __launch_bounds__(CCP_NT)
-csr_col_pass_kernel(CsrMat ct, const double *__restrict__ y, double lambda, int64_t K,
-                    double *__restrict__ z, const State *st) {
+csr_col_seg_kernel(CsrMat ct, const int32_t *__restrict__ seg_row,
+                   const int32_t *__restrict__ row_seg, int64_t nseg, const double *__restrict__ y,
+                   double *__restrict__ zseg, const State *st) {
     if (st && st->done) return;
-    const int64_t j = (int64_t)blockIdx.x * (CCP_NT / 64) + (threadIdx.x >> 6);
-    if (j >= ct.nrows) return;
+    const int64_t g = (int64_t)blockIdx.x * (CCP_NT / 64) + (threadIdx.x >> 6);
+    if (g >= nseg) return;
     const int lane = threadIdx.x & 63;
+    const int j = seg_row[g];
+    const int64_t e0 = ct.ptr[j] + (g - row_seg[j]) * SparseView::kColSeg;
+    const int64_t e1 = min(e0 + SparseView::kColSeg, ct.ptr[j + 1]);
     double t = 0.0;
-    const int64_t e0 = ct.ptr[j], e1 = ct.ptr[j + 1];
     for (int64_t e = e0 + lane; e < e1; e += 64) t += ct.val[e] * y[ct.idx[e]];
     t = wave_sum(t);
-    if (lane == 0) z[j] = lambda > 0.0 ? t + lambda * y[K + j] : t;
+    if (lane == 0) zseg[g] = t;
+}
+
+// z_j = the segments of column j summed in order (+ lambda y_{K+j}).
+__global__ void __launch_bounds__(256)
+csr_col_combine_kernel(const int32_t *__restrict__ row_seg, int64_t d,
+                       const double *__restrict__ zseg, const double *__restrict__ y, double lambda,
+                       int64_t K, double *__restrict__ z, const State *st) {
+    if (st && st->done) return;
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= d) return;
+    double t = 0.0;
+    for (int g = row_seg[j]; g < row_seg[j + 1]; ++g) t += zseg[g];
+    z[j] = lambda > 0.0 ? t + lambda * y[K + j] : t;
 }
 
 // st->acc = sums of the row-pass partials (fixed order).
@@ -984,11 +1003,14 @@ struct Ctx {
     int cpt, R;
     int ngroups, chunk;
     DevBuf zpart, spart, zred, sred, z, stbuf, Pt;
+    DevBuf zseg;  // sparse: per-segment column sums
     State *state;
     const double *Ptp;  // P^T, r x L row-major (ld L)
     // optional per-launch timing of the sweep kernel
     bool profile = false;
     std::vector<hipEvent_t> ev;
+    // precision form: sweeps read the FP64 T instead of its FP32 copy
+    bool force_f64 = false;
 
     ~Ctx() {
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
@@ -1019,6 +1041,7 @@ struct Ctx {
             ngroups = 1;
             spart.alloc((size_t)nblocks * 4 * sizeof(double));
             z.alloc((size_t)L * sizeof(double));
+            zseg.alloc((size_t)pb.sp->nseg * sizeof(double));
             stbuf.alloc(sizeof(State));
             state = stbuf.as<State>();
             Pt.alloc((size_t)std::max<int64_t>(pb.r, 1) * L * sizeof(double));
@@ -1080,7 +1103,8 @@ struct Ctx {
             return;
         }
         SweepArgs a;
-        a.T = pb.T; a.T32 = pb.T32; a.ldt = pb.ldt; a.rows = pb.rows; a.L = L; a.nblocks = nblocks;
+        a.T = pb.T; a.T32 = force_f64 ? nullptr : pb.T32; a.ldt = pb.ldt; a.rows = pb.rows; a.L = L;
+        a.nblocks = nblocks;
         a.rows_per_block = rows_per_block; a.w = w; a.zpart = zpart.as<double>();
         a.spart = spart.as<double>(); a.y = y; a.xv = xv; a.wv = wv; a.st = state;
         a.lambda = pb.tall ? pb.lambda : 0.0; a.alpha = alpha; a.beta = beta;
@@ -1131,8 +1155,12 @@ struct Ctx {
             case OP_LSQR_FAT: csr_row_pass_kernel<OP_LSQR_FAT><<<nblocks, CRP_NT, 0, st>>>(a); break;
             default: csr_row_pass_kernel<OP_CS_FAT><<<nblocks, CRP_NT, 0, st>>>(a); break;
         }
-        csr_col_pass_kernel<<<(unsigned)ceil_div(L, CCP_NT / 64), CCP_NT, 0, st>>>(
-            pb.sp->cols, y, pb.lambda, pb.rows, z.as<double>(), state);
+        csr_col_seg_kernel<<<(unsigned)ceil_div(pb.sp->nseg, CCP_NT / 64), CCP_NT, 0, st>>>(
+            pb.sp->cols, pb.sp->seg_row.as<int32_t>(), pb.sp->row_seg.as<int32_t>(), pb.sp->nseg, y,
+            zseg.as<double>(), state);
+        csr_col_combine_kernel<<<(unsigned)ceil_div(L, 256), 256, 0, st>>>(
+            pb.sp->row_seg.as<int32_t>(), L, zseg.as<double>(), y, pb.lambda, pb.rows, z.as<double>(),
+            state);
         LSRN_HIP(hipGetLastError());
         if (profile) LSRN_HIP(hipEventRecord(e1, st));
         reduce_spart_kernel<<<1, 256, 0, st>>>(spart.as<double>(), nblocks, state);
@@ -1445,7 +1473,11 @@ IterResult iterate_on(const IterProblem &pb, const double *b, double *x, const l
             DevBuf ybuf(pb.sp ? (size_t)(pb.rows + L) * sizeof(double) : 0);
             GraphExec cg_graph;  // the CG chunk keeps its buffers across refinement steps
             double dn_prev = 0.0;
-            for (int step = 0; step < opt.refine; ++step) {
+            // the precision form: once its FP32 sweeps stop shrinking the
+            // corrections (or the step budget is spent) the refinement goes on
+            // with sweeps over the FP64 A, a few steps more at most
+            int budget = opt.refine;
+            for (int step = 0; step < budget; ++step) {
                 if (pb.sp) {
                     // rows: res = b^ - T^ x (dd); columns: h = T^^T res (dd), rounded
                     csr_resid_rows_dd_kernel<<<cx.nblocks, CRP_NT, 0, st>>>(
@@ -1488,15 +1520,32 @@ IterResult iterate_on(const IterProblem &pb, const double *b, double *x, const l
                 axpby_kernel<<<grid1(L), 256, 0, st>>>(L, 1.0, dx.as<double>(), 1.0, x);
                 LSRN_HIP(hipGetLastError());
                 ++res.refine_steps;
+                if (cx.force_f64) ++res.fp64_refine_steps;
                 const double dn = host_norm(dx.as<double>(), L, st), xn = host_norm(x, L, st);
-                // the precision form's main LSQR runs on fl32(A): its answer
-                // is settled by the refinement, whose last correction must
-                // have become negligible
-                if (pb.T32) conv = dn <= std::max(opt.tol, 1e-12) * xn;
+                const bool stalled = step > 0 && dn > 0.5 * dn_prev;
+                dn_prev = dn;
+                if (pb.T32) {
+                    // the precision form's main LSQR runs on fl32(A): its
+                    // answer is settled by the refinement, whose last
+                    // correction must have become negligible
+                    conv = dn <= std::max(opt.tol, 1e-12) * xn;
+                    if (conv) break;
+                    if (!cx.force_f64 && (stalled || step + 1 == budget)) {
+                        cx.force_f64 = true;
+                        if (cg_graph.g) {
+                            LSRN_HIP(hipGraphExecDestroy(cg_graph.g));
+                            cg_graph.g = nullptr;
+                        }
+                        budget = step + 1 + 3;
+                        dn_prev = std::numeric_limits<double>::infinity();
+                        continue;
+                    }
+                    if (cx.force_f64 && stalled) break;
+                    continue;
+                }
                 // stop at convergence, or once the corrections stop shrinking
                 // (the floor of the inner arithmetic is reached)
-                if (dn <= 1e-15 * xn || (step > 0 && dn > 0.5 * dn_prev)) break;
-                dn_prev = dn;
+                if (dn <= 1e-15 * xn || stalled) break;
             }
         }
         LSRN_HIP(hipStreamSynchronize(st));  // before the solver's buffers are freed
