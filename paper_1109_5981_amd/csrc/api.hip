@@ -514,22 +514,30 @@ lsrn_status lsrn_solve_batch(int32_t count, const int64_t *m, const int64_t *n,
     std::vector<IterProblem> pbs((size_t)count);
     std::vector<const double *> bs((size_t)count);
     std::vector<double *> xs((size_t)count);
-    std::vector<DevBuf> Ps;
-    Ps.reserve((size_t)count);
+    std::vector<DevBuf> Ps((size_t)count), Xs((size_t)count), sigmas((size_t)count);
+    std::vector<double *> Xp((size_t)count), Pp((size_t)count), sp((size_t)count);
     std::vector<PrecondResult> prs((size_t)count);
     std::vector<int64_t> ss((size_t)count);
     for (int32_t p = 0; p < count; ++p) {
         const int64_t d = n[p];
         const int64_t s = (int64_t)std::ceil(opt.gamma * (double)d);
         ss[(size_t)p] = s;
-        DevBuf X((size_t)s * (size_t)d * sizeof(double)), sigma((size_t)d * sizeof(double));
-        sketch_rows(m[p], d, A[p], lda[p], 0.0, s, opt.seed, X.as<double>(), st);
-        Ps.emplace_back((size_t)d * (size_t)d * sizeof(double));
-        prs[(size_t)p] = precond(s, d, X.as<double>(), opt.rcond, sigma.as<double>(),
-                                 Ps.back().as<double>(), st);
+        Xs[(size_t)p].alloc((size_t)s * (size_t)d * sizeof(double));
+        sigmas[(size_t)p].alloc((size_t)d * sizeof(double));
+        Ps[(size_t)p].alloc((size_t)d * (size_t)d * sizeof(double));
+        Xp[(size_t)p] = Xs[(size_t)p].as<double>();
+        Pp[(size_t)p] = Ps[(size_t)p].as<double>();
+        sp[(size_t)p] = sigmas[(size_t)p].as<double>();
+        sketch_rows(m[p], d, A[p], lda[p], 0.0, s, opt.seed, Xp[(size_t)p], st);
+    }
+    precond_batch(count, ss.data(), n, Xp.data(), opt.rcond, sp.data(), Pp.data(), prs.data(), st);
+    Xs.clear();
+    sigmas.clear();
+    for (int32_t p = 0; p < count; ++p) {
+        const int64_t d = n[p];
         IterProblem &pb = pbs[(size_t)p];
         pb.tall = true; pb.rows = m[p]; pb.cols = d; pb.T = A[p]; pb.ldt = lda[p];
-        pb.P = Ps.back().as<double>(); pb.ldp = d; pb.r = prs[(size_t)p].rank; pb.s = s;
+        pb.P = Pp[(size_t)p]; pb.ldp = d; pb.r = prs[(size_t)p].rank; pb.s = ss[(size_t)p];
         bs[(size_t)p] = b[p];
         xs[(size_t)p] = x[p];
     }

@@ -94,6 +94,11 @@ struct PrecondResult {
 // hold V_r Sigma_r^{-1}); sigma: d values, descending.  Synchronises.
 PrecondResult precond(int64_t s, int64_t d, double *X, double rcond, double *sigma, double *P,
                       hipStream_t st, bool profile = false);
+// precond for `count` sketches at once: the QR of each, then the Jacobi
+// sweeps of all problems with d <= 512 in shared launches (wider ones one
+// at a time).  X[p] is overwritten.
+void precond_batch(int count, const int64_t *s, const int64_t *d, double *const *X, double rcond,
+                   double *const *sigma, double *const *P, PrecondResult *res, hipStream_t st);
 size_t precond_workspace_bytes(int64_t s, int64_t d);
 // Householder QR of X (s x d, column-major, in place; R in the upper
 // triangle).  Synchronises.

@@ -266,9 +266,8 @@ __device__ __forceinline__ int rotate_pair(double *wp, double *wq, int len, doub
 }
 
 // Whole matrix in LDS (d <= 128), all sweeps in one workgroup.
-__global__ void __launch_bounds__(1024)
-jacobi_small_kernel(double *__restrict__ Y, int d, int max_sweeps, double tol,
-                    int *__restrict__ sweeps_out) {
+__device__ __forceinline__ void jacobi_small(double *__restrict__ Y, int d, int max_sweeps,
+                                             double tol, int *__restrict__ sweeps_out) {
     extern __shared__ double W[];  // d * d, column p at W + p*d
     __shared__ int rot;
     const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
@@ -299,6 +298,12 @@ jacobi_small_kernel(double *__restrict__ Y, int d, int max_sweeps, double tol,
     }
     for (int t = tid; t < d * d; t += blockDim.x) Y[t] = W[t];
     if (tid == 0) *sweeps_out = sweep + 1;
+}
+
+__global__ void __launch_bounds__(1024)
+jacobi_small_kernel(double *__restrict__ Y, int d, int max_sweeps, double tol,
+                    int *__restrict__ sweeps_out) {
+    jacobi_small(Y, d, max_sweeps, tol, sweeps_out);
 }
 
 // Compile-time round-robin pair (same schedule as rr_pair).
@@ -408,9 +413,9 @@ __device__ __forceinline__ bool jacobi_angle(double a, double b, double g, doubl
 // workgroup returns at once -- an exact shortcut for the converging sweeps.
 // d <= 512 EPU.
 template <int BW, int EPU>
-__global__ void __launch_bounds__(512)
-jacobi_gram_round_kernel(double *__restrict__ Y, int d, int nblocks, int round, double tol,
-                         int *__restrict__ rot_count, int *__restrict__ last_mod, int rnow) {
+__device__ __forceinline__ void
+jacobi_gram_round(double *__restrict__ Y, int d, int nblocks, int round, int pair, double tol,
+                  int *__restrict__ rot_count, int *__restrict__ last_mod, int rnow) {
     constexpr int NL = 2 * BW;
     constexpr int NG = NL * (NL + 1) / 2;
     constexpr int NFULL = NG / 32;                        // 32-value reduction chunks
@@ -422,7 +427,7 @@ jacobi_gram_round_kernel(double *__restrict__ Y, int d, int nblocks, int round, 
     __shared__ int nrot_s, any_s[NL];
     const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
     int bi, bj;
-    rr_pair(nblocks, round, blockIdx.x, bi, bj);
+    rr_pair(nblocks, round, pair, bi, bj);
     const int prev = rnow - (nblocks - 1);
     if (prev >= 0 && last_mod[bi] < prev && last_mod[bj] < prev) return;
     // local column order follows the global one: block min(bi, bj) first
@@ -561,6 +566,53 @@ jacobi_gram_round_kernel(double *__restrict__ Y, int d, int nblocks, int round, 
     }
 }
 
+template <int BW, int EPU>
+__global__ void __launch_bounds__(512)
+jacobi_gram_round_kernel(double *__restrict__ Y, int d, int nblocks, int round, double tol,
+                         int *__restrict__ rot_count, int *__restrict__ last_mod, int rnow) {
+    jacobi_gram_round<BW, EPU>(Y, d, nblocks, round, blockIdx.x, tol, rot_count, last_mod, rnow);
+}
+
+// One problem of a batch for the batched Jacobi rounds.
+struct JacobiItem {
+    double *Y;
+    int d, nblocks;
+    double tol;
+    int *rot;       // rotations of the current sweep
+    int *last_mod;  // nblocks entries
+};
+
+// Round `round` of sweep `sweep` for every active problem of a batch: work
+// item g is pair g - pair_off[p] of problem p (pair_off: prefix sums of
+// nblocks / 2).  Problems whose own round count is smaller, or that have
+// converged (active[p] == 0), leave their work items empty.
+template <int BW, int EPU>
+__global__ void __launch_bounds__(512)
+jacobi_gram_round_batch_kernel(const JacobiItem *__restrict__ items, const int *__restrict__ pair_off,
+                               const int *__restrict__ active, int count, int round, int sweep) {
+    const int g = blockIdx.x;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pair_off[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    const JacobiItem it = items[lo];
+    const int period = it.nblocks - 1;
+    if (!active[lo] || round >= period) return;
+    jacobi_gram_round<BW, EPU>(it.Y, it.d, it.nblocks, round, g - pair_off[lo], it.tol, it.rot,
+                               it.last_mod, sweep * period + round);
+}
+
+// Whole sweeps of many small problems (d <= 128, the matrix in LDS), one
+// workgroup per problem: item p is problem p.
+__global__ void __launch_bounds__(1024)
+jacobi_small_batch_kernel(const JacobiItem *__restrict__ items, int max_sweeps,
+                          int *__restrict__ sweeps_out) {
+    const JacobiItem it = items[blockIdx.x];
+    jacobi_small(it.Y, it.d, max_sweeps, it.tol, sweeps_out + blockIdx.x);
+}
+
 // sigma_p = ||Y[:, p]||, one wavefront per column.
 __global__ void __launch_bounds__(256)
 col_norms_kernel(const double *__restrict__ Y, int64_t d, double *__restrict__ nrm) {
@@ -673,93 +725,103 @@ void householder_qr(int64_t s, int64_t d, double *X, hipStream_t st) {
     LSRN_HIP(hipStreamSynchronize(st));  // before the panel buffers are freed
 }
 
-PrecondResult precond(int64_t s, int64_t d, double *X, double rcond, double *sigma, double *P,
-                      hipStream_t st, bool profile) {
-    LSRN_REQUIRE(s >= d && d > 0, "precond: need s >= d > 0");
-    PrecondResult res;
+namespace {
 
-    // ---- Householder QR
-    householder_qr(s, d, X, st);
+constexpr int kJacobiMaxSweeps = 60;
 
-    // ---- Jacobi on Y = R^T
-    const double tol = (double)d * DBL_EPSILON;
-    const int max_sweeps = 60;
-    const size_t lds = lds_limit();
-    // column-block width and rows per thread of the Gram round kernel: the
-    // widest block whose 2 BW register columns fit next to the reduction
+// Which Jacobi kernel a d x d matrix Y = R^T uses, and its padded width:
+// the whole matrix in LDS for d <= 128, else the Gram round kernel with the
+// widest column block whose 2 BW register columns fit next to the
+// reduction.
+struct JacobiPlan {
+    bool small = false;
+    int variant = -1;  // index into the round-kernel tables
+    int64_t nblocks = 0, dcols = 0;
+};
+
+JacobiPlan jacobi_plan(int64_t d) {
     static const int kBW[] = {8, 8, 8, 4, 2}, kDMAX[] = {512, 1024, 2048, 4096, 8192};
-    int variant = -1;
-    for (int v = 0; v < 5 && variant < 0; ++v)
-        if (d <= kDMAX[v]) variant = v;
-    const int bw = variant >= 0 ? kBW[variant] : 1;
-    const bool small = (size_t)d * (size_t)d * sizeof(double) <= lds && d <= 128;
-    if (!small && variant < 0)
+    JacobiPlan pl;
+    for (int v = 0; v < 5 && pl.variant < 0; ++v)
+        if (d <= kDMAX[v]) pl.variant = v;
+    pl.small = (size_t)d * (size_t)d * sizeof(double) <= lds_limit() && d <= 128;
+    if (!pl.small && pl.variant < 0)
         fail(LSRN_E_UNSUPPORTED, "precond: the Jacobi kernels support min(m, n) <= 8192");
-    int64_t nblocks = ceil_div(d, bw);
-    nblocks += nblocks & 1;
-    const int64_t dcols = small ? d : nblocks * bw;
-    DevBuf Yb((size_t)d * (size_t)dcols * sizeof(double));
-    double *Y = Yb.as<double>();
-    r_to_y_kernel<<<grid1d(d * dcols), 256, 0, st>>>(X, s, d, dcols, Y);
-    LSRN_HIP(hipGetLastError());
+    const int bw = pl.variant >= 0 ? kBW[pl.variant] : 1;
+    pl.nblocks = ceil_div(d, bw);
+    pl.nblocks += pl.nblocks & 1;
+    pl.dcols = pl.small ? d : pl.nblocks * bw;
+    return pl;
+}
 
+void set_small_lds(size_t bytes, const void *fn) {
+    if (bytes > 65536)
+        LSRN_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+}
+
+// All sweeps of one problem; returns the sweep count.
+int64_t jacobi_single(double *Y, int64_t d, const JacobiPlan &pl, hipStream_t st, bool profile,
+                      PrecondResult &res) {
+    const double tol = (double)d * DBL_EPSILON;
     DevBuf cnt(2 * sizeof(int));
     int *dcnt = cnt.as<int>();
-    if (small) {
+    if (pl.small) {
         const size_t bytes = (size_t)d * d * sizeof(double);
-        if (bytes > 65536)
-            LSRN_HIP(hipFuncSetAttribute((const void *)jacobi_small_kernel,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-        jacobi_small_kernel<<<1, 1024, bytes, st>>>(Y, (int)d, max_sweeps, tol, dcnt);
+        set_small_lds(bytes, (const void *)jacobi_small_kernel);
+        jacobi_small_kernel<<<1, 1024, bytes, st>>>(Y, (int)d, kJacobiMaxSweeps, tol, dcnt);
         LSRN_HIP(hipGetLastError());
         int sw = 0;
         LSRN_HIP(hipMemcpyAsync(&sw, dcnt, sizeof(int), hipMemcpyDeviceToHost, st));
         LSRN_HIP(hipStreamSynchronize(st));
-        res.sweeps = sw;
-    } else {
-        typedef void (*RoundFn)(double *, int, int, int, double, int *, int *, int);
-        static const RoundFn kFn[] = {jacobi_gram_round_kernel<8, 1>, jacobi_gram_round_kernel<8, 2>,
-                                      jacobi_gram_round_kernel<8, 4>, jacobi_gram_round_kernel<4, 8>,
-                                      jacobi_gram_round_kernel<2, 16>};
-        const RoundFn fn = kFn[variant];
-        DevBuf lastb((size_t)nblocks * sizeof(int));
-        int *last_mod = lastb.as<int>();
-        LSRN_HIP(hipMemsetAsync(last_mod, 0, (size_t)nblocks * sizeof(int), st));
-        const int period = (int)nblocks - 1;
-        hipEvent_t ev[2] = {nullptr, nullptr};
-        if (profile) {
-            LSRN_HIP(hipEventCreate(&ev[0]));
-            LSRN_HIP(hipEventCreate(&ev[1]));
-        }
-        int sweep = 0;
-        for (; sweep < max_sweeps; ++sweep) {
-            LSRN_HIP(hipMemsetAsync(dcnt, 0, sizeof(int), st));
-            if (profile) LSRN_HIP(hipEventRecord(ev[0], st));
-            for (int round = 0; round < period; ++round) {
-                hipLaunchKernelGGL(fn, dim3((unsigned)(nblocks / 2)), dim3(512), 0, st, Y, (int)d,
-                                   (int)nblocks, round, tol, dcnt, last_mod, sweep * period + round);
-            }
-            LSRN_HIP(hipGetLastError());
-            if (profile) LSRN_HIP(hipEventRecord(ev[1], st));
-            int rot = 0;
-            LSRN_HIP(hipMemcpyAsync(&rot, dcnt, sizeof(int), hipMemcpyDeviceToHost, st));
-            LSRN_HIP(hipStreamSynchronize(st));
-            if (profile) {
-                float ms = 0.f;
-                LSRN_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
-                res.t_jacobi_kernel_ms += ms;
-                res.jacobi_kernels += period;
-            }
-            if (rot == 0) break;
-        }
-        if (profile) {
-            (void)hipEventDestroy(ev[0]);
-            (void)hipEventDestroy(ev[1]);
-        }
-        res.sweeps = sweep + 1;
+        return sw;
     }
+    typedef void (*RoundFn)(double *, int, int, int, double, int *, int *, int);
+    static const RoundFn kFn[] = {jacobi_gram_round_kernel<8, 1>, jacobi_gram_round_kernel<8, 2>,
+                                  jacobi_gram_round_kernel<8, 4>, jacobi_gram_round_kernel<4, 8>,
+                                  jacobi_gram_round_kernel<2, 16>};
+    const RoundFn fn = kFn[pl.variant];
+    const int64_t nblocks = pl.nblocks;
+    DevBuf lastb((size_t)nblocks * sizeof(int));
+    int *last_mod = lastb.as<int>();
+    LSRN_HIP(hipMemsetAsync(last_mod, 0, (size_t)nblocks * sizeof(int), st));
+    const int period = (int)nblocks - 1;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    if (profile) {
+        LSRN_HIP(hipEventCreate(&ev[0]));
+        LSRN_HIP(hipEventCreate(&ev[1]));
+    }
+    int sweep = 0;
+    for (; sweep < kJacobiMaxSweeps; ++sweep) {
+        LSRN_HIP(hipMemsetAsync(dcnt, 0, sizeof(int), st));
+        if (profile) LSRN_HIP(hipEventRecord(ev[0], st));
+        for (int round = 0; round < period; ++round) {
+            hipLaunchKernelGGL(fn, dim3((unsigned)(nblocks / 2)), dim3(512), 0, st, Y, (int)d,
+                               (int)nblocks, round, tol, dcnt, last_mod, sweep * period + round);
+        }
+        LSRN_HIP(hipGetLastError());
+        if (profile) LSRN_HIP(hipEventRecord(ev[1], st));
+        int rot = 0;
+        LSRN_HIP(hipMemcpyAsync(&rot, dcnt, sizeof(int), hipMemcpyDeviceToHost, st));
+        LSRN_HIP(hipStreamSynchronize(st));
+        if (profile) {
+            float ms = 0.f;
+            LSRN_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+            res.t_jacobi_kernel_ms += ms;
+            res.jacobi_kernels += period;
+        }
+        if (rot == 0) break;
+    }
+    if (profile) {
+        (void)hipEventDestroy(ev[0]);
+        (void)hipEventDestroy(ev[1]);
+    }
+    return std::min(sweep + 1, kJacobiMaxSweeps);
+}
 
-    // ---- singular values, order, rank, N
+// Singular values (column norms of the converged Y), their order, the rank
+// cutoff and P = Y(:, order) Sigma^-2 for the kept columns.
+void precond_finish(int64_t s, int64_t d, const double *Y, double rcond, double *sigma, double *P,
+                    PrecondResult &res, hipStream_t st) {
     DevBuf nrmb((size_t)d * sizeof(double)), ordb((size_t)d * sizeof(int64_t));
     col_norms_kernel<<<(unsigned)ceil_div(d, 4), 256, 0, st>>>(Y, d, nrmb.as<double>());
     rank_sort_kernel<<<(unsigned)ceil_div(d, 256), 256, 0, st>>>(nrmb.as<double>(), d,
@@ -779,7 +841,124 @@ PrecondResult precond(int64_t s, int64_t d, double *X, double rcond, double *sig
         LSRN_HIP(hipGetLastError());
     }
     LSRN_HIP(hipStreamSynchronize(st));
+}
+
+}  // namespace
+
+PrecondResult precond(int64_t s, int64_t d, double *X, double rcond, double *sigma, double *P,
+                      hipStream_t st, bool profile) {
+    LSRN_REQUIRE(s >= d && d > 0, "precond: need s >= d > 0");
+    PrecondResult res;
+    householder_qr(s, d, X, st);
+    // ---- Jacobi on Y = R^T
+    const JacobiPlan pl = jacobi_plan(d);
+    DevBuf Yb((size_t)d * (size_t)pl.dcols * sizeof(double));
+    double *Y = Yb.as<double>();
+    r_to_y_kernel<<<grid1d(d * pl.dcols), 256, 0, st>>>(X, s, d, pl.dcols, Y);
+    LSRN_HIP(hipGetLastError());
+    res.sweeps = jacobi_single(Y, d, pl, st, profile, res);
+    precond_finish(s, d, Y, rcond, sigma, P, res, st);
     return res;
+}
+
+void precond_batch(int count, const int64_t *s, const int64_t *d, double *const *X, double rcond,
+                   double *const *sigma, double *const *P, PrecondResult *res, hipStream_t st) {
+    for (int p = 0; p < count; ++p) {
+        LSRN_REQUIRE(s[p] >= d[p] && d[p] > 0, "precond: need s >= d > 0");
+        householder_qr(s[p], d[p], X[p], st);
+    }
+    std::vector<JacobiPlan> pl((size_t)count);
+    std::vector<DevBuf> Yb((size_t)count);
+    std::vector<int> small_ids, gram_ids, other_ids;
+    for (int p = 0; p < count; ++p) {
+        res[p] = PrecondResult();
+        pl[(size_t)p] = jacobi_plan(d[p]);
+        Yb[(size_t)p].alloc((size_t)d[p] * (size_t)pl[(size_t)p].dcols * sizeof(double));
+        r_to_y_kernel<<<grid1d(d[p] * pl[(size_t)p].dcols), 256, 0, st>>>(
+            X[p], s[p], d[p], pl[(size_t)p].dcols, Yb[(size_t)p].as<double>());
+        LSRN_HIP(hipGetLastError());
+        if (pl[(size_t)p].small) small_ids.push_back(p);
+        else if (pl[(size_t)p].variant == 0) gram_ids.push_back(p);
+        else other_ids.push_back(p);
+    }
+    // ---- d <= 128: one workgroup per problem, all sweeps, one launch
+    if (!small_ids.empty()) {
+        const int n = (int)small_ids.size();
+        std::vector<JacobiItem> it((size_t)n);
+        size_t bytes = 0;
+        for (int k = 0; k < n; ++k) {
+            const int p = small_ids[(size_t)k];
+            it[(size_t)k] = JacobiItem{Yb[(size_t)p].as<double>(), (int)d[p], 0,
+                                       (double)d[p] * DBL_EPSILON, nullptr, nullptr};
+            bytes = std::max(bytes, (size_t)d[p] * (size_t)d[p] * sizeof(double));
+        }
+        DevBuf ditems((size_t)n * sizeof(JacobiItem)), dsw((size_t)n * sizeof(int));
+        LSRN_HIP(hipMemcpyAsync(ditems.as<JacobiItem>(), it.data(), (size_t)n * sizeof(JacobiItem),
+                                hipMemcpyHostToDevice, st));
+        set_small_lds(bytes, (const void *)jacobi_small_batch_kernel);
+        jacobi_small_batch_kernel<<<(unsigned)n, 1024, bytes, st>>>(ditems.as<JacobiItem>(),
+                                                                     kJacobiMaxSweeps, dsw.as<int>());
+        LSRN_HIP(hipGetLastError());
+        std::vector<int> sw((size_t)n);
+        LSRN_HIP(hipMemcpyAsync(sw.data(), dsw.as<int>(), (size_t)n * sizeof(int), hipMemcpyDeviceToHost, st));
+        LSRN_HIP(hipStreamSynchronize(st));
+        for (int k = 0; k < n; ++k) res[small_ids[(size_t)k]].sweeps = sw[(size_t)k];
+    }
+    // ---- 128 < d <= 512: every problem's round r in one launch, one host
+    // check per sweep for the whole batch
+    if (!gram_ids.empty()) {
+        const int n = (int)gram_ids.size();
+        std::vector<JacobiItem> it((size_t)n);
+        std::vector<int> off((size_t)n + 1, 0), lastoff((size_t)n + 1, 0), active((size_t)n, 1);
+        int max_period = 0;
+        for (int k = 0; k < n; ++k) {
+            const int64_t nb = pl[(size_t)gram_ids[(size_t)k]].nblocks;
+            off[(size_t)k + 1] = off[(size_t)k] + (int)(nb / 2);
+            lastoff[(size_t)k + 1] = lastoff[(size_t)k] + (int)nb;
+            max_period = std::max(max_period, (int)nb - 1);
+        }
+        DevBuf ditems((size_t)n * sizeof(JacobiItem)), doff(((size_t)n + 1) * sizeof(int));
+        DevBuf dact((size_t)n * sizeof(int)), drot((size_t)n * sizeof(int));
+        DevBuf dlast((size_t)lastoff[(size_t)n] * sizeof(int));
+        for (int k = 0; k < n; ++k) {
+            const int p = gram_ids[(size_t)k];
+            it[(size_t)k] = JacobiItem{Yb[(size_t)p].as<double>(), (int)d[p], (int)pl[(size_t)p].nblocks,
+                                       (double)d[p] * DBL_EPSILON, drot.as<int>() + k,
+                                       dlast.as<int>() + lastoff[(size_t)k]};
+        }
+        LSRN_HIP(hipMemcpyAsync(ditems.as<JacobiItem>(), it.data(), (size_t)n * sizeof(JacobiItem),
+                                hipMemcpyHostToDevice, st));
+        LSRN_HIP(hipMemcpyAsync(doff.as<int>(), off.data(), ((size_t)n + 1) * sizeof(int),
+                                hipMemcpyHostToDevice, st));
+        LSRN_HIP(hipMemsetAsync(dlast.as<int>(), 0, (size_t)lastoff[(size_t)n] * sizeof(int), st));
+        std::vector<int> rot((size_t)n);
+        int left = n;
+        for (int sweep = 0; sweep < kJacobiMaxSweeps && left > 0; ++sweep) {
+            LSRN_HIP(hipMemsetAsync(drot.as<int>(), 0, (size_t)n * sizeof(int), st));
+            LSRN_HIP(hipMemcpyAsync(dact.as<int>(), active.data(), (size_t)n * sizeof(int),
+                                    hipMemcpyHostToDevice, st));
+            for (int round = 0; round < max_period; ++round)
+                jacobi_gram_round_batch_kernel<8, 1><<<(unsigned)off[(size_t)n], 512, 0, st>>>(
+                    ditems.as<JacobiItem>(), doff.as<int>(), dact.as<int>(), n, round, sweep);
+            LSRN_HIP(hipGetLastError());
+            LSRN_HIP(hipMemcpyAsync(rot.data(), drot.as<int>(), (size_t)n * sizeof(int),
+                                    hipMemcpyDeviceToHost, st));
+            LSRN_HIP(hipStreamSynchronize(st));
+            for (int k = 0; k < n; ++k) {
+                if (!active[(size_t)k]) continue;
+                res[gram_ids[(size_t)k]].sweeps = sweep + 1;
+                if (rot[(size_t)k] == 0) {
+                    active[(size_t)k] = 0;
+                    --left;
+                }
+            }
+        }
+    }
+    // ---- wider problems: one at a time
+    for (int p : other_ids)
+        res[p].sweeps = jacobi_single(Yb[(size_t)p].as<double>(), d[p], pl[(size_t)p], st, false, res[p]);
+    for (int p = 0; p < count; ++p)
+        precond_finish(s[p], d[p], Yb[(size_t)p].as<double>(), rcond, sigma[p], P[p], res[p], st);
 }
 
 PrecondResult precond_qr_inverse(int64_t s, int64_t d, double *X, double rcond, double *sigma,
