@@ -87,9 +87,8 @@ qr_panel_kernel(double *__restrict__ X, int64_t s, int64_t p0, int nb, double *_
 // in registers: thread t owns rows p0 + t + 1024 e, e < EPT, so each column
 // step costs three block reductions and no global traffic.
 template <int NB, int EPT>
-__global__ void __launch_bounds__(1024)
-qr_panel_reg_kernel(double *__restrict__ X, int64_t s, int64_t p0, int nb, double *__restrict__ V,
-                    double *__restrict__ beta) {
+__device__ __forceinline__ void qr_panel_reg(double *__restrict__ X, int64_t s, int64_t p0, int nb,
+                                             double *__restrict__ V, double *__restrict__ beta) {
     __shared__ double red[16][NB];
     __shared__ double bc[NB + 1];
     __shared__ double scratch[16];
@@ -175,14 +174,39 @@ qr_panel_reg_kernel(double *__restrict__ X, int64_t s, int64_t p0, int nb, doubl
         }
 }
 
+template <int NB, int EPT>
+__global__ void __launch_bounds__(1024)
+qr_panel_reg_kernel(double *__restrict__ X, int64_t s, int64_t p0, int nb, double *__restrict__ V,
+                    double *__restrict__ beta) {
+    qr_panel_reg<NB, EPT>(X, s, p0, nb, V, beta);
+}
+
+// One problem of a batched QR: the sketch and its panel buffers.
+struct QrItem {
+    double *X;
+    int64_t s, d;
+    double *V, *beta;  // s x QNB and QNB entries
+};
+
+// The panel at column p0 of every problem with d > p0, workgroup p for
+// problem p.
+template <int NB, int EPT>
+__global__ void __launch_bounds__(1024)
+qr_panel_reg_batch_kernel(const QrItem *__restrict__ items, int64_t p0, int pw) {
+    const QrItem it = items[blockIdx.x];
+    if (it.d <= p0) return;
+    const int nb = (int)min((int64_t)pw, it.d - p0);
+    qr_panel_reg<NB, EPT>(it.X, it.s, p0, nb, it.V, it.beta);
+}
+
 // Apply the nb reflectors of a panel, in order, to the trailing columns
 // c >= p0 + nb: one column per workgroup, held in registers.
 template <int NT, int EPT>
-__global__ void __launch_bounds__(NT)
-qr_apply_kernel(double *__restrict__ X, int64_t s, int64_t p0, int nb, const double *__restrict__ V,
-                const double *__restrict__ beta) {
+__device__ __forceinline__ void qr_apply(double *__restrict__ X, int64_t s, int64_t p0, int nb,
+                                         const double *__restrict__ V,
+                                         const double *__restrict__ beta, int64_t col) {
     __shared__ double scratch[NT / 64];
-    const int64_t c = p0 + nb + blockIdx.x;
+    const int64_t c = p0 + nb + col;
     double *xc = X + c * s;
     double reg[EPT];
 #pragma unroll
@@ -210,6 +234,25 @@ qr_apply_kernel(double *__restrict__ X, int64_t s, int64_t p0, int nb, const dou
         const int64_t i = p0 + threadIdx.x + (int64_t)NT * e;
         if (i < s) xc[i] = reg[e];
     }
+}
+
+template <int NT, int EPT>
+__global__ void __launch_bounds__(NT)
+qr_apply_kernel(double *__restrict__ X, int64_t s, int64_t p0, int nb, const double *__restrict__ V,
+                const double *__restrict__ beta) {
+    qr_apply<NT, EPT>(X, s, p0, nb, V, beta, blockIdx.x);
+}
+
+// The trailing update of the panel at p0 for every problem: workgroup
+// (p, y) updates trailing column y of problem p, if it has one.
+template <int NT, int EPT>
+__global__ void __launch_bounds__(NT)
+qr_apply_batch_kernel(const QrItem *__restrict__ items, int64_t p0, int pw) {
+    const QrItem it = items[blockIdx.x];
+    if (it.d <= p0) return;
+    const int nb = (int)min((int64_t)pw, it.d - p0);
+    if ((int64_t)blockIdx.y >= it.d - p0 - nb) return;
+    qr_apply<NT, EPT>(it.X, it.s, p0, nb, it.V, it.beta, blockIdx.y);
 }
 
 // Y (d x dcols, column-major, ld d): column p = row p of R (R upper
@@ -863,9 +906,44 @@ PrecondResult precond(int64_t s, int64_t d, double *X, double rcond, double *sig
 
 void precond_batch(int count, const int64_t *s, const int64_t *d, double *const *X, double rcond,
                    double *const *sigma, double *const *P, PrecondResult *res, hipStream_t st) {
-    for (int p = 0; p < count; ++p) {
-        LSRN_REQUIRE(s[p] >= d[p] && d[p] > 0, "precond: need s >= d > 0");
-        householder_qr(s[p], d[p], X[p], st);
+    // ---- QR: sketches of up to 1024 rows factor together, one launch per
+    // panel step for all of them; taller ones one at a time
+    {
+        std::vector<QrItem> qi;
+        int64_t vtotal = 0, dmax = 0;
+        for (int p = 0; p < count; ++p) {
+            LSRN_REQUIRE(s[p] >= d[p] && d[p] > 0, "precond: need s >= d > 0");
+            if (s[p] <= 1024) {
+                qi.push_back(QrItem{X[p], s[p], d[p], nullptr, nullptr});
+                vtotal += s[p] * QNB;
+                dmax = std::max(dmax, d[p]);
+            } else {
+                householder_qr(s[p], d[p], X[p], st);
+            }
+        }
+        if (!qi.empty()) {
+            const int n = (int)qi.size();
+            DevBuf Vb((size_t)vtotal * sizeof(double)), bb((size_t)n * QNB * sizeof(double));
+            int64_t vo = 0;
+            for (int k = 0; k < n; ++k) {
+                qi[(size_t)k].V = Vb.as<double>() + vo;
+                qi[(size_t)k].beta = bb.as<double>() + (size_t)k * QNB;
+                vo += qi[(size_t)k].s * QNB;
+            }
+            DevBuf ditems((size_t)n * sizeof(QrItem));
+            LSRN_HIP(hipMemcpyAsync(ditems.as<QrItem>(), qi.data(), (size_t)n * sizeof(QrItem),
+                                    hipMemcpyHostToDevice, st));
+            const int pw = 8;
+            for (int64_t p0 = 0; p0 < dmax; p0 += pw) {
+                qr_panel_reg_batch_kernel<8, 1><<<(unsigned)n, 1024, 0, st>>>(ditems.as<QrItem>(), p0, pw);
+                const int64_t ncols = dmax - p0 - std::min<int64_t>(pw, dmax - p0);
+                if (ncols > 0)
+                    qr_apply_batch_kernel<256, 4><<<dim3((unsigned)n, (unsigned)ncols), 256, 0, st>>>(
+                        ditems.as<QrItem>(), p0, pw);
+                LSRN_HIP(hipGetLastError());
+            }
+            LSRN_HIP(hipStreamSynchronize(st));  // before the panel buffers are freed
+        }
     }
     std::vector<JacobiPlan> pl((size_t)count);
     std::vector<DevBuf> Yb((size_t)count);
