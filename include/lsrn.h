@@ -262,12 +262,13 @@ lsrn_status lsrn_iterate_csr(int64_t m, int64_t n, int64_t nnz, const int64_t *r
  * Many small over-determined solves at once (Alg. 1 for each problem): A[p]
  * dense FP64 row-major, m[p] >= n[p], n[p] <= 512, leading dimension
  * lda[p]; b[p] length m[p]; x[p] length n[p] (arrays of device pointers
- * held on the host).  Each problem's sketch and SVD run in turn on the
- * stream; then the LSQR iterations of all problems advance together: every
- * kernel launch covers the whole batch (one work item per problem row
- * block, column chunk or problem) and each chunk of iterations is replayed
- * as a HIP graph, so the number of launches does not grow with the number
- * of problems.  One option set for all problems; LSQR only, no refinement,
+ * held on the host).  Each problem's sketch runs in turn on the stream;
+ * the QR of the sketches (up to 1024 rows) and the Jacobi sweeps (d <= 512)
+ * run for all problems in shared launches; then the LSQR iterations of all
+ * problems advance together: every kernel launch covers the whole batch
+ * (one work item per problem row block, column chunk or problem) and each
+ * chunk of iterations is replayed as a HIP graph, so the number of
+ * launches does not grow with the number of problems.  One option set for all problems; LSQR only, no refinement,
  * lambda = 0, precision FP64, the SVD preconditioner (LSRN_E_UNSUPPORTED
  * otherwise).  infos (count entries, may be NULL) report per problem; the
  * stage times are those of the whole batch.  LSRN_E_NOT_CONVERGED if any
@@ -277,6 +278,49 @@ lsrn_status lsrn_solve_batch(int32_t count, const int64_t *m, const int64_t *n,
                              const double *const *A, const int64_t *lda, const double *const *b,
                              double *const *x, const lsrn_options *opt, lsrn_info *infos,
                              void *stream);
+
+/* ------------------------------------------------------------------------
+ * Plans: steps 1-5 of Alg. 1/2 (sketch, SVD, preconditioner N or M) run
+ * once for a matrix; lsrn_plan_solve then runs steps 6-7 (and refinement)
+ * for any number of right-hand sides.  By Thm. 2 the preconditioner does
+ * not depend on b, so every solve gets the min-length solution; a solve
+ * through a plan returns bit for bit what lsrn_solve_dense /
+ * lsrn_solve_csr return for the same A, b and options.
+ *
+ * The plan keeps the caller's pointers to A (it copies only what a layout
+ * conversion needs): A must stay valid and unchanged until
+ * lsrn_plan_destroy.  The plan owns its preconditioner (d x d FP64), the
+ * transposed copy of A when the layout needs one, the CSR transpose, and
+ * (precision form) the FP32 copy of A.  Creation synchronises `stream`;
+ * afterwards the plan is read-only, so solves on one plan may run
+ * concurrently on different streams.
+ *
+ * `opt` of lsrn_plan_solve may be NULL (the creation options) or carry new
+ * per-solve settings: tol, max_iter, method, refine, refine_tol, profile.
+ * gamma, lambda, seed, rcond, precond and precision must equal the
+ * creation ones (LSRN_E_INVALID otherwise).  Errors as in lsrn_solve_dense.
+ * ---------------------------------------------------------------------- */
+typedef struct lsrn_plan lsrn_plan;
+
+/* Steps 1-5 for dense A (arguments as lsrn_solve_dense); *out receives the
+ * plan; info (may be NULL) reports the sketch and the SVD (s, d, rank,
+ * sweeps, sigma_max, sigma_min_kept, t_sketch_ms, t_svd_ms). */
+lsrn_status lsrn_plan_create_dense(int64_t m, int64_t n, const double *A, int64_t lda,
+                                   int32_t layout, const lsrn_options *opt, lsrn_plan **out,
+                                   lsrn_info *info, void *stream);
+
+/* Steps 1-5 for CSR A (arguments as lsrn_solve_csr). */
+lsrn_status lsrn_plan_create_csr(int64_t m, int64_t n, int64_t nnz, const int64_t *rowptr,
+                                 const int32_t *colind, const double *val,
+                                 const lsrn_options *opt, lsrn_plan **out, lsrn_info *info,
+                                 void *stream);
+
+/* Steps 6-7 (+ refinement) for b (length m) into x (length n). */
+lsrn_status lsrn_plan_solve(const lsrn_plan *plan, const double *b, double *x,
+                            const lsrn_options *opt, lsrn_info *info, void *stream);
+
+/* Free the plan's device memory (after its solves have finished). */
+void lsrn_plan_destroy(lsrn_plan *plan);
 
 /* ------------------------------------------------------------------------
  * Serving runtime: solves of different shapes submitted as they arrive,

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <algorithm>
 #include <exception>
 #include <new>
@@ -203,10 +204,19 @@ bool use_qr_inverse(const lsrn_options &opt, int64_t d) {
          "min(m, n) above 8192 needs lambda > 0 (full-rank QR-inverse preconditioner)");
 }
 
-// Steps 1-7 for a dense (dv) or sparse (sv) tall view; tm has its first mark.
-lsrn_status solve_impl(bool tall, int64_t K, int64_t d, int64_t n, const TallView *dv,
-                       const SparseView *sv, const double *b, double *x, const lsrn_options &opt,
-                       lsrn_info *info, hipStream_t st, StageTimer &tm) {
+// Steps 1-5 of a solve, kept for the iterations: the preconditioner and
+// (precision form) the FP32 copy of the tall view.
+struct Prepared {
+    int64_t s = 0, d = 0;
+    PrecondResult pr;
+    DevBuf sigma, P, T32;
+    double sketch_kernel_ms = 0.0;
+};
+
+// Steps 1-5 for a dense (dv) or sparse (sv) tall view; tm gets two marks
+// (after the sketch, after the preconditioner).
+void prepare(bool tall, int64_t K, int64_t d, const TallView *dv, const SparseView *sv,
+             const lsrn_options &opt, hipStream_t st, StageTimer &tm, Prepared &pp) {
     const int64_t s = (int64_t)std::ceil(opt.gamma * (double)d);
     const bool qr_inv = use_qr_inverse(opt, d);
     const bool mixed = opt.precision == LSRN_PREC_MIXED;
@@ -216,82 +226,115 @@ lsrn_status solve_impl(bool tall, int64_t K, int64_t d, int64_t n, const TallVie
     // min-length solution would be off by about kappa(A) 2^-24
     if (mixed && !tall)
         fail(LSRN_E_UNSUPPORTED, "the precision form is provided for over-determined A");
+    pp.s = s;
+    pp.d = d;
     DevBuf X((size_t)s * (size_t)d * sizeof(double));
-    double sketch_kernel_ms = 0.0;
-    DevBuf T32;
     if (sv) {
         sketch_csr(*sv, tall ? opt.lambda : 0.0, s, opt.seed, X.as<double>(), st,
-                   opt.profile ? &sketch_kernel_ms : nullptr);
+                   opt.profile ? &pp.sketch_kernel_ms : nullptr);
     } else if (mixed) {
-        T32.alloc((size_t)K * (size_t)dv->ldt * sizeof(float));
-        to_f32(K, d, dv->T, dv->ldt, T32.as<float>(), st);
+        pp.T32.alloc((size_t)K * (size_t)dv->ldt * sizeof(float));
+        to_f32(K, d, dv->T, dv->ldt, pp.T32.as<float>(), st);
         sketch_rows_bf16(K, d, dv->T, dv->ldt, tall ? opt.lambda : 0.0, s, opt.seed, X.as<double>(),
-                         st, opt.profile ? &sketch_kernel_ms : nullptr);
+                         st, opt.profile ? &pp.sketch_kernel_ms : nullptr);
     } else {
         sketch_rows(K, d, dv->T, dv->ldt, tall ? opt.lambda : 0.0, s, opt.seed, X.as<double>(), st,
-                    opt.profile ? &sketch_kernel_ms : nullptr);
+                    opt.profile ? &pp.sketch_kernel_ms : nullptr);
     }
     tm.mark();
-    DevBuf sigma((size_t)d * sizeof(double)), P((size_t)d * (size_t)d * sizeof(double));
-    PrecondResult pr = qr_inv ? precond_qr_inverse(s, d, X.as<double>(), opt.rcond, sigma.as<double>(),
-                                                   P.as<double>(), st)
-                              : precond(s, d, X.as<double>(), opt.rcond, sigma.as<double>(),
-                                        P.as<double>(), st, opt.profile != 0);
-    X.release();
+    pp.sigma.alloc((size_t)d * sizeof(double));
+    pp.P.alloc((size_t)d * (size_t)d * sizeof(double));
+    pp.pr = qr_inv ? precond_qr_inverse(s, d, X.as<double>(), opt.rcond, pp.sigma.as<double>(),
+                                        pp.P.as<double>(), st)
+                   : precond(s, d, X.as<double>(), opt.rcond, pp.sigma.as<double>(), pp.P.as<double>(),
+                             st, opt.profile != 0);
     tm.mark();
+}
+
+// Steps 6-7 (+ refinement) with a prepared preconditioner.
+IterResult run_iterations(bool tall, int64_t K, int64_t d, int64_t n, const TallView *dv,
+                          const SparseView *sv, const Prepared &pp, const double *b, double *x,
+                          const lsrn_options &opt, hipStream_t st) {
     IterResult ir;
-    if (pr.rank > 0) {
-        IterProblem pb;
-        pb.tall = tall; pb.rows = K; pb.cols = d;
-        if (sv) pb.sp = sv;
-        else { pb.T = dv->T; pb.ldt = dv->ldt; }
-        pb.lambda = tall ? opt.lambda : 0.0; pb.P = P.as<double>(); pb.ldp = d;
-        pb.r = pr.rank; pb.s = s;
-        if (mixed) {
-            pb.T32 = T32.as<float>();
-            lsrn_options om = opt;
-            if (om.refine == 0) om.refine = 10;
-            ir = iterate(pb, b, x, om, st);
-        } else {
-            ir = iterate(pb, b, x, opt, st);
-        }
-    } else {
+    if (pp.pr.rank <= 0) {
         LSRN_HIP(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), st));
+        return ir;
     }
-    tm.mark();
+    IterProblem pb;
+    pb.tall = tall; pb.rows = K; pb.cols = d;
+    if (sv) pb.sp = sv;
+    else { pb.T = dv->T; pb.ldt = dv->ldt; }
+    pb.lambda = tall ? opt.lambda : 0.0;
+    pb.P = pp.P.as<double>(); pb.ldp = d;
+    pb.r = pp.pr.rank; pb.s = pp.s;
+    if (pp.T32.bytes() > 0) {
+        pb.T32 = pp.T32.as<float>();
+        lsrn_options om = opt;
+        if (om.refine == 0) om.refine = 10;
+        return iterate(pb, b, x, om, st);
+    }
+    return iterate(pb, b, x, opt, st);
+}
+
+lsrn_status finish_info(bool tall, const Prepared &pp, const IterResult &ir, const lsrn_options &opt,
+                        lsrn_info *info, StageTimer *tm) {
     if (info) {
         std::memset(info, 0, sizeof(*info));
-        info->s = s; info->d = d; info->rank = pr.rank; info->iters = ir.iters;
+        info->s = pp.s; info->d = pp.d; info->rank = pp.pr.rank; info->iters = ir.iters;
         info->refine_steps = ir.refine_steps; info->refine_iters = ir.refine_iters;
         info->fp64_refine_steps = ir.fp64_refine_steps;
-        info->sweeps = pr.sweeps; info->tall = tall; info->converged = ir.converged;
+        info->sweeps = pp.pr.sweeps; info->tall = tall; info->converged = ir.converged;
         info->sigma_l = ir.sigma_l; info->sigma_u = ir.sigma_u;
-        info->sigma_max = pr.sigma_max; info->sigma_min_kept = pr.sigma_min_kept;
-        info->t_sketch_ms = tm.elapsed_ms(0, 1);
-        info->t_svd_ms = tm.elapsed_ms(1, 2);
+        info->sigma_max = pp.pr.sigma_max; info->sigma_min_kept = pp.pr.sigma_min_kept;
+        if (tm) {
+            info->t_sketch_ms = tm->elapsed_ms(0, 1);
+            info->t_svd_ms = tm->elapsed_ms(1, 2);
+            info->t_total_ms = tm->elapsed_ms(0, 3);
+        } else {
+            info->t_total_ms = ir.t_iter_ms + ir.t_refine_ms;
+        }
         info->t_iter_ms = ir.t_iter_ms;
         info->t_refine_ms = ir.t_refine_ms;
-        info->t_total_ms = tm.elapsed_ms(0, 3);
         if (opt.profile) {
-            info->t_sketch_kernel_ms = sketch_kernel_ms;
-            info->sketch_kernels = 1;
+            info->t_sketch_kernel_ms = pp.sketch_kernel_ms;
+            info->sketch_kernels = tm ? 1 : 0;
             info->t_sweep_kernel_ms = ir.t_sweep_kernel_ms;
             info->sweep_kernels = ir.sweep_kernels;
-            info->t_jacobi_kernel_ms = pr.t_jacobi_kernel_ms;
-            info->jacobi_kernels = pr.jacobi_kernels;
+            info->t_jacobi_kernel_ms = pp.pr.t_jacobi_kernel_ms;
+            info->jacobi_kernels = pp.pr.jacobi_kernels;
         }
     }
-    if (!ir.converged) {
+    if (pp.pr.rank > 0 && !ir.converged) {
         g_last_error = "LSQR reached max_iter";
         return LSRN_E_NOT_CONVERGED;
     }
     return LSRN_OK;
 }
 
+// Steps 1-7 for a dense (dv) or sparse (sv) tall view; tm has its first mark.
+lsrn_status solve_impl(bool tall, int64_t K, int64_t d, int64_t n, const TallView *dv,
+                       const SparseView *sv, const double *b, double *x, const lsrn_options &opt,
+                       lsrn_info *info, hipStream_t st, StageTimer &tm) {
+    Prepared pp;
+    prepare(tall, K, d, dv, sv, opt, st, tm, pp);
+    const IterResult ir = run_iterations(tall, K, d, n, dv, sv, pp, b, x, opt, st);
+    tm.mark();
+    return finish_info(tall, pp, ir, opt, info, &tm);
+}
+
 }  // namespace
 }  // namespace lsrn
 
 using namespace lsrn;
+
+struct lsrn_plan {
+    bool tall = true, sparse = false;
+    int64_t m = 0, n = 0;
+    lsrn_options opt{};
+    lsrn::TallView dv;
+    lsrn::SparseView sv;
+    lsrn::Prepared pp;
+};
 
 extern "C" {
 
@@ -446,6 +489,92 @@ lsrn_status lsrn_solve_csr(int64_t m, int64_t n, int64_t nnz, const int64_t *row
     make_sparse_view(v, m, n, nnz, rowptr, colind, val, st);
     return solve_impl(v.tall, v.K, v.d, n, nullptr, &v, b, x, opt, info, st, tm);
     LSRN_API_END
+}
+
+lsrn_status lsrn_plan_create_dense(int64_t m, int64_t n, const double *A, int64_t lda,
+                                   int32_t layout, const lsrn_options *opt_in, lsrn_plan **out,
+                                   lsrn_info *info, void *stream) {
+    LSRN_API_BEGIN
+    const lsrn_options opt = opt_in ? *opt_in : defaults();
+    check_options(opt);
+    LSRN_REQUIRE(out, "NULL pointer");
+    *out = nullptr;
+    LSRN_REQUIRE(m > 0 && n > 0, "sizes must be positive");
+    LSRN_REQUIRE(A, "NULL pointer");
+    hipStream_t st = (hipStream_t)stream;
+    auto plan = std::make_unique<lsrn_plan>();
+    plan->m = m; plan->n = n; plan->opt = opt;
+    StageTimer tm(st);
+    tm.mark();
+    make_view(plan->dv, m, n, A, lda, layout, opt.lambda, st);
+    plan->tall = plan->dv.tall;
+    prepare(plan->tall, plan->dv.K, plan->dv.d, &plan->dv, nullptr, opt, st, tm, plan->pp);
+    tm.mark();
+    LSRN_HIP(hipStreamSynchronize(st));
+    finish_info(plan->tall, plan->pp, IterResult(), opt, info, &tm);
+    *out = plan.release();
+    LSRN_API_END
+}
+
+lsrn_status lsrn_plan_create_csr(int64_t m, int64_t n, int64_t nnz, const int64_t *rowptr,
+                                 const int32_t *colind, const double *val,
+                                 const lsrn_options *opt_in, lsrn_plan **out, lsrn_info *info,
+                                 void *stream) {
+    LSRN_API_BEGIN
+    const lsrn_options opt = opt_in ? *opt_in : defaults();
+    check_options(opt);
+    LSRN_REQUIRE(out, "NULL pointer");
+    *out = nullptr;
+    LSRN_REQUIRE(m > 0 && n > 0, "sizes must be positive");
+    if (opt.lambda > 0.0 && m < n)
+        fail(LSRN_E_UNSUPPORTED, "Tikhonov regularisation needs m >= n (under-determined form not provided)");
+    hipStream_t st = (hipStream_t)stream;
+    auto plan = std::make_unique<lsrn_plan>();
+    plan->m = m; plan->n = n; plan->opt = opt; plan->sparse = true;
+    StageTimer tm(st);
+    tm.mark();
+    make_sparse_view(plan->sv, m, n, nnz, rowptr, colind, val, st);
+    plan->tall = plan->sv.tall;
+    prepare(plan->tall, plan->sv.K, plan->sv.d, nullptr, &plan->sv, opt, st, tm, plan->pp);
+    tm.mark();
+    LSRN_HIP(hipStreamSynchronize(st));
+    finish_info(plan->tall, plan->pp, IterResult(), opt, info, &tm);
+    *out = plan.release();
+    LSRN_API_END
+}
+
+lsrn_status lsrn_plan_solve(const lsrn_plan *plan, const double *b, double *x,
+                            const lsrn_options *opt_in, lsrn_info *info, void *stream) {
+    LSRN_API_BEGIN
+    LSRN_REQUIRE(plan && b && x, "NULL pointer");
+    lsrn_options opt = plan->opt;
+    if (opt_in) {
+        check_options(*opt_in);
+        LSRN_REQUIRE(opt_in->gamma == opt.gamma && opt_in->lambda == opt.lambda &&
+                         opt_in->seed == opt.seed && opt_in->rcond == opt.rcond &&
+                         opt_in->precond == opt.precond && opt_in->precision == opt.precision,
+                     "gamma, lambda, seed, rcond, precond and precision must match the plan");
+        opt.tol = opt_in->tol;
+        opt.max_iter = opt_in->max_iter;
+        opt.method = opt_in->method;
+        opt.refine = opt_in->refine;
+        opt.refine_tol = opt_in->refine_tol;
+        opt.profile = opt_in->profile;
+        opt.t_margin = opt_in->t_margin;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t K = plan->sparse ? plan->sv.K : plan->dv.K;
+    const int64_t d = plan->sparse ? plan->sv.d : plan->dv.d;
+    const IterResult ir = run_iterations(plan->tall, K, d, plan->n, plan->sparse ? nullptr : &plan->dv,
+                                         plan->sparse ? &plan->sv : nullptr, plan->pp, b, x, opt, st);
+    return finish_info(plan->tall, plan->pp, ir, opt, info, nullptr);
+    LSRN_API_END
+}
+
+void lsrn_plan_destroy(lsrn_plan *plan) {
+    if (!plan) return;
+    (void)hipDeviceSynchronize();
+    delete plan;
 }
 
 lsrn_status lsrn_sketch_csr(int64_t m, int64_t n, int64_t nnz, const int64_t *rowptr,

@@ -64,11 +64,14 @@ SERVER_EXPORTS = ["lsrn_server_create", "lsrn_server_submit_dense", "lsrn_server
                   "lsrn_server_wait", "lsrn_server_stats", "lsrn_server_last_error",
                   "lsrn_server_destroy"]
 EXPORTS = EXPORTS + SERVER_EXPORTS
+PLAN_EXPORTS = ["lsrn_plan_create_dense", "lsrn_plan_create_csr", "lsrn_plan_solve",
+                "lsrn_plan_destroy"]
+EXPORTS = EXPORTS + PLAN_EXPORTS
 PRECOND = {"auto": 0, "svd": 1, "qr": 2}
 PRECISION = {"fp64": 0, "mixed": 1}
 _SIZE_FNS = ("lsrn_default_options", "lsrn_status_string", "lsrn_last_error",
              "lsrn_workspace_bytes", "lsrn_workspace_bytes_csr", "lsrn_server_last_error",
-             "lsrn_server_destroy")
+             "lsrn_server_destroy", "lsrn_plan_destroy")
 
 
 class ServerTiming(C.Structure):
@@ -119,6 +122,13 @@ def lib():
         L.lsrn_server_last_error.restype = C.c_char_p
         L.lsrn_server_destroy.argtypes = [P]
         L.lsrn_server_destroy.restype = None
+        L.lsrn_plan_create_dense.argtypes = [I64, I64, P, I64, I32, C.POINTER(Options),
+                                             C.POINTER(C.c_void_p), C.POINTER(Info), P]
+        L.lsrn_plan_create_csr.argtypes = [I64, I64, I64, P, P, P, C.POINTER(Options),
+                                           C.POINTER(C.c_void_p), C.POINTER(Info), P]
+        L.lsrn_plan_solve.argtypes = [P, P, P, C.POINTER(Options), C.POINTER(Info), P]
+        L.lsrn_plan_destroy.argtypes = [P]
+        L.lsrn_plan_destroy.restype = None
         for name in EXPORTS:
             if name not in _SIZE_FNS:
                 getattr(L, name).restype = C.c_int
@@ -341,6 +351,63 @@ def iterate_csr(A: Csr, b: torch.Tensor, P: torch.Tensor, s: int, **opts):
     _check(lib().lsrn_iterate_csr(*A.args(), b.data_ptr(), P.data_ptr(), P.stride(0), P.shape[1], s,
                                   x.data_ptr(), C.byref(o), C.byref(info), _stream()))
     return x, info.as_dict()
+
+
+class Plan:
+    """lsrn_plan_*: the sketch and preconditioner of one matrix (steps 1-5)
+    made once, then solves for many right-hand sides (steps 6-7).  Build
+    with Plan.dense(A, ...) or Plan.csr(A, ...); keeps A alive."""
+
+    def __init__(self, handle, m: int, n: int, keep, info: dict, opts: dict):
+        self._h, self.m, self.n, self._keep, self.info = handle, m, n, keep, info
+        self._opts = dict(opts)
+
+    @classmethod
+    def dense(cls, A: torch.Tensor, *, layout: int = ROW_MAJOR, **opts) -> "Plan":
+        _dev_f64(A, "A")
+        m, n, lda = _layout_dims(A, layout)
+        h, o, info = C.c_void_p(), options(**opts), Info()
+        _check(lib().lsrn_plan_create_dense(m, n, A.data_ptr(), lda, layout, C.byref(o),
+                                            C.byref(h), C.byref(info), _stream()))
+        return cls(h, m, n, (A,), info.as_dict(), opts)
+
+    @classmethod
+    def csr(cls, A: "Csr", **opts) -> "Plan":
+        h, o, info = C.c_void_p(), options(**opts), Info()
+        _check(lib().lsrn_plan_create_csr(*A.args(), C.byref(o), C.byref(h), C.byref(info),
+                                          _stream()))
+        return cls(h, A.m, A.n, (A,), info.as_dict(), opts)
+
+    def solve(self, b: torch.Tensor, x: torch.Tensor | None = None, *,
+              allow_not_converged: bool = False, **opts):
+        """Steps 6-7 for b; opts update the plan's per-solve settings (tol,
+        max_iter, method, refine, ...).  Returns (x, info)."""
+        if self._h is None:
+            raise RuntimeError("plan is closed")
+        _dev_f64(b, "b")
+        if b.numel() != self.m or not b.is_contiguous():
+            raise ValueError("b must be contiguous with m entries")
+        if x is None:
+            x = torch.empty(self.n, dtype=torch.float64, device=b.device)
+        info = Info()
+        o = C.byref(options(**{**self._opts, **opts})) if opts else None
+        st = lib().lsrn_plan_solve(self._h, b.data_ptr(), x.data_ptr(), o, C.byref(info), _stream())
+        if not (allow_not_converged and st == 4):
+            _check(st)
+        out = info.as_dict()
+        out["status"] = int(st)
+        return x, out
+
+    def close(self):
+        if self._h is not None:
+            lib().lsrn_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:
