@@ -280,6 +280,31 @@ lsrn_status lsrn_solve_batch(int32_t count, const int64_t *m, const int64_t *n,
                              void *stream);
 
 /* ------------------------------------------------------------------------
+ * A given only through products (Sec. 1 and 4: LSRN needs A only through
+ * A v and A^T u, and the sketch G A).
+ *
+ * The routine computes out = A in (trans = 0; in: n x k, out: m x k) or
+ * out = A^T in (trans = 1; in: m x k, out: n x k), both column-major with
+ * leading dimensions ldin and ldout, device pointers.  It must enqueue its
+ * work on `stream` (or finish it before returning), must not write `in`,
+ * and returns 0 on success; any other value ends the solve with
+ * LSRN_E_INVALID.  The library calls it with k up to s (sketch: G^T in
+ * column blocks of at most 2^27 / max(m, n) columns, i.e. <= 1 GiB) and with
+ * k = 1 (iterations: one product with A and one with A^T per iteration,
+ * since the fused pass needs A's rows).
+ * ---------------------------------------------------------------------- */
+typedef int (*lsrn_apply_fn)(void *ctx, int32_t trans, int64_t k, const double *in, int64_t ldin,
+                             double *out, int64_t ldout, void *stream);
+
+/* The whole solve (Alg. 1 / Alg. 2, Sec. 5) for an operator A (m x n):
+ * b length m, x length n; options as lsrn_solve_dense except that
+ * refinement and the precision form are not provided (refine must be 0,
+ * precision FP64; LSRN_E_UNSUPPORTED otherwise).  The sketch is formed
+ * from the routine's products with G^T, generated block by block. */
+lsrn_status lsrn_solve_op(int64_t m, int64_t n, lsrn_apply_fn apply, void *ctx, const double *b,
+                          double *x, const lsrn_options *opt, lsrn_info *info, void *stream);
+
+/* ------------------------------------------------------------------------
  * Plans: steps 1-5 of Alg. 1/2 (sketch, SVD, preconditioner N or M) run
  * once for a matrix; lsrn_plan_solve then runs steps 6-7 (and refinement)
  * for any number of right-hand sides.  By Thm. 2 the preconditioner does

@@ -491,6 +491,68 @@ lsrn_status lsrn_solve_csr(int64_t m, int64_t n, int64_t nnz, const int64_t *row
     LSRN_API_END
 }
 
+lsrn_status lsrn_solve_op(int64_t m, int64_t n, lsrn_apply_fn apply, void *ctx, const double *b,
+                          double *x, const lsrn_options *opt_in, lsrn_info *info, void *stream) {
+    LSRN_API_BEGIN
+    const lsrn_options opt = opt_in ? *opt_in : defaults();
+    check_options(opt);
+    LSRN_REQUIRE(m > 0 && n > 0, "sizes must be positive");
+    LSRN_REQUIRE(apply && b && x, "NULL pointer");
+    if (opt.refine != 0 || opt.precision != LSRN_PREC_FP64)
+        fail(LSRN_E_UNSUPPORTED, "an operator A is solved without refinement, in FP64");
+    if (opt.lambda > 0.0 && m < n)
+        fail(LSRN_E_UNSUPPORTED, "Tikhonov regularisation needs m >= n (under-determined form not provided)");
+    hipStream_t st = (hipStream_t)stream;
+    StageTimer tm(st);
+    tm.mark();
+    OpView ov;
+    ov.fn = apply; ov.ctx = ctx; ov.m = m; ov.n = n;
+    const bool tall = m >= n;
+    const int64_t K = tall ? m : n, d = tall ? n : m;
+    Prepared pp;
+    pp.d = d;
+    pp.s = (int64_t)std::ceil(opt.gamma * (double)d);
+    const int64_t s = pp.s;
+    // sketch: X^T = T^T G^T, G^T generated in blocks of k columns
+    DevBuf X((size_t)s * (size_t)d * sizeof(double));
+    {
+        DevBuf XT((size_t)s * (size_t)d * sizeof(double));
+        const int64_t k = std::max<int64_t>(1, std::min<int64_t>(s, ((int64_t)1 << 27) / K));
+        DevBuf Gc((size_t)k * (size_t)K * sizeof(double));
+        for (int64_t i0 = 0; i0 < s; i0 += k) {
+            const int64_t kk = std::min(k, s - i0);
+            launch_gauss_fill(opt.seed, i0, kk, 0, K, Gc.as<double>(), st);
+            ov.apply_t(1, kk, Gc.as<double>(), K, XT.as<double>() + i0 * d, d, st);
+        }
+        transpose(s, d, XT.as<double>(), d, X.as<double>(), st);
+        if (tall && opt.lambda > 0.0) add_identity_rows(K, d, s, opt.lambda, opt.seed, X.as<double>(), st);
+        LSRN_HIP(hipStreamSynchronize(st));  // before the blocks are freed
+    }
+    tm.mark();
+    pp.sigma.alloc((size_t)d * sizeof(double));
+    pp.P.alloc((size_t)d * (size_t)d * sizeof(double));
+    pp.pr = use_qr_inverse(opt, d)
+                ? precond_qr_inverse(s, d, X.as<double>(), opt.rcond, pp.sigma.as<double>(),
+                                     pp.P.as<double>(), st)
+                : precond(s, d, X.as<double>(), opt.rcond, pp.sigma.as<double>(), pp.P.as<double>(),
+                          st, opt.profile != 0);
+    X.release();
+    tm.mark();
+    IterResult ir;
+    if (pp.pr.rank > 0) {
+        IterProblem pb;
+        pb.tall = tall; pb.rows = K; pb.cols = d; pb.op = &ov;
+        pb.lambda = tall ? opt.lambda : 0.0; pb.P = pp.P.as<double>(); pb.ldp = d;
+        pb.r = pp.pr.rank; pb.s = s;
+        ir = iterate(pb, b, x, opt, st);
+    } else {
+        LSRN_HIP(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), st));
+    }
+    tm.mark();
+    return finish_info(tall, pp, ir, opt, info, &tm);
+    LSRN_API_END
+}
+
 lsrn_status lsrn_plan_create_dense(int64_t m, int64_t n, const double *A, int64_t lda,
                                    int32_t layout, const lsrn_options *opt_in, lsrn_plan **out,
                                    lsrn_info *info, void *stream) {

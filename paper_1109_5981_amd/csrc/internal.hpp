@@ -130,6 +130,19 @@ void trtri_upper(int64_t d, const double *R, int64_t ldr, double *Rinv, int64_t 
 // The operator of the iteration phase.  Tall: T = A row-major (rows = m,
 // cols = n) with optional lambda rows; Fat: T = A^T row-major (rows = n,
 // cols = m).  P is d x r row-major (leading dim ldp), d = cols of T.
+// A matrix given only through the caller's product routine: out = op(A) in
+// for k columns (trans = 0: A, trans = 1: A^T), m x n.
+struct OpView {
+    lsrn_apply_fn fn = nullptr;
+    void *ctx = nullptr;
+    int64_t m = 0, n = 0;
+    // out (rows of the result) = T in (t = 0) or T^T in (t = 1) for the
+    // tall view T: A when m >= n, A^T otherwise.  Throws on a nonzero
+    // return of the routine.
+    void apply_t(int t, int64_t k, const double *in, int64_t ldin, double *out, int64_t ldout,
+                 hipStream_t st) const;
+};
+
 struct IterProblem {
     bool tall = true;
     int64_t rows = 0;       // rows of T
@@ -142,6 +155,7 @@ struct IterProblem {
     int64_t r = 0;
     int64_t s = 0;
     const SparseView *sp = nullptr;  // sparse T (then T and ldt are unused)
+    const OpView *op = nullptr;      // T through the caller's products (no refinement)
     // precision form: FP32 copy of T (leading dimension ldt) read by every
     // sweep; refinement residuals still use the FP64 T
     const float *T32 = nullptr;

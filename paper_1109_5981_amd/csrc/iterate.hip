@@ -804,38 +804,37 @@ __device__ __forceinline__ dd group8_sum_dd(dd v) {
     return v;
 }
 
-template <int OP>
-__global__ void __launch_bounds__(CRP_NT) csr_row_pass_kernel(CsrArgs a) {
-    if (a.st->done) return;
-    __shared__ double red[CRP_NT / 64][4];
-    const int tid = threadIdx.x, g = tid / CRP_G, l = tid % CRP_G;
-    constexpr int NG = CRP_NT / CRP_G;
+// The scalars of the current iteration that the row-local update needs.
+struct RowScalars {
     double coef = 0.0, inv_alpha = 0.0, beta = 0.0, phi_rho = 0.0, theta_rho = 0.0;
     int pending = 0;
-    if (OP == OP_LSQR_TALL) coef = a.st->coef;
-    if (OP == OP_CS_TALL) coef = a.alpha;
+};
+
+template <int OP>
+__device__ __forceinline__ RowScalars row_scalars(const CsrArgs &a) {
+    RowScalars r;
+    if (OP == OP_LSQR_TALL) r.coef = a.st->coef;
+    if (OP == OP_CS_TALL) r.coef = a.alpha;
     if (OP == OP_LSQR_FAT) {
-        inv_alpha = a.st->inv_alpha;
-        beta = a.st->beta;
-        phi_rho = a.st->phi_rho;
-        theta_rho = a.st->theta_rho;
-        pending = a.st->pending;
+        r.inv_alpha = a.st->inv_alpha;
+        r.beta = a.st->beta;
+        r.phi_rho = a.st->phi_rho;
+        r.theta_rho = a.st->theta_rho;
+        r.pending = a.st->pending;
     }
-    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-    const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_block;
-    const int64_t r1 = min(a.total, r0 + a.rows_per_block);
-    for (int64_t row = r0 + g; row < r1; row += NG) {
-        double q = 0.0;
-        if (OP != OP_ATB) {
-            if (row < a.K) {
-                const int64_t e0 = a.t.ptr[row], e1 = a.t.ptr[row + 1];
-                for (int64_t e = e0 + l; e < e1; e += CRP_G) q += a.t.val[e] * a.w[a.t.idx[e]];
-                q = group8_sum(q);
-            } else {
-                q = a.lambda * a.w[row - a.K];
-            }
-        }
-        if (l != 0) continue;
+    return r;
+}
+
+// The row-local part of a pass, given q = T_row w: the same update as the
+// dense sweep's, with the partial norms in acc0 .. acc3.
+template <int OP>
+__device__ __forceinline__ void row_local(const CsrArgs &a, const RowScalars &sc, int64_t row,
+                                          double q, double &acc0, double &acc1, double &acc2,
+                                          double &acc3) {
+    const double coef = sc.coef, inv_alpha = sc.inv_alpha, beta = sc.beta;
+    const double phi_rho = sc.phi_rho, theta_rho = sc.theta_rho;
+    const int pending = sc.pending;
+    {
         if (OP == OP_ATB) {
             const double c = a.y[row];
             acc0 += c * c;
@@ -874,6 +873,13 @@ __global__ void __launch_bounds__(CRP_NT) csr_row_pass_kernel(CsrArgs a) {
             acc0 += c * c;
         }
     }
+}
+
+// The workgroup's partial norms into spart (fixed order).
+__device__ __forceinline__ void store_row_partials(const CsrArgs &a, double acc0, double acc1,
+                                                   double acc2, double acc3) {
+    __shared__ double red[CRP_NT / 64][4];
+    const int tid = threadIdx.x;
     acc0 = wave_sum(acc0);
     acc1 = wave_sum(acc1);
     acc2 = wave_sum(acc2);
@@ -888,6 +894,49 @@ __global__ void __launch_bounds__(CRP_NT) csr_row_pass_kernel(CsrArgs a) {
         for (int w = 0; w < CRP_NT / 64; ++w) t += red[w][tid];
         a.spart[(int64_t)blockIdx.x * 4 + tid] = t;
     }
+}
+
+template <int OP>
+__global__ void __launch_bounds__(CRP_NT) csr_row_pass_kernel(CsrArgs a) {
+    if (a.st->done) return;
+    const int tid = threadIdx.x, g = tid / CRP_G, l = tid % CRP_G;
+    constexpr int NG = CRP_NT / CRP_G;
+    const RowScalars sc = row_scalars<OP>(a);
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+    const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_block;
+    const int64_t r1 = min(a.total, r0 + a.rows_per_block);
+    for (int64_t row = r0 + g; row < r1; row += NG) {
+        double q = 0.0;
+        if (OP != OP_ATB) {
+            if (row < a.K) {
+                const int64_t e0 = a.t.ptr[row], e1 = a.t.ptr[row + 1];
+                for (int64_t e = e0 + l; e < e1; e += CRP_G) q += a.t.val[e] * a.w[a.t.idx[e]];
+                q = group8_sum(q);
+            } else {
+                q = a.lambda * a.w[row - a.K];
+            }
+        }
+        if (l != 0) continue;
+        row_local<OP>(a, sc, row, q, acc0, acc1, acc2, acc3);
+    }
+    store_row_partials(a, acc0, acc1, acc2, acc3);
+}
+
+// Row pass of an operator T: q = T w was formed by the caller's product
+// (qv, K rows); the Tikhonov rows give lambda w.  One thread per row.
+template <int OP>
+__global__ void __launch_bounds__(CRP_NT) op_row_pass_kernel(CsrArgs a, const double *__restrict__ qv) {
+    if (a.st->done) return;
+    const RowScalars sc = row_scalars<OP>(a);
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+    const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_block;
+    const int64_t r1 = min(a.total, r0 + a.rows_per_block);
+    for (int64_t row = r0 + threadIdx.x; row < r1; row += CRP_NT) {
+        double q = 0.0;
+        if (OP != OP_ATB) q = row < a.K ? qv[row] : a.lambda * a.w[row - a.K];
+        row_local<OP>(a, sc, row, q, acc0, acc1, acc2, acc3);
+    }
+    store_row_partials(a, acc0, acc1, acc2, acc3);
 }
 
 // Column pass over segments: zseg_g = sum of T(k, j) y_k over segment g
@@ -1004,6 +1053,7 @@ struct Ctx {
     int ngroups, chunk;
     DevBuf zpart, spart, zred, sred, z, stbuf, Pt;
     DevBuf zseg;  // sparse: per-segment column sums
+    DevBuf qv;    // operator: T w from the caller's product
     State *state;
     const double *Ptp;  // P^T, r x L row-major (ld L)
     // optional per-launch timing of the sweep kernel
@@ -1029,7 +1079,7 @@ struct Ctx {
 
     Ctx(const IterProblem &p, hipStream_t s) : pb(p), st(s) {
         L = (int)pb.cols;
-        if (pb.sp) {
+        if (pb.sp || pb.op) {
             // sparse: row-pass workgroups over the rows of T and the Tikhonov rows
             cpt = 0; R = 1;
             const int64_t total = pb.rows + (pb.lambda > 0.0 ? pb.cols : 0);
@@ -1041,7 +1091,8 @@ struct Ctx {
             ngroups = 1;
             spart.alloc((size_t)nblocks * 4 * sizeof(double));
             z.alloc((size_t)L * sizeof(double));
-            zseg.alloc((size_t)pb.sp->nseg * sizeof(double));
+            if (pb.sp) zseg.alloc((size_t)pb.sp->nseg * sizeof(double));
+            else qv.alloc((size_t)pb.rows * sizeof(double));
             stbuf.alloc(sizeof(State));
             state = stbuf.as<State>();
             Pt.alloc((size_t)std::max<int64_t>(pb.r, 1) * L * sizeof(double));
@@ -1100,6 +1151,10 @@ struct Ctx {
                double beta = 0.0) {
         if (pb.sp) {
             sweep_sparse(op, w, y, xv, wv, alpha, beta);
+            return;
+        }
+        if (pb.op) {
+            sweep_op(op, w, y, xv, wv, alpha, beta);
             return;
         }
         SweepArgs a;
@@ -1163,6 +1218,37 @@ struct Ctx {
             state);
         LSRN_HIP(hipGetLastError());
         if (profile) LSRN_HIP(hipEventRecord(e1, st));
+        reduce_spart_kernel<<<1, 256, 0, st>>>(spart.as<double>(), nblocks, state);
+        LSRN_HIP(hipGetLastError());
+    }
+
+    // Operator sweep: q = T w by the caller's product, the row pass on q,
+    // z = T^T y by the caller's product (+ lambda y of the Tikhonov rows).
+    // The products run even after the device-side done flag is set; the
+    // library's kernels then leave every vector unchanged.
+    void sweep_op(int op, const double *w, double *y, double *xv, double *wv, double alpha,
+                  double beta) {
+        CsrArgs a;
+        a.K = pb.rows;
+        a.total = pb.rows + (pb.lambda > 0.0 ? pb.cols : 0);
+        a.rows_per_block = rows_per_block; a.w = w; a.y = y; a.xv = xv; a.wv = wv;
+        a.spart = spart.as<double>(); a.st = state; a.lambda = pb.lambda; a.alpha = alpha; a.beta = beta;
+        if (op != OP_ATB) pb.op->apply_t(0, 1, w, L, qv.as<double>(), pb.rows, st);
+        const double *q = qv.as<double>();
+        switch (op) {
+            case OP_ATB: op_row_pass_kernel<OP_ATB><<<nblocks, CRP_NT, 0, st>>>(a, q); break;
+            case OP_LSQR_TALL: op_row_pass_kernel<OP_LSQR_TALL><<<nblocks, CRP_NT, 0, st>>>(a, q); break;
+            case OP_CS_TALL: op_row_pass_kernel<OP_CS_TALL><<<nblocks, CRP_NT, 0, st>>>(a, q); break;
+            case OP_NORMAL: op_row_pass_kernel<OP_NORMAL><<<nblocks, CRP_NT, 0, st>>>(a, q); break;
+            case OP_LSQR_FAT: op_row_pass_kernel<OP_LSQR_FAT><<<nblocks, CRP_NT, 0, st>>>(a, q); break;
+            default: op_row_pass_kernel<OP_CS_FAT><<<nblocks, CRP_NT, 0, st>>>(a, q); break;
+        }
+        LSRN_HIP(hipGetLastError());
+        pb.op->apply_t(1, 1, y, pb.rows, z.as<double>(), L, st);
+        if (pb.lambda > 0.0) {
+            axpby_kernel<<<grid1(L), 256, 0, st>>>(L, pb.lambda, y + pb.rows, 1.0, z.as<double>());
+            LSRN_HIP(hipGetLastError());
+        }
         reduce_spart_kernel<<<1, 256, 0, st>>>(spart.as<double>(), nblocks, state);
         LSRN_HIP(hipGetLastError());
     }
@@ -1434,7 +1520,8 @@ IterResult iterate_on(const IterProblem &pb, const double *b, double *x, const l
     IterResult res;
     Ctx cx(pb, st);
     cx.profile = opt.profile != 0;
-    cx.use_graphs = !cx.profile && st != nullptr && graphs_allowed();
+    // the caller's products of an operator may do anything on the stream
+    cx.use_graphs = !cx.profile && st != nullptr && graphs_allowed() && !pb.op;
     double sl = 0.0, su = 0.0;
     const int64_t maxiter = default_maxiter(pb, opt, sl, su);
     res.sigma_l = sl;
@@ -1620,7 +1707,9 @@ IterResult iterate_on(const IterProblem &pb, const double *b, double *x, const l
 
 IterResult iterate(const IterProblem &pb, const double *b, double *x, const lsrn_options &opt,
                    hipStream_t st) {
-    if (st) return iterate_on(pb, b, x, opt, st);
+    // an operator's products are promised the caller's stream, and its
+    // iterations are never captured
+    if (st || pb.op) return iterate_on(pb, b, x, opt, st);
     // the null stream cannot be captured into graphs: run on a stream of our
     // own (default priority) after the caller's work on the null stream
     LSRN_HIP(hipStreamSynchronize(nullptr));
@@ -1636,6 +1725,15 @@ IterResult iterate(const IterProblem &pb, const double *b, double *x, const lsrn
         (void)hipStreamDestroy(own);
         throw;
     }
+}
+
+void OpView::apply_t(int t, int64_t k, const double *in, int64_t ldin, double *out, int64_t ldout,
+                     hipStream_t st) const {
+    // T = A (m >= n) or A^T: T in is A in or A^T in
+    const int trans = (m >= n) ? t : 1 - t;
+    if (fn(ctx, trans, k, in, ldin, out, ldout, (void *)st) != 0)
+        fail(LSRN_E_INVALID, "the operator's product routine returned an error");
+    LSRN_HIP(hipGetLastError());
 }
 
 // ------------------------------------------------------- batched LSQR

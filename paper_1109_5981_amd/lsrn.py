@@ -66,7 +66,10 @@ SERVER_EXPORTS = ["lsrn_server_create", "lsrn_server_submit_dense", "lsrn_server
 EXPORTS = EXPORTS + SERVER_EXPORTS
 PLAN_EXPORTS = ["lsrn_plan_create_dense", "lsrn_plan_create_csr", "lsrn_plan_solve",
                 "lsrn_plan_destroy"]
-EXPORTS = EXPORTS + PLAN_EXPORTS
+EXPORTS = EXPORTS + PLAN_EXPORTS + ["lsrn_solve_op"]
+# lsrn_apply_fn: (ctx, trans, k, in, ldin, out, ldout, stream) -> int
+APPLY_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_int64,
+                       C.c_void_p, C.c_int64, C.c_void_p)
 PRECOND = {"auto": 0, "svd": 1, "qr": 2}
 PRECISION = {"fp64": 0, "mixed": 1}
 _SIZE_FNS = ("lsrn_default_options", "lsrn_status_string", "lsrn_last_error",
@@ -129,6 +132,8 @@ def lib():
         L.lsrn_plan_solve.argtypes = [P, P, P, C.POINTER(Options), C.POINTER(Info), P]
         L.lsrn_plan_destroy.argtypes = [P]
         L.lsrn_plan_destroy.restype = None
+        L.lsrn_solve_op.argtypes = [I64, I64, APPLY_FN, P, P, P, C.POINTER(Options),
+                                    C.POINTER(Info), P]
         for name in EXPORTS:
             if name not in _SIZE_FNS:
                 getattr(L, name).restype = C.c_int
@@ -351,6 +356,54 @@ def iterate_csr(A: Csr, b: torch.Tensor, P: torch.Tensor, s: int, **opts):
     _check(lib().lsrn_iterate_csr(*A.args(), b.data_ptr(), P.data_ptr(), P.stride(0), P.shape[1], s,
                                   x.data_ptr(), C.byref(o), C.byref(info), _stream()))
     return x, info.as_dict()
+
+
+class _DeviceArray:
+    """A device pointer described by the CUDA array interface."""
+
+    def __init__(self, ptr: int, shape, strides):
+        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": "<f8",
+                                         "data": (int(ptr), False), "version": 2,
+                                         "strides": tuple(strides)}
+
+
+def device_view(ptr: int, rows: int, cols: int, ld: int) -> torch.Tensor:
+    """A column-major rows x cols FP64 array at a device pointer (leading
+    dimension ld) as a torch tensor of shape (rows, cols), without a copy."""
+    if cols == 0 or rows == 0:
+        return torch.empty((rows, cols), dtype=torch.float64, device="cuda")
+    t = torch.as_tensor(_DeviceArray(ptr, (cols, rows), (ld * 8, 8)), device="cuda")
+    return t.T
+
+
+def solve_op(m: int, n: int, apply, b: torch.Tensor, x: torch.Tensor | None = None, *,
+             allow_not_converged: bool = False, **opts):
+    """lsrn_solve_op: A (m x n) given by apply(trans, k, in_ptr, ldin, out_ptr,
+    ldout, stream) -> 0 on success, which writes out = A in (trans 0) or
+    A^T in (trans 1) for k column-major columns.  Returns (x, info)."""
+    _dev_f64(b, "b")
+    if b.numel() != m or not b.is_contiguous():
+        raise ValueError("b must be contiguous with m entries")
+    if x is None:
+        x = torch.empty(n, dtype=torch.float64, device=b.device)
+
+    def trampoline(ctx, trans, k, pin, ldin, pout, ldout, stream):
+        try:
+            return int(apply(int(trans), int(k), pin, int(ldin), pout, int(ldout), stream) or 0)
+        except Exception:  # an error must not cross the C boundary as a silent 0
+            import traceback
+            traceback.print_exc()
+            return 1
+
+    cb = APPLY_FN(trampoline)
+    o, info = options(**opts), Info()
+    st = lib().lsrn_solve_op(m, n, cb, None, b.data_ptr(), x.data_ptr(), C.byref(o), C.byref(info),
+                             _stream())
+    if not (allow_not_converged and st == 4):
+        _check(st)
+    out = info.as_dict()
+    out["status"] = int(st)
+    return x, out
 
 
 class Plan:
