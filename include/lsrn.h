@@ -108,7 +108,10 @@ typedef struct lsrn_options {
                           t_*_kernel_ms); 0                                     */
     int32_t precond;   /* lsrn_precond_kind; LSRN_PRECOND_AUTO                 */
     int32_t precision; /* lsrn_precision; LSRN_PREC_FP64                       */
-    int32_t reserved[1];
+    int32_t autotune;  /* nonzero: the first solve of a new shape key times
+                          the candidate launch shapes of the dense sweep and
+                          records the fastest (see lsrn_tune_export); zero:
+                          recorded shapes if any, else the built-in ones; 0 */
 } lsrn_options;
 
 typedef struct lsrn_info {
@@ -278,6 +281,30 @@ lsrn_status lsrn_solve_batch(int32_t count, const int64_t *m, const int64_t *n,
                              const double *const *A, const int64_t *lda, const double *const *b,
                              double *const *x, const lsrn_options *opt, lsrn_info *infos,
                              void *stream);
+
+/* ------------------------------------------------------------------------
+ * Launch-shape tuning table (not a paper passage).  Keys are (phase, dtype,
+ * rows bucket, cols): phase "sweep" is the fused pass over dense A, dtype
+ * "f64" or "f32" (precision form), rows bucket = ceil(log2(rows of the tall
+ * view)), cols = d.  The value is the number of sweep workgroups per
+ * compute unit.  Entries are made by solves with opt->autotune set and used
+ * by every later solve in the process; the choice changes only the
+ * summation order of the sweep's partial sums, so importing a table
+ * reproduces results across processes.  The table is process-wide and
+ * guarded by a mutex.
+ * ---------------------------------------------------------------------- */
+
+/* Write the table as text, one "phase dtype rows_log2 cols value" line per
+ * entry, into buf (len bytes, NUL-terminated when it fits); returns the
+ * length the text needs including the NUL. */
+size_t lsrn_tune_export(char *buf, size_t len);
+
+/* Add the entries of such a text (replacing equal keys); LSRN_E_INVALID on
+ * a malformed line (then nothing is added). */
+lsrn_status lsrn_tune_import(const char *text);
+
+/* Forget every entry. */
+void lsrn_tune_clear(void);
 
 /* ------------------------------------------------------------------------
  * A given only through products (Sec. 1 and 4: LSRN needs A only through

@@ -130,6 +130,18 @@ void trtri_upper(int64_t d, const double *R, int64_t ldr, double *Rinv, int64_t 
 // The operator of the iteration phase.  Tall: T = A row-major (rows = m,
 // cols = n) with optional lambda rows; Fat: T = A^T row-major (rows = n,
 // cols = m).  P is d x r row-major (leading dim ldp), d = cols of T.
+// ------------------------------------------------------------ tune.hip
+enum TunePhase { TUNE_SWEEP = 0 };
+struct TuneKey {
+    int phase = TUNE_SWEEP;
+    int dtype = 0;      // 0: FP64 sweeps, 1: FP32 (precision form)
+    int rows_log2 = 0;  // ceil(log2(rows of the tall view))
+    int64_t cols = 0;
+};
+int rows_bucket(int64_t rows);
+bool tune_lookup(const TuneKey &k, int &value);
+void tune_store(const TuneKey &k, int value);
+
 // A matrix given only through the caller's product routine: out = op(A) in
 // for k columns (trans = 0: A, trans = 1: A^T), m x n.
 struct OpView {

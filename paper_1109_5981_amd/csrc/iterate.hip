@@ -1077,7 +1077,7 @@ struct Ctx {
         return t;
     }
 
-    Ctx(const IterProblem &p, hipStream_t s) : pb(p), st(s) {
+    Ctx(const IterProblem &p, hipStream_t s, bool autotune = false) : pb(p), st(s) {
         L = (int)pb.cols;
         if (pb.sp || pb.op) {
             // sparse: row-pass workgroups over the rows of T and the Tikhonov rows
@@ -1105,12 +1105,19 @@ struct Ctx {
         else if (L <= 2048) { cpt = 8; R = 4; }
         else if (L <= 4096) { cpt = 16; R = 2; }
         else fail(LSRN_E_UNSUPPORTED, "dense iteration supports min(m, n) <= 4096");
-        const int64_t want = 2 * (int64_t)device_cus();
-        nblocks = (int)std::max<int64_t>(1, std::min<int64_t>(want, ceil_div(pb.rows, R)));
-        rows_per_block = round_up(ceil_div(pb.rows, nblocks), R);
-        nblocks = (int)std::max<int64_t>(1, ceil_div(pb.rows, rows_per_block));
+        // workgroups per compute unit: a recorded (tuned) value for this
+        // shape key, else 2; with autotune and no record, every candidate is
+        // timed below on this problem and the fastest recorded
+        TuneKey key;
+        key.phase = TUNE_SWEEP;
+        key.dtype = pb.T32 ? 1 : 0;
+        key.rows_log2 = rows_bucket(pb.rows);
+        key.cols = L;
+        int per_cu = 2;
+        const bool recorded = tune_lookup(key, per_cu);
+        const bool tune = autotune && !recorded;
         chunk = 16;
-        ngroups = (int)ceil_div(nblocks, chunk);
+        shape(tune ? kMaxPerCu : per_cu);
         zpart.alloc((size_t)nblocks * L * sizeof(double));
         spart.alloc((size_t)nblocks * 4 * sizeof(double));
         zred.alloc((size_t)ngroups * L * sizeof(double));
@@ -1122,6 +1129,52 @@ struct Ctx {
         Pt.alloc((size_t)std::max<int64_t>(pb.r, 1) * L * sizeof(double));
         transpose(L, pb.r, pb.P, pb.ldp, Pt.as<double>(), st);
         Ptp = Pt.as<double>();
+        if (tune) per_cu = tune_sweep(key);
+        shape(per_cu);
+    }
+
+    static constexpr int kMaxPerCu = 4;
+
+    // Dense sweep launch shape for `per_cu` workgroups per compute unit.
+    void shape(int per_cu) {
+        const int64_t want = (int64_t)per_cu * device_cus();
+        nblocks = (int)std::max<int64_t>(1, std::min<int64_t>(want, ceil_div(pb.rows, R)));
+        rows_per_block = round_up(ceil_div(pb.rows, nblocks), R);
+        nblocks = (int)std::max<int64_t>(1, ceil_div(pb.rows, rows_per_block));
+        ngroups = (int)ceil_div(nblocks, chunk);
+    }
+
+    // Time the normal-equation sweep (one pass over A, the iterations' pass)
+    // for 1 .. kMaxPerCu workgroups per compute unit on this problem,
+    // record the fastest for the shape key and return it.
+    int tune_sweep(const TuneKey &key) {
+        DevBuf wb((size_t)L * sizeof(double)), yb((size_t)pb.rows * sizeof(double));
+        fill_kernel<<<grid1(L), 256, 0, st>>>(L, 0.0, wb.as<double>());
+        LSRN_HIP(hipGetLastError());
+        hipEvent_t e0, e1;
+        LSRN_HIP(hipEventCreate(&e0));
+        LSRN_HIP(hipEventCreate(&e1));
+        int best = 2;
+        float best_ms = 0.f;
+        for (int c = 1; c <= kMaxPerCu; ++c) {
+            shape(c);
+            reset_state(1);
+            sweep(OP_NORMAL, wb.as<double>(), yb.as<double>(), nullptr, nullptr);
+            LSRN_HIP(hipEventRecord(e0, st));
+            for (int k = 0; k < 3; ++k) sweep(OP_NORMAL, wb.as<double>(), yb.as<double>(), nullptr, nullptr);
+            LSRN_HIP(hipEventRecord(e1, st));
+            LSRN_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            LSRN_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (c == 1 || ms < best_ms) {
+                best = c;
+                best_ms = ms;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        tune_store(key, best);
+        return best;
     }
 
     void reset_state(int maxiter) {
@@ -1518,7 +1571,7 @@ namespace {
 IterResult iterate_on(const IterProblem &pb, const double *b, double *x, const lsrn_options &opt,
                       hipStream_t st) {
     IterResult res;
-    Ctx cx(pb, st);
+    Ctx cx(pb, st, opt.autotune != 0);
     cx.profile = opt.profile != 0;
     // the caller's products of an operator may do anything on the stream
     cx.use_graphs = !cx.profile && st != nullptr && graphs_allowed() && !pb.op;

@@ -33,7 +33,7 @@ class Options(C.Structure):
                 ("rcond", C.c_double), ("t_margin", C.c_double), ("refine_tol", C.c_double),
                 ("seed", C.c_uint64), ("max_iter", C.c_int64), ("method", C.c_int32),
                 ("refine", C.c_int32), ("profile", C.c_int32), ("precond", C.c_int32),
-                ("precision", C.c_int32), ("reserved", C.c_int32 * 1)]
+                ("precision", C.c_int32), ("autotune", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -66,7 +66,8 @@ SERVER_EXPORTS = ["lsrn_server_create", "lsrn_server_submit_dense", "lsrn_server
 EXPORTS = EXPORTS + SERVER_EXPORTS
 PLAN_EXPORTS = ["lsrn_plan_create_dense", "lsrn_plan_create_csr", "lsrn_plan_solve",
                 "lsrn_plan_destroy"]
-EXPORTS = EXPORTS + PLAN_EXPORTS + ["lsrn_solve_op"]
+EXPORTS = EXPORTS + PLAN_EXPORTS + ["lsrn_solve_op", "lsrn_tune_export", "lsrn_tune_import",
+                                     "lsrn_tune_clear"]
 # lsrn_apply_fn: (ctx, trans, k, in, ldin, out, ldout, stream) -> int
 APPLY_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_int64,
                        C.c_void_p, C.c_int64, C.c_void_p)
@@ -74,7 +75,7 @@ PRECOND = {"auto": 0, "svd": 1, "qr": 2}
 PRECISION = {"fp64": 0, "mixed": 1}
 _SIZE_FNS = ("lsrn_default_options", "lsrn_status_string", "lsrn_last_error",
              "lsrn_workspace_bytes", "lsrn_workspace_bytes_csr", "lsrn_server_last_error",
-             "lsrn_server_destroy", "lsrn_plan_destroy")
+             "lsrn_server_destroy", "lsrn_plan_destroy", "lsrn_tune_export", "lsrn_tune_clear")
 
 
 class ServerTiming(C.Structure):
@@ -134,6 +135,11 @@ def lib():
         L.lsrn_plan_destroy.restype = None
         L.lsrn_solve_op.argtypes = [I64, I64, APPLY_FN, P, P, P, C.POINTER(Options),
                                     C.POINTER(Info), P]
+        L.lsrn_tune_export.argtypes = [C.c_char_p, C.c_size_t]
+        L.lsrn_tune_export.restype = C.c_size_t
+        L.lsrn_tune_import.argtypes = [C.c_char_p]
+        L.lsrn_tune_clear.argtypes = []
+        L.lsrn_tune_clear.restype = None
         for name in EXPORTS:
             if name not in _SIZE_FNS:
                 getattr(L, name).restype = C.c_int
@@ -356,6 +362,22 @@ def iterate_csr(A: Csr, b: torch.Tensor, P: torch.Tensor, s: int, **opts):
     _check(lib().lsrn_iterate_csr(*A.args(), b.data_ptr(), P.data_ptr(), P.stride(0), P.shape[1], s,
                                   x.data_ptr(), C.byref(o), C.byref(info), _stream()))
     return x, info.as_dict()
+
+
+def tune_export() -> str:
+    """The launch-shape tuning table as text (lsrn_tune_export)."""
+    need = lib().lsrn_tune_export(None, 0)
+    buf = C.create_string_buffer(need)
+    lib().lsrn_tune_export(buf, need)
+    return buf.value.decode()
+
+
+def tune_import(text: str) -> None:
+    _check(lib().lsrn_tune_import(text.encode()))
+
+
+def tune_clear() -> None:
+    lib().lsrn_tune_clear()
 
 
 class _DeviceArray:

@@ -52,3 +52,26 @@ def test_default_options_and_struct_layout():
     assert L.lsrn_status_string(5) == b"unsupported"
     # host-only size query
     assert lsrn.workspace_bytes(200000, 2000) > 200000 * 8
+
+
+def test_tune_table_round_trip():
+    """The launch-shape table's text form (host only, no GPU needed)."""
+    if not os.path.exists(LIB):
+        pytest.skip("liblsrn.so not built")
+    from paper_1109_5981_amd import lsrn
+    lsrn.tune_clear()
+    assert lsrn.tune_export() == ""
+    lsrn.tune_import("sweep f64 18 2000 3\nsweep f32 20 4000 1\n\n")
+    text = lsrn.tune_export()
+    assert sorted(text.strip().splitlines()) == ["sweep f32 20 4000 1", "sweep f64 18 2000 3"]
+    # an equal key is replaced
+    lsrn.tune_import("sweep f64 18 2000 2")
+    assert "sweep f64 18 2000 2" in lsrn.tune_export()
+    # malformed input adds nothing
+    for bad in ("sweep f64 18", "sweep f16 18 2000 2", "qr f64 18 2000 2", "sweep f64 18 2000 0",
+                "sweep f64 18 2000 2 extra"):
+        with pytest.raises(lsrn.LSRNError):
+            lsrn.tune_import(bad + "\nsweep f64 5 5 5")
+        assert "sweep f64 5 5 5" not in lsrn.tune_export()
+    lsrn.tune_clear()
+    assert lsrn.tune_export() == ""
