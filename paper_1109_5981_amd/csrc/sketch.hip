@@ -16,12 +16,15 @@ namespace {
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 constexpr int BM = 128;   // rows of X (sketch rows i) per workgroup
-constexpr int BN = 128;   // cols of X per workgroup
 constexpr int KT = 16;    // k per LDS stage (four MFMA k-steps)
 constexpr int LDP = 144;  // LDS row pitch in doubles: 144*2 = 288 = 32 (mod 64)
                           // dwords, so the four 16-lane groups of a wave read
                           // two disjoint bank halves
-constexpr int NT = 256;
+// A workgroup is 2 x WN wavefronts of 64 x 64 each: 128 x 64 WN of X, so
+// each generated slice of G serves 64 WN columns.
+template <int WN> constexpr int BN_ = 64 * WN;          // cols of X per workgroup
+template <int WN> constexpr int NT_ = 128 * WN;         // threads
+template <int WN> constexpr int TP_ = 64 * WN + 16;     // pitch of the T tile (same banks)
 
 // One MFMA 16x16x4 f64 step: lane l supplies A[l%16][l/16] (a 16x4 slice of
 // G) and B[l/16][l%16] (a 4x16 slice of T); the 16x16 accumulator holds
@@ -33,14 +36,16 @@ __device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c) {
 // G(i, k) for the 128 rows of the tile and the 16 k of one stage:
 // 128 rows x 4 Philox blocks; thread t takes row t%128 and blocks
 // (t/128) and (t/128)+2 of the stage.
+template <int WN>
 __device__ __forceinline__ void gen_g_stage(double (*Gs)[LDP], uint64_t seed, int64_t m0,
                                             int64_t kstage) {
+    constexpr int GROUPS = NT_<WN> / BM;  // threads per row of the slice
     const int t = threadIdx.x;
     const int row = t & (BM - 1);
-    const int qb = t >> 7;  // 0 or 1
+    const int qb = t >> 7;  // 0 .. GROUPS - 1
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int qloc = qb + 2 * h;  // 0..3
+    for (int h = 0; h < 4 / GROUPS; ++h) {
+        const int qloc = qb + GROUPS * h;  // 0..3
         double g[4];
         gauss4(seed, (uint64_t)(m0 + row), (uint64_t)((kstage >> 2) + qloc), g);
 #pragma unroll
@@ -48,17 +53,18 @@ __device__ __forceinline__ void gen_g_stage(double (*Gs)[LDP], uint64_t seed, in
     }
 }
 
-// 16 rows x 128 columns of T for one stage into registers (zero outside
-// [k0, kend) x [0, d)).
-template <bool VEC2>
+// 16 rows x BN columns of T for one stage into registers (zero outside
+// [k0, kend) x [0, d)): four double2 per thread.
+template <int WN, bool VEC2>
 __device__ __forceinline__ void load_t_stage(const double *__restrict__ T, int64_t ldt,
                                              int64_t kstage, int64_t kend, int64_t n0, int64_t d,
                                              double2 (&reg)[4]) {
+    constexpr int HALF = BN_<WN> / 2;  // double2 per row of the tile
 #pragma unroll
     for (int it = 0; it < 4; ++it) {
-        const int idx = it * NT + threadIdx.x;
-        const int kk = idx >> 6;          // 0..15
-        const int c2 = (idx & 63) * 2;    // 0..126
+        const int idx = it * NT_<WN> + threadIdx.x;
+        const int kk = idx / HALF;         // 0..15
+        const int c2 = (idx % HALF) * 2;   // 0..BN-2
         const int64_t k = kstage + kk, col = n0 + c2;
         double2 v = make_double2(0.0, 0.0);
         if (k < kend) {
@@ -74,32 +80,34 @@ __device__ __forceinline__ void load_t_stage(const double *__restrict__ T, int64
     }
 }
 
-__device__ __forceinline__ void store_t_stage(double (*Ts)[LDP], const double2 (&reg)[4]) {
+template <int WN>
+__device__ __forceinline__ void store_t_stage(double (*Ts)[TP_<WN>], const double2 (&reg)[4]) {
+    constexpr int HALF = BN_<WN> / 2;
 #pragma unroll
     for (int it = 0; it < 4; ++it) {
-        const int idx = it * NT + threadIdx.x;
-        const int kk = idx >> 6, c2 = (idx & 63) * 2;
+        const int idx = it * NT_<WN> + threadIdx.x;
+        const int kk = idx / HALF, c2 = (idx % HALF) * 2;
         Ts[kk][c2] = reg[it].x;
         Ts[kk][c2 + 1] = reg[it].y;
     }
 }
 
-template <bool VEC2>
-__global__ void __launch_bounds__(NT, 2)
+template <int WN, bool VEC2>
+__global__ void __launch_bounds__(NT_<WN>, 4 / WN)
 sketch_mfma_kernel(const double *__restrict__ T, int64_t ldt, int64_t K, int64_t d, int64_t s,
                    uint64_t seed, int64_t k_per_split, int tiles_m, double *__restrict__ Xp) {
     __shared__ double Gs[2][KT][LDP];
-    __shared__ double Ts[2][KT][LDP];
+    __shared__ double Ts[2][KT][TP_<WN>];
 
     const int tile = blockIdx.x;
     const int64_t m0 = (int64_t)(tile % tiles_m) * BM;
-    const int64_t n0 = (int64_t)(tile / tiles_m) * BN;
+    const int64_t n0 = (int64_t)(tile / tiles_m) * BN_<WN>;
     const int64_t kbeg = (int64_t)blockIdx.y * k_per_split;
     const int64_t kend = min(K, kbeg + k_per_split);
     double *__restrict__ Xout = Xp + (int64_t)blockIdx.y * s * d;
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
+    const int wm = wave / WN, wn = wave % WN;
     const int lr = lane & 15, lk = lane >> 4;
 
     f64x4 acc[4][4];
@@ -111,9 +119,9 @@ sketch_mfma_kernel(const double *__restrict__ T, int64_t ldt, int64_t K, int64_t
     const int64_t nstage = kend > kbeg ? ceil_div(kend - kbeg, KT) : 0;
     double2 treg[4];
     if (nstage > 0) {
-        gen_g_stage(Gs[0], seed, m0, kbeg);
-        load_t_stage<VEC2>(T, ldt, kbeg, kend, n0, d, treg);
-        store_t_stage(Ts[0], treg);
+        gen_g_stage<WN>(Gs[0], seed, m0, kbeg);
+        load_t_stage<WN, VEC2>(T, ldt, kbeg, kend, n0, d, treg);
+        store_t_stage<WN>(Ts[0], treg);
     }
     __syncthreads();
 
@@ -121,7 +129,7 @@ sketch_mfma_kernel(const double *__restrict__ T, int64_t ldt, int64_t K, int64_t
         const int buf = (int)(st & 1);
         const bool more = st + 1 < nstage;
         const int64_t knext = kbeg + (st + 1) * KT;
-        if (more) load_t_stage<VEC2>(T, ldt, knext, kend, n0, d, treg);
+        if (more) load_t_stage<WN, VEC2>(T, ldt, knext, kend, n0, d, treg);
 #pragma unroll
         for (int kk = 0; kk < KT / 4; ++kk) {
             double a[4], b[4];
@@ -135,8 +143,8 @@ sketch_mfma_kernel(const double *__restrict__ T, int64_t ldt, int64_t K, int64_t
                 for (int j = 0; j < 4; ++j) acc[i][j] = mfma16(a[i], b[j], acc[i][j]);
         }
         if (more) {
-            gen_g_stage(Gs[buf ^ 1], seed, m0, knext);
-            store_t_stage(Ts[buf ^ 1], treg);
+            gen_g_stage<WN>(Gs[buf ^ 1], seed, m0, knext);
+            store_t_stage<WN>(Ts[buf ^ 1], treg);
         }
         __syncthreads();
     }
@@ -201,16 +209,21 @@ transpose_kernel(int64_t rows, int64_t cols, const double *__restrict__ in, int6
 }
 
 struct SketchPlan {
-    int tiles_m, tiles_n, nsplit;
+    int wn, tiles_m, tiles_n, nsplit;
     int64_t k_per_split;
 };
 
+// The wide tile (4 wavefronts across, one workgroup per CU) halves the
+// regeneration of G when it alone gives every CU a tile; else the narrow
+// tile (two workgroups per CU), with split-K when even that is too few.
 SketchPlan plan_sketch(int64_t K, int64_t d, int64_t s) {
     SketchPlan p;
+    const int64_t cus = device_cus();
+    p.wn = ceil_div(s, BM) * ceil_div(d, 256) >= cus ? 4 : 2;
     p.tiles_m = (int)ceil_div(s, BM);
-    p.tiles_n = (int)ceil_div(d, BN);
+    p.tiles_n = (int)ceil_div(d, 64 * p.wn);
     const int64_t tiles = (int64_t)p.tiles_m * p.tiles_n;
-    const int64_t want = 2 * (int64_t)device_cus();  // two workgroups per CU
+    const int64_t want = (p.wn == 4 ? 1 : 2) * cus;  // resident workgroups
     int64_t nsplit = tiles >= want ? 1 : ceil_div(want, tiles);
     // keep at least 8 stages per slice and the partial sums under 2 GiB
     nsplit = std::min<int64_t>(nsplit, std::max<int64_t>(1, K / (8 * KT)));
@@ -246,12 +259,21 @@ void sketch_rows(int64_t K, int64_t d, const double *T, int64_t ldt, double lamb
         LSRN_HIP(hipEventCreate(&ev[1]));
         LSRN_HIP(hipEventRecord(ev[0], st));
     }
-    if (vec2)
-        sketch_mfma_kernel<true><<<grid, NT, 0, st>>>(T, ldt, K, d, s, seed, p.k_per_split,
-                                                      p.tiles_m, Xp);
-    else
-        sketch_mfma_kernel<false><<<grid, NT, 0, st>>>(T, ldt, K, d, s, seed, p.k_per_split,
-                                                       p.tiles_m, Xp);
+    if (p.wn == 4) {
+        if (vec2)
+            sketch_mfma_kernel<4, true><<<grid, NT_<4>, 0, st>>>(T, ldt, K, d, s, seed, p.k_per_split,
+                                                                p.tiles_m, Xp);
+        else
+            sketch_mfma_kernel<4, false><<<grid, NT_<4>, 0, st>>>(T, ldt, K, d, s, seed, p.k_per_split,
+                                                                 p.tiles_m, Xp);
+    } else {
+        if (vec2)
+            sketch_mfma_kernel<2, true><<<grid, NT_<2>, 0, st>>>(T, ldt, K, d, s, seed, p.k_per_split,
+                                                                p.tiles_m, Xp);
+        else
+            sketch_mfma_kernel<2, false><<<grid, NT_<2>, 0, st>>>(T, ldt, K, d, s, seed, p.k_per_split,
+                                                                 p.tiles_m, Xp);
+    }
     LSRN_HIP(hipGetLastError());
     if (kernel_ms) {
         LSRN_HIP(hipEventRecord(ev[1], st));

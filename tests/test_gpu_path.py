@@ -87,6 +87,24 @@ def test_sketch_matches_oracle(L, orc, m, n, layout, lam, s):
     assert np.all(np.abs(Xg - Xo) <= bound)
 
 
+def test_sketch_wide_tiles_sampled(L, orc):
+    """Sizes whose tile grid fills the chip take the wide (2 x 4 wavefront)
+    tiles; entries recomputed one by one by the oracle's G and exact sums."""
+    import math
+    K, d, s, seed = 3000, 2048, 4096, 77
+    rng = np.random.default_rng(5)
+    T = rng.standard_normal((K, d))
+    X = host(L.sketch_dense(dev(T), s, seed=seed)).T        # s x d
+    eps = np.finfo(float).eps
+    picks = [(0, 0), (s - 1, d - 1), (127, 255), (128, 256), (4000, 1000)]
+    picks += [(int(i), int(c)) for i, c in zip(rng.integers(0, s, 60), rng.integers(0, d, 60))]
+    for i, c in picks:
+        g = orc.gauss_fill(seed, i, 1, 0, K)[0]
+        ref = math.fsum(g * T[:, c])
+        bound = 2 * K * eps * (np.abs(g) @ np.abs(T[:, c])) + 1e-14
+        assert abs(X[i, c] - ref) <= bound, (i, c, X[i, c], ref)
+
+
 # ---------------------------------------------------------------- steps 4-5
 
 @pytest.mark.parametrize("s,d,rank", [(200, 100, 100), (263, 131, 131), (500, 240, 200),
