@@ -23,6 +23,7 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <type_traits>
 #include <vector>
 
 #include "internal.hpp"
@@ -77,8 +78,17 @@ __device__ __forceinline__ int col_of(int tid, int e) {
     return 2 * tid + 512 * (e >> 1) + (e & 1);
 }
 
+// Column of element e of a thread when each thread holds groups of W
+// consecutive columns (W = 2: double2 loads, W = 4: float4 loads).
+template <int W>
+__device__ __forceinline__ int col_of_w(int tid, int e) {
+    return W * tid + (NT * W) * (e / W) + (e % W);
+}
+
 template <int CPT, int R, int OP, bool F32>
 __device__ __forceinline__ void sweep_body(const SweepArgs &a, const int block) {
+    // FP32 rows load as float4 (16 bytes a lane, like the FP64 double2)
+    constexpr int W = (F32 && CPT >= 4) ? 4 : 2;
     if (a.st->done) return;
     __shared__ double red[2][NT / 64][R];
     __shared__ double accred[NT / 64][4];
@@ -88,7 +98,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const int block) 
     double wr[CPT], zr[CPT];
 #pragma unroll
     for (int e = 0; e < CPT; ++e) {
-        const int col = col_of<CPT>(tid, e);
+        const int col = col_of_w<W>(tid, e);
         wr[e] = (OP != OP_ATB && col < L) ? a.w[col] : 0.0;
         zr[e] = 0.0;
     }
@@ -108,30 +118,57 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const int block) 
 
     const int64_t r0 = (int64_t)block * a.rows_per_block;
     const int64_t r1 = min(a.rows, r0 + a.rows_per_block);
-    const bool vec2 = F32 ? (((a.ldt & 1) == 0) && ((reinterpret_cast<uintptr_t>(a.T32) & 7) == 0))
+    const bool vec2 = F32 ? (((a.ldt & (W - 1)) == 0) &&
+                             ((reinterpret_cast<uintptr_t>(a.T32) & (4 * W - 1)) == 0))
                           : (((a.ldt & 1) == 0) && ((reinterpret_cast<uintptr_t>(a.T) & 15) == 0));
-    // R rows of T (and of the per-row vector) starting at j0 into registers
-    // (FP32 storage is widened to FP64 on load)
-    auto load_rows = [&](int64_t j0, double (&av)[R][CPT], double (&yv)[R]) {
+    // R rows of T (and of the per-row vector) starting at j0 into registers;
+    // FP32 storage stays FP32 in registers (half the registers per byte in
+    // flight) and is widened where it is used
+    using E = std::conditional_t<F32, float, double>;
+    auto load_rows = [&](int64_t j0, E (&av)[R][CPT], double (&yv)[R]) {
 #pragma unroll
         for (int rr = 0; rr < R; ++rr) {
             const int64_t row = j0 + rr;
             const bool valid = row < r1;
+            if constexpr (W == 4) {
+#pragma unroll
+                for (int e = 0; e < CPT; e += 4) {
+                    const int col = col_of_w<W>(tid, e);
+                    float4 f = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (valid) {
+                        const float *trow = a.T32 + row * a.ldt;
+                        if (vec2 && col + 3 < L) {
+                            f = *reinterpret_cast<const float4 *>(trow + col);
+                        } else {
+                            if (col < L) f.x = trow[col];
+                            if (col + 1 < L) f.y = trow[col + 1];
+                            if (col + 2 < L) f.z = trow[col + 2];
+                            if (col + 3 < L) f.w = trow[col + 3];
+                        }
+                    }
+                    av[rr][e] = f.x;
+                    av[rr][e + 1] = f.y;
+                    av[rr][e + 2] = f.z;
+                    av[rr][e + 3] = f.w;
+                }
+            } else {
 #pragma unroll
             for (int e = 0; e < CPT; e += 2) {
-                const int col = col_of<CPT>(tid, e);
-                double2 v = make_double2(0.0, 0.0);
+                const int col = col_of_w<W>(tid, e);
+                E vx = 0, vy = 0;
                 if (valid) {
-                    if (F32) {
+                    if constexpr (F32) {
                         const float *trow = a.T32 + row * a.ldt;
                         if (vec2 && col + 1 < L) {
                             const float2 f = *reinterpret_cast<const float2 *>(trow + col);
-                            v = make_double2((double)f.x, (double)f.y);
+                            vx = f.x;
+                            vy = f.y;
                         } else {
-                            if (col < L) v.x = (double)trow[col];
-                            if (col + 1 < L) v.y = (double)trow[col + 1];
+                            if (col < L) vx = trow[col];
+                            if (col + 1 < L) vy = trow[col + 1];
                         }
                     } else {
+                        double2 v = make_double2(0.0, 0.0);
                         const double *trow = a.T + row * a.ldt;
                         if (vec2 && col + 1 < L) {
                             v = *reinterpret_cast<const double2 *>(trow + col);
@@ -139,29 +176,45 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const int block) 
                             if (col < L) v.x = trow[col];
                             if (col + 1 < L) v.y = trow[col + 1];
                         }
+                        vx = v.x;
+                        vy = v.y;
                     }
                 }
-                av[rr][e] = v.x;
-                av[rr][e + 1] = v.y;
+                av[rr][e] = vx;
+                av[rr][e + 1] = vy;
+            }
             }
             yv[rr] = (valid && OP != OP_NORMAL) ? a.y[row] : 0.0;
         }
     };
-    // software pipeline: the loads of step k+1 are in flight while step k
-    // reduces and updates
-    double avn[R][CPT], yvn[R];
+    // software pipeline: the loads of the next DEPTH steps are in flight
+    // while step k reduces and updates (two steps ahead where the register
+    // budget allows it; FP32 rows take half the registers, so the FP32 form
+    // keeps as many bytes in flight as the FP64 one)
+    constexpr int DEPTH = (F32 ? CPT * R / 2 : CPT * R) <= 16 ? 2 : 1;
+    E avn[R][CPT], avm[R][CPT];
+    double yvn[R], yvm[R];
     if (r0 < r1) load_rows(r0, avn, yvn);
+    if (DEPTH == 2 && r0 + R < r1) load_rows(r0 + R, avm, yvm);
     int parity = 0;
     for (int64_t j0 = r0; j0 < r1; j0 += R) {
-        double av[R][CPT];
+        E av[R][CPT];
         double yv[R];
 #pragma unroll
         for (int rr = 0; rr < R; ++rr) {
             yv[rr] = yvn[rr];
+            if (DEPTH == 2) yvn[rr] = yvm[rr];
 #pragma unroll
-            for (int e = 0; e < CPT; ++e) av[rr][e] = avn[rr][e];
+            for (int e = 0; e < CPT; ++e) {
+                av[rr][e] = avn[rr][e];
+                if (DEPTH == 2) avn[rr][e] = avm[rr][e];
+            }
         }
-        if (j0 + R < r1) load_rows(j0 + R, avn, yvn);
+        if (DEPTH == 2) {
+            if (j0 + 2 * R < r1) load_rows(j0 + 2 * R, avm, yvm);
+        } else {
+            if (j0 + R < r1) load_rows(j0 + R, avn, yvn);
+        }
         double q[R];
         if (OP != OP_ATB) {
             double pd[R];
@@ -169,7 +222,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const int block) 
             for (int rr = 0; rr < R; ++rr) {
                 double t = 0.0;
 #pragma unroll
-                for (int e = 0; e < CPT; ++e) t += av[rr][e] * wr[e];
+                for (int e = 0; e < CPT; ++e) t += (double)av[rr][e] * wr[e];
                 pd[rr] = wave_sum(t);
             }
             if (lane == 0) {
@@ -232,7 +285,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const int block) 
                 }
             }
 #pragma unroll
-            for (int e = 0; e < CPT; ++e) zr[e] += c * av[rr][e];
+            for (int e = 0; e < CPT; ++e) zr[e] += c * (double)av[rr][e];
         }
     }
 
@@ -241,7 +294,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const int block) 
     if (a.lambda > 0.0 && OP != OP_LSQR_FAT && OP != OP_CS_FAT) {
 #pragma unroll
         for (int e = 0; e < CPT; ++e) {
-            const int col = col_of<CPT>(tid, e);
+            const int col = col_of_w<W>(tid, e);
             if (col < L && (col % a.nblocks) == block) {
                 const int64_t row = a.rows + col;
                 const double qv = a.lambda * wr[e];
@@ -258,7 +311,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const int block) 
 
 #pragma unroll
     for (int e = 0; e < CPT; ++e) {
-        const int col = col_of<CPT>(tid, e);
+        const int col = col_of_w<W>(tid, e);
         if (col < L) a.zpart[(int64_t)block * L + col] = zr[e];
     }
     acc0 = wave_sum(acc0);
@@ -1723,7 +1776,10 @@ IterResult iterate_on(const IterProblem &pb, const double *b, double *x, const l
                 LSRN_HIP(hipMemcpyAsync(xsave.as<double>(), x, (size_t)n * sizeof(double),
                                         hipMemcpyDeviceToDevice, st));
                 bool c2 = true;
-                res.refine_iters += cs ? fs.cs(sl, su, opt.tol) : fs.lsqr(maxiter, opt.tol, c2);
+                // the correction needs only refine_tol relative accuracy:
+                // the error left after it is that times the error before
+                const double ctol = std::max(opt.tol, opt.refine_tol);
+                res.refine_iters += cs ? fs.cs(sl, su, ctol) : fs.lsqr(maxiter, ctol, c2);
                 // fs wrote the correction into x; x = xsave + dx
                 const double dn = host_norm(x, n, st);
                 axpby_kernel<<<grid1(n), 256, 0, st>>>(n, 1.0, xsave.as<double>(), 1.0, x);
