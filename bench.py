@@ -398,6 +398,9 @@ def main():
     ap.add_argument("--refine", type=int, default=1)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--precond", default="auto", choices=["auto", "svd", "qr"])
+    ap.add_argument("--storage", default="f64", choices=["f64", "f32"],
+                    help="storage of A handed to the library (f32: lsrn_solve_dense_f32 on the "
+                         "FP32-rounded matrix, FP64 arithmetic)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the built-in sweep launch shape")
@@ -479,15 +482,22 @@ def main():
     opts = dict(method=args.method, refine=args.refine, seed=2024, tol=1e-14,
                 profile=0 if args.no_profile else 1, precision=args.precision,
                 precond=args.precond, autotune=0 if args.no_autotune else 1)
+    solve = lsrn.solve_dense
+    if args.storage == "f32":
+        # the problem becomes the FP32-rounded matrix; the generator's solution
+        # then differs by about kappa 2^-24
+        A = A.float()
+        torch.cuda.empty_cache()
+        solve = lsrn.solve_dense_f32
     for _ in range(args.warmup):
-        x, info = lsrn.solve_dense(A, b, layout=layout, allow_not_converged=True, **opts)
+        x, info = solve(A, b, layout=layout, allow_not_converged=True, **opts)
     torch.cuda.synchronize()
 
     lat, infos = [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         ts = time.perf_counter()
-        x, info = lsrn.solve_dense(A, b, layout=layout, allow_not_converged=True, **opts)
+        x, info = solve(A, b, layout=layout, allow_not_converged=True, **opts)
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - ts) * 1e3)
         infos.append(info)
@@ -519,7 +529,7 @@ def main():
     sketch_flop = 2.0 * s * K * d
     sweeps_per_solve = info["sweep_kernels"] if info["sweep_kernels"] else None
     # one read of A (FP32 copy in the precision form) + long vector read/write
-    bytes_per_sweep = (8.0 if args.precision == "fp64" else 4.0) * K * d + 16.0 * K
+    bytes_per_sweep = (8.0 if (args.precision == "fp64" and args.storage == "f64") else 4.0) * K * d + 16.0 * K
     mean = lambda key: sum(i[key] for i in infos) / len(infos)
     t_sketch_k = mean("t_sketch_kernel_ms")
     t_sweep_k = mean("t_sweep_kernel_ms")
@@ -580,11 +590,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "bf16 sketch + f32 sweeps + f64",
+        "dtype": ("f64" if args.storage == "f64" else "f64 arithmetic on f32-stored A")
+                 if args.precision == "fp64" else "bf16 sketch + f32 sweeps + f64",
         "data": "synthetic (seeded; U, V Haar, sigma log-spaced, b ~ N(0,1))",
         "config": {"workload": args.workload, "m": m_ls, "n": n_ls, "rank": wl["rank"],
                    "gamma": 2.0, "tol": 1e-14, "method": args.method, "refine": args.refine,
-                   "precision": args.precision, "precond": args.precond,
+                   "precision": args.precision, "precond": args.precond, "storage": args.storage,
                    "autotune": not args.no_autotune},
         "tuned_shapes": lsrn.tune_export().strip().splitlines(),
         "latency_ms": {"p50": round(percentile(lat, 50), 3), "p99": round(percentile(lat, 99), 3)},

@@ -169,6 +169,18 @@ lsrn_status lsrn_solve_dense(int64_t m, int64_t n, const double *A, int64_t lda,
                              int32_t layout, const double *b, double *x,
                              const lsrn_options *opt, lsrn_info *info, void *stream);
 
+/* lsrn_solve_dense for A stored in FP32 (b and x FP64): the least-squares
+ * problem of the stored FP32 values, solved in FP64 arithmetic -- the
+ * sketch reads the FP32 entries into the FP64 matrix cores, the sweeps load
+ * them as FP32 and accumulate in FP64, and refinement residuals are formed
+ * from them exactly in double-double, so the FP64 accuracy bar holds while
+ * every pass over A moves half the bytes.  Same layouts, options (precision
+ * must be FP64; LSRN_E_UNSUPPORTED otherwise) and errors as
+ * lsrn_solve_dense. */
+lsrn_status lsrn_solve_dense_f32(int64_t m, int64_t n, const float *A, int64_t lda, int32_t layout,
+                                 const double *b, double *x, const lsrn_options *opt,
+                                 lsrn_info *info, void *stream);
+
 /* Bytes of device workspace lsrn_solve_dense allocates for these sizes
  * (used for HBM admission by callers that batch solves). */
 size_t lsrn_workspace_bytes(int64_t m, int64_t n, int32_t layout, const lsrn_options *opt);

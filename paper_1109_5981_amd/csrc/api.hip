@@ -134,6 +134,7 @@ struct TallView {
     const double *T;
     int64_t ldt;
     DevBuf buf;
+    const float *T32 = nullptr;  // A stored in FP32 (then T is NULL)
 };
 
 void make_view(TallView &v, int64_t m, int64_t n, const double *A, int64_t lda, int32_t layout,
@@ -156,6 +157,29 @@ void make_view(TallView &v, int64_t m, int64_t n, const double *A, int64_t lda, 
     v.buf.alloc((size_t)rows * (size_t)cols * sizeof(double));
     transpose(rows, cols, A, lda, v.buf.as<double>(), st);
     v.T = v.buf.as<double>();
+    v.ldt = rows;
+}
+
+// The tall view of FP32 storage (same rules as make_view).
+void make_view_f32(TallView &v, int64_t m, int64_t n, const float *A, int64_t lda, int32_t layout,
+                   double lambda, hipStream_t st) {
+    LSRN_REQUIRE(layout == LSRN_ROW_MAJOR || layout == LSRN_COL_MAJOR, "unknown layout");
+    LSRN_REQUIRE(lda >= (layout == LSRN_ROW_MAJOR ? n : m), "lda too small for the layout");
+    if (lambda > 0.0 && m < n)
+        fail(LSRN_E_UNSUPPORTED, "Tikhonov regularisation needs m >= n (under-determined form not provided)");
+    v.tall = m >= n;
+    v.K = v.tall ? m : n;
+    v.d = v.tall ? n : m;
+    v.T = nullptr;
+    if ((v.tall && layout == LSRN_ROW_MAJOR) || (!v.tall && layout == LSRN_COL_MAJOR)) {
+        v.T32 = A;
+        v.ldt = lda;
+        return;
+    }
+    const int64_t rows = v.tall ? n : m, cols = v.tall ? m : n;
+    v.buf.alloc((size_t)rows * (size_t)cols * sizeof(float));
+    transpose(rows, cols, A, lda, v.buf.as<float>(), st);
+    v.T32 = v.buf.as<float>();
     v.ldt = rows;
 }
 
@@ -229,9 +253,14 @@ void prepare(bool tall, int64_t K, int64_t d, const TallView *dv, const SparseVi
     pp.s = s;
     pp.d = d;
     DevBuf X((size_t)s * (size_t)d * sizeof(double));
+    if (mixed && dv && dv->T32)
+        fail(LSRN_E_UNSUPPORTED, "FP32 storage of A is solved in FP64 arithmetic (precision FP64)");
     if (sv) {
         sketch_csr(*sv, tall ? opt.lambda : 0.0, s, opt.seed, X.as<double>(), st,
                    opt.profile ? &pp.sketch_kernel_ms : nullptr);
+    } else if (dv->T32) {
+        sketch_rows(K, d, dv->T32, dv->ldt, tall ? opt.lambda : 0.0, s, opt.seed, X.as<double>(), st,
+                    opt.profile ? &pp.sketch_kernel_ms : nullptr);
     } else if (mixed) {
         pp.T32.alloc((size_t)K * (size_t)dv->ldt * sizeof(float));
         to_f32(K, d, dv->T, dv->ldt, pp.T32.as<float>(), st);
@@ -263,7 +292,7 @@ IterResult run_iterations(bool tall, int64_t K, int64_t d, int64_t n, const Tall
     IterProblem pb;
     pb.tall = tall; pb.rows = K; pb.cols = d;
     if (sv) pb.sp = sv;
-    else { pb.T = dv->T; pb.ldt = dv->ldt; }
+    else { pb.T = dv->T; pb.T32 = dv->T32; pb.ldt = dv->ldt; }
     pb.lambda = tall ? opt.lambda : 0.0;
     pb.P = pp.P.as<double>(); pb.ldp = d;
     pb.r = pp.pr.rank; pb.s = pp.s;
@@ -468,6 +497,23 @@ lsrn_status lsrn_solve_dense(int64_t m, int64_t n, const double *A, int64_t lda,
     tm.mark();
     TallView v;
     make_view(v, m, n, A, lda, layout, opt.lambda, st);
+    return solve_impl(v.tall, v.K, v.d, n, &v, nullptr, b, x, opt, info, st, tm);
+    LSRN_API_END
+}
+
+lsrn_status lsrn_solve_dense_f32(int64_t m, int64_t n, const float *A, int64_t lda, int32_t layout,
+                                 const double *b, double *x, const lsrn_options *opt_in,
+                                 lsrn_info *info, void *stream) {
+    LSRN_API_BEGIN
+    const lsrn_options opt = opt_in ? *opt_in : defaults();
+    check_options(opt);
+    LSRN_REQUIRE(m > 0 && n > 0, "sizes must be positive");
+    LSRN_REQUIRE(A && b && x, "NULL pointer");
+    hipStream_t st = (hipStream_t)stream;
+    StageTimer tm(st);
+    tm.mark();
+    TallView v;
+    make_view_f32(v, m, n, A, lda, layout, opt.lambda, st);
     return solve_impl(v.tall, v.K, v.d, n, &v, nullptr, b, x, opt, info, st, tm);
     LSRN_API_END
 }

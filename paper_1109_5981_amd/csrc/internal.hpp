@@ -24,6 +24,9 @@ void launch_gauss_fill(uint64_t seed, int64_t row0, int64_t nrows, int64_t col0,
 // With kernel_ms != NULL the GEMM kernel is timed with HIP events on st.
 void sketch_rows(int64_t K, int64_t d, const double *T, int64_t ldt, double lambda, int64_t s,
                  uint64_t seed, double *X, hipStream_t st, double *kernel_ms = nullptr);
+// The same for T stored in FP32 (each entry exact in FP64).
+void sketch_rows(int64_t K, int64_t d, const float *T, int64_t ldt, double lambda, int64_t s,
+                 uint64_t seed, double *X, hipStream_t st, double *kernel_ms = nullptr);
 size_t sketch_workspace_bytes(int64_t K, int64_t d, int64_t s);
 
 // The precision form's sketch: X = bf16(G) fl32(T) on the BF16 matrix
@@ -42,6 +45,8 @@ void add_identity_rows(int64_t K, int64_t d, int64_t s, double lambda, uint64_t 
 // Out-of-place transpose: out (cols x rows, leading dim rows) = in^T, in
 // row-major rows x cols with leading dim ldin.
 void transpose(int64_t rows, int64_t cols, const double *in, int64_t ldin, double *out,
+               hipStream_t st);
+void transpose(int64_t rows, int64_t cols, const float *in, int64_t ldin, float *out,
                hipStream_t st);
 
 // ------------------------------------------------------------- csr.hip

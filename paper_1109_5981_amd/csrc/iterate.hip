@@ -644,9 +644,9 @@ __global__ void set_state_kernel(State *st, int maxiter) {
 
 // Tall: h = T^T (b^ - T x) - lambda^2 x in double-double, one pass over T.
 // x (length L) is held per thread like w in the sweep.
-template <int CPT>
+template <int CPT, typename TT>
 __global__ void __launch_bounds__(NT)
-resid_dd_tall_kernel(const double *__restrict__ T, int64_t ldt, int64_t rows, int L, int nblocks,
+resid_dd_tall_kernel(const TT *__restrict__ T, int64_t ldt, int64_t rows, int L, int nblocks,
                      int64_t rows_per_block, const double *__restrict__ b,
                      const double *__restrict__ x, double lambda, double *__restrict__ hpart_hi,
                      double *__restrict__ hpart_lo) {
@@ -664,13 +664,13 @@ resid_dd_tall_kernel(const double *__restrict__ T, int64_t ldt, int64_t rows, in
     const int64_t r1 = min(rows, r0 + rows_per_block);
     int parity = 0;
     for (int64_t row = r0; row < r1; ++row) {
-        const double *trow = T + row * ldt;
+        const TT *trow = T + row * ldt;
         double av[CPT];
         dd p = {0.0, 0.0};
 #pragma unroll
         for (int e = 0; e < CPT; ++e) {
             const int col = col_of<CPT>(tid, e);
-            av[e] = col < L ? trow[col] : 0.0;
+            av[e] = col < L ? (double)trow[col] : 0.0;
             p = dd_fma(p, av[e], xr[e]);
         }
         p = wave_sum_dd(p);
@@ -707,9 +707,9 @@ resid_dd_tall_kernel(const double *__restrict__ T, int64_t ldt, int64_t rows, in
 }
 
 // Fat: z = T^T x = A x in double-double (rows of T weighted by x).
-template <int CPT>
+template <int CPT, typename TT>
 __global__ void __launch_bounds__(NT)
-ax_dd_fat_kernel(const double *__restrict__ T, int64_t ldt, int64_t rows, int L,
+ax_dd_fat_kernel(const TT *__restrict__ T, int64_t ldt, int64_t rows, int L,
                  int64_t rows_per_block, const double *__restrict__ x,
                  double *__restrict__ zpart_hi, double *__restrict__ zpart_lo) {
     const int tid = threadIdx.x;
@@ -719,12 +719,12 @@ ax_dd_fat_kernel(const double *__restrict__ T, int64_t ldt, int64_t rows, int L,
     const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
     const int64_t r1 = min(rows, r0 + rows_per_block);
     for (int64_t row = r0; row < r1; ++row) {
-        const double *trow = T + row * ldt;
+        const TT *trow = T + row * ldt;
         const double xv = x[row];
 #pragma unroll
         for (int e = 0; e < CPT; ++e) {
             const int col = col_of<CPT>(tid, e);
-            if (col < L) zr[e] = dd_fma(zr[e], trow[col], xv);
+            if (col < L) zr[e] = dd_fma(zr[e], (double)trow[col], xv);
         }
     }
 #pragma unroll
@@ -1596,16 +1596,26 @@ struct FatSolver {
     }
 };
 
+// The residual passes read the FP64 T, or the FP32 T when the problem's
+// matrix is stored in FP32 (then its values are exact in FP64).
 template <int CPT>
 void launch_resid_tall(Ctx &cx, const double *b, const double *x, double *hi, double *lo) {
-    resid_dd_tall_kernel<CPT><<<cx.nblocks, NT, 0, cx.st>>>(
-        cx.pb.T, cx.pb.ldt, cx.pb.rows, cx.L, cx.nblocks, cx.rows_per_block, b, x, cx.pb.lambda, hi, lo);
+    if (cx.pb.T)
+        resid_dd_tall_kernel<CPT, double><<<cx.nblocks, NT, 0, cx.st>>>(
+            cx.pb.T, cx.pb.ldt, cx.pb.rows, cx.L, cx.nblocks, cx.rows_per_block, b, x, cx.pb.lambda, hi, lo);
+    else
+        resid_dd_tall_kernel<CPT, float><<<cx.nblocks, NT, 0, cx.st>>>(
+            cx.pb.T32, cx.pb.ldt, cx.pb.rows, cx.L, cx.nblocks, cx.rows_per_block, b, x, cx.pb.lambda, hi, lo);
 }
 
 template <int CPT>
 void launch_ax_fat(Ctx &cx, const double *x, double *hi, double *lo) {
-    ax_dd_fat_kernel<CPT><<<cx.nblocks, NT, 0, cx.st>>>(cx.pb.T, cx.pb.ldt, cx.pb.rows, cx.L,
-                                                        cx.rows_per_block, x, hi, lo);
+    if (cx.pb.T)
+        ax_dd_fat_kernel<CPT, double><<<cx.nblocks, NT, 0, cx.st>>>(cx.pb.T, cx.pb.ldt, cx.pb.rows, cx.L,
+                                                                    cx.rows_per_block, x, hi, lo);
+    else
+        ax_dd_fat_kernel<CPT, float><<<cx.nblocks, NT, 0, cx.st>>>(cx.pb.T32, cx.pb.ldt, cx.pb.rows, cx.L,
+                                                                   cx.rows_per_block, x, hi, lo);
 }
 
 double host_norm(const double *d, int64_t n, hipStream_t st) {
@@ -1649,7 +1659,7 @@ IterResult iterate_on(const IterProblem &pb, const double *b, double *x, const l
         ts.load_rhs(b);
         // the precision form's main solve runs on fl32(A): no point in going
         // below 1e-8 before the refinement
-        const double tol_main = pb.T32 ? std::max(opt.tol, 1e-8) : opt.tol;
+        const double tol_main = (pb.T && pb.T32) ? std::max(opt.tol, 1e-8) : opt.tol;
         res.iters = cs ? ts.cs(sl, su, opt.tol) : ts.lsqr(maxiter, tol_main, conv);
         ts.x_from_y(x);
         LSRN_HIP(hipEventRecord(e1, st));
@@ -1717,7 +1727,7 @@ IterResult iterate_on(const IterProblem &pb, const double *b, double *x, const l
                 const double dn = host_norm(dx.as<double>(), L, st), xn = host_norm(x, L, st);
                 const bool stalled = step > 0 && dn > 0.5 * dn_prev;
                 dn_prev = dn;
-                if (pb.T32) {
+                if (pb.T && pb.T32) {
                     // the precision form's main LSQR runs on fl32(A): its
                     // answer is settled by the refinement, whose last
                     // correction must have become negligible

@@ -55,8 +55,8 @@ __device__ __forceinline__ void gen_g_stage(double (*Gs)[LDP], uint64_t seed, in
 
 // 16 rows x BN columns of T for one stage into registers (zero outside
 // [k0, kend) x [0, d)): four double2 per thread.
-template <int WN, bool VEC2>
-__device__ __forceinline__ void load_t_stage(const double *__restrict__ T, int64_t ldt,
+template <int WN, bool VEC2, typename TT>
+__device__ __forceinline__ void load_t_stage(const TT *__restrict__ T, int64_t ldt,
                                              int64_t kstage, int64_t kend, int64_t n0, int64_t d,
                                              double2 (&reg)[4]) {
     constexpr int HALF = BN_<WN> / 2;  // double2 per row of the tile
@@ -68,12 +68,17 @@ __device__ __forceinline__ void load_t_stage(const double *__restrict__ T, int64
         const int64_t k = kstage + kk, col = n0 + c2;
         double2 v = make_double2(0.0, 0.0);
         if (k < kend) {
-            const double *p = T + k * ldt + col;
+            const TT *p = T + k * ldt + col;
             if (VEC2 && col + 1 < d) {
-                v = *reinterpret_cast<const double2 *>(p);
+                if constexpr (sizeof(TT) == 8) {
+                    v = *reinterpret_cast<const double2 *>(p);
+                } else {
+                    const float2 f = *reinterpret_cast<const float2 *>(p);
+                    v = make_double2((double)f.x, (double)f.y);
+                }
             } else {
-                if (col < d) v.x = p[0];
-                if (col + 1 < d) v.y = p[1];
+                if (col < d) v.x = (double)p[0];
+                if (col + 1 < d) v.y = (double)p[1];
             }
         }
         reg[it] = v;
@@ -92,9 +97,9 @@ __device__ __forceinline__ void store_t_stage(double (*Ts)[TP_<WN>], const doubl
     }
 }
 
-template <int WN, bool VEC2>
+template <int WN, bool VEC2, typename TT = double>
 __global__ void __launch_bounds__(NT_<WN>, 4 / WN)
-sketch_mfma_kernel(const double *__restrict__ T, int64_t ldt, int64_t K, int64_t d, int64_t s,
+sketch_mfma_kernel(const TT *__restrict__ T, int64_t ldt, int64_t K, int64_t d, int64_t s,
                    uint64_t seed, int64_t k_per_split, int tiles_m, double *__restrict__ Xp) {
     __shared__ double Gs[2][KT][LDP];
     __shared__ double Ts[2][KT][TP_<WN>];
@@ -120,7 +125,7 @@ sketch_mfma_kernel(const double *__restrict__ T, int64_t ldt, int64_t K, int64_t
     double2 treg[4];
     if (nstage > 0) {
         gen_g_stage<WN>(Gs[0], seed, m0, kbeg);
-        load_t_stage<WN, VEC2>(T, ldt, kbeg, kend, n0, d, treg);
+        load_t_stage<WN, VEC2, TT>(T, ldt, kbeg, kend, n0, d, treg);
         store_t_stage<WN>(Ts[0], treg);
     }
     __syncthreads();
@@ -129,7 +134,7 @@ sketch_mfma_kernel(const double *__restrict__ T, int64_t ldt, int64_t K, int64_t
         const int buf = (int)(st & 1);
         const bool more = st + 1 < nstage;
         const int64_t knext = kbeg + (st + 1) * KT;
-        if (more) load_t_stage<WN, VEC2>(T, ldt, knext, kend, n0, d, treg);
+        if (more) load_t_stage<WN, VEC2, TT>(T, ldt, knext, kend, n0, d, treg);
 #pragma unroll
         for (int kk = 0; kk < KT / 4; ++kk) {
             double a[4], b[4];
@@ -191,10 +196,11 @@ add_identity_rows_kernel(int64_t K, int64_t d, int64_t s, double lambda, uint64_
     }
 }
 
+template <typename E = double>
 __global__ void __launch_bounds__(256)
-transpose_kernel(int64_t rows, int64_t cols, const double *__restrict__ in, int64_t ldin,
-                 double *__restrict__ out) {
-    __shared__ double tile[32][33];
+transpose_kernel(int64_t rows, int64_t cols, const E *__restrict__ in, int64_t ldin,
+                 E *__restrict__ out) {
+    __shared__ E tile[32][33];
     const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
     for (int k = ty; k < 32; k += 8) {
@@ -242,8 +248,11 @@ size_t sketch_workspace_bytes(int64_t K, int64_t d, int64_t s) {
     return p.nsplit > 1 ? (size_t)p.nsplit * (size_t)s * (size_t)d * sizeof(double) : 0;
 }
 
-void sketch_rows(int64_t K, int64_t d, const double *T, int64_t ldt, double lambda, int64_t s,
-                 uint64_t seed, double *X, hipStream_t st, double *kernel_ms) {
+namespace {
+
+template <typename TT>
+void sketch_rows_t(int64_t K, int64_t d, const TT *T, int64_t ldt, double lambda, int64_t s,
+                   uint64_t seed, double *X, hipStream_t st, double *kernel_ms) {
     SketchPlan p = plan_sketch(K, d, s);
     DevBuf part;
     double *Xp = X;
@@ -252,7 +261,7 @@ void sketch_rows(int64_t K, int64_t d, const double *T, int64_t ldt, double lamb
         Xp = part.as<double>();
     }
     dim3 grid((unsigned)(p.tiles_m * p.tiles_n), (unsigned)p.nsplit);
-    const bool vec2 = (ldt % 2 == 0) && ((reinterpret_cast<uintptr_t>(T) & 15) == 0);
+    const bool vec2 = (ldt % 2 == 0) && ((reinterpret_cast<uintptr_t>(T) & (2 * sizeof(TT) - 1)) == 0);
     hipEvent_t ev[2] = {nullptr, nullptr};
     if (kernel_ms) {
         LSRN_HIP(hipEventCreate(&ev[0]));
@@ -261,18 +270,18 @@ void sketch_rows(int64_t K, int64_t d, const double *T, int64_t ldt, double lamb
     }
     if (p.wn == 4) {
         if (vec2)
-            sketch_mfma_kernel<4, true><<<grid, NT_<4>, 0, st>>>(T, ldt, K, d, s, seed, p.k_per_split,
-                                                                p.tiles_m, Xp);
+            sketch_mfma_kernel<4, true, TT><<<grid, NT_<4>, 0, st>>>(T, ldt, K, d, s, seed, p.k_per_split,
+                                                                    p.tiles_m, Xp);
         else
-            sketch_mfma_kernel<4, false><<<grid, NT_<4>, 0, st>>>(T, ldt, K, d, s, seed, p.k_per_split,
-                                                                 p.tiles_m, Xp);
+            sketch_mfma_kernel<4, false, TT><<<grid, NT_<4>, 0, st>>>(T, ldt, K, d, s, seed, p.k_per_split,
+                                                                     p.tiles_m, Xp);
     } else {
         if (vec2)
-            sketch_mfma_kernel<2, true><<<grid, NT_<2>, 0, st>>>(T, ldt, K, d, s, seed, p.k_per_split,
-                                                                p.tiles_m, Xp);
+            sketch_mfma_kernel<2, true, TT><<<grid, NT_<2>, 0, st>>>(T, ldt, K, d, s, seed, p.k_per_split,
+                                                                    p.tiles_m, Xp);
         else
-            sketch_mfma_kernel<2, false><<<grid, NT_<2>, 0, st>>>(T, ldt, K, d, s, seed, p.k_per_split,
-                                                                 p.tiles_m, Xp);
+            sketch_mfma_kernel<2, false, TT><<<grid, NT_<2>, 0, st>>>(T, ldt, K, d, s, seed, p.k_per_split,
+                                                                     p.tiles_m, Xp);
     }
     LSRN_HIP(hipGetLastError());
     if (kernel_ms) {
@@ -297,6 +306,18 @@ void sketch_rows(int64_t K, int64_t d, const double *T, int64_t ldt, double lamb
     if (p.nsplit > 1) LSRN_HIP(hipStreamSynchronize(st));  // before `part` is freed
 }
 
+}  // namespace
+
+void sketch_rows(int64_t K, int64_t d, const double *T, int64_t ldt, double lambda, int64_t s,
+                 uint64_t seed, double *X, hipStream_t st, double *kernel_ms) {
+    sketch_rows_t(K, d, T, ldt, lambda, s, seed, X, st, kernel_ms);
+}
+
+void sketch_rows(int64_t K, int64_t d, const float *T, int64_t ldt, double lambda, int64_t s,
+                 uint64_t seed, double *X, hipStream_t st, double *kernel_ms) {
+    sketch_rows_t(K, d, T, ldt, lambda, s, seed, X, st, kernel_ms);
+}
+
 void add_identity_rows(int64_t K, int64_t d, int64_t s, double lambda, uint64_t seed, double *X,
                        hipStream_t st) {
     if (!(lambda > 0.0)) return;
@@ -305,10 +326,17 @@ void add_identity_rows(int64_t K, int64_t d, int64_t s, double lambda, uint64_t 
     LSRN_HIP(hipGetLastError());
 }
 
+void transpose(int64_t rows, int64_t cols, const float *in, int64_t ldin, float *out,
+               hipStream_t st) {
+    dim3 grid((unsigned)ceil_div(cols, 32), (unsigned)ceil_div(rows, 32));
+    transpose_kernel<float><<<grid, 256, 0, st>>>(rows, cols, in, ldin, out);
+    LSRN_HIP(hipGetLastError());
+}
+
 void transpose(int64_t rows, int64_t cols, const double *in, int64_t ldin, double *out,
                hipStream_t st) {
     dim3 grid((unsigned)ceil_div(cols, 32), (unsigned)ceil_div(rows, 32));
-    transpose_kernel<<<grid, 256, 0, st>>>(rows, cols, in, ldin, out);
+    transpose_kernel<double><<<grid, 256, 0, st>>>(rows, cols, in, ldin, out);
     LSRN_HIP(hipGetLastError());
 }
 

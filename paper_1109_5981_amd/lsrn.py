@@ -67,7 +67,7 @@ EXPORTS = EXPORTS + SERVER_EXPORTS
 PLAN_EXPORTS = ["lsrn_plan_create_dense", "lsrn_plan_create_csr", "lsrn_plan_solve",
                 "lsrn_plan_destroy"]
 EXPORTS = EXPORTS + PLAN_EXPORTS + ["lsrn_solve_op", "lsrn_tune_export", "lsrn_tune_import",
-                                     "lsrn_tune_clear"]
+                                     "lsrn_tune_clear", "lsrn_solve_dense_f32"]
 # lsrn_apply_fn: (ctx, trans, k, in, ldin, out, ldout, stream) -> int
 APPLY_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_int64,
                        C.c_void_p, C.c_int64, C.c_void_p)
@@ -135,6 +135,8 @@ def lib():
         L.lsrn_plan_destroy.restype = None
         L.lsrn_solve_op.argtypes = [I64, I64, APPLY_FN, P, P, P, C.POINTER(Options),
                                     C.POINTER(Info), P]
+        L.lsrn_solve_dense_f32.argtypes = [I64, I64, P, I64, I32, P, P, C.POINTER(Options),
+                                           C.POINTER(Info), P]
         L.lsrn_tune_export.argtypes = [C.c_char_p, C.c_size_t]
         L.lsrn_tune_export.restype = C.c_size_t
         L.lsrn_tune_import.argtypes = [C.c_char_p]
@@ -203,6 +205,27 @@ def solve_dense(A: torch.Tensor, b: torch.Tensor, x: torch.Tensor | None = None,
     o, info = options(**opts), Info()
     st = lib().lsrn_solve_dense(m, n, A.data_ptr(), lda, layout, b.data_ptr(), x.data_ptr(),
                                 C.byref(o), C.byref(info), _stream())
+    if not (allow_not_converged and st == 4):
+        _check(st)
+    out = info.as_dict()
+    out["status"] = int(st)
+    return x, out
+
+
+def solve_dense_f32(A: torch.Tensor, b: torch.Tensor, x: torch.Tensor | None = None, *,
+                    layout: int = ROW_MAJOR, allow_not_converged: bool = False, **opts):
+    """lsrn_solve_dense_f32: A stored in FP32 (b, x FP64).  Returns (x, info)."""
+    if not (isinstance(A, torch.Tensor) and A.is_cuda and A.dtype == torch.float32):
+        raise TypeError("A must be a float32 tensor on the GPU")
+    _dev_f64(b, "b")
+    m, n, lda = _layout_dims(A, layout)
+    if b.numel() != m or not b.is_contiguous():
+        raise ValueError("b must be contiguous with m entries")
+    if x is None:
+        x = torch.empty(n, dtype=torch.float64, device=A.device)
+    o, info = options(**opts), Info()
+    st = lib().lsrn_solve_dense_f32(m, n, A.data_ptr(), lda, layout, b.data_ptr(), x.data_ptr(),
+                                    C.byref(o), C.byref(info), _stream())
     if not (allow_not_converged and st == 4):
         _check(st)
     out = info.as_dict()

@@ -138,14 +138,15 @@ def matvec_device(A, x, trans: bool = False):
     """A x (or A^T x) in row chunks."""
     import torch
     m, n = A.shape
+    dt = x.dtype  # FP32-stored A is widened chunk by chunk
     if not trans:
-        out = torch.empty(m, dtype=A.dtype, device=A.device)
+        out = torch.empty(m, dtype=dt, device=A.device)
         for r0, r1 in _row_chunks(m, n):
-            out[r0:r1] = A[r0:r1] @ x
+            out[r0:r1] = A[r0:r1].to(dt) @ x
         return out
-    out = torch.zeros(n, dtype=A.dtype, device=A.device)
+    out = torch.zeros(n, dtype=dt, device=A.device)
     for r0, r1 in _row_chunks(m, n):
-        out += A[r0:r1].T @ x[r0:r1]
+        out += A[r0:r1].to(dt).T @ x[r0:r1]
     return out
 
 
