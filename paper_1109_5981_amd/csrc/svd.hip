@@ -7,6 +7,7 @@
 // vectors of X, so N = V_r Sigma_r^{-1} = W_r Sigma_r^{-2} needs no
 // accumulated rotations.  r counts sigma_i > rcond sigma_1.
 #include <algorithm>
+#include <mutex>
 #include <cfloat>
 #include <cmath>
 #include <vector>
@@ -797,9 +798,19 @@ JacobiPlan jacobi_plan(int64_t d) {
     return pl;
 }
 
-void set_small_lds(size_t bytes, const void *fn) {
-    if (bytes > 65536)
-        LSRN_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+// The small-matrix Jacobi kernels use d^2 doubles of dynamic LDS, at most
+// 128 KiB (d <= 128); the attribute is raised once per process, not per
+// call, which solves on several host threads would do concurrently.
+void set_small_lds(size_t bytes) {
+    static std::once_flag once;
+    if (bytes <= 65536) return;
+    std::call_once(once, [] {
+        const int lim = 128 * 1024;
+        LSRN_HIP(hipFuncSetAttribute((const void *)jacobi_small_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+        LSRN_HIP(hipFuncSetAttribute((const void *)jacobi_small_batch_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+    });
 }
 
 // All sweeps of one problem; returns the sweep count.
@@ -810,7 +821,7 @@ int64_t jacobi_single(double *Y, int64_t d, const JacobiPlan &pl, hipStream_t st
     int *dcnt = cnt.as<int>();
     if (pl.small) {
         const size_t bytes = (size_t)d * d * sizeof(double);
-        set_small_lds(bytes, (const void *)jacobi_small_kernel);
+        set_small_lds(bytes);
         jacobi_small_kernel<<<1, 1024, bytes, st>>>(Y, (int)d, kJacobiMaxSweeps, tol, dcnt);
         LSRN_HIP(hipGetLastError());
         int sw = 0;
@@ -973,7 +984,7 @@ void precond_batch(int count, const int64_t *s, const int64_t *d, double *const 
         DevBuf ditems((size_t)n * sizeof(JacobiItem)), dsw((size_t)n * sizeof(int));
         LSRN_HIP(hipMemcpyAsync(ditems.as<JacobiItem>(), it.data(), (size_t)n * sizeof(JacobiItem),
                                 hipMemcpyHostToDevice, st));
-        set_small_lds(bytes, (const void *)jacobi_small_batch_kernel);
+        set_small_lds(bytes);
         jacobi_small_batch_kernel<<<(unsigned)n, 1024, bytes, st>>>(ditems.as<JacobiItem>(),
                                                                      kJacobiMaxSweeps, dsw.as<int>());
         LSRN_HIP(hipGetLastError());
