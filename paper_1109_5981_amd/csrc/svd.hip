@@ -438,6 +438,43 @@ __device__ __forceinline__ bool jacobi_angle(double a, double b, double g, doubl
     return true;
 }
 
+// Raw buffer resource over the n doubles of one column at p: the hardware
+// range check returns 0 for loads past the end and drops stores past the
+// end, so the padding rows of a thread's share need no branches.  Word 3
+// is the gfx9 buffer format word (32-bit data format).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t column_rsrc(double *p, int n) {
+    return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, n * (int)sizeof(double), 0x00020000);
+}
+__device__ __forceinline__ double column_load(__amdgpu_buffer_rsrc_t rs, int i) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, i * 8, 0, 0));
+}
+__device__ __forceinline__ void column_store(__amdgpu_buffer_rsrc_t rs, int i, double v) {
+    typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rs, i * 8, 0, 0);
+}
+
+// Partner of player i (i < NL, NL even) in sub-round TS of the circle-
+// method round robin, and the index of their pair (as in rr_pair), without
+// branches: the sub-round loop is unrolled, so these run once per thread
+// and sub-round on the update's critical path.
+template <int NL, int TS>
+__device__ __forceinline__ int rr_partner(int i) {
+    constexpr int M = NL - 1;
+    int p = 2 * TS - i;
+    p += p < 0 ? M : 0;
+    p -= p >= M ? M : 0;
+    p = i == TS ? M : p;
+    return i == M ? TS : p;
+}
+template <int NL, int TS>
+__device__ __forceinline__ int rr_pair_index(int i) {
+    constexpr int M = NL - 1;
+    int u = i - TS;
+    u += u < 0 ? M : 0;
+    const int k = u < M - u ? u : M - u;
+    return i == M ? 0 : k;
+}
+
 // One round of the block round robin, Gram form.  The 2 BW columns of the
 // block pair stay in registers (thread t owns rows t + 512 u, u < EPU).
 // Their 2 BW x 2 BW Gram matrix G is reduced once; the 2 BW - 1 sub-rounds
@@ -480,12 +517,9 @@ jacobi_gram_round(double *__restrict__ Y, int d, int nblocks, int round, int pai
 #pragma unroll
     for (int cl = 0; cl < NL; ++cl) {
         const int64_t col = (int64_t)(cl < BW ? blo : bhi) * BW + (cl % BW);
-        const double *src = Y + col * d;
+        const __amdgpu_buffer_rsrc_t rs = column_rsrc(Y + col * d, d);
 #pragma unroll
-        for (int u = 0; u < EPU; ++u) {
-            const int i = tid + 512 * u;
-            x[cl][u] = i < d ? src[i] : 0.0;
-        }
+        for (int u = 0; u < EPU; ++u) x[cl][u] = column_load(rs, tid + 512 * u);
     }
     if (tid == 0) nrot_s = 0;
     if (tid < NL) any_s[tid] = 0;
@@ -536,8 +570,10 @@ jacobi_gram_round(double *__restrict__ Y, int d, int nblocks, int round, int pai
         // (a) the angle of pair k, once, by thread k
         if (tid < BW) {
             const int k = tid;
-            const int a = k == 0 ? NL - 1 : (TS + k) % (NL - 1);
-            const int b = k == 0 ? TS : (TS - k + (NL - 1)) % (NL - 1);
+            int a = TS + k, b = TS - k;
+            a -= a >= NL - 1 ? NL - 1 : 0;
+            b += b < 0 ? NL - 1 : 0;
+            a = k == 0 ? NL - 1 : a;
             const int pp = a < b ? a : b, qq = a < b ? b : a;
             double cs, sn;
             if (jacobi_angle(Gs[cur][pp][pp], Gs[cur][qq][qq], Gs[cur][pp][qq], tol, cs, sn)) {
@@ -551,18 +587,9 @@ jacobi_gram_round(double *__restrict__ Y, int d, int nblocks, int round, int pai
         if (!any_s[TS]) return;  // uniform: G and J stay as they are
         // (b) G <- R^T G R and J <- J R entry by entry
         if (owner) {
-            // partner of i in this sub-round and the index of their pair
-            auto partner = [](int i) {
-                if (i == NL - 1) return TS;
-                if (i == TS) return NL - 1;
-                return (2 * TS - i + 2 * (NL - 1)) % (NL - 1);
-            };
-            auto pair_of = [](int i) {
-                if (i == NL - 1 || i == TS) return 0;
-                const int u = (i - TS + (NL - 1)) % (NL - 1), v = (TS - i + (NL - 1)) % (NL - 1);
-                return u < v ? u : v;
-            };
-            const int r2 = partner(r), c2 = partner(c), kr = pair_of(r), kc = pair_of(c);
+            // partners of r and c in this sub-round and the indices of their pairs
+            const int r2 = rr_partner<NL, TS>(r), c2 = rr_partner<NL, TS>(c);
+            const int kr = rr_pair_index<NL, TS>(r), kc = rr_pair_index<NL, TS>(c);
             // new column x = alpha x_own + beta x_partner
             const double ar = CSs[kr][0], br = r < r2 ? -CSs[kr][1] : CSs[kr][1];
             const double ac = CSs[kc][0], bc = c < c2 ? -CSs[kc][1] : CSs[kc][1];
@@ -596,12 +623,9 @@ jacobi_gram_round(double *__restrict__ Y, int d, int nblocks, int round, int pai
             for (int u = 0; u < EPU; ++u) acc[u] += x[p][u] * jpq;
         }
         const int64_t col = (int64_t)(q < BW ? blo : bhi) * BW + (q % BW);
-        double *dst = Y + col * d;
+        const __amdgpu_buffer_rsrc_t rs = column_rsrc(Y + col * d, d);
 #pragma unroll
-        for (int u = 0; u < EPU; ++u) {
-            const int i = tid + 512 * u;
-            if (i < d) dst[i] = acc[u];
-        }
+        for (int u = 0; u < EPU; ++u) column_store(rs, tid + 512 * u, acc[u]);
     }
     if (tid == 0) {
         atomicAdd(rot_count, nrot);
