@@ -118,84 +118,94 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const int block) 
 
     const int64_t r0 = (int64_t)block * a.rows_per_block;
     const int64_t r1 = min(a.rows, r0 + a.rows_per_block);
-    const bool vec2 = F32 ? (((a.ldt & (W - 1)) == 0) &&
-                             ((reinterpret_cast<uintptr_t>(a.T32) & (4 * W - 1)) == 0))
-                          : (((a.ldt & 1) == 0) && ((reinterpret_cast<uintptr_t>(a.T) & 15) == 0));
-    // R rows of T (and of the per-row vector) starting at j0 into registers;
+    // rows are loaded W columns a lane at a time when the rows are aligned
+    // for it, element by element otherwise
+    const bool vec = F32 ? (((a.ldt & (W - 1)) == 0) &&
+                            ((reinterpret_cast<uintptr_t>(a.T32) & (4 * W - 1)) == 0))
+                         : (((a.ldt & 1) == 0) && ((reinterpret_cast<uintptr_t>(a.T) & 15) == 0));
     // FP32 storage stays FP32 in registers (half the registers per byte in
     // flight) and is widened where it is used
     using E = std::conditional_t<F32, float, double>;
+    const E *tbase;
+    if constexpr (F32) tbase = a.T32;
+    else tbase = a.T;
+    // the per-row vector of this block (loads past r1 return 0)
+    const __amdgpu_buffer_rsrc_t rsy = __builtin_amdgcn_make_buffer_rsrc(
+        a.y + (r0 < r1 ? r0 : 0), (short)0, (int)(r0 < r1 ? (r1 - r0) * 8 : 0), 0x00020000);
+    auto sweep_rows = [&](auto vec_c) {
+    constexpr bool VEC = decltype(vec_c)::value;
+    // R rows of T (and of the per-row vector) starting at j0 into registers.
+    // Each row is read through a raw buffer resource of L elements (none
+    // for rows >= r1): the hardware range check, per dword, returns 0 for
+    // the columns >= L of a lane's vector and for whole rows past the
+    // block, so no load carries a per-lane guard.  (Per-lane guards split
+    // every load into a vector and a scalar path writing the same
+    // registers, and the compiler then waited for all loads in flight,
+    // the prefetched rows included, before each of them.)
     auto load_rows = [&](int64_t j0, E (&av)[R][CPT], double (&yv)[R]) {
 #pragma unroll
         for (int rr = 0; rr < R; ++rr) {
             const int64_t row = j0 + rr;
             const bool valid = row < r1;
-            if constexpr (W == 4) {
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<E *>(tbase + (valid ? row : 0) * a.ldt), (short)0,
+                valid ? L * (int)sizeof(E) : 0, 0x00020000);
+            if constexpr (VEC && W * sizeof(E) == 16) {
+                typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 #pragma unroll
-                for (int e = 0; e < CPT; e += 4) {
+                for (int e = 0; e < CPT; e += W) {
                     const int col = col_of_w<W>(tid, e);
-                    float4 f = make_float4(0.f, 0.f, 0.f, 0.f);
-                    if (valid) {
-                        const float *trow = a.T32 + row * a.ldt;
-                        if (vec2 && col + 3 < L) {
-                            f = *reinterpret_cast<const float4 *>(trow + col);
-                        } else {
-                            if (col < L) f.x = trow[col];
-                            if (col + 1 < L) f.y = trow[col + 1];
-                            if (col + 2 < L) f.z = trow[col + 2];
-                            if (col + 3 < L) f.w = trow[col + 3];
-                        }
+                    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, col * (int)sizeof(E), 0, 0);
+                    if constexpr (F32) {
+                        const float4 f = __builtin_bit_cast(float4, v);
+                        av[rr][e] = f.x;
+                        av[rr][e + 1] = f.y;
+                        av[rr][e + 2] = f.z;
+                        av[rr][e + 3] = f.w;
+                    } else {
+                        const double2 f = __builtin_bit_cast(double2, v);
+                        av[rr][e] = f.x;
+                        av[rr][e + 1] = f.y;
                     }
+                }
+            } else if constexpr (VEC) {  // FP32 pairs
+#pragma unroll
+                for (int e = 0; e < CPT; e += W) {
+                    const int col = col_of_w<W>(tid, e);
+                    const float2 f = __builtin_bit_cast(
+                        float2, __builtin_amdgcn_raw_buffer_load_b64(rs, col * 4, 0, 0));
                     av[rr][e] = f.x;
                     av[rr][e + 1] = f.y;
-                    av[rr][e + 2] = f.z;
-                    av[rr][e + 3] = f.w;
                 }
             } else {
 #pragma unroll
-            for (int e = 0; e < CPT; e += 2) {
-                const int col = col_of_w<W>(tid, e);
-                E vx = 0, vy = 0;
-                if (valid) {
-                    if constexpr (F32) {
-                        const float *trow = a.T32 + row * a.ldt;
-                        if (vec2 && col + 1 < L) {
-                            const float2 f = *reinterpret_cast<const float2 *>(trow + col);
-                            vx = f.x;
-                            vy = f.y;
-                        } else {
-                            if (col < L) vx = trow[col];
-                            if (col + 1 < L) vy = trow[col + 1];
-                        }
-                    } else {
-                        double2 v = make_double2(0.0, 0.0);
-                        const double *trow = a.T + row * a.ldt;
-                        if (vec2 && col + 1 < L) {
-                            v = *reinterpret_cast<const double2 *>(trow + col);
-                        } else {
-                            if (col < L) v.x = trow[col];
-                            if (col + 1 < L) v.y = trow[col + 1];
-                        }
-                        vx = v.x;
-                        vy = v.y;
-                    }
+                for (int e = 0; e < CPT; ++e) {
+                    const int col = col_of_w<W>(tid, e);
+                    if constexpr (F32)
+                        av[rr][e] = __builtin_bit_cast(
+                            float, __builtin_amdgcn_raw_buffer_load_b32(rs, col * 4, 0, 0));
+                    else
+                        av[rr][e] = __builtin_bit_cast(
+                            double, __builtin_amdgcn_raw_buffer_load_b64(rs, col * 8, 0, 0));
                 }
-                av[rr][e] = vx;
-                av[rr][e + 1] = vy;
             }
-            }
-            yv[rr] = (valid && OP != OP_NORMAL) ? a.y[row] : 0.0;
+            if constexpr (OP != OP_NORMAL)
+                yv[rr] = __builtin_bit_cast(
+                    double, __builtin_amdgcn_raw_buffer_load_b64(rsy, (int)(row - r0) * 8, 0, 0));
+            else
+                yv[rr] = 0.0;
         }
     };
     // software pipeline: the loads of the next DEPTH steps are in flight
     // while step k reduces and updates (two steps ahead where the register
     // budget allows it; FP32 rows take half the registers, so the FP32 form
-    // keeps as many bytes in flight as the FP64 one)
+    // keeps as many bytes in flight as the FP64 one).  Rows past the block
+    // load as zeros and are never used.
     constexpr int DEPTH = (F32 ? CPT * R / 2 : CPT * R) <= 16 ? 2 : 1;
     E avn[R][CPT], avm[R][CPT];
     double yvn[R], yvm[R];
-    if (r0 < r1) load_rows(r0, avn, yvn);
-    if (DEPTH == 2 && r0 + R < r1) load_rows(r0 + R, avm, yvm);
+    load_rows(r0, avn, yvn);
+    if (DEPTH == 2) load_rows(r0 + R, avm, yvm);
     int parity = 0;
     for (int64_t j0 = r0; j0 < r1; j0 += R) {
         E av[R][CPT];
@@ -210,11 +220,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const int block) 
                 if (DEPTH == 2) avn[rr][e] = avm[rr][e];
             }
         }
-        if (DEPTH == 2) {
-            if (j0 + 2 * R < r1) load_rows(j0 + 2 * R, avm, yvm);
-        } else {
-            if (j0 + R < r1) load_rows(j0 + R, avn, yvn);
-        }
+        if (DEPTH == 2) load_rows(j0 + 2 * R, avm, yvm);
+        else load_rows(j0 + R, avn, yvn);
         double q[R];
         if (OP != OP_ATB) {
             double pd[R];
@@ -288,6 +295,10 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const int block) 
             for (int e = 0; e < CPT; ++e) zr[e] += c * (double)av[rr][e];
         }
     }
+
+    };
+    if (vec) sweep_rows(std::true_type{});
+    else sweep_rows(std::false_type{});
 
     // Tikhonov rows m + k (row vector lambda e_k) of the augmented tall
     // matrix: handled by the thread that owns column k, in block k % nblocks.
