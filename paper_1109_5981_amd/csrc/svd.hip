@@ -453,6 +453,240 @@ __device__ __forceinline__ void column_store(__amdgpu_buffer_rsrc_t rs, int i, d
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rs, i * 8, 0, 0);
 }
 
+// ------------------------------------------- QR, compact WY trailing updates
+
+// Buffer resource over the rows p0 .. s-1 of column `col` of X (s rows,
+// column-major); empty when `live` is false, so loads return 0 and stores
+// are dropped.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t panel_rsrc(double *X, int64_t s, int64_t p0,
+                                                             int64_t col, bool live) {
+    return __builtin_amdgcn_make_buffer_rsrc(X + col * s + p0, (short)0,
+                                             live ? (int)((s - p0) * (int64_t)sizeof(double)) : 0,
+                                             0x00020000);
+}
+
+// Householder factorisation of the panel of nb <= NB columns at p0 (rows
+// >= p0 in registers: thread t owns rows p0 + t + 1024 e, e < EPT) with a
+// single block reduction per column.  For column j (diagonal row c) the
+// reduction carries |x_j|^2 and x_j . x_k for the later columns k, all over
+// rows >= c; with v = x_j - alpha e_c (alpha = -sign(x_jc) |x_j|) the
+// products the update needs follow as v . x_k = x_j . x_k - alpha x_kc, and
+// x_kc comes from the thread that owns row c.  The reflector
+// H_j = I - beta_j v_j v_j^T is stored in V[:, j] (rows >= p0, zero above
+// row c).  At the end the upper-triangular T of the compact WY form
+// H_1 ... H_nb = I - V T V^T (Schreiber & Van Loan 1989) is formed from
+// V^T V and the betas and written row-major to T (NB x NB).
+template <int NB, int EPT>
+__global__ void __launch_bounds__(1024)
+qr_panel_wy_kernel(double *__restrict__ X, int64_t s, int64_t p0, int nb, double *__restrict__ V,
+                   double *__restrict__ T) {
+    constexpr int NW = 16;
+    constexpr int NG = NB * (NB - 1) / 2;  // strictly upper entries of V^T V
+    constexpr int NGP = NG <= 1 ? 2 : pow2_at_least<NG>();
+    static_assert(NB <= 32 && NGP <= 32, "one butterfly chunk");
+    __shared__ double red[NW][NGP > NB ? NGP : NB];
+    __shared__ double tot[NGP > NB ? NGP : NB];
+    __shared__ double rowc[2][NB];
+    __shared__ double betas[NB];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    double pr[NB][EPT];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        const __amdgpu_buffer_rsrc_t rs = panel_rsrc(X, s, p0, p0 + k, k < nb);
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) pr[k][e] = column_load(rs, tid + 1024 * e);
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        if (j >= nb) break;
+        const int64_t c = p0 + j;
+        const int buf = j & 1;
+        double part[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) part[k] = 0.0;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const bool act = p0 + tid + 1024 * e >= c;
+            const double xj = act ? pr[j][e] : 0.0;
+            part[j] += xj * xj;
+#pragma unroll
+            for (int k = j + 1; k < NB; ++k) part[k] += xj * pr[k][e];
+        }
+        if (tid == j) {  // row c: thread j, e = 0
+#pragma unroll
+            for (int k = j; k < NB; ++k) rowc[buf][k] = pr[k][0];
+        }
+        const double wt = wave_reduce_n<NB>(part);
+        if ((lane & 1) == 0 && (lane >> 1) < NB) red[wid][lane >> 1] = wt;
+        __syncthreads();
+        if (tid < NB) {
+            double t = 0.0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) t += red[w][tid];
+            tot[tid] = t;
+        }
+        __syncthreads();
+        const double nrm2 = tot[j], x0 = rowc[buf][j];
+        const double normx = sqrt(nrm2);
+        const double alpha = x0 >= 0.0 ? -normx : normx;
+        const double v0 = x0 - alpha;
+        const double vtv = nrm2 - x0 * x0 + v0 * v0;
+        const double bet = normx == 0.0 ? 0.0 : 2.0 / vtv;
+        double v[EPT];
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int64_t i = p0 + tid + 1024 * e;
+            v[e] = i > c ? pr[j][e] : (i == c ? v0 : 0.0);
+        }
+#pragma unroll
+        for (int k = j + 1; k < NB; ++k) {
+            if (k < nb) {
+                const double f = bet * (tot[k] - alpha * rowc[buf][k]);
+#pragma unroll
+                for (int e = 0; e < EPT; ++e) pr[k][e] -= f * v[e];
+            }
+        }
+        const __amdgpu_buffer_rsrc_t rv = panel_rsrc(V, s, p0, j, true);
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int64_t i = p0 + tid + 1024 * e;
+            column_store(rv, tid + 1024 * e, v[e]);
+            pr[j][e] = i == c ? alpha : (i > c ? 0.0 : pr[j][e]);
+        }
+        if (tid == 0) betas[j] = bet;
+    }
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        const __amdgpu_buffer_rsrc_t rs = panel_rsrc(X, s, p0, p0 + k, k < nb);
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) column_store(rs, tid + 1024 * e, pr[k][e]);
+    }
+    // T from G = V^T V: T_jj = beta_j, T(0:j, j) = -beta_j T(0:j, 0:j) G(0:j, j).
+    // Each thread reads back the reflector rows it wrote itself.
+    double vv[NB][EPT];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        const __amdgpu_buffer_rsrc_t rv = panel_rsrc(V, s, p0, k, k < nb);
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) vv[k][e] = column_load(rv, tid + 1024 * e);
+    }
+    double g[NGP];
+#pragma unroll
+    for (int q = 0; q < NGP; ++q) g[q] = 0.0;
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = a + 1; b < NB; ++b) {
+            const int q = b * (b - 1) / 2 + a;
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) g[q] += vv[a][e] * vv[b][e];
+        }
+    const double gt = wave_reduce_n<NGP>(g);
+    if ((lane & 1) == 0 && (lane >> 1) < NGP) red[wid][lane >> 1] = gt;
+    __syncthreads();
+    if (tid < NGP) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) t += red[w][tid];
+        tot[tid] = t;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double Tl[NB][NB];
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) Tl[a][b] = 0.0;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            if (b >= nb) break;
+            const double bb = betas[b];
+            Tl[b][b] = bb;
+#pragma unroll
+            for (int a = 0; a < b; ++a) {
+                double t = 0.0;
+#pragma unroll
+                for (int l = a; l < b; ++l) t += Tl[a][l] * tot[b * (b - 1) / 2 + l];
+                Tl[a][b] = -bb * t;
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) T[a * NB + b] = Tl[a][b];
+    }
+}
+
+// Trailing update by the panel's reflectors in compact WY form,
+// x <- (I - V T^T V^T) x = H_nb ... H_1 x, for CPW trailing columns per
+// workgroup (rows >= p0 in registers, thread t owns rows p0 + t + 1024 e):
+// w = V^T x in one block reduction for all columns, u = T^T w, x -= V u.
+template <int NB, int EPT, int CPW>
+__global__ void __launch_bounds__(1024)
+qr_apply_wy_kernel(double *__restrict__ X, int64_t s, int64_t p0, int nb, int64_t ncols,
+                   double *__restrict__ V, const double *__restrict__ T) {
+    constexpr int NW = 16, NV = CPW * NB;
+    static_assert(NV <= 32 && (NV & (NV - 1)) == 0, "one butterfly chunk");
+    __shared__ double red[NW][NV];
+    __shared__ double wt[NV], ut[NV];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int64_t c0 = p0 + nb + (int64_t)blockIdx.x * CPW;
+    double x[CPW][EPT];
+#pragma unroll
+    for (int q = 0; q < CPW; ++q) {
+        const __amdgpu_buffer_rsrc_t rs = panel_rsrc(X, s, p0, c0 + q, c0 + q < p0 + nb + ncols);
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) x[q][e] = column_load(rs, tid + 1024 * e);
+    }
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const __amdgpu_buffer_rsrc_t rv = panel_rsrc(V, s, p0, j, j < nb);
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const double vj = column_load(rv, tid + 1024 * e);
+#pragma unroll
+            for (int q = 0; q < CPW; ++q) acc[q * NB + j] += vj * x[q][e];
+        }
+    }
+    const double wsum = wave_reduce_n<NV>(acc);
+    if ((lane & 1) == 0 && (lane >> 1) < NV) red[wid][lane >> 1] = wsum;
+    __syncthreads();
+    if (tid < NV) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) t += red[w][tid];
+        wt[tid] = t;
+    }
+    __syncthreads();
+    if (tid < NV) {
+        const int q = tid / NB, j = tid % NB;
+        double u = 0.0;
+        if (j < nb)
+            for (int i = 0; i <= j; ++i) u += T[i * NB + j] * wt[q * NB + i];
+        ut[tid] = u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const __amdgpu_buffer_rsrc_t rv = panel_rsrc(V, s, p0, j, j < nb);
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const double vj = column_load(rv, tid + 1024 * e);
+#pragma unroll
+            for (int q = 0; q < CPW; ++q) x[q][e] -= vj * ut[q * NB + j];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < CPW; ++q) {
+        const __amdgpu_buffer_rsrc_t rs = panel_rsrc(X, s, p0, c0 + q, c0 + q < p0 + nb + ncols);
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) column_store(rs, tid + 1024 * e, x[q][e]);
+    }
+}
+
 // Partner of player i (i < NL, NL even) in sub-round TS of the circle-
 // method round robin, and the index of their pair (as in rr_pair), without
 // branches: the sub-round loop is unrolled, so these run once per thread
@@ -765,9 +999,37 @@ void householder_qr(int64_t s, int64_t d, double *X, hipStream_t st) {
     LSRN_REQUIRE(s >= d && d > 0, "qr: need s >= d > 0");
     if (s > 1024 * 40) fail(LSRN_E_UNSUPPORTED, "precond: the QR kernels support sketches of up to 40960 rows");
     DevBuf Vb((size_t)s * QNB * sizeof(double)), betab(QNB * sizeof(double));
-    // panel width: 8 (4 when s > 4096) with the register panel kernel, 32
-    // with the global-memory one for taller sketches
-    const int pw = s <= 4096 ? 8 : (s <= 8192 ? 4 : QNB);
+    if (s <= 8192) {
+        // register panels of 8 columns (4 while more than 4096 rows remain)
+        // with one block reduction per column; trailing updates in compact
+        // WY form, one block reduction per trailing column and panel
+        DevBuf Tb(8 * 8 * sizeof(double));
+        double *Vp = Vb.as<double>(), *Tp = Tb.as<double>();
+        for (int64_t p0 = 0; p0 < d;) {
+            const int64_t rows = s - p0;
+            const int pw = rows <= 4096 ? 8 : 4;
+            const int nb = (int)std::min<int64_t>(pw, d - p0);
+            if (rows <= 1024) qr_panel_wy_kernel<8, 1><<<1, 1024, 0, st>>>(X, s, p0, nb, Vp, Tp);
+            else if (rows <= 2048) qr_panel_wy_kernel<8, 2><<<1, 1024, 0, st>>>(X, s, p0, nb, Vp, Tp);
+            else if (rows <= 4096) qr_panel_wy_kernel<8, 4><<<1, 1024, 0, st>>>(X, s, p0, nb, Vp, Tp);
+            else qr_panel_wy_kernel<4, 8><<<1, 1024, 0, st>>>(X, s, p0, nb, Vp, Tp);
+            LSRN_HIP(hipGetLastError());
+            const int64_t ncols = d - p0 - nb;
+            if (ncols > 0) {
+                const dim3 g4((unsigned)ceil_div(ncols, 4)), g2((unsigned)ceil_div(ncols, 2));
+                if (rows <= 1024) qr_apply_wy_kernel<8, 1, 4><<<g4, 1024, 0, st>>>(X, s, p0, nb, ncols, Vp, Tp);
+                else if (rows <= 2048) qr_apply_wy_kernel<8, 2, 4><<<g4, 1024, 0, st>>>(X, s, p0, nb, ncols, Vp, Tp);
+                else if (rows <= 4096) qr_apply_wy_kernel<8, 4, 4><<<g4, 1024, 0, st>>>(X, s, p0, nb, ncols, Vp, Tp);
+                else qr_apply_wy_kernel<4, 8, 2><<<g2, 1024, 0, st>>>(X, s, p0, nb, ncols, Vp, Tp);
+                LSRN_HIP(hipGetLastError());
+            }
+            p0 += nb;
+        }
+        LSRN_HIP(hipStreamSynchronize(st));  // before the panel buffers are freed
+        return;
+    }
+    // taller sketches: panels of 32 columns in global memory
+    const int pw = QNB;
     for (int64_t p0 = 0; p0 < d; p0 += pw) {
         const int nb = (int)std::min<int64_t>(pw, d - p0);
         double *Vp = Vb.as<double>(), *bp = betab.as<double>();
