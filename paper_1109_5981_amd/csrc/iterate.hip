@@ -395,9 +395,26 @@ gemv_kernel(const double *__restrict__ M, int64_t ld, int64_t nrows, int64_t nco
     const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (row >= nrows) return;
     const int lane = threadIdx.x & 63;
-    const double *mr = M + row * ld;
+    // the row and x through buffer resources of ncols entries: eight loads
+    // of each in flight per lane, zeros past the end, and lane l still sums
+    // its columns l, l + 64, ... in ascending order
+    const int nbytes = (int)(ncols * (int64_t)sizeof(double));
+    const __amdgpu_buffer_rsrc_t rm = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<double *>(M + row * ld), (short)0, nbytes, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<double *>(x), (short)0, nbytes, 0x00020000);
     double t = 0.0;
-    for (int64_t c = lane; c < ncols; c += 64) t += mr[c] * x[c];
+    for (int64_t c0 = 0; c0 < ncols; c0 += 512) {
+        double a[8], b[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int off = (int)(c0 + lane + 64 * k) * 8;
+            a[k] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rm, off, 0, 0));
+            b[k] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rx, off, 0, 0));
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) t += a[k] * b[k];
+    }
     t = wave_sum(t);
     if (lane == 0) y[row] = t;
 }
@@ -1944,9 +1961,26 @@ batch_gemv_kernel(const BatchItem *__restrict__ it, const int *__restrict__ off,
            y = which == 0 ? const_cast<double *>(b.sw.w) : b.x; }
     if (row >= nrows) return;
     const int lane = threadIdx.x & 63;
-    const double *mr = M + row * ld;
+    // the row and x through buffer resources of ncols entries: eight loads
+    // of each in flight per lane, zeros past the end, and lane l still sums
+    // its columns l, l + 64, ... in ascending order
+    const int nbytes = (int)(ncols * (int64_t)sizeof(double));
+    const __amdgpu_buffer_rsrc_t rm = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<double *>(M + row * ld), (short)0, nbytes, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<double *>(x), (short)0, nbytes, 0x00020000);
     double t = 0.0;
-    for (int64_t c = lane; c < ncols; c += 64) t += mr[c] * x[c];
+    for (int64_t c0 = 0; c0 < ncols; c0 += 512) {
+        double a[8], b[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int off = (int)(c0 + lane + 64 * k) * 8;
+            a[k] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rm, off, 0, 0));
+            b[k] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rx, off, 0, 0));
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) t += a[k] * b[k];
+    }
     t = wave_sum(t);
     if (lane == 0) y[row] = t;
 }
