@@ -55,6 +55,21 @@ def test_f32_storage_equals_fp64_storage_of_same_values(L):
     assert np.linalg.norm(host(x1) - host(x2)) / np.linalg.norm(host(x2)) < 1e-11
 
 
+def test_f32_odd_leading_dimension_equals_contiguous(L):
+    """FP32 rows with an odd leading dimension take the element-by-element
+    loads; the solve equals the contiguous one bit for bit."""
+    P = workloads.dense_problem(3000, 70, smin=1e-4, seed=107)
+    A32 = torch.from_numpy(P.A.astype(np.float32)).cuda()
+    m, n = A32.shape
+    big = torch.zeros((m, n + 1), dtype=torch.float32, device="cuda")
+    big[:, :n] = A32
+    A_v = big[:, :n]
+    b = torch.from_numpy(workloads.rhs_gauss(m, 108)).cuda()
+    x_v, _ = L.solve_dense_f32(A_v, b, seed=3, refine=1)
+    x_c, _ = L.solve_dense_f32(A32, b, seed=3, refine=1)
+    np.testing.assert_array_equal(host(x_v), host(x_c))
+
+
 def test_f32_rejections(L):
     A32 = torch.ones(100, 5, dtype=torch.float32, device="cuda")
     b = torch.ones(100, dtype=torch.float64, device="cuda")

@@ -248,6 +248,32 @@ def test_solve_is_bitwise_deterministic(L, dense_workload):
     np.testing.assert_array_equal(host(x1), host(x2))
 
 
+@pytest.mark.parametrize("view", ["odd_lda", "misaligned"])
+def test_padded_and_misaligned_views(L, dense_workload, view):
+    """Rows with an odd leading dimension, or a base that is not 16-byte
+    aligned, are read element by element by the sketch and the sweeps (the
+    paired loads need aligned rows).  The solve reaches the oracle's
+    solution and equals the contiguous solve bit for bit: the summation
+    orders do not depend on how the rows are loaded."""
+    P, b, ref = dense_workload
+    m, n = P.A.shape
+    A_c, b_d = dev(P.A), dev(b)
+    if view == "odd_lda":
+        big = torch.zeros((m, n + 1), dtype=torch.float64, device="cuda")
+        big[:, :n] = A_c
+        A_v = big[:, :n]                     # lda = n + 1 = 101
+    else:
+        big = torch.zeros((m, n + 2), dtype=torch.float64, device="cuda")
+        big[:, 1:n + 1] = A_c
+        A_v = big[:, 1:n + 1]                # base 8 bytes past a 16-byte boundary
+    assert A_v.stride(0) % 2 == 1 or A_v.data_ptr() % 16 == 8
+    x_v, info_v = L.solve_dense(A_v, b_d, seed=5, refine=2)
+    x_c, info_c = L.solve_dense(A_c, b_d, seed=5, refine=2)
+    assert info_v["iters"] == info_c["iters"]
+    np.testing.assert_array_equal(host(x_v), host(x_c))
+    assert rel(host(x_v), ref.x) <= 1e-10
+
+
 @pytest.mark.parametrize("method", [0, 1])
 def test_solve_fat_rank_deficient(L, orc, method):
     Pd = workloads.dense_problem(2500, 60, rank=50, smin=1e-6, seed=13)
