@@ -47,13 +47,85 @@ __device__ __forceinline__ Words4 philox_block(uint64_t seed, uint64_t row, uint
                          (uint32_t)seed, (uint32_t)(seed >> 32));
 }
 
-// Two standard normals from two words; sincospi avoids rounding 2 pi u.
+// -2 ln(u) for u = (a + 1/2) 2^-32.  With a + 1/2 = m 2^e, m in
+// [sqrt(1/2), sqrt(2)), ln m = 2 atanh(f), f = (m - 1)/(m + 1), |f| <= 0.1716,
+// summed as the Taylor series of atanh through f^21 (the next term is below
+// 1e-18 |f|); ln 2 enters split so that (e - 32) ln2_hi is exact.  A few ulp.
+__device__ __forceinline__ double neg2_log_u(uint32_t a) {
+    constexpr double kLn2Hi = 0x1.62e42fefa2000p-1, kLn2Lo = 0x1.9ef35793c7673p-41;
+    const double x = (double)a + 0.5;  // exact
+    int e;
+    double m = frexp(x, &e);  // x = m 2^e, m in [1/2, 1)
+    const bool low = m < 0x1.6a09e667f3bcdp-1;
+    m = low ? 2.0 * m : m;
+    e = low ? e - 1 : e;
+    const double num = m - 1.0;  // exact
+    const double den = m + 1.0;
+    double y = __builtin_amdgcn_rcp(den);
+    y = y * fma(-den, y, 2.0);
+    y = y * fma(-den, y, 2.0);
+    double f = num * y;
+    f = fma(y, fma(-f, den, num), f);  // one correction from the exact residual
+    const double z = f * f;
+    double p = 0x1.8618618618618p-5;  // 1/21
+    p = fma(p, z, 0x1.af286bca1af28p-5);  // 1/19
+    p = fma(p, z, 0x1.e1e1e1e1e1e1ep-5);  // 1/17
+    p = fma(p, z, 0x1.1111111111111p-4);  // 1/15
+    p = fma(p, z, 0x1.3b13b13b13b14p-4);  // 1/13
+    p = fma(p, z, 0x1.745d1745d1746p-4);  // 1/11
+    p = fma(p, z, 0x1.c71c71c71c71cp-4);  // 1/9
+    p = fma(p, z, 0x1.2492492492492p-3);  // 1/7
+    p = fma(p, z, 0x1.999999999999ap-3);  // 1/5
+    p = fma(p, z, 0x1.5555555555555p-2);  // 1/3
+    const double s = fma(f * z, p, f);      // atanh f
+    const double k = (double)(e - 32);
+    const double lnu = fma(k, kLn2Hi, fma(k, kLn2Lo, 2.0 * s));
+    return -2.0 * lnu;
+}
+
+// sin and cos of 2 pi (b + 1/2) 2^-32.  The octant is the top three bits of
+// b; the rest gives r = (c + 1/2) 2^-32 in (0, 1/8) exactly (reflected to
+// 1/8 - r, also exact, in odd octants), t = 2 pi r in (0, pi/4), and the
+// Taylor series of sin t through t^17 and of cos t through t^16 (next
+// terms below 1e-19 and 3e-18); the octant's symmetry then swaps and
+// negates.
+__device__ __forceinline__ void sincos_2pi_u(uint32_t b, double &sn, double &cs) {
+    constexpr double kTwoPiHi = 0x1.921fb54442d18p+2, kTwoPiLo = 0x1.1a62633145c07p-52;
+    const uint32_t oct = b >> 29;
+    uint32_t c = b & 0x1fffffffu;
+    c = (oct & 1u) ? 0x1fffffffu - c : c;
+    const double r = ((double)c + 0.5) * 0x1p-32;
+    const double t = fma(r, kTwoPiHi, r * kTwoPiLo);
+    const double z = t * t;
+    double ps = 0x1.952c77030ad4ap-49;        // 1/17!
+    ps = fma(ps, z, -0x1.ae7f3e733b81fp-41);   // -1/15!
+    ps = fma(ps, z, 0x1.6124613a86d09p-33);    // 1/13!
+    ps = fma(ps, z, -0x1.ae64567f544e4p-26);   // -1/11!
+    ps = fma(ps, z, 0x1.71de3a556c734p-19);    // 1/9!
+    ps = fma(ps, z, -0x1.a01a01a01a01ap-13);   // -1/7!
+    ps = fma(ps, z, 0x1.1111111111111p-7);     // 1/5!
+    ps = fma(ps, z, -0x1.5555555555555p-3);    // -1/3!
+    const double st = fma(t * z, ps, t);
+    double pc = 0x1.ae7f3e733b81fp-45;        // 1/16!
+    pc = fma(pc, z, -0x1.93974a8c07c9dp-37);   // -1/14!
+    pc = fma(pc, z, 0x1.1eed8eff8d898p-29);    // 1/12!
+    pc = fma(pc, z, -0x1.27e4fb7789f5cp-22);   // -1/10!
+    pc = fma(pc, z, 0x1.a01a01a01a01ap-16);    // 1/8!
+    pc = fma(pc, z, -0x1.6c16c16c16c17p-10);   // -1/6!
+    pc = fma(pc, z, 0x1.5555555555555p-5);     // 1/4!
+    pc = fma(pc, z, -0.5);                     // -1/2!
+    const double ct = fma(z, pc, 1.0);
+    const bool swap = (((oct + 1u) >> 1) & 1u) != 0;
+    const double s0 = swap ? ct : st, c0 = swap ? st : ct;
+    sn = oct >= 4u ? -s0 : s0;
+    cs = ((oct + 2u) & 7u) >= 4u ? -c0 : c0;
+}
+
+// Two standard normals from two words.
 __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, double &g0, double &g1) {
-    const double u0 = ((double)a + 0.5) * 0x1p-32;
-    const double u1 = ((double)b + 0.5) * 0x1p-32;
-    const double rad = sqrt(-2.0 * log(u0));
+    const double rad = sqrt(neg2_log_u(a));
     double sn, cs;
-    sincospi(2.0 * u1, &sn, &cs);
+    sincos_2pi_u(b, sn, cs);
     g0 = rad * cs;
     g1 = rad * sn;
 }
