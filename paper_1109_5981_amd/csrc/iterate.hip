@@ -1905,6 +1905,7 @@ struct BatchItem {
     int64_t r, L;
     double *v, *wdir, *yv, *t, *z, *x;
     double tol;
+    int lpr;  // lanes per row of the narrow sweep (0: the wide sweep)
 };
 
 __device__ __forceinline__ int find_item(const int *__restrict__ off, int n, int g) {
@@ -1917,11 +1918,124 @@ __device__ __forceinline__ int find_item(const int *__restrict__ off, int n, int
     return lo;
 }
 
+// The sweep for narrow rows (L <= 8 LPR): LPR lanes share a row, each
+// holding 8 of its columns (pairs interleaved by LPR), so a wavefront
+// works on 64 / LPR rows at a time with no barrier inside the loop; the
+// row products reduce over the LPR lanes of a row, the z partials first
+// over the lanes of a column slot, then over the wavefronts.  T and the
+// per-row vector are read through buffer resources (zeros past the
+// problem); the columns >= L are zeroed by a select.  Tall OP_ATB and
+// OP_LSQR_TALL only.  The problem's rows * ldt doubles must span less
+// than 2^31 bytes.  `zred` holds NT / 64 x 64 x 8 doubles.
+template <int LPR, int OP>
+__device__ __forceinline__ void sweep_narrow_body(const SweepArgs &a, const int block,
+                                                  double *__restrict__ zred,
+                                                  double *__restrict__ accred) {
+    static_assert(OP == OP_ATB || OP == OP_LSQR_TALL, "tall start and LSQR sweeps");
+    constexpr int CPT = 8, RPW = 64 / LPR, NW = NT / 64, STEP = NW * RPW;
+    if (a.st->done) return;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int sl = lane % LPR, rw = lane / LPR;
+    const int L = a.L;
+    double wr[CPT], zr[CPT];
+#pragma unroll
+    for (int e = 0; e < CPT; ++e) {
+        const int col = 2 * sl + 2 * LPR * (e >> 1) + (e & 1);
+        wr[e] = (OP != OP_ATB && col < L) ? a.w[col] : 0.0;
+        zr[e] = 0.0;
+    }
+    const double coef = OP == OP_LSQR_TALL ? a.st->coef : 0.0;
+    const int64_t r0 = (int64_t)block * a.rows_per_block;
+    const int64_t r1 = min(a.rows, r0 + a.rows_per_block);
+    const __amdgpu_buffer_rsrc_t rt = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<double *>(a.T), (short)0, (int)(a.rows * a.ldt * (int64_t)sizeof(double)), 0x00020000);
+    const __amdgpu_buffer_rsrc_t ry = __builtin_amdgcn_make_buffer_rsrc(
+        a.y, (short)0, (int)(r1 * (int64_t)sizeof(double)), 0x00020000);
+    auto load = [&](int64_t j0, double (&av)[CPT], double &yv) {
+        const int64_t row = j0 + wid * RPW + rw;
+        const int base = (int)(row * a.ldt) * 8;
+#pragma unroll
+        for (int e = 0; e < CPT; ++e) {
+            const int col = 2 * sl + 2 * LPR * (e >> 1) + (e & 1);
+            const double v = __builtin_bit_cast(
+                double, __builtin_amdgcn_raw_buffer_load_b64(rt, base + col * 8, 0, 0));
+            av[e] = col < L ? v : 0.0;
+        }
+        yv = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(ry, (int)row * 8, 0, 0));
+    };
+    double avn[CPT], yvn;
+    load(r0, avn, yvn);
+    double acc0 = 0.0;
+    for (int64_t j0 = r0; j0 < r1; j0 += STEP) {
+        double av[CPT];
+#pragma unroll
+        for (int e = 0; e < CPT; ++e) av[e] = avn[e];
+        const double yv = yvn;
+        load(j0 + STEP, avn, yvn);
+        const int64_t row = j0 + wid * RPW + rw;
+        const bool valid = row < r1;
+        double t = 0.0;
+#pragma unroll
+        for (int e = 0; e < CPT; ++e) t += av[e] * wr[e];
+#pragma unroll
+        for (int o = 1; o < LPR; o <<= 1) t += __shfl_xor(t, o, 64);
+        double c = OP == OP_ATB ? yv : t - coef * yv;
+        c = valid ? c : 0.0;
+        if (sl == 0 && valid) {
+            if (OP == OP_LSQR_TALL) a.y[row] = c;
+            acc0 += c * c;
+        }
+#pragma unroll
+        for (int e = 0; e < CPT; ++e) zr[e] += c * av[e];
+    }
+#pragma unroll
+    for (int e = 0; e < CPT; ++e)
+#pragma unroll
+        for (int o = LPR; o < 64; o <<= 1) zr[e] += __shfl_xor(zr[e], o, 64);
+    if (rw == 0) {
+#pragma unroll
+        for (int e = 0; e < CPT; ++e) zred[(wid * 64 + sl) * CPT + e] = zr[e];
+    }
+    acc0 = wave_sum(acc0);
+    if (lane == 0) accred[wid] = acc0;
+    __syncthreads();
+    if (wid == 0 && lane < LPR) {
+#pragma unroll
+        for (int e = 0; e < CPT; ++e) {
+            const int col = 2 * lane + 2 * LPR * (e >> 1) + (e & 1);
+            if (col < L) {
+                double t = 0.0;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) t += zred[(w * 64 + lane) * CPT + e];
+                a.zpart[(int64_t)block * L + col] = t;
+            }
+        }
+    }
+    if (tid < 4) {
+        double t = 0.0;
+        if (tid == 0)
+#pragma unroll
+            for (int w = 0; w < NW; ++w) t += accred[w];
+        a.spart[(int64_t)block * 4 + tid] = t;
+    }
+}
+
 template <int OP>
 __global__ void __launch_bounds__(NT, 2)
 batch_sweep_kernel(const BatchItem *__restrict__ it, const int *__restrict__ off, int n) {
+    __shared__ double zred[(NT / 64) * 64 * 8];
+    __shared__ double accred[NT / 64];
     const int p = find_item(off, n, (int)blockIdx.x);
-    sweep_body<BCPT, BR, OP, false>(it[p].sw, (int)blockIdx.x - off[p]);
+    const int blk = (int)blockIdx.x - off[p];
+    switch (it[p].lpr) {
+        case 2: sweep_narrow_body<2, OP>(it[p].sw, blk, zred, accred); break;
+        case 4: sweep_narrow_body<4, OP>(it[p].sw, blk, zred, accred); break;
+        case 8: sweep_narrow_body<8, OP>(it[p].sw, blk, zred, accred); break;
+        case 16: sweep_narrow_body<16, OP>(it[p].sw, blk, zred, accred); break;
+        case 32: sweep_narrow_body<32, OP>(it[p].sw, blk, zred, accred); break;
+        case 64: sweep_narrow_body<64, OP>(it[p].sw, blk, zred, accred); break;
+        default: sweep_body<BCPT, BR, OP, false>(it[p].sw, blk); break;
+    }
 }
 
 // z_p = sum of the row-block partials, st_p->acc = sum of the scalar partials.
@@ -2045,6 +2159,10 @@ std::vector<IterResult> iterate_batch_tall(const std::vector<IterProblem> &pbs,
         b.v = buf((size_t)r); b.wdir = buf((size_t)r); b.yv = buf((size_t)r); b.t = buf((size_t)r);
         b.z = buf((size_t)L); b.x = xs[(size_t)p];
         b.tol = opt.tol;
+        b.lpr = 0;
+        if ((pb.rows + 512) * pb.ldt < ((int64_t)1 << 28))  // offsets stay in 31 bits
+            for (int l = 2; l <= 64 && !b.lpr; l *= 2)
+                if (L <= 8 * l) b.lpr = l;
         LSRN_HIP(hipMemcpyAsync(b.sw.y, bs[(size_t)p], (size_t)pb.rows * sizeof(double),
                                 hipMemcpyDeviceToDevice, st));
         double sl = 0.0, su = 0.0;
