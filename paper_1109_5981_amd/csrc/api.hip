@@ -751,25 +751,37 @@ lsrn_status lsrn_solve_batch(int32_t count, const int64_t *m, const int64_t *n,
     std::vector<IterProblem> pbs((size_t)count);
     std::vector<const double *> bs((size_t)count);
     std::vector<double *> xs((size_t)count);
-    std::vector<DevBuf> Ps((size_t)count), Xs((size_t)count), sigmas((size_t)count);
+    // the sketches, sigmas and preconditioners of all problems carved from
+    // one allocation each (32-double alignment)
     std::vector<double *> Xp((size_t)count), Pp((size_t)count), sp((size_t)count);
     std::vector<PrecondResult> prs((size_t)count);
     std::vector<int64_t> ss((size_t)count);
+    auto carve = [](size_t elems) { return (std::max<size_t>(elems, 1) + 31) & ~(size_t)31; };
+    size_t nx = 0, np = 0, ns = 0;
     for (int32_t p = 0; p < count; ++p) {
         const int64_t d = n[p];
-        const int64_t s = (int64_t)std::ceil(opt.gamma * (double)d);
-        ss[(size_t)p] = s;
-        Xs[(size_t)p].alloc((size_t)s * (size_t)d * sizeof(double));
-        sigmas[(size_t)p].alloc((size_t)d * sizeof(double));
-        Ps[(size_t)p].alloc((size_t)d * (size_t)d * sizeof(double));
-        Xp[(size_t)p] = Xs[(size_t)p].as<double>();
-        Pp[(size_t)p] = Ps[(size_t)p].as<double>();
-        sp[(size_t)p] = sigmas[(size_t)p].as<double>();
-        sketch_rows(m[p], d, A[p], lda[p], 0.0, s, opt.seed, Xp[(size_t)p], st);
+        ss[(size_t)p] = (int64_t)std::ceil(opt.gamma * (double)d);
+        nx += carve((size_t)ss[(size_t)p] * (size_t)d);
+        np += carve((size_t)d * (size_t)d);
+        ns += carve((size_t)d);
     }
+    DevBuf Xpool(std::max<size_t>(nx, 1) * sizeof(double)), Ppool(std::max<size_t>(np, 1) * sizeof(double));
+    DevBuf Spool(std::max<size_t>(ns, 1) * sizeof(double));
+    size_t ox = 0, op = 0, os = 0;
+    for (int32_t p = 0; p < count; ++p) {
+        const size_t d = (size_t)n[p];
+        Xp[(size_t)p] = Xpool.as<double>() + ox;
+        Pp[(size_t)p] = Ppool.as<double>() + op;
+        sp[(size_t)p] = Spool.as<double>() + os;
+        ox += carve((size_t)ss[(size_t)p] * d);
+        op += carve(d * d);
+        os += carve(d);
+    }
+    if (count > 0)
+        sketch_rows_batch(count, m, n, A, lda, ss.data(), opt.seed, Xp.data(), st);
     precond_batch(count, ss.data(), n, Xp.data(), opt.rcond, sp.data(), Pp.data(), prs.data(), st);
-    Xs.clear();
-    sigmas.clear();
+    Xpool.release();
+    Spool.release();
     for (int32_t p = 0; p < count; ++p) {
         const int64_t d = n[p];
         IterProblem &pb = pbs[(size_t)p];

@@ -28,6 +28,11 @@ void sketch_rows(int64_t K, int64_t d, const double *T, int64_t ldt, double lamb
 void sketch_rows(int64_t K, int64_t d, const float *T, int64_t ldt, double lambda, int64_t s,
                  uint64_t seed, double *X, hipStream_t st, double *kernel_ms = nullptr);
 size_t sketch_workspace_bytes(int64_t K, int64_t d, int64_t s);
+// The sketches of `count` tall problems (T[p] row-major K[p] x d[p]) in one
+// launch per alignment class, no split of K.  Synchronises.
+void sketch_rows_batch(int count, const int64_t *K, const int64_t *d, const double *const *T,
+                       const int64_t *ldt, const int64_t *s, uint64_t seed, double *const *X,
+                       hipStream_t st);
 
 // The precision form's sketch: X = bf16(G) fl32(T) on the BF16 matrix
 // cores (FP32 accumulation flushed to FP64), plus the FP64 rows lambda G of

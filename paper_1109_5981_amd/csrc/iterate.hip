@@ -2127,14 +2127,23 @@ std::vector<IterResult> iterate_batch_tall(const std::vector<IterProblem> &pbs,
     for (const IterProblem &pb : pbs)
         LSRN_REQUIRE(pb.tall && !pb.sp && !pb.T32 && pb.lambda == 0.0 && pb.cols <= 512,
                      "batched iterations: tall dense FP64 problems with n <= 512");
-    // per-problem buffers, one allocation per kind
+    // per-problem buffers carved from one allocation (32-double alignment)
     std::vector<BatchItem> items((size_t)n);
     std::vector<int> off_sw(n + 1), off_red(n + 1), off_gP(n + 1), off_gPt(n + 1), maxit(n);
-    std::vector<DevBuf> bufs;
-    bufs.reserve((size_t)n * 12);
+    auto carve = [](size_t elems) { return (std::max<size_t>(elems, 1) + 31) & ~(size_t)31; };
+    size_t pool_elems = 0;
+    for (const IterProblem &pb : pbs) {
+        const size_t L = (size_t)pb.cols, r = (size_t)pb.r;
+        const size_t nb = (size_t)std::max<int64_t>(1, ceil_div(pb.rows, B_ROWS_PER_BLOCK));
+        pool_elems += carve(nb * L) + carve(nb * 4) + carve((size_t)pb.rows) + carve(L) + carve(r * L) +
+                      4 * carve(r) + carve(L);
+    }
+    DevBuf pool(pool_elems * sizeof(double));
+    size_t pool_used = 0;
     auto buf = [&](size_t elems) {
-        bufs.emplace_back(std::max<size_t>(elems, 1) * sizeof(double));
-        return bufs.back().as<double>();
+        double *q = pool.as<double>() + pool_used;
+        pool_used += carve(elems);
+        return q;
     };
     DevBuf states((size_t)n * sizeof(State));
     for (int p = 0; p < n; ++p) {
@@ -2174,6 +2183,7 @@ std::vector<IterResult> iterate_batch_tall(const std::vector<IterProblem> &pbs,
         off_gP[(size_t)p + 1] = off_gP[(size_t)p] + (int)ceil_div(L, 4);
         off_gPt[(size_t)p + 1] = off_gPt[(size_t)p] + (int)ceil_div(r, 4);
     }
+    LSRN_REQUIRE(pool_used <= pool_elems, "batched iterations: buffer pool overrun");
     DevBuf ditems((size_t)n * sizeof(BatchItem)), doffs((size_t)(4 * (n + 1) + n) * sizeof(int));
     int *o_sw = doffs.as<int>(), *o_red = o_sw + (n + 1), *o_gP = o_red + (n + 1),
         *o_gPt = o_gP + (n + 1), *o_max = o_gPt + (n + 1);

@@ -6,6 +6,8 @@
 // The product runs on the FP64 matrix cores (v_mfma_f64_16x16x4f64): each
 // 256-thread workgroup owns a 128 x 128 tile of X and one slice of K; the
 // slices are summed in a fixed order by a second kernel.
+#include <vector>
+
 #include "internal.hpp"
 #include "rng.hpp"
 
@@ -97,19 +99,20 @@ __device__ __forceinline__ void store_t_stage(double (*Ts)[TP_<WN>], const doubl
     }
 }
 
-template <int WN, bool VEC2, typename TT = double>
-__global__ void __launch_bounds__(NT_<WN>, 4 / WN)
-sketch_mfma_kernel(const TT *__restrict__ T, int64_t ldt, int64_t K, int64_t d, int64_t s,
-                   uint64_t seed, int64_t k_per_split, int tiles_m, double *__restrict__ Xp) {
+// Tile `tile` of X for K-slice `split` (the workgroup's whole work).
+template <int WN, bool VEC2, typename TT>
+__device__ __forceinline__ void sketch_tile(const TT *__restrict__ T, int64_t ldt, int64_t K,
+                                            int64_t d, int64_t s, uint64_t seed,
+                                            int64_t k_per_split, int tiles_m,
+                                            double *__restrict__ Xp, int tile, int split) {
     __shared__ double Gs[2][KT][LDP];
     __shared__ double Ts[2][KT][TP_<WN>];
 
-    const int tile = blockIdx.x;
     const int64_t m0 = (int64_t)(tile % tiles_m) * BM;
     const int64_t n0 = (int64_t)(tile / tiles_m) * BN_<WN>;
-    const int64_t kbeg = (int64_t)blockIdx.y * k_per_split;
+    const int64_t kbeg = (int64_t)split * k_per_split;
     const int64_t kend = min(K, kbeg + k_per_split);
-    double *__restrict__ Xout = Xp + (int64_t)blockIdx.y * s * d;
+    double *__restrict__ Xout = Xp + (int64_t)split * s * d;
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave / WN, wn = wave % WN;
@@ -168,6 +171,40 @@ sketch_mfma_kernel(const TT *__restrict__ T, int64_t ldt, int64_t K, int64_t d, 
                     if (rbase + 4 * v < s) Xout[col * s + rbase + 4 * v] = acc[i][j][v];
             }
         }
+}
+
+template <int WN, bool VEC2, typename TT = double>
+__global__ void __launch_bounds__(NT_<WN>, 4 / WN)
+sketch_mfma_kernel(const TT *__restrict__ T, int64_t ldt, int64_t K, int64_t d, int64_t s,
+                   uint64_t seed, int64_t k_per_split, int tiles_m, double *__restrict__ Xp) {
+    sketch_tile<WN, VEC2, TT>(T, ldt, K, d, s, seed, k_per_split, tiles_m, Xp, (int)blockIdx.x,
+                              (int)blockIdx.y);
+}
+
+// One problem of a batched sketch (no split of K).
+struct SkItem {
+    const double *T;
+    int64_t ldt, K, d, s;
+    double *X;
+    int tiles_m;
+};
+
+// Every tile of every problem in one launch: workgroup g is tile
+// g - off[p] of problem p (off: prefix sums of the tile counts).
+template <bool VEC2>
+__global__ void __launch_bounds__(NT_<2>, 2)
+sketch_batch_kernel(const SkItem *__restrict__ items, const int *__restrict__ off, int n,
+                    uint64_t seed) {
+    const int g = (int)blockIdx.x;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    const SkItem it = items[lo];
+    sketch_tile<2, VEC2, double>(it.T, it.ldt, it.K, it.d, it.s, seed, it.K, it.tiles_m, it.X,
+                                 g - off[lo], 0);
 }
 
 // X[idx] = sum over slices of Xp[slice][idx], slices in ascending order.
@@ -316,6 +353,37 @@ void sketch_rows(int64_t K, int64_t d, const double *T, int64_t ldt, double lamb
 void sketch_rows(int64_t K, int64_t d, const float *T, int64_t ldt, double lambda, int64_t s,
                  uint64_t seed, double *X, hipStream_t st, double *kernel_ms) {
     sketch_rows_t(K, d, T, ldt, lambda, s, seed, X, st, kernel_ms);
+}
+
+void sketch_rows_batch(int count, const int64_t *K, const int64_t *d, const double *const *T,
+                       const int64_t *ldt, const int64_t *s, uint64_t seed, double *const *X,
+                       hipStream_t st) {
+    for (int pass = 0; pass < 2; ++pass) {  // rows aligned for paired loads, then the rest
+        std::vector<SkItem> items;
+        std::vector<int> off(1, 0);
+        for (int p = 0; p < count; ++p) {
+            const bool vec2 = (ldt[p] % 2 == 0) && ((reinterpret_cast<uintptr_t>(T[p]) & 15) == 0);
+            if (vec2 != (pass == 0)) continue;
+            const int tm = (int)ceil_div(s[p], BM), tn = (int)ceil_div(d[p], BN_<2>);
+            items.push_back(SkItem{T[p], ldt[p], K[p], d[p], s[p], X[p], tm});
+            off.push_back(off.back() + tm * tn);
+        }
+        if (items.empty()) continue;
+        const int n = (int)items.size();
+        DevBuf ditems((size_t)n * sizeof(SkItem)), doff(off.size() * sizeof(int));
+        LSRN_HIP(hipMemcpyAsync(ditems.as<SkItem>(), items.data(), (size_t)n * sizeof(SkItem),
+                                hipMemcpyHostToDevice, st));
+        LSRN_HIP(hipMemcpyAsync(doff.as<int>(), off.data(), off.size() * sizeof(int),
+                                hipMemcpyHostToDevice, st));
+        if (pass == 0)
+            sketch_batch_kernel<true><<<(unsigned)off.back(), NT_<2>, 0, st>>>(ditems.as<SkItem>(),
+                                                                               doff.as<int>(), n, seed);
+        else
+            sketch_batch_kernel<false><<<(unsigned)off.back(), NT_<2>, 0, st>>>(ditems.as<SkItem>(),
+                                                                                doff.as<int>(), n, seed);
+        LSRN_HIP(hipGetLastError());
+        LSRN_HIP(hipStreamSynchronize(st));  // before the tables are freed
+    }
 }
 
 void add_identity_rows(int64_t K, int64_t d, int64_t s, double lambda, uint64_t seed, double *X,

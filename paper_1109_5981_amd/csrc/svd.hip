@@ -1243,14 +1243,21 @@ void precond_batch(int count, const int64_t *s, const int64_t *d, double *const 
         }
     }
     std::vector<JacobiPlan> pl((size_t)count);
-    std::vector<DevBuf> Yb((size_t)count);
+    std::vector<double *> Yb((size_t)count);  // carved from one allocation
     std::vector<int> small_ids, gram_ids, other_ids;
+    size_t ytotal = 0;
+    for (int p = 0; p < count; ++p) {
+        pl[(size_t)p] = jacobi_plan(d[p]);
+        ytotal += ((size_t)d[p] * (size_t)pl[(size_t)p].dcols + 31) & ~(size_t)31;
+    }
+    DevBuf Ypool(std::max<size_t>(ytotal, 1) * sizeof(double));
+    size_t yused = 0;
     for (int p = 0; p < count; ++p) {
         res[p] = PrecondResult();
-        pl[(size_t)p] = jacobi_plan(d[p]);
-        Yb[(size_t)p].alloc((size_t)d[p] * (size_t)pl[(size_t)p].dcols * sizeof(double));
+        Yb[(size_t)p] = Ypool.as<double>() + yused;
+        yused += ((size_t)d[p] * (size_t)pl[(size_t)p].dcols + 31) & ~(size_t)31;
         r_to_y_kernel<<<grid1d(d[p] * pl[(size_t)p].dcols), 256, 0, st>>>(
-            X[p], s[p], d[p], pl[(size_t)p].dcols, Yb[(size_t)p].as<double>());
+            X[p], s[p], d[p], pl[(size_t)p].dcols, Yb[(size_t)p]);
         LSRN_HIP(hipGetLastError());
         if (pl[(size_t)p].small) small_ids.push_back(p);
         else if (pl[(size_t)p].variant == 0) gram_ids.push_back(p);
@@ -1263,7 +1270,7 @@ void precond_batch(int count, const int64_t *s, const int64_t *d, double *const 
         size_t bytes = 0;
         for (int k = 0; k < n; ++k) {
             const int p = small_ids[(size_t)k];
-            it[(size_t)k] = JacobiItem{Yb[(size_t)p].as<double>(), (int)d[p], 0,
+            it[(size_t)k] = JacobiItem{Yb[(size_t)p], (int)d[p], 0,
                                        (double)d[p] * DBL_EPSILON, nullptr, nullptr};
             bytes = std::max(bytes, (size_t)d[p] * (size_t)d[p] * sizeof(double));
         }
@@ -1297,7 +1304,7 @@ void precond_batch(int count, const int64_t *s, const int64_t *d, double *const 
         DevBuf dlast((size_t)lastoff[(size_t)n] * sizeof(int));
         for (int k = 0; k < n; ++k) {
             const int p = gram_ids[(size_t)k];
-            it[(size_t)k] = JacobiItem{Yb[(size_t)p].as<double>(), (int)d[p], (int)pl[(size_t)p].nblocks,
+            it[(size_t)k] = JacobiItem{Yb[(size_t)p], (int)d[p], (int)pl[(size_t)p].nblocks,
                                        (double)d[p] * DBL_EPSILON, drot.as<int>() + k,
                                        dlast.as<int>() + lastoff[(size_t)k]};
         }
@@ -1331,9 +1338,38 @@ void precond_batch(int count, const int64_t *s, const int64_t *d, double *const 
     }
     // ---- wider problems: one at a time
     for (int p : other_ids)
-        res[p].sweeps = jacobi_single(Yb[(size_t)p].as<double>(), d[p], pl[(size_t)p], st, false, res[p]);
-    for (int p = 0; p < count; ++p)
-        precond_finish(s[p], d[p], Yb[(size_t)p].as<double>(), rcond, sigma[p], P[p], res[p], st);
+        res[p].sweeps = jacobi_single(Yb[(size_t)p], d[p], pl[(size_t)p], st, false, res[p]);
+    // sigma, order and P of every problem: the norms and sorts in one pass
+    // of launches, one read-back of all sigmas, then the P of each
+    std::vector<size_t> so((size_t)count + 1, 0);
+    for (int p = 0; p < count; ++p) so[(size_t)p + 1] = so[(size_t)p] + (size_t)d[p];
+    DevBuf nrmb(so[(size_t)count] * sizeof(double)), ordb(so[(size_t)count] * sizeof(int64_t));
+    std::vector<double> hs(so[(size_t)count]);
+    for (int p = 0; p < count; ++p) {
+        double *nrm = nrmb.as<double>() + so[(size_t)p];
+        int64_t *ord = ordb.as<int64_t>() + so[(size_t)p];
+        col_norms_kernel<<<(unsigned)ceil_div(d[p], 4), 256, 0, st>>>(Yb[(size_t)p], d[p], nrm);
+        rank_sort_kernel<<<(unsigned)ceil_div(d[p], 256), 256, 0, st>>>(nrm, d[p], ord, sigma[p]);
+        LSRN_HIP(hipGetLastError());
+        LSRN_HIP(hipMemcpyAsync(hs.data() + so[(size_t)p], sigma[p], (size_t)d[p] * sizeof(double),
+                                hipMemcpyDeviceToHost, st));
+    }
+    LSRN_HIP(hipStreamSynchronize(st));
+    for (int p = 0; p < count; ++p) {
+        const double *h = hs.data() + so[(size_t)p];
+        const double rc = rcond > 0.0 ? rcond : (double)std::max(s[p], d[p]) * DBL_EPSILON;
+        int64_t r = 0;
+        while (r < d[p] && h[0] > 0.0 && h[r] > rc * h[0]) ++r;
+        res[p].rank = r;
+        res[p].sigma_max = h[0];
+        res[p].sigma_min_kept = r > 0 ? h[r - 1] : 0.0;
+        if (r > 0) {
+            form_p_kernel<<<grid1d(d[p] * r), 256, 0, st>>>(Yb[(size_t)p], d[p], r,
+                                                            ordb.as<int64_t>() + so[(size_t)p], sigma[p], P[p]);
+            LSRN_HIP(hipGetLastError());
+        }
+    }
+    LSRN_HIP(hipStreamSynchronize(st));
 }
 
 PrecondResult precond_qr_inverse(int64_t s, int64_t d, double *X, double rcond, double *sigma,
