@@ -345,6 +345,122 @@ __global__ void __launch_bounds__(NT, 2) sweep_kernel(SweepArgs a) {
     sweep_body<CPT, R, OP, F32>(a, (int)blockIdx.x);
 }
 
+// The sweep for narrow rows (L <= 8 LPR): LPR lanes share a row, each
+// holding 8 of its columns (pairs interleaved by LPR), so a wavefront
+// works on 64 / LPR rows at a time with no barrier inside the loop; the
+// row products reduce over the LPR lanes of a row, the z partials first
+// over the lanes of a column slot, then over the wavefronts.  T and the
+// per-row vector are read through buffer resources (zeros past the
+// problem); the columns >= L are zeroed by a select.  Tall FP64 ops
+// without Tikhonov rows.  The problem's rows * ldt doubles must span less
+// than 2^31 bytes.  `zred` holds NT / 64 x 64 x 8 doubles.
+template <int LPR, int OP>
+__device__ __forceinline__ void sweep_narrow_body(const SweepArgs &a, const int block,
+                                                  double *__restrict__ zred,
+                                                  double *__restrict__ accred) {
+    static_assert(OP == OP_ATB || OP == OP_LSQR_TALL || OP == OP_CS_TALL || OP == OP_NORMAL,
+                  "tall sweeps");
+    constexpr int CPT = 8, RPW = 64 / LPR, NW = NT / 64, STEP = NW * RPW;
+    if (a.st->done) return;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int sl = lane % LPR, rw = lane / LPR;
+    const int L = a.L;
+    double wr[CPT], zr[CPT];
+#pragma unroll
+    for (int e = 0; e < CPT; ++e) {
+        const int col = 2 * sl + 2 * LPR * (e >> 1) + (e & 1);
+        wr[e] = (OP != OP_ATB && col < L) ? a.w[col] : 0.0;
+        zr[e] = 0.0;
+    }
+    const double coef = OP == OP_LSQR_TALL ? a.st->coef : (OP == OP_CS_TALL ? a.alpha : 0.0);
+    const int64_t r0 = (int64_t)block * a.rows_per_block;
+    const int64_t r1 = min(a.rows, r0 + a.rows_per_block);
+    const __amdgpu_buffer_rsrc_t rt = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<double *>(a.T), (short)0, (int)(a.rows * a.ldt * (int64_t)sizeof(double)), 0x00020000);
+    const __amdgpu_buffer_rsrc_t ry = __builtin_amdgcn_make_buffer_rsrc(
+        a.y, (short)0, (int)(r1 * (int64_t)sizeof(double)), 0x00020000);
+    auto load = [&](int64_t j0, double (&av)[CPT], double &yv) {
+        const int64_t row = j0 + wid * RPW + rw;
+        const int base = (int)(row * a.ldt) * 8;
+#pragma unroll
+        for (int e = 0; e < CPT; ++e) {
+            const int col = 2 * sl + 2 * LPR * (e >> 1) + (e & 1);
+            const double v = __builtin_bit_cast(
+                double, __builtin_amdgcn_raw_buffer_load_b64(rt, base + col * 8, 0, 0));
+            av[e] = col < L ? v : 0.0;
+        }
+        yv = OP == OP_NORMAL ? 0.0
+                             : __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(ry, (int)row * 8, 0, 0));
+    };
+    double avn[CPT], yvn;
+    load(r0, avn, yvn);
+    double acc0 = 0.0;
+    for (int64_t j0 = r0; j0 < r1; j0 += STEP) {
+        double av[CPT];
+#pragma unroll
+        for (int e = 0; e < CPT; ++e) av[e] = avn[e];
+        const double yv = yvn;
+        load(j0 + STEP, avn, yvn);
+        const int64_t row = j0 + wid * RPW + rw;
+        const bool valid = row < r1;
+        double t = 0.0;
+#pragma unroll
+        for (int e = 0; e < CPT; ++e) t += av[e] * wr[e];
+#pragma unroll
+        for (int o = 1; o < LPR; o <<= 1) t += __shfl_xor(t, o, 64);
+        double c;
+        if (OP == OP_ATB) c = yv;
+        else if (OP == OP_LSQR_TALL) c = t - coef * yv;
+        else if (OP == OP_CS_TALL) c = yv - coef * t;
+        else c = t;
+        c = valid ? c : 0.0;
+        if (sl == 0 && valid) {
+            if (OP == OP_LSQR_TALL || OP == OP_CS_TALL) a.y[row] = c;
+            acc0 += c * c;
+        }
+#pragma unroll
+        for (int e = 0; e < CPT; ++e) zr[e] += c * av[e];
+    }
+#pragma unroll
+    for (int e = 0; e < CPT; ++e)
+#pragma unroll
+        for (int o = LPR; o < 64; o <<= 1) zr[e] += __shfl_xor(zr[e], o, 64);
+    if (rw == 0) {
+#pragma unroll
+        for (int e = 0; e < CPT; ++e) zred[(wid * 64 + sl) * CPT + e] = zr[e];
+    }
+    acc0 = wave_sum(acc0);
+    if (lane == 0) accred[wid] = acc0;
+    __syncthreads();
+    if (wid == 0 && lane < LPR) {
+#pragma unroll
+        for (int e = 0; e < CPT; ++e) {
+            const int col = 2 * lane + 2 * LPR * (e >> 1) + (e & 1);
+            if (col < L) {
+                double t = 0.0;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) t += zred[(w * 64 + lane) * CPT + e];
+                a.zpart[(int64_t)block * L + col] = t;
+            }
+        }
+    }
+    if (tid < 4) {
+        double t = 0.0;
+        if (tid == 0)
+#pragma unroll
+            for (int w = 0; w < NW; ++w) t += accred[w];
+        a.spart[(int64_t)block * 4 + tid] = t;
+    }
+}
+
+template <int LPR, int OP>
+__global__ void __launch_bounds__(NT, 2) sweep_narrow_kernel(SweepArgs a) {
+    __shared__ double zred[(NT / 64) * 64 * 8];
+    __shared__ double accred[NT / 64];
+    sweep_narrow_body<LPR, OP>(a, (int)blockIdx.x, zred, accred);
+}
+
+
 // Stage 1 of the partial-sum reduction: group g of the workgroup partials
 // (rows [g*chunk, (g+1)*chunk) of zpart) summed per column.
 __global__ void __launch_bounds__(256)
@@ -1131,6 +1247,7 @@ struct Ctx {
     int nblocks;
     int64_t rows_per_block;
     int cpt, R;
+    int narrow = 0;  // lanes per row of the narrow tall sweep (0: the wide sweep)
     int ngroups, chunk;
     DevBuf zpart, spart, zred, sred, z, stbuf, Pt;
     DevBuf zseg;  // sparse: per-segment column sums
@@ -1186,6 +1303,10 @@ struct Ctx {
         else if (L <= 2048) { cpt = 8; R = 4; }
         else if (L <= 4096) { cpt = 16; R = 2; }
         else fail(LSRN_E_UNSUPPORTED, "dense iteration supports min(m, n) <= 4096");
+        // narrow tall rows: LPR lanes per row instead of the whole workgroup
+        if (pb.tall && L <= 256 && (pb.rows + 512) * pb.ldt < ((int64_t)1 << 28))
+            for (int l = 2; l <= 32 && !narrow; l *= 2)
+                if (L <= 8 * l) narrow = l;
         // workgroups per compute unit: a recorded (tuned) value for this
         // shape key, else 2; with autotune and no record, every candidate is
         // timed below on this problem and the fastest recorded
@@ -1274,6 +1395,24 @@ struct Ctx {
             default: sweep_kernel<CPT, RR, OP_CS_FAT, F32><<<nblocks, NT, 0, st>>>(a); break;
         }
     }
+    template <int LPR>
+    void sweep_narrow_l(int op, SweepArgs &a) {
+        switch (op) {
+            case OP_ATB: sweep_narrow_kernel<LPR, OP_ATB><<<nblocks, NT, 0, st>>>(a); break;
+            case OP_LSQR_TALL: sweep_narrow_kernel<LPR, OP_LSQR_TALL><<<nblocks, NT, 0, st>>>(a); break;
+            case OP_CS_TALL: sweep_narrow_kernel<LPR, OP_CS_TALL><<<nblocks, NT, 0, st>>>(a); break;
+            default: sweep_narrow_kernel<LPR, OP_NORMAL><<<nblocks, NT, 0, st>>>(a); break;
+        }
+    }
+    void sweep_narrow(int op, SweepArgs &a) {
+        switch (narrow) {
+            case 2: sweep_narrow_l<2>(op, a); break;
+            case 4: sweep_narrow_l<4>(op, a); break;
+            case 8: sweep_narrow_l<8>(op, a); break;
+            case 16: sweep_narrow_l<16>(op, a); break;
+            default: sweep_narrow_l<32>(op, a); break;
+        }
+    }
     template <int CPT, int RR>
     void sweep_t(int op, SweepArgs &a) {
         if (a.T32) sweep_tf<CPT, RR, true>(op, a);
@@ -1305,7 +1444,9 @@ struct Ctx {
             ev.push_back(e1);
             LSRN_HIP(hipEventRecord(e0, st));
         }
-        if (cpt == 2) sweep_t<2, 8>(op, a);
+        if (narrow && !a.T32 && a.lambda == 0.0 &&
+            (op == OP_ATB || op == OP_LSQR_TALL || op == OP_CS_TALL || op == OP_NORMAL)) sweep_narrow(op, a);
+        else if (cpt == 2) sweep_t<2, 8>(op, a);
         else if (cpt == 4) sweep_t<4, 4>(op, a);
         else if (cpt == 8) sweep_t<8, 4>(op, a);
         else sweep_t<16, 2>(op, a);
@@ -1916,108 +2057,6 @@ __device__ __forceinline__ int find_item(const int *__restrict__ off, int n, int
         else hi = mid - 1;
     }
     return lo;
-}
-
-// The sweep for narrow rows (L <= 8 LPR): LPR lanes share a row, each
-// holding 8 of its columns (pairs interleaved by LPR), so a wavefront
-// works on 64 / LPR rows at a time with no barrier inside the loop; the
-// row products reduce over the LPR lanes of a row, the z partials first
-// over the lanes of a column slot, then over the wavefronts.  T and the
-// per-row vector are read through buffer resources (zeros past the
-// problem); the columns >= L are zeroed by a select.  Tall OP_ATB and
-// OP_LSQR_TALL only.  The problem's rows * ldt doubles must span less
-// than 2^31 bytes.  `zred` holds NT / 64 x 64 x 8 doubles.
-template <int LPR, int OP>
-__device__ __forceinline__ void sweep_narrow_body(const SweepArgs &a, const int block,
-                                                  double *__restrict__ zred,
-                                                  double *__restrict__ accred) {
-    static_assert(OP == OP_ATB || OP == OP_LSQR_TALL, "tall start and LSQR sweeps");
-    constexpr int CPT = 8, RPW = 64 / LPR, NW = NT / 64, STEP = NW * RPW;
-    if (a.st->done) return;
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int sl = lane % LPR, rw = lane / LPR;
-    const int L = a.L;
-    double wr[CPT], zr[CPT];
-#pragma unroll
-    for (int e = 0; e < CPT; ++e) {
-        const int col = 2 * sl + 2 * LPR * (e >> 1) + (e & 1);
-        wr[e] = (OP != OP_ATB && col < L) ? a.w[col] : 0.0;
-        zr[e] = 0.0;
-    }
-    const double coef = OP == OP_LSQR_TALL ? a.st->coef : 0.0;
-    const int64_t r0 = (int64_t)block * a.rows_per_block;
-    const int64_t r1 = min(a.rows, r0 + a.rows_per_block);
-    const __amdgpu_buffer_rsrc_t rt = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<double *>(a.T), (short)0, (int)(a.rows * a.ldt * (int64_t)sizeof(double)), 0x00020000);
-    const __amdgpu_buffer_rsrc_t ry = __builtin_amdgcn_make_buffer_rsrc(
-        a.y, (short)0, (int)(r1 * (int64_t)sizeof(double)), 0x00020000);
-    auto load = [&](int64_t j0, double (&av)[CPT], double &yv) {
-        const int64_t row = j0 + wid * RPW + rw;
-        const int base = (int)(row * a.ldt) * 8;
-#pragma unroll
-        for (int e = 0; e < CPT; ++e) {
-            const int col = 2 * sl + 2 * LPR * (e >> 1) + (e & 1);
-            const double v = __builtin_bit_cast(
-                double, __builtin_amdgcn_raw_buffer_load_b64(rt, base + col * 8, 0, 0));
-            av[e] = col < L ? v : 0.0;
-        }
-        yv = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(ry, (int)row * 8, 0, 0));
-    };
-    double avn[CPT], yvn;
-    load(r0, avn, yvn);
-    double acc0 = 0.0;
-    for (int64_t j0 = r0; j0 < r1; j0 += STEP) {
-        double av[CPT];
-#pragma unroll
-        for (int e = 0; e < CPT; ++e) av[e] = avn[e];
-        const double yv = yvn;
-        load(j0 + STEP, avn, yvn);
-        const int64_t row = j0 + wid * RPW + rw;
-        const bool valid = row < r1;
-        double t = 0.0;
-#pragma unroll
-        for (int e = 0; e < CPT; ++e) t += av[e] * wr[e];
-#pragma unroll
-        for (int o = 1; o < LPR; o <<= 1) t += __shfl_xor(t, o, 64);
-        double c = OP == OP_ATB ? yv : t - coef * yv;
-        c = valid ? c : 0.0;
-        if (sl == 0 && valid) {
-            if (OP == OP_LSQR_TALL) a.y[row] = c;
-            acc0 += c * c;
-        }
-#pragma unroll
-        for (int e = 0; e < CPT; ++e) zr[e] += c * av[e];
-    }
-#pragma unroll
-    for (int e = 0; e < CPT; ++e)
-#pragma unroll
-        for (int o = LPR; o < 64; o <<= 1) zr[e] += __shfl_xor(zr[e], o, 64);
-    if (rw == 0) {
-#pragma unroll
-        for (int e = 0; e < CPT; ++e) zred[(wid * 64 + sl) * CPT + e] = zr[e];
-    }
-    acc0 = wave_sum(acc0);
-    if (lane == 0) accred[wid] = acc0;
-    __syncthreads();
-    if (wid == 0 && lane < LPR) {
-#pragma unroll
-        for (int e = 0; e < CPT; ++e) {
-            const int col = 2 * lane + 2 * LPR * (e >> 1) + (e & 1);
-            if (col < L) {
-                double t = 0.0;
-#pragma unroll
-                for (int w = 0; w < NW; ++w) t += zred[(w * 64 + lane) * CPT + e];
-                a.zpart[(int64_t)block * L + col] = t;
-            }
-        }
-    }
-    if (tid < 4) {
-        double t = 0.0;
-        if (tid == 0)
-#pragma unroll
-            for (int w = 0; w < NW; ++w) t += accred[w];
-        a.spart[(int64_t)block * 4 + tid] = t;
-    }
 }
 
 template <int OP>

@@ -282,74 +282,6 @@ __device__ __forceinline__ void rr_pair(int n, int t, int k, int &a, int &b) {
     }
 }
 
-// Rotation of columns (wp, wq) of length len, one wavefront; returns 1 if
-// the pair was rotated.  Golub & Van Loan Sec. 8.6 formula.
-__device__ __forceinline__ int rotate_pair(double *wp, double *wq, int len, double tol) {
-    const int lane = threadIdx.x & 63;
-    double a = 0.0, b = 0.0, g = 0.0;
-    for (int i = lane; i < len; i += 64) {
-        const double x = wp[i], y = wq[i];
-        a += x * x;
-        b += y * y;
-        g += x * y;
-    }
-    a = wave_sum(a);
-    b = wave_sum(b);
-    g = wave_sum(g);
-    if (g == 0.0 || fabs(g) <= tol * sqrt(a) * sqrt(b)) return 0;
-    const double zeta = (b - a) / (2.0 * g);
-    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
-    const double c = 1.0 / sqrt(1.0 + t * t);
-    const double sn = c * t;
-    for (int i = lane; i < len; i += 64) {
-        const double x = wp[i], y = wq[i];
-        wp[i] = c * x - sn * y;
-        wq[i] = sn * x + c * y;
-    }
-    return 1;
-}
-
-// Whole matrix in LDS (d <= 128), all sweeps in one workgroup.
-__device__ __forceinline__ void jacobi_small(double *__restrict__ Y, int d, int max_sweeps,
-                                             double tol, int *__restrict__ sweeps_out) {
-    extern __shared__ double W[];  // d * d, column p at W + p*d
-    __shared__ int rot;
-    const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
-    const int nw = blockDim.x >> 6;
-    for (int t = tid; t < d * d; t += blockDim.x) W[t] = Y[t];
-    const int n = d + (d & 1);
-    int sweep = 0;
-    for (; sweep < max_sweeps; ++sweep) {
-        if (tid == 0) rot = 0;
-        __syncthreads();
-        int mine = 0;
-        for (int round = 0; round < n - 1; ++round) {
-            for (int k = wid; k < n / 2; k += nw) {
-                int p, q;
-                rr_pair(n, round, k, p, q);
-                if (p < d && q < d) {
-                    if (p > q) { const int tmp = p; p = q; q = tmp; }
-                    mine += rotate_pair(W + p * d, W + q * d, d, tol);
-                }
-            }
-            __syncthreads();
-        }
-        if (lane == 0 && mine) atomicAdd(&rot, mine);
-        __syncthreads();
-        const int total = rot;
-        __syncthreads();
-        if (total == 0) break;
-    }
-    for (int t = tid; t < d * d; t += blockDim.x) Y[t] = W[t];
-    if (tid == 0) *sweeps_out = sweep + 1;
-}
-
-__global__ void __launch_bounds__(1024)
-jacobi_small_kernel(double *__restrict__ Y, int d, int max_sweeps, double tol,
-                    int *__restrict__ sweeps_out) {
-    jacobi_small(Y, d, max_sweeps, tol, sweeps_out);
-}
-
 // Compile-time round-robin pair (same schedule as rr_pair).
 template <int N, int T, int K>
 struct RR {
@@ -436,6 +368,78 @@ __device__ __forceinline__ bool jacobi_angle(double a, double b, double g, doubl
     c = rsqrt_nr<2>(fma(t, t, 1.0));
     s = c * t;
     return true;
+}
+
+// Whole matrix in LDS (d <= 128), all sweeps in one workgroup of 1024
+// threads.  In each round of the circle-method round robin every pair is
+// rotated at once by its own group of 16 lanes (lane j holds rows j, j + 16,
+// ... in registers); the group's three inner products reduce by xor
+// butterflies inside the group, so a round costs one barrier.
+__device__ __forceinline__ void jacobi_small(double *__restrict__ Y, int d, int max_sweeps,
+                                             double tol, int *__restrict__ sweeps_out) {
+    extern __shared__ double W[];  // d * d, column p at W + p*d
+    __shared__ int rot;
+    constexpr int GS = 16, RPL = 128 / GS;  // lanes per pair, rows per lane
+    const int tid = threadIdx.x, grp = tid / GS, j = tid % GS;
+    for (int t = tid; t < d * d; t += blockDim.x) W[t] = Y[t];
+    const int n = d + (d & 1);
+    int sweep = 0;
+    for (; sweep < max_sweeps; ++sweep) {
+        if (tid == 0) rot = 0;
+        __syncthreads();
+        int mine = 0;
+        for (int round = 0; round < n - 1; ++round) {
+            int p = 0, q = 0;
+            if (grp < n / 2) {
+                rr_pair(n, round, grp, p, q);
+                if (p > q) { const int t = p; p = q; q = t; }
+            }
+            const bool live = grp < n / 2 && q < d;
+            double xr[RPL], yr[RPL], a = 0.0, b = 0.0, g = 0.0;
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) {
+                const int i = j + GS * k;
+                const bool in = live && i < d;
+                xr[k] = in ? W[p * d + i] : 0.0;
+                yr[k] = in ? W[q * d + i] : 0.0;
+                a += xr[k] * xr[k];
+                b += yr[k] * yr[k];
+                g += xr[k] * yr[k];
+            }
+#pragma unroll
+            for (int o = 1; o < GS; o <<= 1) {
+                a += __shfl_xor(a, o, 64);
+                b += __shfl_xor(b, o, 64);
+                g += __shfl_xor(g, o, 64);
+            }
+            double c, sn;
+            if (live && jacobi_angle(a, b, g, tol, c, sn)) {
+#pragma unroll
+                for (int k = 0; k < RPL; ++k) {
+                    const int i = j + GS * k;
+                    if (i < d) {
+                        W[p * d + i] = c * xr[k] - sn * yr[k];
+                        W[q * d + i] = sn * xr[k] + c * yr[k];
+                    }
+                }
+                if (j == 0) ++mine;
+            }
+            __syncthreads();
+        }
+        if (mine) atomicAdd(&rot, mine);
+        __syncthreads();
+        const int total = rot;
+        __syncthreads();
+        if (total == 0) break;
+    }
+    for (int t = tid; t < d * d; t += blockDim.x) Y[t] = W[t];
+    if (tid == 0) *sweeps_out = sweep + 1;
+}
+
+__global__ void __launch_bounds__(1024)
+jacobi_small_kernel(double *__restrict__ Y, int d, int max_sweeps, double tol,
+                    int *__restrict__ sweeps_out) {
+    jacobi_small(Y, d, max_sweeps, tol, sweeps_out);
 }
 
 // Raw buffer resource over the n doubles of one column at p: the hardware
