@@ -27,6 +27,17 @@ FP64_MFMA_PEAK_TFS = 78.6    # MI355X dense FP64 matrix
 BF16_MFMA_PEAK_TFS = 2500.0  # MI355X dense BF16 matrix
 FP64_VECTOR_PEAK_TFS = 78.6  # MI355X FP64 vector: 256 CUs x 64 FMA/clk x 2 x 2.4 GHz
 
+# HBM bytes per launch of a workload's dominant kernel, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE passes over this script (averaged over every
+# launch of the kernel in one timed solve, like `achieved`), scaled by the
+# counters of a plain 1 GiB device copy (FETCH_SIZE reads half the copied
+# bytes, WRITE_SIZE all of them).  Commands and per-kernel figures:
+# profiles/pmc_traffic_rankdef_200000x2000.md.  An entry is dropped when
+# its kernel changes.
+MEASURED_TRAFFIC = {
+    ("rankdef_200000x2000", "fp64", "f64", "jacobi_round"): 50.5e6,
+}
+
 WORKLOADS = {
     "rankdef_200000x2000": dict(m=200_000, n=2000, rank=1800, smin=1e-6, seed=12, fat=False),
     "rankdef_2000x200000": dict(m=200_000, n=2000, rank=1800, smin=1e-6, seed=112, fat=True),
@@ -569,7 +580,8 @@ def main():
         kk = kernels[dom]
         roofline = {"kernel": dom, "bound": kk["bound"], "achieved": round(kk["achieved"], 3),
                     "peak": kk["peak"], "unit": kk["unit"],
-                    "frac": round(kk["achieved"] / kk["peak"], 4), "traffic": None}
+                    "frac": round(kk["achieved"] / kk["peak"], 4),
+                    "traffic": MEASURED_TRAFFIC.get((args.workload, args.precision, args.storage, dom))}
 
     cpu = None
     if not args.no_cpu_baseline and args.workload == "rankdef_200000x2000":
