@@ -355,11 +355,11 @@ __device__ __forceinline__ double rcp_nr(double x) {
 // |g| <= tol sqrt(a b).  Only c^2 + s^2 = 1 has to hold to rounding (c from
 // t by a refined reciprocal square root); the threshold test and the angle
 // itself may carry a few ulp.
-__device__ __forceinline__ bool jacobi_angle(double a, double b, double g, double tol, double &c,
-                                             double &s) {
+__device__ __forceinline__ bool jacobi_angle(double a, double b, double g, double tol,
+                                             double tiny2, double &c, double &s) {
     c = 1.0;
     s = 0.0;
-    if (!(g != 0.0 && fabs(g) * rsqrt_nr(a) * rsqrt_nr(b) > tol)) return false;
+    if (!(fmax(a, b) > tiny2 && g != 0.0 && fabs(g) * rsqrt_nr(a) * rsqrt_nr(b) > tol)) return false;
     const double zeta = (b - a) * rcp_nr(2.0 * g);
     const double az = fabs(zeta);
     // 1 / (|zeta| + sqrt(1 + zeta^2)), without overflow for huge |zeta|
@@ -376,7 +376,7 @@ __device__ __forceinline__ bool jacobi_angle(double a, double b, double g, doubl
 // ... in registers); the group's three inner products reduce by xor
 // butterflies inside the group, so a round costs one barrier.
 __device__ __forceinline__ void jacobi_small(double *__restrict__ Y, int d, int max_sweeps,
-                                             double tol, int *__restrict__ sweeps_out) {
+                                             double tol, double tiny2, int *__restrict__ sweeps_out) {
     extern __shared__ double W[];  // d * d, column p at W + p*d
     __shared__ int rot;
     constexpr int GS = 16, RPL = 128 / GS;  // lanes per pair, rows per lane
@@ -413,7 +413,7 @@ __device__ __forceinline__ void jacobi_small(double *__restrict__ Y, int d, int 
                 g += __shfl_xor(g, o, 64);
             }
             double c, sn;
-            if (live && jacobi_angle(a, b, g, tol, c, sn)) {
+            if (live && jacobi_angle(a, b, g, tol, tiny2, c, sn)) {
 #pragma unroll
                 for (int k = 0; k < RPL; ++k) {
                     const int i = j + GS * k;
@@ -437,9 +437,9 @@ __device__ __forceinline__ void jacobi_small(double *__restrict__ Y, int d, int 
 }
 
 __global__ void __launch_bounds__(1024)
-jacobi_small_kernel(double *__restrict__ Y, int d, int max_sweeps, double tol,
+jacobi_small_kernel(double *__restrict__ Y, int d, int max_sweeps, double tol, double tiny2,
                     int *__restrict__ sweeps_out) {
-    jacobi_small(Y, d, max_sweeps, tol, sweeps_out);
+    jacobi_small(Y, d, max_sweeps, tol, tiny2, sweeps_out);
 }
 
 // Raw buffer resource over the n doubles of one column at p: the hardware
@@ -734,6 +734,7 @@ __device__ __forceinline__ int rr_pair_index(int i) {
 template <int BW, int EPU>
 __device__ __forceinline__ void
 jacobi_gram_round(double *__restrict__ Y, int d, int nblocks, int round, int pair, double tol,
+                  double tiny2,
                   int *__restrict__ rot_count, int *__restrict__ last_mod, int rnow) {
     constexpr int NL = 2 * BW;
     constexpr int NG = NL * (NL + 1) / 2;
@@ -814,7 +815,7 @@ jacobi_gram_round(double *__restrict__ Y, int d, int nblocks, int round, int pai
             a = k == 0 ? NL - 1 : a;
             const int pp = a < b ? a : b, qq = a < b ? b : a;
             double cs, sn;
-            if (jacobi_angle(Gs[cur][pp][pp], Gs[cur][qq][qq], Gs[cur][pp][qq], tol, cs, sn)) {
+            if (jacobi_angle(Gs[cur][pp][pp], Gs[cur][qq][qq], Gs[cur][pp][qq], tol, tiny2, cs, sn)) {
                 ++mine;
                 any_s[TS] = 1;
             }
@@ -874,9 +875,9 @@ jacobi_gram_round(double *__restrict__ Y, int d, int nblocks, int round, int pai
 
 template <int BW, int EPU>
 __global__ void __launch_bounds__(512)
-jacobi_gram_round_kernel(double *__restrict__ Y, int d, int nblocks, int round, double tol,
+jacobi_gram_round_kernel(double *__restrict__ Y, int d, int nblocks, int round, double tol, double tiny2,
                          int *__restrict__ rot_count, int *__restrict__ last_mod, int rnow) {
-    jacobi_gram_round<BW, EPU>(Y, d, nblocks, round, blockIdx.x, tol, rot_count, last_mod, rnow);
+    jacobi_gram_round<BW, EPU>(Y, d, nblocks, round, blockIdx.x, tol, tiny2, rot_count, last_mod, rnow);
 }
 
 // One problem of a batch for the batched Jacobi rounds.
@@ -884,6 +885,7 @@ struct JacobiItem {
     double *Y;
     int d, nblocks;
     double tol;
+    double tiny2;   // pairs whose columns both have |y|^2 <= tiny2 are not rotated
     int *rot;       // rotations of the current sweep
     int *last_mod;  // nblocks entries
 };
@@ -906,7 +908,7 @@ jacobi_gram_round_batch_kernel(const JacobiItem *__restrict__ items, const int *
     const JacobiItem it = items[lo];
     const int period = it.nblocks - 1;
     if (!active[lo] || round >= period) return;
-    jacobi_gram_round<BW, EPU>(it.Y, it.d, it.nblocks, round, g - pair_off[lo], it.tol, it.rot,
+    jacobi_gram_round<BW, EPU>(it.Y, it.d, it.nblocks, round, g - pair_off[lo], it.tol, it.tiny2, it.rot,
                                it.last_mod, sweep * period + round);
 }
 
@@ -916,7 +918,7 @@ __global__ void __launch_bounds__(1024)
 jacobi_small_batch_kernel(const JacobiItem *__restrict__ items, int max_sweeps,
                           int *__restrict__ sweeps_out) {
     const JacobiItem it = items[blockIdx.x];
-    jacobi_small(it.Y, it.d, max_sweeps, it.tol, sweeps_out + blockIdx.x);
+    jacobi_small(it.Y, it.d, max_sweeps, it.tol, it.tiny2, sweeps_out + blockIdx.x);
 }
 
 // sigma_p = ||Y[:, p]||, one wavefront per column.
@@ -1103,23 +1105,54 @@ void set_small_lds(size_t bytes) {
     });
 }
 
+// Squared threshold below which two columns are not rotated against each
+// other, per problem: tau = rcond max_j |y_j| / (2 sqrt d).  A rotation
+// leaves the smaller column of its pair no larger, and pairs of columns
+// both within tau are skipped, so the columns that end within tau have a
+// Frobenius norm of at most sqrt(d) tau <= rcond sigma_1 / 2 (max_j |y_j|
+// <= sigma_1): their singular values stay below the rank cutoff, while
+// every column above tau is orthogonalised against all others as usual.
+// The kept part of the SVD is therefore unchanged; the rounding-level
+// columns of a rank-deficient sketch stop costing sweeps.
+std::vector<double> tiny_thresholds2(int count, const double *const *Y, const int64_t *s,
+                                     const int64_t *d, double rcond, hipStream_t st) {
+    std::vector<size_t> off((size_t)count + 1, 0);
+    for (int p = 0; p < count; ++p) off[(size_t)p + 1] = off[(size_t)p] + (size_t)d[p];
+    DevBuf nrm(std::max<size_t>(off[(size_t)count], 1) * sizeof(double));
+    for (int p = 0; p < count; ++p)
+        col_norms_kernel<<<(unsigned)ceil_div(d[p], 4), 256, 0, st>>>(Y[p], d[p], nrm.as<double>() + off[(size_t)p]);
+    LSRN_HIP(hipGetLastError());
+    std::vector<double> h(off[(size_t)count]);
+    LSRN_HIP(hipMemcpyAsync(h.data(), nrm.as<double>(), h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    LSRN_HIP(hipStreamSynchronize(st));
+    std::vector<double> t2((size_t)count);
+    for (int p = 0; p < count; ++p) {
+        double mx = 0.0;
+        for (size_t j = off[(size_t)p]; j < off[(size_t)p + 1]; ++j) mx = std::max(mx, h[j]);
+        const double rc = rcond > 0.0 ? rcond : (double)std::max(s[p], d[p]) * DBL_EPSILON;
+        const double tau = rc * mx / (2.0 * std::sqrt((double)d[p]));
+        t2[(size_t)p] = tau * tau;
+    }
+    return t2;
+}
+
 // All sweeps of one problem; returns the sweep count.
 int64_t jacobi_single(double *Y, int64_t d, const JacobiPlan &pl, hipStream_t st, bool profile,
-                      PrecondResult &res) {
+                      PrecondResult &res, double tiny2) {
     const double tol = (double)d * DBL_EPSILON;
     DevBuf cnt(2 * sizeof(int));
     int *dcnt = cnt.as<int>();
     if (pl.small) {
         const size_t bytes = (size_t)d * d * sizeof(double);
         set_small_lds(bytes);
-        jacobi_small_kernel<<<1, 1024, bytes, st>>>(Y, (int)d, kJacobiMaxSweeps, tol, dcnt);
+        jacobi_small_kernel<<<1, 1024, bytes, st>>>(Y, (int)d, kJacobiMaxSweeps, tol, tiny2, dcnt);
         LSRN_HIP(hipGetLastError());
         int sw = 0;
         LSRN_HIP(hipMemcpyAsync(&sw, dcnt, sizeof(int), hipMemcpyDeviceToHost, st));
         LSRN_HIP(hipStreamSynchronize(st));
         return sw;
     }
-    typedef void (*RoundFn)(double *, int, int, int, double, int *, int *, int);
+    typedef void (*RoundFn)(double *, int, int, int, double, double, int *, int *, int);
     static const RoundFn kFn[] = {jacobi_gram_round_kernel<8, 1>, jacobi_gram_round_kernel<8, 2>,
                                   jacobi_gram_round_kernel<8, 4>, jacobi_gram_round_kernel<4, 8>,
                                   jacobi_gram_round_kernel<2, 16>};
@@ -1140,7 +1173,7 @@ int64_t jacobi_single(double *Y, int64_t d, const JacobiPlan &pl, hipStream_t st
         if (profile) LSRN_HIP(hipEventRecord(ev[0], st));
         for (int round = 0; round < period; ++round) {
             hipLaunchKernelGGL(fn, dim3((unsigned)(nblocks / 2)), dim3(512), 0, st, Y, (int)d,
-                               (int)nblocks, round, tol, dcnt, last_mod, sweep * period + round);
+                               (int)nblocks, round, tol, tiny2, dcnt, last_mod, sweep * period + round);
         }
         LSRN_HIP(hipGetLastError());
         if (profile) LSRN_HIP(hipEventRecord(ev[1], st));
@@ -1200,7 +1233,9 @@ PrecondResult precond(int64_t s, int64_t d, double *X, double rcond, double *sig
     double *Y = Yb.as<double>();
     r_to_y_kernel<<<grid1d(d * pl.dcols), 256, 0, st>>>(X, s, d, pl.dcols, Y);
     LSRN_HIP(hipGetLastError());
-    res.sweeps = jacobi_single(Y, d, pl, st, profile, res);
+    const double *Yc = Y;
+    const double tiny2 = tiny_thresholds2(1, &Yc, &s, &d, rcond, st)[0];
+    res.sweeps = jacobi_single(Y, d, pl, st, profile, res, tiny2);
     precond_finish(s, d, Y, rcond, sigma, P, res, st);
     return res;
 }
@@ -1267,6 +1302,8 @@ void precond_batch(int count, const int64_t *s, const int64_t *d, double *const 
         else if (pl[(size_t)p].variant == 0) gram_ids.push_back(p);
         else other_ids.push_back(p);
     }
+    std::vector<const double *> Ycs(Yb.begin(), Yb.end());
+    const std::vector<double> tiny2 = tiny_thresholds2(count, Ycs.data(), s, d, rcond, st);
     // ---- d <= 128: one workgroup per problem, all sweeps, one launch
     if (!small_ids.empty()) {
         const int n = (int)small_ids.size();
@@ -1275,7 +1312,7 @@ void precond_batch(int count, const int64_t *s, const int64_t *d, double *const 
         for (int k = 0; k < n; ++k) {
             const int p = small_ids[(size_t)k];
             it[(size_t)k] = JacobiItem{Yb[(size_t)p], (int)d[p], 0,
-                                       (double)d[p] * DBL_EPSILON, nullptr, nullptr};
+                                       (double)d[p] * DBL_EPSILON, tiny2[(size_t)p], nullptr, nullptr};
             bytes = std::max(bytes, (size_t)d[p] * (size_t)d[p] * sizeof(double));
         }
         DevBuf ditems((size_t)n * sizeof(JacobiItem)), dsw((size_t)n * sizeof(int));
@@ -1309,7 +1346,7 @@ void precond_batch(int count, const int64_t *s, const int64_t *d, double *const 
         for (int k = 0; k < n; ++k) {
             const int p = gram_ids[(size_t)k];
             it[(size_t)k] = JacobiItem{Yb[(size_t)p], (int)d[p], (int)pl[(size_t)p].nblocks,
-                                       (double)d[p] * DBL_EPSILON, drot.as<int>() + k,
+                                       (double)d[p] * DBL_EPSILON, tiny2[(size_t)p], drot.as<int>() + k,
                                        dlast.as<int>() + lastoff[(size_t)k]};
         }
         LSRN_HIP(hipMemcpyAsync(ditems.as<JacobiItem>(), it.data(), (size_t)n * sizeof(JacobiItem),
@@ -1342,7 +1379,7 @@ void precond_batch(int count, const int64_t *s, const int64_t *d, double *const 
     }
     // ---- wider problems: one at a time
     for (int p : other_ids)
-        res[p].sweeps = jacobi_single(Yb[(size_t)p], d[p], pl[(size_t)p], st, false, res[p]);
+        res[p].sweeps = jacobi_single(Yb[(size_t)p], d[p], pl[(size_t)p], st, false, res[p], tiny2[(size_t)p]);
     // sigma, order and P of every problem: the norms and sorts in one pass
     // of launches, one read-back of all sigmas, then the P of each
     std::vector<size_t> so((size_t)count + 1, 0);
