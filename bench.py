@@ -35,6 +35,7 @@ FP64_VECTOR_PEAK_TFS = 78.6  # MI355X FP64 vector: 256 CUs x 64 FMA/clk x 2 x 2.
 # profiles/pmc_traffic_rankdef_200000x2000.md.  An entry is dropped when
 # its kernel changes.
 MEASURED_TRAFFIC = {
+    ("rankdef_200000x2000", "fp64", "f64", "jacobi_round"): 53.4e6,
 }
 
 WORKLOADS = {
