@@ -2,10 +2,12 @@
 //
 // X = G T for the tall view T of A (K x d, row-major): X is s x d, written
 // column-major.  G (s x K) is generated on the fly from the Philox stream
-// (rng.hpp) into LDS, one 128 x 16 tile at a time, and never reaches HBM.
-// The product runs on the FP64 matrix cores (v_mfma_f64_16x16x4f64): each
-// 256-thread workgroup owns a 128 x 128 tile of X and one slice of K; the
-// slices are summed in a fixed order by a second kernel.
+// (rng.hpp) into LDS, one 16-column slice of the tile's rows at a time, and
+// never reaches HBM.  The product runs on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64): each workgroup owns a tile of X (64 x 512,
+// 128 x 256 or 128 x 128) and one slice of K; the slices are summed in a
+// fixed order by a second kernel.
+#include <algorithm>
 #include <vector>
 
 #include "internal.hpp"
@@ -17,16 +19,16 @@ namespace {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 128;   // rows of X (sketch rows i) per workgroup
 constexpr int KT = 16;    // k per LDS stage (four MFMA k-steps)
-constexpr int LDP = 144;  // LDS row pitch in doubles: 144*2 = 288 = 32 (mod 64)
-                          // dwords, so the four 16-lane groups of a wave read
-                          // two disjoint bank halves
-// A workgroup is 2 x WN wavefronts of 64 x 64 each: 128 x 64 WN of X, so
-// each generated slice of G serves 64 WN columns.
-template <int WN> constexpr int BN_ = 64 * WN;          // cols of X per workgroup
-template <int WN> constexpr int NT_ = 128 * WN;         // threads
-template <int WN> constexpr int TP_ = 64 * WN + 16;     // pitch of the T tile (same banks)
+// A workgroup is WM x WN wavefronts of 64 x 64 each: 64 WM x 64 WN of X, so
+// each generated slice of G serves 64 WN columns.  LDS row pitches are
+// 32 (mod 64) dwords, so the four 16-lane groups of a wave read two
+// disjoint bank halves.
+template <int WM> constexpr int BM_ = 64 * WM;                  // rows of X per workgroup
+template <int WN> constexpr int BN_ = 64 * WN;                  // cols of X per workgroup
+template <int WM, int WN> constexpr int NT_ = 64 * WM * WN;     // threads
+template <int WM> constexpr int LDP_ = 64 * WM + 16;            // pitch of the G slice
+template <int WN> constexpr int TP_ = 64 * WN + 16;             // pitch of the T tile
 
 // One MFMA 16x16x4 f64 step: lane l supplies A[l%16][l/16] (a 16x4 slice of
 // G) and B[l/16][l%16] (a 4x16 slice of T); the 16x16 accumulator holds
@@ -35,19 +37,19 @@ __device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// G(i, k) for the 128 rows of the tile and the 16 k of one stage:
-// 128 rows x 4 Philox blocks; thread t takes row t%128 and blocks
-// (t/128) and (t/128)+2 of the stage.
-template <int WN>
-__device__ __forceinline__ void gen_g_stage(double (*Gs)[LDP], uint64_t seed, int64_t m0,
+// G(i, k) for the BM rows of the tile and the 16 k of one stage: BM rows x
+// 4 Philox blocks, block b of the slice (row b % BM, block b / BM of the
+// stage) taken by thread b % NT.  With more threads than blocks (WM = 1,
+// WN = 8) the first four wavefronts generate, one on each SIMD.
+template <int WM, int WN>
+__device__ __forceinline__ void gen_g_stage(double (*Gs)[LDP_<WM>], uint64_t seed, int64_t m0,
                                             int64_t kstage) {
-    constexpr int GROUPS = NT_<WN> / BM;  // threads per row of the slice
-    const int t = threadIdx.x;
-    const int row = t & (BM - 1);
-    const int qb = t >> 7;  // 0 .. GROUPS - 1
+    constexpr int NB = 4 * BM_<WM>, NT = NT_<WM, WN>;
 #pragma unroll
-    for (int h = 0; h < 4 / GROUPS; ++h) {
-        const int qloc = qb + GROUPS * h;  // 0..3
+    for (int h = 0; h < (NB + NT - 1) / NT; ++h) {
+        const int b = (int)threadIdx.x + NT * h;
+        if (NB % NT != 0 && b >= NB) break;
+        const int row = b % BM_<WM>, qloc = b / BM_<WM>;  // qloc 0..3
         double g[4];
         gauss4(seed, (uint64_t)(m0 + row), (uint64_t)((kstage >> 2) + qloc), g);
 #pragma unroll
@@ -56,15 +58,16 @@ __device__ __forceinline__ void gen_g_stage(double (*Gs)[LDP], uint64_t seed, in
 }
 
 // 16 rows x BN columns of T for one stage into registers (zero outside
-// [k0, kend) x [0, d)): four double2 per thread.
-template <int WN, bool VEC2, typename TT>
+// [k0, kend) x [0, d)): 8 / WM double2 per thread.
+template <int WM> constexpr int NLD_ = 8 / WM;
+template <int WM, int WN, bool VEC2, typename TT>
 __device__ __forceinline__ void load_t_stage(const TT *__restrict__ T, int64_t ldt,
                                              int64_t kstage, int64_t kend, int64_t n0, int64_t d,
-                                             double2 (&reg)[4]) {
+                                             double2 (&reg)[NLD_<WM>]) {
     constexpr int HALF = BN_<WN> / 2;  // double2 per row of the tile
 #pragma unroll
-    for (int it = 0; it < 4; ++it) {
-        const int idx = it * NT_<WN> + threadIdx.x;
+    for (int it = 0; it < NLD_<WM>; ++it) {
+        const int idx = it * NT_<WM, WN> + threadIdx.x;
         const int kk = idx / HALF;         // 0..15
         const int c2 = (idx % HALF) * 2;   // 0..BN-2
         const int64_t k = kstage + kk, col = n0 + c2;
@@ -87,12 +90,12 @@ __device__ __forceinline__ void load_t_stage(const TT *__restrict__ T, int64_t l
     }
 }
 
-template <int WN>
-__device__ __forceinline__ void store_t_stage(double (*Ts)[TP_<WN>], const double2 (&reg)[4]) {
+template <int WM, int WN>
+__device__ __forceinline__ void store_t_stage(double (*Ts)[TP_<WN>], const double2 (&reg)[NLD_<WM>]) {
     constexpr int HALF = BN_<WN> / 2;
 #pragma unroll
-    for (int it = 0; it < 4; ++it) {
-        const int idx = it * NT_<WN> + threadIdx.x;
+    for (int it = 0; it < NLD_<WM>; ++it) {
+        const int idx = it * NT_<WM, WN> + threadIdx.x;
         const int kk = idx / HALF, c2 = (idx % HALF) * 2;
         Ts[kk][c2] = reg[it].x;
         Ts[kk][c2 + 1] = reg[it].y;
@@ -100,15 +103,15 @@ __device__ __forceinline__ void store_t_stage(double (*Ts)[TP_<WN>], const doubl
 }
 
 // Tile `tile` of X for K-slice `split` (the workgroup's whole work).
-template <int WN, bool VEC2, typename TT>
+template <int WM, int WN, bool VEC2, typename TT>
 __device__ __forceinline__ void sketch_tile(const TT *__restrict__ T, int64_t ldt, int64_t K,
                                             int64_t d, int64_t s, uint64_t seed,
                                             int64_t k_per_split, int tiles_m,
                                             double *__restrict__ Xp, int tile, int split) {
-    __shared__ double Gs[2][KT][LDP];
+    __shared__ double Gs[2][KT][LDP_<WM>];
     __shared__ double Ts[2][KT][TP_<WN>];
 
-    const int64_t m0 = (int64_t)(tile % tiles_m) * BM;
+    const int64_t m0 = (int64_t)(tile % tiles_m) * BM_<WM>;
     const int64_t n0 = (int64_t)(tile / tiles_m) * BN_<WN>;
     const int64_t kbeg = (int64_t)split * k_per_split;
     const int64_t kend = min(K, kbeg + k_per_split);
@@ -125,11 +128,11 @@ __device__ __forceinline__ void sketch_tile(const TT *__restrict__ T, int64_t ld
         for (int j = 0; j < 4; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
 
     const int64_t nstage = kend > kbeg ? ceil_div(kend - kbeg, KT) : 0;
-    double2 treg[4];
+    double2 treg[NLD_<WM>];
     if (nstage > 0) {
-        gen_g_stage<WN>(Gs[0], seed, m0, kbeg);
-        load_t_stage<WN, VEC2, TT>(T, ldt, kbeg, kend, n0, d, treg);
-        store_t_stage<WN>(Ts[0], treg);
+        gen_g_stage<WM, WN>(Gs[0], seed, m0, kbeg);
+        load_t_stage<WM, WN, VEC2, TT>(T, ldt, kbeg, kend, n0, d, treg);
+        store_t_stage<WM, WN>(Ts[0], treg);
     }
     __syncthreads();
 
@@ -137,7 +140,7 @@ __device__ __forceinline__ void sketch_tile(const TT *__restrict__ T, int64_t ld
         const int buf = (int)(st & 1);
         const bool more = st + 1 < nstage;
         const int64_t knext = kbeg + (st + 1) * KT;
-        if (more) load_t_stage<WN, VEC2, TT>(T, ldt, knext, kend, n0, d, treg);
+        if (more) load_t_stage<WM, WN, VEC2, TT>(T, ldt, knext, kend, n0, d, treg);
 #pragma unroll
         for (int kk = 0; kk < KT / 4; ++kk) {
             double a[4], b[4];
@@ -151,8 +154,8 @@ __device__ __forceinline__ void sketch_tile(const TT *__restrict__ T, int64_t ld
                 for (int j = 0; j < 4; ++j) acc[i][j] = mfma16(a[i], b[j], acc[i][j]);
         }
         if (more) {
-            gen_g_stage<WN>(Gs[buf ^ 1], seed, m0, knext);
-            store_t_stage<WN>(Ts[buf ^ 1], treg);
+            gen_g_stage<WM, WN>(Gs[buf ^ 1], seed, m0, knext);
+            store_t_stage<WM, WN>(Ts[buf ^ 1], treg);
         }
         __syncthreads();
     }
@@ -173,11 +176,11 @@ __device__ __forceinline__ void sketch_tile(const TT *__restrict__ T, int64_t ld
         }
 }
 
-template <int WN, bool VEC2, typename TT = double>
-__global__ void __launch_bounds__(NT_<WN>, 4 / WN)
+template <int WM, int WN, bool VEC2, typename TT = double>
+__global__ void __launch_bounds__((NT_<WM, WN>), 8 / (WM * WN))
 sketch_mfma_kernel(const TT *__restrict__ T, int64_t ldt, int64_t K, int64_t d, int64_t s,
                    uint64_t seed, int64_t k_per_split, int tiles_m, double *__restrict__ Xp) {
-    sketch_tile<WN, VEC2, TT>(T, ldt, K, d, s, seed, k_per_split, tiles_m, Xp, (int)blockIdx.x,
+    sketch_tile<WM, WN, VEC2, TT>(T, ldt, K, d, s, seed, k_per_split, tiles_m, Xp, (int)blockIdx.x,
                               (int)blockIdx.y);
 }
 
@@ -192,7 +195,7 @@ struct SkItem {
 // Every tile of every problem in one launch: workgroup g is tile
 // g - off[p] of problem p (off: prefix sums of the tile counts).
 template <bool VEC2>
-__global__ void __launch_bounds__(NT_<2>, 2)
+__global__ void __launch_bounds__((NT_<2, 2>), 2)
 sketch_batch_kernel(const SkItem *__restrict__ items, const int *__restrict__ off, int n,
                     uint64_t seed) {
     const int g = (int)blockIdx.x;
@@ -203,7 +206,7 @@ sketch_batch_kernel(const SkItem *__restrict__ items, const int *__restrict__ of
         else hi = mid - 1;
     }
     const SkItem it = items[lo];
-    sketch_tile<2, VEC2, double>(it.T, it.ldt, it.K, it.d, it.s, seed, it.K, it.tiles_m, it.X,
+    sketch_tile<2, 2, VEC2, double>(it.T, it.ldt, it.K, it.d, it.s, seed, it.K, it.tiles_m, it.X,
                                  g - off[lo], 0);
 }
 
@@ -252,22 +255,35 @@ transpose_kernel(int64_t rows, int64_t cols, const E *__restrict__ in, int64_t l
 }
 
 struct SketchPlan {
-    int wn, tiles_m, tiles_n, nsplit;
+    int wm, wn, tiles_m, tiles_n, nsplit;
     int64_t k_per_split;
 };
 
-// The wide tile (4 wavefronts across, one workgroup per CU) halves the
-// regeneration of G when it alone gives every CU a tile; else the narrow
-// tile (two workgroups per CU), with split-K when even that is too few.
-SketchPlan plan_sketch(int64_t K, int64_t d, int64_t s) {
+// G is generated once per column tile, so wider tiles regenerate it less.
+// The 64 x 512 tile (8 wavefronts across, one workgroup per CU) is taken
+// when its grid gives all but a sixteenth of the CUs a tile without padding
+// more columns than the 128 x 256 tile (4 across, one per CU), which is
+// taken when it alone gives every CU a tile; else the 128 x 128 tile (two
+// workgroups per CU), with split-K when even that is too few.  The sums
+// over k run in the same order in every tile shape.  FP32 entries keep to
+// the 128-row tiles (measured: the 64 x 512 tile is slower for them).
+SketchPlan plan_sketch(int64_t K, int64_t d, int64_t s, bool f64_entries) {
     SketchPlan p;
     const int64_t cus = device_cus();
-    p.wn = ceil_div(s, BM) * ceil_div(d, 256) >= cus ? 4 : 2;
-    p.tiles_m = (int)ceil_div(s, BM);
+    const int64_t tiles8 = ceil_div(s, BM_<1>) * ceil_div(d, BN_<8>);
+    const bool pad_ok = ceil_div(d, BN_<8>) * BN_<8> <= ceil_div(d, BN_<4>) * BN_<4>;
+    if (f64_entries && pad_ok && tiles8 * 16 >= cus * 15) {
+        p.wm = 1;
+        p.wn = 8;
+    } else {
+        p.wm = 2;
+        p.wn = ceil_div(s, BM_<2>) * ceil_div(d, BN_<4>) >= cus ? 4 : 2;
+    }
+    p.tiles_m = (int)ceil_div(s, 64 * p.wm);
     p.tiles_n = (int)ceil_div(d, 64 * p.wn);
     const int64_t tiles = (int64_t)p.tiles_m * p.tiles_n;
-    const int64_t want = (p.wn == 4 ? 1 : 2) * cus;  // resident workgroups
-    int64_t nsplit = tiles >= want ? 1 : ceil_div(want, tiles);
+    const int64_t want = (p.wm * p.wn == 8 ? 1 : 2) * cus;  // resident workgroups
+    int64_t nsplit = (tiles >= want || p.wm == 1) ? 1 : ceil_div(want, tiles);
     // keep at least 8 stages per slice and the partial sums under 2 GiB
     nsplit = std::min<int64_t>(nsplit, std::max<int64_t>(1, K / (8 * KT)));
     const int64_t cap = std::max<int64_t>(1, (int64_t(1) << 31) / (8 * s * d));
@@ -281,8 +297,12 @@ SketchPlan plan_sketch(int64_t K, int64_t d, int64_t s) {
 }  // namespace
 
 size_t sketch_workspace_bytes(int64_t K, int64_t d, int64_t s) {
-    SketchPlan p = plan_sketch(K, d, s);
-    return p.nsplit > 1 ? (size_t)p.nsplit * (size_t)s * (size_t)d * sizeof(double) : 0;
+    size_t most = 0;
+    for (const bool f64 : {true, false}) {
+        const SketchPlan p = plan_sketch(K, d, s, f64);
+        if (p.nsplit > 1) most = std::max(most, (size_t)p.nsplit * (size_t)s * (size_t)d * sizeof(double));
+    }
+    return most;
 }
 
 namespace {
@@ -290,7 +310,7 @@ namespace {
 template <typename TT>
 void sketch_rows_t(int64_t K, int64_t d, const TT *T, int64_t ldt, double lambda, int64_t s,
                    uint64_t seed, double *X, hipStream_t st, double *kernel_ms) {
-    SketchPlan p = plan_sketch(K, d, s);
+    SketchPlan p = plan_sketch(K, d, s, sizeof(TT) == sizeof(double));
     DevBuf part;
     double *Xp = X;
     if (p.nsplit > 1) {
@@ -305,21 +325,22 @@ void sketch_rows_t(int64_t K, int64_t d, const TT *T, int64_t ldt, double lambda
         LSRN_HIP(hipEventCreate(&ev[1]));
         LSRN_HIP(hipEventRecord(ev[0], st));
     }
-    if (p.wn == 4) {
+    auto launch = [&](auto wm_c, auto wn_c) {
+        constexpr int WM = decltype(wm_c)::value, WN = decltype(wn_c)::value;
         if (vec2)
-            sketch_mfma_kernel<4, true, TT><<<grid, NT_<4>, 0, st>>>(T, ldt, K, d, s, seed, p.k_per_split,
-                                                                    p.tiles_m, Xp);
+            sketch_mfma_kernel<WM, WN, true, TT><<<grid, NT_<WM, WN>, 0, st>>>(
+                T, ldt, K, d, s, seed, p.k_per_split, p.tiles_m, Xp);
         else
-            sketch_mfma_kernel<4, false, TT><<<grid, NT_<4>, 0, st>>>(T, ldt, K, d, s, seed, p.k_per_split,
-                                                                     p.tiles_m, Xp);
-    } else {
-        if (vec2)
-            sketch_mfma_kernel<2, true, TT><<<grid, NT_<2>, 0, st>>>(T, ldt, K, d, s, seed, p.k_per_split,
-                                                                    p.tiles_m, Xp);
-        else
-            sketch_mfma_kernel<2, false, TT><<<grid, NT_<2>, 0, st>>>(T, ldt, K, d, s, seed, p.k_per_split,
-                                                                     p.tiles_m, Xp);
-    }
+            sketch_mfma_kernel<WM, WN, false, TT><<<grid, NT_<WM, WN>, 0, st>>>(
+                T, ldt, K, d, s, seed, p.k_per_split, p.tiles_m, Xp);
+    };
+    if (p.wm == 1) {  // FP64 entries only
+        if constexpr (sizeof(TT) == sizeof(double))
+            launch(std::integral_constant<int, 1>{}, std::integral_constant<int, 8>{});
+    } else if (p.wn == 4)
+        launch(std::integral_constant<int, 2>{}, std::integral_constant<int, 4>{});
+    else
+        launch(std::integral_constant<int, 2>{}, std::integral_constant<int, 2>{});
     LSRN_HIP(hipGetLastError());
     if (kernel_ms) {
         LSRN_HIP(hipEventRecord(ev[1], st));
@@ -364,7 +385,7 @@ void sketch_rows_batch(int count, const int64_t *K, const int64_t *d, const doub
         for (int p = 0; p < count; ++p) {
             const bool vec2 = (ldt[p] % 2 == 0) && ((reinterpret_cast<uintptr_t>(T[p]) & 15) == 0);
             if (vec2 != (pass == 0)) continue;
-            const int tm = (int)ceil_div(s[p], BM), tn = (int)ceil_div(d[p], BN_<2>);
+            const int tm = (int)ceil_div(s[p], BM_<2>), tn = (int)ceil_div(d[p], BN_<2>);
             items.push_back(SkItem{T[p], ldt[p], K[p], d[p], s[p], X[p], tm});
             off.push_back(off.back() + tm * tn);
         }
@@ -376,10 +397,10 @@ void sketch_rows_batch(int count, const int64_t *K, const int64_t *d, const doub
         LSRN_HIP(hipMemcpyAsync(doff.as<int>(), off.data(), off.size() * sizeof(int),
                                 hipMemcpyHostToDevice, st));
         if (pass == 0)
-            sketch_batch_kernel<true><<<(unsigned)off.back(), NT_<2>, 0, st>>>(ditems.as<SkItem>(),
+            sketch_batch_kernel<true><<<(unsigned)off.back(), NT_<2, 2>, 0, st>>>(ditems.as<SkItem>(),
                                                                                doff.as<int>(), n, seed);
         else
-            sketch_batch_kernel<false><<<(unsigned)off.back(), NT_<2>, 0, st>>>(ditems.as<SkItem>(),
+            sketch_batch_kernel<false><<<(unsigned)off.back(), NT_<2, 2>, 0, st>>>(ditems.as<SkItem>(),
                                                                                 doff.as<int>(), n, seed);
         LSRN_HIP(hipGetLastError());
         LSRN_HIP(hipStreamSynchronize(st));  // before the tables are freed
