@@ -132,6 +132,17 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const int block) 
     // the per-row vector of this block (loads past r1 return 0)
     const __amdgpu_buffer_rsrc_t rsy = __builtin_amdgcn_make_buffer_rsrc(
         a.y + (r0 < r1 ? r0 : 0), (short)0, (int)(r0 < r1 ? (r1 - r0) * 8 : 0), 0x00020000);
+    // the fat forms' x (and LSQR's w) of this block's rows, read by thread
+    // rr < R for row j0 + rr (the row it owns in the update) before the
+    // next rows are requested, so that the owner's update waits for none
+    // of the rows in flight
+    constexpr bool FATX = OP == OP_LSQR_FAT || OP == OP_CS_FAT, FATW = OP == OP_LSQR_FAT;
+    auto row_rsrc = [&](double *v, bool used) {
+        const bool ok = used && v != nullptr && r0 < r1;
+        return __builtin_amdgcn_make_buffer_rsrc(ok ? v + r0 : a.y, (short)0,
+                                                 (int)(ok ? (r1 - r0) * 8 : 0), 0x00020000);
+    };
+    const __amdgpu_buffer_rsrc_t rsx = row_rsrc(a.xv, FATX), rsw = row_rsrc(a.wv, FATW);
     auto sweep_rows = [&](auto vec_c) {
     constexpr bool VEC = decltype(vec_c)::value;
     // R rows of T (and of the per-row vector) starting at j0 into registers.
@@ -210,6 +221,11 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const int block) 
     for (int64_t j0 = r0; j0 < r1; j0 += R) {
         E av[R][CPT];
         double yv[R];
+        const int own = (int)(j0 - r0) + (tid < R ? tid : 0);
+        const double xo_own =
+            FATX ? __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rsx, own * 8, 0, 0)) : 0.0;
+        const double wo_own =
+            FATW ? __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rsw, own * 8, 0, 0)) : 0.0;
 #pragma unroll
         for (int rr = 0; rr < R; ++rr) {
             yv[rr] = yvn[rr];
@@ -272,8 +288,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const int block) 
                         a.wv[row] = v;
                         acc3 += v * v;
                     } else if (pending == 2) {
-                        const double xo = a.xv[row] + phi_rho * a.wv[row];
-                        const double wn = v - theta_rho * a.wv[row];
+                        const double xo = xo_own + phi_rho * wo_own;
+                        const double wn = v - theta_rho * wo_own;
                         a.xv[row] = xo;
                         a.wv[row] = wn;
                         acc1 += xo * xo;
@@ -287,7 +303,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const int block) 
                 c = a.beta * yv[rr] + q[rr];
                 if (owner) {
                     a.y[row] = c;
-                    a.xv[row] += a.alpha * c;
+                    a.xv[row] = xo_own + a.alpha * c;
                     acc0 += c * c;
                 }
             }
