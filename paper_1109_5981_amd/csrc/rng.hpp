@@ -28,8 +28,9 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
     constexpr uint32_t kWeylA = 0x9E3779B9u, kWeylB = 0xBB67AE85u;
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
-        const uint32_t lo_a = kMulA * c0, hi_a = __umulhi(kMulA, c0);
-        const uint32_t lo_b = kMulB * c2, hi_b = __umulhi(kMulB, c2);
+        const uint64_t pa = (uint64_t)kMulA * c0, pb = (uint64_t)kMulB * c2;  // 32 x 32 -> 64
+        const uint32_t lo_a = (uint32_t)pa, hi_a = (uint32_t)(pa >> 32);
+        const uint32_t lo_b = (uint32_t)pb, hi_b = (uint32_t)(pb >> 32);
         const uint32_t n0 = hi_b ^ c1 ^ k0;
         const uint32_t n2 = hi_a ^ c3 ^ k1;
         c0 = n0;
