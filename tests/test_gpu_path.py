@@ -87,19 +87,21 @@ def test_sketch_matches_oracle(L, orc, m, n, layout, lam, s):
     assert np.all(np.abs(Xg - Xo) <= bound)
 
 
-@pytest.mark.parametrize("K,d,s", [
-    (3000, 2048, 4096),    # 64 x 512 tiles (1 x 8 wavefronts), 256 of them
-    (3000, 1990, 3990),    # 64 x 512 tiles, ragged in both dimensions
-    (3000, 768, 11008),    # 128 x 256 tiles (2 x 4): 512-column tiles would pad
+@pytest.mark.parametrize("K,d,s,pad", [
+    (3000, 2048, 4096, 0),    # 64 x 512 tiles (1 x 8 wavefronts), 256 of them
+    (3000, 1990, 3990, 0),    # 64 x 512 tiles, ragged in both dimensions
+    (3000, 2048, 4096, 1),    # 64 x 512 tiles, odd leading dimension (single loads)
+    (3000, 768, 11008, 0),    # 128 x 256 tiles (2 x 4): 512-column tiles would pad
 ])
-def test_sketch_wide_tiles_sampled(L, orc, K, d, s):
+def test_sketch_wide_tiles_sampled(L, orc, K, d, s, pad):
     """Sizes whose tile grid fills the chip take the wide tiles; entries
     recomputed one by one by the oracle's G and exact sums."""
     import math
     seed = 77
     rng = np.random.default_rng(5)
-    T = rng.standard_normal((K, d))
-    X = host(L.sketch_dense(dev(T), s, seed=seed)).T        # s x d
+    Tbuf = rng.standard_normal((K, d + pad))
+    T = Tbuf[:, :d]
+    X = host(L.sketch_dense(dev(Tbuf)[:, :d], s, seed=seed)).T        # s x d
     eps = np.finfo(float).eps
     picks = [(0, 0), (s - 1, d - 1), (63, 511), (64, 512), (127, 255), (128, 256),
              (s - 1, 0), (0, d - 1), (s // 2, d // 2)]
