@@ -153,12 +153,18 @@ void orc_matvec_t(const orc_matrix *A, const double *y, double *x)
                 x[A->colind[p]] += A->val[p] * y[i];
         return;
     }
+    /* Columns in groups of 8 per thread, so that the rows of a row-major A
+     * are read along their length; each x[j] is still the sum over i in
+     * ascending order. */
 #pragma omp parallel for schedule(static)
-    for (int64_t j = 0; j < A->n; ++j) {
-        double acc = 0.0;
+    for (int64_t j0 = 0; j0 < A->n; j0 += 8) {
+        const int64_t j1 = j0 + 8 < A->n ? j0 + 8 : A->n;
+        double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         for (int64_t i = 0; i < A->m; ++i)
-            acc += a_at(A, i, j) * y[i];
-        x[j] = acc;
+            for (int64_t j = j0; j < j1; ++j)
+                acc[j - j0] += a_at(A, i, j) * y[i];
+        for (int64_t j = j0; j < j1; ++j)
+            x[j] = acc[j - j0];
     }
 }
 
@@ -579,6 +585,7 @@ typedef struct {
 
 static void p_times(const precond_ctx *c, const double *y, double *out) /* out = P y */
 {
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < c->d; ++i) {
         double acc = 0.0;
         for (int64_t k = 0; k < c->r; ++k)
@@ -589,13 +596,20 @@ static void p_times(const precond_ctx *c, const double *y, double *out) /* out =
 
 static void pt_times(const precond_ctx *c, const double *h, double *out) /* out = P^T h */
 {
-    for (int64_t k = 0; k < c->r; ++k) {
-        double acc = 0.0;
+    /* groups of 8 outputs per thread (P is read along its rows); each
+     * out[k] is the sum over i in ascending order */
+#pragma omp parallel for schedule(static)
+    for (int64_t k0 = 0; k0 < c->r; k0 += 8) {
+        const int64_t k1 = k0 + 8 < c->r ? k0 + 8 : c->r;
+        double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         for (int64_t i = 0; i < c->d; ++i)
-            acc += c->P[i * c->ldp + k] * h[i];
-        out[k] = acc;
+            for (int64_t k = k0; k < k1; ++k)
+                acc[k - k0] += c->P[i * c->ldp + k] * h[i];
+        for (int64_t k = k0; k < k1; ++k)
+            out[k] = acc[k - k0];
     }
 }
+
 
 static void tall_mv(void *vctx, const double *y, double *out)
 {
@@ -738,6 +752,7 @@ int orc_lsrn_iterate(const orc_matrix *A, const double *b, const double *P, int6
     for (int32_t step = 0; step < opt->refine; ++step) {
         double xn = nrm2(n, x), dxn = 0.0;
         long double *res = (long double *)malloc(sizeof(long double) * (size_t)m);
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < m; ++i) {            /* res = b - A x in long double */
             long double acc = (long double)b[i];
             if (A->kind == ORC_CSR) {
@@ -760,11 +775,18 @@ int orc_lsrn_iterate(const orc_matrix *A, const double *b, const double *P, int6
                     for (int64_t p = A->rowptr[i]; p < A->rowptr[i + 1]; ++p)
                         h[A->colind[p]] += (long double)A->val[p] * res[i];
             } else {
-                for (int64_t j = 0; j < n; ++j)
+                /* groups of 8 columns per thread; each h[j] still sums over
+                 * i in ascending order */
+#pragma omp parallel for schedule(static)
+                for (int64_t j0 = 0; j0 < n; j0 += 8) {
+                    const int64_t j1 = j0 + 8 < n ? j0 + 8 : n;
                     for (int64_t i = 0; i < m; ++i)
-                        h[j] += (long double)a_at(A, i, j) * res[i];
+                        for (int64_t j = j0; j < j1; ++j)
+                            h[j] += (long double)a_at(A, i, j) * res[i];
+                }
             }
             double *c = (double *)malloc(sizeof(double) * (size_t)r);
+#pragma omp parallel for schedule(static)
             for (int64_t k = 0; k < r; ++k) {
                 long double acc = 0.0L;
                 for (int64_t i = 0; i < d; ++i)
@@ -783,6 +805,7 @@ int orc_lsrn_iterate(const orc_matrix *A, const double *b, const double *P, int6
             /* e = M^T (b - A x) in long double; solve M^T A dx = e with the
              * same method as the main solve. */
             double *e = (double *)malloc(sizeof(double) * (size_t)r);
+#pragma omp parallel for schedule(static)
             for (int64_t k = 0; k < r; ++k) {
                 long double acc = 0.0L;
                 for (int64_t i = 0; i < m; ++i)
