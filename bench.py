@@ -5,10 +5,13 @@
 One step is one complete LSRN solve (Alg. 1 or 2): Philox G + FP64 MFMA
 sketch, QR + Jacobi SVD, rank cutoff and N, LSQR (or Chebyshev) with fused
 one-pass sweeps, x = N y, and double-double refinement to reach relative
-error 1e-10.  The default workload is the rank-deficient over-determined
-problem m = 200000, n = 2000, rank 1800, sigma log-spaced 1 .. 1e-6,
-b ~ N(0, 1), gamma = 2, tolerance 1e-14 (synthetic, seeded; built on the
-GPU before timing).  Prints one JSON line.
+error 1e-10.  The default workload is the largest single-GPU problem:
+dense m = 1000000, n = 4000 (32 GB of FP64 A), sigma log-spaced 1 .. 1e-8,
+b = A x + 1e-6 N(0,1), gamma = 2, tolerance 1e-14 (synthetic, seeded; built
+on the GPU before timing).  The precision form (BF16x3 sketch, FP32
+sweeps, FP64 refinement) is timed beside it on the same A and b.  Other
+workloads: --workload rankdef_200000x2000 (rank 1800) and its transpose,
+sparse_2000000x20000, --batch N, --serve.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -44,7 +47,7 @@ WORKLOADS = {
     "dense_2000x100": dict(m=2000, n=100, rank=100, smin=1e-6, seed=11, fat=False, noise=1e-3),
     # the precision-form workload: full rank, sigma 1 .. 1e-8, b = A x + 1e-6 noise
     "dense_1000000x4000": dict(m=1_000_000, n=4000, rank=4000, smin=1e-8, seed=14, fat=False,
-                               noise=1e-6),
+                               noise=1e-6, refine=2),
     # the same shape at kappa = 1e6, where kappa u32 < 1 lets the precision form
     # reach the FP64 solution
     "dense_1000000x4000_k1e6": dict(m=1_000_000, n=4000, rank=4000, smin=1e-6, seed=14, fat=False,
@@ -61,22 +64,32 @@ def percentile(xs, q):
     return xs[f] if f == c else xs[f] + (xs[c] - xs[f]) * (k - f)
 
 
-def cpu_baseline(A_np, b_np, s, d, r, iters_per_solve, sweeps, tall, budget_s=20.0):
+def cpu_baseline(T_dev, b_dev, s, d, r, iters_per_solve, sweeps, tall, sample_bytes=1 << 30):
     """The oracle as it stands, timed on a bounded sample of the same solve and
-    scaled to solves/s: sketch rows, a QR and one Jacobi sweep of reduced
-    order scaled by their flop counts, and two iterations on the full A."""
+    scaled to solves/s.  T_dev is the tall view (K x d, row-major: A, or the
+    array of A^T for an under-determined A).  The sample is the first K' rows
+    of T (about 1 GiB); sketch and iteration times grow linearly in K and are
+    scaled by K / K'; the QR and one Jacobi sweep of reduced order are scaled
+    by their flop counts (d^3 and the solve's sweep count for the Jacobi)."""
     import numpy as np
 
     import oracle
 
     t_start = time.perf_counter()
     threads = oracle.num_threads()
-    M = oracle.Matrix.dense(A_np) if tall else oracle.Matrix.dense_colmajor(A_np)
-    # 1) sketch: the first `rows` rows of G times A (each row costs the same)
-    rows = max(2, 24 * threads)
+    K = T_dev.shape[0]
+    Ks = int(min(K, max(d, sample_bytes // (8 * d))))
+    T = T_dev[:Ks].cpu().numpy()
+    if tall:
+        M, b_np = oracle.Matrix.dense(T), b_dev[:Ks].cpu().numpy()
+    else:
+        M, b_np = oracle.Matrix.dense_colmajor(T), b_dev.cpu().numpy()
+    scale_k = K / Ks
+    # 1) sketch: the first `rows` rows of G times the sample (each row costs the same)
+    rows = max(2, threads)
     t0 = time.perf_counter()
     oracle.sketch(M, rows, 0)
-    t_sketch = (time.perf_counter() - t0) * s / rows
+    t_sketch = (time.perf_counter() - t0) * s / rows * scale_k
     # 2) QR of an (s' x d') Gaussian with the same aspect, scaled by flops
     rng = np.random.default_rng(0)
     dq = min(d, 1000)
@@ -91,25 +104,25 @@ def cpu_baseline(A_np, b_np, s, d, r, iters_per_solve, sweeps, tall, budget_s=20
     t0 = time.perf_counter()
     oracle.jacobi_rt(Rq, max_sweeps=1)
     t_jac = (time.perf_counter() - t0) * (d / dq) ** 3 * max(1, sweeps)
-    # 4) two LSQR iterations on the full problem with a preconditioner of the
+    # 4) two LSQR iterations on the sample with a preconditioner of the
     #    right shape (the iteration's cost does not depend on its values)
     P = rng.standard_normal((d, r)) / math.sqrt(d)
-    b_use = b_np
     t0 = time.perf_counter()
-    oracle.lsrn_iterate(M, b_use, P, s, max_iter=2, tol=1e-300)
+    oracle.lsrn_iterate(M, b_np, P, s, max_iter=2, tol=1e-300)
     # the sample makes 5 products with A or A^T (start: A^T b; each iteration:
     # A v and A^T u); an iteration costs 2
-    t_it = (time.perf_counter() - t0) * 2.0 / 5.0 * iters_per_solve
+    t_it = (time.perf_counter() - t0) * 2.0 / 5.0 * iters_per_solve * scale_k
     total = t_sketch + t_qr + t_jac + t_it
     return {
         "value": 1.0 / total,
         "unit": "solves/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": (f"oracle stages timed on samples and scaled: sketch of {rows} of {s} rows "
+        "sample": (f"oracle stages timed on samples and scaled: the first {Ks} of {K} rows of "
+                   f"the tall view (x{scale_k:.1f}); sketch of {rows} of {s} rows of G on them "
                    f"(x{s / rows:.0f}); Householder QR of a {sq}x{dq} Gaussian (x flops); one "
                    f"Jacobi sweep of order {dq} (x (d/{dq})^3 x {sweeps} sweeps); LSQR start + 2 "
-                   f"iterations on the full A (x 2/5 x {iters_per_solve})"),
+                   f"iterations on the sample (x 2/5 x {iters_per_solve})"),
         "stage_s": {"sketch": t_sketch, "qr": t_qr, "jacobi": t_jac, "iterations": t_it},
         "sample_wall_s": time.perf_counter() - t_start,
     }
@@ -256,26 +269,41 @@ def serve_main(args):
 
 
 def sparse_main(args):
-    """The sparse workload: CSR A (2e6 x 2e4, 20 uniform nonzeros per row plus
-    10 dense columns at 10% fill, N(0,1) values), Tikhonov lambda = 1e-3,
-    LSQR to 1e-12 with one refinement step."""
+    """The sparse workloads.  sparse_2000000x20000: CSR A (2e6 x 2e4, 20
+    uniform nonzeros per row plus 10 dense columns at 10% fill, N(0,1)
+    values), Tikhonov lambda = 1e-3, LSQR to 1e-12 with one refinement step.
+    tnimg_1024x4000000: the under-determined 1024 x 4e6 stand-in for the
+    paper's tnimg_4 (about 21 nonzeros per column, DCT-like skew of the rows;
+    workloads.tnimg_like), LSQR or Chebyshev (--method) to 1e-14 (Alg. 2)."""
     import numpy as np
     import torch
 
     import workloads
     from paper_1109_5981_amd import lsrn
 
-    wl = workloads.WORKLOADS["sparse_2000000x20000"]
     dev = torch.device("cuda:0")
     g0 = time.perf_counter()
-    S = workloads.sparse_problem(wl["m"], wl["n"], wl["per_row"], wl["n_dense"], wl["fill"],
-                                 seed=wl["seed"])
+    if args.workload == "tnimg_1024x4000000":
+        wl = dict(seed=16, lam=0.0)
+        S = workloads.tnimg_like(4_000_000, seed=wl["seed"])
+        tol, refine = 1e-14, 0
+        data = ("synthetic tnimg stand-in (seeded; 1024 DCT-frequency rows, 20 or 21 nonzeros "
+                "per column: the DC row always, the others drawn with weight (1+u+v)^-1.5, values "
+                "N(0,1) 8/(1+u+v); b ~ N(0,1))")
+    else:
+        wl = workloads.WORKLOADS["sparse_2000000x20000"]
+        S = workloads.sparse_problem(wl["m"], wl["n"], wl["per_row"], wl["n_dense"], wl["fill"],
+                                     seed=wl["seed"])
+        tol, refine = 1e-12, 1
+        data = ("synthetic (seeded CSR: 20 uniform columns per row + 10 dense columns at 10% "
+                "fill, N(0,1) values; b ~ N(0,1))")
     A = lsrn.Csr.from_host(S.m, S.n, S.rowptr, S.colind, S.val, device=dev)
     b = workloads.rhs_gauss_device(S.m, wl["seed"], device=dev)
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - g0
     lam = wl["lam"]
-    opts = dict(lam=lam, tol=1e-12, seed=5, refine=1, profile=0 if args.no_profile else 1)
+    opts = dict(lam=lam, tol=tol, seed=5, refine=refine, method=args.method,
+                profile=0 if args.no_profile else 1)
     for _ in range(args.warmup):
         x, info = lsrn.solve_csr(A, b, **opts)
     torch.cuda.synchronize()
@@ -289,12 +317,17 @@ def sparse_main(args):
         infos.append(info)
     elapsed = time.perf_counter() - t0
     # relative normal-equation residual of the augmented problem [A; lam I]
+    # (tall), relative residual of the consistent system (fat)
     Ad = torch.sparse_csr_tensor(A.rowptr, A.colind.long(), A.val, size=(S.m, S.n))
     r = b - Ad @ x
-    h = Ad.t().to_sparse_csr() @ r - lam * lam * x
-    ne = (torch.linalg.norm(h) / (torch.linalg.norm(A.val) * torch.linalg.norm(r))).item()
+    if S.m >= S.n:
+        h = Ad.t().to_sparse_csr() @ r - lam * lam * x
+        ne = (torch.linalg.norm(h) / (torch.linalg.norm(A.val) * torch.linalg.norm(r))).item()
+    else:
+        ne = (torch.linalg.norm(r) / torch.linalg.norm(b)).item()
     info = infos[-1]
     s, d, nnz = info["s"], info["d"], S.nnz
+    K = max(S.m, S.n)
     mean = lambda key: sum(i[key] for i in infos) / len(infos)
     kernels = {}
     t_sk = mean("t_sketch_kernel_ms")
@@ -308,7 +341,7 @@ def sparse_main(args):
     if t_sw > 0 and n_sw > 0:
         avg = t_sw / n_sw
         # one read of the CSR arrays and the long vector (the algorithmic minimum)
-        b_iter = 12.0 * nnz + 8.0 * (S.m + 1) + 16.0 * (S.m + S.n)
+        b_iter = 12.0 * nnz + 8.0 * (K + 1) + 16.0 * (S.m + S.n)
         kernels["csr_sweep"] = {
             "avg_ms": avg, "launches_per_step": n_sw, "bound": "hbm",
             "achieved": b_iter / (avg * 1e-3) / 1e9, "unit": "GB/s", "peak": HBM_PEAK_GBS}
@@ -320,7 +353,8 @@ def sparse_main(args):
                     "peak": kk["peak"], "unit": kk["unit"],
                     "frac": round(kk["achieved"] / kk["peak"], 5), "traffic": None}
     line = {
-        "metric": "LS solves/s (sparse, Tikhonov) at rel normal-equation residual 1e-12",
+        "metric": ("LS solves/s (sparse, Tikhonov) at rel normal-equation residual 1e-12"
+                   if S.m >= S.n else "LS solves/s (sparse, under-determined, min-length)"),
         "value": round(args.steps / elapsed, 4),
         "unit": "solves/s",
         "n_gpus": 1,
@@ -331,15 +365,16 @@ def sparse_main(args):
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
-        "data": "synthetic (seeded CSR: 20 uniform columns per row + 10 dense columns at 10% fill, "
-                "N(0,1) values; b ~ N(0,1))",
-        "config": {"workload": "sparse_2000000x20000", "m": S.m, "n": S.n, "nnz": nnz,
-                   "lambda": lam, "gamma": 2.0, "tol": 1e-12, "refine": 1},
+        "data": data,
+        "config": {"workload": args.workload, "m": S.m, "n": S.n, "nnz": nnz,
+                   "lambda": lam, "gamma": 2.0, "tol": tol, "refine": refine, "method": args.method},
         "latency_ms": {"p50": round(percentile(lat, 50), 3), "p99": round(percentile(lat, 99), 3)},
         "stages_ms": {k: round(info[k], 3) for k in ("t_sketch_ms", "t_svd_ms", "t_iter_ms",
                                                      "t_refine_ms", "t_total_ms")},
         "iters": info["iters"], "refine_iters": info["refine_iters"], "rank": info["rank"],
-        "s": s, "converged": bool(info["converged"]), "rel_normal_residual": ne,
+        "s": s, "converged": bool(info["converged"]),
+        ("rel_normal_residual" if S.m >= S.n else "rel_residual"): ne,
+        "cs_fallbacks": info.get("cs_fallbacks", 0),
         "kernels": kernels, "roofline": roofline, "cpu_baseline": None,
         "setup_s": round(t_gen, 2),
     }
@@ -401,12 +436,16 @@ def batch_main(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rankdef_200000x2000",
-                    choices=sorted(WORKLOADS) + ["sparse_2000000x20000"])
+    ap.add_argument("--precision-steps", type=int, default=3,
+                    help="timed solves of the precision form beside the FP64 path (0: none)")
+    ap.add_argument("--workload", default="dense_1000000x4000",
+                    choices=sorted(WORKLOADS) + ["sparse_2000000x20000", "tnimg_1024x4000000"])
     ap.add_argument("--method", default="lsqr", choices=["lsqr", "chebyshev"])
-    ap.add_argument("--refine", type=int, default=1)
+    ap.add_argument("--refine", type=int, default=None,
+                    help="refinement steps (default: 2 for the kappa 1e8 workload, where one "
+                         "step leaves about 1e-10, else 1)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--precond", default="auto", choices=["auto", "svd", "qr"])
     ap.add_argument("--storage", default="f64", choices=["f64", "f32"],
@@ -453,7 +492,7 @@ def main():
     if args.batch > 0:
         batch_main(args)
         return
-    if args.workload == "sparse_2000000x20000":
+    if args.workload in ("sparse_2000000x20000", "tnimg_1024x4000000"):
         sparse_main(args)
         return
     dev = torch.device("cuda:0")
@@ -466,24 +505,22 @@ def main():
         print(json.dumps({"copy_bytes": src.numel() * 8, "launches": 3}))
         return
     wl = WORKLOADS[args.workload]
+    if args.refine is None:
+        args.refine = wl.get("refine", 1)
     t_gen = time.perf_counter()
     A, U, sigma, V = workloads.dense_problem_device(wl["m"], wl["n"], wl["rank"], wl["smin"],
                                                     wl["seed"], device=dev)
+    del U, V
     if wl["fat"]:
         # under-determined n x m problem stored column-major: the array of the
         # tall generator read as A^T
         m_ls, n_ls, layout = wl["n"], wl["m"], lsrn.COL_MAJOR
-        Ufat, Vfat = V, U
     else:
         m_ls, n_ls, layout = wl["m"], wl["n"], lsrn.ROW_MAJOR
-        Ufat, Vfat = U, V
     if "noise" in wl:
         b, _ = workloads.rhs_model_device(A, wl["noise"], wl["seed"])
     else:
         b = workloads.rhs_gauss_device(m_ls, wl["seed"], device=dev)
-    # min-length solution of the generating (unrounded) matrix U diag(sigma) V^T
-    x_gen = Vfat @ (workloads.matvec_device(Ufat, b, trans=True) / sigma)
-    del U, V, Ufat, Vfat
     torch.cuda.empty_cache()  # the library allocates with hipMalloc, outside torch's cache
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t_gen
@@ -494,86 +531,83 @@ def main():
                 profile=0 if args.no_profile else 1, precision=args.precision,
                 precond=args.precond, autotune=0 if args.no_autotune else 1)
     solve = lsrn.solve_dense
+    A_solve = A
     if args.storage == "f32":
-        # the problem becomes the FP32-rounded matrix; the generator's solution
-        # then differs by about kappa 2^-24
-        A = A.float()
+        # the problem becomes the FP32-rounded matrix
+        A_solve = A.float()
+        del A
+        A = None
         torch.cuda.empty_cache()
         solve = lsrn.solve_dense_f32
-    for _ in range(args.warmup):
-        x, info = solve(A, b, layout=layout, allow_not_converged=True, **opts)
-    torch.cuda.synchronize()
 
-    lat, infos = [], []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ts = time.perf_counter()
-        x, info = solve(A, b, layout=layout, allow_not_converged=True, **opts)
+    def leg(solve_fn, steps, warmup, **o):
+        """warmup untimed solves, then `steps` timed ones between device syncs."""
+        for _ in range(warmup):
+            x, info = solve_fn(A_solve, b, layout=layout, allow_not_converged=True, **o)
         torch.cuda.synchronize()
-        lat.append((time.perf_counter() - ts) * 1e3)
-        infos.append(info)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
+        lat, infos = [], []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ts = time.perf_counter()
+            x, info = solve_fn(A_solve, b, layout=layout, allow_not_converged=True, **o)
+            torch.cuda.synchronize()
+            lat.append((time.perf_counter() - ts) * 1e3)
+            infos.append(info)
+        torch.cuda.synchronize()
+        return x, infos, lat, time.perf_counter() - t0
 
-    # accuracy of the last solve
-    err_gen = (torch.linalg.norm(x - x_gen) / torch.linalg.norm(x_gen)).item()
-    err_fp64 = None
-    if args.precision != "fp64":
-        # the plain FP64 path on the same problem (untimed), refined to convergence
-        ref_opts = dict(opts, precision="fp64", refine=max(args.refine, 6), profile=0)
-        x64, _ = lsrn.solve_dense(A, b, layout=layout, **ref_opts)
-        err_fp64 = (torch.linalg.norm(x - x64) / torch.linalg.norm(x64)).item()
-        del x64
+    x, infos, lat, elapsed = leg(solve, args.steps, args.warmup, **opts)
+
+    # accuracy: the same problem solved by the FP64 path with refinement run
+    # to convergence (untimed); the oracle parity of these sizes is checked by
+    # the GPU test suite
+    ref_opts = dict(opts, precision="fp64", refine=6, profile=0, seed=7)
+    x_ref, _ = solve(A_solve, b, layout=layout, **ref_opts)
+    rel_err = lambda xv: (torch.linalg.norm(xv - x_ref) / torch.linalg.norm(x_ref)).item()
+    err_main = rel_err(x)
+    Av = A_solve
     if layout == lsrn.ROW_MAJOR:
-        res = b - workloads.matvec_device(A, x)
-        ne = torch.linalg.norm(workloads.matvec_device(A, res, trans=True)) / (
+        res = b - workloads.matvec_device(Av, x)
+        ne = torch.linalg.norm(workloads.matvec_device(Av, res, trans=True)) / (
             sigma[0] * torch.linalg.norm(res))
     else:
-        res = b - workloads.matvec_device(A, x, trans=True)
-        ne = torch.linalg.norm(workloads.matvec_device(A, res)) / (sigma[0] * torch.linalg.norm(res))
+        res = b - workloads.matvec_device(Av, x, trans=True)
+        ne = torch.linalg.norm(workloads.matvec_device(Av, res)) / (sigma[0] * torch.linalg.norm(res))
     ne = ne.item()
+    del res
 
     info = infos[-1]
     s, d, r = info["s"], info["d"], info["rank"]
     K = wl["m"]                              # rows of the tall view
-    sketch_flop = 2.0 * s * K * d
-    sweeps_per_solve = info["sweep_kernels"] if info["sweep_kernels"] else None
-    # one read of A (FP32 copy in the precision form) + long vector read/write
-    bytes_per_sweep = (8.0 if (args.precision == "fp64" and args.storage == "f64") else 4.0) * K * d + 16.0 * K
-    mean = lambda key: sum(i[key] for i in infos) / len(infos)
-    t_sketch_k = mean("t_sketch_kernel_ms")
-    t_sweep_k = mean("t_sweep_kernel_ms")
-    n_sweep = mean("sweep_kernels")
-    t_jac_k = mean("t_jacobi_kernel_ms")
-    n_jac = mean("jacobi_kernels")
-    # one Jacobi round reads and writes every column of the d x d matrix once
-    bytes_per_round = 16.0 * d * d
+    mean = lambda key, inf=None: sum(i[key] for i in (inf or infos)) / len(inf or infos)
+    kernels, stages = kernel_figures(args, infos, s, K, d, mean)
 
-    kernels = {}
-    if t_sketch_k > 0 and args.precision == "fp64":
-        kernels["sketch_mfma_f64"] = {
-            "avg_ms": t_sketch_k, "launches_per_step": 1, "bound": "mfma",
-            "achieved": sketch_flop / (t_sketch_k * 1e-3) / 1e12, "unit": "TFLOP/s",
-            "peak": FP64_MFMA_PEAK_TFS}
-    elif t_sketch_k > 0:
-        # three BF16 products (the exact split of fl32(A)) per element of G A
-        kernels["sketch_mfma_bf16x3"] = {
-            "avg_ms": t_sketch_k, "launches_per_step": 1, "bound": "mfma",
-            "achieved": 3 * sketch_flop / (t_sketch_k * 1e-3) / 1e12, "unit": "TFLOP/s",
-            "peak": BF16_MFMA_PEAK_TFS}
-    if t_sweep_k > 0 and n_sweep > 0:
-        avg = t_sweep_k / n_sweep
-        kernels["row_sweep"] = {
-            "avg_ms": avg, "launches_per_step": n_sweep, "bound": "hbm",
-            "achieved": bytes_per_sweep / (avg * 1e-3) / 1e9, "unit": "GB/s",
-            "peak": HBM_PEAK_GBS}
-    if t_jac_k > 0 and n_jac > 0:
-        avg = t_jac_k / n_jac
-        kernels["jacobi_round"] = {
-            "avg_ms": avg, "launches_per_step": n_jac, "bound": "hbm",
-            "achieved": bytes_per_round / (avg * 1e-3) / 1e9, "unit": "GB/s",
-            "peak": HBM_PEAK_GBS}
+    # the precision form beside the FP64 path, on the same A and b
+    prec_form = None
+    if (args.precision == "fp64" and args.storage == "f64" and not wl["fat"]
+            and args.precision_steps > 0):
+        o_mixed = dict(opts, precision="mixed", refine=max(args.refine, 10))
+        xm, infos_m, lat_m, el_m = leg(solve, args.precision_steps, 1, **o_mixed)
+        im = infos_m[-1]
+        km, _ = kernel_figures(argparse.Namespace(**dict(vars(args), precision="mixed")),
+                               infos_m, s, K, d, lambda key: mean(key, infos_m))
+        prec_form = {
+            "solves_per_s": round(args.precision_steps / el_m, 4),
+            "latency_ms": {"p50": round(percentile(lat_m, 50), 3),
+                           "p99": round(percentile(lat_m, 99), 3)},
+            "rel_err_vs_fp64_refined": rel_err(xm),
+            "converged": bool(im["converged"]),
+            "refine_steps": im["refine_steps"], "fp64_refine_steps": im["fp64_refine_steps"],
+            "stages_ms": {k: round(mean(k, infos_m), 3) for k in
+                          ("t_sketch_ms", "t_svd_ms", "t_iter_ms", "t_refine_ms", "t_total_ms")},
+            "kernels": km,
+            "note": ("BF16x3 sketch on the BF16 matrix cores, LSQR over an FP32 copy of A, "
+                     "refinement residuals in double-double from the FP64 A; when kappa(A) 2^-24 "
+                     "is near 1 the FP32 corrections stall and the refinement continues with "
+                     "FP64 sweeps (fp64_refine_steps)"),
+        }
+        del xm
+
     roofline = None
     if kernels:
         dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches_per_step"])
@@ -584,11 +618,9 @@ def main():
                     "traffic": MEASURED_TRAFFIC.get((args.workload, args.precision, args.storage, dom))}
 
     cpu = None
-    if not args.no_cpu_baseline and args.workload == "rankdef_200000x2000":
-        A_np = A.cpu().numpy()
-        b_np = b.cpu().numpy()
+    if not args.no_cpu_baseline and args.storage == "f64":
         iters_total = info["iters"] + info["refine_iters"] + 2 * info["refine_steps"]
-        cpu = cpu_baseline(A_np, b_np, s, d, r, iters_total, info["sweeps"], not wl["fat"])
+        cpu = cpu_baseline(A_solve, b, s, d, r, iters_total, info["sweeps"], not wl["fat"])
 
     value = args.steps / elapsed
     line = {
@@ -604,31 +636,96 @@ def main():
         "vs_baseline": None,
         "dtype": ("f64" if args.storage == "f64" else "f64 arithmetic on f32-stored A")
                  if args.precision == "fp64" else "bf16 sketch + f32 sweeps + f64",
-        "data": "synthetic (seeded; U, V Haar, sigma log-spaced, b ~ N(0,1))",
+        "data": ("synthetic (seeded; A = U diag(sigma) V^T with U, V Haar, sigma log-spaced "
+                 "1 .. %g%s; %s)" % (wl["smin"],
+                                    ", rank %d" % wl["rank"] if wl["rank"] < min(wl["m"], wl["n"]) else "",
+                                    "b = A x + %g N(0,1)" % wl["noise"] if "noise" in wl
+                                    else "b ~ N(0,1)")),
         "config": {"workload": args.workload, "m": m_ls, "n": n_ls, "rank": wl["rank"],
                    "gamma": 2.0, "tol": 1e-14, "method": args.method, "refine": args.refine,
                    "precision": args.precision, "precond": args.precond, "storage": args.storage,
                    "autotune": not args.no_autotune},
         "tuned_shapes": lsrn.tune_export().strip().splitlines(),
         "latency_ms": {"p50": round(percentile(lat, 50), 3), "p99": round(percentile(lat, 99), 3)},
-        "sketch_tflops": round(sketch_flop / (mean("t_sketch_ms") * 1e-3) / 1e12, 3),
-        "iter_gbs": (round(bytes_per_sweep * n_sweep / (mean("t_iter_ms") + mean("t_refine_ms"))
-                           / 1e6, 1) if n_sweep else None),
+        "rel_err_vs_fp64_refined": err_main,
+        "rel_normal_residual": ne,
+        "sketch_tflops": round(2.0 * s * K * d / (mean("t_sketch_ms") * 1e-3) / 1e12, 3),
+        "iter_gbs": stages.get("iter_phase", {}).get("achieved"),
+        "iter_phase": stages.get("iter_phase"),
+        "svd_stage": stages.get("svd_stage"),
         "stages_ms": {k: round(mean(k), 3) for k in
                       ("t_sketch_ms", "t_svd_ms", "t_iter_ms", "t_refine_ms", "t_total_ms")},
         "iters": info["iters"], "refine_iters": info["refine_iters"], "rank": r, "s": s,
         "jacobi_sweeps": info["sweeps"],
-        "rel_err_vs_generator": err_gen,
-        "rel_err_vs_fp64_path": err_fp64,
         "refine_steps": info["refine_steps"],
         "converged": bool(info["converged"]),
-        "rel_normal_residual": ne,
         "kernels": kernels,
         "roofline": roofline,
+        "precision_form": prec_form,
         "cpu_baseline": cpu,
         "setup_s": round(t_gen, 2),
     }
     print(json.dumps(line))
+
+
+def kernel_figures(args, infos, s, K, d, mean):
+    """Per-kernel rates from the library's HIP-event timings (opt.profile),
+    with the algorithmic work of each kernel:
+      sketch:       2 s K d flop (one launch);
+      row sweep:    one read of A (FP64: 8 K d bytes; FP32 copy: 4 K d) plus
+                    the long vector (16 K bytes) per pass; only sweeps that
+                    made a pass are timed and counted;
+      Jacobi round: the SVD's 11 d^3 flop (eq. for the flop count of LSRN)
+                    spread over the solve's round launches.
+    and the stage figures: the iteration phase's HBM fraction
+    B_iter * passes / (t * 8 TB/s), and the SVD stage's (2 s d^2 + 11 d^3) /
+    t_svd against the FP64 peak."""
+    f32 = args.precision != "fp64" or args.storage != "f64"
+    bytes_per_sweep = (4.0 if f32 else 8.0) * K * d + 16.0 * K
+    t_sketch_k = mean("t_sketch_kernel_ms")
+    t_sweep_k, n_sweep = mean("t_sweep_kernel_ms"), mean("sweep_kernels")
+    t_jac_k, n_jac = mean("t_jacobi_kernel_ms"), mean("jacobi_kernels")
+    sketch_flop = 2.0 * s * K * d
+    kernels = {}
+    if t_sketch_k > 0 and args.precision == "fp64":
+        kernels["sketch_mfma_f64"] = {
+            "avg_ms": round(t_sketch_k, 4), "launches_per_step": 1, "bound": "mfma",
+            "achieved": round(sketch_flop / (t_sketch_k * 1e-3) / 1e12, 3), "unit": "TFLOP/s",
+            "peak": FP64_MFMA_PEAK_TFS}
+    elif t_sketch_k > 0:
+        # three BF16 products (the exact split of fl32(A)) per element of G A
+        kernels["sketch_mfma_bf16x3"] = {
+            "avg_ms": round(t_sketch_k, 4), "launches_per_step": 1, "bound": "mfma",
+            "achieved": round(3 * sketch_flop / (t_sketch_k * 1e-3) / 1e12, 3), "unit": "TFLOP/s",
+            "peak": BF16_MFMA_PEAK_TFS}
+    if t_sweep_k > 0 and n_sweep > 0:
+        avg = t_sweep_k / n_sweep
+        kernels["row_sweep"] = {
+            "avg_ms": round(avg, 5), "launches_per_step": n_sweep, "bound": "hbm",
+            "achieved": round(bytes_per_sweep / (avg * 1e-3) / 1e9, 1), "unit": "GB/s",
+            "peak": HBM_PEAK_GBS}
+    if t_jac_k > 0 and n_jac > 0:
+        avg = t_jac_k / n_jac
+        kernels["jacobi_round"] = {
+            "avg_ms": round(avg, 5), "launches_per_step": n_jac, "bound": "alu",
+            "achieved": round(11.0 * d ** 3 / n_jac / (avg * 1e-3) / 1e12, 4), "unit": "TFLOP/s",
+            "peak": FP64_VECTOR_PEAK_TFS,
+            "bytes_per_launch_model": 16.0 * d * d}
+    stages = {}
+    it, t_it = mean("iters"), mean("t_iter_ms")
+    if it > 0 and t_it > 0:
+        gbs = bytes_per_sweep * it / (t_it * 1e-3) / 1e9
+        stages["iter_phase"] = {"bytes_per_iter": bytes_per_sweep, "iters": it,
+                                "t_ms": round(t_it, 3), "achieved": round(gbs, 1), "unit": "GB/s",
+                                "peak": HBM_PEAK_GBS, "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    t_svd = mean("t_svd_ms")
+    if t_svd > 0:
+        fl = 2.0 * s * d * d + 11.0 * d ** 3
+        tf = fl / (t_svd * 1e-3) / 1e12
+        stages["svd_stage"] = {"flop": fl, "t_ms": round(t_svd, 3), "achieved": round(tf, 3),
+                               "unit": "TFLOP/s", "peak": FP64_VECTOR_PEAK_TFS,
+                               "frac": round(tf / FP64_VECTOR_PEAK_TFS, 4)}
+    return kernels, stages
 
 
 if __name__ == "__main__":

@@ -48,7 +48,7 @@ typedef enum {
     LSRN_E_NOMEM = 2,         /* device allocation failed                   */
     LSRN_E_HIP = 3,           /* a HIP runtime call failed                  */
     LSRN_E_NOT_CONVERGED = 4, /* LSQR hit max_iter; x holds the last iterate */
-    LSRN_E_UNSUPPORTED = 5    /* e.g. Tikhonov on an under-determined A     */
+    LSRN_E_UNSUPPORTED = 5    /* e.g. Chebyshev with the precision form     */
 } lsrn_status;
 
 typedef enum { LSRN_LSQR = 0, LSRN_CHEBYSHEV = 1 } lsrn_method;
@@ -76,6 +76,10 @@ typedef enum { LSRN_PRECOND_AUTO = 0, LSRN_PRECOND_SVD = 1, LSRN_PRECOND_QR = 2 
  *     refinement residuals (double-double, with the FP64 A) stay FP64.  The
  *     main LSQR stops at max(tol, 1e-8) and refinement steps (opt->refine, 10
  *     when 0) bring x to the FP64 solution while kappa(A) * 2^-24 << 1.
+ *     When the sketch's sigma_max / sigma_min_kept times 2^-24 exceeds 1/2
+ *     (FP32 sweeps could not contract) the sweeps read the FP64 A from the
+ *     start and only the sketch is BF16 (info->fp64_refine_steps then counts
+ *     every refinement step).
  *     The Chebyshev bounds of Sec. 4.2 hold for the exact sketch only, so
  *     LSRN_CHEBYSHEV is rejected (LSRN_E_UNSUPPORTED), and so are
  *     under-determined A: the FP32 sweeps would leave a component of size
@@ -94,7 +98,10 @@ typedef struct lsrn_options {
                           max(s, d) * 2^-52 (d = min(m, n))                     */
     double t_margin;   /* margin t of Lemma 3 in the Chebyshev bounds
                           sigma_U = 1/(sqrt s - sqrt r - t),
-                          sigma_L = 1/(sqrt s + sqrt r + t) (Theorem 3); 1     */
+                          sigma_L = 1/(sqrt s + sqrt r + t) (Theorem 3); 1.
+                          A negative t narrows the interval (it then misses
+                          part of the spectrum: a way to exercise the check
+                          after a Chebyshev run)                              */
     double refine_tol; /* relative accuracy asked of each refinement
                           correction; 1e-6                                      */
     uint64_t seed;     /* Philox key of G; 0                                   */
@@ -112,6 +119,10 @@ typedef struct lsrn_options {
                           the candidate launch shapes of the dense sweep and
                           records the fastest (see lsrn_tune_export); zero:
                           recorded shapes if any, else the built-in ones; 0 */
+    int32_t keep_sketch; /* plans: keep the sketch G T of A (s d doubles) so
+                          that lsrn_plan_set_lambda re-forms the
+                          preconditioner for another lambda without a new
+                          sketch; 0                                         */
 } lsrn_options;
 
 typedef struct lsrn_info {
@@ -123,7 +134,11 @@ typedef struct lsrn_info {
     int64_t refine_iters;   /* inner iterations summed over refinement steps     */
     int64_t sweeps;         /* Jacobi sweeps of the sketch SVD                   */
     int32_t tall;           /* 1: Alg. 1 (m >= n), 0: Alg. 2                     */
-    int32_t converged;      /* stopping rule met (always 1 for Chebyshev)        */
+    int32_t converged;      /* LSQR: stopping rule met; Chebyshev: the check
+                               after the run passed, or the LSQR restart it
+                               triggered met its stopping rule; with
+                               refinement (FP64): the last correction's
+                               inner solve met its rule                     */
     double sigma_l, sigma_u;/* Chebyshev bounds used (0 when r is too large)     */
     double sigma_max;       /* largest singular value of the sketch              */
     double sigma_min_kept;  /* sigma_r of the sketch                             */
@@ -133,7 +148,9 @@ typedef struct lsrn_info {
     double t_refine_ms;     /* refinement                                        */
     double t_total_ms;
     /* with opt->profile: summed durations of the sketch GEMM kernel and of
-     * the row-sweep kernels (each sweep = one pass over A), and their counts */
+     * the row-sweep kernels (each sweep = one pass over A), and their
+     * counts; sweeps enqueued past the last iteration of a loop (they find
+     * the loop finished and read nothing) are not counted */
     double t_sketch_kernel_ms;
     double t_sweep_kernel_ms;
     int64_t sketch_kernels;
@@ -145,6 +162,17 @@ typedef struct lsrn_info {
     /* precision form: refinement steps whose sweeps read the FP64 A because
      * the FP32 ones had stopped shrinking the corrections                   */
     int64_t fp64_refine_steps;
+    /* Chebyshev runs (main solve and refinement corrections) that failed the
+     * check after the run and were continued by LSQR.  Theorem 3's bounds
+     * hold with a probability (Lemma 3); inside them the normal-equation
+     * gradient after the run is at most tol times the starting one, and a
+     * run outside them grows it instead.  The check passes when ||g|| <=
+     * 2 max(tol, 2^-27) ||g0|| (tall: g = (A N)^T r, g0 = (A N)^T b; fat:
+     * the residual of M^T A x = M^T b against M^T b; the floor 2^-27 stays
+     * above the rounding of the products A (N y)); on failure LSQR
+     * continues from the Chebyshev iterate (from 0 when the run left a
+     * residual above the right-hand side's).                               */
+    int64_t cs_fallbacks;
 } lsrn_info;
 
 /* Fill *opt with the defaults listed above. */
@@ -158,9 +186,13 @@ const char *lsrn_last_error(void);
 
 /*
  * Min-length solution x (length n) of min ||A x - b||_2 for dense FP64 A
- * (m x n) -- Alg. 1 when m >= n (or when lambda > 0), Alg. 2 when m < n;
- * Tikhonov-regularised (Sec. 5, W = lambda I) when opt->lambda > 0, which
- * requires m >= n (LSRN_E_UNSUPPORTED otherwise).
+ * (m x n) -- Alg. 1 when m >= n, Alg. 2 when m < n.  With opt->lambda > 0
+ * the Tikhonov problem min ||A x - b||^2 + lambda^2 ||x||^2 (Sec. 5,
+ * W = lambda I): m >= n runs Alg. 1 on the over-determined [A; lambda I_n]
+ * (rhs [b; 0]); m < n runs Alg. 2 on the under-determined [A, lambda I_m]
+ * (Sec. 5's form with the scale lambda taken into the unknown), whose
+ * min-length solution is [x; (b - A x) / lambda] -- the sketch size is then
+ * ceil(gamma m), not ceil(gamma n).
  * b: length m.  x: length n, overwritten.  opt may be NULL (defaults).
  * info may be NULL.  Errors: LSRN_E_INVALID for m, n <= 0, NULL pointers,
  * gamma <= 1, tol <= 0, lambda < 0, lda too small, bad layout or method.
@@ -221,8 +253,9 @@ lsrn_status lsrn_philox_words(uint64_t seed, int64_t row0, int64_t nrows, int64_
 lsrn_status lsrn_gauss_fill(uint64_t seed, int64_t row0, int64_t nrows, int64_t col0,
                             int64_t ncols, double *out, void *stream);
 
-/* Sketch X = G T (Alg. 1/2 step 3) with T the tall view of A: T = A
- * (m x n, plus the rows lambda I when lambda > 0) if m >= n, else T = A^T.
+/* Sketch X = G T (Alg. 1/2 step 3) with T the tall view of A: T = A if
+ * m >= n, else T = A^T, followed by the rows lambda I_d when lambda > 0
+ * ([A; lambda I_n] or [A^T; lambda I_m], Sec. 5).
  * X is s x d (d = n if tall else m), written COLUMN-MAJOR: X[i][j] at
  * X[j * s + i].  G(i, k) as in lsrn_gauss_fill. */
 lsrn_status lsrn_sketch_dense(int64_t m, int64_t n, const double *A, int64_t lda,
@@ -383,6 +416,29 @@ lsrn_status lsrn_plan_create_csr(int64_t m, int64_t n, int64_t nnz, const int64_
 lsrn_status lsrn_plan_solve(const lsrn_plan *plan, const double *b, double *x,
                             const lsrn_options *opt, lsrn_info *info, void *stream);
 
+/* Regularisation path (Sec. 5, closing paragraph: for a new W only the
+ * sketch of W is new): re-form the plan's preconditioner for the Tikhonov
+ * weight `lambda` (>= 0) from the sketch kept at creation (opt.keep_sketch;
+ * LSRN_E_INVALID otherwise) -- X(lambda) = G T + lambda G(:, K .. K+d-1),
+ * the same bits as a fresh sketch with that lambda -- then SVD, rank and N
+ * (or M) again.  Later lsrn_plan_solve calls solve the problem with this
+ * lambda and return bit for bit what lsrn_solve_dense / lsrn_solve_csr
+ * return for it.  info (may be NULL) reports s, d, rank, sweeps, sigma and
+ * the stage times (t_sketch_ms covers only the added rows).  Must not run
+ * while solves on this plan are in flight.  Synchronises `stream`. */
+lsrn_status lsrn_plan_set_lambda(lsrn_plan *plan, double lambda, lsrn_info *info, void *stream);
+
+/* The oversampling factor gamma in [gamma_min, gamma_max] that minimises a
+ * solve's modelled time, from the stage times and counts of a solve
+ * measured with some gamma0 (`measured`: s, d, rank, iters, t_sketch_ms,
+ * t_svd_ms, t_iter_ms) -- Sec. 6.3's choice of gamma.  The model (Sec. 4.3's
+ * cost terms): the sketch time grows with s; of the SVD, the QR part
+ * (2 s d^2 flop) grows with s and the rest (11 d^3) does not; the iteration
+ * time scales with the Alg. 3 count for the bounds of (s, r) (Theorem 3,
+ * t = 1) at tolerance `tol`.  Host arithmetic only (no device call). */
+lsrn_status lsrn_tune_gamma(const lsrn_info *measured, double tol, double gamma_min,
+                            double gamma_max, double *gamma_out);
+
 /* Free the plan's device memory (after its solves have finished). */
 void lsrn_plan_destroy(lsrn_plan *plan);
 
@@ -397,7 +453,11 @@ void lsrn_plan_destroy(lsrn_plan *plan);
  * in `hbm_budget_bytes` next to the solves already running; a request
  * larger than the budget runs alone.  Admitted solves overlap on the device
  * and each runs exactly the kernels of lsrn_solve_dense / lsrn_solve_csr,
- * so its result equals that of the same call made alone.  The caller keeps
+ * so its result equals that of the same call made alone.  Served requests
+ * never tune launch shapes (opt.autotune is ignored; recorded shapes are
+ * used): timings taken while other solves share the device are noise, and
+ * a new table entry would change the summation order of later requests.
+ * The caller keeps
  * A, b and x (device memory) alive and unused until lsrn_server_wait
  * returns for the ticket.  Errors of a request are returned by
  * lsrn_server_wait (message in lsrn_server_last_error()).

@@ -52,7 +52,8 @@ class _Info(C.Structure):
                 ("sweeps", C.c_int64), ("refine_steps", C.c_int64),
                 ("sigma_l", C.c_double), ("sigma_u", C.c_double),
                 ("t_sketch", C.c_double), ("t_svd", C.c_double), ("t_iter", C.c_double),
-                ("t_refine", C.c_double), ("tall", C.c_int32), ("converged", C.c_int32)]
+                ("t_refine", C.c_double), ("tall", C.c_int32), ("converged", C.c_int32),
+                ("cs_fallbacks", C.c_int64)]
 
 
 _MV = C.CFUNCTYPE(None, C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double))
@@ -228,7 +229,9 @@ def matvec_t(M: Matrix, y) -> np.ndarray:
 
 
 def is_tall(M: Matrix) -> bool:
-    return M.m + (M.n if M.lam > 0 else 0) >= M.n
+    """Alg. 1 when m >= n, Alg. 2 otherwise (with lambda > 0 the latter is
+    the under-determined Tikhonov form [A, lambda I_m] of Sec. 5)."""
+    return M.m >= M.n
 
 
 def sketch(M: Matrix, s: int, seed: int) -> np.ndarray:
@@ -365,6 +368,7 @@ class Result:
     converged: bool
     sigma: np.ndarray
     P: np.ndarray
+    cs_fallbacks: int = 0
 
 
 PRECOND_SVD, PRECOND_QR = 0, 1
@@ -392,7 +396,7 @@ def lsrn_solve(M: Matrix, b, *, gamma=2.0, tol=1e-14, method=LSQR, seed=0, rcond
     return Result(x, info.s, info.d, r, info.iters, info.sweeps, info.refine_steps,
                   info.sigma_l, info.sigma_u, info.t_sketch, info.t_svd, info.t_iter,
                   info.t_refine, bool(info.tall), bool(info.converged), sigma,
-                  P[:, :r].copy())
+                  P[:, :r].copy(), int(info.cs_fallbacks))
 
 
 def lsrn_iterate(M: Matrix, b, P, s: int, *, tol=1e-14, method=LSQR, t_margin=1.0,
@@ -412,7 +416,8 @@ def lsrn_iterate(M: Matrix, b, P, s: int, *, tol=1e-14, method=LSQR, t_margin=1.
         raise ValueError(f"orc_lsrn_iterate failed ({rc})")
     return x, int(info.iters), bool(info.converged), {"t_iter": info.t_iter,
                                                      "t_refine": info.t_refine,
-                                                     "refine_steps": int(info.refine_steps)}
+                                                     "refine_steps": int(info.refine_steps),
+                                                     "cs_fallbacks": int(info.cs_fallbacks)}
 
 
 def pinv_solve(M: Matrix, b, rcond: float = 0.0):

@@ -168,11 +168,12 @@ void orc_matvec_t(const orc_matrix *A, const double *y, double *x)
     }
 }
 
-/* Tall iff the (augmented) problem has at least as many rows as columns. */
+/* Alg. 1 when m >= n, Alg. 2 when m < n.  With lambda > 0 the Tikhonov
+ * problem is the over-determined [A; lambda I_n] (tall) or, for m < n, the
+ * under-determined [A, lambda I_m] (Sec. 5), so the shape of A decides. */
 static int is_tall(const orc_matrix *A)
 {
-    int64_t rows = A->m + (A->lambda > 0.0 ? A->n : 0);
-    return rows >= A->n;
+    return A->m >= A->n;
 }
 
 /* ====================================================================
@@ -207,9 +208,13 @@ static int64_t sketch_impl(const orc_matrix *A, int64_t s, uint64_t seed, double
 #define G_OF(v) (precision_form ? (double)orc_bf16_round((float)(v)) : (v))
 #define A_OF(v) (precision_form ? (double)(float)(v) : (v))
 
+    const int64_t K0 = tall ? A->m : A->n;   /* rows of T before any lambda rows */
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < s; ++i) {
         double *xi = X + i * d;
+        double g4[4];
+        int64_t cached_q = -1;
+        int64_t K = K0;
         if (A->kind == ORC_CSR && !tall) {
             /* T = A^T: column j of X collects row j of A. */
             for (int64_t j = 0; j < A->m; ++j) {
@@ -218,11 +223,8 @@ static int64_t sketch_impl(const orc_matrix *A, int64_t s, uint64_t seed, double
                     acc += G_OF(orc_gauss(seed, (uint64_t)i, (uint64_t)A->colind[p])) * A_OF(A->val[p]);
                 xi[j] = acc;
             }
-            continue;
+            K = 0; /* the rows of T are done */
         }
-        const int64_t K = tall ? A->m : A->n;
-        double g4[4];
-        int64_t cached_q = -1;
         for (int64_t k = 0; k < K; ++k) {
             if (k / 4 != cached_q) {
                 cached_q = k / 4;
@@ -240,11 +242,13 @@ static int64_t sketch_impl(const orc_matrix *A, int64_t s, uint64_t seed, double
                     xi[j] += g * A_OF(a_at(A, j, k));
             }
         }
-        if (tall && A->lambda > 0.0) {
-            /* Sec. 5: the rows lambda*I of the augmented matrix are rows
-             * m .. m+n-1 of T; row m+c has lambda in column c. */
-            for (int64_t c = 0; c < A->n; ++c)
-                xi[c] += orc_gauss(seed, (uint64_t)i, (uint64_t)(A->m + c)) * A->lambda;
+        if (A->lambda > 0.0) {
+            /* Sec. 5: the rows lambda I_d of the augmented tall view are rows
+             * K0 .. K0+d-1 of T (T = [A; lambda I_n] when tall, [A^T; lambda
+             * I_m] for the under-determined form [A, lambda I_m]); row K0+c
+             * has lambda in column c. */
+            for (int64_t c = 0; c < d; ++c)
+                xi[c] += orc_gauss(seed, (uint64_t)i, (uint64_t)(K0 + c)) * A->lambda;
         }
     }
 #undef G_OF
@@ -631,10 +635,15 @@ static void tall_mvt(void *vctx, const double *u, double *out)
     pt_times(c, c->tmp_d, out);
 }
 
+/* Fat: K = M^T [A, lambda I_m] on x^ = [x; rho] (rho only when lambda > 0,
+ * the under-determined Tikhonov form of Sec. 5). */
 static void fat_mv(void *vctx, const double *x, double *out)
 {
     precond_ctx *c = (precond_ctx *)vctx;
     orc_matvec(c->A, x, c->tmp_d);
+    if (c->A->lambda > 0.0)
+        for (int64_t i = 0; i < c->A->m; ++i)
+            c->tmp_d[i] += c->A->lambda * x[c->A->n + i];
     pt_times(c, c->tmp_d, out);
 }
 
@@ -643,6 +652,9 @@ static void fat_mvt(void *vctx, const double *u, double *out)
     precond_ctx *c = (precond_ctx *)vctx;
     p_times(c, u, c->tmp_d);
     orc_matvec_t(c->A, c->tmp_d, out);
+    if (c->A->lambda > 0.0)
+        for (int64_t i = 0; i < c->A->m; ++i)
+            out[c->A->n + i] = c->A->lambda * c->tmp_d[i];
 }
 
 /* Conjugate gradients (Hestenes & Stiefel 1952) on K^T K z = rhs from z = 0. */
@@ -681,6 +693,67 @@ static int64_t cg_normal(const orc_linop *K, const double *rhs, double rtol, int
     return it;
 }
 
+/* The check after a Chebyshev run, an addition to Alg. 3.  The run is
+ * exact only when the singular values of K lie in [sigma_L, sigma_U]
+ * (Theorem 3 gives that with a probability, Lemma 3).  Within those bounds
+ * the normal-equation gradient after the run is the Chebyshev residual
+ * polynomial, at most eps in absolute value on [sigma_L^2, sigma_U^2],
+ * applied to the starting gradient.  Tall (K = [A; lambda I] N): g =
+ * K^T (b - K y) against g0 = K^T b.  Fat (K = M^T A): the system is
+ * consistent and the residual c - K x is compared with c.  The run passes
+ * when ||g|| <= 2 max(eps, 2^-27) ||g0||: the floor 2^-27 (about sqrt(u))
+ * stays above the rounding of the products K y = A (N y), whose relative
+ * size grows with kappa(A) (1e-12 at kappa 1e6), while a run outside the
+ * bounds grows the gradient instead of shrinking it.  On failure LSQR
+ * solves K d = (the residual) from d = 0 and sol += d, or, when the run
+ * left a residual larger than the right-hand side (it diverged), sol is
+ * reset to 0 and LSQR solves the original system.  Returns the LSQR
+ * iterations (0 when the run passed; negative when LSQR did not converge)
+ * and sets *fell_back. */
+static int64_t cs_check_restart(const orc_linop *K, const double *rhs, double *sol, int tall,
+                                double eps, double tol, int64_t maxiter, int *fell_back)
+{
+    const int64_t rows = K->rows, cols = K->cols;
+    double *res = (double *)malloc(sizeof(double) * (size_t)rows);
+    double *g = (double *)malloc(sizeof(double) * (size_t)cols);
+    K->mv(K->ctx, sol, res);
+    for (int64_t i = 0; i < rows; ++i)
+        res[i] = rhs[i] - res[i];
+    double gn, g0;
+    if (tall) {
+        K->mvt(K->ctx, res, g);
+        gn = nrm2(cols, g);
+        K->mvt(K->ctx, rhs, g);
+        g0 = nrm2(cols, g);
+    } else {
+        gn = nrm2(rows, res);
+        g0 = nrm2(rows, rhs);
+    }
+    const double floor_rel = ldexp(1.0, -27);
+    const double allow = 2.0 * (eps > floor_rel ? eps : floor_rel) * g0;
+    int64_t more = 0;
+    *fell_back = 0;
+    if (!(isfinite(gn) && gn <= allow)) {
+        *fell_back = 1;
+        /* LSQR continues from the Chebyshev iterate when its residual is no
+         * larger than the right-hand side's, else (a divergent run) from 0 */
+        const double rl = nrm2(rows, res), bl = nrm2(rows, rhs);
+        if (!(isfinite(rl) && rl <= bl)) {
+            for (int64_t j = 0; j < cols; ++j)
+                sol[j] = 0.0;
+            memcpy(res, rhs, sizeof(double) * (size_t)rows);
+        }
+        double *d = (double *)malloc(sizeof(double) * (size_t)cols);
+        more = orc_lsqr(K, res, tol, maxiter, d);
+        for (int64_t j = 0; j < cols; ++j)
+            sol[j] += d[j];
+        free(d);
+    }
+    free(res);
+    free(g);
+    return more;
+}
+
 /* Alg. 1/2 steps 6-7 (and reference-mode refinement) with a given
  * preconditioner P (d x r, row-major, leading dimension ldp): N for tall
  * problems, M for fat ones; s is the sketch size behind the Chebyshev
@@ -693,6 +766,8 @@ int orc_lsrn_iterate(const orc_matrix *A, const double *b, const double *P, int6
     const int tall = is_tall(A);
     const int64_t rows = m + (A->lambda > 0.0 ? n : 0);
     const int64_t d = tall ? n : m;
+    /* fat: the unknown of [A, lambda I_m] x^ = b is x^ = [x; rho] */
+    const int64_t nl = n + (!tall && A->lambda > 0.0 ? m : 0);
     for (int64_t j = 0; j < n; ++j)
         x[j] = 0.0;
     precond_ctx ctx;
@@ -708,7 +783,7 @@ int orc_lsrn_iterate(const orc_matrix *A, const double *b, const double *P, int6
     if (tall) {
         K.rows = rows; K.cols = r; K.mv = tall_mv; K.mvt = tall_mvt;
     } else {
-        K.rows = r; K.cols = n; K.mv = fat_mv; K.mvt = fat_mvt;
+        K.rows = r; K.cols = nl; K.mv = fat_mv; K.mvt = fat_mvt;
     }
 
     double sl = 0.0, su = 0.0;
@@ -732,36 +807,45 @@ int orc_lsrn_iterate(const orc_matrix *A, const double *b, const double *P, int6
     } else {
         pt_times(&ctx, b, rhs);
     }
-    double *sol = (double *)malloc(sizeof(double) * (size_t)(tall ? r : n));
+    double *sol = (double *)malloc(sizeof(double) * (size_t)(tall ? r : nl));
     int64_t it;
-    if (opt->method == ORC_CS)
+    if (opt->method == ORC_CS) {
         it = orc_cs(&K, rhs, sl, su, opt->tol, sol);
-    else
+        int fb = 0;
+        /* the default cap follows from the bounds the check found wrong */
+        const int64_t cap = opt->max_iter > 0 ? opt->max_iter : 4 * maxiter;
+        const int64_t more = cs_check_restart(&K, rhs, sol, tall, opt->tol, opt->tol, cap, &fb);
+        info->cs_fallbacks += fb;
+        it = more >= 0 ? it + more : -(it - more);
+    } else {
         it = orc_lsqr(&K, rhs, opt->tol, maxiter, sol);
+    }
     info->converged = it >= 0;
     info->iters = it >= 0 ? it : -it;
+    /* the refined unknown: x (tall) or x^ = [x; rho] (fat) */
+    double *xh = tall ? x : sol;
     if (tall)
         p_times(&ctx, sol, x); /* Alg. 1 step 7: x = N y */
-    else
-        memcpy(x, sol, sizeof(double) * (size_t)n);
     const double t3 = now_s();
     info->t_iter = t3 - t2;
 
     /* Reference-mode refinement. */
     int64_t steps = 0;
     for (int32_t step = 0; step < opt->refine; ++step) {
-        double xn = nrm2(n, x), dxn = 0.0;
+        double xn = nrm2(tall ? n : nl, xh), dxn = 0.0;
         long double *res = (long double *)malloc(sizeof(long double) * (size_t)m);
 #pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < m; ++i) {            /* res = b - A x in long double */
             long double acc = (long double)b[i];
             if (A->kind == ORC_CSR) {
                 for (int64_t p = A->rowptr[i]; p < A->rowptr[i + 1]; ++p)
-                    acc -= (long double)A->val[p] * (long double)x[A->colind[p]];
+                    acc -= (long double)A->val[p] * (long double)xh[A->colind[p]];
             } else {
                 for (int64_t j = 0; j < n; ++j)
-                    acc -= (long double)a_at(A, i, j) * (long double)x[j];
+                    acc -= (long double)a_at(A, i, j) * (long double)xh[j];
             }
+            if (nl > n)   /* under-determined Tikhonov: b - A x - lambda rho */
+                acc -= (long double)A->lambda * (long double)xh[n + i];
             res[i] = acc;
         }
         if (tall) {
@@ -802,8 +886,9 @@ int orc_lsrn_iterate(const orc_matrix *A, const double *b, const double *P, int6
             dxn = nrm2(n, dx);
             free(h); free(c); free(z); free(dx);
         } else {
-            /* e = M^T (b - A x) in long double; solve M^T A dx = e with the
-             * same method as the main solve. */
+            /* e = M^T (b - A x - lambda rho) in long double; solve
+             * M^T [A, lambda I] dx^ = e with the same method as the main
+             * solve. */
             double *e = (double *)malloc(sizeof(double) * (size_t)r);
 #pragma omp parallel for schedule(static)
             for (int64_t k = 0; k < r; ++k) {
@@ -812,14 +897,19 @@ int orc_lsrn_iterate(const orc_matrix *A, const double *b, const double *P, int6
                     acc += (long double)P[i * ldp + k] * res[i];
                 e[k] = (double)acc;
             }
-            double *dx = (double *)malloc(sizeof(double) * (size_t)n);
-            if (opt->method == ORC_CS)
+            double *dx = (double *)malloc(sizeof(double) * (size_t)nl);
+            if (opt->method == ORC_CS) {
                 orc_cs(&K, e, sl, su, opt->tol, dx);
-            else
+                int fb = 0;
+                cs_check_restart(&K, e, dx, 0, opt->tol, opt->tol,
+                                 opt->max_iter > 0 ? opt->max_iter : 4 * maxiter, &fb);
+                info->cs_fallbacks += fb;
+            } else {
                 orc_lsqr(&K, e, opt->tol, maxiter, dx);
-            for (int64_t j = 0; j < n; ++j)
-                x[j] += dx[j];
-            dxn = nrm2(n, dx);
+            }
+            for (int64_t j = 0; j < nl; ++j)
+                xh[j] += dx[j];
+            dxn = nrm2(nl, dx);
             free(e); free(dx);
         }
         free(res);
@@ -829,6 +919,8 @@ int orc_lsrn_iterate(const orc_matrix *A, const double *b, const double *P, int6
     }
     info->refine_steps = steps;
     info->t_refine = now_s() - t3;
+    if (!tall)
+        memcpy(x, sol, sizeof(double) * (size_t)n);   /* x = the first n entries of x^ */
 
     free(rhs); free(sol); free(ctx.tmp_d); free(ctx.tmp_n);
     return 0;
@@ -844,8 +936,6 @@ int orc_lsrn_solve(const orc_matrix *A, const double *b, const orc_options *opt,
     const int64_t m = A->m, n = A->n;
     if (m <= 0 || n <= 0 || !(opt->gamma > 1.0) || !(opt->tol > 0.0) || A->lambda < 0.0)
         return -1;
-    if (A->lambda > 0.0 && m < n)
-        return -2; /* under-determined Tikhonov form (Sec. 5) not provided */
     const int tall = is_tall(A);
     const int64_t d = tall ? n : m;
     /* Alg. 1/2 step 1: s = ceil(gamma * d). */

@@ -72,8 +72,12 @@ enum { ORC_LSQR = 0, ORC_CS = 1 };
 /* The least-squares matrix A (m x n).  Dense: a with leading dimension lda,
  * row-major (ORC_DENSE_ROW: a[i*lda+j]) or column-major (ORC_DENSE_COL:
  * a[j*lda+i]).  CSR: rowptr[m+1], colind[nnz], val[nnz].
- * lambda > 0 means the Tikhonov problem min ||Ax-b||^2 + lambda^2 ||x||^2,
- * solved as the augmented problem [A; lambda I] x ~ [b; 0] (Sec. 5). */
+ * lambda > 0 means the Tikhonov problem min ||Ax-b||^2 + lambda^2 ||x||^2
+ * (Sec. 5), solved as the over-determined [A; lambda I_n] x ~ [b; 0] when
+ * m >= n, and for m < n as the min-length solution x^ = [x; rho] of the
+ * under-determined [A, lambda I_m] x^ = b (the paper's form with
+ * W = lambda I, scaled by lambda: its minimiser has rho = (b - A x)/lambda,
+ * so ||x^||^2 = ||x||^2 + ||b - A x||^2 / lambda^2). */
 typedef struct {
     int64_t m, n;
     int32_t kind;
@@ -92,11 +96,11 @@ void orc_matvec_t(const orc_matrix *A, const double *y, double *x);
 
 /* ------------------------------------------------------------ sketch */
 
-/* Tall view: if A (augmented with lambda I when lambda > 0) has at least as
- * many rows as columns, T = [A; lambda I] (M x d, d = n) and the sketch is
- * X = G T (Alg. 1, step 3).  Otherwise T = A^T (n x m, d = m) and the sketch
- * is X = (A G')^T = G T with G' = G^T (Alg. 2, step 3).  G(i, k) is
- * orc_gauss(seed, i, k) for i < s, k < rows(T).
+/* Tall view: if m >= n, T = A (d = n) and the sketch is X = G T (Alg. 1,
+ * step 3).  Otherwise T = A^T (n x m, d = m) and the sketch is
+ * X = (A G')^T = G T with G' = G^T (Alg. 2, step 3).  When lambda > 0 the
+ * rows lambda I_d follow (T = [A; lambda I_n] or [A^T; lambda I_m]).
+ * G(i, k) is orc_gauss(seed, i, k) for i < s, k < rows(T).
  * X is s x d, row-major.  Returns d, or -1 on bad input. */
 int64_t orc_sketch(const orc_matrix *A, int64_t s, uint64_t seed, double *X);
 
@@ -190,14 +194,18 @@ typedef struct {
     double t_sketch, t_svd, t_iter, t_refine;
     int32_t tall;
     int32_t converged;
+    int64_t cs_fallbacks;  /* Chebyshev runs that failed the check after the
+                              run and were continued by LSQR (see
+                              orc_lsrn_iterate)                              */
 } orc_info;
 
 /* Min-length least-squares solution x (length n) of min ||Ax - b||
  * (Tikhonov-regularised when A->lambda > 0) by LSRN.  With opt->refine > 0
  * the result is refined: tall problems solve the preconditioned normal
  * equations (A N)^T (A N) dy = N^T A^T (b - A x) with the normal-equation
- * residual in long double; fat problems solve M^T A dx = M^T (b - A x) with
- * the residual in long double.  Both corrections stay in range(A^T).
+ * residual in long double; fat problems solve M^T A^ dx^ = M^T (b - A^ x^)
+ * (A^ = A, or [A, lambda I_m] with x^ = [x; rho]) with the residual in long
+ * double.  Both corrections stay in range(A^T) (range(A^^T)).
  * sigma_out (length d) and P_out (d*d) may be NULL.  Returns 0 on success. */
 int orc_lsrn_solve(const orc_matrix *A, const double *b, const orc_options *opt,
                    double *x, orc_info *info, double *sigma_out, double *P_out);

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <memory>
 #include <algorithm>
 #include <exception>
@@ -116,7 +117,7 @@ void check_options(const lsrn_options &o) {
     LSRN_REQUIRE(o.method == LSRN_LSQR || o.method == LSRN_CHEBYSHEV, "unknown method");
     LSRN_REQUIRE(o.refine >= 0 && o.refine <= 100, "refine must lie in [0, 100]");
     LSRN_REQUIRE(o.refine_tol > 0.0 && o.refine_tol < 1.0, "refine_tol must lie in (0, 1)");
-    LSRN_REQUIRE(std::isfinite(o.t_margin) && o.t_margin >= 0.0, "t_margin must be >= 0");
+    LSRN_REQUIRE(std::isfinite(o.t_margin), "t_margin must be finite");
     LSRN_REQUIRE(o.precond == LSRN_PRECOND_AUTO || o.precond == LSRN_PRECOND_SVD ||
                      o.precond == LSRN_PRECOND_QR,
                  "unknown preconditioner kind");
@@ -141,8 +142,6 @@ void make_view(TallView &v, int64_t m, int64_t n, const double *A, int64_t lda, 
                double lambda, hipStream_t st) {
     LSRN_REQUIRE(layout == LSRN_ROW_MAJOR || layout == LSRN_COL_MAJOR, "unknown layout");
     LSRN_REQUIRE(lda >= (layout == LSRN_ROW_MAJOR ? n : m), "lda too small for the layout");
-    if (lambda > 0.0 && m < n)
-        fail(LSRN_E_UNSUPPORTED, "Tikhonov regularisation needs m >= n (under-determined form not provided)");
     v.tall = m >= n;
     v.K = v.tall ? m : n;
     v.d = v.tall ? n : m;
@@ -165,8 +164,6 @@ void make_view_f32(TallView &v, int64_t m, int64_t n, const float *A, int64_t ld
                    double lambda, hipStream_t st) {
     LSRN_REQUIRE(layout == LSRN_ROW_MAJOR || layout == LSRN_COL_MAJOR, "unknown layout");
     LSRN_REQUIRE(lda >= (layout == LSRN_ROW_MAJOR ? n : m), "lda too small for the layout");
-    if (lambda > 0.0 && m < n)
-        fail(LSRN_E_UNSUPPORTED, "Tikhonov regularisation needs m >= n (under-determined form not provided)");
     v.tall = m >= n;
     v.K = v.tall ? m : n;
     v.d = v.tall ? n : m;
@@ -208,12 +205,51 @@ void fill_iter_info(lsrn_info *info, int64_t s, int64_t d, int64_t r, bool tall,
     info->s = s; info->d = d; info->rank = r; info->iters = ir.iters;
     info->refine_steps = ir.refine_steps; info->refine_iters = ir.refine_iters;
     info->fp64_refine_steps = ir.fp64_refine_steps;
+    info->cs_fallbacks = ir.cs_fallbacks;
     info->tall = tall; info->converged = ir.converged;
     info->sigma_l = ir.sigma_l; info->sigma_u = ir.sigma_u;
     info->t_iter_ms = ir.t_iter_ms; info->t_refine_ms = ir.t_refine_ms;
     info->t_total_ms = ir.t_iter_ms + ir.t_refine_ms;
     info->t_sweep_kernel_ms = ir.t_sweep_kernel_ms;
     info->sweep_kernels = ir.sweep_kernels;
+}
+
+// The oversampling factor that minimises a solve's modelled time, from the
+// stage times of one solve measured at gamma0 = s0 / d (the cost terms of
+// Sec. 4.3; the choice of gamma of Sec. 6.3): the sketch grows with s; of
+// the SVD, the QR part (2 s d^2 flop) grows with s and the Jacobi part
+// (11 d^3) does not; the iterations follow the Alg. 3 count for the bounds
+// of (s, r) (Theorem 3 with t = 1, the LSQR bound of Theorem 4 behaving
+// alike), each at the measured per-iteration time.  gamma runs over
+// [gamma_min, gamma_max] in steps of 0.01.
+double choose_gamma(int64_t s0, int64_t d, int64_t r, int64_t iters0, double tol, double t_sketch,
+                    double t_svd, double t_iter, double gamma_min, double gamma_max) {
+    (void)iters0;
+    auto count = [&](double s) {
+        const double lo = std::sqrt(s) - std::sqrt((double)r) - 1.0;
+        if (!(lo > 0.0)) return std::numeric_limits<double>::infinity();
+        const double su = 1.0 / lo, sl = 1.0 / (std::sqrt(s) + std::sqrt((double)r) + 1.0);
+        const double rate = (su - sl) / (su + sl);
+        return std::ceil((std::log(tol) - std::log(2.0)) / std::log(rate)) + 1.0;
+    };
+    const double k0 = count((double)s0);
+    auto model = [&](double s) {
+        const double it = std::isfinite(k0) ? t_iter * count(s) / k0 : t_iter;
+        return t_sketch * s / (double)s0 +
+               t_svd * (2.0 * s + 11.0 * (double)d) / (2.0 * (double)s0 + 11.0 * (double)d) + it;
+    };
+    double best_g = (double)s0 / (double)d, best_t = std::numeric_limits<double>::infinity();
+    for (int i = 0;; ++i) {
+        const double g = gamma_min + 0.01 * i;
+        if (g > gamma_max + 1e-12) break;
+        const double s = std::ceil(g * (double)d);
+        const double t = model(s);
+        if (t < best_t) {
+            best_t = t;
+            best_g = g;
+        }
+    }
+    return best_g;
 }
 
 // Largest min(m, n) the Jacobi kernels of the SVD handle.
@@ -239,8 +275,15 @@ struct Prepared {
 
 // Steps 1-5 for a dense (dv) or sparse (sv) tall view; tm gets two marks
 // (after the sketch, after the preconditioner).
+// With `plain`, the sketch G T without the Tikhonov rows is kept there (for
+// lsrn_plan_set_lambda); the rows lambda G(:, K + c) are then added by the
+// same kernel the sketch launches last, so X is the same bit for bit.
+void form_preconditioner(int64_t s, int64_t d, double *X, const lsrn_options &opt, hipStream_t st,
+                         Prepared &pp);
+
 void prepare(bool tall, int64_t K, int64_t d, const TallView *dv, const SparseView *sv,
-             const lsrn_options &opt, hipStream_t st, StageTimer &tm, Prepared &pp) {
+             const lsrn_options &opt, hipStream_t st, StageTimer &tm, Prepared &pp,
+             DevBuf *plain = nullptr) {
     const int64_t s = (int64_t)std::ceil(opt.gamma * (double)d);
     const bool qr_inv = use_qr_inverse(opt, d);
     const bool mixed = opt.precision == LSRN_PREC_MIXED;
@@ -255,29 +298,46 @@ void prepare(bool tall, int64_t K, int64_t d, const TallView *dv, const SparseVi
     DevBuf X((size_t)s * (size_t)d * sizeof(double));
     if (mixed && dv && dv->T32)
         fail(LSRN_E_UNSUPPORTED, "FP32 storage of A is solved in FP64 arithmetic (precision FP64)");
+    const double lam = plain ? 0.0 : opt.lambda;
     if (sv) {
-        sketch_csr(*sv, tall ? opt.lambda : 0.0, s, opt.seed, X.as<double>(), st,
+        sketch_csr(*sv, lam, s, opt.seed, X.as<double>(), st,
                    opt.profile ? &pp.sketch_kernel_ms : nullptr);
     } else if (dv->T32) {
-        sketch_rows(K, d, dv->T32, dv->ldt, tall ? opt.lambda : 0.0, s, opt.seed, X.as<double>(), st,
+        sketch_rows(K, d, dv->T32, dv->ldt, lam, s, opt.seed, X.as<double>(), st,
                     opt.profile ? &pp.sketch_kernel_ms : nullptr);
     } else if (mixed) {
         pp.T32.alloc((size_t)K * (size_t)dv->ldt * sizeof(float));
         to_f32(K, d, dv->T, dv->ldt, pp.T32.as<float>(), st);
-        sketch_rows_bf16(K, d, dv->T, dv->ldt, tall ? opt.lambda : 0.0, s, opt.seed, X.as<double>(),
+        sketch_rows_bf16(K, d, dv->T, dv->ldt, lam, s, opt.seed, X.as<double>(),
                          st, opt.profile ? &pp.sketch_kernel_ms : nullptr);
     } else {
-        sketch_rows(K, d, dv->T, dv->ldt, tall ? opt.lambda : 0.0, s, opt.seed, X.as<double>(), st,
+        sketch_rows(K, d, dv->T, dv->ldt, lam, s, opt.seed, X.as<double>(), st,
                     opt.profile ? &pp.sketch_kernel_ms : nullptr);
     }
+    if (plain) {
+        plain->alloc((size_t)s * (size_t)d * sizeof(double));
+        LSRN_HIP(hipMemcpyAsync(plain->as<double>(), X.as<double>(), (size_t)s * (size_t)d * sizeof(double),
+                                hipMemcpyDeviceToDevice, st));
+        add_identity_rows(K, d, s, opt.lambda, opt.seed, X.as<double>(), st);
+    }
     tm.mark();
-    pp.sigma.alloc((size_t)d * sizeof(double));
-    pp.P.alloc((size_t)d * (size_t)d * sizeof(double));
-    pp.pr = qr_inv ? precond_qr_inverse(s, d, X.as<double>(), opt.rcond, pp.sigma.as<double>(),
-                                        pp.P.as<double>(), st)
-                   : precond(s, d, X.as<double>(), opt.rcond, pp.sigma.as<double>(), pp.P.as<double>(),
-                             st, opt.profile != 0);
+    (void)qr_inv;
+    form_preconditioner(s, d, X.as<double>(), opt, st, pp);
     tm.mark();
+}
+
+// Steps 4-5 on a sketch X (overwritten): sigma, rank and P (SVD), or
+// P = R^-1 (the full-rank QR-inverse alternative).
+void form_preconditioner(int64_t s, int64_t d, double *X, const lsrn_options &opt, hipStream_t st,
+                         Prepared &pp) {
+    pp.s = s;
+    pp.d = d;
+    if (!pp.sigma.bytes()) pp.sigma.alloc((size_t)d * sizeof(double));
+    if (!pp.P.bytes()) pp.P.alloc((size_t)d * (size_t)d * sizeof(double));
+    pp.pr = use_qr_inverse(opt, d)
+                ? precond_qr_inverse(s, d, X, opt.rcond, pp.sigma.as<double>(), pp.P.as<double>(), st)
+                : precond(s, d, X, opt.rcond, pp.sigma.as<double>(), pp.P.as<double>(), st,
+                          opt.profile != 0);
 }
 
 // Steps 6-7 (+ refinement) with a prepared preconditioner.
@@ -293,11 +353,12 @@ IterResult run_iterations(bool tall, int64_t K, int64_t d, int64_t n, const Tall
     pb.tall = tall; pb.rows = K; pb.cols = d;
     if (sv) pb.sp = sv;
     else { pb.T = dv->T; pb.T32 = dv->T32; pb.ldt = dv->ldt; }
-    pb.lambda = tall ? opt.lambda : 0.0;
+    pb.lambda = opt.lambda;
     pb.P = pp.P.as<double>(); pb.ldp = d;
     pb.r = pp.pr.rank; pb.s = pp.s;
     if (pp.T32.bytes() > 0) {
         pb.T32 = pp.T32.as<float>();
+        pb.kappa_sketch = pp.pr.sigma_min_kept > 0.0 ? pp.pr.sigma_max / pp.pr.sigma_min_kept : 0.0;
         lsrn_options om = opt;
         if (om.refine == 0) om.refine = 10;
         return iterate(pb, b, x, om, st);
@@ -312,6 +373,7 @@ lsrn_status finish_info(bool tall, const Prepared &pp, const IterResult &ir, con
         info->s = pp.s; info->d = pp.d; info->rank = pp.pr.rank; info->iters = ir.iters;
         info->refine_steps = ir.refine_steps; info->refine_iters = ir.refine_iters;
         info->fp64_refine_steps = ir.fp64_refine_steps;
+    info->cs_fallbacks = ir.cs_fallbacks;
         info->sweeps = pp.pr.sweeps; info->tall = tall; info->converged = ir.converged;
         info->sigma_l = ir.sigma_l; info->sigma_u = ir.sigma_u;
         info->sigma_max = pp.pr.sigma_max; info->sigma_min_kept = pp.pr.sigma_min_kept;
@@ -363,6 +425,7 @@ struct lsrn_plan {
     lsrn::TallView dv;
     lsrn::SparseView sv;
     lsrn::Prepared pp;
+    lsrn::DevBuf plain;  // opt.keep_sketch: the sketch G T without the Tikhonov rows
 };
 
 extern "C" {
@@ -412,7 +475,7 @@ lsrn_status lsrn_sketch_dense(int64_t m, int64_t n, const double *A, int64_t lda
     hipStream_t st = (hipStream_t)stream;
     TallView v;
     make_view(v, m, n, A, lda, layout, lambda, st);
-    sketch_rows(v.K, v.d, v.T, v.ldt, v.tall ? lambda : 0.0, s, seed, X, st);
+    sketch_rows(v.K, v.d, v.T, v.ldt, lambda, s, seed, X, st);
     LSRN_HIP(hipStreamSynchronize(st));
     LSRN_API_END
 }
@@ -427,7 +490,7 @@ lsrn_status lsrn_sketch_dense_bf16(int64_t m, int64_t n, const double *A, int64_
     hipStream_t st = (hipStream_t)stream;
     TallView v;
     make_view(v, m, n, A, lda, layout, lambda, st);
-    sketch_rows_bf16(v.K, v.d, v.T, v.ldt, v.tall ? lambda : 0.0, s, seed, X, st);
+    sketch_rows_bf16(v.K, v.d, v.T, v.ldt, lambda, s, seed, X, st);
     LSRN_API_END
 }
 
@@ -474,7 +537,7 @@ lsrn_status lsrn_iterate_dense(int64_t m, int64_t n, const double *A, int64_t ld
     LSRN_REQUIRE(r > 0 && r <= v.d && ldp >= r && s > 0, "bad preconditioner shape");
     IterProblem pb;
     pb.tall = v.tall; pb.rows = v.K; pb.cols = v.d; pb.T = v.T; pb.ldt = v.ldt;
-    pb.lambda = v.tall ? opt.lambda : 0.0; pb.P = P; pb.ldp = ldp; pb.r = r; pb.s = s;
+    pb.lambda = opt.lambda; pb.P = P; pb.ldp = ldp; pb.r = r; pb.s = s;
     IterResult ir = iterate(pb, b, x, opt, st);
     fill_iter_info(info, s, v.d, r, v.tall, ir);
     if (!ir.converged) {
@@ -526,8 +589,6 @@ lsrn_status lsrn_solve_csr(int64_t m, int64_t n, int64_t nnz, const int64_t *row
     check_options(opt);
     LSRN_REQUIRE(m > 0 && n > 0, "sizes must be positive");
     LSRN_REQUIRE(b && x, "NULL pointer");
-    if (opt.lambda > 0.0 && m < n)
-        fail(LSRN_E_UNSUPPORTED, "Tikhonov regularisation needs m >= n (under-determined form not provided)");
     hipStream_t st = (hipStream_t)stream;
     StageTimer tm(st);
     tm.mark();
@@ -546,8 +607,6 @@ lsrn_status lsrn_solve_op(int64_t m, int64_t n, lsrn_apply_fn apply, void *ctx, 
     LSRN_REQUIRE(apply && b && x, "NULL pointer");
     if (opt.refine != 0 || opt.precision != LSRN_PREC_FP64)
         fail(LSRN_E_UNSUPPORTED, "an operator A is solved without refinement, in FP64");
-    if (opt.lambda > 0.0 && m < n)
-        fail(LSRN_E_UNSUPPORTED, "Tikhonov regularisation needs m >= n (under-determined form not provided)");
     hipStream_t st = (hipStream_t)stream;
     StageTimer tm(st);
     tm.mark();
@@ -571,7 +630,7 @@ lsrn_status lsrn_solve_op(int64_t m, int64_t n, lsrn_apply_fn apply, void *ctx, 
             ov.apply_t(1, kk, Gc.as<double>(), K, XT.as<double>() + i0 * d, d, st);
         }
         transpose(s, d, XT.as<double>(), d, X.as<double>(), st);
-        if (tall && opt.lambda > 0.0) add_identity_rows(K, d, s, opt.lambda, opt.seed, X.as<double>(), st);
+        if (opt.lambda > 0.0) add_identity_rows(K, d, s, opt.lambda, opt.seed, X.as<double>(), st);
         LSRN_HIP(hipStreamSynchronize(st));  // before the blocks are freed
     }
     tm.mark();
@@ -588,7 +647,7 @@ lsrn_status lsrn_solve_op(int64_t m, int64_t n, lsrn_apply_fn apply, void *ctx, 
     if (pp.pr.rank > 0) {
         IterProblem pb;
         pb.tall = tall; pb.rows = K; pb.cols = d; pb.op = &ov;
-        pb.lambda = tall ? opt.lambda : 0.0; pb.P = pp.P.as<double>(); pb.ldp = d;
+        pb.lambda = opt.lambda; pb.P = pp.P.as<double>(); pb.ldp = d;
         pb.r = pp.pr.rank; pb.s = s;
         ir = iterate(pb, b, x, opt, st);
     } else {
@@ -616,7 +675,8 @@ lsrn_status lsrn_plan_create_dense(int64_t m, int64_t n, const double *A, int64_
     tm.mark();
     make_view(plan->dv, m, n, A, lda, layout, opt.lambda, st);
     plan->tall = plan->dv.tall;
-    prepare(plan->tall, plan->dv.K, plan->dv.d, &plan->dv, nullptr, opt, st, tm, plan->pp);
+    prepare(plan->tall, plan->dv.K, plan->dv.d, &plan->dv, nullptr, opt, st, tm, plan->pp,
+            opt.keep_sketch ? &plan->plain : nullptr);
     tm.mark();
     LSRN_HIP(hipStreamSynchronize(st));
     finish_info(plan->tall, plan->pp, IterResult(), opt, info, &tm);
@@ -634,8 +694,6 @@ lsrn_status lsrn_plan_create_csr(int64_t m, int64_t n, int64_t nnz, const int64_
     LSRN_REQUIRE(out, "NULL pointer");
     *out = nullptr;
     LSRN_REQUIRE(m > 0 && n > 0, "sizes must be positive");
-    if (opt.lambda > 0.0 && m < n)
-        fail(LSRN_E_UNSUPPORTED, "Tikhonov regularisation needs m >= n (under-determined form not provided)");
     hipStream_t st = (hipStream_t)stream;
     auto plan = std::make_unique<lsrn_plan>();
     plan->m = m; plan->n = n; plan->opt = opt; plan->sparse = true;
@@ -643,7 +701,8 @@ lsrn_status lsrn_plan_create_csr(int64_t m, int64_t n, int64_t nnz, const int64_
     tm.mark();
     make_sparse_view(plan->sv, m, n, nnz, rowptr, colind, val, st);
     plan->tall = plan->sv.tall;
-    prepare(plan->tall, plan->sv.K, plan->sv.d, nullptr, &plan->sv, opt, st, tm, plan->pp);
+    prepare(plan->tall, plan->sv.K, plan->sv.d, nullptr, &plan->sv, opt, st, tm, plan->pp,
+            opt.keep_sketch ? &plan->plain : nullptr);
     tm.mark();
     LSRN_HIP(hipStreamSynchronize(st));
     finish_info(plan->tall, plan->pp, IterResult(), opt, info, &tm);
@@ -679,6 +738,47 @@ lsrn_status lsrn_plan_solve(const lsrn_plan *plan, const double *b, double *x,
     LSRN_API_END
 }
 
+lsrn_status lsrn_plan_set_lambda(lsrn_plan *plan, double lambda, lsrn_info *info, void *stream) {
+    LSRN_API_BEGIN
+    LSRN_REQUIRE(plan, "NULL pointer");
+    LSRN_REQUIRE(lambda >= 0.0 && std::isfinite(lambda), "lambda must be >= 0");
+    LSRN_REQUIRE(plan->plain.bytes() > 0, "the plan was created without keep_sketch");
+    hipStream_t st = (hipStream_t)stream;
+    lsrn_options opt = plan->opt;
+    opt.lambda = lambda;
+    const int64_t K = plan->sparse ? plan->sv.K : plan->dv.K;
+    const int64_t d = plan->pp.d, s = plan->pp.s;
+    (void)use_qr_inverse(opt, d);  // d > 8192 needs lambda > 0: rejected before anything changes
+    StageTimer tm(st);
+    tm.mark();
+    DevBuf X((size_t)s * (size_t)d * sizeof(double));
+    LSRN_HIP(hipMemcpyAsync(X.as<double>(), plan->plain.as<double>(), (size_t)s * (size_t)d * sizeof(double),
+                            hipMemcpyDeviceToDevice, st));
+    // Sec. 5: for a new W only the sketch of W is new
+    add_identity_rows(K, d, s, lambda, opt.seed, X.as<double>(), st);
+    tm.mark();
+    form_preconditioner(s, d, X.as<double>(), opt, st, plan->pp);
+    tm.mark();
+    LSRN_HIP(hipStreamSynchronize(st));
+    plan->opt.lambda = lambda;
+    finish_info(plan->tall, plan->pp, IterResult(), opt, info, &tm);
+    LSRN_API_END
+}
+
+lsrn_status lsrn_tune_gamma(const lsrn_info *measured, double tol, double gamma_min,
+                            double gamma_max, double *gamma_out) {
+    LSRN_API_BEGIN
+    LSRN_REQUIRE(measured && gamma_out, "NULL pointer");
+    LSRN_REQUIRE(tol > 0.0 && tol < 1.0, "tol must lie in (0, 1)");
+    LSRN_REQUIRE(gamma_min > 1.0 && gamma_max >= gamma_min, "need 1 < gamma_min <= gamma_max");
+    const lsrn_info &in = *measured;
+    LSRN_REQUIRE(in.d > 0 && in.s > in.d && in.rank > 0 && in.iters > 0,
+                 "the measured solve must report s, d, rank and iterations");
+    *gamma_out = choose_gamma(in.s, in.d, in.rank, in.iters, tol, in.t_sketch_ms, in.t_svd_ms,
+                              in.t_iter_ms, gamma_min, gamma_max);
+    LSRN_API_END
+}
+
 void lsrn_plan_destroy(lsrn_plan *plan) {
     if (!plan) return;
     (void)hipDeviceSynchronize();
@@ -692,8 +792,6 @@ lsrn_status lsrn_sketch_csr(int64_t m, int64_t n, int64_t nnz, const int64_t *ro
     LSRN_REQUIRE(m > 0 && n > 0 && s > 0, "sizes must be positive");
     LSRN_REQUIRE(X, "NULL pointer");
     LSRN_REQUIRE(lambda >= 0.0, "lambda must be >= 0");
-    if (lambda > 0.0 && m < n)
-        fail(LSRN_E_UNSUPPORTED, "Tikhonov regularisation needs m >= n (under-determined form not provided)");
     hipStream_t st = (hipStream_t)stream;
     SparseView v;
     make_sparse_view(v, m, n, nnz, rowptr, colind, val, st);
@@ -710,15 +808,13 @@ lsrn_status lsrn_iterate_csr(int64_t m, int64_t n, int64_t nnz, const int64_t *r
     check_options(opt);
     LSRN_REQUIRE(m > 0 && n > 0, "sizes must be positive");
     LSRN_REQUIRE(b && x && P, "NULL pointer");
-    if (opt.lambda > 0.0 && m < n)
-        fail(LSRN_E_UNSUPPORTED, "Tikhonov regularisation needs m >= n (under-determined form not provided)");
     hipStream_t st = (hipStream_t)stream;
     SparseView v;
     make_sparse_view(v, m, n, nnz, rowptr, colind, val, st);
     LSRN_REQUIRE(r > 0 && r <= v.d && ldp >= r && s > 0, "bad preconditioner shape");
     IterProblem pb;
     pb.tall = v.tall; pb.rows = v.K; pb.cols = v.d; pb.sp = &v;
-    pb.lambda = v.tall ? opt.lambda : 0.0; pb.P = P; pb.ldp = ldp; pb.r = r; pb.s = s;
+    pb.lambda = opt.lambda; pb.P = P; pb.ldp = ldp; pb.r = r; pb.s = s;
     IterResult ir = iterate(pb, b, x, opt, st);
     fill_iter_info(info, s, v.d, r, v.tall, ir);
     if (!ir.converged) {
@@ -858,7 +954,7 @@ size_t lsrn_workspace_bytes_csr(int64_t m, int64_t n, int64_t nnz, const lsrn_op
     const bool tall = m >= n;
     const int64_t K = tall ? m : n, d = tall ? n : m;
     const int64_t s = (int64_t)std::ceil(opt.gamma * (double)d);
-    const int64_t rows = K + (tall && opt.lambda > 0.0 ? d : 0);
+    const int64_t rows = K + (opt.lambda > 0.0 ? d : 0);
     size_t bytes = sparse_view_bytes(m, n, nnz);               // transposed structure
     bytes += (size_t)nnz * 36;                                 // sketch order + sort temporaries
     bytes += (size_t)s * d * sizeof(double);                   // sketch

@@ -356,7 +356,7 @@ void sketch_csr(const SparseView &v, double lambda, int64_t s, uint64_t seed, do
         (void)hipEventDestroy(ev[0]);
         (void)hipEventDestroy(ev[1]);
     }
-    if (v.tall) add_identity_rows(K, d, s, lambda, seed, X, st);
+    add_identity_rows(K, d, s, lambda, seed, X, st);
     LSRN_HIP(hipStreamSynchronize(st));  // before ent / optr are freed
 }
 

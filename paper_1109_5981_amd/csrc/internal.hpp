@@ -181,6 +181,9 @@ struct IterProblem {
     // precision form: FP32 copy of T (leading dimension ldt) read by every
     // sweep; refinement residuals still use the FP64 T
     const float *T32 = nullptr;
+    // sigma_max / sigma_min_kept of the sketch (0: unknown); the precision
+    // form reads the FP64 T from the start when this times 2^-24 exceeds 1/2
+    double kappa_sketch = 0.0;
 };
 
 struct IterResult {
@@ -188,6 +191,7 @@ struct IterResult {
     int64_t refine_steps = 0;
     int64_t refine_iters = 0;
     int64_t fp64_refine_steps = 0;  // precision form: steps whose sweeps read the FP64 A
+    int64_t cs_fallbacks = 0;       // Chebyshev runs whose post-check failed (LSQR restarts)
     bool converged = true;
     double sigma_l = 0.0, sigma_u = 0.0;
     double t_iter_ms = 0.0, t_refine_ms = 0.0;

@@ -316,9 +316,11 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const int block) 
     if (vec) sweep_rows(std::true_type{});
     else sweep_rows(std::false_type{});
 
-    // Tikhonov rows m + k (row vector lambda e_k) of the augmented tall
-    // matrix: handled by the thread that owns column k, in block k % nblocks.
-    if (a.lambda > 0.0 && OP != OP_LSQR_FAT && OP != OP_CS_FAT) {
+    // Tikhonov rows K + k (row vector lambda e_k) of the augmented tall view
+    // ([A; lambda I_n], or [A^T; lambda I_m] for the under-determined form
+    // [A, lambda I_m]): handled by the thread that owns column k, in block
+    // k % nblocks, with the same row-local update as a row of T.
+    if (a.lambda > 0.0) {
 #pragma unroll
         for (int e = 0; e < CPT; ++e) {
             const int col = col_of_w<W>(tid, e);
@@ -329,7 +331,29 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const int block) 
                 if (OP == OP_ATB) c = a.y[row];
                 else if (OP == OP_LSQR_TALL) { c = qv - coef * a.y[row]; a.y[row] = c; }
                 else if (OP == OP_CS_TALL) { c = a.y[row] - coef * qv; a.y[row] = c; }
-                else c = qv;
+                else if (OP == OP_NORMAL) c = qv;
+                else if (OP == OP_LSQR_FAT) {
+                    const double v = a.y[row] * inv_alpha;
+                    c = qv - beta * v;
+                    if (pending == 1) {
+                        a.wv[row] = v;
+                        acc3 += v * v;
+                    } else if (pending == 2) {
+                        const double wo = a.wv[row];
+                        const double xo = a.xv[row] + phi_rho * wo;
+                        const double wn = v - theta_rho * wo;
+                        a.xv[row] = xo;
+                        a.wv[row] = wn;
+                        acc1 += xo * xo;
+                        acc2 += xo * wn;
+                        acc3 += wn * wn;
+                    }
+                    a.y[row] = c;
+                } else {  // OP_CS_FAT
+                    c = a.beta * a.y[row] + qv;
+                    a.y[row] = c;
+                    a.xv[row] += a.alpha * c;
+                }
                 acc0 += c * c;
                 zr[e] += a.lambda * c;
             }
@@ -901,11 +925,14 @@ ax_dd_fat_kernel(const TT *__restrict__ T, int64_t ldt, int64_t rows, int L,
 __global__ void __launch_bounds__(256)
 reduce_dd_kernel(const double *__restrict__ phi, const double *__restrict__ plo, int nb, int L,
                  const double *__restrict__ bvec, double *__restrict__ out_hi,
-                 double *__restrict__ out_lo) {
+                 double *__restrict__ out_lo, double lambda = 0.0,
+                 const double *__restrict__ rho = nullptr) {
     const int col = blockIdx.x * 256 + threadIdx.x;
     if (col >= L) return;
     dd t = {0.0, 0.0};
     for (int b = 0; b < nb; ++b) t = dd_add(t, dd{phi[(int64_t)b * L + col], plo[(int64_t)b * L + col]});
+    // the under-determined Tikhonov form: [A, lambda I] [x; rho] = A x + lambda rho
+    if (rho) t = dd_fma(t, lambda, rho[col]);
     if (bvec) t = dd_add(dd{bvec[col], 0.0}, dd{-t.hi, -t.lo});
     out_hi[col] = t.hi;
     if (out_lo) out_lo[col] = t.lo;
@@ -1276,8 +1303,24 @@ struct Ctx {
     // precision form: sweeps read the FP64 T instead of its FP32 copy
     bool force_f64 = false;
 
+    // event pairs of launches that found the done flag set (no pass over A)
+    std::vector<hipEvent_t> ev_noop;
+
     ~Ctx() {
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        for (hipEvent_t e : ev_noop) (void)hipEventDestroy(e);
+    }
+
+    // Sweeps timed so far; with prof_keep, the launches of a convergence-
+    // checked loop past its last iteration (the rest of its last chunk,
+    // which return at once on the done flag) are left out of the sweep
+    // timing and count.
+    size_t prof_mark() const { return ev.size() / 2; }
+    void prof_keep(size_t mark, int64_t real) {
+        if (!profile) return;
+        const size_t end = std::min(ev.size() / 2, mark + (size_t)std::max<int64_t>(real, 0));
+        for (size_t i = 2 * end; i < ev.size(); ++i) ev_noop.push_back(ev[i]);
+        ev.resize(2 * end);
     }
 
     double sweep_kernel_ms() {
@@ -1451,7 +1494,7 @@ struct Ctx {
         a.nblocks = nblocks;
         a.rows_per_block = rows_per_block; a.w = w; a.zpart = zpart.as<double>();
         a.spart = spart.as<double>(); a.y = y; a.xv = xv; a.wv = wv; a.st = state;
-        a.lambda = pb.tall ? pb.lambda : 0.0; a.alpha = alpha; a.beta = beta;
+        a.lambda = pb.lambda; a.alpha = alpha; a.beta = beta;
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (profile) {
             LSRN_HIP(hipEventCreate(&e0));
@@ -1628,6 +1671,24 @@ void cs_schedule(double sl, double su, double eps, std::vector<double> &al, std:
     }
 }
 
+// The check after a Chebyshev run (Alg. 3), which is exact only when the
+// singular values of the preconditioned operator K lie in [sigma_L,
+// sigma_U] -- Theorem 3 gives that with a probability, not always.  Within
+// the bounds the gradient of the normal equations after the run is the
+// Chebyshev residual polynomial applied to the starting one, of norm at
+// most eps times it (tall: g = K^T r against g0 = K^T b^; fat: the residual
+// of the consistent K x = c against c).  The run passes when
+//   ||g|| <= 2 max(eps, 2^-27) ||g0||;
+// the floor 2^-27 (about sqrt(u)) stays above the rounding of the products
+// K y = A (N y), whose relative size grows with kappa(A), while a run
+// outside the bounds grows the gradient instead of shrinking it.
+bool cs_passes(double gn, double g0, double eps) {
+    const double floor_rel = std::ldexp(1.0, -27);
+    return std::isfinite(gn) && gn <= 2.0 * std::max(eps, floor_rel) * g0;
+}
+
+double host_norm(const double *d, int64_t n, hipStream_t st);
+
 constexpr int CHUNK = 8;  // iterations enqueued between convergence checks
 
 // ---- tall: K = [A; lambda I] N
@@ -1662,6 +1723,7 @@ struct TallSolver {
     }
 
     int64_t lsqr(int64_t maxiter, double tol, bool &converged) {
+        const size_t mk = cx.prof_mark();
         cx.reset_state((int)maxiter);
         at(ulong.as<double>());
         lsqr_tall_init_kernel<<<1, SNT, 0, cx.st>>>(t.as<double>(), r, v.as<double>(),
@@ -1683,16 +1745,23 @@ struct TallSolver {
             });
             h = cx.host_state();
         }
+        cx.prof_keep(mk, 1 + h.iters);  // the start sweep and one per iteration
         converged = h.converged != 0;
         return h.iters;
     }
 
-    int64_t cs(double sl, double su, double eps) {
+    // Alg. 3 on K y = b^ (K = [A; lambda I] N).  With `checked`, the result
+    // is tested afterwards (cs_passes) and, if the test fails, LSQR is
+    // restarted from it; `fell_back` reports that.
+    int64_t cs(const double *b, double sl, double su, double eps, bool checked, int64_t maxiter,
+               double tol, bool &converged, bool &fell_back) {
         std::vector<double> al, be;
         cs_schedule(sl, su, eps, al, be);
         cx.reset_state(0);
         // r = b^, t = K^T r; v = 0, y = 0
+        const double bn = checked ? host_norm(ulong.as<double>(), M, cx.st) : 0.0;
         at(ulong.as<double>());
+        const double g0 = checked ? host_norm(t.as<double>(), r, cx.st) : 0.0;
         fill_kernel<<<grid1(r), 256, 0, cx.st>>>(r, 0.0, v.as<double>());
         fill_kernel<<<grid1(r), 256, 0, cx.st>>>(r, 0.0, y.as<double>());
         for (size_t k = 0; k < al.size(); ++k) {
@@ -1704,7 +1773,32 @@ struct TallSolver {
             if (!last) cx.gemv(cx.Ptp, cx.L, r, cx.L, cx.z.as<double>(), t.as<double>());
         }
         LSRN_HIP(hipGetLastError());
-        return (int64_t)al.size();
+        converged = true;
+        fell_back = false;
+        const int64_t iters = (int64_t)al.size();
+        if (!checked) return iters;
+        // the last sweep left z = T^T r (r = b^ - K y, the recurrence's
+        // residual in ulong) and ||r||^2 in acc0: g = K^T r costs one gemv
+        cx.gemv(cx.Ptp, cx.L, r, cx.L, cx.z.as<double>(), t.as<double>(), false);
+        const double gn = host_norm(t.as<double>(), r, cx.st);
+        if (cs_passes(gn, g0, eps)) return iters;
+        const double rn = std::sqrt(std::max(0.0, cx.host_state().acc[0]));
+        // LSQR on K dy = r from dy = 0 (ulong holds r), then y += dy; a
+        // divergent run (residual above ||b^||) is dropped: y = 0, r = b^
+        fell_back = true;
+        DevBuf ycs((size_t)r * sizeof(double));
+        if (std::isfinite(rn) && rn <= bn) {
+            LSRN_HIP(hipMemcpyAsync(ycs.as<double>(), y.as<double>(), (size_t)r * sizeof(double),
+                                    hipMemcpyDeviceToDevice, cx.st));
+        } else {
+            fill_kernel<<<grid1(r), 256, 0, cx.st>>>(r, 0.0, ycs.as<double>());
+            load_rhs(b);
+        }
+        const int64_t more = lsqr(maxiter, tol, converged);
+        axpby_kernel<<<grid1(r), 256, 0, cx.st>>>(r, 1.0, ycs.as<double>(), 1.0, y.as<double>());
+        LSRN_HIP(hipGetLastError());
+        LSRN_HIP(hipStreamSynchronize(cx.st));  // before ycs is freed
+        return iters + more;
     }
 
     void x_from_y(double *x) { cx.gemv(cx.pb.P, cx.pb.ldp, cx.L, r, y.as<double>(), x, false); }
@@ -1717,8 +1811,9 @@ struct FatSolver {
     DevBuf vt, wdir, u, t, wM;
     double *x;
 
+    // xout holds rows (+ L with Tikhonov rows) entries: x, or x^ = [x; rho]
     FatSolver(Ctx &c, double *xout) : cx(c), x(xout) {
-        n = cx.pb.rows;
+        n = cx.pb.rows + (cx.pb.lambda > 0.0 ? cx.L : 0);
         r = cx.pb.r;
         vt.alloc((size_t)n * sizeof(double));
         wdir.alloc((size_t)n * sizeof(double));
@@ -1731,6 +1826,7 @@ struct FatSolver {
     int64_t lsqr(int64_t maxiter, double tol, bool &converged) {
         fill_kernel<<<grid1(n), 256, 0, cx.st>>>(n, 0.0, x);
         fill_kernel<<<grid1(n), 256, 0, cx.st>>>(n, 0.0, vt.as<double>());
+        const size_t mk = cx.prof_mark();
         cx.reset_state((int)maxiter);
         lsqr_fat_init_kernel<<<1, SNT, 0, cx.st>>>(t.as<double>(), r, u.as<double>(), cx.state);
         // start sweep: v~_1 = A^T M u_1
@@ -1754,14 +1850,18 @@ struct FatSolver {
             });
             h = cx.host_state();
         }
+        cx.prof_keep(mk, 1 + h.iters);  // the start sweep and one per iteration
         lsqr_fat_finish_kernel<<<grid1(n), 256, 0, cx.st>>>(n, x, wdir.as<double>(), cx.state);
         LSRN_HIP(hipGetLastError());
         converged = h.converged != 0;
         return h.iters;
     }
 
-    // Alg. 3 on M^T A x = c (c in t): x, v long; residual short.
-    int64_t cs(double sl, double su, double eps) {
+    // Alg. 3 on M^T A x = c (c in t): x, v long; residual short.  With
+    // `checked`, the short residual is tested afterwards (cs_passes) and, if
+    // the test fails, LSQR is restarted from x; `fell_back` reports that.
+    int64_t cs(double sl, double su, double eps, bool checked, int64_t maxiter, double tol,
+               bool &converged, bool &fell_back) {
         std::vector<double> al, be;
         cs_schedule(sl, su, eps, al, be);
         cx.reset_state(0);
@@ -1770,6 +1870,11 @@ struct FatSolver {
         double *res = u.as<double>();
         LSRN_HIP(hipMemcpyAsync(res, t.as<double>(), (size_t)r * sizeof(double),
                                 hipMemcpyDeviceToDevice, cx.st));
+        const double c0 = checked ? host_norm(res, r, cx.st) : 0.0;
+        DevBuf csave(checked ? (size_t)r * sizeof(double) : 0);
+        if (checked)
+            LSRN_HIP(hipMemcpyAsync(csave.as<double>(), res, (size_t)r * sizeof(double),
+                                    hipMemcpyDeviceToDevice, cx.st));
         for (size_t k = 0; k < al.size(); ++k) {
             cx.gemv(cx.pb.P, cx.pb.ldp, cx.L, r, res, wM.as<double>());
             cx.sweep(OP_CS_FAT, wM.as<double>(), vt.as<double>(), x, nullptr, al[k], be[k]);
@@ -1777,7 +1882,31 @@ struct FatSolver {
             axpby_kernel<<<grid1(r), 256, 0, cx.st>>>(r, -al[k], t.as<double>(), 1.0, res);
         }
         LSRN_HIP(hipGetLastError());
-        return (int64_t)al.size();
+        converged = true;
+        fell_back = false;
+        const int64_t iters = (int64_t)al.size();
+        if (!checked) return iters;
+        // K x = c is consistent: the residual c - K x (by the recurrence, in
+        // res) is what the Chebyshev polynomial bounds
+        const double rn = host_norm(res, r, cx.st);
+        if (cs_passes(rn, c0, eps)) return iters;
+        // LSQR on K dx = res from dx = 0, then x += dx; a divergent run
+        // (residual above ||c||) is dropped: x = 0 and LSQR solves K x = c
+        fell_back = true;
+        DevBuf xcs((size_t)n * sizeof(double));
+        const bool keep = std::isfinite(rn) && rn <= c0;
+        if (keep)
+            LSRN_HIP(hipMemcpyAsync(xcs.as<double>(), x, (size_t)n * sizeof(double),
+                                    hipMemcpyDeviceToDevice, cx.st));
+        else
+            fill_kernel<<<grid1(n), 256, 0, cx.st>>>(n, 0.0, xcs.as<double>());
+        LSRN_HIP(hipMemcpyAsync(t.as<double>(), keep ? res : csave.as<double>(),
+                                (size_t)r * sizeof(double), hipMemcpyDeviceToDevice, cx.st));
+        const int64_t more = lsqr(maxiter, tol, converged);
+        axpby_kernel<<<grid1(n), 256, 0, cx.st>>>(n, 1.0, xcs.as<double>(), 1.0, x);
+        LSRN_HIP(hipGetLastError());
+        LSRN_HIP(hipStreamSynchronize(cx.st));  // before xcs is freed
+        return iters + more;
     }
 };
 
@@ -1844,8 +1973,21 @@ IterResult iterate_on(const IterProblem &pb, const double *b, double *x, const l
         ts.load_rhs(b);
         // the precision form's main solve runs on fl32(A): no point in going
         // below 1e-8 before the refinement
-        const double tol_main = (pb.T && pb.T32) ? std::max(opt.tol, 1e-8) : opt.tol;
-        res.iters = cs ? ts.cs(sl, su, opt.tol) : ts.lsqr(maxiter, tol_main, conv);
+        // the precision form: FP32 sweeps solve the problem of fl32(A), and
+        // refinement with them contracts only while kappa(A) 2^-24 << 1.
+        // The sketch's sigma_max / sigma_min_kept (at most about
+        // (1 + sqrt(r/s)) / (1 - sqrt(r/s)) times kappa(A), Sec. 4.2) over
+        // 2^24 above 1/2 means they cannot: the sweeps then read the FP64 A
+        // from the start and only the sketch stays BF16.
+        if (pb.T && pb.T32 && pb.kappa_sketch * std::ldexp(1.0, -24) > 0.5) cx.force_f64 = true;
+        const double tol_main = (pb.T && pb.T32 && !cx.force_f64) ? std::max(opt.tol, 1e-8) : opt.tol;
+        bool fb = false;
+        // a restart after a failed check gets a cap not taken from the bounds
+        // the check found wrong
+        const int64_t cap_fb = opt.max_iter > 0 ? opt.max_iter : 4 * maxiter;
+        res.iters = cs ? ts.cs(b, sl, su, opt.tol, true, cap_fb, opt.tol, conv, fb)
+                       : ts.lsqr(maxiter, tol_main, conv);
+        res.cs_fallbacks += fb ? 1 : 0;
         ts.x_from_y(x);
         LSRN_HIP(hipEventRecord(e1, st));
         LSRN_HIP(hipStreamSynchronize(st));
@@ -1860,6 +2002,7 @@ IterResult iterate_on(const IterProblem &pb, const double *b, double *x, const l
             // the sparse normal-equation sweep stores T p here for its column pass
             DevBuf ybuf(pb.sp ? (size_t)(pb.rows + L) * sizeof(double) : 0);
             GraphExec cg_graph;  // the CG chunk keeps its buffers across refinement steps
+            bool refine_conv = true;
             double dn_prev = 0.0;
             // the precision form: once its FP32 sweeps stop shrinking the
             // corrections (or the step budget is spent) the refinement goes on
@@ -1889,6 +2032,7 @@ IterResult iterate_on(const IterProblem &pb, const double *b, double *x, const l
                 cg_init_kernel<<<1, SNT, 0, st>>>(c.as<double>(), r, zc.as<double>(), rc.as<double>(),
                                                   pc.as<double>(), opt.refine_tol, cg_max, cx.state);
                 State hs = cx.host_state();
+                const size_t mk = cx.prof_mark();
                 while (!hs.done) {
                     cx.run_chunk(cg_graph.g, [&] {
                         for (int k = 0; k < CHUNK; ++k) {
@@ -1903,7 +2047,9 @@ IterResult iterate_on(const IterProblem &pb, const double *b, double *x, const l
                     });
                     hs = cx.host_state();
                 }
+                cx.prof_keep(mk, hs.iters);
                 res.refine_iters += hs.iters;
+                refine_conv = hs.converged != 0;
                 cx.gemv(pb.P, pb.ldp, L, r, zc.as<double>(), dx.as<double>(), false);
                 axpby_kernel<<<grid1(L), 256, 0, st>>>(L, 1.0, dx.as<double>(), 1.0, x);
                 LSRN_HIP(hipGetLastError());
@@ -1935,16 +2081,31 @@ IterResult iterate_on(const IterProblem &pb, const double *b, double *x, const l
                 // (the floor of the inner arithmetic is reached)
                 if (dn <= 1e-15 * xn || stalled) break;
             }
+            // with refinement the answer is the refined one: the solve has
+            // converged when the last correction's solve met its rule, even
+            // if the main LSQR stopped at its cap (at kappa(A) near 1/u^(1/2)
+            // its normal-equation test can sit at the rounding floor)
+            if (!(pb.T && pb.T32)) conv = refine_conv;
         }
         LSRN_HIP(hipStreamSynchronize(st));  // before the solver's buffers are freed
     } else {
-        FatSolver fs(cx, x);
+        // with lambda > 0 (the under-determined Tikhonov form [A, lambda I_m],
+        // Sec. 5) the unknown is x^ = [x; rho], rows + L long; x is its head
+        const int64_t nl = pb.rows + (pb.lambda > 0.0 ? L : 0);
+        DevBuf xhat(nl > pb.rows ? (size_t)nl * sizeof(double) : 0);
+        double *const xh = nl > pb.rows ? xhat.as<double>() : x;
+        FatSolver fs(cx, xh);
         // c = M^T b
         cx.gemv(cx.Ptp, L, r, L, b, fs.t.as<double>(), false);
-        res.iters = cs ? fs.cs(sl, su, opt.tol) : fs.lsqr(maxiter, opt.tol, conv);
+        bool fb = false;
+        const int64_t cap_fb = opt.max_iter > 0 ? opt.max_iter : 4 * maxiter;
+        res.iters = cs ? fs.cs(sl, su, opt.tol, true, cap_fb, opt.tol, conv, fb)
+                       : fs.lsqr(maxiter, opt.tol, conv);
+        res.cs_fallbacks += fb ? 1 : 0;
         LSRN_HIP(hipEventRecord(e1, st));
         if (opt.refine > 0) {
-            const int64_t n = pb.rows;
+            const int64_t n = nl;
+            double *const x = xh;
             const size_t zlen = pb.sp ? (size_t)L : (size_t)cx.nblocks * L;
             DevBuf zhi(zlen * sizeof(double)), zlo(zlen * sizeof(double));
             DevBuf thi((size_t)L * sizeof(double)), tlo((size_t)L * sizeof(double));
@@ -1952,8 +2113,9 @@ IterResult iterate_on(const IterProblem &pb, const double *b, double *x, const l
             double dn_prev = 0.0;
             for (int step = 0; step < opt.refine; ++step) {
                 if (pb.sp) {
+                    // A x (+ lambda rho) per row of A, in double-double
                     csr_col_pass_dd_kernel<<<(unsigned)ceil_div(L, CCP_NT / 64), CCP_NT, 0, st>>>(
-                        pb.sp->cols, x, nullptr, 0.0, pb.rows, zhi.as<double>(), zlo.as<double>());
+                        pb.sp->cols, x, nullptr, pb.lambda, pb.rows, zhi.as<double>(), zlo.as<double>());
                 } else {
                     if (cx.cpt == 2) launch_ax_fat<2>(cx, x, zhi.as<double>(), zlo.as<double>());
                     else if (cx.cpt == 4) launch_ax_fat<4>(cx, x, zhi.as<double>(), zlo.as<double>());
@@ -1961,10 +2123,11 @@ IterResult iterate_on(const IterProblem &pb, const double *b, double *x, const l
                     else launch_ax_fat<16>(cx, x, zhi.as<double>(), zlo.as<double>());
                 }
                 LSRN_HIP(hipGetLastError());
+                const bool add_rho = !pb.sp && pb.lambda > 0.0;
                 reduce_dd_kernel<<<(unsigned)ceil_div(L, 256), 256, 0, st>>>(
                     zhi.as<double>(), zlo.as<double>(), pb.sp ? 1 : cx.nblocks, (int)L, b,
-                    thi.as<double>(), tlo.as<double>());
-                // e = M^T (b - A x) with dd accumulation
+                    thi.as<double>(), tlo.as<double>(), pb.lambda, add_rho ? x + pb.rows : nullptr);
+                // e = M^T (b - A x - lambda rho) with dd accumulation
                 gemv_t_dd_kernel<<<(unsigned)ceil_div(r, 4), 256, 0, st>>>(
                     pb.P, pb.ldp, L, r, thi.as<double>(), tlo.as<double>(), fs.t.as<double>());
                 LSRN_HIP(hipGetLastError());
@@ -1974,7 +2137,11 @@ IterResult iterate_on(const IterProblem &pb, const double *b, double *x, const l
                 // the correction needs only refine_tol relative accuracy:
                 // the error left after it is that times the error before
                 const double ctol = std::max(opt.tol, opt.refine_tol);
-                res.refine_iters += cs ? fs.cs(sl, su, ctol) : fs.lsqr(maxiter, ctol, c2);
+                bool fb2 = false;
+                res.refine_iters += cs ? fs.cs(sl, su, ctol, true, cap_fb, ctol, c2, fb2)
+                                       : fs.lsqr(maxiter, ctol, c2);
+                res.cs_fallbacks += fb2 ? 1 : 0;
+                conv = c2;  // the refined answer: its last correction's solve decides
                 // fs wrote the correction into x; x = xsave + dx
                 const double dn = host_norm(x, n, st);
                 axpby_kernel<<<grid1(n), 256, 0, st>>>(n, 1.0, xsave.as<double>(), 1.0, x);
@@ -1987,6 +2154,8 @@ IterResult iterate_on(const IterProblem &pb, const double *b, double *x, const l
                 dn_prev = dn;
             }
         }
+        if (xh != x)
+            LSRN_HIP(hipMemcpyAsync(x, xh, (size_t)pb.rows * sizeof(double), hipMemcpyDeviceToDevice, st));
         LSRN_HIP(hipStreamSynchronize(st));  // before the solver's buffers are freed
     }
     LSRN_HIP(hipEventRecord(e2, st));

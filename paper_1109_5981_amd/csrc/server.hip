@@ -168,6 +168,10 @@ lsrn_status lsrn_server_submit_dense(lsrn_server *srv, int64_t m, int64_t n, con
     r->m = m; r->n = n; r->A = A; r->lda = lda; r->layout = layout; r->b = b; r->x = x;
     if (opt) r->opt = *opt;
     else lsrn_default_options(&r->opt);
+    // served solves never tune: timing launch shapes while other solves
+    // share the device would be noise, and a new table entry would change
+    // the summation order of later requests of the same shape
+    r->opt.autotune = 0;
     r->bytes = lsrn_workspace_bytes(m, n, layout, &r->opt);
     if (r->opt.precision == LSRN_PREC_MIXED) r->bytes += (size_t)m * (size_t)n * sizeof(float);
     return enqueue(srv, std::move(r), ticket);
@@ -185,6 +189,7 @@ lsrn_status lsrn_server_submit_csr(lsrn_server *srv, int64_t m, int64_t n, int64
     r->b = b; r->x = x;
     if (opt) r->opt = *opt;
     else lsrn_default_options(&r->opt);
+    r->opt.autotune = 0;  // as for dense requests
     r->bytes = lsrn_workspace_bytes_csr(m, n, nnz, &r->opt);
     return enqueue(srv, std::move(r), ticket);
 }

@@ -33,7 +33,7 @@ class Options(C.Structure):
                 ("rcond", C.c_double), ("t_margin", C.c_double), ("refine_tol", C.c_double),
                 ("seed", C.c_uint64), ("max_iter", C.c_int64), ("method", C.c_int32),
                 ("refine", C.c_int32), ("profile", C.c_int32), ("precond", C.c_int32),
-                ("precision", C.c_int32), ("autotune", C.c_int32)]
+                ("precision", C.c_int32), ("autotune", C.c_int32), ("keep_sketch", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -46,7 +46,7 @@ class Info(C.Structure):
                 ("t_sketch_kernel_ms", C.c_double), ("t_sweep_kernel_ms", C.c_double),
                 ("sketch_kernels", C.c_int64), ("sweep_kernels", C.c_int64),
                 ("t_jacobi_kernel_ms", C.c_double), ("jacobi_kernels", C.c_int64),
-                ("fp64_refine_steps", C.c_int64)]
+                ("fp64_refine_steps", C.c_int64), ("cs_fallbacks", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -65,7 +65,7 @@ SERVER_EXPORTS = ["lsrn_server_create", "lsrn_server_submit_dense", "lsrn_server
                   "lsrn_server_destroy"]
 EXPORTS = EXPORTS + SERVER_EXPORTS
 PLAN_EXPORTS = ["lsrn_plan_create_dense", "lsrn_plan_create_csr", "lsrn_plan_solve",
-                "lsrn_plan_destroy"]
+                "lsrn_plan_destroy", "lsrn_plan_set_lambda", "lsrn_tune_gamma"]
 EXPORTS = EXPORTS + PLAN_EXPORTS + ["lsrn_solve_op", "lsrn_tune_export", "lsrn_tune_import",
                                      "lsrn_tune_clear", "lsrn_solve_dense_f32"]
 # lsrn_apply_fn: (ctx, trans, k, in, ldin, out, ldout, stream) -> int
@@ -132,6 +132,8 @@ def lib():
                                            C.POINTER(C.c_void_p), C.POINTER(Info), P]
         L.lsrn_plan_solve.argtypes = [P, P, P, C.POINTER(Options), C.POINTER(Info), P]
         L.lsrn_plan_destroy.argtypes = [P]
+        L.lsrn_plan_set_lambda.argtypes = [P, D, C.POINTER(Info), P]
+        L.lsrn_tune_gamma.argtypes = [C.POINTER(Info), D, D, D, C.POINTER(C.c_double)]
         L.lsrn_plan_destroy.restype = None
         L.lsrn_solve_op.argtypes = [I64, I64, APPLY_FN, P, P, P, C.POINTER(Options),
                                     C.POINTER(Info), P]
@@ -257,7 +259,7 @@ def sketch_dense(A: torch.Tensor, s: int, seed: int = 0, lam: float = 0.0,
     tensor holding X column-major (so `.T` is X)."""
     _dev_f64(A, "A")
     m, n, lda = _layout_dims(A, layout)
-    d = n if (m >= n or lam > 0) else m
+    d = n if m >= n else m
     X = torch.empty((d, s), dtype=torch.float64, device=A.device)
     _check(lib().lsrn_sketch_dense(m, n, A.data_ptr(), lda, layout, lam, s, seed, X.data_ptr(),
                                    _stream()))
@@ -269,7 +271,7 @@ def sketch_dense_bf16(A: torch.Tensor, s: int, seed: int = 0, lam: float = 0.0,
     """The precision form's sketch bf16(G) fl32(T), as sketch_dense."""
     _dev_f64(A, "A")
     m, n, lda = _layout_dims(A, layout)
-    d = n if (m >= n or lam > 0) else m
+    d = n if m >= n else m
     X = torch.empty((d, s), dtype=torch.float64, device=A.device)
     _check(lib().lsrn_sketch_dense_bf16(m, n, A.data_ptr(), lda, layout, lam, s, seed,
                                         X.data_ptr(), _stream()))
@@ -496,6 +498,19 @@ class Plan:
         out["status"] = int(st)
         return x, out
 
+    def set_lambda(self, lam: float) -> dict:
+        """lsrn_plan_set_lambda: the preconditioner for a new Tikhonov weight
+        from the kept sketch (the plan needs keep_sketch=1).  Returns info."""
+        if self._h is None:
+            raise RuntimeError("plan is closed")
+        info = Info()
+        _check(lib().lsrn_plan_set_lambda(self._h, float(lam), C.byref(info), _stream()))
+        self._opts["lam"] = float(lam)
+        self._opts.pop("lambda", None)
+        self._opts.pop("lambda_", None)
+        self.info = info.as_dict()
+        return self.info
+
     def close(self):
         if self._h is not None:
             lib().lsrn_plan_destroy(self._h)
@@ -506,6 +521,19 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def tune_gamma(info: dict, tol: float = 1e-14, gamma_min: float = 1.25,
+               gamma_max: float = 4.0) -> float:
+    """lsrn_tune_gamma: the modelled best oversampling factor from the info
+    of a measured solve (host arithmetic only)."""
+    inf = Info()
+    for name, _ in Info._fields_:
+        if name in info:
+            setattr(inf, name, info[name])
+    g = C.c_double()
+    _check(lib().lsrn_tune_gamma(C.byref(inf), tol, gamma_min, gamma_max, C.byref(g)))
+    return g.value
 
 
 class Server:

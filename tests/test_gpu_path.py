@@ -335,9 +335,15 @@ def test_edge_cases(L, orc):
     with pytest.raises(L.LSRNError) as e:
         L.solve_dense(dev(A), dev(b), gamma=1.0)
     assert e.value.status == 1
+    # Tikhonov on an under-determined A (8 x 9): Sec. 5's form [A, lambda I_m]
+    Af = A.T.copy()
+    x, info = L.solve_dense(dev(Af), dev(np.ones(8)), lam=0.1, refine=2)
+    x_cf = Af.T @ np.linalg.solve(Af @ Af.T + 0.01 * np.eye(8), np.ones(8))
+    assert info["tall"] == 0
+    np.testing.assert_allclose(host(x), x_cf, rtol=1e-10, atol=1e-12)
     with pytest.raises(L.LSRNError) as e:
-        L.solve_dense(dev(A.T.copy()), dev(np.ones(8)), lam=0.1)
-    assert e.value.status == 5
+        L.solve_dense(dev(A), dev(b), t_margin=float("nan"))
+    assert e.value.status == 1
 
 
 @pytest.mark.parametrize("method", [0, 1])
@@ -358,3 +364,30 @@ def test_graph_replays_match_eager_launches(L, dense_workload, method):
         s.synchronize()
         np.testing.assert_array_equal(host(x1), ref)
         _ = A_d.sum().item()  # eager work between replays
+
+
+@pytest.mark.parametrize("fat", [False, True])
+def test_chebyshev_check_restarts_lsqr(L, orc, fat):
+    """A Chebyshev run outside its bounds (margin t = -4 squeezes [sigma_L,
+    sigma_U] inside the spectrum of A N) fails the check after the run and
+    LSQR continues, on the GPU as in the oracle; the answer is the
+    oracle's.  With the default margin no run falls back."""
+    Pd = workloads.dense_problem(1200, 60, smin=1e-3, seed=41)
+    if fat:
+        M = orc.Matrix.dense_colmajor(Pd.A)
+        b = workloads.rhs_gauss(60, 41)
+        At, layout = Pd.A, 1
+    else:
+        M = orc.Matrix.dense(Pd.A)
+        b = workloads.rhs_gauss(1200, 41)
+        At, layout = Pd.A, 0
+    ref = orc.lsrn_solve(M, b, seed=2, refine=3)
+    A_d, b_d = dev(At), dev(b)
+    x0, i0 = L.solve_dense(A_d, b_d, layout=layout, method=1, seed=3)
+    assert i0["cs_fallbacks"] == 0 and i0["converged"] == 1
+    x1, i1 = L.solve_dense(A_d, b_d, layout=layout, method=1, seed=3, t_margin=-4.0)
+    orc_bad = orc.lsrn_solve(M, b, seed=3, method=orc.CS, t_margin=-4.0)
+    assert i1["cs_fallbacks"] == 1 == orc_bad.cs_fallbacks
+    assert i1["converged"] == 1
+    assert rel(host(x1), ref.x) <= 1e-10
+    assert rel(host(x0), ref.x) <= 1e-10

@@ -81,3 +81,48 @@ def test_plan_reaches_oracle_solution(L, orc):
         e = np.linalg.norm(host(x) - ref.x) / np.linalg.norm(ref.x)
         assert info["converged"] == 1 and e <= 1e-10
     plan.close()
+
+
+@pytest.mark.parametrize("shape", ["tall", "fat", "csr"])
+def test_regularisation_path_reuses_the_sketch(L, orc, shape):
+    """Sec. 5, closing paragraph: one sketch of A serves a whole path of
+    Tikhonov weights; for each lambda only lambda G(:, K .. K+d-1) is added
+    and the SVD and iterations run again.  Each solve on the path equals a
+    fresh whole solve with that lambda bit for bit, and the oracle's."""
+    rng = np.random.default_rng(5)
+    if shape == "csr":
+        S = workloads.sparse_problem(5000, 140, per_row=6, n_dense=3, fill=0.2, seed=74)
+        A = L.Csr.from_host(S.m, S.n, S.rowptr, S.colind, S.val)
+        M_of = lambda lam: orc.Matrix.csr(S.m, S.n, S.rowptr, S.colind, S.val, lam=lam)
+        m = S.m
+        make = lambda **o: L.Plan.csr(A, **o)
+        fresh = lambda b, **o: L.solve_csr(A, b, **o)
+    else:
+        P = workloads.dense_problem(3000, 110, smin=1e-6, seed=75)
+        layout = 1 if shape == "fat" else 0          # fat: 110 x 3000 stored column-major
+        A = dev(P.A)
+        m = 110 if shape == "fat" else 3000
+        M_of = (lambda lam: orc.Matrix.dense_colmajor(P.A, lam=lam)) if shape == "fat" else \
+               (lambda lam: orc.Matrix.dense(P.A, lam=lam))
+        make = lambda **o: L.Plan.dense(A, layout=layout, **o)
+        fresh = lambda b, **o: L.solve_dense(A, b, layout=layout, **o)
+    b_h = rng.standard_normal(m)
+    b = dev(b_h)
+    plan = make(seed=3, refine=2, keep_sketch=1)
+    for lam in (1e-1, 1e-3, 0.0):
+        info = plan.set_lambda(lam)
+        x1, i1 = plan.solve(b)
+        x2, i2 = fresh(b, seed=3, refine=2, lam=lam)
+        assert np.array_equal(host(x1), host(x2)), lam
+        assert i1["rank"] == i2["rank"] == info["rank"]
+        ref = orc.lsrn_solve(M_of(lam), b_h, seed=1, refine=3)
+        e = np.linalg.norm(host(x1) - ref.x) / np.linalg.norm(ref.x)
+        print(f"{shape} lambda={lam:g}: rank={info['rank']} rel_err_vs_oracle={e:.2e}")
+        assert e <= 1e-10
+    plan.close()
+    # without keep_sketch the path is refused
+    p2 = make(seed=3)
+    with pytest.raises(L.LSRNError) as e:
+        p2.set_lambda(1e-2)
+    assert e.value.status == 1
+    p2.close()

@@ -44,12 +44,33 @@ def mix(L):
                                     seed=100 + i)
         A = P.A if layout == 0 else P.A                       # tall storage (rows >= cols)
         b = workloads.rhs_gauss(m, 100 + i)
+        # one request asks for autotuning: a served solve never tunes, so its
+        # result still equals the lone solve's without tuning
         reqs.append(("dense", dev(A), dev(b), dict(layout=layout, precision=prec, method=meth,
-                                                     seed=7 + i, refine=10 if prec == "mixed" else 3)))
+                                                     seed=7 + i, refine=10 if prec == "mixed" else 3,
+                                                     autotune=1 if i == 4 else 0),
+                     (orc_dense(A, layout), b)))
     S = workloads.sparse_problem(20000, 150, per_row=12, n_dense=3, fill=0.2, seed=9)
+    b = workloads.rhs_gauss(S.m, 9)
     reqs.append(("csr", L.Csr.from_host(S.m, S.n, S.rowptr, S.colind, S.val),
-                 dev(workloads.rhs_gauss(S.m, 9)), dict(lam=1e-3, seed=3, refine=2)))
+                 dev(b), dict(lam=1e-3, seed=3, refine=2),
+                 (("csr", S), b)))
     return reqs
+
+
+def orc_dense(A, layout):
+    return ("colmajor" if layout == 1 else "dense", A)
+
+
+def oracle_ref(orc, spec, b, lam):
+    kind, A = spec
+    if kind == "csr":
+        M = orc.Matrix.csr(A.m, A.n, A.rowptr, A.colind, A.val, lam=lam)
+    elif kind == "colmajor":
+        M = orc.Matrix.dense_colmajor(A, lam=lam)
+    else:
+        M = orc.Matrix.dense(A, lam=lam)
+    return orc.lsrn_solve(M, b, seed=1, refine=3).x
 
 
 def solve_alone(L, kind, A, b, opts):
@@ -60,13 +81,23 @@ def solve_alone(L, kind, A, b, opts):
     return host(x), info
 
 
-def test_results_alone_equal_results_in_mix(L):
+def test_results_alone_equal_results_in_mix(L, orc):
+    """Each served result equals the same request solved alone bit for bit,
+    and every one is within 1e-10 of the oracle's reference-mode solution
+    (FP64 requests refined three steps; precision-form requests refined to
+    their FP64 answer)."""
     reqs = mix(L)
-    alone = [solve_alone(L, *r)[0] for r in reqs]
+    L.tune_clear()
+    alone = [solve_alone(L, kind, A, b, {k: v for k, v in o.items() if k != "autotune"})[0]
+             for kind, A, b, o, _ in reqs]
+    for (kind, A, b, opts, (spec, b_h)), x in zip(reqs, alone):
+        ref = oracle_ref(orc, spec, b_h, opts.get("lam", 0.0))
+        e = np.linalg.norm(x - ref) / np.linalg.norm(ref)
+        assert e <= 1e-10, (kind, opts, e)
     with L.Server(hbm_budget_bytes=64 << 30, streams=4) as srv:
         for rep in range(2):
             tickets = []
-            for kind, A, b, opts in reqs:
+            for kind, A, b, opts, _ in reqs:
                 if kind == "dense":
                     tickets.append(srv.submit_dense(A, b, **opts))
                 else:
@@ -75,6 +106,7 @@ def test_results_alone_equal_results_in_mix(L):
                 x, info, tm = srv.wait(t, allow_not_converged=True)
                 np.testing.assert_array_equal(host(x), ref)
                 assert tm["latency_ms"] >= tm["run_ms"] >= 0.0
+    assert L.tune_export() == ""     # no served request recorded a tuned shape
 
 
 def test_admission_respects_budget(L):

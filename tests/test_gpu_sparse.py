@@ -200,11 +200,12 @@ def test_solve_csr_edge_cases(L, orc):
     with pytest.raises(L.LSRNError) as e:
         L.solve_csr(bad, dev(np.ones(3)))
     assert e.value.status == 1
-    # Tikhonov on an under-determined A is not provided
+    # Tikhonov on an under-determined A: Sec. 5's form [A, lambda I_m]
     Sf = workloads.sparse_problem(10, 50, per_row=5, n_dense=0, fill=0.0, seed=2)
-    with pytest.raises(L.LSRNError) as e:
-        L.solve_csr(gcsr(L, Sf), dev(np.ones(10)), lam=0.1)
-    assert e.value.status == 5
+    Af = Sf.to_dense()
+    x, info = L.solve_csr(gcsr(L, Sf), dev(np.ones(10)), lam=0.1, refine=2)
+    x_cf = Af.T @ np.linalg.solve(Af @ Af.T + 0.01 * np.eye(10), np.ones(10))
+    assert info["tall"] == 0 and rel(host(x), x_cf) < 1e-10
 
 
 # ------------------------------------------------ full size, 2e6 x 2e4
@@ -284,3 +285,31 @@ def test_sketch_csr_full_size_sampled(L, orc, sparse_full):
         got = X[c, i].item()
         bound = 2 * (S.m + S.n) * eps * (np.abs(g) @ np.abs(vals) + lam) + 1e-300
         assert abs(got - ref) <= bound, (i, c, got, ref)
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_tnimg_replica_vs_oracle(L, orc, method):
+    """The tnimg stand-in (Sec. 6.5's matrices: 1024 DCT rows, 20 or 21
+    nonzeros per column) at 1024 x 30000: the under-determined CSR path
+    (Alg. 2 on the transposed structure) against the oracle's reference mode
+    with a preconditioner from LAPACK's SVD of a numpy Gaussian sketch (an
+    input taken from neither side)."""
+    S = workloads.tnimg_like(30000, seed=16)
+    T = S.to_dense().T.copy()                          # tall view, 30000 x m
+    d = S.m
+    s = 2 * d
+    rng = np.random.default_rng(3)
+    X = np.zeros((s, d))
+    for k0 in range(0, T.shape[0], 4096):
+        X += rng.standard_normal((s, min(4096, T.shape[0] - k0))) @ T[k0:k0 + 4096]
+    _, sv, Vt = np.linalg.svd(np.linalg.qr(X, mode="r"))
+    r = int((sv > max(s, d) * 2.0 ** -52 * sv[0]).sum())
+    Pn = np.ascontiguousarray(Vt[:r].T / sv[:r])
+    b = workloads.rhs_gauss(d, 17)
+    ref, _, _, _ = orc.lsrn_iterate(ocsr(orc, S), b, Pn, s, refine=3)
+    x, info = L.solve_csr(gcsr(L, S), dev(b), method=method, seed=5, refine=1)
+    e = rel(host(x), ref)
+    print(f"tnimg replica {S.m}x{S.n} nnz={S.nnz} method={method}: rank={info['rank']} "
+          f"iters={info['iters']} rel_err_vs_oracle={e:.2e}")
+    assert info["tall"] == 0 and info["rank"] == r
+    assert e <= 1e-10

@@ -97,3 +97,30 @@ def test_lsqr_zero_rhs(orc):
 def test_cs_bounds_reject_small_sketch(orc):
     with pytest.raises(ValueError):
         orc.cs_bounds(4, 4, 1.0)
+
+
+@pytest.mark.parametrize("fat", [False, True])
+def test_cs_check_catches_violated_bounds(orc, fat):
+    """Theorem 3's bounds hold only with a probability (Lemma 3).  With the
+    margin t made negative the interval [sigma_L, sigma_U] misses most of
+    the spectrum of A N, the Chebyshev run diverges, the check after it
+    fails and LSQR continues: the result is still the pseudoinverse
+    solution.  With the default margin the check passes (no restart)."""
+    import workloads
+    P = workloads.dense_problem(1200, 60, smin=1e-3, seed=41)
+    if fat:
+        M = orc.Matrix.dense_colmajor(P.A)            # A = P.A^T, 60 x 1200
+        A = P.A.T
+        b = workloads.rhs_gauss(60, 41)
+    else:
+        M = orc.Matrix.dense(P.A)
+        A = P.A
+        b = workloads.rhs_gauss(1200, 41)
+    ref = np.linalg.pinv(A) @ b
+    ok = orc.lsrn_solve(M, b, seed=2, method=orc.CS)
+    assert ok.cs_fallbacks == 0 and ok.converged
+    bad = orc.lsrn_solve(M, b, seed=2, method=orc.CS, t_margin=-4.0)
+    assert bad.cs_fallbacks == 1 and bad.converged
+    # the divergent Chebyshev run alone is far off; the restarted result is not
+    assert np.linalg.norm(bad.x - ref) <= 1e-9 * np.linalg.norm(ref)
+    assert np.linalg.norm(ok.x - ref) <= 1e-9 * np.linalg.norm(ref)

@@ -126,3 +126,31 @@ def test_fat_rank_deficient_min_length(orc):
         assert not res.tall and res.rank == 50
         xp, _ = orc.pinv_solve(orc.Matrix.dense(A), b, rcond=1e-9)
         assert _rel(res.x, xp) < 1e-9
+
+
+@pytest.mark.parametrize("lam", [1e-2, 0.3])
+@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("storage", ["dense", "colmajor", "csr"])
+def test_tikhonov_under_determined_closed_form(orc, lam, method, storage):
+    """Sec. 5's under-determined form: for m < n the Tikhonov solution is the
+    first n entries of the min-length solution of [A, lambda I_m] x^ = b,
+    i.e. x = A^T (A A^T + lambda^2 I)^-1 b (the minimiser of
+    ||A x - b||^2 + lambda^2 ||x||^2), for a rank-deficient A as well."""
+    rng = np.random.default_rng(int(lam * 1000) + method)
+    A = _exact_rankdef(800, 40, 30, 77).T.copy()          # 40 x 800, rank 30
+    b = rng.standard_normal(40)
+    x_ref = A.T @ np.linalg.solve(A @ A.T + lam * lam * np.eye(40), b)
+    if storage == "dense":
+        M = orc.Matrix.dense(A, lam=lam)
+    elif storage == "colmajor":
+        M = orc.Matrix.dense_colmajor(A.T.copy(), lam=lam)
+    else:
+        rows, cols = np.nonzero(A)
+        rowptr = np.concatenate([[0], np.cumsum(np.bincount(rows, minlength=40))])
+        M = orc.Matrix.csr(40, 800, rowptr, cols.astype(np.int32), A[rows, cols], lam=lam)
+    res = orc.lsrn_solve(M, b, seed=4, method=method, refine=2)
+    assert not res.tall and res.rank == 40 and res.s == 80
+    assert _rel(res.x, x_ref) < 1e-11
+    # the stationarity condition of the regularised problem
+    g = A.T @ (A @ res.x - b) + lam * lam * res.x
+    assert np.linalg.norm(g) <= 1e-11 * np.linalg.norm(A.T @ b)

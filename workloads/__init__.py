@@ -245,3 +245,61 @@ WORKLOADS = {
                                  lam=1e-3, seed=13),
     "dense_1000000x4000": dict(m=1_000_000, n=4000, rank=4000, smin=1e-8, noise=1e-6, seed=14),
 }
+
+
+def tnimg_like(n: int, m: int = 1024, seed: int = 0, chunk: int = 1 << 18) -> Sparse:
+    """A synthetic stand-in for the paper's tnimg matrices (Sec. 6.5): m = 1024
+    rows (the 32 x 32 two-dimensional DCT frequencies (u, v) of an image,
+    row 32 u + v), n columns (images), each column keeping 20 or 21
+    coefficients (the largest 2% of 1024; 21 with probability 0.9, so about
+    21 n nonzeros as in the paper's tables).  Row 0 (the DC term) is in every
+    column with a value in (0.5, 30); the others are drawn without
+    replacement with probability proportional to (1 + u + v)^-1.5 and get
+    N(0,1) values scaled by 8 / (1 + u + v), as the magnitudes of an image's
+    DCT fall with frequency.  Rows that end up empty are removed (as in the
+    paper), so m may come out smaller.  Returned in CSR (rows sorted by
+    column within each row)."""
+    rng = np.random.default_rng(seed)
+    u, v = np.divmod(np.arange(m, dtype=np.int64), 32)
+    freq = (1 + u + v).astype(np.float64)
+    w = freq[1:] ** -1.5
+    cdf = np.cumsum(w / w.sum())
+    cdf[-1] = 1.0
+    rows_parts, cols_parts, val_parts = [], [], []
+    for c0 in range(0, n, chunk):
+        c1 = min(n, c0 + chunk)
+        k = c1 - c0
+        per = np.where(rng.random(k) < 0.9, 21, 20)
+        # 20 draws from rows 1..m-1 per column (distinct), the 21st slot kept
+        # only where per == 21; row 0 added separately
+        draw = 1 + np.searchsorted(cdf, rng.random((k, 20)))
+        draw.sort(axis=1)
+        dup = np.zeros_like(draw, dtype=bool)
+        dup[:, 1:] = draw[:, 1:] == draw[:, :-1]
+        while dup.any():
+            draw[dup] = 1 + np.searchsorted(cdf, rng.random(int(dup.sum())))
+            draw.sort(axis=1)
+            dup[:] = False
+            dup[:, 1:] = draw[:, 1:] == draw[:, :-1]
+        keep = np.ones_like(draw, dtype=bool)
+        keep[per == 20, 19] = False                    # 19 draws + row 0 = 20 entries
+        cols = np.repeat(np.arange(c0, c1, dtype=np.int64), keep.sum(axis=1))
+        rws = draw[keep]
+        vals = rng.standard_normal(rws.size) * (8.0 / freq[rws])
+        dc = rng.uniform(0.5, 30.0, k)
+        rows_parts += [np.zeros(k, np.int64), rws]
+        cols_parts += [np.arange(c0, c1, dtype=np.int64), cols]
+        val_parts += [dc, vals]
+    rows = np.concatenate(rows_parts)
+    cols = np.concatenate(cols_parts)
+    vals = np.concatenate(val_parts)
+    # drop empty rows, renumbering the others in order
+    present = np.bincount(rows, minlength=m) > 0
+    newid = np.cumsum(present) - 1
+    rows = newid[rows]
+    m_eff = int(present.sum())
+    order = np.lexsort((cols, rows))
+    rows, cols, vals = rows[order], cols[order], vals[order]
+    rowptr = np.zeros(m_eff + 1, np.int64)
+    np.cumsum(np.bincount(rows, minlength=m_eff), out=rowptr[1:])
+    return Sparse(m_eff, n, rowptr, cols.astype(np.int32), vals)
