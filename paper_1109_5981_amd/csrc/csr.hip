@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <mutex>
 #include <vector>
 
 #include "common.hpp"
@@ -335,8 +336,14 @@ void sketch_csr(const SparseView &v, double lambda, int64_t s, uint64_t seed, do
         LSRN_HIP(hipMemsetAsync(optr.as<int64_t>(), 0, (size_t)(ngroups + 1) * sizeof(int64_t), st));
     }
     const size_t lds = sizeof(double) * ((size_t)SK_S * C + (size_t)SK_S * SK_KB);
-    LSRN_HIP(hipFuncSetAttribute((const void *)csr_sketch_kernel<SK_S, SK_NT>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    // the dynamic-LDS limit is raised once per process: solves on several
+    // host threads (the serving runtime's workers) would otherwise set the
+    // attribute of the same kernel concurrently
+    static std::once_flag lds_once;
+    std::call_once(lds_once, [lds] {
+        LSRN_HIP(hipFuncSetAttribute((const void *)csr_sketch_kernel<SK_S, SK_NT>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    });
     hipEvent_t ev[2] = {nullptr, nullptr};
     if (kernel_ms) {
         LSRN_HIP(hipEventCreate(&ev[0]));
