@@ -262,6 +262,29 @@ lsrn_status lsrn_sketch_dense(int64_t m, int64_t n, const double *A, int64_t lda
                               int32_t layout, double lambda, int64_t s, uint64_t seed,
                               double *X, void *stream);
 
+/* Size of the static device scratch behind lsrn_sketch_dense_noalloc:
+ * 64 MiB (the partial sums of every sketch with min(m, n) <= 512 and
+ * s = 2 min(m, n) fit), held on every device the library runs on until
+ * the process ends. */
+#define LSRN_NOALLOC_SCRATCH_BYTES (64ll << 20)
+
+/* lsrn_sketch_dense for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and the same result bit for bit, with the
+ * split-K partial sums of small tile grids kept in the library's static
+ * scratch (LSRN_NOALLOC_SCRATCH_BYTES) instead of an allocation.  It
+ * allocates nothing and does not synchronise: it returns once the work is
+ * enqueued on `stream`.  A must be stored so that it is read in place
+ * (row-major when m >= n, column-major when m < n;
+ * LSRN_E_UNSUPPORTED otherwise).  LSRN_E_NOMEM when the partial sums of
+ * this shape would exceed the scratch.  All calls on one device share its
+ * scratch: calls whose work overlaps on the device (enqueued on different
+ * streams without ordering between them) race; calls on one stream, or
+ * ordered by events, do not. */
+lsrn_status lsrn_sketch_dense_noalloc(int64_t m, int64_t n, const double *A, int64_t lda,
+                                      int32_t layout, double lambda, int64_t s, uint64_t seed,
+                                      double *X, void *stream);
+
 /* The precision form's sketch X = bf16(G) fl32(T) (+ lambda G(:, K + c) in
  * FP64), arguments and layout as lsrn_sketch_dense. */
 lsrn_status lsrn_sketch_dense_bf16(int64_t m, int64_t n, const double *A, int64_t lda,

@@ -480,6 +480,25 @@ lsrn_status lsrn_sketch_dense(int64_t m, int64_t n, const double *A, int64_t lda
     LSRN_API_END
 }
 
+lsrn_status lsrn_sketch_dense_noalloc(int64_t m, int64_t n, const double *A, int64_t lda,
+                                      int32_t layout, double lambda, int64_t s, uint64_t seed,
+                                      double *X, void *stream) {
+    LSRN_API_BEGIN
+    LSRN_REQUIRE(m > 0 && n > 0 && s > 0, "sizes must be positive");
+    LSRN_REQUIRE(A && X, "NULL pointer");
+    LSRN_REQUIRE(lambda >= 0.0, "lambda must be >= 0");
+    LSRN_REQUIRE(layout == LSRN_ROW_MAJOR || layout == LSRN_COL_MAJOR, "unknown layout");
+    LSRN_REQUIRE(lda >= (layout == LSRN_ROW_MAJOR ? n : m), "lda too small for the layout");
+    const bool tall = m >= n;
+    if ((tall && layout != LSRN_ROW_MAJOR) || (!tall && layout != LSRN_COL_MAJOR))
+        fail(LSRN_E_UNSUPPORTED,
+             "the no-allocation sketch reads A in place: row-major when m >= n, "
+             "column-major when m < n");
+    sketch_rows_noalloc(tall ? m : n, tall ? n : m, A, lda, lambda, s, seed, X,
+                        (hipStream_t)stream);
+    LSRN_API_END
+}
+
 lsrn_status lsrn_sketch_dense_bf16(int64_t m, int64_t n, const double *A, int64_t lda,
                                    int32_t layout, double lambda, int64_t s, uint64_t seed,
                                    double *X, void *stream) {

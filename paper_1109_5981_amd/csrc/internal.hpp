@@ -28,6 +28,13 @@ void sketch_rows(int64_t K, int64_t d, const double *T, int64_t ldt, double lamb
 void sketch_rows(int64_t K, int64_t d, const float *T, int64_t ldt, double lambda, int64_t s,
                  uint64_t seed, double *X, hipStream_t st, double *kernel_ms = nullptr);
 size_t sketch_workspace_bytes(int64_t K, int64_t d, int64_t s);
+// Bytes of split-K partial sums sketch_rows takes for FP64 T (0: none).
+size_t sketch_slices_bytes(int64_t K, int64_t d, int64_t s);
+// sketch_rows for FP64 T with the partial sums in the library's static
+// scratch (LSRN_NOALLOC_SCRATCH_BYTES): allocates nothing and does not
+// synchronise; LSRN_E_NOMEM when the partial sums would not fit.
+void sketch_rows_noalloc(int64_t K, int64_t d, const double *T, int64_t ldt, double lambda,
+                         int64_t s, uint64_t seed, double *X, hipStream_t st);
 // The sketches of `count` tall problems (T[p] row-major K[p] x d[p]) in one
 // launch per alignment class, no split of K.  Synchronises.
 void sketch_rows_batch(int count, const int64_t *K, const int64_t *d, const double *const *T,

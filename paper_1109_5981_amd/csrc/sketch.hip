@@ -8,10 +8,17 @@
 // 128 x 256 or 128 x 128) and one slice of K; the slices are summed in a
 // fixed order by a second kernel.
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "internal.hpp"
 #include "rng.hpp"
+
+// Device memory of the no-allocation sketch (lsrn_sketch_dense_noalloc):
+// the split-K partial sketches.  Every device the library runs on holds
+// this array until the process ends.  In host code `scratch` is only a
+// handle for hipGetSymbolAddress; kernels get the address it returns.
+static __device__ __align__(256) unsigned char scratch[LSRN_NOALLOC_SCRATCH_BYTES];
 
 namespace lsrn {
 
@@ -307,15 +314,22 @@ size_t sketch_workspace_bytes(int64_t K, int64_t d, int64_t s) {
 
 namespace {
 
+// With `slices` (device memory of at least nsplit s d doubles) the split-K
+// partial sketches go there and nothing is allocated or synchronised.
 template <typename TT>
 void sketch_rows_t(int64_t K, int64_t d, const TT *T, int64_t ldt, double lambda, int64_t s,
-                   uint64_t seed, double *X, hipStream_t st, double *kernel_ms) {
+                   uint64_t seed, double *X, hipStream_t st, double *kernel_ms,
+                   double *slices = nullptr) {
     SketchPlan p = plan_sketch(K, d, s, sizeof(TT) == sizeof(double));
     DevBuf part;
     double *Xp = X;
     if (p.nsplit > 1) {
-        part.alloc((size_t)p.nsplit * (size_t)s * (size_t)d * sizeof(double));
-        Xp = part.as<double>();
+        if (slices) {
+            Xp = slices;
+        } else {
+            part.alloc((size_t)p.nsplit * (size_t)s * (size_t)d * sizeof(double));
+            Xp = part.as<double>();
+        }
     }
     dim3 grid((unsigned)(p.tiles_m * p.tiles_n), (unsigned)p.nsplit);
     const bool vec2 = (ldt % 2 == 0) && ((reinterpret_cast<uintptr_t>(T) & (2 * sizeof(TT) - 1)) == 0);
@@ -361,10 +375,46 @@ void sketch_rows_t(int64_t K, int64_t d, const TT *T, int64_t ldt, double lambda
         add_identity_rows_kernel<<<blocks, 256, 0, st>>>(K, d, s, lambda, seed, X);
         LSRN_HIP(hipGetLastError());
     }
-    if (p.nsplit > 1) LSRN_HIP(hipStreamSynchronize(st));  // before `part` is freed
+    if (p.nsplit > 1 && !slices) LSRN_HIP(hipStreamSynchronize(st));  // before `part` is freed
+}
+
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current.
+double *scratch_on_current_device() {
+    int dev = 0;
+    LSRN_HIP(hipGetDevice(&dev));
+    LSRN_REQUIRE(dev >= 0 && dev < kMaxDevices, "device ordinal out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        LSRN_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        LSRN_REQUIRE(ptr != nullptr, "no device address for the static scratch");
+        g_scratch_ptr[dev] = ptr;
+    }
+    return static_cast<double *>(g_scratch_ptr[dev]);
 }
 
 }  // namespace
+
+size_t sketch_slices_bytes(int64_t K, int64_t d, int64_t s) {
+    const SketchPlan p = plan_sketch(K, d, s, true);
+    return p.nsplit > 1 ? (size_t)p.nsplit * (size_t)s * (size_t)d * sizeof(double) : 0;
+}
+
+void sketch_rows_noalloc(int64_t K, int64_t d, const double *T, int64_t ldt, double lambda,
+                         int64_t s, uint64_t seed, double *X, hipStream_t st) {
+    const size_t need = sketch_slices_bytes(K, d, s);
+    if (need > (size_t)LSRN_NOALLOC_SCRATCH_BYTES)
+        fail(LSRN_E_NOMEM, "the sketch needs " + std::to_string(need) +
+                               " bytes of partial sums; the static scratch holds " +
+                               std::to_string((size_t)LSRN_NOALLOC_SCRATCH_BYTES));
+    double *slices = need > 0 ? scratch_on_current_device() : nullptr;
+    sketch_rows_t(K, d, T, ldt, lambda, s, seed, X, st, nullptr, slices);
+}
 
 void sketch_rows(int64_t K, int64_t d, const double *T, int64_t ldt, double lambda, int64_t s,
                  uint64_t seed, double *X, hipStream_t st, double *kernel_ms) {

@@ -67,7 +67,9 @@ EXPORTS = EXPORTS + SERVER_EXPORTS
 PLAN_EXPORTS = ["lsrn_plan_create_dense", "lsrn_plan_create_csr", "lsrn_plan_solve",
                 "lsrn_plan_destroy", "lsrn_plan_set_lambda", "lsrn_tune_gamma"]
 EXPORTS = EXPORTS + PLAN_EXPORTS + ["lsrn_solve_op", "lsrn_tune_export", "lsrn_tune_import",
-                                     "lsrn_tune_clear", "lsrn_solve_dense_f32"]
+                                     "lsrn_tune_clear", "lsrn_solve_dense_f32",
+                                     "lsrn_sketch_dense_noalloc"]
+NOALLOC_SCRATCH_BYTES = 64 << 20    # LSRN_NOALLOC_SCRATCH_BYTES
 # lsrn_apply_fn: (ctx, trans, k, in, ldin, out, ldout, stream) -> int
 APPLY_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_int64,
                        C.c_void_p, C.c_int64, C.c_void_p)
@@ -102,6 +104,7 @@ def lib():
         L.lsrn_gauss_fill.argtypes = [U64, I64, I64, I64, I64, P, P]
         L.lsrn_sketch_dense.argtypes = [I64, I64, P, I64, I32, D, I64, U64, P, P]
         L.lsrn_sketch_dense_bf16.argtypes = [I64, I64, P, I64, I32, D, I64, U64, P, P]
+        L.lsrn_sketch_dense_noalloc.argtypes = [I64, I64, P, I64, I32, D, I64, U64, P, P]
         L.lsrn_precond.argtypes = [I64, I64, P, D, P, P, C.POINTER(C.c_int64),
                                    C.POINTER(C.c_int64), P]
         L.lsrn_iterate_dense.argtypes = [I64, I64, P, I64, I32, P, P, I64, I64, I64, P,
@@ -263,6 +266,24 @@ def sketch_dense(A: torch.Tensor, s: int, seed: int = 0, lam: float = 0.0,
     X = torch.empty((d, s), dtype=torch.float64, device=A.device)
     _check(lib().lsrn_sketch_dense(m, n, A.data_ptr(), lda, layout, lam, s, seed, X.data_ptr(),
                                    _stream()))
+    return X
+
+
+def sketch_dense_noalloc(A: torch.Tensor, s: int, seed: int = 0, lam: float = 0.0,
+                         layout: int = ROW_MAJOR, X: torch.Tensor | None = None) -> torch.Tensor:
+    """lsrn_sketch_dense_noalloc: sketch_dense with the library's static
+    scratch instead of device allocations; enqueued on the current stream
+    without a synchronisation.  X (d, s) may be given (else allocated here
+    by torch, outside the call)."""
+    _dev_f64(A, "A")
+    m, n, lda = _layout_dims(A, layout)
+    d = n if m >= n else m
+    if X is None:
+        X = torch.empty((d, s), dtype=torch.float64, device=A.device)
+    if tuple(X.shape) != (d, s) or not X.is_contiguous():
+        raise ValueError("X must be a contiguous (d, s) tensor")
+    _check(lib().lsrn_sketch_dense_noalloc(m, n, A.data_ptr(), lda, layout, lam, s, seed,
+                                           X.data_ptr(), _stream()))
     return X
 
 
