@@ -253,7 +253,8 @@ def serve_main(args):
                 "request draws one and a fresh b ~ N(0,1))",
         "config": {"workload": "serving_uneven", "requests": nreq, "arrival_rate_per_s": rate,
                    "m": [1000, 100000], "n": [16, 512], "fat_fraction": 0.25,
-                   "streams": args.serve_streams, "budget_gb": args.serve_budget_gb},
+                   "streams": args.serve_streams, "budget_gb": args.serve_budget_gb,
+                   "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))},
         "latency_ms": {"p50": round(percentile(lat, 50), 3), "p99": round(percentile(lat, 99), 3),
                        "mean_queue": round(float(np.mean([r["queue_ms"] for r in results.values()])), 3)},
         "wall_s": round(t1 - t0, 3),
@@ -471,6 +472,11 @@ def main():
                          "its FETCH_SIZE / WRITE_SIZE counters calibrate the traffic figures")
     args = ap.parse_args()
 
+    if args.serve:
+        # HIP maps streams onto GPU_MAX_HW_QUEUES hardware queues (4 by
+        # default); with more worker streams than queues, streams share a
+        # queue and their solves serialise.  Set before the runtime starts.
+        os.environ.setdefault("GPU_MAX_HW_QUEUES", str(min(32, max(4, args.serve_streams))))
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "the solver runs on exactly one GPU; --gpus must be 1",
@@ -540,16 +546,18 @@ def main():
         torch.cuda.empty_cache()
         solve = lsrn.solve_dense_f32
 
-    def leg(solve_fn, steps, warmup, **o):
+    def leg(solve_fn, steps, warmup, A_=None, b_=None, **o):
         """warmup untimed solves, then `steps` timed ones between device syncs."""
+        A_ = A_solve if A_ is None else A_
+        b_ = b if b_ is None else b_
         for _ in range(warmup):
-            x, info = solve_fn(A_solve, b, layout=layout, allow_not_converged=True, **o)
+            x, info = solve_fn(A_, b_, layout=layout, allow_not_converged=True, **o)
         torch.cuda.synchronize()
         lat, infos = [], []
         t0 = time.perf_counter()
         for _ in range(steps):
             ts = time.perf_counter()
-            x, info = solve_fn(A_solve, b, layout=layout, allow_not_converged=True, **o)
+            x, info = solve_fn(A_, b_, layout=layout, allow_not_converged=True, **o)
             torch.cuda.synchronize()
             lat.append((time.perf_counter() - ts) * 1e3)
             infos.append(info)
@@ -582,31 +590,62 @@ def main():
     mean = lambda key, inf=None: sum(i[key] for i in (inf or infos)) / len(inf or infos)
     kernels, stages = kernel_figures(args, infos, s, K, d, mean)
 
-    # the precision form beside the FP64 path, on the same A and b
+    cpu = None
+    if not args.no_cpu_baseline and args.storage == "f64":
+        iters_total = info["iters"] + info["refine_iters"] + 2 * info["refine_steps"]
+        cpu = cpu_baseline(A_solve, b, s, d, r, iters_total, info["sweeps"], not wl["fat"])
+
+    def leg_summary(xv, infs, latv, el, steps, ref, label_args):
+        i_ = infs[-1]
+        km, _ = kernel_figures(label_args, infs, s, K, d, lambda key: mean(key, infs))
+        return {
+            "solves_per_s": round(steps / el, 4),
+            "latency_ms": {"p50": round(percentile(latv, 50), 3), "p99": round(percentile(latv, 99), 3)},
+            "rel_err_vs_fp64_refined": (torch.linalg.norm(xv - ref) / torch.linalg.norm(ref)).item(),
+            "converged": bool(i_["converged"]), "iters": i_["iters"],
+            "refine_steps": i_["refine_steps"], "refine_iters": i_["refine_iters"],
+            "fp64_refine_steps": i_["fp64_refine_steps"],
+            "stages_ms": {k: round(mean(k, infs), 3) for k in
+                          ("t_sketch_ms", "t_svd_ms", "t_iter_ms", "t_refine_ms", "t_total_ms")},
+            "kernels": km,
+        }
+
+    # the precision form beside the FP64 path: on the same A and b, and (for
+    # the 1e6 x 4000 problem) on the same shape at kappa 1e6, where FP32
+    # sweeps can carry the iterations
     prec_form = None
     if (args.precision == "fp64" and args.storage == "f64" and not wl["fat"]
             and args.precision_steps > 0):
+        mixed_args = argparse.Namespace(**dict(vars(args), precision="mixed"))
         o_mixed = dict(opts, precision="mixed", refine=max(args.refine, 10))
         xm, infos_m, lat_m, el_m = leg(solve, args.precision_steps, 1, **o_mixed)
-        im = infos_m[-1]
-        km, _ = kernel_figures(argparse.Namespace(**dict(vars(args), precision="mixed")),
-                               infos_m, s, K, d, lambda key: mean(key, infos_m))
-        prec_form = {
-            "solves_per_s": round(args.precision_steps / el_m, 4),
-            "latency_ms": {"p50": round(percentile(lat_m, 50), 3),
-                           "p99": round(percentile(lat_m, 99), 3)},
-            "rel_err_vs_fp64_refined": rel_err(xm),
-            "converged": bool(im["converged"]),
-            "refine_steps": im["refine_steps"], "fp64_refine_steps": im["fp64_refine_steps"],
-            "stages_ms": {k: round(mean(k, infos_m), 3) for k in
-                          ("t_sketch_ms", "t_svd_ms", "t_iter_ms", "t_refine_ms", "t_total_ms")},
-            "kernels": km,
-            "note": ("BF16x3 sketch on the BF16 matrix cores, LSQR over an FP32 copy of A, "
-                     "refinement residuals in double-double from the FP64 A; when kappa(A) 2^-24 "
-                     "is near 1 the FP32 corrections stall and the refinement continues with "
-                     "FP64 sweeps (fp64_refine_steps)"),
-        }
+        prec_form = {"same_problem": leg_summary(xm, infos_m, lat_m, el_m, args.precision_steps,
+                                                 x_ref, mixed_args),
+                     "note": ("BF16x3 sketch on the BF16 matrix cores, LSQR over an FP32 copy of A, "
+                              "refinement residuals in double-double from the FP64 A; when the "
+                              "sketch's sigma_max / sigma_min_kept times 2^-24 exceeds 1/2 the "
+                              "sweeps read the FP64 A from the start (fp64_refine_steps)")}
         del xm
+        if args.workload == "dense_1000000x4000":
+            del A_solve, A, x_ref, x
+            torch.cuda.empty_cache()
+            w6 = WORKLOADS["dense_1000000x4000_k1e6"]
+            A6, U6, s6, V6 = workloads.dense_problem_device(w6["m"], w6["n"], w6["rank"], w6["smin"],
+                                                            w6["seed"], device=dev)
+            del U6, V6
+            b6, _ = workloads.rhs_model_device(A6, w6["noise"], w6["seed"])
+            torch.cuda.empty_cache()
+            o64 = dict(opts, refine=1)
+            x64, i64, l64, e64 = leg(solve, args.precision_steps, 1, A_=A6, b_=b6, **o64)
+            ref6, _ = solve(A6, b6, layout=layout, **dict(opts, refine=6, profile=0, seed=7))
+            xm6, im6, lm6, em6 = leg(solve, args.precision_steps, 1, A_=A6, b_=b6, **o_mixed)
+            prec_form["kappa_1e6"] = {
+                "workload": "dense_1000000x4000_k1e6",
+                "fp64": leg_summary(x64, i64, l64, e64, args.precision_steps, ref6, args),
+                "mixed": leg_summary(xm6, im6, lm6, em6, args.precision_steps, ref6, mixed_args),
+                "speedup_mixed_over_fp64": round(e64 / em6, 4),
+            }
+            del A6, b6, x64, xm6, ref6
 
     roofline = None
     if kernels:
@@ -616,11 +655,6 @@ def main():
                     "peak": kk["peak"], "unit": kk["unit"],
                     "frac": round(kk["achieved"] / kk["peak"], 4),
                     "traffic": MEASURED_TRAFFIC.get((args.workload, args.precision, args.storage, dom))}
-
-    cpu = None
-    if not args.no_cpu_baseline and args.storage == "f64":
-        iters_total = info["iters"] + info["refine_iters"] + 2 * info["refine_steps"]
-        cpu = cpu_baseline(A_solve, b, s, d, r, iters_total, info["sweeps"], not wl["fat"])
 
     value = args.steps / elapsed
     line = {

@@ -7,10 +7,16 @@
 // in order of their row k.  G(i, 4q .. 4q+3) is one Philox block, so the
 // workgroup generates, batch by batch, the S x 4QB slice of G for the rows
 // kb .. kb + 4QB of T once into LDS; every nonzero (k, c, v) of the batch
-// then adds v G(i, k) to X(i, c) for the S rows.  Nonzeros are grouped by
-// the thread that owns their column (c mod NT), so each column of the tile
-// has one writer and the summation order is fixed: the result is
-// deterministic.  Each slice of G is generated once per column block.
+// then adds v G(i, k) to a slot of the tile for the S rows.  Each slot has
+// one writer thread (slot mod NT) and its nonzeros come in row order, so
+// the summation order is fixed and the result deterministic.  A column of
+// T with many nonzeros per batch (the dense columns of a sparse matrix, the
+// low DCT frequencies of an image matrix) would make its one writer walk
+// all of them while the workgroup waits at the next batch: such a column
+// gets P slots past the C column slots (a power of two chosen so that each
+// receives about 4 nonzeros per batch), nonzero k goes to slot k mod P, and
+// the column is the sum of its slots in slot order at the end.  Each slice
+// of G is generated once per column block.
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
@@ -99,16 +105,29 @@ __global__ void gather_transpose_kernel(int64_t nnz, const int32_t *__restrict__
     }
 }
 
+// Tile slot of a nonzero in column c, row k of T: the column's own slot
+// c mod C, or for a column split into nslot[c] > 1 slots, slot
+// C + sbase[c] + (k mod nslot[c]).
+__device__ __forceinline__ int sketch_slot(int32_t c, int32_t k, int C,
+                                           const int32_t *__restrict__ sbase,
+                                           const int32_t *__restrict__ nslot) {
+    const int p = nslot[c];
+    return p > 1 ? C + sbase[c] + (k & (p - 1)) : c % C;
+}
+
 // key of entry e for the sketch order: (column block, batch of rows of T,
-// owning thread); the stable sort keeps the rows in order within a key.
+// writer thread of its slot); the stable sort keeps the rows in order
+// within a key.
 __global__ void sketch_keys_kernel(int64_t nnz, const int32_t *__restrict__ idx,
                                    const int32_t *__restrict__ rowof, int C, int64_t nbatch,
-                                   uint32_t *__restrict__ keys) {
+                                   const int32_t *__restrict__ sbase,
+                                   const int32_t *__restrict__ nslot, uint32_t *__restrict__ keys) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz;
          e += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t c = idx[e];
-        const int64_t batch = rowof[e] / SK_KB;
-        keys[e] = (uint32_t)(((int64_t)(c / C) * nbatch + batch) * SK_NT + (c % SK_NT));
+        const int32_t c = idx[e], k = rowof[e];
+        const int64_t batch = k / SK_KB;
+        const int slot = sketch_slot(c, k, C, sbase, nslot);
+        keys[e] = (uint32_t)(((int64_t)(c / C) * nbatch + batch) * SK_NT + (slot % SK_NT));
     }
 }
 
@@ -116,35 +135,39 @@ __global__ void gather_sketch_kernel(int64_t nnz, const int32_t *__restrict__ pe
                                      const int32_t *__restrict__ rowof,
                                      const int32_t *__restrict__ idx,
                                      const double *__restrict__ val, int C,
+                                     const int32_t *__restrict__ sbase,
+                                     const int32_t *__restrict__ nslot,
                                      SkEntry *__restrict__ out) {
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nnz;
          j += (int64_t)gridDim.x * blockDim.x) {
         const int32_t e = perm[j];
-        const int32_t c = idx[e];
-        out[j] = SkEntry{rowof[e], c % C, val[e]};
+        const int32_t c = idx[e], k = rowof[e];
+        out[j] = SkEntry{k, sketch_slot(c, k, C, sbase, nslot), val[e]};
     }
 }
 
 template <int S, int NT>
 __global__ void __launch_bounds__(NT)
 csr_sketch_kernel(const SkEntry *__restrict__ ent, const int64_t *__restrict__ optr, int64_t K,
-                  int64_t d, int C, int64_t nbatch, int64_t s, uint64_t seed,
+                  int64_t d, int C, int W, int64_t nbatch, int64_t s, uint64_t seed,
+                  const int32_t *__restrict__ sbase, const int32_t *__restrict__ nslot,
                   double *__restrict__ X) {
     static_assert(S == 4, "the LDS tiles hold 4 sketch rows per column as two 16-byte vectors");
     constexpr int QB = NT / S;  // Philox blocks (quads of rows of T) per batch per sketch row
     constexpr int KB = 4 * QB;  // rows of T per batch
     extern __shared__ double lds[];
-    // Xs[c][i] = X(i0 + i, c0 + c), Gs[kl][i] = G(i0 + i, kb + kl): the S values
-    // an entry touches are contiguous
-    double2 *Xs = reinterpret_cast<double2 *>(lds);                      // [C][S/2]
-    double2 *Gs = reinterpret_cast<double2 *>(lds + (size_t)S * C);      // [KB][S/2]
-    double *Gd = lds + (size_t)S * C;
+    // Xs[w][i] = slot w of X(i0 + i, :) (slot c < C: column c0 + c),
+    // Gs[kl][i] = G(i0 + i, kb + kl): the S values an entry touches are
+    // contiguous.  W = C + the split columns' slots (for every block).
+    double2 *Xs = reinterpret_cast<double2 *>(lds);                      // [W][S/2]
+    double2 *Gs = reinterpret_cast<double2 *>(lds + (size_t)S * W);      // [KB][S/2]
+    double *Gd = lds + (size_t)S * W;
     const int tid = threadIdx.x;
     const int b = blockIdx.y;
     const int64_t i0 = (int64_t)blockIdx.x * S;
     const int64_t c0 = (int64_t)b * C;
     const int cw = (int)min<int64_t>((int64_t)C, d - c0);
-    for (int j = tid; j < S * C; j += NT) lds[j] = 0.0;
+    for (int j = tid; j < S * W; j += NT) lds[j] = 0.0;
     const int gi = tid / QB, gq = tid % QB;
     const uint64_t grow = (uint64_t)min<int64_t>(i0 + gi, s - 1);
     // this thread's entries of batch j: [optr[g], optr[g + 1]), g = (b nbatch + j) NT + tid
@@ -196,7 +219,13 @@ csr_sketch_kernel(const SkEntry *__restrict__ ent, const int64_t *__restrict__ o
     __syncthreads();
     for (int j = tid; j < S * cw; j += NT) {
         const int c = j / S, i = j % S;
-        if (i0 + i < s) X[(c0 + c) * s + i0 + i] = lds[c * S + i];
+        const int p = nslot[c0 + c];
+        double v = lds[c * S + i];
+        if (p > 1) {  // a split column: its slots in order
+            const int w0 = C + sbase[c0 + c];
+            for (int q = 0; q < p; ++q) v += lds[(w0 + q) * S + i];
+        }
+        if (i0 + i < s) X[(c0 + c) * s + i0 + i] = v;
     }
 }
 
@@ -304,15 +333,68 @@ size_t sparse_view_bytes(int64_t m, int64_t n, int64_t nnz) {
     return (size_t)(n + 1) * 8 + (size_t)nnz * 12 + (size_t)nnz * 16 + (size_t)nnz * 8 + seg;
 }
 
+// Split columns: column c of T with about e nonzeros per batch (of SK_KB
+// rows) gets P = the power of two >= e / 4 slots (P = 1: not split), as
+// long as every block's extra slots fit in `room`; the largest columns are
+// split first.  sbase[c] = first extra slot of c within its block.
+int plan_split_columns(const SparseView &v, int C, int room, std::vector<int32_t> &sbase,
+                       std::vector<int32_t> &nslot, hipStream_t st) {
+    const int64_t d = v.d, K = v.K;
+    std::vector<int64_t> ptr((size_t)d + 1);
+    LSRN_HIP(hipMemcpyAsync(ptr.data(), v.cols.ptr, ((size_t)d + 1) * sizeof(int64_t),
+                            hipMemcpyDeviceToHost, st));
+    LSRN_HIP(hipStreamSynchronize(st));
+    sbase.assign((size_t)d, 0);
+    nslot.assign((size_t)d, 1);
+    const int64_t nb = ceil_div(d, C);
+    int most = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+        const int64_t c0 = b * C, c1 = std::min<int64_t>(d, c0 + C);
+        std::vector<std::pair<double, int64_t>> heavy;
+        for (int64_t c = c0; c < c1; ++c) {
+            const double per_batch = (double)(ptr[(size_t)c + 1] - ptr[(size_t)c]) * SK_KB / (double)K;
+            if (per_batch > 8.0) heavy.emplace_back(per_batch, c);
+        }
+        std::sort(heavy.begin(), heavy.end(), [](const auto &x, const auto &y) {
+            return x.first > y.first || (x.first == y.first && x.second < y.second);
+        });
+        int used = 0;
+        for (const auto &h : heavy) {
+            int p = 1;
+            while (p < 256 && p * 4.0 < h.first) p *= 2;
+            if (used + p > room) break;
+            sbase[(size_t)h.second] = used;
+            nslot[(size_t)h.second] = p;
+            used += p;
+        }
+        most = std::max(most, used);
+    }
+    return most;
+}
+
 void sketch_csr(const SparseView &v, double lambda, int64_t s, uint64_t seed, double *X,
                 hipStream_t st, double *kernel_ms) {
     const int64_t K = v.K, d = v.d, nnz = v.nnz;
-    const int C = SK_C;
+    // column slots per block (fewer than SK_C when T is narrower, which
+    // leaves the room to the split columns' slots)
+    const int C = (int)std::min<int64_t>(SK_C, d);
     const int64_t nb = ceil_div(d, C);
     const int64_t nbatch = std::max<int64_t>(1, ceil_div(K, SK_KB));
     const int64_t ngroups = nb * nbatch * SK_NT;
     LSRN_REQUIRE(ngroups < ((int64_t)1 << 31), "sparse sketch: too many (column block, batch) groups");
     LSRN_REQUIRE(nb <= 65535, "sparse sketch: too many column blocks");
+    // LDS: the tile (C column slots + the split columns' slots) and the
+    // batch's slice of G, within 160 KiB
+    const int lds_max = 160 * 1024 / (int)sizeof(double);
+    const int room = lds_max / SK_S - C - SK_KB;
+    std::vector<int32_t> sbase_h, nslot_h;
+    const int extra = plan_split_columns(v, C, std::max(room, 0), sbase_h, nslot_h, st);
+    const int W = C + extra;
+    DevBuf sbase((size_t)d * sizeof(int32_t)), nslot((size_t)d * sizeof(int32_t));
+    LSRN_HIP(hipMemcpyAsync(sbase.as<int32_t>(), sbase_h.data(), (size_t)d * sizeof(int32_t),
+                            hipMemcpyHostToDevice, st));
+    LSRN_HIP(hipMemcpyAsync(nslot.as<int32_t>(), nslot_h.data(), (size_t)d * sizeof(int32_t),
+                            hipMemcpyHostToDevice, st));
     DevBuf ent((size_t)std::max<int64_t>(nnz, 1) * sizeof(SkEntry));
     DevBuf optr((size_t)(ngroups + 1) * sizeof(int64_t));
     const CsrMat &t = v.rows;  // CSR(T)
@@ -321,6 +403,7 @@ void sketch_csr(const SparseView &v, double lambda, int64_t s, uint64_t seed, do
         DevBuf iota((size_t)nnz * 4), perm((size_t)nnz * 4);
         expand_rows_kernel<<<grid_for(t.nrows), 256, 0, st>>>(t.nrows, t.ptr, rowof.as<int32_t>());
         sketch_keys_kernel<<<grid_for(nnz), 256, 0, st>>>(nnz, t.idx, rowof.as<int32_t>(), C, nbatch,
+                                                          sbase.as<int32_t>(), nslot.as<int32_t>(),
                                                           keys.as<uint32_t>());
         iota_kernel<<<grid_for(nnz), 256, 0, st>>>(nnz, iota.as<int32_t>());
         LSRN_HIP(hipGetLastError());
@@ -329,20 +412,22 @@ void sketch_csr(const SparseView &v, double lambda, int64_t s, uint64_t seed, do
         bounds_kernel<<<grid_for(ngroups + 1), 256, 0, st>>>(nnz, ksort.as<uint32_t>(), ngroups,
                                                              optr.as<int64_t>());
         gather_sketch_kernel<<<grid_for(nnz), 256, 0, st>>>(nnz, perm.as<int32_t>(), rowof.as<int32_t>(),
-                                                            t.idx, t.val, C, ent.as<SkEntry>());
+                                                            t.idx, t.val, C, sbase.as<int32_t>(),
+                                                            nslot.as<int32_t>(), ent.as<SkEntry>());
         LSRN_HIP(hipGetLastError());
         LSRN_HIP(hipStreamSynchronize(st));
     } else {
         LSRN_HIP(hipMemsetAsync(optr.as<int64_t>(), 0, (size_t)(ngroups + 1) * sizeof(int64_t), st));
     }
-    const size_t lds = sizeof(double) * ((size_t)SK_S * C + (size_t)SK_S * SK_KB);
-    // the dynamic-LDS limit is raised once per process: solves on several
-    // host threads (the serving runtime's workers) would otherwise set the
-    // attribute of the same kernel concurrently
+    const size_t lds = sizeof(double) * ((size_t)SK_S * W + (size_t)SK_S * SK_KB);
+    // the dynamic-LDS limit (the most any call takes) is raised once per
+    // process: solves on several host threads (the serving runtime's
+    // workers) would otherwise set the attribute of the same kernel
+    // concurrently
     static std::once_flag lds_once;
-    std::call_once(lds_once, [lds] {
+    std::call_once(lds_once, [] {
         LSRN_HIP(hipFuncSetAttribute((const void *)csr_sketch_kernel<SK_S, SK_NT>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
     });
     hipEvent_t ev[2] = {nullptr, nullptr};
     if (kernel_ms) {
@@ -352,7 +437,8 @@ void sketch_csr(const SparseView &v, double lambda, int64_t s, uint64_t seed, do
     }
     dim3 grid((unsigned)ceil_div(s, SK_S), (unsigned)nb);
     csr_sketch_kernel<SK_S, SK_NT><<<grid, SK_NT, lds, st>>>(ent.as<SkEntry>(), optr.as<int64_t>(), K, d,
-                                                             C, nbatch, s, seed, X);
+                                                             C, W, nbatch, s, seed, sbase.as<int32_t>(),
+                                                             nslot.as<int32_t>(), X);
     LSRN_HIP(hipGetLastError());
     if (kernel_ms) {
         LSRN_HIP(hipEventRecord(ev[1], st));
