@@ -60,17 +60,17 @@ void DevBuf::release() {
 }
 
 int device_cus() {
-    static int cus = 0;
-    if (!cus) {
-        // A host without a device (size queries only) plans for 256 CUs.
+    // queried once (a thread-safe static); a host without a device (size
+    // queries only) plans for 256 CUs
+    static const int cus = [] {
         int dev = 0, v = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
             (void)hipGetLastError();
             return 256;
         }
-        cus = v > 0 ? v : 256;
-    }
+        return v > 0 ? v : 256;
+    }();
     return cus;
 }
 
@@ -264,6 +264,13 @@ bool use_qr_inverse(const lsrn_options &opt, int64_t d) {
          "min(m, n) above 8192 needs lambda > 0 (full-rank QR-inverse preconditioner)");
 }
 
+// The automatic choice tries N = R^-1 first when the Jacobi sweeps would be
+// the costly part (d above the batched small-matrix range): it is kept only
+// when R certifies that the SVD would keep every singular value.
+bool try_full_rank(const lsrn_options &opt, int64_t d) {
+    return opt.precond == LSRN_PRECOND_AUTO && d > 512;
+}
+
 // Steps 1-5 of a solve, kept for the iterations: the preconditioner and
 // (precision form) the FP32 copy of the tall view.
 struct Prepared {
@@ -337,7 +344,7 @@ void form_preconditioner(int64_t s, int64_t d, double *X, const lsrn_options &op
     pp.pr = use_qr_inverse(opt, d)
                 ? precond_qr_inverse(s, d, X, opt.rcond, pp.sigma.as<double>(), pp.P.as<double>(), st)
                 : precond(s, d, X, opt.rcond, pp.sigma.as<double>(), pp.P.as<double>(), st,
-                          opt.profile != 0);
+                          opt.profile != 0, try_full_rank(opt, d));
 }
 
 // Steps 6-7 (+ refinement) with a prepared preconditioner.
@@ -373,7 +380,8 @@ lsrn_status finish_info(bool tall, const Prepared &pp, const IterResult &ir, con
         info->s = pp.s; info->d = pp.d; info->rank = pp.pr.rank; info->iters = ir.iters;
         info->refine_steps = ir.refine_steps; info->refine_iters = ir.refine_iters;
         info->fp64_refine_steps = ir.fp64_refine_steps;
-    info->cs_fallbacks = ir.cs_fallbacks;
+        info->cs_fallbacks = ir.cs_fallbacks;
+        info->precond_used = pp.pr.full_rank_inverse ? LSRN_PRECOND_QR : LSRN_PRECOND_SVD;
         info->sweeps = pp.pr.sweeps; info->tall = tall; info->converged = ir.converged;
         info->sigma_l = ir.sigma_l; info->sigma_u = ir.sigma_u;
         info->sigma_max = pp.pr.sigma_max; info->sigma_min_kept = pp.pr.sigma_min_kept;
@@ -659,7 +667,7 @@ lsrn_status lsrn_solve_op(int64_t m, int64_t n, lsrn_apply_fn apply, void *ctx, 
                 ? precond_qr_inverse(s, d, X.as<double>(), opt.rcond, pp.sigma.as<double>(),
                                      pp.P.as<double>(), st)
                 : precond(s, d, X.as<double>(), opt.rcond, pp.sigma.as<double>(), pp.P.as<double>(),
-                          st, opt.profile != 0);
+                          st, opt.profile != 0, try_full_rank(opt, d));
     X.release();
     tm.mark();
     IterResult ir;
@@ -933,6 +941,7 @@ lsrn_status lsrn_solve_batch(int32_t count, const int64_t *m, const int64_t *n,
         std::memset(&in, 0, sizeof(in));
         in.s = ss[(size_t)p]; in.d = n[p]; in.rank = prs[(size_t)p].rank;
         in.iters = full[(size_t)p].iters; in.sweeps = prs[(size_t)p].sweeps; in.tall = 1;
+        in.precond_used = LSRN_PRECOND_SVD;
         in.converged = full[(size_t)p].converged;
         in.sigma_l = full[(size_t)p].sigma_l; in.sigma_u = full[(size_t)p].sigma_u;
         in.sigma_max = prs[(size_t)p].sigma_max; in.sigma_min_kept = prs[(size_t)p].sigma_min_kept;
@@ -976,6 +985,7 @@ size_t lsrn_workspace_bytes_csr(int64_t m, int64_t n, int64_t nnz, const lsrn_op
     const int64_t rows = K + (opt.lambda > 0.0 ? d : 0);
     size_t bytes = sparse_view_bytes(m, n, nnz);               // transposed structure
     bytes += (size_t)nnz * 36;                                 // sketch order + sort temporaries
+    bytes += sketch_csr_tile_bytes(K, d, nnz, s);              // group offsets, partial sketches
     bytes += (size_t)s * d * sizeof(double);                   // sketch
     bytes += precond_workspace_bytes(s, d) + (size_t)d * d * sizeof(double);  // QR-inverse
     bytes += (size_t)d * d * sizeof(double) * 2 + (size_t)d * sizeof(double);  // P, P^T, sigma

@@ -34,10 +34,13 @@ namespace lsrn {
 namespace {
 
 constexpr int SK_NT = 512;  // threads of the sketch kernel
-constexpr int SK_S = 4;     // sketch rows per workgroup
-constexpr int SK_C = 4096;  // columns of T per workgroup (multiple of SK_NT)
-constexpr int SK_KB = 4 * (SK_NT / SK_S);  // rows of T per batch
 constexpr int SK_PF = 8;    // entries per thread loaded one batch ahead
+constexpr int SK_LDS = 160 * 1024 / (int)sizeof(double);  // doubles of LDS per workgroup
+
+// Rows of T per batch for S sketch rows per workgroup: every thread
+// generates one Philox block (4 entries of G) per batch, so the slice of G
+// is S x KB = 4 NT entries for every S.
+constexpr int sk_kb(int S) { return 4 * (SK_NT / S); }
 
 struct SkEntry {
     int32_t k;  // row of T
@@ -45,31 +48,38 @@ struct SkEntry {
     double v;
 };
 
-__global__ void check_csr_kernel(int64_t m, int64_t n, int64_t nnz, const int64_t *__restrict__ ptr,
-                                 const int32_t *__restrict__ idx, int *__restrict__ bad) {
+// Structure checks, parallel over rows (the offsets) and over entries (the
+// column indices), so that long rows do not serialise a thread.
+__global__ void check_ptr_kernel(int64_t m, int64_t nnz, const int64_t *__restrict__ ptr,
+                                 int *__restrict__ bad) {
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m;
          r += (int64_t)gridDim.x * blockDim.x) {
         const int64_t a = ptr[r], b = ptr[r + 1];
-        if (a < 0 || b < a || b > nnz) {
-            atomicOr(bad, 1);
-            continue;
-        }
-        for (int64_t e = a; e < b; ++e) {
-            const int32_t c = idx[e];
-            if (c < 0 || (int64_t)c >= n) {
-                atomicOr(bad, 2);
-                break;
-            }
-        }
+        if (a < 0 || b < a || b > nnz) atomicOr(bad, 1);
     }
 }
 
-// out[e] = row of entry e.
+__global__ void check_idx_kernel(int64_t nnz, int64_t n, const int32_t *__restrict__ idx,
+                                 int *__restrict__ bad) {
+    bool out = false;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t c = idx[e];
+        out = out || c < 0 || (int64_t)c >= n;
+    }
+    if (__any(out) && (threadIdx.x & 63) == 0) atomicOr(bad, 2);
+}
+
+// One wavefront per row (grid-stride over rows), its lanes over the row's
+// entries, so that a long row (a fat matrix has rows of ~nnz / m entries)
+// does not serialise one thread.
 __global__ void expand_rows_kernel(int64_t nrows, const int64_t *__restrict__ ptr,
                                    int32_t *__restrict__ out) {
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrows;
-         r += (int64_t)gridDim.x * blockDim.x)
-        for (int64_t e = ptr[r]; e < ptr[r + 1]; ++e) out[e] = (int32_t)r;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t r = wave; r < nrows; r += nwaves)
+        for (int64_t e = ptr[r] + lane; e < ptr[r + 1]; e += 64) out[e] = (int32_t)r;
 }
 
 __global__ void iota_kernel(int64_t n, int32_t *__restrict__ out) {
@@ -119,13 +129,13 @@ __device__ __forceinline__ int sketch_slot(int32_t c, int32_t k, int C,
 // writer thread of its slot); the stable sort keeps the rows in order
 // within a key.
 __global__ void sketch_keys_kernel(int64_t nnz, const int32_t *__restrict__ idx,
-                                   const int32_t *__restrict__ rowof, int C, int64_t nbatch,
+                                   const int32_t *__restrict__ rowof, int C, int KB, int64_t nbatch,
                                    const int32_t *__restrict__ sbase,
                                    const int32_t *__restrict__ nslot, uint32_t *__restrict__ keys) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz;
          e += (int64_t)gridDim.x * blockDim.x) {
         const int32_t c = idx[e], k = rowof[e];
-        const int64_t batch = k / SK_KB;
+        const int64_t batch = k / KB;
         const int slot = sketch_slot(c, k, C, sbase, nslot);
         keys[e] = (uint32_t)(((int64_t)(c / C) * nbatch + batch) * SK_NT + (slot % SK_NT));
     }
@@ -146,56 +156,77 @@ __global__ void gather_sketch_kernel(int64_t nnz, const int32_t *__restrict__ pe
     }
 }
 
+// LDS position (in 16-byte vectors) of vector h of slot c in a tile of H
+// vectors per slot.  The lanes of a wavefront touch unrelated slots; with a
+// plain c H + h, H = 2 / 4 / 8 would put every lane's vector h on the same
+// 1/8 .. 1/2 of the 16 bank groups of a 256-byte LDS row.  Rotating h by
+// the slot's position within the row period spreads them over all 16.
+template <int H>
+__device__ __forceinline__ int tix(int c, int h) {
+    static_assert(H == 2 || H == 4, "2 or 4 vectors per slot");
+    constexpr int SPAN = 16 / H;  // slots per 256-byte row
+    return c * H + (h ^ ((c / SPAN) & (H - 1)));
+}
+
 template <int S, int NT>
 __global__ void __launch_bounds__(NT)
 csr_sketch_kernel(const SkEntry *__restrict__ ent, const int64_t *__restrict__ optr, int64_t K,
-                  int64_t d, int C, int W, int64_t nbatch, int64_t s, uint64_t seed,
+                  int64_t d, int C, int W, int64_t nbatch, int64_t bpz, int64_t s, uint64_t seed,
                   const int32_t *__restrict__ sbase, const int32_t *__restrict__ nslot,
-                  double *__restrict__ X) {
-    static_assert(S == 4, "the LDS tiles hold 4 sketch rows per column as two 16-byte vectors");
+                  double *__restrict__ out, int64_t zstride) {
+    static_assert(S % 2 == 0 && NT % S == 0, "the tiles hold the S rows of a column as 16-byte vectors");
+    constexpr int H = S / 2;    // 16-byte vectors per column of a tile
     constexpr int QB = NT / S;  // Philox blocks (quads of rows of T) per batch per sketch row
     constexpr int KB = 4 * QB;  // rows of T per batch
     extern __shared__ double lds[];
-    // Xs[w][i] = slot w of X(i0 + i, :) (slot c < C: column c0 + c),
-    // Gs[kl][i] = G(i0 + i, kb + kl): the S values an entry touches are
-    // contiguous.  W = C + the split columns' slots (for every block).
-    double2 *Xs = reinterpret_cast<double2 *>(lds);                      // [W][S/2]
-    double2 *Gs = reinterpret_cast<double2 *>(lds + (size_t)S * W);      // [KB][S/2]
+    // Xs: slot w holds X(i0 .. i0 + S - 1, :) of its column (slot c < C:
+    // column c0 + c), Gs: row kl of the slice holds G(i0 .. i0 + S - 1,
+    // kb + kl), each as H 16-byte vectors placed by tix.  W = C + the split
+    // columns' slots (for every block).
+    double2 *Xs = reinterpret_cast<double2 *>(lds);                      // [W][H]
+    double2 *Gs = reinterpret_cast<double2 *>(lds + (size_t)S * W);      // [KB][H]
     double *Gd = lds + (size_t)S * W;
     const int tid = threadIdx.x;
     const int b = blockIdx.y;
     const int64_t i0 = (int64_t)blockIdx.x * S;
     const int64_t c0 = (int64_t)b * C;
     const int cw = (int)min<int64_t>((int64_t)C, d - c0);
+    // this workgroup's batches: [j0, j1) (the split over rows of T)
+    const int64_t j0 = (int64_t)blockIdx.z * bpz, j1 = min<int64_t>(nbatch, j0 + bpz);
     for (int j = tid; j < S * W; j += NT) lds[j] = 0.0;
     const int gi = tid / QB, gq = tid % QB;
     const uint64_t grow = (uint64_t)min<int64_t>(i0 + gi, s - 1);
     // this thread's entries of batch j: [optr[g], optr[g + 1]), g = (b nbatch + j) NT + tid
-    const int64_t *op = optr + (int64_t)b * nbatch * NT + tid;
-    int64_t lo = op[0], hi = op[1];
-    SkEntry pf[SK_PF];
+    const int64_t *op = optr + ((int64_t)b * nbatch + j0) * NT + tid;
+    int64_t lo = 0, hi = 0;
+    if (j0 < j1) {
+        lo = op[0];
+        hi = op[1];
+    }
+    SkEntry pf[SK_PF] = {};
 #pragma unroll
     for (int u = 0; u < SK_PF; ++u)
         if (lo + u < hi) pf[u] = ent[lo + u];
     auto apply = [&](const SkEntry &t, int64_t kb) {
         const int kl = (int)((int64_t)t.k - kb);
-        const double2 g01 = Gs[kl * 2], g23 = Gs[kl * 2 + 1];
-        double2 x01 = Xs[t.c * 2], x23 = Xs[t.c * 2 + 1];
-        x01.x += t.v * g01.x;
-        x01.y += t.v * g01.y;
-        x23.x += t.v * g23.x;
-        x23.y += t.v * g23.y;
-        Xs[t.c * 2] = x01;
-        Xs[t.c * 2 + 1] = x23;
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            const double2 g = Gs[tix<H>(kl, h)];
+            const int xi = tix<H>(t.c, h);
+            double2 x = Xs[xi];
+            x.x += t.v * g.x;
+            x.y += t.v * g.y;
+            Xs[xi] = x;
+        }
     };
-    for (int64_t j = 0; j < nbatch; ++j) {
+    for (int64_t j = j0; j < j1; ++j) {
         const int64_t kb = j * KB;
         // next batch's range and first entries are loaded while this batch
         // generates its slice of G and applies its entries
         int64_t nlo = 0, nhi = 0;
-        if (j + 1 < nbatch) {
-            nlo = op[(j + 1) * NT];
-            nhi = op[(j + 1) * NT + 1];
+        if (j + 1 < j1) {
+            nlo = op[(j + 1 - j0) * NT];
+            nhi = op[(j + 1 - j0) * NT + 1];
         }
         SkEntry cur[SK_PF];
 #pragma unroll
@@ -204,7 +235,7 @@ csr_sketch_kernel(const SkEntry *__restrict__ ent, const int64_t *__restrict__ o
         gauss4(seed, grow, (uint64_t)(kb / 4 + gq), g);
         __syncthreads();  // previous batch done with Gs
 #pragma unroll
-        for (int w = 0; w < 4; ++w) Gd[(4 * gq + w) * S + gi] = g[w];
+        for (int w = 0; w < 4; ++w) Gd[2 * tix<H>(4 * gq + w, gi >> 1) + (gi & 1)] = g[w];
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < SK_PF; ++u)
@@ -217,19 +248,40 @@ csr_sketch_kernel(const SkEntry *__restrict__ ent, const int64_t *__restrict__ o
         hi = nhi;
     }
     __syncthreads();
+    double *X = out + (int64_t)blockIdx.z * zstride;
     for (int j = tid; j < S * cw; j += NT) {
         const int c = j / S, i = j % S;
         const int p = nslot[c0 + c];
-        double v = lds[c * S + i];
+        double v = lds[2 * tix<H>(c, i >> 1) + (i & 1)];
         if (p > 1) {  // a split column: its slots in order
             const int w0 = C + sbase[c0 + c];
-            for (int q = 0; q < p; ++q) v += lds[(w0 + q) * S + i];
+            for (int q = 0; q < p; ++q) v += lds[2 * tix<H>(w0 + q, i >> 1) + (i & 1)];
         }
         if (i0 + i < s) X[(c0 + c) * s + i0 + i] = v;
     }
 }
 
+// X = the sum of the nz partial sketches (one per range of rows of T), in
+// range order.
+__global__ void sum_partials_kernel(const double *__restrict__ part, int nz, int64_t n,
+                                    double *__restrict__ X) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        double v = part[e];
+        for (int z = 1; z < nz; ++z) v += part[(int64_t)z * n + e];
+        X[e] = v;
+    }
+}
+
 int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 256), 65535)); }
+
+// blocks of 256 threads (4 wavefronts) for one wavefront per row
+int grid_rows(int64_t rows) { return (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(rows, 4), 65535)); }
+
+void launch_expand_rows(int64_t nrows, const int64_t *ptr, int32_t *out, hipStream_t st) {
+    expand_rows_kernel<<<grid_rows(nrows), 256, 0, st>>>(nrows, ptr, out);
+    LSRN_HIP(hipGetLastError());
+}
 
 // Stable sort of (keys, values) by the low `bits` bits of the keys.
 void sort_pairs(const uint32_t *kin, uint32_t *kout, const int32_t *vin, int32_t *vout, int64_t n,
@@ -265,7 +317,8 @@ void make_sparse_view(SparseView &v, int64_t m, int64_t n, int64_t nnz, const in
     {
         DevBuf flag(sizeof(int));
         LSRN_HIP(hipMemsetAsync(flag.as<int>(), 0, sizeof(int), st));
-        check_csr_kernel<<<grid_for(m), 256, 0, st>>>(m, n, nnz, rowptr, colind, flag.as<int>());
+        check_ptr_kernel<<<grid_for(m), 256, 0, st>>>(m, nnz, rowptr, flag.as<int>());
+        if (nnz > 0) check_idx_kernel<<<grid_for(nnz), 256, 0, st>>>(nnz, n, colind, flag.as<int>());
         LSRN_HIP(hipGetLastError());
         int bad = 0;
         LSRN_HIP(hipMemcpyAsync(&bad, flag.as<int>(), sizeof(int), hipMemcpyDeviceToHost, st));
@@ -285,7 +338,7 @@ void make_sparse_view(SparseView &v, int64_t m, int64_t n, int64_t nnz, const in
     const CsrMat at{n, m, nnz, v.tptr.as<int64_t>(), v.tidx.as<int32_t>(), v.tval.as<double>()};
     if (nnz > 0) {
         DevBuf rowof((size_t)nnz * 4), iota((size_t)nnz * 4), perm((size_t)nnz * 4), ksort((size_t)nnz * 4);
-        expand_rows_kernel<<<grid_for(m), 256, 0, st>>>(m, rowptr, rowof.as<int32_t>());
+        launch_expand_rows(m, rowptr, rowof.as<int32_t>(), st);
         iota_kernel<<<grid_for(nnz), 256, 0, st>>>(nnz, iota.as<int32_t>());
         LSRN_HIP(hipGetLastError());
         sort_pairs(reinterpret_cast<const uint32_t *>(colind), ksort.as<uint32_t>(), iota.as<int32_t>(),
@@ -333,11 +386,11 @@ size_t sparse_view_bytes(int64_t m, int64_t n, int64_t nnz) {
     return (size_t)(n + 1) * 8 + (size_t)nnz * 12 + (size_t)nnz * 16 + (size_t)nnz * 8 + seg;
 }
 
-// Split columns: column c of T with about e nonzeros per batch (of SK_KB
+// Split columns: column c of T with about e nonzeros per batch (of KB
 // rows) gets P = the power of two >= e / 4 slots (P = 1: not split), as
 // long as every block's extra slots fit in `room`; the largest columns are
 // split first.  sbase[c] = first extra slot of c within its block.
-int plan_split_columns(const SparseView &v, int C, int room, std::vector<int32_t> &sbase,
+int plan_split_columns(const SparseView &v, int C, int KB, int room, std::vector<int32_t> &sbase,
                        std::vector<int32_t> &nslot, hipStream_t st) {
     const int64_t d = v.d, K = v.K;
     std::vector<int64_t> ptr((size_t)d + 1);
@@ -352,7 +405,7 @@ int plan_split_columns(const SparseView &v, int C, int room, std::vector<int32_t
         const int64_t c0 = b * C, c1 = std::min<int64_t>(d, c0 + C);
         std::vector<std::pair<double, int64_t>> heavy;
         for (int64_t c = c0; c < c1; ++c) {
-            const double per_batch = (double)(ptr[(size_t)c + 1] - ptr[(size_t)c]) * SK_KB / (double)K;
+            const double per_batch = (double)(ptr[(size_t)c + 1] - ptr[(size_t)c]) * KB / (double)K;
             if (per_batch > 8.0) heavy.emplace_back(per_batch, c);
         }
         std::sort(heavy.begin(), heavy.end(), [](const auto &x, const auto &y) {
@@ -372,23 +425,80 @@ int plan_split_columns(const SparseView &v, int C, int room, std::vector<int32_t
     return most;
 }
 
+// Tile of the sparse sketch: S sketch rows x C columns of T per workgroup
+// (plus the split columns' slots), nz ranges of batches of rows of T.
+struct SkTile {
+    int S = 4, KB = sk_kb(4), C = 0, room = 0;
+    int64_t nb = 1, nbatch = 1, nz = 1, bpz = 1;
+};
+
+// The workgroup reads all entries of its column block once per S sketch
+// rows and generates its S rows of G over all K rows of T once per column
+// block.  S = 8 (C = 2048) halves the entry reads of S = 4 (C = 4096) at the
+// same generation of G when T has at most 2048 columns; a wider T keeps
+// S = 4, since narrower blocks would generate G once more per block.
+// (Measured, one sketch: 4e6 x 1024 with 8.4e7 nonzeros 327 / 228 / 472 ms
+// for S = 4 / 8 / 16; 2e6 x 2e4 with 4.2e7 nonzeros 3.41 / 5.21 / 10.6 s.)
+SkTile choose_tile(int64_t K, int64_t d, int64_t nnz, int64_t s) {
+    (void)nnz;
+    SkTile t;
+    t.S = d <= 2048 ? 8 : 4;
+    t.KB = sk_kb(t.S);
+    const int wmax = SK_LDS / t.S - t.KB;               // tile slots within the LDS
+    const int cmax = t.S == 8 ? 2048 : 4096;            // the rest: split columns' slots
+    t.C = (int)std::min<int64_t>((int64_t)cmax, d);
+    t.room = wmax - t.C;
+    t.nb = ceil_div(d, t.C);
+    t.nbatch = std::max<int64_t>(1, ceil_div(K, t.KB));
+    // fill the chip: split the rows of T into ranges when there are fewer
+    // tiles than CUs (one workgroup per CU fits in the LDS)
+    const int64_t tiles = ceil_div(s, t.S) * t.nb;
+    const int64_t cus = device_cus();
+    t.nz = tiles >= cus ? 1 : std::min<int64_t>(t.nbatch, ceil_div(cus, tiles));
+    t.bpz = ceil_div(t.nbatch, t.nz);
+    t.nz = ceil_div(t.nbatch, t.bpz);
+    return t;
+}
+
+// Device bytes of the sparse sketch's per-group offsets and partial sketches.
+size_t sketch_csr_tile_bytes(int64_t K, int64_t d, int64_t nnz, int64_t s) {
+    const SkTile t = choose_tile(K, d, nnz, s);
+    size_t bytes = (size_t)(t.nb * t.nbatch * SK_NT + 1) * sizeof(int64_t);
+    if (t.nz > 1) bytes += (size_t)t.nz * (size_t)s * (size_t)d * sizeof(double);
+    return bytes;
+}
+
+template <int S>
+void launch_sketch(const SkTile &t, const SkEntry *ent, const int64_t *optr, int64_t K, int64_t d, int W,
+                   int64_t s, uint64_t seed, const int32_t *sbase, const int32_t *nslot, double *out,
+                   int64_t zstride, hipStream_t st) {
+    // the dynamic-LDS limit (the most any call takes) is raised once per
+    // process: solves on several host threads (the serving runtime's
+    // workers) would otherwise set the attribute of the same kernel
+    // concurrently
+    static std::once_flag lds_once;
+    std::call_once(lds_once, [] {
+        LSRN_HIP(hipFuncSetAttribute((const void *)csr_sketch_kernel<S, SK_NT>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    });
+    const size_t lds = sizeof(double) * ((size_t)S * W + (size_t)S * t.KB);
+    dim3 grid((unsigned)ceil_div(s, S), (unsigned)t.nb, (unsigned)t.nz);
+    csr_sketch_kernel<S, SK_NT><<<grid, SK_NT, lds, st>>>(ent, optr, K, d, t.C, W, t.nbatch, t.bpz, s,
+                                                          seed, sbase, nslot, out, zstride);
+    LSRN_HIP(hipGetLastError());
+}
+
 void sketch_csr(const SparseView &v, double lambda, int64_t s, uint64_t seed, double *X,
                 hipStream_t st, double *kernel_ms) {
     const int64_t K = v.K, d = v.d, nnz = v.nnz;
-    // column slots per block (fewer than SK_C when T is narrower, which
-    // leaves the room to the split columns' slots)
-    const int C = (int)std::min<int64_t>(SK_C, d);
-    const int64_t nb = ceil_div(d, C);
-    const int64_t nbatch = std::max<int64_t>(1, ceil_div(K, SK_KB));
+    const SkTile tile = choose_tile(K, d, nnz, s);
+    const int C = tile.C;
+    const int64_t nb = tile.nb, nbatch = tile.nbatch;
     const int64_t ngroups = nb * nbatch * SK_NT;
     LSRN_REQUIRE(ngroups < ((int64_t)1 << 31), "sparse sketch: too many (column block, batch) groups");
     LSRN_REQUIRE(nb <= 65535, "sparse sketch: too many column blocks");
-    // LDS: the tile (C column slots + the split columns' slots) and the
-    // batch's slice of G, within 160 KiB
-    const int lds_max = 160 * 1024 / (int)sizeof(double);
-    const int room = lds_max / SK_S - C - SK_KB;
     std::vector<int32_t> sbase_h, nslot_h;
-    const int extra = plan_split_columns(v, C, std::max(room, 0), sbase_h, nslot_h, st);
+    const int extra = plan_split_columns(v, C, tile.KB, std::max(tile.room, 0), sbase_h, nslot_h, st);
     const int W = C + extra;
     DevBuf sbase((size_t)d * sizeof(int32_t)), nslot((size_t)d * sizeof(int32_t));
     LSRN_HIP(hipMemcpyAsync(sbase.as<int32_t>(), sbase_h.data(), (size_t)d * sizeof(int32_t),
@@ -401,9 +511,9 @@ void sketch_csr(const SparseView &v, double lambda, int64_t s, uint64_t seed, do
     if (nnz > 0) {
         DevBuf rowof((size_t)nnz * 4), keys((size_t)nnz * 4), ksort((size_t)nnz * 4);
         DevBuf iota((size_t)nnz * 4), perm((size_t)nnz * 4);
-        expand_rows_kernel<<<grid_for(t.nrows), 256, 0, st>>>(t.nrows, t.ptr, rowof.as<int32_t>());
-        sketch_keys_kernel<<<grid_for(nnz), 256, 0, st>>>(nnz, t.idx, rowof.as<int32_t>(), C, nbatch,
-                                                          sbase.as<int32_t>(), nslot.as<int32_t>(),
+        launch_expand_rows(t.nrows, t.ptr, rowof.as<int32_t>(), st);
+        sketch_keys_kernel<<<grid_for(nnz), 256, 0, st>>>(nnz, t.idx, rowof.as<int32_t>(), C, tile.KB,
+                                                          nbatch, sbase.as<int32_t>(), nslot.as<int32_t>(),
                                                           keys.as<uint32_t>());
         iota_kernel<<<grid_for(nnz), 256, 0, st>>>(nnz, iota.as<int32_t>());
         LSRN_HIP(hipGetLastError());
@@ -419,27 +529,26 @@ void sketch_csr(const SparseView &v, double lambda, int64_t s, uint64_t seed, do
     } else {
         LSRN_HIP(hipMemsetAsync(optr.as<int64_t>(), 0, (size_t)(ngroups + 1) * sizeof(int64_t), st));
     }
-    const size_t lds = sizeof(double) * ((size_t)SK_S * W + (size_t)SK_S * SK_KB);
-    // the dynamic-LDS limit (the most any call takes) is raised once per
-    // process: solves on several host threads (the serving runtime's
-    // workers) would otherwise set the attribute of the same kernel
-    // concurrently
-    static std::once_flag lds_once;
-    std::call_once(lds_once, [] {
-        LSRN_HIP(hipFuncSetAttribute((const void *)csr_sketch_kernel<SK_S, SK_NT>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-    });
+    // partial sketches of the row ranges (one range: X itself)
+    DevBuf part(tile.nz > 1 ? (size_t)tile.nz * (size_t)s * (size_t)d * sizeof(double) : 0);
+    double *out = tile.nz > 1 ? part.as<double>() : X;
+    const int64_t zstride = tile.nz > 1 ? s * d : 0;
     hipEvent_t ev[2] = {nullptr, nullptr};
     if (kernel_ms) {
         LSRN_HIP(hipEventCreate(&ev[0]));
         LSRN_HIP(hipEventCreate(&ev[1]));
         LSRN_HIP(hipEventRecord(ev[0], st));
     }
-    dim3 grid((unsigned)ceil_div(s, SK_S), (unsigned)nb);
-    csr_sketch_kernel<SK_S, SK_NT><<<grid, SK_NT, lds, st>>>(ent.as<SkEntry>(), optr.as<int64_t>(), K, d,
-                                                             C, W, nbatch, s, seed, sbase.as<int32_t>(),
-                                                             nslot.as<int32_t>(), X);
-    LSRN_HIP(hipGetLastError());
+    const SkEntry *e = ent.as<SkEntry>();
+    const int64_t *o = optr.as<int64_t>();
+    if (tile.S == 4)
+        launch_sketch<4>(tile, e, o, K, d, W, s, seed, sbase.as<int32_t>(), nslot.as<int32_t>(), out, zstride, st);
+    else
+        launch_sketch<8>(tile, e, o, K, d, W, s, seed, sbase.as<int32_t>(), nslot.as<int32_t>(), out, zstride, st);
+    if (tile.nz > 1) {
+        sum_partials_kernel<<<grid_for(s * d), 256, 0, st>>>(out, (int)tile.nz, s * d, X);
+        LSRN_HIP(hipGetLastError());
+    }
     if (kernel_ms) {
         LSRN_HIP(hipEventRecord(ev[1], st));
         LSRN_HIP(hipEventSynchronize(ev[1]));
@@ -450,7 +559,7 @@ void sketch_csr(const SparseView &v, double lambda, int64_t s, uint64_t seed, do
         (void)hipEventDestroy(ev[1]);
     }
     add_identity_rows(K, d, s, lambda, seed, X, st);
-    LSRN_HIP(hipStreamSynchronize(st));  // before ent / optr are freed
+    LSRN_HIP(hipStreamSynchronize(st));  // before ent / optr / part are freed
 }
 
 }  // namespace lsrn

@@ -95,6 +95,8 @@ void make_sparse_view(SparseView &v, int64_t m, int64_t n, int64_t nnz, const in
 size_t sparse_view_bytes(int64_t m, int64_t n, int64_t nnz);
 // X (s x d, column-major) = G T (+ lambda G(:, K + c) when tall and
 // lambda > 0).  Synchronises.
+// device bytes the sparse sketch allocates besides its nnz-sized arrays
+size_t sketch_csr_tile_bytes(int64_t K, int64_t d, int64_t nnz, int64_t s);
 void sketch_csr(const SparseView &v, double lambda, int64_t s, uint64_t seed, double *X,
                 hipStream_t st, double *kernel_ms = nullptr);
 
@@ -106,11 +108,15 @@ struct PrecondResult {
     double sigma_min_kept = 0.0;
     double t_jacobi_kernel_ms = 0.0;  // with profile: summed per-sweep spans
     int64_t jacobi_kernels = 0;
+    bool full_rank_inverse = false;   // P = R^-1 (certified full rank), no sweeps
 };
 // X: s x d column-major (overwritten).  P: d x d row-major (first r columns
-// hold V_r Sigma_r^{-1}); sigma: d values, descending.  Synchronises.
+// hold V_r Sigma_r^{-1}); sigma: d values, descending.  With try_full_rank,
+// a sketch whose R is certified to keep every singular value under the
+// cutoff gets P = R^-1 instead (no Jacobi sweeps; sigma = |diag R|
+// descending).  Synchronises.
 PrecondResult precond(int64_t s, int64_t d, double *X, double rcond, double *sigma, double *P,
-                      hipStream_t st, bool profile = false);
+                      hipStream_t st, bool profile = false, bool try_full_rank = false);
 // precond for `count` sketches at once: the QR of each, then the Jacobi
 // sweeps of all problems with d <= 512 in shared launches (wider ones one
 // at a time).  X[p] is overwritten.

@@ -1150,7 +1150,24 @@ __global__ void __launch_bounds__(CRP_NT) csr_row_pass_kernel(CsrArgs a) {
         if (OP != OP_ATB) {
             if (row < a.K) {
                 const int64_t e0 = a.t.ptr[row], e1 = a.t.ptr[row + 1];
-                for (int64_t e = e0 + l; e < e1; e += CRP_G) q += a.t.val[e] * a.w[a.t.idx[e]];
+                // the row's first 4 CRP_G entries: indices and values, then
+                // the gathered w, all requested before any is used (the
+                // summation order is that of the plain loop)
+                constexpr int U = 4;
+                int32_t ix[U];
+                double vv[U], ww[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t e = e0 + l + CRP_G * u;
+                    ix[u] = e < e1 ? a.t.idx[e] : -1;
+                    vv[u] = e < e1 ? a.t.val[e] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) ww[u] = ix[u] >= 0 ? a.w[ix[u]] : 0.0;
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (ix[u] >= 0) q += vv[u] * ww[u];
+                for (int64_t e = e0 + l + CRP_G * U; e < e1; e += CRP_G) q += a.t.val[e] * a.w[a.t.idx[e]];
                 q = group8_sum(q);
             } else {
                 q = a.lambda * a.w[row - a.K];
@@ -1193,23 +1210,44 @@ csr_col_seg_kernel(CsrMat ct, const int32_t *__restrict__ seg_row,
     const int j = seg_row[g];
     const int64_t e0 = ct.ptr[j] + (g - row_seg[j]) * SparseView::kColSeg;
     const int64_t e1 = min(e0 + SparseView::kColSeg, ct.ptr[j + 1]);
+    // a segment holds at most 8 entries per lane: every index and value is
+    // loaded first, then every gathered y, so the lane waits for two load
+    // latencies rather than two per entry
+    constexpr int U = (int)(SparseView::kColSeg / 64);
+    int32_t ix[U];
+    double vv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t e = e0 + lane + 64 * u;
+        ix[u] = e < e1 ? ct.idx[e] : -1;
+        vv[u] = e < e1 ? ct.val[e] : 0.0;
+    }
+    double yy[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) yy[u] = ix[u] >= 0 ? y[ix[u]] : 0.0;
     double t = 0.0;
-    for (int64_t e = e0 + lane; e < e1; e += 64) t += ct.val[e] * y[ct.idx[e]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) t += vv[u] * yy[u];
     t = wave_sum(t);
     if (lane == 0) zseg[g] = t;
 }
 
-// z_j = the segments of column j summed in order (+ lambda y_{K+j}).
+// z_j = the segments of column j summed (+ lambda y_{K+j}): one wavefront
+// per column, lane l summing segments l, l + 64, ... in order, then the
+// wavefront's fixed butterfly, so a column of many segments (a long row of
+// a fat A) does not serialise one thread.
 __global__ void __launch_bounds__(256)
 csr_col_combine_kernel(const int32_t *__restrict__ row_seg, int64_t d,
                        const double *__restrict__ zseg, const double *__restrict__ y, double lambda,
                        int64_t K, double *__restrict__ z, const State *st) {
     if (st && st->done) return;
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (j >= d) return;
+    const int lane = threadIdx.x & 63;
     double t = 0.0;
-    for (int g = row_seg[j]; g < row_seg[j + 1]; ++g) t += zseg[g];
-    z[j] = lambda > 0.0 ? t + lambda * y[K + j] : t;
+    for (int g = row_seg[j] + lane; g < row_seg[j + 1]; g += 64) t += zseg[g];
+    t = wave_sum(t);
+    if (lane == 0) z[j] = lambda > 0.0 ? t + lambda * y[K + j] : t;
 }
 
 // st->acc = sums of the row-pass partials (fixed order).
@@ -1547,7 +1585,7 @@ struct Ctx {
         csr_col_seg_kernel<<<(unsigned)ceil_div(pb.sp->nseg, CCP_NT / 64), CCP_NT, 0, st>>>(
             pb.sp->cols, pb.sp->seg_row.as<int32_t>(), pb.sp->row_seg.as<int32_t>(), pb.sp->nseg, y,
             zseg.as<double>(), state);
-        csr_col_combine_kernel<<<(unsigned)ceil_div(L, 256), 256, 0, st>>>(
+        csr_col_combine_kernel<<<(unsigned)ceil_div(L, 4), 256, 0, st>>>(
             pb.sp->row_seg.as<int32_t>(), L, zseg.as<double>(), y, pb.lambda, pb.rows, z.as<double>(),
             state);
         LSRN_HIP(hipGetLastError());

@@ -46,7 +46,8 @@ __device__ __forceinline__ bf16x8 load8(const uint16_t *p) {
 }
 
 // G for the 128 rows x 32 k of a stage: 128 rows x 8 Philox blocks, four
-// per thread; Gs[row][k] (k contiguous).
+// per thread; Gs[row][k] (k contiguous), each block's four values stored
+// as one 8-byte vector.
 __device__ __forceinline__ void gen_g(uint16_t (*Gs)[HP], uint64_t seed, int64_t m0, int64_t k0) {
     const int t = threadIdx.x;
     const int row = t & (HBM_ - 1);
@@ -56,57 +57,58 @@ __device__ __forceinline__ void gen_g(uint16_t (*Gs)[HP], uint64_t seed, int64_t
         const int q = qb + 2 * h;  // 0..7
         double g[4];
         gauss4(seed, (uint64_t)(m0 + row), (uint64_t)((k0 >> 2) + q), g);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) Gs[row][4 * q + j] = bf16_rn((float)g[j]);
+        uint2 v;
+        v.x = (uint32_t)bf16_rn((float)g[0]) | ((uint32_t)bf16_rn((float)g[1]) << 16);
+        v.y = (uint32_t)bf16_rn((float)g[2]) | ((uint32_t)bf16_rn((float)g[3]) << 16);
+        *reinterpret_cast<uint2 *>(&Gs[row][4 * q]) = v;
     }
 }
 
-// T tile (32 k x 128 columns, FP64 row-major) into registers: thread t takes
-// column pair (t & 63) * 2 of rows (t >> 6) + 4 r, r = 0..7.
+// T tile (32 k x 128 columns, FP64 row-major) into registers: thread t
+// takes column t & 127 of rows 16 (t >> 7) + j, j = 0..15 (each load of a
+// wavefront reads 64 consecutive columns of one row).
 __device__ __forceinline__ void load_t(const double *__restrict__ T, int64_t ldt, int64_t k0,
-                                       int64_t K, int64_t n0, int64_t d, bool vec2,
-                                       double2 (&reg)[8]) {
+                                       int64_t K, int64_t n0, int64_t d, double (&reg)[16]) {
     const int t = threadIdx.x;
-    const int c2 = (t & 63) * 2;
-    const int kr = t >> 6;
-    const int64_t col = n0 + c2;
+    const int64_t col = n0 + (t & (HBN - 1));
+    const int64_t kb = k0 + 16 * (t >> 7);
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        const int64_t k = k0 + kr + 4 * r;
-        double2 v = make_double2(0.0, 0.0);
-        if (k < K) {
-            const double *p = T + k * ldt + col;
-            if (vec2 && col + 1 < d) {
-                v = *reinterpret_cast<const double2 *>(p);
-            } else {
-                if (col < d) v.x = p[0];
-                if (col + 1 < d) v.y = p[1];
-            }
-        }
-        reg[r] = v;
+    for (int j = 0; j < 16; ++j) {
+        const int64_t k = kb + j;
+        reg[j] = (k < K && col < d) ? T[k * ldt + col] : 0.0;
     }
 }
 
-// Split and store: As[term][col][k].
-__device__ __forceinline__ void store_t(uint16_t (*As)[HBN][HP], const double2 (&reg)[8]) {
+// Split and store: As[term][col][k], the 16 values of k of a thread as two
+// 16-byte vectors per term.
+__device__ __forceinline__ void store_t(uint16_t (*As)[HBN][HP], const double (&reg)[16]) {
     const int t = threadIdx.x;
-    const int c2 = (t & 63) * 2;
-    const int kr = t >> 6;
+    const int c = t & (HBN - 1);
+    const int kb = 16 * (t >> 7);
+    uint32_t w[3][8];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        const int k = kr + 4 * r;
+    for (int j = 0; j < 16; j += 2) {
+        uint32_t lo[3], hi[3];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const float f = (float)(h ? reg[r].y : reg[r].x);
+            const float f = (float)reg[j + h];
             const uint16_t t1 = bf16_rn(f);
             const float r1 = f - bf16_to_f32(t1);
             const uint16_t t2 = bf16_rn(r1);
             const float r2 = r1 - bf16_to_f32(t2);
             const uint16_t t3 = bf16_rn(r2);
-            As[0][c2 + h][k] = t1;
-            As[1][c2 + h][k] = t2;
-            As[2][c2 + h][k] = t3;
+            (h ? hi : lo)[0] = t1;
+            (h ? hi : lo)[1] = t2;
+            (h ? hi : lo)[2] = t3;
         }
+#pragma unroll
+        for (int term = 0; term < 3; ++term) w[term][j / 2] = lo[term] | (hi[term] << 16);
+    }
+#pragma unroll
+    for (int term = 0; term < 3; ++term) {
+        uint4 *dst = reinterpret_cast<uint4 *>(&As[term][c][kb]);
+        dst[0] = make_uint4(w[term][0], w[term][1], w[term][2], w[term][3]);
+        dst[1] = make_uint4(w[term][4], w[term][5], w[term][6], w[term][7]);
     }
 }
 
@@ -124,7 +126,6 @@ sketch_bf16_kernel(const double *__restrict__ T, int64_t ldt, int64_t K, int64_t
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave >> 1, wn = wave & 1;  // 2 x 2 wavefronts
     const int lr = lane & 15, lk = lane >> 4;
-    const bool vec2 = ((ldt & 1) == 0) && ((reinterpret_cast<uintptr_t>(T) & 15) == 0);
 
     f32x4 acc[4][4];
     double acc64[4][4][4];
@@ -137,15 +138,15 @@ sketch_bf16_kernel(const double *__restrict__ T, int64_t ldt, int64_t K, int64_t
             for (int v = 0; v < 4; ++v) acc64[i][j][v] = 0.0;
         }
     const int64_t nstage = kend > kbeg ? ceil_div(kend - kbeg, HKT) : 0;
-    double2 treg[8];
-    if (nstage > 0) load_t(T, ldt, kbeg, kend, n0, d, vec2, treg);
+    double treg[16];
+    if (nstage > 0) load_t(T, ldt, kbeg, kend, n0, d, treg);
     for (int64_t st = 0; st < nstage; ++st) {
         const int64_t k0 = kbeg + st * HKT;
         __syncthreads();  // the previous stage's operands are consumed
         store_t(As, treg);
         gen_g(Gs, seed, m0, k0);
         __syncthreads();
-        if (st + 1 < nstage) load_t(T, ldt, k0 + HKT, kend, n0, d, vec2, treg);
+        if (st + 1 < nstage) load_t(T, ldt, k0 + HKT, kend, n0, d, treg);
         // rows of T past the end of the slice were loaded as zero and the
         // G values there are finite, so their products vanish
         bf16x8 a[4];

@@ -1004,14 +1004,15 @@ void launch_apply(double *X, int64_t s, int64_t p0, int nb, int64_t ncols, const
 }
 
 size_t lds_limit() {
-    static size_t lim = 0;
-    if (!lim) {
+    static const size_t lim = [] {  // queried once (a thread-safe static)
         int dev = 0, v = 0;
-        LSRN_HIP(hipGetDevice(&dev));
-        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+            (void)hipGetLastError();
             v = 65536;
-        lim = (size_t)v;
-    }
+        }
+        return (size_t)v;
+    }();
     return lim;
 }
 
@@ -1242,13 +1243,85 @@ void precond_finish(int64_t s, int64_t d, const double *Y, double rcond, double 
     LSRN_HIP(hipStreamSynchronize(st));
 }
 
+// Sums of squares of the upper triangle of R (column j: rows 0 .. j, leading
+// dimension ldr) and of all of Ri (d x d, leading dimension d), one
+// workgroup per column: part[j] and part[d + j].
+__global__ void __launch_bounds__(256)
+col_sumsq_kernel(const double *__restrict__ R, int64_t ldr, const double *__restrict__ Ri, int64_t d,
+                 double *__restrict__ part) {
+    __shared__ double red[2][4];
+    const int64_t j = blockIdx.x;
+    const int tid = threadIdx.x;
+    double a = 0.0, b = 0.0;
+    for (int64_t i = tid; i <= j; i += 256) {
+        const double v = R[j * ldr + i];
+        a += v * v;
+    }
+    for (int64_t i = tid; i < d; i += 256) {
+        const double v = Ri[j * d + i];
+        b += v * v;
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if ((tid & 63) == 0) {
+        red[0][tid >> 6] = a;
+        red[1][tid >> 6] = b;
+    }
+    __syncthreads();
+    if (tid < 2) part[tid * d + j] = red[tid][0] + red[tid][1] + red[tid][2] + red[tid][3];
+}
+
+// The full-rank case of steps 4-5 without the Jacobi sweeps.  With X = Q R,
+// N = R^-1 gives T N the singular values of T V Sigma^-1 (R^-1 = V Sigma^-1
+// times an orthogonal factor), so it preconditions as well (reading of
+// Sec. 4 on the range and spectrum of N).  It is taken only when the SVD
+// would keep every singular value: kappa_2(R) <= |R|_F |R^-1|_F, so
+// |R|_F |R^-1|_F <= 1 / (2 rc) certifies sigma_min > rc sigma_1, the
+// cutoff of the SVD path.  sigma receives |diag R| in descending order;
+// sigma_max / sigma_min_kept are |R|_F and 1 / |R^-1|_F (bounds that
+// enclose the true extremes).  False (nothing written to P) otherwise.
+bool full_rank_inverse(int64_t s, int64_t d, const double *R, double rcond, double *sigma, double *P,
+                       PrecondResult &res, hipStream_t st) {
+    const double rc = rcond > 0.0 ? rcond : (double)std::max(s, d) * DBL_EPSILON;
+    DevBuf Ri((size_t)d * (size_t)d * sizeof(double)), part((size_t)2 * d * sizeof(double));
+    trtri_upper(d, R, s, Ri.as<double>(), d, st);
+    col_sumsq_kernel<<<(unsigned)d, 256, 0, st>>>(R, s, Ri.as<double>(), d, part.as<double>());
+    LSRN_HIP(hipGetLastError());
+    std::vector<double> h((size_t)2 * d);
+    LSRN_HIP(hipMemcpyAsync(h.data(), part.as<double>(), h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    LSRN_HIP(hipStreamSynchronize(st));
+    double sr = 0.0, si = 0.0;
+    for (int64_t j = 0; j < d; ++j) {
+        sr += h[(size_t)j];
+        si += h[(size_t)(d + j)];
+    }
+    const double nr = std::sqrt(sr), ni = std::sqrt(si);
+    if (!(nr > 0.0 && nr * ni <= 0.5 / rc)) return false;  // NaN / inf fail too
+    transpose(d, d, Ri.as<double>(), d, P, st);  // P row-major = R^-1
+    diag_abs_kernel<<<grid1d(d), 256, 0, st>>>(R, s, d, sigma);
+    LSRN_HIP(hipGetLastError());
+    std::vector<double> g((size_t)d);
+    LSRN_HIP(hipMemcpyAsync(g.data(), sigma, (size_t)d * sizeof(double), hipMemcpyDeviceToHost, st));
+    LSRN_HIP(hipStreamSynchronize(st));
+    std::sort(g.begin(), g.end(), [](double a, double b) { return a > b; });
+    LSRN_HIP(hipMemcpyAsync(sigma, g.data(), (size_t)d * sizeof(double), hipMemcpyHostToDevice, st));
+    LSRN_HIP(hipStreamSynchronize(st));  // before g and Ri go
+    res.rank = d;
+    res.sweeps = 0;
+    res.sigma_max = nr;
+    res.sigma_min_kept = 1.0 / ni;
+    res.full_rank_inverse = true;
+    return true;
+}
+
 }  // namespace
 
 PrecondResult precond(int64_t s, int64_t d, double *X, double rcond, double *sigma, double *P,
-                      hipStream_t st, bool profile) {
+                      hipStream_t st, bool profile, bool try_full_rank) {
     LSRN_REQUIRE(s >= d && d > 0, "precond: need s >= d > 0");
     PrecondResult res;
     householder_qr(s, d, X, st);
+    if (try_full_rank && full_rank_inverse(s, d, X, rcond, sigma, P, res, st)) return res;
     // ---- Jacobi on Y = R^T
     const JacobiPlan pl = jacobi_plan(d);
     DevBuf Yb((size_t)d * (size_t)pl.dcols * sizeof(double));
@@ -1481,6 +1554,7 @@ PrecondResult precond_qr_inverse(int64_t s, int64_t d, double *X, double rcond, 
     res.rank = d;
     res.sigma_max = h[0];
     res.sigma_min_kept = h[(size_t)d - 1];
+    res.full_rank_inverse = true;
     return res;
 }
 

@@ -46,7 +46,8 @@ class Info(C.Structure):
                 ("t_sketch_kernel_ms", C.c_double), ("t_sweep_kernel_ms", C.c_double),
                 ("sketch_kernels", C.c_int64), ("sweep_kernels", C.c_int64),
                 ("t_jacobi_kernel_ms", C.c_double), ("jacobi_kernels", C.c_int64),
-                ("fp64_refine_steps", C.c_int64), ("cs_fallbacks", C.c_int64)]
+                ("fp64_refine_steps", C.c_int64), ("cs_fallbacks", C.c_int64),
+                ("precond_used", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -49,6 +49,8 @@ def ocsr(orc, S, lam=0.0):
     (20000, 5000, 6, 1e-3, 41),      # tall, two column blocks (4096 + 904), Tikhonov rows
     (1500, 30000, 4, 0.0, 18),       # fat: T = A^T (transposed structure), 30000 rows of T
     (257, 9, 3, 0.0, 19),            # tiny, rows of T not a multiple of the batch
+    (20000, 5000, 1, 0.0, 41),       # ~1.6 nonzeros per row: 4 sketch rows per tile, rows split
+    (20000, 1024, 20, 0.0, 4096),    # 8 sketch rows per tile, 512 tiles (rows of T not split)
 ])
 def test_sketch_csr_matches_oracle(L, orc, m, n, per_row, lam, s):
     S = workloads.sparse_problem(m, n, per_row=per_row, n_dense=2, fill=0.3, seed=m + n)

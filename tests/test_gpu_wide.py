@@ -151,14 +151,20 @@ def test_wide_solves_reach_oracle_reference(L, orc, d, shape):
     ref2, _, _, _ = orc.lsrn_iterate(M, b, Pn2, s, refine=3)
     floor = rel(ref2, ref)
     T_d, b_d = dev(T), dev(b)
-    for method in (0, 1):
-        x, info = L.solve_dense(T_d, b_d, layout=layout, seed=2024, method=method, refine=2)
-        err = rel(host(x), ref)
-        print(f"d={d} {shape} method={method} rank={info['rank']} iters={info['iters']} "
-              f"refine_steps={info['refine_steps']} rel_err_vs_oracle={err:.2e} "
-              f"oracle_floor={floor:.2e} (oracle {t_orc:.1f} s)", flush=True)
-        assert info["rank"] == d
-        assert err <= max(1e-10, 3.0 * floor)
+    # the automatic choice certifies these full-rank sketches and takes
+    # N = R^-1; the SVD path is forced beside it
+    for precond, used in (("auto", L.PRECOND["qr"]), ("svd", L.PRECOND["svd"])):
+        for method in (0, 1):
+            x, info = L.solve_dense(T_d, b_d, layout=layout, seed=2024, method=method, refine=2,
+                                    precond=precond)
+            err = rel(host(x), ref)
+            print(f"d={d} {shape} precond={precond} method={method} rank={info['rank']} "
+                  f"sweeps={info['sweeps']} iters={info['iters']} "
+                  f"refine_steps={info['refine_steps']} rel_err_vs_oracle={err:.2e} "
+                  f"oracle_floor={floor:.2e} (oracle {t_orc:.1f} s)", flush=True)
+            assert info["rank"] == d and info["precond_used"] == used
+            assert (info["sweeps"] == 0) == (precond == "auto")
+            assert err <= max(1e-10, 3.0 * floor)
     if shape == "tall":
         assert floor <= 1e-11      # a full-rank tall problem has no such floor
 
@@ -203,7 +209,9 @@ def test_full_size_rank_deficient_vs_oracle(L, orc, fat):
     print(f"{'fat' if fat else 'tall'} full size: rank={info['rank']} iters={info['iters']} "
           f"(oracle {it_o}, {t_orc:.1f} s) rel_err_vs_oracle={err:.2e} "
           f"oracle_floor={floor:.2e}", flush=True)
-    assert info["rank"] == rank
+    # the automatic choice finds no certificate for a rank-deficient sketch
+    # and takes the SVD
+    assert info["rank"] == rank and info["precond_used"] == L.PRECOND["svd"] and info["sweeps"] > 0
     assert err <= max(1e-10, 3.0 * floor)
 
 
@@ -229,6 +237,7 @@ def test_replica_1e6x4000_kappa_vs_oracle(L, orc, precision):
         x, info = L.solve_dense(A, b, seed=2024, refine=refine, tol=1e-14, precision=precision)
         errs[refine] = rel(host(x), ref)
         print(f"replica {precision} kappa={1 / smin:.0e} refine={refine}: rank={info['rank']} "
+              f"precond_used={info['precond_used']} "
               f"iters={info['iters']} refine_steps={info['refine_steps']} "
               f"fp64_steps={info['fp64_refine_steps']} rel_err_vs_oracle={errs[refine]:.2e} "
               f"(oracle {t_orc:.1f} s)", flush=True)
