@@ -33,14 +33,13 @@ namespace lsrn {
 
 namespace {
 
-constexpr int SK_NT = 512;  // threads of the sketch kernel
 constexpr int SK_PF = 8;    // entries per thread loaded one batch ahead
 constexpr int SK_LDS = 160 * 1024 / (int)sizeof(double);  // doubles of LDS per workgroup
 
-// Rows of T per batch for S sketch rows per workgroup: every thread
-// generates one Philox block (4 entries of G) per batch, so the slice of G
-// is S x KB = 4 NT entries for every S.
-constexpr int sk_kb(int S) { return 4 * (SK_NT / S); }
+// Rows of T per batch for S sketch rows per workgroup of NT threads: every
+// thread generates one Philox block (4 entries of G) per batch, so the
+// slice of G is S x KB = 4 NT entries.
+constexpr int sk_kb(int S, int NT) { return 4 * (NT / S); }
 
 struct SkEntry {
     int32_t k;  // row of T
@@ -129,7 +128,7 @@ __device__ __forceinline__ int sketch_slot(int32_t c, int32_t k, int C,
 // writer thread of its slot); the stable sort keeps the rows in order
 // within a key.
 __global__ void sketch_keys_kernel(int64_t nnz, const int32_t *__restrict__ idx,
-                                   const int32_t *__restrict__ rowof, int C, int KB, int64_t nbatch,
+                                   const int32_t *__restrict__ rowof, int C, int KB, int NT, int64_t nbatch,
                                    const int32_t *__restrict__ sbase,
                                    const int32_t *__restrict__ nslot, uint32_t *__restrict__ keys) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz;
@@ -137,7 +136,7 @@ __global__ void sketch_keys_kernel(int64_t nnz, const int32_t *__restrict__ idx,
         const int32_t c = idx[e], k = rowof[e];
         const int64_t batch = k / KB;
         const int slot = sketch_slot(c, k, C, sbase, nslot);
-        keys[e] = (uint32_t)(((int64_t)(c / C) * nbatch + batch) * SK_NT + (slot % SK_NT));
+        keys[e] = (uint32_t)(((int64_t)(c / C) * nbatch + batch) * NT + (slot % NT));
     }
 }
 
@@ -428,24 +427,28 @@ int plan_split_columns(const SparseView &v, int C, int KB, int room, std::vector
 // Tile of the sparse sketch: S sketch rows x C columns of T per workgroup
 // (plus the split columns' slots), nz ranges of batches of rows of T.
 struct SkTile {
-    int S = 4, KB = sk_kb(4), C = 0, room = 0;
+    int S = 4, NT = 1024, KB = sk_kb(4, 1024), C = 0, room = 0;
     int64_t nb = 1, nbatch = 1, nz = 1, bpz = 1;
 };
 
 // The workgroup reads all entries of its column block once per S sketch
 // rows and generates its S rows of G over all K rows of T once per column
-// block.  S = 8 (C = 2048) halves the entry reads of S = 4 (C = 4096) at the
-// same generation of G when T has at most 2048 columns; a wider T keeps
-// S = 4, since narrower blocks would generate G once more per block.
-// (Measured, one sketch: 4e6 x 1024 with 8.4e7 nonzeros 327 / 228 / 472 ms
-// for S = 4 / 8 / 16; 2e6 x 2e4 with 4.2e7 nonzeros 3.41 / 5.21 / 10.6 s.)
+// block.  S = 8 (C = 2048, 512 threads) halves the entry reads of S = 4 at
+// the same generation of G when T has at most 2048 columns; a wider T keeps
+// S = 4, since narrower blocks would generate G once more per block, with
+// 1024 threads (C = 3584), whose extra wavefronts hide the latency of the
+// uneven per-thread work.  (Measured, one sketch: 4e6 x 1024 with 8.4e7
+// nonzeros 327 / 228 / 472 ms for S = 4 / 8 / 16 at 512 threads, 266 ms for
+// S = 8 at 1024; 2e6 x 2e4 with 4.2e7 nonzeros 3.41 / 5.21 / 10.6 s at 512
+// threads, 2.93 s for S = 4 at 1024.)
 SkTile choose_tile(int64_t K, int64_t d, int64_t nnz, int64_t s) {
     (void)nnz;
     SkTile t;
     t.S = d <= 2048 ? 8 : 4;
-    t.KB = sk_kb(t.S);
+    t.NT = t.S == 8 ? 512 : 1024;
+    t.KB = sk_kb(t.S, t.NT);
     const int wmax = SK_LDS / t.S - t.KB;               // tile slots within the LDS
-    const int cmax = t.S == 8 ? 2048 : 4096;            // the rest: split columns' slots
+    const int cmax = t.S == 8 ? 2048 : 3584;            // the rest: split columns' slots
     t.C = (int)std::min<int64_t>((int64_t)cmax, d);
     t.room = wmax - t.C;
     t.nb = ceil_div(d, t.C);
@@ -463,12 +466,12 @@ SkTile choose_tile(int64_t K, int64_t d, int64_t nnz, int64_t s) {
 // Device bytes of the sparse sketch's per-group offsets and partial sketches.
 size_t sketch_csr_tile_bytes(int64_t K, int64_t d, int64_t nnz, int64_t s) {
     const SkTile t = choose_tile(K, d, nnz, s);
-    size_t bytes = (size_t)(t.nb * t.nbatch * SK_NT + 1) * sizeof(int64_t);
+    size_t bytes = (size_t)(t.nb * t.nbatch * t.NT + 1) * sizeof(int64_t);
     if (t.nz > 1) bytes += (size_t)t.nz * (size_t)s * (size_t)d * sizeof(double);
     return bytes;
 }
 
-template <int S>
+template <int S, int NT>
 void launch_sketch(const SkTile &t, const SkEntry *ent, const int64_t *optr, int64_t K, int64_t d, int W,
                    int64_t s, uint64_t seed, const int32_t *sbase, const int32_t *nslot, double *out,
                    int64_t zstride, hipStream_t st) {
@@ -478,12 +481,12 @@ void launch_sketch(const SkTile &t, const SkEntry *ent, const int64_t *optr, int
     // concurrently
     static std::once_flag lds_once;
     std::call_once(lds_once, [] {
-        LSRN_HIP(hipFuncSetAttribute((const void *)csr_sketch_kernel<S, SK_NT>,
+        LSRN_HIP(hipFuncSetAttribute((const void *)csr_sketch_kernel<S, NT>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
     });
     const size_t lds = sizeof(double) * ((size_t)S * W + (size_t)S * t.KB);
     dim3 grid((unsigned)ceil_div(s, S), (unsigned)t.nb, (unsigned)t.nz);
-    csr_sketch_kernel<S, SK_NT><<<grid, SK_NT, lds, st>>>(ent, optr, K, d, t.C, W, t.nbatch, t.bpz, s,
+    csr_sketch_kernel<S, NT><<<grid, NT, lds, st>>>(ent, optr, K, d, t.C, W, t.nbatch, t.bpz, s,
                                                           seed, sbase, nslot, out, zstride);
     LSRN_HIP(hipGetLastError());
 }
@@ -494,7 +497,7 @@ void sketch_csr(const SparseView &v, double lambda, int64_t s, uint64_t seed, do
     const SkTile tile = choose_tile(K, d, nnz, s);
     const int C = tile.C;
     const int64_t nb = tile.nb, nbatch = tile.nbatch;
-    const int64_t ngroups = nb * nbatch * SK_NT;
+    const int64_t ngroups = nb * nbatch * tile.NT;
     LSRN_REQUIRE(ngroups < ((int64_t)1 << 31), "sparse sketch: too many (column block, batch) groups");
     LSRN_REQUIRE(nb <= 65535, "sparse sketch: too many column blocks");
     std::vector<int32_t> sbase_h, nslot_h;
@@ -513,7 +516,7 @@ void sketch_csr(const SparseView &v, double lambda, int64_t s, uint64_t seed, do
         DevBuf iota((size_t)nnz * 4), perm((size_t)nnz * 4);
         launch_expand_rows(t.nrows, t.ptr, rowof.as<int32_t>(), st);
         sketch_keys_kernel<<<grid_for(nnz), 256, 0, st>>>(nnz, t.idx, rowof.as<int32_t>(), C, tile.KB,
-                                                          nbatch, sbase.as<int32_t>(), nslot.as<int32_t>(),
+                                                          tile.NT, nbatch, sbase.as<int32_t>(), nslot.as<int32_t>(),
                                                           keys.as<uint32_t>());
         iota_kernel<<<grid_for(nnz), 256, 0, st>>>(nnz, iota.as<int32_t>());
         LSRN_HIP(hipGetLastError());
@@ -542,9 +545,11 @@ void sketch_csr(const SparseView &v, double lambda, int64_t s, uint64_t seed, do
     const SkEntry *e = ent.as<SkEntry>();
     const int64_t *o = optr.as<int64_t>();
     if (tile.S == 4)
-        launch_sketch<4>(tile, e, o, K, d, W, s, seed, sbase.as<int32_t>(), nslot.as<int32_t>(), out, zstride, st);
+        launch_sketch<4, 1024>(tile, e, o, K, d, W, s, seed, sbase.as<int32_t>(), nslot.as<int32_t>(), out, zstride,
+                               st);
     else
-        launch_sketch<8>(tile, e, o, K, d, W, s, seed, sbase.as<int32_t>(), nslot.as<int32_t>(), out, zstride, st);
+        launch_sketch<8, 512>(tile, e, o, K, d, W, s, seed, sbase.as<int32_t>(), nslot.as<int32_t>(), out, zstride,
+                              st);
     if (tile.nz > 1) {
         sum_partials_kernel<<<grid_for(s * d), 256, 0, st>>>(out, (int)tile.nz, s * d, X);
         LSRN_HIP(hipGetLastError());

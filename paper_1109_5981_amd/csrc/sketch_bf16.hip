@@ -30,6 +30,7 @@ constexpr int HKT = 32;    // k per stage
 constexpr int HP = 40;     // LDS pitch (bf16) of a row of 32 k: 80 bytes
 constexpr int HNT = 256;
 constexpr int FLUSH = 8;   // stages accumulated in FP32 before the FP64 flush
+constexpr size_t kPreGenMaxBytes = (size_t)32 << 30;  // largest pre-generated bf16(G)
 
 // FP32 -> BF16 bits, round to nearest even (finite inputs).
 __device__ __forceinline__ uint16_t bf16_rn(float f) {
@@ -112,9 +113,53 @@ __device__ __forceinline__ void store_t(uint16_t (*As)[HBN][HP], const double (&
     }
 }
 
+// bf16(G) for the whole sketch, generated once: panel p (k = 32 p ..
+// 32 p + 31) holds rows 0 .. s - 1, each as 32 consecutive values of k, so
+// the 128 x 32 tile of a stage is one contiguous 8 KB block.  One thread per
+// Philox block (row, four values of k); the values are those gen_g forms.
+__global__ void __launch_bounds__(256)
+gauss_bf16_panels_kernel(uint64_t seed, int64_t s, int64_t npanel, uint16_t *__restrict__ Gb) {
+    const int64_t total = npanel * s * 8;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = t / (s * 8), rem = t % (s * 8);
+        const int64_t row = rem >> 3;
+        const int qq = (int)(rem & 7);
+        double g[4];
+        gauss4(seed, (uint64_t)row, (uint64_t)(8 * p + qq), g);
+        uint2 v;
+        v.x = (uint32_t)bf16_rn((float)g[0]) | ((uint32_t)bf16_rn((float)g[1]) << 16);
+        v.y = (uint32_t)bf16_rn((float)g[2]) | ((uint32_t)bf16_rn((float)g[3]) << 16);
+        *reinterpret_cast<uint2 *>(Gb + ((p * s + row) * 32 + 4 * qq)) = v;
+    }
+}
+
+// The stage's 128 x 32 tile of a pre-generated G into registers: thread t
+// takes 16 values of k (half t & 1) of row t >> 1 (rows past s repeat row
+// s - 1: their sketch rows are not written).
+__device__ __forceinline__ void load_g(const uint16_t *__restrict__ Gb, int64_t s, int64_t m0, int64_t k0,
+                                       uint4 (&reg)[2]) {
+    const int t = threadIdx.x;
+    const int64_t row = min(m0 + (t >> 1), s - 1);
+    const uint4 *src = reinterpret_cast<const uint4 *>(Gb + (((k0 >> 5) * s + row) * 32 + 16 * (t & 1)));
+    reg[0] = src[0];
+    reg[1] = src[1];
+}
+
+__device__ __forceinline__ void store_g(uint16_t (*Gs)[HP], const uint4 (&reg)[2]) {
+    const int t = threadIdx.x;
+    uint4 *dst = reinterpret_cast<uint4 *>(&Gs[t >> 1][16 * (t & 1)]);
+    dst[0] = reg[0];
+    dst[1] = reg[1];
+}
+
+// PRE: G comes from the pre-generated panels Gb, else each stage generates
+// its tile (gen_g).
+template <bool PRE>
 __global__ void __launch_bounds__(HNT, 1)
 sketch_bf16_kernel(const double *__restrict__ T, int64_t ldt, int64_t K, int64_t d, int64_t s,
-                   uint64_t seed, int64_t k_per_split, int tiles_m, double *__restrict__ Xp) {
+                   uint64_t seed, const uint16_t *__restrict__ Gb, int64_t k_per_split, int tiles_m,
+                   double *__restrict__ Xp) {
     __shared__ uint16_t Gs[HBM_][HP];
     __shared__ uint16_t As[3][HBN][HP];
     const int tile = blockIdx.x;
@@ -139,14 +184,22 @@ sketch_bf16_kernel(const double *__restrict__ T, int64_t ldt, int64_t K, int64_t
         }
     const int64_t nstage = kend > kbeg ? ceil_div(kend - kbeg, HKT) : 0;
     double treg[16];
-    if (nstage > 0) load_t(T, ldt, kbeg, kend, n0, d, treg);
+    uint4 greg[2];
+    if (nstage > 0) {
+        load_t(T, ldt, kbeg, kend, n0, d, treg);
+        if (PRE) load_g(Gb, s, m0, kbeg, greg);
+    }
     for (int64_t st = 0; st < nstage; ++st) {
         const int64_t k0 = kbeg + st * HKT;
         __syncthreads();  // the previous stage's operands are consumed
         store_t(As, treg);
-        gen_g(Gs, seed, m0, k0);
+        if (PRE) store_g(Gs, greg);
+        else gen_g(Gs, seed, m0, k0);
         __syncthreads();
-        if (st + 1 < nstage) load_t(T, ldt, k0 + HKT, kend, n0, d, treg);
+        if (st + 1 < nstage) {
+            load_t(T, ldt, k0 + HKT, kend, n0, d, treg);
+            if (PRE) load_g(Gb, s, m0, k0 + HKT, greg);
+        }
         // rows of T past the end of the slice were loaded as zero and the
         // G values there are finite, so their products vanish
         bf16x8 a[4];
@@ -214,6 +267,11 @@ to_f32_kernel(int64_t rows, int64_t cols, const double *__restrict__ T, int64_t 
 
 }  // namespace
 
+size_t sketch_bf16_g_bytes(int64_t K, int64_t s) {
+    const size_t b = (size_t)ceil_div(K, HKT) * (size_t)s * 32 * sizeof(uint16_t);
+    return b <= kPreGenMaxBytes ? b : 0;
+}
+
 void sketch_rows_bf16(int64_t K, int64_t d, const double *T, int64_t ldt, double lambda, int64_t s,
                       uint64_t seed, double *X, hipStream_t st, double *kernel_ms) {
     const int tiles_m = (int)ceil_div(s, HBM_), tiles_n = (int)ceil_div(d, HBN);
@@ -237,8 +295,28 @@ void sketch_rows_bf16(int64_t K, int64_t d, const double *T, int64_t ldt, double
         LSRN_HIP(hipEventCreate(&ev[1]));
         LSRN_HIP(hipEventRecord(ev[0], st));
     }
+    // bf16(G) generated once into panels (s x K x 2 bytes) when that fits:
+    // each tile of G is then read instead of generated once per column tile
+    DevBuf gpan;
+    const int64_t npanel = ceil_div(K, HKT);
+    const size_t gbytes = (size_t)npanel * (size_t)s * 32 * sizeof(uint16_t);
+    if (gbytes <= kPreGenMaxBytes) {
+        try {
+            gpan.alloc(gbytes);
+        } catch (const Error &) {
+            gpan.release();  // not enough device memory: generate in the kernel
+        }
+    }
     dim3 grid((unsigned)tiles, (unsigned)nsplit);
-    sketch_bf16_kernel<<<grid, HNT, 0, st>>>(T, ldt, K, d, s, seed, kps, tiles_m, Xp);
+    if (gpan.bytes()) {
+        const int64_t total = npanel * s * 8;
+        gauss_bf16_panels_kernel<<<(unsigned)std::min<int64_t>(ceil_div(total, 256), 1 << 20), 256, 0, st>>>(
+            seed, s, npanel, gpan.as<uint16_t>());
+        sketch_bf16_kernel<true><<<grid, HNT, 0, st>>>(T, ldt, K, d, s, seed, gpan.as<uint16_t>(), kps,
+                                                       tiles_m, Xp);
+    } else {
+        sketch_bf16_kernel<false><<<grid, HNT, 0, st>>>(T, ldt, K, d, s, seed, nullptr, kps, tiles_m, Xp);
+    }
     LSRN_HIP(hipGetLastError());
     if (kernel_ms) {
         LSRN_HIP(hipEventRecord(ev[1], st));
