@@ -35,10 +35,14 @@ FP64_VECTOR_PEAK_TFS = 78.6  # MI355X FP64 vector: 256 CUs x 64 FMA/clk x 2 x 2.
 # launch of the kernel in one timed solve, like `achieved`), scaled by the
 # counters of a plain 1 GiB device copy (FETCH_SIZE reads half the copied
 # bytes, WRITE_SIZE all of them).  Commands and per-kernel figures:
-# profiles/pmc_traffic_rankdef_200000x2000.md.  An entry is dropped when
-# its kernel changes.
+# profiles/pmc_sketches.md (the 1e6 x 4000 sketches, counted on
+# `--sketch-probe`: the same kernel at the same shape).  An entry is dropped
+# when its kernel changes.
 MEASURED_TRAFFIC = {
-    ("rankdef_200000x2000", "fp64", "f64", "jacobi_round"): 53.4e6,
+    ("dense_1000000x4000", "fp64", "f64", "sketch_mfma_f64"): 362.6e9,
+    ("dense_1000000x4000_k1e6", "fp64", "f64", "sketch_mfma_f64"): 362.6e9,
+    ("dense_1000000x4000", "mixed", "f64", "sketch_mfma_bf16x3"): 829.7e9,
+    ("dense_1000000x4000_k1e6", "mixed", "f64", "sketch_mfma_bf16x3"): 829.7e9,
 }
 
 WORKLOADS = {
@@ -467,6 +471,9 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=96.0)
     ap.add_argument("--serve-pool", type=int, default=128,
                     help="distinct matrices the requests draw from (built before timing)")
+    ap.add_argument("--sketch-probe", action="store_true",
+                    help="counter runs: one dense sketch (FP64 MFMA, then BF16x3 with --precision "
+                         "mixed) of a Gaussian A of the workload's shape, nothing else")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (3 times); "
                          "its FETCH_SIZE / WRITE_SIZE counters calibrate the traffic figures")
@@ -511,6 +518,9 @@ def main():
         print(json.dumps({"copy_bytes": src.numel() * 8, "launches": 3}))
         return
     wl = WORKLOADS[args.workload]
+    if args.sketch_probe:
+        sketch_probe(args, wl, dev)
+        return
     if args.refine is None:
         args.refine = wl.get("refine", 1)
     t_gen = time.perf_counter()
@@ -702,6 +712,39 @@ def main():
     print(json.dumps(line))
 
 
+def sketch_probe(args, wl, dev):
+    """One sketch of the workload's shape for hardware-counter passes: A is
+    Gaussian (the counters depend on the shapes, not the values), filled in
+    row blocks of at most 2^28 entries, and no other library routine runs
+    (the solve's input generator calls torch's QR)."""
+    import torch
+    from paper_1109_5981_amd import lsrn
+    # the tall generator's array; a fat workload reads it column-major as A^T
+    m, n = wl["m"], wl["n"]
+    rows, cols = m, n
+    g = torch.Generator(device=dev)
+    g.manual_seed(wl["seed"])
+    A = torch.empty((rows, cols), dtype=torch.float64, device=dev)
+    step = max(1, (1 << 28) // cols)
+    for r0 in range(0, rows, step):
+        r1 = min(rows, r0 + step)
+        A[r0:r1].normal_(generator=g)
+    layout = lsrn.COL_MAJOR if wl["fat"] else lsrn.ROW_MAJOR
+    s = int(math.ceil(2.0 * min(m, n)))
+    out = {"probe": "sketch", "workload": args.workload, "s": s}
+    fns = [("fp64", lsrn.sketch_dense)]
+    if args.precision == "mixed":
+        fns.append(("bf16x3", lsrn.sketch_dense_bf16))
+    for name, fn in fns:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        X = fn(A, s, seed=1, layout=layout)
+        torch.cuda.synchronize()
+        out[name + "_ms"] = round((time.perf_counter() - t0) * 1e3, 3)
+        del X
+    print(json.dumps(out))
+
+
 def kernel_figures(args, infos, s, K, d, mean):
     """Per-kernel rates from the library's HIP-event timings (opt.profile),
     with the algorithmic work of each kernel:
@@ -712,8 +755,10 @@ def kernel_figures(args, infos, s, K, d, mean):
       Jacobi round: the SVD's 11 d^3 flop (eq. for the flop count of LSRN)
                     spread over the solve's round launches.
     and the stage figures: the iteration phase's HBM fraction
-    B_iter * passes / (t * 8 TB/s), and the SVD stage's (2 s d^2 + 11 d^3) /
-    t_svd against the FP64 peak."""
+    B_iter * passes / (t * 8 TB/s), and the preconditioner stage against the
+    FP64 peak: (2 s d^2 + 11 d^3) / t_svd for the SVD, or, when the
+    certified full-rank path formed N = R^-1, the flops it made (Householder
+    QR 2 s d^2 - 2 d^3 / 3 and the triangular inverse d^3 / 3)."""
     f32 = args.precision != "fp64" or args.storage != "f64"
     bytes_per_sweep = (4.0 if f32 else 8.0) * K * d + 16.0 * K
     t_sketch_k = mean("t_sketch_kernel_ms")
@@ -754,9 +799,11 @@ def kernel_figures(args, infos, s, K, d, mean):
                                 "peak": HBM_PEAK_GBS, "frac": round(gbs / HBM_PEAK_GBS, 4)}
     t_svd = mean("t_svd_ms")
     if t_svd > 0:
-        fl = 2.0 * s * d * d + 11.0 * d ** 3
+        r_inv = mean("precond_used") == 2
+        fl = (2.0 * s * d * d - 2.0 * d ** 3 / 3 + d ** 3 / 3) if r_inv else 2.0 * s * d * d + 11.0 * d ** 3
         tf = fl / (t_svd * 1e-3) / 1e12
-        stages["svd_stage"] = {"flop": fl, "t_ms": round(t_svd, 3), "achieved": round(tf, 3),
+        stages["svd_stage"] = {"form": "qr + R^-1 (certified full rank)" if r_inv else "qr + jacobi svd",
+                               "flop": fl, "t_ms": round(t_svd, 3), "achieved": round(tf, 3),
                                "unit": "TFLOP/s", "peak": FP64_VECTOR_PEAK_TFS,
                                "frac": round(tf / FP64_VECTOR_PEAK_TFS, 4)}
     return kernels, stages

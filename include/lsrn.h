@@ -61,13 +61,13 @@ typedef enum { LSRN_ROW_MAJOR = 0, LSRN_COL_MAJOR = 1 } lsrn_layout;
  *     orthonormal columns, the property the condition-number bound of
  *     Sec. 4.2 rests on, but no rank is revealed: needs a full-rank sketch
  *     (guaranteed when lambda > 0) and returns LSRN_E_UNSUPPORTED otherwise.
- *   LSRN_PRECOND_AUTO: for min(m, n) <= 8192 the SVD, except that above
- *     512 the QR of the sketch is first tested: when |R|_F |R^-1|_F <=
- *     1 / (2 rcond) (so every singular value lies above the SVD's cutoff)
- *     N = R^-1 is used and the Jacobi sweeps are skipped (same
- *     preconditioned spectrum, same solution; lsrn_info.precond_used
- *     reports the choice).  Above 8192: QR when lambda > 0, else
- *     LSRN_E_UNSUPPORTED. */
+ *   LSRN_PRECOND_AUTO: for min(m, n) <= 8192 the SVD, except that the QR
+ *     of the sketch is first tested: when |R|_F |R^-1|_F <= 1 / (2 rcond)
+ *     (so every singular value lies above the SVD's cutoff) N = R^-1 is
+ *     used and the Jacobi sweeps are skipped (same preconditioned
+ *     spectrum, same solution; lsrn_info.precond_used reports the choice).
+ *     Above 8192: QR when lambda > 0, else LSRN_E_UNSUPPORTED.
+ *     lsrn_solve_batch always takes the SVD. */
 typedef enum { LSRN_PRECOND_AUTO = 0, LSRN_PRECOND_SVD = 1, LSRN_PRECOND_QR = 2 } lsrn_precond_kind;
 
 /* Arithmetic of the solve (dense A only).
@@ -145,8 +145,10 @@ typedef struct lsrn_info {
                                refinement (FP64): the last correction's
                                inner solve met its rule                     */
     double sigma_l, sigma_u;/* Chebyshev bounds used (0 when r is too large)     */
-    double sigma_max;       /* largest singular value of the sketch              */
-    double sigma_min_kept;  /* sigma_r of the sketch                             */
+    double sigma_max;       /* largest singular value of the sketch (N = R^-1:
+                               an estimate, the largest column norm of R)    */
+    double sigma_min_kept;  /* sigma_r of the sketch (N = R^-1: an estimate,
+                               1 / |R^-1|_2 from eight power steps)          */
     double t_sketch_ms;     /* RNG + sketch GEMM                                 */
     double t_svd_ms;        /* QR + Jacobi + cutoff + N                          */
     double t_iter_ms;       /* iterations incl. x = N y                          */
@@ -180,12 +182,12 @@ typedef struct lsrn_info {
     int64_t cs_fallbacks;
     /* the preconditioner formed: LSRN_PRECOND_SVD (N = V_r Sigma_r^-1 from
      * the Jacobi SVD) or LSRN_PRECOND_QR (N = R^-1: chosen by
-     * opt->precond, or by LSRN_PRECOND_AUTO for d > 512 when |R|_F |R^-1|_F
+     * opt->precond, or by LSRN_PRECOND_AUTO when |R|_F |R^-1|_F
      * <= 1 / (2 rcond) certifies that the SVD would keep every singular
      * value -- the sketch's R^-1 and V Sigma^-1 differ by an orthogonal
      * factor, so the preconditioned spectrum and the solution are the
-     * same; sweeps is then 0 and sigma_max / sigma_min_kept are |R|_F and
-     * 1 / |R^-1|_F).  0 when no preconditioner was formed (lsrn_iterate_*). */
+     * same; sweeps is then 0 and sigma_max / sigma_min_kept are estimates).
+     * 0 when no preconditioner was formed (lsrn_iterate_*). */
     int64_t precond_used;
 } lsrn_info;
 

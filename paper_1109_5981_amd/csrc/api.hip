@@ -264,11 +264,12 @@ bool use_qr_inverse(const lsrn_options &opt, int64_t d) {
          "min(m, n) above 8192 needs lambda > 0 (full-rank QR-inverse preconditioner)");
 }
 
-// The automatic choice tries N = R^-1 first when the Jacobi sweeps would be
-// the costly part (d above the batched small-matrix range): it is kept only
-// when R certifies that the SVD would keep every singular value.
+// The automatic choice tries N = R^-1 first: it is kept only when R
+// certifies that the SVD would keep every singular value (then the Jacobi
+// sweeps, most of the preconditioner's time at every size, are skipped).
 bool try_full_rank(const lsrn_options &opt, int64_t d) {
-    return opt.precond == LSRN_PRECOND_AUTO && d > 512;
+    (void)d;
+    return opt.precond == LSRN_PRECOND_AUTO;
 }
 
 // Steps 1-5 of a solve, kept for the iterations: the preconditioner and

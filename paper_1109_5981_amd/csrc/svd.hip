@@ -1271,6 +1271,42 @@ col_sumsq_kernel(const double *__restrict__ R, int64_t ldr, const double *__rest
     if (tid < 2) part[tid * d + j] = red[tid][0] + red[tid][1] + red[tid][2] + red[tid][3];
 }
 
+// y = M x for a row-major d x d M (leading dimension ld): one wavefront per
+// row, lanes over the columns, the wavefront's fixed butterfly.
+__global__ void __launch_bounds__(256)
+gemv_sq_kernel(const double *__restrict__ M, int64_t ld, int64_t d, const double *__restrict__ x,
+               double *__restrict__ y) {
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= d) return;
+    const int lane = threadIdx.x & 63;
+    double t = 0.0;
+    for (int64_t j = lane; j < d; j += 64) t += M[row * ld + j] * x[j];
+    t = wave_sum(t);
+    if (lane == 0) y[row] = t;
+}
+
+// v <- v / |v| (one workgroup); out[0] = |v|.
+__global__ void __launch_bounds__(1024) normalize_kernel(double *__restrict__ v, int64_t d,
+                                                         double *__restrict__ out) {
+    __shared__ double red[16];
+    const int tid = threadIdx.x;
+    double t = 0.0;
+    for (int64_t i = tid; i < d; i += 1024) t += v[i] * v[i];
+    t = wave_sum(t);
+    if ((tid & 63) == 0) red[tid >> 6] = t;
+    __syncthreads();
+    if (tid == 0) {
+        double a = 0.0;
+        for (int w = 0; w < 16; ++w) a += red[w];
+        red[0] = sqrt(a);
+        out[0] = red[0];
+    }
+    __syncthreads();
+    const double nv = red[0];
+    if (nv > 0.0)
+        for (int64_t i = tid; i < d; i += 1024) v[i] /= nv;
+}
+
 // The full-rank case of steps 4-5 without the Jacobi sweeps.  With X = Q R,
 // N = R^-1 gives T N the singular values of T V Sigma^-1 (R^-1 = V Sigma^-1
 // times an orthogonal factor), so it preconditions as well (reading of
@@ -1278,8 +1314,8 @@ col_sumsq_kernel(const double *__restrict__ R, int64_t ldr, const double *__rest
 // would keep every singular value: kappa_2(R) <= |R|_F |R^-1|_F, so
 // |R|_F |R^-1|_F <= 1 / (2 rc) certifies sigma_min > rc sigma_1, the
 // cutoff of the SVD path.  sigma receives |diag R| in descending order;
-// sigma_max / sigma_min_kept are |R|_F and 1 / |R^-1|_F (bounds that
-// enclose the true extremes).  False (nothing written to P) otherwise.
+// sigma_max / sigma_min_kept are estimates of sigma_1 and sigma_d (below).
+// False (nothing written to P) otherwise.
 bool full_rank_inverse(int64_t s, int64_t d, const double *R, double rcond, double *sigma, double *P,
                        PrecondResult &res, hipStream_t st) {
     const double rc = rcond > 0.0 ? rcond : (double)std::max(s, d) * DBL_EPSILON;
@@ -1305,11 +1341,31 @@ bool full_rank_inverse(int64_t s, int64_t d, const double *R, double rcond, doub
     LSRN_HIP(hipStreamSynchronize(st));
     std::sort(g.begin(), g.end(), [](double a, double b) { return a > b; });
     LSRN_HIP(hipMemcpyAsync(sigma, g.data(), (size_t)d * sizeof(double), hipMemcpyHostToDevice, st));
-    LSRN_HIP(hipStreamSynchronize(st));  // before g and Ri go
+    // estimates of the extreme singular values of R (the precision form
+    // chooses FP32 or FP64 sweeps from their ratio): the largest column norm
+    // of R for sigma_1, and 1 / |R^-1|_2 for sigma_d with |R^-1|_2 from eight
+    // power steps on R^-T R^-1 (P is R^-1 row-major; Ri, column-major, is
+    // R^-T row-major).  Both are lower bounds on the true values, each within
+    // a small factor for such sketches.
+    double cmax = 0.0;
+    for (int64_t j = 0; j < d; ++j) cmax = std::max(cmax, h[(size_t)j]);
+    DevBuf vb((size_t)2 * d * sizeof(double)), nb(sizeof(double));
+    std::vector<double> v0((size_t)d, 1.0 / std::sqrt((double)d));
+    LSRN_HIP(hipMemcpyAsync(vb.as<double>(), v0.data(), (size_t)d * sizeof(double), hipMemcpyHostToDevice, st));
+    double *v = vb.as<double>(), *u = vb.as<double>() + d;
+    for (int it = 0; it < 8; ++it) {
+        gemv_sq_kernel<<<(unsigned)ceil_div(d, 4), 256, 0, st>>>(P, d, d, v, u);
+        gemv_sq_kernel<<<(unsigned)ceil_div(d, 4), 256, 0, st>>>(Ri.as<double>(), d, d, u, v);
+        normalize_kernel<<<1, 1024, 0, st>>>(v, d, nb.as<double>());
+    }
+    LSRN_HIP(hipGetLastError());
+    double lam = 0.0;
+    LSRN_HIP(hipMemcpyAsync(&lam, nb.as<double>(), sizeof(double), hipMemcpyDeviceToHost, st));
+    LSRN_HIP(hipStreamSynchronize(st));  // before g, v0 and the buffers go
     res.rank = d;
     res.sweeps = 0;
-    res.sigma_max = nr;
-    res.sigma_min_kept = 1.0 / ni;
+    res.sigma_max = std::sqrt(cmax);
+    res.sigma_min_kept = lam > 0.0 ? 1.0 / std::sqrt(lam) : g[(size_t)d - 1];
     res.full_rank_inverse = true;
     return true;
 }

@@ -47,7 +47,9 @@ def test_batch_matches_single_solves_and_oracle(L, orc):
     bs.append(dev(np.ones(700)))
     xs, infos = L.solve_batch(As, bs, seed=11)
     for k, (A, b) in enumerate(zip(As[:-1], bs[:-1])):
-        x1, i1 = L.solve_dense(A, b, seed=11)
+        # the batch forms the SVD preconditioner; the lone solve is asked for
+        # the same (its automatic choice would take R^-1 for a full-rank sketch)
+        x1, i1 = L.solve_dense(A, b, seed=11, precond="svd")
         assert infos[k]["rank"] == i1["rank"]
         assert abs(infos[k]["iters"] - i1["iters"]) <= 1
         # same sketch and preconditioner; the sweeps sum in other orders
