@@ -51,7 +51,7 @@ WORKLOADS = {
     "dense_2000x100": dict(m=2000, n=100, rank=100, smin=1e-6, seed=11, fat=False, noise=1e-3),
     # the precision-form workload: full rank, sigma 1 .. 1e-8, b = A x + 1e-6 noise
     "dense_1000000x4000": dict(m=1_000_000, n=4000, rank=4000, smin=1e-8, seed=14, fat=False,
-                               noise=1e-6, refine=2),
+                               noise=1e-6, refine=1, refine_tol=1e-8),
     # the same shape at kappa = 1e6, where kappa u32 < 1 lets the precision form
     # reach the FP64 solution
     "dense_1000000x4000_k1e6": dict(m=1_000_000, n=4000, rank=4000, smin=1e-6, seed=14, fat=False,
@@ -451,6 +451,9 @@ def main():
     ap.add_argument("--refine", type=int, default=None,
                     help="refinement steps (default: 2 for the kappa 1e8 workload, where one "
                          "step leaves about 1e-10, else 1)")
+    ap.add_argument("--refine-tol", type=float, default=None,
+                    help="relative accuracy of each refinement correction (default: the "
+                         "workload's, else the library's 1e-6)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--precond", default="auto", choices=["auto", "svd", "qr"])
     ap.add_argument("--storage", default="f64", choices=["f64", "f32"],
@@ -546,6 +549,10 @@ def main():
     opts = dict(method=args.method, refine=args.refine, seed=2024, tol=1e-14,
                 profile=0 if args.no_profile else 1, precision=args.precision,
                 precond=args.precond, autotune=0 if args.no_autotune else 1)
+    if args.refine_tol is None:
+        args.refine_tol = wl.get("refine_tol")
+    if args.refine_tol is not None:
+        opts["refine_tol"] = args.refine_tol
     solve = lsrn.solve_dense
     A_solve = A
     if args.storage == "f32":
@@ -627,7 +634,10 @@ def main():
     if (args.precision == "fp64" and args.storage == "f64" and not wl["fat"]
             and args.precision_steps > 0):
         mixed_args = argparse.Namespace(**dict(vars(args), precision="mixed"))
-        o_mixed = dict(opts, precision="mixed", refine=max(args.refine, 10))
+        # the precision form's refinement runs its own steps (up to 10, each
+        # correction to the library's 1e-6)
+        o_mixed = dict({k: v for k, v in opts.items() if k != "refine_tol"}, precision="mixed",
+                       refine=max(args.refine, 10))
         xm, infos_m, lat_m, el_m = leg(solve, args.precision_steps, 1, **o_mixed)
         prec_form = {"same_problem": leg_summary(xm, infos_m, lat_m, el_m, args.precision_steps,
                                                  x_ref, mixed_args),
@@ -645,7 +655,8 @@ def main():
             del U6, V6
             b6, _ = workloads.rhs_model_device(A6, w6["noise"], w6["seed"])
             torch.cuda.empty_cache()
-            o64 = dict(opts, refine=1)
+            # kappa 1e6: one FP64 refinement step with the library's 1e-6 corrections
+            o64 = dict({k: v for k, v in opts.items() if k != "refine_tol"}, refine=1)
             x64, i64, l64, e64 = leg(solve, args.precision_steps, 1, A_=A6, b_=b6, **o64)
             ref6, _ = solve(A6, b6, layout=layout, **dict(opts, refine=6, profile=0, seed=7))
             xm6, im6, lm6, em6 = leg(solve, args.precision_steps, 1, A_=A6, b_=b6, **o_mixed)
@@ -687,6 +698,7 @@ def main():
                                     else "b ~ N(0,1)")),
         "config": {"workload": args.workload, "m": m_ls, "n": n_ls, "rank": wl["rank"],
                    "gamma": 2.0, "tol": 1e-14, "method": args.method, "refine": args.refine,
+                   "refine_tol": args.refine_tol if args.refine_tol is not None else 1e-6,
                    "precision": args.precision, "precond": args.precond, "storage": args.storage,
                    "autotune": not args.no_autotune},
         "tuned_shapes": lsrn.tune_export().strip().splitlines(),

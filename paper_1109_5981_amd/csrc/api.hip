@@ -32,6 +32,9 @@ void set_alloc_stream(hipStream_t s) { g_alloc_stream = s; }
 static thread_local bool g_graphs_allowed = true;
 void set_graphs_allowed(bool on) { g_graphs_allowed = on; }
 bool graphs_allowed() { return g_graphs_allowed; }
+static thread_local bool g_fast_paths_allowed = true;
+void set_fast_paths_allowed(bool on) { g_fast_paths_allowed = on; }
+bool fast_paths_allowed() { return g_fast_paths_allowed; }
 
 void DevBuf::alloc(size_t bytes) {
     release();
@@ -269,7 +272,7 @@ bool use_qr_inverse(const lsrn_options &opt, int64_t d) {
 // sweeps, most of the preconditioner's time at every size, are skipped).
 bool try_full_rank(const lsrn_options &opt, int64_t d) {
     (void)d;
-    return opt.precond == LSRN_PRECOND_AUTO;
+    return opt.precond == LSRN_PRECOND_AUTO && fast_paths_allowed();
 }
 
 // Steps 1-5 of a solve, kept for the iterations: the preconditioner and

@@ -160,10 +160,8 @@ __global__ void __launch_bounds__(HNT, 1)
 sketch_bf16_kernel(const double *__restrict__ T, int64_t ldt, int64_t K, int64_t d, int64_t s,
                    uint64_t seed, const uint16_t *__restrict__ Gb, int64_t k_per_split, int tiles_m,
                    double *__restrict__ Xp) {
-    // two stages of operands: stage st is multiplied from buffer st & 1
-    // while stage st + 1 is stored into the other, one barrier per stage
-    __shared__ uint16_t Gs[2][HBM_][HP];
-    __shared__ uint16_t As[2][3][HBN][HP];
+    __shared__ uint16_t Gs[HBM_][HP];
+    __shared__ uint16_t As[3][HBN][HP];
     const int tile = blockIdx.x;
     const int64_t m0 = (int64_t)(tile % tiles_m) * HBM_;
     const int64_t n0 = (int64_t)(tile / tiles_m) * HBN;
@@ -187,42 +185,31 @@ sketch_bf16_kernel(const double *__restrict__ T, int64_t ldt, int64_t K, int64_t
     const int64_t nstage = kend > kbeg ? ceil_div(kend - kbeg, HKT) : 0;
     double treg[16];
     uint4 greg[2];
-    if (nstage > 0) {  // stage 0 into buffer 0, stage 1 into registers
+    if (nstage > 0) {
         load_t(T, ldt, kbeg, kend, n0, d, treg);
         if (PRE) load_g(Gb, s, m0, kbeg, greg);
-        store_t(As[0], treg);
-        if (PRE) store_g(Gs[0], greg);
-        else gen_g(Gs[0], seed, m0, kbeg);
-        if (nstage > 1) {
-            load_t(T, ldt, kbeg + HKT, kend, n0, d, treg);
-            if (PRE) load_g(Gb, s, m0, kbeg + HKT, greg);
-        }
-        __syncthreads();
     }
     for (int64_t st = 0; st < nstage; ++st) {
         const int64_t k0 = kbeg + st * HKT;
-        const int cb = (int)(st & 1);
+        __syncthreads();  // the previous stage's operands are consumed
+        store_t(As, treg);
+        if (PRE) store_g(Gs, greg);
+        else gen_g(Gs, seed, m0, k0);
+        __syncthreads();
+        if (st + 1 < nstage) {
+            load_t(T, ldt, k0 + HKT, kend, n0, d, treg);
+            if (PRE) load_g(Gb, s, m0, k0 + HKT, greg);
+        }
         // rows of T past the end of the slice were loaded as zero and the
         // G values there are finite, so their products vanish
         bf16x8 a[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) a[i] = load8(&Gs[cb][wm * 64 + i * 16 + lr][lk * 8]);
-        // stage st + 1 into the other buffer (its readers, stage st - 1,
-        // passed the last barrier), stage st + 2 into registers
-        if (st + 1 < nstage) {
-            store_t(As[cb ^ 1], treg);
-            if (PRE) store_g(Gs[cb ^ 1], greg);
-            else gen_g(Gs[cb ^ 1], seed, m0, k0 + HKT);
-            if (st + 2 < nstage) {
-                load_t(T, ldt, k0 + 2 * HKT, kend, n0, d, treg);
-                if (PRE) load_g(Gb, s, m0, k0 + 2 * HKT, greg);
-            }
-        }
+        for (int i = 0; i < 4; ++i) a[i] = load8(&Gs[wm * 64 + i * 16 + lr][lk * 8]);
 #pragma unroll
         for (int term = 0; term < 3; ++term) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const bf16x8 b = load8(&As[cb][term][wn * 64 + j * 16 + lr][lk * 8]);
+                const bf16x8 b = load8(&As[term][wn * 64 + j * 16 + lr][lk * 8]);
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b, acc[i][j], 0, 0, 0);
@@ -238,7 +225,6 @@ sketch_bf16_kernel(const double *__restrict__ T, int64_t ldt, int64_t K, int64_t
                     acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
                 }
         }
-        __syncthreads();  // buffer cb ^ 1 complete, buffer cb free
     }
     // accumulator element v of lane (lr, lk) is row 4 lk + v, column lr of its
     // 16 x 16 block; X is column-major
@@ -314,7 +300,7 @@ void sketch_rows_bf16(int64_t K, int64_t d, const double *T, int64_t ldt, double
     DevBuf gpan;
     const int64_t npanel = ceil_div(K, HKT);
     const size_t gbytes = (size_t)npanel * (size_t)s * 32 * sizeof(uint16_t);
-    if (gbytes <= kPreGenMaxBytes) {
+    if (gbytes <= kPreGenMaxBytes && fast_paths_allowed()) {
         try {
             gpan.alloc(gbytes);
         } catch (const Error &) {
