@@ -976,7 +976,7 @@ size_t lsrn_workspace_bytes(int64_t m, int64_t n, int32_t layout, const lsrn_opt
     bytes += (size_t)(K + d) * sizeof(double) * 3;           // long vectors
     bytes += (size_t)1024 * d * sizeof(double) * 3;          // sweep partials
     if (opt.precision == LSRN_PREC_MIXED)                    // FP32 copy, bf16(G)
-        bytes += (size_t)K * d * sizeof(float) + sketch_bf16_g_bytes(K, s);
+        bytes += (size_t)K * d * sizeof(float) + sketch_bf16_g_bytes(K, d, s);
     return bytes;
 } catch (...) {
     return 0;

@@ -44,8 +44,9 @@ void sketch_rows_batch(int count, const int64_t *K, const int64_t *d, const doub
 // The precision form's sketch: X = bf16(G) fl32(T) on the BF16 matrix
 // cores (FP32 accumulation flushed to FP64), plus the FP64 rows lambda G of
 // the Tikhonov block.  Synchronises.
-// device bytes of the precision-form sketch's pre-generated bf16(G) (0: generated in the kernel)
-size_t sketch_bf16_g_bytes(int64_t K, int64_t s);
+// device bytes of the precision-form sketch's pre-generated bf16(G) and split
+// terms of T (0: generated and split in the kernel)
+size_t sketch_bf16_g_bytes(int64_t K, int64_t d, int64_t s);
 void sketch_rows_bf16(int64_t K, int64_t d, const double *T, int64_t ldt, double lambda, int64_t s,
                       uint64_t seed, double *X, hipStream_t st, double *kernel_ms = nullptr);
 // T32 (rows x cols, leading dimension ldt) = T rounded to FP32.

@@ -59,6 +59,38 @@ def test_sketch_bf16_matches_oracle(L, orc, m, n, layout, lam, s):
     assert np.all(np.abs(Xg - Xo) <= bound)
 
 
+@pytest.mark.parametrize("m,n,layout,lam,s", [
+    (2000, 100, 0, 0.0, 200),
+    (9001, 131, 0, 0.5, 263),
+    (100, 3000, 1, 0.0, 200),
+])
+def test_sketch_bf16_operand_paths_agree(L, orc, monkeypatch, m, n, layout, lam, s):
+    """The three ways the kernel takes its operands -- bf16(G) and the split
+    terms of T pre-formed in device memory, only bf16(G) pre-formed, both
+    formed per stage -- give the same bits (same values, same order of
+    products and sums), and match the oracle.  LSRN_PREGEN_MAX_BYTES caps
+    the pre-formed operands: 8e6 bytes holds bf16(G) of these shapes
+    (at most 64 s ceil(K / 32) bytes) but not the split terms (at least
+    3 x 64 x 128 ceil(K / 32) bytes)."""
+    rng = np.random.default_rng(7 * m + n)
+    A = rng.standard_normal((m, n)) * np.exp(rng.standard_normal((m, n)))
+    seed = 17
+    At = dev(A if layout == 0 else A.T.copy())
+    out = {}
+    for name, cap in (("both", None), ("g_only", "8000000"), ("none", "0")):
+        if cap is None:
+            monkeypatch.delenv("LSRN_PREGEN_MAX_BYTES", raising=False)
+        else:
+            monkeypatch.setenv("LSRN_PREGEN_MAX_BYTES", cap)
+        out[name] = host(L.sketch_dense_bf16(At, s, seed=seed, lam=lam, layout=layout))
+    monkeypatch.delenv("LSRN_PREGEN_MAX_BYTES", raising=False)
+    np.testing.assert_array_equal(out["g_only"], out["both"])
+    np.testing.assert_array_equal(out["none"], out["both"])
+    Xo = orc.sketch_bf16(orc.Matrix.dense(A, lam=lam), s, seed)
+    e = np.abs(out["both"].T - Xo).max() / np.abs(Xo).max()
+    assert e <= 1e-5, e
+
+
 @pytest.fixture(scope="module")
 def kappa6(orc):
     P = workloads.dense_problem(20000, 200, smin=1e-6, seed=61)
