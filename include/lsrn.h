@@ -491,10 +491,8 @@ void lsrn_plan_destroy(lsrn_plan *plan);
  * lsrn_workspace_bytes_csr, plus the FP32 copy of the precision form) fits
  * in `hbm_budget_bytes` next to the solves already running; a request
  * larger than the budget runs alone.  Admitted solves overlap on the device
- * and each runs the kernels of lsrn_solve_dense / lsrn_solve_csr with
- * LSRN_PRECOND_AUTO taken as LSRN_PRECOND_SVD and G generated in the sketch
- * tiles (no pre-generated G array), so its result equals that of the same
- * call made alone with precond = LSRN_PRECOND_SVD.  Served requests
+ * and each runs exactly the kernels of lsrn_solve_dense / lsrn_solve_csr,
+ * so its result equals that of the same call made alone.  Served requests
  * never tune launch shapes (opt.autotune is ignored; recorded shapes are
  * used): timings taken while other solves share the device are noise, and
  * a new table entry would change the summation order of later requests.

@@ -32,9 +32,6 @@ void set_alloc_stream(hipStream_t s) { g_alloc_stream = s; }
 static thread_local bool g_graphs_allowed = true;
 void set_graphs_allowed(bool on) { g_graphs_allowed = on; }
 bool graphs_allowed() { return g_graphs_allowed; }
-static thread_local bool g_fast_paths_allowed = true;
-void set_fast_paths_allowed(bool on) { g_fast_paths_allowed = on; }
-bool fast_paths_allowed() { return g_fast_paths_allowed; }
 
 void DevBuf::alloc(size_t bytes) {
     release();
@@ -272,7 +269,7 @@ bool use_qr_inverse(const lsrn_options &opt, int64_t d) {
 // sweeps, most of the preconditioner's time at every size, are skipped).
 bool try_full_rank(const lsrn_options &opt, int64_t d) {
     (void)d;
-    return opt.precond == LSRN_PRECOND_AUTO && fast_paths_allowed();
+    return opt.precond == LSRN_PRECOND_AUTO;
 }
 
 // Steps 1-5 of a solve, kept for the iterations: the preconditioner and
@@ -993,7 +990,7 @@ size_t lsrn_workspace_bytes_csr(int64_t m, int64_t n, int64_t nnz, const lsrn_op
     bytes += (size_t)nnz * 36;                                 // sketch order + sort temporaries
     bytes += sketch_csr_tile_bytes(K, d, nnz, s);              // group offsets, partial sketches
     bytes += (size_t)s * d * sizeof(double);                   // sketch
-    bytes += precond_workspace_bytes(s, d) + (size_t)d * d * sizeof(double);  // QR-inverse
+    bytes += precond_workspace_bytes(s, d) + (size_t)d * d * sizeof(double);  // QR-inverse (its R^-1 counted above)
     bytes += (size_t)d * d * sizeof(double) * 2 + (size_t)d * sizeof(double);  // P, P^T, sigma
     bytes += (size_t)rows * sizeof(double) * 5;                // long vectors
     return bytes;

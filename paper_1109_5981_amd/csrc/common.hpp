@@ -73,14 +73,6 @@ void set_alloc_stream(hipStream_t s);
 void set_graphs_allowed(bool on);
 bool graphs_allowed();
 
-// Whether this thread's solves may take the certified N = R^-1 shortcut and
-// pre-generate the precision form's bf16(G) into a device array.  The
-// serving workers do not: served solves keep the SVD preconditioner and
-// generate G in the sketch tiles (concurrent serving runs faulted the GPU
-// with these paths on, cause not established).
-void set_fast_paths_allowed(bool on);
-bool fast_paths_allowed();
-
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 __host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 

@@ -151,6 +151,8 @@ void gemm_nn(int64_t M, int64_t N, int64_t K, double alpha, const double *A, int
 // Rinv (column-major, ldi) = R^-1 for upper-triangular R (column-major, ldr;
 // entries below the diagonal are ignored).
 void trtri_upper(int64_t d, const double *R, int64_t ldr, double *Rinv, int64_t ldi, hipStream_t st);
+// Elements of the temporary product buffer trtri_upper allocates for order d.
+int64_t trtri_work_elems(int64_t d);
 
 // --------------------------------------------------------- iterate.hip
 // The operator of the iteration phase.  Tall: T = A row-major (rows = m,

@@ -283,15 +283,31 @@ void gemm_nn(int64_t M, int64_t N, int64_t K, double alpha, const double *A, int
 
 namespace {
 
+// Split of a diagonal block of n > TB rows: n1 (a multiple of TB, about
+// n / 2) and n - n1.
+int64_t trtri_split(int64_t n) { return TB * ceil_div(ceil_div(n, 2), TB); }
+
+// Elements of the product buffer W that the halving tree of a block of n
+// rows needs: the largest n1 (n - n1) over all its levels.  (A sub-block can
+// need more than the top split: n = 130 splits 128 + 2, and the 128 block
+// then 64 + 64.)
+int64_t trtri_work(int64_t n) {
+    if (n <= TB) return 0;
+    const int64_t n1 = trtri_split(n), n2 = n - n1;
+    return std::max(n1 * n2, std::max(trtri_work(n1), trtri_work(n2)));
+}
+
 // Off-diagonal blocks of the inverse, bottom-up over the halving tree: for
 // the diagonal block [off, off + n) split as [A B; 0 C] with both diagonal
-// inverses already in Rinv, Rinv(top-right) = -A^-1 B C^-1.
+// inverses already in Rinv, Rinv(top-right) = -A^-1 B C^-1.  W holds wcap
+// elements.
 void trtri_rec(int64_t off, int64_t n, const double *R, int64_t ldr, double *Rinv, int64_t ldi,
-               double *W, hipStream_t st) {
+               double *W, int64_t wcap, hipStream_t st) {
     if (n <= TB) return;
-    const int64_t n1 = TB * ceil_div(ceil_div(n, 2), TB), n2 = n - n1;
-    trtri_rec(off, n1, R, ldr, Rinv, ldi, W, st);
-    trtri_rec(off + n1, n2, R, ldr, Rinv, ldi, W, st);
+    const int64_t n1 = trtri_split(n), n2 = n - n1;
+    LSRN_REQUIRE(n1 * n2 <= wcap, "trtri: product buffer too small");
+    trtri_rec(off, n1, R, ldr, Rinv, ldi, W, wcap, st);
+    trtri_rec(off + n1, n2, R, ldr, Rinv, ldi, W, wcap, st);
     // W (n1 x n2, ld n1) = A^-1 B
     gemm_nn(n1, n2, n1, 1.0, Rinv + off * ldi + off, ldi, R + (off + n1) * ldr + off, ldr, 0.0, W, n1,
             st);
@@ -302,14 +318,16 @@ void trtri_rec(int64_t off, int64_t n, const double *R, int64_t ldr, double *Rin
 
 }  // namespace
 
+int64_t trtri_work_elems(int64_t d) { return trtri_work(d); }
+
 void trtri_upper(int64_t d, const double *R, int64_t ldr, double *Rinv, int64_t ldi, hipStream_t st) {
     LSRN_HIP(hipMemsetAsync(Rinv, 0, (size_t)ldi * (size_t)d * sizeof(double), st));
     trtri_diag_kernel<<<(unsigned)ceil_div(d, TB), TB, 0, st>>>(d, R, ldr, Rinv, ldi);
     LSRN_HIP(hipGetLastError());
     if (d > TB) {
-        const int64_t n1 = TB * ceil_div(ceil_div(d, 2), TB);
-        DevBuf W((size_t)n1 * (size_t)(d - n1) * sizeof(double));
-        trtri_rec(0, d, R, ldr, Rinv, ldi, W.as<double>(), st);
+        const int64_t wn = trtri_work(d);
+        DevBuf W((size_t)wn * sizeof(double));
+        trtri_rec(0, d, R, ldr, Rinv, ldi, W.as<double>(), wn, st);
         LSRN_HIP(hipStreamSynchronize(st));  // before W is freed
     }
 }

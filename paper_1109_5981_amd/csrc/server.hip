@@ -71,7 +71,6 @@ struct lsrn_server {
         if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return;
         lsrn::set_alloc_stream(st);
         lsrn::set_graphs_allowed(false);
-        lsrn::set_fast_paths_allowed(false);
         for (;;) {
             Request *r = nullptr;
             {

@@ -416,7 +416,7 @@ void sketch_rows_bf16(int64_t K, int64_t d, const double *T, int64_t ldt, double
     const size_t pre_cap = pregen_max_bytes();
     const int64_t npanel = ceil_div(K, HKT);
     const size_t gbytes = (size_t)npanel * (size_t)s * 32 * sizeof(uint16_t);
-    if (gbytes <= pre_cap && fast_paths_allowed()) {
+    if (gbytes <= pre_cap) {
         try {
             gpan.alloc(gbytes);
         } catch (const Error &) {

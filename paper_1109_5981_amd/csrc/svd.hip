@@ -1020,8 +1020,10 @@ size_t lds_limit() {
 
 size_t precond_workspace_bytes(int64_t s, int64_t d) {
     const int64_t dcols = round_up(d, 64) + 64;
-    return sizeof(double) * ((size_t)s * QNB + QNB + (size_t)d * dcols + 2 * (size_t)d) +
-           sizeof(int64_t) * (size_t)d + 64;
+    // after the QR: the Jacobi path's Y, or the certified path's R^-1, the
+    // triangular inverse's product buffer and the power steps' vectors
+    const size_t after = std::max((size_t)d * dcols, (size_t)d * d + (size_t)trtri_work_elems(d) + 4 * (size_t)d + 1);
+    return sizeof(double) * ((size_t)s * QNB + QNB + after + 2 * (size_t)d) + sizeof(int64_t) * (size_t)d + 64;
 }
 
 void householder_qr(int64_t s, int64_t d, double *X, hipStream_t st) {

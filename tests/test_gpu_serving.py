@@ -9,13 +9,7 @@ import pytest
 import workloads
 
 torch = pytest.importorskip("torch")
-# Two runs with concurrent served solves faulted the GPU (the serving
-# benchmark, then the mix test below) after the certified R^-1 shortcut and
-# the pre-generated G arrays were added; the cause is not established.
-# Served solves now take neither (the paths these tests passed on before),
-# and the tests stay off the GPU until the cause is found.
-pytestmark = [pytest.mark.gpu,
-              pytest.mark.skip(reason="concurrent serving faulted the GPU; cause not established")]
+pytestmark = pytest.mark.gpu
 
 
 @pytest.fixture(scope="module")
@@ -94,9 +88,7 @@ def test_results_alone_equal_results_in_mix(L, orc):
     their FP64 answer)."""
     reqs = mix(L)
     L.tune_clear()
-    # served solves form the SVD preconditioner; the lone solves are asked for it
-    alone = [solve_alone(L, kind, A, b, dict({k: v for k, v in o.items() if k != "autotune"},
-                                             precond="svd"))[0]
+    alone = [solve_alone(L, kind, A, b, {k: v for k, v in o.items() if k != "autotune"})[0]
              for kind, A, b, o, _ in reqs]
     for (kind, A, b, opts, (spec, b_h)), x in zip(reqs, alone):
         ref = oracle_ref(orc, spec, b_h, opts.get("lam", 0.0))

@@ -77,7 +77,7 @@ def test_sketch_csr_is_deterministic(L):
 
 # ----------------------------------------------------- QR-inverse precond
 
-@pytest.mark.parametrize("s,d,spread", [(200, 100, 1e-3), (263, 131, 1e-2), (700, 333, 1e-6)])
+@pytest.mark.parametrize("s,d,spread", [(200, 100, 1e-3), (263, 131, 1e-2), (300, 150, 1e-3), (700, 333, 1e-6)])
 def test_precond_qr_matches_oracle(L, orc, s, d, spread):
     rng = np.random.default_rng(s + d)
     X = rng.standard_normal((s, d)) @ np.diag(10.0 ** np.linspace(0, np.log10(spread), d))
