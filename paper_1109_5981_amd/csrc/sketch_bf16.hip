@@ -31,7 +31,7 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));  // 16 bytes of oper
 constexpr int HBM_ = 128;  // sketch rows per workgroup
 constexpr int HBN = 128;   // columns per workgroup
 constexpr int HKT = 32;    // k per stage
-constexpr int HP = 40;     // LDS pitch (bf16) of a row of 32 k: 80 bytes
+constexpr int HP = 32;     // LDS row (bf16): the 32 k of a stage, 64 bytes, chunks swizzled (swz)
 constexpr int HNT = 512;
 constexpr int FLUSH = 8;   // stages accumulated in FP32 before the FP64 flush
 constexpr size_t kPreGenMaxBytes = (size_t)32 << 30;  // default cap of the pre-generated operands
@@ -45,14 +45,21 @@ __device__ __forceinline__ uint16_t bf16_rn(float f) {
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
+// Position of 16-byte chunk c (k = 8 c .. 8 c + 7) within LDS row r: rows
+// are 64 bytes, unpadded, and the chunk index is XORed with a function of
+// the row so that neither the 16-byte stores (four lanes a row, or one lane
+// a row) nor the MFMA operand reads (sixteen rows, one chunk each) put two
+// lanes of one LDS cycle on the same bank, for 128- and 256-byte cycles.
+__device__ __forceinline__ int swz(int r, int c) { return c ^ (((r >> 1) ^ (r >> 2)) & 3); }
+
 __device__ __forceinline__ bf16x8 load8(const uint16_t *p) {
     const uint4 v = *reinterpret_cast<const uint4 *>(p);
     return __builtin_bit_cast(bf16x8, v);
 }
 
 // G for the 128 rows x 32 k of a stage: 128 rows x 8 Philox blocks, two
-// per thread; Gs[row][k] (k contiguous), each block's four values stored
-// as one 8-byte vector.
+// per thread; Gs[row] holds the row's 32 k in chunks of 8 placed by swz,
+// each block's four values stored as one 8-byte vector.
 __device__ __forceinline__ void gen_g(uint16_t (*Gs)[HP], uint64_t seed, int64_t m0, int64_t k0) {
     const int t = threadIdx.x;
     const int row = t & (HBM_ - 1);
@@ -65,7 +72,7 @@ __device__ __forceinline__ void gen_g(uint16_t (*Gs)[HP], uint64_t seed, int64_t
         uint2 v;
         v.x = (uint32_t)bf16_rn((float)g[0]) | ((uint32_t)bf16_rn((float)g[1]) << 16);
         v.y = (uint32_t)bf16_rn((float)g[2]) | ((uint32_t)bf16_rn((float)g[3]) << 16);
-        *reinterpret_cast<uint2 *>(&Gs[row][4 * q]) = v;
+        *reinterpret_cast<uint2 *>(&Gs[row][8 * swz(row, q >> 1) + 4 * (q & 1)]) = v;
     }
 }
 
@@ -103,8 +110,9 @@ __device__ __forceinline__ uint32_t load_t(const double *__restrict__ T, int64_t
     return mask;
 }
 
-// Split and store: As[term][col][k], the 8 values of k of a thread as one
-// 16-byte vector per term.  The empty asm ties each loaded value to this
+// Split and store: As[term][col] holds column col's 32 k in chunks of 8
+// placed by swz; the 8 values of k of a thread go as one 16-byte vector per
+// term.  The empty asm ties each loaded value to this
 // point, so the compiler cannot convert it (and wait for its load) where the
 // load was issued, a stage earlier.
 __device__ __forceinline__ void store_t(uint16_t (*As)[HBN][HP], const double (&reg)[8], uint32_t mask) {
@@ -124,7 +132,8 @@ __device__ __forceinline__ void store_t(uint16_t (*As)[HBN][HP], const double (&
     }
 #pragma unroll
     for (int term = 0; term < 3; ++term)
-        *reinterpret_cast<uint4 *>(&As[term][c][kb]) = make_uint4(w[term][0], w[term][1], w[term][2], w[term][3]);
+        *reinterpret_cast<uint4 *>(&As[term][c][8 * swz(c, kb >> 3)]) =
+            make_uint4(w[term][0], w[term][1], w[term][2], w[term][3]);
 }
 
 // bf16(G) for the whole sketch, generated once: panel p (k = 32 p ..
@@ -159,7 +168,7 @@ __device__ __forceinline__ u32x4 load_g(const uint16_t *__restrict__ Gb, int64_t
 
 __device__ __forceinline__ void store_g(uint16_t (*Gs)[HP], u32x4 v) {
     const int t = threadIdx.x;
-    *reinterpret_cast<u32x4 *>(&Gs[t >> 2][8 * (t & 3)]) = v;
+    *reinterpret_cast<u32x4 *>(&Gs[t >> 2][8 * swz(t >> 2, t & 3)]) = v;
 }
 
 // fl32(T) split into its three BF16 terms once, in the layout of the
@@ -211,7 +220,8 @@ __device__ __forceinline__ void load_tp(const uint16_t *__restrict__ Tp, int64_t
 __device__ __forceinline__ void store_tp(uint16_t (*As)[HBN][HP], const u32x4 (&reg)[3]) {
     const int t = threadIdx.x;
 #pragma unroll
-    for (int term = 0; term < 3; ++term) *reinterpret_cast<u32x4 *>(&As[term][t >> 2][8 * (t & 3)]) = reg[term];
+    for (int term = 0; term < 3; ++term)
+        *reinterpret_cast<u32x4 *>(&As[term][t >> 2][8 * swz(t >> 2, t & 3)]) = reg[term];
 }
 
 // One stage's operands on their way from HBM to LDS: the T terms (PRET),
@@ -276,12 +286,16 @@ sketch_bf16_kernel(const double *__restrict__ T, int64_t ldt, int64_t K, int64_t
     auto mma = [&](int64_t st) {
         bf16x8 a[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) a[i] = load8(&Gs[wm * 64 + i * 16 + lr][lk * 8]);
+        for (int i = 0; i < 4; ++i) {
+            const int r = wm * 64 + i * 16 + lr;
+            a[i] = load8(&Gs[r][8 * swz(r, lk)]);
+        }
 #pragma unroll
         for (int term = 0; term < 3; ++term) {
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
-                const bf16x8 b = load8(&As[term][wn * 32 + j * 16 + lr][lk * 8]);
+                const int c = wn * 32 + j * 16 + lr;
+                const bf16x8 b = load8(&As[term][c][8 * swz(c, lk)]);
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b, acc[i][j], 0, 0, 0);
