@@ -41,8 +41,8 @@ FP64_VECTOR_PEAK_TFS = 78.6  # MI355X FP64 vector: 256 CUs x 64 FMA/clk x 2 x 2.
 MEASURED_TRAFFIC = {
     ("dense_1000000x4000", "fp64", "f64", "sketch_mfma_f64"): 362.6e9,
     ("dense_1000000x4000_k1e6", "fp64", "f64", "sketch_mfma_f64"): 362.6e9,
-    ("dense_1000000x4000", "mixed", "f64", "sketch_mfma_bf16x3"): 829.7e9,
-    ("dense_1000000x4000_k1e6", "mixed", "f64", "sketch_mfma_bf16x3"): 829.7e9,
+    ("dense_1000000x4000", "mixed", "f64", "sketch_mfma_bf16x3"): 780.1e9,
+    ("dense_1000000x4000_k1e6", "mixed", "f64", "sketch_mfma_bf16x3"): 780.1e9,
 }
 
 WORKLOADS = {
