@@ -716,9 +716,9 @@ __device__ __forceinline__ int rr_pair_index(int i) {
 // One round of the block round robin, Gram form.  The 2 BW columns of the
 // block pair stay in registers (thread t owns rows t + 512 u, u < EPU).
 // Their 2 BW x 2 BW Gram matrix G is reduced once; the 2 BW - 1 sub-rounds
-// of rotations are then carried out on G itself by one wavefront, each lane
-// owning entries of G and of the accumulated rotation J (G <- R^T G R,
-// J <- J R per sub-round, through LDS), and the columns are replaced by x J in a single
+// of rotations are then carried out on G itself, every thread owning one
+// entry of G and of the accumulated rotation J (G <- R^T G R, J <- J R per
+// sub-round, through LDS), and the columns are replaced by x J in a single
 // pass.  Each angle follows the one-sided (Hestenes) formula from the
 // current Gram entries.  The first sub-round tests exact inner products of
 // the columns and a sub-round without rotations leaves G and J bit for bit
@@ -741,10 +741,10 @@ jacobi_gram_round(double *__restrict__ Y, int d, int nblocks, int round, int pai
     constexpr int NFULL = NG / 32;                        // 32-value reduction chunks
     constexpr int NREST = NG - 32 * NFULL;                // values of the last chunk
     constexpr int NVREST = NREST ? pow2_at_least<NREST>() : 1;
-    static_assert(NL <= 16, "the sub-rounds keep NL^2 / 64 entries of G and J per lane");
+    static_assert(NL * NL <= 512, "one thread per Gram entry");
     __shared__ double part[8][32 * NFULL + NVREST];
-    __shared__ double Gs[2][NL][NL + 1], Js[2][NL][NL + 1];
-    __shared__ int nrot_s, cur_s;
+    __shared__ double Gs[2][NL][NL + 1], Js[2][NL][NL + 1], CSs[BW][2];
+    __shared__ int nrot_s, any_s[NL];
     const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
     int bi, bj;
     rr_pair(nblocks, round, pair, bi, bj);
@@ -760,6 +760,8 @@ jacobi_gram_round(double *__restrict__ Y, int d, int nblocks, int round, int pai
 #pragma unroll
         for (int u = 0; u < EPU; ++u) x[cl][u] = column_load(rs, tid + 512 * u);
     }
+    if (tid == 0) nrot_s = 0;
+    if (tid < NL) any_s[tid] = 0;
     // ---- Gram matrix: per-thread partial sums, reduced in chunks of <= 32
     // values per butterfly, then across the 8 wavefronts
     auto chunk = [&](auto cidx, auto nv) {
@@ -788,88 +790,64 @@ jacobi_gram_round(double *__restrict__ Y, int d, int nblocks, int round, int pai
     if constexpr (NREST > 0)
         chunk(std::integral_constant<int, NFULL>{}, std::integral_constant<int, NVREST>{});
     __syncthreads();
-    // The 2 BW - 1 sub-rounds run in wavefront 0 alone: lane l owns the
-    // entries e = l + 64 j of G and J (row e / NL, column e % NL).  The angles
-    // of a sub-round are formed by lanes k < BW and reach the other lanes by
-    // shuffles; a sub-round's G and J go through LDS, ordered within the
-    // wavefront by a fence, so the workgroup meets at two barriers in all
-    // instead of two per sub-round.  Every entry is computed by the same
-    // expression as with one thread per entry.
-    constexpr int NE = NL * NL, EPL = (NE + 63) / 64;
-    if (wid == 0) {
-        double gv[EPL], jv[EPL];
-        int er[EPL], ec[EPL];
+    // thread t < NL^2 owns entry (r, c) of G and J
+    const bool owner = tid < NL * NL;
+    const int r = owner ? tid / NL : 0, c = owner ? tid % NL : 0;
+    double gv = 0.0, jv = 0.0;
+    if (owner) {
+        const int k = r <= c ? gram_index<NL>(r, c) : gram_index<NL>(c, r);
 #pragma unroll
-        for (int j = 0; j < EPL; ++j) {
-            const int e = lane + 64 * j;
-            er[j] = e < NE ? e / NL : 0;
-            ec[j] = e < NE ? e % NL : 0;
-            gv[j] = 0.0;
-            jv[j] = 0.0;
-            if (e < NE) {
-                const int r = er[j], c = ec[j];
-                const int k = r <= c ? gram_index<NL>(r, c) : gram_index<NL>(c, r);
-#pragma unroll
-                for (int w = 0; w < 8; ++w) gv[j] += part[w][k];
-                jv[j] = r == c ? 1.0 : 0.0;
-                Gs[0][r][c] = gv[j];
-                Js[0][r][c] = jv[j];
-            }
-        }
-        __threadfence_block();
-        int cur = 0, mine = 0;
-        auto sub_round = [&](auto tsub) {
-            constexpr int TS = decltype(tsub)::value;
-            // (a) the angle of pair k by lane k
-            double cs = 1.0, sn = 0.0;
-            bool rot = false;
-            if (lane < BW) {
-                const int k = lane;
-                int a = TS + k, b = TS - k;
-                a -= a >= NL - 1 ? NL - 1 : 0;
-                b += b < 0 ? NL - 1 : 0;
-                a = k == 0 ? NL - 1 : a;
-                const int pp = a < b ? a : b, qq = a < b ? b : a;
-                rot = jacobi_angle(Gs[cur][pp][pp], Gs[cur][qq][qq], Gs[cur][pp][qq], tol, tiny2, cs, sn);
-                mine += rot ? 1 : 0;
-            }
-            if (!__any(rot)) return;  // uniform: G and J stay as they are
-            // (b) G <- R^T G R and J <- J R entry by entry
-#pragma unroll
-            for (int j = 0; j < EPL; ++j) {
-                const int r = er[j], c = ec[j];
-                const int r2 = rr_partner<NL, TS>(r), c2 = rr_partner<NL, TS>(c);
-                const int kr = rr_pair_index<NL, TS>(r), kc = rr_pair_index<NL, TS>(c);
-                const double csr = __shfl(cs, kr), snr = __shfl(sn, kr);
-                const double csc = __shfl(cs, kc), snc = __shfl(sn, kc);
-                if (lane + 64 * j < NE) {
-                    const double ar = csr, br = r < r2 ? -snr : snr;
-                    const double ac = csc, bc = c < c2 ? -snc : snc;
-                    const double g_rc2 = Gs[cur][r][c2], g_r2c = Gs[cur][r2][c], g_r2c2 = Gs[cur][r2][c2];
-                    const double j_rc2 = Js[cur][r][c2];
-                    gv[j] = ar * (ac * gv[j] + bc * g_rc2) + br * (ac * g_r2c + bc * g_r2c2);
-                    jv[j] = ac * jv[j] + bc * j_rc2;
-                    Gs[cur ^ 1][r][c] = gv[j];
-                    Js[cur ^ 1][r][c] = jv[j];
-                }
-            }
-            cur ^= 1;
-            __threadfence_block();
-        };
-        [&]<int... TS>(std::integer_sequence<int, TS...>) {
-            (sub_round(std::integral_constant<int, TS>{}), ...);
-        }(std::make_integer_sequence<int, NL - 1>{});
-        // rotations of the round (lanes < BW counted theirs)
-        int tot = mine;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
-        if (lane == 0) {
-            nrot_s = tot;
-            cur_s = cur;
-        }
+        for (int w = 0; w < 8; ++w) gv += part[w][k];
+        jv = r == c ? 1.0 : 0.0;
+        Gs[0][r][c] = gv;
+        Js[0][r][c] = jv;
     }
     __syncthreads();
-    const int nrot = nrot_s, cur = cur_s;
+    int mine = 0, cur = 0;
+    auto sub_round = [&](auto tsub) {
+        constexpr int TS = decltype(tsub)::value;
+        // (a) the angle of pair k, once, by thread k
+        if (tid < BW) {
+            const int k = tid;
+            int a = TS + k, b = TS - k;
+            a -= a >= NL - 1 ? NL - 1 : 0;
+            b += b < 0 ? NL - 1 : 0;
+            a = k == 0 ? NL - 1 : a;
+            const int pp = a < b ? a : b, qq = a < b ? b : a;
+            double cs, sn;
+            if (jacobi_angle(Gs[cur][pp][pp], Gs[cur][qq][qq], Gs[cur][pp][qq], tol, tiny2, cs, sn)) {
+                ++mine;
+                any_s[TS] = 1;
+            }
+            CSs[k][0] = cs;
+            CSs[k][1] = sn;
+        }
+        __syncthreads();
+        if (!any_s[TS]) return;  // uniform: G and J stay as they are
+        // (b) G <- R^T G R and J <- J R entry by entry
+        if (owner) {
+            // partners of r and c in this sub-round and the indices of their pairs
+            const int r2 = rr_partner<NL, TS>(r), c2 = rr_partner<NL, TS>(c);
+            const int kr = rr_pair_index<NL, TS>(r), kc = rr_pair_index<NL, TS>(c);
+            // new column x = alpha x_own + beta x_partner
+            const double ar = CSs[kr][0], br = r < r2 ? -CSs[kr][1] : CSs[kr][1];
+            const double ac = CSs[kc][0], bc = c < c2 ? -CSs[kc][1] : CSs[kc][1];
+            const double g_rc2 = Gs[cur][r][c2], g_r2c = Gs[cur][r2][c], g_r2c2 = Gs[cur][r2][c2];
+            const double j_rc2 = Js[cur][r][c2];
+            gv = ar * (ac * gv + bc * g_rc2) + br * (ac * g_r2c + bc * g_r2c2);
+            jv = ac * jv + bc * j_rc2;
+            Gs[cur ^ 1][r][c] = gv;
+            Js[cur ^ 1][r][c] = jv;
+        }
+        cur ^= 1;
+        __syncthreads();
+    };
+    [&]<int... TS>(std::integer_sequence<int, TS...>) {
+        (sub_round(std::integral_constant<int, TS>{}), ...);
+    }(std::make_integer_sequence<int, NL - 1>{});
+    if (mine) atomicAdd(&nrot_s, mine);
+    __syncthreads();
+    const int nrot = nrot_s;
     if (nrot == 0) return;
     // ---- columns <- x J, written straight back
 #pragma unroll
