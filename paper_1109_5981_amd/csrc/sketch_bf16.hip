@@ -227,25 +227,31 @@ __device__ __forceinline__ void store_tp(uint16_t (*As)[HBN][HP], const u32x4 (&
 // One stage's operands on their way from HBM to LDS: the T terms (PRET),
 // else the FP64 tile of T; the G tile when PRE (else G is generated at the
 // store).
-template <bool PRE, bool PRET>
+template <bool PRE, bool PRET, int NH>
 struct StageRegs {
-    u32x4 tp[PRET ? 3 : 1];
+    u32x4 tp[NH][PRET ? 3 : 1];
     double t[PRET ? 1 : 8];
     uint32_t tmask;
-    u32x4 g;
+    u32x4 g[NH];
 };
 
 // PRE: G comes from the pre-generated panels Gb, else each stage generates
 // its tile (gen_g).  PRET (with PRE): the three terms of T come from the
-// split planes Tp, else each stage splits its tile of T (store_t).
-template <bool PRE, bool PRET>
+// split planes Tp, else each stage splits its tile of T (store_t).  A stage
+// covers NH panels of 32 k (NH = 2 with the pre-formed operands: half the
+// barriers and stores per product), each with its own LDS tiles; the
+// products run in the same k order either way.
+template <bool PRE, bool PRET, int NH>
 __global__ void __launch_bounds__(HNT, 1)
 sketch_bf16_kernel(const double *__restrict__ T, int64_t ldt, int64_t K, int64_t d, int64_t s,
                    uint64_t seed, const uint16_t *__restrict__ Gb, const uint16_t *__restrict__ Tp,
                    int64_t npanel, int64_t dp, int64_t k_per_split, int tiles_m, double *__restrict__ Xp) {
     static_assert(PRE || !PRET, "the split planes come with the pre-generated G");
-    __shared__ uint16_t Gs[HBM_][HP];
-    __shared__ uint16_t As[3][HBN][HP];
+    static_assert(NH == 1 || PRET, "stages of several panels read the pre-formed operands");
+    static_assert(FLUSH % NH == 0, "flushes fall on stage boundaries");
+    constexpr int KS = HKT * NH;  // k per stage
+    __shared__ uint16_t Gs[NH][HBM_][HP];
+    __shared__ uint16_t As[NH][3][HBN][HP];
     const int tile = blockIdx.x;
     const int64_t m0 = (int64_t)(tile % tiles_m) * HBM_;
     const int64_t n0 = (int64_t)(tile / tiles_m) * HBN;
@@ -266,42 +272,53 @@ sketch_bf16_kernel(const double *__restrict__ T, int64_t ldt, int64_t K, int64_t
 #pragma unroll
             for (int v = 0; v < 4; ++v) acc64[i][j][v] = 0.0;
         }
-    const int64_t nstage = kend > kbeg ? ceil_div(kend - kbeg, HKT) : 0;
-    using Regs = StageRegs<PRE, PRET>;
+    const int64_t nstage = kend > kbeg ? ceil_div(kend - kbeg, KS) : 0;
+    using Regs = StageRegs<PRE, PRET, NH>;
+    // (with NH = 2 the stage's second panel always exists: the host pads the
+    // panels to a multiple of NH, zero past K in the planes)
     auto load = [&](Regs &r, int64_t k0) {
-        if constexpr (PRET) load_tp(Tp, npanel, dp, k0, n0, r.tp);
-        else r.tmask = load_t(T, ldt, k0, kend, n0, d, r.t);
-        if constexpr (PRE) r.g = load_g(Gb, s, m0, k0);
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+            if constexpr (PRET) load_tp(Tp, npanel, dp, k0 + HKT * h, n0, r.tp[h]);
+            if constexpr (PRE) r.g[h] = load_g(Gb, s, m0, k0 + HKT * h);
+        }
+        if constexpr (!PRET) r.tmask = load_t(T, ldt, k0, kend, n0, d, r.t);
     };
     auto store = [&](const Regs &r, int64_t k0) {
-        if constexpr (PRET) store_tp(As, r.tp);
-        else store_t(As, r.t, r.tmask);
-        if constexpr (PRE) store_g(Gs, r.g);
-        else gen_g(Gs, seed, m0, k0);
-    };
-    // one stage: 24 MFMA per wavefront on the operands in LDS (rows of T
-    // past the end of the slice were loaded as zero and the G values there
-    // are finite, so their products vanish), then the FP64 flush every
-    // FLUSH stages
-    auto mma = [&](int64_t st) {
-        bf16x8 a[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int r = wm * 64 + i * 16 + lr;
-            a[i] = load8(&Gs[r][8 * swz(r, lk)]);
+        for (int h = 0; h < NH; ++h) {
+            if constexpr (PRET) store_tp(As[h], r.tp[h]);
+            if constexpr (PRE) store_g(Gs[h], r.g[h]);
         }
+        if constexpr (!PRET) store_t(As[0], r.t, r.tmask);
+        if constexpr (!PRE) gen_g(Gs[0], seed, m0, k0);
+    };
+    // one stage: 24 MFMA per wavefront and panel on the operands in LDS
+    // (rows of T past the end of the slice were loaded as zero and the G
+    // values there are finite, so their products vanish), then the FP64
+    // flush every FLUSH panels
+    auto mma = [&](int64_t st) {
 #pragma unroll
-        for (int term = 0; term < 3; ++term) {
+        for (int h = 0; h < NH; ++h) {
+            bf16x8 a[4];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int c = wn * 32 + j * 16 + lr;
-                const bf16x8 b = load8(&As[term][c][8 * swz(c, lk)]);
+            for (int i = 0; i < 4; ++i) {
+                const int r = wm * 64 + i * 16 + lr;
+                a[i] = load8(&Gs[h][r][8 * swz(r, lk)]);
+            }
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b, acc[i][j], 0, 0, 0);
+            for (int term = 0; term < 3; ++term) {
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int c = wn * 32 + j * 16 + lr;
+                    const bf16x8 b = load8(&As[h][term][c][8 * swz(c, lk)]);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b, acc[i][j], 0, 0, 0);
+                }
             }
         }
-        if ((st + 1) % FLUSH == 0 || st + 1 == nstage) {
+        if ((st + 1) % (FLUSH / NH) == 0 || st + 1 == nstage) {
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -318,8 +335,8 @@ sketch_bf16_kernel(const double *__restrict__ T, int64_t ldt, int64_t K, int64_t
     // through the loop leaves the same loads in flight and the waits before
     // the LDS stores cover one set only.
     if (nstage > 0) {
-        const int64_t klast = kbeg + (nstage - 1) * HKT;
-        auto kst = [&](int64_t st) { return min(kbeg + st * HKT, klast); };
+        const int64_t klast = kbeg + (nstage - 1) * KS;
+        auto kst = [&](int64_t st) { return min(kbeg + st * KS, klast); };
         auto stage = [&](Regs &r, int64_t st) {
             __syncthreads();  // the previous stage's operands are consumed
             store(r, kst(st));
@@ -395,9 +412,10 @@ static size_t pregen_max_bytes() {
 
 size_t sketch_bf16_g_bytes(int64_t K, int64_t d, int64_t s) {
     const size_t cap = pregen_max_bytes();
-    const size_t b = (size_t)ceil_div(K, HKT) * (size_t)s * 32 * sizeof(uint16_t);
+    const size_t np = (size_t)round_up(ceil_div(K, HKT), 2);
+    const size_t b = np * (size_t)s * 32 * sizeof(uint16_t);
     if (b > cap) return 0;
-    const size_t t = (size_t)3 * (size_t)ceil_div(K, HKT) * (size_t)(ceil_div(d, HBN) * HBN) * 32 * sizeof(uint16_t);
+    const size_t t = (size_t)3 * np * (size_t)(ceil_div(d, HBN) * HBN) * 32 * sizeof(uint16_t);
     return b + (t <= cap ? t : 0);
 }
 
@@ -405,19 +423,6 @@ void sketch_rows_bf16(int64_t K, int64_t d, const double *T, int64_t ldt, double
                       uint64_t seed, double *X, hipStream_t st, double *kernel_ms) {
     const int tiles_m = (int)ceil_div(s, HBM_), tiles_n = (int)ceil_div(d, HBN);
     const int64_t tiles = (int64_t)tiles_m * tiles_n;
-    const int64_t want = 2 * (int64_t)device_cus();
-    int64_t nsplit = tiles >= want ? 1 : ceil_div(want, tiles);
-    nsplit = std::min<int64_t>(nsplit, std::max<int64_t>(1, K / (16 * HKT)));
-    const int64_t cap = std::max<int64_t>(1, (int64_t(1) << 31) / (8 * s * d));
-    nsplit = std::max<int64_t>(1, std::min(nsplit, cap));
-    const int64_t kps = round_up(ceil_div(K, nsplit), HKT);
-    nsplit = std::max<int64_t>(1, ceil_div(K, kps));
-    DevBuf part;
-    double *Xp = X;
-    if (nsplit > 1) {
-        part.alloc((size_t)nsplit * (size_t)s * (size_t)d * sizeof(double));
-        Xp = part.as<double>();
-    }
     hipEvent_t ev[2] = {nullptr, nullptr};
     if (kernel_ms) {
         LSRN_HIP(hipEventCreate(&ev[0]));
@@ -425,10 +430,12 @@ void sketch_rows_bf16(int64_t K, int64_t d, const double *T, int64_t ldt, double
         LSRN_HIP(hipEventRecord(ev[0], st));
     }
     // bf16(G) generated once into panels (s x K x 2 bytes) when that fits:
-    // each tile of G is then read instead of generated once per column tile
+    // each tile of G is then read instead of generated once per column tile.
+    // The panels are padded to an even count (the kernel's stages of two
+    // panels), and so are the split planes below.
     DevBuf gpan;
     const size_t pre_cap = pregen_max_bytes();
-    const int64_t npanel = ceil_div(K, HKT);
+    const int64_t npanel = round_up(ceil_div(K, HKT), 2);
     const size_t gbytes = (size_t)npanel * (size_t)s * 32 * sizeof(uint16_t);
     if (gbytes <= pre_cap) {
         try {
@@ -450,6 +457,23 @@ void sketch_rows_bf16(int64_t K, int64_t d, const double *T, int64_t ldt, double
             tpl.release();  // split in the kernel
         }
     }
+    // k split into slices when the tiles alone do not fill the chip; each
+    // slice a whole number of two-panel stages on every path, so that the
+    // paths share their slices and flush windows (and give the same bits)
+    const int64_t kstage = 2 * HKT;
+    const int64_t want = 2 * (int64_t)device_cus();
+    int64_t nsplit = tiles >= want ? 1 : ceil_div(want, tiles);
+    nsplit = std::min<int64_t>(nsplit, std::max<int64_t>(1, K / (16 * HKT)));
+    const int64_t cap = std::max<int64_t>(1, (int64_t(1) << 31) / (8 * s * d));
+    nsplit = std::max<int64_t>(1, std::min(nsplit, cap));
+    const int64_t kps = round_up(ceil_div(K, nsplit), kstage);
+    nsplit = std::max<int64_t>(1, ceil_div(K, kps));
+    DevBuf part;
+    double *Xp = X;
+    if (nsplit > 1) {
+        part.alloc((size_t)nsplit * (size_t)s * (size_t)d * sizeof(double));
+        Xp = part.as<double>();
+    }
     dim3 grid((unsigned)tiles, (unsigned)nsplit);
     if (gpan.bytes()) {
         const int64_t total = npanel * s * 8;
@@ -459,14 +483,14 @@ void sketch_rows_bf16(int64_t K, int64_t d, const double *T, int64_t ldt, double
             // npanel x dp / 64 workgroups: at most 2^22 within the 32 GiB bound
             split_t_planes_kernel<<<(unsigned)(npanel * (dp / 64)), 256, 0, st>>>(
                 T, ldt, K, d, npanel, dp, tpl.as<uint16_t>());
-            sketch_bf16_kernel<true, true><<<grid, HNT, 0, st>>>(T, ldt, K, d, s, seed, gpan.as<uint16_t>(),
+            sketch_bf16_kernel<true, true, 2><<<grid, HNT, 0, st>>>(T, ldt, K, d, s, seed, gpan.as<uint16_t>(),
                                                                  tpl.as<uint16_t>(), npanel, dp, kps, tiles_m, Xp);
         } else {
-            sketch_bf16_kernel<true, false><<<grid, HNT, 0, st>>>(T, ldt, K, d, s, seed, gpan.as<uint16_t>(),
+            sketch_bf16_kernel<true, false, 1><<<grid, HNT, 0, st>>>(T, ldt, K, d, s, seed, gpan.as<uint16_t>(),
                                                                   nullptr, npanel, dp, kps, tiles_m, Xp);
         }
     } else {
-        sketch_bf16_kernel<false, false><<<grid, HNT, 0, st>>>(T, ldt, K, d, s, seed, nullptr, nullptr, npanel,
+        sketch_bf16_kernel<false, false, 1><<<grid, HNT, 0, st>>>(T, ldt, K, d, s, seed, nullptr, nullptr, npanel,
                                                                dp, kps, tiles_m, Xp);
     }
     LSRN_HIP(hipGetLastError());
