@@ -1287,6 +1287,26 @@ __global__ void __launch_bounds__(1024) normalize_kernel(double *__restrict__ v,
         for (int64_t i = tid; i < d; i += 1024) v[i] /= nv;
 }
 
+// |R^-1|_2^2 estimated by eight power steps on R^-T R^-1 from a uniform
+// start (P is R^-1 row-major, Ri, column-major, is R^-T row-major): a lower
+// bound, within a small factor for such sketches.  Synchronises.
+double inv_norm2_sq(int64_t d, const double *P, const double *Ri, hipStream_t st) {
+    DevBuf vb((size_t)2 * d * sizeof(double)), nb(sizeof(double));
+    std::vector<double> v0((size_t)d, 1.0 / std::sqrt((double)d));
+    LSRN_HIP(hipMemcpyAsync(vb.as<double>(), v0.data(), (size_t)d * sizeof(double), hipMemcpyHostToDevice, st));
+    double *v = vb.as<double>(), *u = vb.as<double>() + d;
+    for (int it = 0; it < 8; ++it) {
+        gemv_sq_kernel<<<(unsigned)ceil_div(d, 4), 256, 0, st>>>(P, d, d, v, u);
+        gemv_sq_kernel<<<(unsigned)ceil_div(d, 4), 256, 0, st>>>(Ri, d, d, u, v);
+        normalize_kernel<<<1, 1024, 0, st>>>(v, d, nb.as<double>());
+    }
+    LSRN_HIP(hipGetLastError());
+    double lam = 0.0;
+    LSRN_HIP(hipMemcpyAsync(&lam, nb.as<double>(), sizeof(double), hipMemcpyDeviceToHost, st));
+    LSRN_HIP(hipStreamSynchronize(st));  // before v0 and the buffers go
+    return lam;
+}
+
 // The full-rank case of steps 4-5 without the Jacobi sweeps.  With X = Q R,
 // N = R^-1 gives T N the singular values of T V Sigma^-1 (R^-1 = V Sigma^-1
 // times an orthogonal factor), so it preconditions as well (reading of
@@ -1329,19 +1349,7 @@ bool full_rank_inverse(int64_t s, int64_t d, const double *R, double rcond, doub
     // a small factor for such sketches.
     double cmax = 0.0;
     for (int64_t j = 0; j < d; ++j) cmax = std::max(cmax, h[(size_t)j]);
-    DevBuf vb((size_t)2 * d * sizeof(double)), nb(sizeof(double));
-    std::vector<double> v0((size_t)d, 1.0 / std::sqrt((double)d));
-    LSRN_HIP(hipMemcpyAsync(vb.as<double>(), v0.data(), (size_t)d * sizeof(double), hipMemcpyHostToDevice, st));
-    double *v = vb.as<double>(), *u = vb.as<double>() + d;
-    for (int it = 0; it < 8; ++it) {
-        gemv_sq_kernel<<<(unsigned)ceil_div(d, 4), 256, 0, st>>>(P, d, d, v, u);
-        gemv_sq_kernel<<<(unsigned)ceil_div(d, 4), 256, 0, st>>>(Ri.as<double>(), d, d, u, v);
-        normalize_kernel<<<1, 1024, 0, st>>>(v, d, nb.as<double>());
-    }
-    LSRN_HIP(hipGetLastError());
-    double lam = 0.0;
-    LSRN_HIP(hipMemcpyAsync(&lam, nb.as<double>(), sizeof(double), hipMemcpyDeviceToHost, st));
-    LSRN_HIP(hipStreamSynchronize(st));  // before g, v0 and the buffers go
+    const double lam = inv_norm2_sq(d, P, Ri.as<double>(), st);
     res.rank = d;
     res.sweeps = 0;
     res.sigma_max = std::sqrt(cmax);
@@ -1559,18 +1567,41 @@ PrecondResult precond_qr_inverse(int64_t s, int64_t d, double *X, double rcond, 
     };
     // Cholesky QR: R^T R = X^T X from the upper triangle of the Gram matrix
     // (one FP64 MFMA product, then a blocked Cholesky).  X R^-1 is then
-    // orthonormal to about d eps kappa(X)^2, so it is used only while
-    // max r_ii / min r_ii (a lower bound on kappa) keeps that below 1e-3;
-    // otherwise, or when a pivot is not positive, Householder QR of X.
+    // orthonormal to about d eps kappa(X)^2, so it is kept only while an
+    // estimate of kappa(R) (largest column norm of R times |R^-1|_2 from
+    // power steps, both from below, hence the margin) keeps d eps kappa^2
+    // below 1e-5; max r_ii / min r_ii, a cheaper lower bound, screens first.
+    // Otherwise, or when a pivot is not positive, Householder QR of X (for
+    // up to 40960 sketch rows; beyond that the call fails).
     DevBuf gram((size_t)d * (size_t)d * sizeof(double));
     gemm(true, true, d, d, s, 1.0, X, s, X, s, 0.0, gram.as<double>(), d, st);
     const double *R = gram.as<double>();
     int64_t ldr = d;
+    DevBuf Rinv((size_t)d * (size_t)d * sizeof(double));
+    // P (row-major d x d) = R^-1: invert column-major, then transpose
+    auto invert = [&] {
+        trtri_upper(d, R, ldr, Rinv.as<double>(), d, st);
+        transpose(d, d, Rinv.as<double>(), d, P, st);
+        LSRN_HIP(hipStreamSynchronize(st));
+    };
     bool ok = cholesky_upper(d, gram.as<double>(), d, st);
     if (ok) {
         sorted_diag(R, ldr);
         const double ratio = h[0] / h[(size_t)d - 1];
-        ok = h[(size_t)d - 1] > 0.0 && ratio * ratio * (double)d * DBL_EPSILON <= 1e-3;
+        ok = h[(size_t)d - 1] > 0.0 && ratio * ratio * (double)d * DBL_EPSILON <= 1e-5;
+    }
+    if (ok) {
+        invert();
+        DevBuf part((size_t)2 * d * sizeof(double));
+        col_sumsq_kernel<<<(unsigned)d, 256, 0, st>>>(R, ldr, Rinv.as<double>(), d, part.as<double>());
+        LSRN_HIP(hipGetLastError());
+        std::vector<double> cs((size_t)d);
+        LSRN_HIP(hipMemcpyAsync(cs.data(), part.as<double>(), (size_t)d * sizeof(double), hipMemcpyDeviceToHost, st));
+        LSRN_HIP(hipStreamSynchronize(st));
+        double cmax = 0.0;
+        for (int64_t j = 0; j < d; ++j) cmax = std::max(cmax, cs[(size_t)j]);
+        const double k2 = cmax * inv_norm2_sq(d, P, Rinv.as<double>(), st);  // kappa^2 estimate
+        ok = std::isfinite(k2) && k2 * (double)d * DBL_EPSILON <= 1e-5;
     }
     if (!ok) {
         gram.release();
@@ -1582,11 +1613,7 @@ PrecondResult precond_qr_inverse(int64_t s, int64_t d, double *X, double rcond, 
     if (!(h[(size_t)d - 1] > rc * h[0]))
         fail(LSRN_E_UNSUPPORTED, "precond: the QR-inverse preconditioner needs a full-rank sketch");
     LSRN_HIP(hipMemcpyAsync(sigma, h.data(), (size_t)d * sizeof(double), hipMemcpyHostToDevice, st));
-    // P (row-major d x d) = R^-1: invert column-major, then transpose
-    DevBuf Rinv((size_t)d * (size_t)d * sizeof(double));
-    trtri_upper(d, R, ldr, Rinv.as<double>(), d, st);
-    transpose(d, d, Rinv.as<double>(), d, P, st);
-    LSRN_HIP(hipStreamSynchronize(st));
+    if (!ok) invert();
     res.rank = d;
     res.sigma_max = h[0];
     res.sigma_min_kept = h[(size_t)d - 1];

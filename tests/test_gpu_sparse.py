@@ -86,10 +86,11 @@ def test_precond_qr_matches_oracle(L, orc, s, d, spread):
     dg_g, P_g = host(dg_g), host(P_g)
     eps = np.finfo(float).eps
     kappa = np.linalg.cond(X)
-    # the library takes R from the Cholesky factor of X^T X while
-    # (max |r_ii| / min |r_ii|)^2 d eps <= 1e-3, else from Householder QR:
-    # backward errors of order d eps kappa^2 and d eps kappa respectively
-    cholesky = (dg_o[0] / dg_o[-1]) ** 2 * d * eps <= 1e-3
+    # the library takes R from the Cholesky factor of X^T X while its
+    # estimate of kappa keeps d eps kappa^2 <= 1e-5, else from Householder
+    # QR: backward errors of order d eps kappa^2 and d eps kappa
+    # respectively (these cases lie far on either side of the threshold)
+    cholesky = kappa ** 2 * d * eps <= 1e-5
     err = 10 * d * eps * kappa ** 2 if cholesky else 100 * d * eps * kappa
     assert (spread >= 1e-3) == cholesky
     np.testing.assert_allclose(dg_g, dg_o, rtol=err, atol=0)
@@ -100,6 +101,22 @@ def test_precond_qr_matches_oracle(L, orc, s, d, spread):
     assert np.linalg.norm(PPg - PPo) / np.linalg.norm(PPo) < err
     Q = X @ P_g
     assert np.linalg.norm(Q.T @ Q - np.eye(d), 2) < err
+
+
+def test_precond_qr_unit_diagonal_ill_conditioned(L):
+    """A sketch whose R has a unit diagonal (ratio 1) but kappa 2.8e6: the
+    diagonal ratio alone would keep Cholesky QR (orthogonality lost to
+    about 8e-6 here); the kappa estimate sends it to Householder QR, whose
+    X R^-1 is orthonormal to the order of d eps kappa."""
+    d, s = 40, 100
+    R0 = np.eye(d) - 0.4 * np.triu(np.ones((d, d)), 1)
+    Q0, _ = np.linalg.qr(np.random.default_rng(3).standard_normal((s, d)))
+    X = Q0 @ R0
+    kappa = np.linalg.cond(X)
+    assert 1e6 < kappa < 1e7
+    _, P_g = L.precond_qr(dev(X.T.copy()))
+    Q = X @ host(P_g)
+    assert np.linalg.norm(Q.T @ Q - np.eye(d), 2) < 100 * d * np.finfo(float).eps * kappa
 
 
 def test_precond_qr_rejects_rank_deficient(L):
