@@ -418,6 +418,20 @@ def batch_main(args):
     torch.cuda.synchronize()
     t_single = time.perf_counter() - t0
     diff = max((torch.linalg.norm(a - c) / torch.linalg.norm(c)).item() for a, c in zip(xs, xs1))
+    # the same batch with two refinement steps (double-double residuals, CG
+    # corrections in shared launches), against the single solves refined
+    # the same way with the SVD preconditioner the batch forms
+    ropts = dict(opts, refine=2)
+    lsrn.solve_batch(As, bs, allow_not_converged=True, **ropts)       # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xr, infos_r = lsrn.solve_batch(As, bs, allow_not_converged=True, **ropts)
+    torch.cuda.synchronize()
+    t_batch_r = time.perf_counter() - t0
+    xr1 = [lsrn.solve_dense(A, b, allow_not_converged=True, precond="svd", **ropts)[0]
+           for A, b in zip(As, bs)]
+    torch.cuda.synchronize()
+    diff_r = max((torch.linalg.norm(a - c) / torch.linalg.norm(c)).item() for a, c in zip(xr, xr1))
     line = {
         "metric": "batched small LS solves/s (one launch per phase for the whole batch)",
         "value": round(args.batch / t_batch, 2),
@@ -434,6 +448,10 @@ def batch_main(args):
                      "batched_iterations": round(infos[0]["t_iter_ms"], 3)},
         "iters_mean": float(np.mean([i["iters"] for i in infos])),
         "max_rel_diff_vs_single": diff,
+        "refined": {"refine": 2, "solves_per_s": round(args.batch / t_batch_r, 2),
+                    "batched_iterations_ms": round(infos_r[0]["t_iter_ms"], 3),
+                    "refine_iters_mean": float(np.mean([i["refine_iters"] for i in infos_r])),
+                    "max_rel_diff_vs_single_refined": diff_r},
     }
     print(json.dumps(line))
 

@@ -349,17 +349,22 @@ lsrn_status lsrn_iterate_csr(int64_t m, int64_t n, int64_t nnz, const int64_t *r
  * Many small over-determined solves at once (Alg. 1 for each problem): A[p]
  * dense FP64 row-major, m[p] >= n[p], n[p] <= 512, leading dimension
  * lda[p]; b[p] length m[p]; x[p] length n[p] (arrays of device pointers
- * held on the host).  Each problem's sketch runs in turn on the stream;
- * the QR of the sketches (up to 1024 rows) and the Jacobi sweeps (d <= 512)
+ * held on the host).  The sketches of all problems run in one launch; the
+ * QR of the sketches (up to 1024 rows) and the Jacobi sweeps (d <= 512)
  * run for all problems in shared launches; then the LSQR iterations of all
  * problems advance together: every kernel launch covers the whole batch
  * (one work item per problem row block, column chunk or problem) and each
  * chunk of iterations is replayed as a HIP graph, so the number of
- * launches does not grow with the number of problems.  One option set for all problems; LSQR only, no refinement,
+ * launches does not grow with the number of problems.  opt->refine
+ * refinement steps follow the same way (the double-double residual
+ * A^T (b - A x) of every problem, then CG on the preconditioned normal
+ * equations to opt->refine_tol for all problems together, x += N z; as in
+ * lsrn_solve_dense).  One option set for all problems; LSQR only,
  * lambda = 0, precision FP64, the SVD preconditioner (LSRN_E_UNSUPPORTED
  * otherwise).  infos (count entries, may be NULL) report per problem; the
- * stage times are those of the whole batch.  LSRN_E_NOT_CONVERGED if any
- * problem reached max_iter (its x holds the last iterate).
+ * stage times are those of the whole batch (t_iter_ms includes the
+ * refinement).  LSRN_E_NOT_CONVERGED if any problem's LSQR reached
+ * max_iter (its x holds the last iterate, refined).
  */
 lsrn_status lsrn_solve_batch(int32_t count, const int64_t *m, const int64_t *n,
                              const double *const *A, const int64_t *lda, const double *const *b,

@@ -861,10 +861,10 @@ lsrn_status lsrn_solve_batch(int32_t count, const int64_t *m, const int64_t *n,
     check_options(opt);
     LSRN_REQUIRE(count >= 0, "count must be >= 0");
     LSRN_REQUIRE(count == 0 || (m && n && A && lda && b && x), "NULL pointer");
-    if (opt.method != LSRN_LSQR || opt.refine != 0 || opt.lambda != 0.0 ||
-        opt.precision != LSRN_PREC_FP64 || opt.precond == LSRN_PRECOND_QR)
+    if (opt.method != LSRN_LSQR || opt.lambda != 0.0 || opt.precision != LSRN_PREC_FP64 ||
+        opt.precond == LSRN_PRECOND_QR)
         fail(LSRN_E_UNSUPPORTED, "the batched path runs FP64 LSQR with the SVD preconditioner, "
-                                 "without refinement or lambda");
+                                 "without lambda");
     hipStream_t st = (hipStream_t)stream;
     for (int32_t p = 0; p < count; ++p) {
         LSRN_REQUIRE(m[p] >= n[p] && n[p] > 0 && n[p] <= 512, "batched problems need m >= n, 0 < n <= 512");
@@ -942,12 +942,13 @@ lsrn_status lsrn_solve_batch(int32_t count, const int64_t *m, const int64_t *n,
         std::memset(&in, 0, sizeof(in));
         in.s = ss[(size_t)p]; in.d = n[p]; in.rank = prs[(size_t)p].rank;
         in.iters = full[(size_t)p].iters; in.sweeps = prs[(size_t)p].sweeps; in.tall = 1;
+        in.refine_steps = full[(size_t)p].refine_steps; in.refine_iters = full[(size_t)p].refine_iters;
         in.precond_used = LSRN_PRECOND_SVD;
         in.converged = full[(size_t)p].converged;
         in.sigma_l = full[(size_t)p].sigma_l; in.sigma_u = full[(size_t)p].sigma_u;
         in.sigma_max = prs[(size_t)p].sigma_max; in.sigma_min_kept = prs[(size_t)p].sigma_min_kept;
         in.t_svd_ms = tm.elapsed_ms(0, 1);   // sketches + preconditioners of the whole batch
-        in.t_iter_ms = tm.elapsed_ms(1, 2);  // batched iterations of the whole batch
+        in.t_iter_ms = tm.elapsed_ms(1, 2);  // batched iterations (and refinement) of the whole batch
         in.t_total_ms = tm.elapsed_ms(0, 2);
     }
     if (!all_conv) {

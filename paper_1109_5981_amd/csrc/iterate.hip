@@ -829,11 +829,11 @@ __global__ void set_state_kernel(State *st, int maxiter) {
 // Tall: h = T^T (b^ - T x) - lambda^2 x in double-double, one pass over T.
 // x (length L) is held per thread like w in the sweep.
 template <int CPT, typename TT>
-__global__ void __launch_bounds__(NT)
-resid_dd_tall_kernel(const TT *__restrict__ T, int64_t ldt, int64_t rows, int L, int nblocks,
-                     int64_t rows_per_block, const double *__restrict__ b,
-                     const double *__restrict__ x, double lambda, double *__restrict__ hpart_hi,
-                     double *__restrict__ hpart_lo) {
+__device__ __forceinline__ void resid_dd_tall_body(const TT *__restrict__ T, int64_t ldt, int64_t rows, int L,
+                                                   int nblocks, int64_t rows_per_block,
+                                                   const double *__restrict__ b, const double *__restrict__ x,
+                                                   double lambda, double *__restrict__ hpart_hi,
+                                                   double *__restrict__ hpart_lo, const int block) {
     __shared__ double red_hi[2][NT / 64], red_lo[2][NT / 64];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     double xr[CPT];
@@ -844,7 +844,7 @@ resid_dd_tall_kernel(const TT *__restrict__ T, int64_t ldt, int64_t rows, int L,
         xr[e] = col < L ? x[col] : 0.0;
         zr[e] = {0.0, 0.0};
     }
-    const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+    const int64_t r0 = (int64_t)block * rows_per_block;
     const int64_t r1 = min(rows, r0 + rows_per_block);
     int parity = 0;
     for (int64_t row = r0; row < r1; ++row) {
@@ -873,7 +873,7 @@ resid_dd_tall_kernel(const TT *__restrict__ T, int64_t ldt, int64_t rows, int L,
 #pragma unroll
         for (int e = 0; e < CPT; ++e) {
             const int col = col_of<CPT>(tid, e);
-            if (col < L && (col % nblocks) == (int)blockIdx.x) {
+            if (col < L && (col % nblocks) == block) {
                 // row m + col: residual 0 - lambda x_col, contributes lambda * residual
                 dd res = two_prod(-lambda, xr[e]);
                 zr[e] = dd_fma_dd(zr[e], lambda, res);
@@ -884,10 +884,20 @@ resid_dd_tall_kernel(const TT *__restrict__ T, int64_t ldt, int64_t rows, int L,
     for (int e = 0; e < CPT; ++e) {
         const int col = col_of<CPT>(tid, e);
         if (col < L) {
-            hpart_hi[(int64_t)blockIdx.x * L + col] = zr[e].hi;
-            hpart_lo[(int64_t)blockIdx.x * L + col] = zr[e].lo;
+            hpart_hi[(int64_t)block * L + col] = zr[e].hi;
+            hpart_lo[(int64_t)block * L + col] = zr[e].lo;
         }
     }
+}
+
+template <int CPT, typename TT>
+__global__ void __launch_bounds__(NT)
+resid_dd_tall_kernel(const TT *__restrict__ T, int64_t ldt, int64_t rows, int L, int nblocks,
+                     int64_t rows_per_block, const double *__restrict__ b,
+                     const double *__restrict__ x, double lambda, double *__restrict__ hpart_hi,
+                     double *__restrict__ hpart_lo) {
+    resid_dd_tall_body<CPT, TT>(T, ldt, rows, L, nblocks, rows_per_block, b, x, lambda, hpart_hi, hpart_lo,
+                                (int)blockIdx.x);
 }
 
 // Fat: z = T^T x = A x in double-double (rows of T weighted by x).
@@ -954,9 +964,8 @@ gemv_t_dd_kernel(const double *__restrict__ M, int64_t ld, int64_t nrows, int64_
 }
 
 // CG on K^T K z = c: given t = K^T K p (sweep) and acc0 = ||K p||^2.
-__global__ void __launch_bounds__(SNT)
-cg_step_kernel(const double *__restrict__ t, int64_t r, double *__restrict__ z,
-               double *__restrict__ res, double *__restrict__ p, State *st) {
+__device__ __forceinline__ void cg_step_body(const double *__restrict__ t, int64_t r, double *__restrict__ z,
+                                             double *__restrict__ res, double *__restrict__ p, State *st) {
     if (st->done) return;
     __shared__ double scratch[SNT / 64];
     const double pbp = st->acc[0];
@@ -983,9 +992,14 @@ cg_step_kernel(const double *__restrict__ t, int64_t r, double *__restrict__ z,
 }
 
 __global__ void __launch_bounds__(SNT)
-cg_init_kernel(const double *__restrict__ c, int64_t r, double *__restrict__ z,
-               double *__restrict__ res, double *__restrict__ p, double rtol, int maxiter,
-               State *st) {
+cg_step_kernel(const double *__restrict__ t, int64_t r, double *__restrict__ z,
+               double *__restrict__ res, double *__restrict__ p, State *st) {
+    cg_step_body(t, r, z, res, p, st);
+}
+
+__device__ __forceinline__ void cg_init_body(const double *__restrict__ c, int64_t r, double *__restrict__ z,
+                                             double *__restrict__ res, double *__restrict__ p, double rtol,
+                                             int maxiter, State *st) {
     __shared__ double scratch[SNT / 64];
     double part = 0.0;
     for (int64_t i = threadIdx.x; i < r; i += SNT) {
@@ -1004,6 +1018,13 @@ cg_init_kernel(const double *__restrict__ c, int64_t r, double *__restrict__ z,
         s0.converged = s0.done;
         *st = s0;
     }
+}
+
+__global__ void __launch_bounds__(SNT)
+cg_init_kernel(const double *__restrict__ c, int64_t r, double *__restrict__ z,
+               double *__restrict__ res, double *__restrict__ p, double rtol, int maxiter,
+               State *st) {
+    cg_init_body(c, r, z, res, p, rtol, maxiter, st);
 }
 
 // ------------------------------------------------------------ sparse passes
@@ -2270,6 +2291,11 @@ struct BatchItem {
     double *v, *wdir, *yv, *t, *z, *x;
     double tol;
     int lpr;  // lanes per row of the narrow sweep (0: the wide sweep)
+    // refinement: the right-hand side, h = A^T (b - A x) (double-double
+    // partials per row block, then rounded), c = N^T h, and the CG vectors
+    const double *bvec;
+    double *hhi, *hlo, *h, *c, *zc, *rc, *pc;
+    double rtol;
 };
 
 __device__ __forceinline__ int find_item(const int *__restrict__ off, int n, int g) {
@@ -2321,20 +2347,28 @@ batch_reduce_kernel(const BatchItem *__restrict__ it, const int *__restrict__ of
     }
 }
 
-// which 0: wN = P v; 1: t = P^T z; 2: x = P y (ignores the done flag).
+// which 0: wN = P v; 1: t = P^T z; 2: x = P y; refinement: 3: c = P^T h;
+// 4: wN = P p (the CG direction); 5: x += P z (the CG solution).  2, 3 and
+// 5 run after the loops, whatever the done flags say.
 __global__ void __launch_bounds__(256)
 batch_gemv_kernel(const BatchItem *__restrict__ it, const int *__restrict__ off, int n, int which) {
     const int p = find_item(off, n, (int)blockIdx.x);
     const BatchItem &b = it[p];
-    if (which != 2 && b.sw.st->done) return;
+    if ((which == 0 || which == 1 || which == 4) && b.sw.st->done) return;
     const int64_t row = (int64_t)((int)blockIdx.x - off[p]) * 4 + (threadIdx.x >> 6);
     const double *M;
     int64_t ld, nrows, ncols;
     const double *x;
     double *y;
-    if (which == 1) { M = b.Pt; ld = b.L; nrows = b.r; ncols = b.L; x = b.z; y = b.t; }
-    else { M = b.P; ld = b.ldp; nrows = b.L; ncols = b.r; x = which == 0 ? b.v : b.yv;
-           y = which == 0 ? const_cast<double *>(b.sw.w) : b.x; }
+    if (which == 1 || which == 3) {
+        M = b.Pt; ld = b.L; nrows = b.r; ncols = b.L;
+        x = which == 1 ? b.z : b.h;
+        y = which == 1 ? b.t : b.c;
+    } else {
+        M = b.P; ld = b.ldp; nrows = b.L; ncols = b.r;
+        x = which == 0 ? b.v : which == 2 ? b.yv : which == 4 ? b.pc : b.zc;
+        y = (which == 0 || which == 4) ? const_cast<double *>(b.sw.w) : b.x;
+    }
     if (row >= nrows) return;
     const int lane = threadIdx.x & 63;
     // the row and x through buffer resources of ncols entries: eight loads
@@ -2358,7 +2392,43 @@ batch_gemv_kernel(const BatchItem *__restrict__ it, const int *__restrict__ off,
         for (int k = 0; k < 8; ++k) t += a[k] * b[k];
     }
     t = wave_sum(t);
-    if (lane == 0) y[row] = t;
+    if (lane == 0) {
+        if (which == 5) y[row] += t;
+        else y[row] = t;
+    }
+}
+
+// h partials of the refinement: per row block of each problem, in double-
+// double (the single-problem kernel's body, the row blocks of the sweeps).
+__global__ void __launch_bounds__(NT)
+batch_resid_kernel(const BatchItem *__restrict__ it, const int *__restrict__ off, int n) {
+    const int p = find_item(off, n, (int)blockIdx.x);
+    const BatchItem &b = it[p];
+    resid_dd_tall_body<BCPT, double>(b.sw.T, b.sw.ldt, b.sw.rows, b.sw.L, b.sw.nblocks, b.sw.rows_per_block,
+                                     b.bvec, b.x, 0.0, b.hhi, b.hlo, (int)blockIdx.x - off[p]);
+}
+
+// h = the double-double sum of the row-block partials, rounded.
+__global__ void __launch_bounds__(256)
+batch_reduce_dd_kernel(const BatchItem *__restrict__ it, const int *__restrict__ off, int n) {
+    const int p = find_item(off, n, (int)blockIdx.x);
+    const BatchItem &b = it[p];
+    const int col = ((int)blockIdx.x - off[p]) * 256 + threadIdx.x;
+    if (col >= b.L) return;
+    dd t = {0.0, 0.0};
+    for (int k = 0; k < b.sw.nblocks; ++k)
+        t = dd_add(t, dd{b.hhi[(int64_t)k * b.L + col], b.hlo[(int64_t)k * b.L + col]});
+    b.h[col] = t.hi;
+}
+
+__global__ void __launch_bounds__(SNT) batch_cg_init_kernel(const BatchItem *__restrict__ it, int maxiter) {
+    const BatchItem &b = it[blockIdx.x];
+    cg_init_body(b.c, b.r, b.zc, b.rc, b.pc, b.rtol, maxiter, b.sw.st);
+}
+
+__global__ void __launch_bounds__(SNT) batch_cg_step_kernel(const BatchItem *__restrict__ it) {
+    const BatchItem &b = it[blockIdx.x];
+    cg_step_body(b.t, b.r, b.zc, b.rc, b.pc, b.sw.st);
 }
 
 __global__ void __launch_bounds__(SNT) batch_init_kernel(const BatchItem *__restrict__ it) {
@@ -2399,6 +2469,7 @@ std::vector<IterResult> iterate_batch_tall(const std::vector<IterProblem> &pbs,
         const size_t nb = (size_t)std::max<int64_t>(1, ceil_div(pb.rows, B_ROWS_PER_BLOCK));
         pool_elems += carve(nb * L) + carve(nb * 4) + carve((size_t)pb.rows) + carve(L) + carve(r * L) +
                       4 * carve(r) + carve(L);
+        if (opt.refine > 0) pool_elems += 2 * carve(nb * L) + carve(L) + 4 * carve(r);
     }
     DevBuf pool(pool_elems * sizeof(double));
     size_t pool_used = 0;
@@ -2430,6 +2501,13 @@ std::vector<IterResult> iterate_batch_tall(const std::vector<IterProblem> &pbs,
         b.v = buf((size_t)r); b.wdir = buf((size_t)r); b.yv = buf((size_t)r); b.t = buf((size_t)r);
         b.z = buf((size_t)L); b.x = xs[(size_t)p];
         b.tol = opt.tol;
+        b.bvec = bs[(size_t)p];
+        b.rtol = opt.refine_tol;
+        if (opt.refine > 0) {
+            b.hhi = buf((size_t)nblocks * L); b.hlo = buf((size_t)nblocks * L);
+            b.h = buf((size_t)L);
+            b.c = buf((size_t)r); b.zc = buf((size_t)r); b.rc = buf((size_t)r); b.pc = buf((size_t)r);
+        }
         b.lpr = 0;
         if ((pb.rows + 512) * pb.ldt < ((int64_t)1 << 28))  // offsets stay in 31 bits
             for (int l = 2; l <= 64 && !b.lpr; l *= 2)
@@ -2479,7 +2557,7 @@ std::vector<IterResult> iterate_batch_tall(const std::vector<IterProblem> &pbs,
             if (!h.done) return false;
         return true;
     };
-    hipGraphExec_t exec = nullptr;
+    hipGraphExec_t exec = nullptr, exec_cg = nullptr;
     auto chunk = [&] {
         for (int k = 0; k < CHUNK; ++k) {
             batch_gemv_kernel<<<off_gP[(size_t)n], 256, 0, st>>>(di, o_gP, n, 0);
@@ -2490,37 +2568,74 @@ std::vector<IterResult> iterate_batch_tall(const std::vector<IterProblem> &pbs,
         }
         LSRN_HIP(hipGetLastError());
     };
-    try {
+    // CG on (A N)^T (A N) z = c for every problem (the refinement's inner solve)
+    auto chunk_cg = [&] {
+        for (int k = 0; k < CHUNK; ++k) {
+            batch_gemv_kernel<<<off_gP[(size_t)n], 256, 0, st>>>(di, o_gP, n, 4);
+            batch_sweep_kernel<OP_NORMAL><<<off_sw[(size_t)n], NT, 0, st>>>(di, o_sw, n);
+            batch_reduce_kernel<<<off_red[(size_t)n], 256, 0, st>>>(di, o_red, n);
+            batch_gemv_kernel<<<off_gPt[(size_t)n], 256, 0, st>>>(di, o_gPt, n, 1);
+            batch_cg_step_kernel<<<n, SNT, 0, st>>>(di);
+        }
+        LSRN_HIP(hipGetLastError());
+    };
+    // chunks until every problem's done flag is set, each chunk replayed
+    // from a captured graph where graphs are allowed
+    auto run_until_done = [&](hipGraphExec_t &ex, auto &&body) {
         while (!all_done()) {
             if (st && graphs_allowed()) {
-                if (!exec) {
+                if (!ex) {
                     hipGraph_t g = nullptr;
                     LSRN_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
                     try {
-                        chunk();
+                        body();
                     } catch (...) {
                         (void)hipStreamEndCapture(st, &g);
                         if (g) (void)hipGraphDestroy(g);
                         throw;
                     }
                     LSRN_HIP(hipStreamEndCapture(st, &g));
-                    const hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+                    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
                     (void)hipGraphDestroy(g);
                     LSRN_HIP(e);
                 }
-                LSRN_HIP(hipGraphLaunch(exec, st));
+                LSRN_HIP(hipGraphLaunch(ex, st));
             } else {
-                chunk();
+                body();
             }
+        }
+    };
+    std::vector<int64_t> iters_main((size_t)n), refine_iters((size_t)n, 0);
+    std::vector<bool> conv_main((size_t)n);
+    try {
+        run_until_done(exec, chunk);
+        for (int p = 0; p < n; ++p) {
+            iters_main[(size_t)p] = hs[(size_t)p].iters;
+            conv_main[(size_t)p] = hs[(size_t)p].converged != 0;
+        }
+        batch_gemv_kernel<<<off_gP[(size_t)n], 256, 0, st>>>(di, o_gP, n, 2);
+        LSRN_HIP(hipGetLastError());
+        // refinement steps (as for one problem): h = A^T (b - A x) in
+        // double-double, CG on (A N)^T (A N) z = N^T h to refine_tol, x += N z
+        for (int step = 0; step < opt.refine; ++step) {
+            batch_resid_kernel<<<off_sw[(size_t)n], NT, 0, st>>>(di, o_sw, n);
+            batch_reduce_dd_kernel<<<off_red[(size_t)n], 256, 0, st>>>(di, o_red, n);
+            batch_gemv_kernel<<<off_gPt[(size_t)n], 256, 0, st>>>(di, o_gPt, n, 3);
+            batch_cg_init_kernel<<<n, SNT, 0, st>>>(di, 200);
+            LSRN_HIP(hipGetLastError());
+            run_until_done(exec_cg, chunk_cg);
+            for (int p = 0; p < n; ++p) refine_iters[(size_t)p] += hs[(size_t)p].iters;
+            batch_gemv_kernel<<<off_gP[(size_t)n], 256, 0, st>>>(di, o_gP, n, 5);
+            LSRN_HIP(hipGetLastError());
         }
     } catch (...) {
         if (exec) (void)hipGraphExecDestroy(exec);
+        if (exec_cg) (void)hipGraphExecDestroy(exec_cg);
         (void)hipStreamSynchronize(st);
         throw;
     }
     if (exec) (void)hipGraphExecDestroy(exec);
-    batch_gemv_kernel<<<off_gP[(size_t)n], 256, 0, st>>>(di, o_gP, n, 2);
-    LSRN_HIP(hipGetLastError());
+    if (exec_cg) (void)hipGraphExecDestroy(exec_cg);
     LSRN_HIP(hipEventRecord(e1, st));
     LSRN_HIP(hipEventSynchronize(e1));
     float ms = 0.f;
@@ -2528,8 +2643,10 @@ std::vector<IterResult> iterate_batch_tall(const std::vector<IterProblem> &pbs,
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     for (int p = 0; p < n; ++p) {
-        res[(size_t)p].iters = hs[(size_t)p].iters;
-        res[(size_t)p].converged = hs[(size_t)p].converged != 0;
+        res[(size_t)p].iters = iters_main[(size_t)p];
+        res[(size_t)p].converged = conv_main[(size_t)p];
+        res[(size_t)p].refine_steps = opt.refine;
+        res[(size_t)p].refine_iters = refine_iters[(size_t)p];
         res[(size_t)p].t_iter_ms = ms;
     }
     LSRN_HIP(hipStreamSynchronize(st));  // before the buffers are freed

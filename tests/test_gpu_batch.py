@@ -59,6 +59,32 @@ def test_batch_matches_single_solves_and_oracle(L, orc):
     assert infos[-1]["rank"] == 0 and np.all(host(xs[-1]) == 0.0)
 
 
+def test_batch_refined_matches_oracle_1e10(L, orc):
+    """With refinement steps (double-double residuals, CG corrections for
+    all problems in shared launches) every batched solution is within 1e-10
+    of the oracle's reference-mode solution, across the narrow and wide
+    sweep classes and condition numbers up to 1e6; each problem's result
+    equals the same problem batched alone (its arithmetic does not depend
+    on the other problems)."""
+    rng = np.random.default_rng(15)
+    As, bs, refs = [], [], []
+    for i, n in enumerate([5, 16, 40, 64, 130, 256, 300, 512]):
+        m = int(rng.integers(3 * n + 300, 8000))
+        P = workloads.dense_problem(m, n, smin=10.0 ** -(2 + i % 5), seed=900 + i)
+        b = workloads.rhs_gauss(m, 900 + i)
+        As.append(dev(P.A)); bs.append(dev(b))
+        refs.append(orc.lsrn_solve(orc.Matrix.dense(P.A), b, seed=1, refine=3).x)
+    xs, infos = L.solve_batch(As, bs, seed=13, refine=2)
+    for k, xr in enumerate(refs):
+        assert infos[k]["refine_steps"] == 2 and infos[k]["refine_iters"] > 0
+        e = rel(host(xs[k]), xr)
+        assert e <= 1e-10, (k, e)
+    for k in (0, 4, 7):
+        x1, i1 = L.solve_batch([As[k]], [bs[k]], seed=13, refine=2)
+        np.testing.assert_array_equal(host(x1[0]), host(xs[k]))
+        assert i1[0]["iters"] == infos[k]["iters"] and i1[0]["refine_iters"] == infos[k]["refine_iters"]
+
+
 def test_batch_padded_rows_equal_contiguous(L):
     """Problems given with an odd leading dimension (element loads in the
     batched sketch and sweeps) give bit for bit the batch result of the
@@ -84,7 +110,7 @@ def test_batch_padded_rows_equal_contiguous(L):
 def test_batch_rejections(L):
     P = workloads.dense_problem(500, 20, smin=1e-3, seed=6)
     A, b = dev(P.A), dev(workloads.rhs_gauss(500, 6))
-    for bad in (dict(refine=1), dict(method="chebyshev"), dict(lam=0.1), dict(precision="mixed")):
+    for bad in (dict(method="chebyshev"), dict(lam=0.1), dict(precision="mixed")):
         with pytest.raises(L.LSRNError) as e:
             L.solve_batch([A], [b], **bad)
         assert e.value.status == 5
