@@ -181,6 +181,7 @@ def serve_main(args):
             with lock:
                 results[meta["i"]] = dict(meta, latency_ms=tm["latency_ms"], queue_ms=tm["queue_ms"],
                                           run_ms=tm["run_ms"], status=info["status"],
+                                          batch_size=tm["batch_size"],
                                           iters=info["iters"], check=check,
                                           fp64_steps=info.get("fp64_refine_steps", 0))
 
@@ -245,6 +246,15 @@ def serve_main(args):
             # under-determined requests the residual of A x = b can be
             # kappa(A) times tol
             worst[key] = {"check": r["check"], "cond": r["cond"], "tol": r["tol"]}
+    routes = {}
+    for name, sel in (("batched", lambda r: r["batch_size"] > 0), ("single", lambda r: r["batch_size"] == 0)):
+        rs = [r for r in results.values() if sel(r)]
+        if rs:
+            routes[name] = {"count": len(rs),
+                            "mean_batch_size": round(float(np.mean([r["batch_size"] for r in rs])), 2),
+                            "p50_latency_ms": round(percentile([r["latency_ms"] for r in rs], 50), 3),
+                            "mean_run_ms": round(float(np.mean([r["run_ms"] for r in rs])), 3),
+                            "mean_queue_ms": round(float(np.mean([r["queue_ms"] for r in rs])), 3)}
     line = {
         "metric": "serving: LS solves/s with p50/p99 latency (Poisson arrivals, uneven shapes)",
         "value": round(len(results) / (t1 - t0), 2),
@@ -261,6 +271,7 @@ def serve_main(args):
                    "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))},
         "latency_ms": {"p50": round(percentile(lat, 50), 3), "p99": round(percentile(lat, 99), 3),
                        "mean_queue": round(float(np.mean([r["queue_ms"] for r in results.values()])), 3)},
+        "routes": routes,
         "wall_s": round(t1 - t0, 3),
         "pool_build_s": round(t_gen, 3),
         "pool_size": args.serve_pool,

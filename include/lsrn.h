@@ -371,6 +371,19 @@ lsrn_status lsrn_solve_batch(int32_t count, const int64_t *m, const int64_t *n,
                              double *const *x, const lsrn_options *opt, lsrn_info *infos,
                              void *stream);
 
+/* lsrn_solve_batch with one option set per problem (opts: count entries):
+ * each problem has its own seed, gamma, tol, max_iter, refine and
+ * refine_tol; every problem must meet the batch's limits above, and all
+ * must share rcond (their preconditioners are formed together).  A
+ * problem's result does not depend on the other problems of the batch: it
+ * equals the same problem batched alone.  The serving runtime solves its
+ * qualifying requests together through this call (an addition, not a step
+ * of the paper). */
+lsrn_status lsrn_solve_batch_opts(int32_t count, const int64_t *m, const int64_t *n,
+                                  const double *const *A, const int64_t *lda, const double *const *b,
+                                  double *const *x, const lsrn_options *opts, lsrn_info *infos,
+                                  void *stream);
+
 /* ------------------------------------------------------------------------
  * Launch-shape tuning table (not a paper passage).  Keys are (phase, dtype,
  * rows bucket, cols): phase "sweep" is the fused pass over dense A, dtype
@@ -513,6 +526,8 @@ typedef struct lsrn_server_timing {
     double run_ms;            /* admitted -> finished                        */
     double latency_ms;        /* submit -> finished                          */
     int64_t footprint_bytes;  /* memory the admission reserved               */
+    int64_t batch_size;       /* requests solved in the same batched call,
+                                 0 for a request solved on its own          */
 } lsrn_server_timing;
 
 /* Start the worker threads on the current device.  0 < streams <= 64. */

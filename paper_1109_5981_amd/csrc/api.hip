@@ -852,20 +852,22 @@ lsrn_status lsrn_iterate_csr(int64_t m, int64_t n, int64_t nnz, const int64_t *r
     LSRN_API_END
 }
 
-lsrn_status lsrn_solve_batch(int32_t count, const int64_t *m, const int64_t *n,
-                             const double *const *A, const int64_t *lda, const double *const *b,
-                             double *const *x, const lsrn_options *opt_in, lsrn_info *infos,
-                             void *stream) {
-    LSRN_API_BEGIN
-    const lsrn_options opt = opt_in ? *opt_in : defaults();
-    check_options(opt);
-    LSRN_REQUIRE(count >= 0, "count must be >= 0");
-    LSRN_REQUIRE(count == 0 || (m && n && A && lda && b && x), "NULL pointer");
-    if (opt.method != LSRN_LSQR || opt.lambda != 0.0 || opt.precision != LSRN_PREC_FP64 ||
-        opt.precond == LSRN_PRECOND_QR)
-        fail(LSRN_E_UNSUPPORTED, "the batched path runs FP64 LSQR with the SVD preconditioner, "
-                                 "without lambda");
-    hipStream_t st = (hipStream_t)stream;
+// The batched solve with one option set per problem (ov[p]); lsrn_solve_batch
+// passes the same set for all.  Throws; the entry points report.
+static lsrn_status solve_batch_body(int32_t count, const int64_t *m, const int64_t *n,
+                                    const double *const *A, const int64_t *lda, const double *const *b,
+                                    double *const *x, const std::vector<lsrn_options> &ov,
+                                    lsrn_info *infos, hipStream_t st) {
+    for (int32_t p = 0; p < count; ++p) {
+        const lsrn_options &opt = ov[(size_t)p];
+        check_options(opt);
+        if (opt.method != LSRN_LSQR || opt.lambda != 0.0 || opt.precision != LSRN_PREC_FP64 ||
+            opt.precond == LSRN_PRECOND_QR)
+            fail(LSRN_E_UNSUPPORTED, "the batched path runs FP64 LSQR with the SVD preconditioner, "
+                                     "without lambda");
+        // the preconditioners of the batch are formed together with one cutoff
+        LSRN_REQUIRE(opt.rcond == ov[0].rcond, "batched problems need the same rcond");
+    }
     for (int32_t p = 0; p < count; ++p) {
         LSRN_REQUIRE(m[p] >= n[p] && n[p] > 0 && n[p] <= 512, "batched problems need m >= n, 0 < n <= 512");
         LSRN_REQUIRE(A[p] && b[p] && x[p] && lda[p] >= n[p], "bad batched problem");
@@ -884,7 +886,7 @@ lsrn_status lsrn_solve_batch(int32_t count, const int64_t *m, const int64_t *n,
     size_t nx = 0, np = 0, ns = 0;
     for (int32_t p = 0; p < count; ++p) {
         const int64_t d = n[p];
-        ss[(size_t)p] = (int64_t)std::ceil(opt.gamma * (double)d);
+        ss[(size_t)p] = (int64_t)std::ceil(ov[(size_t)p].gamma * (double)d);
         nx += carve((size_t)ss[(size_t)p] * (size_t)d);
         np += carve((size_t)d * (size_t)d);
         ns += carve((size_t)d);
@@ -901,9 +903,12 @@ lsrn_status lsrn_solve_batch(int32_t count, const int64_t *m, const int64_t *n,
         op += carve(d * d);
         os += carve(d);
     }
+    std::vector<uint64_t> seeds((size_t)count);
+    for (int32_t p = 0; p < count; ++p) seeds[(size_t)p] = ov[(size_t)p].seed;
     if (count > 0)
-        sketch_rows_batch(count, m, n, A, lda, ss.data(), opt.seed, Xp.data(), st);
-    precond_batch(count, ss.data(), n, Xp.data(), opt.rcond, sp.data(), Pp.data(), prs.data(), st);
+        sketch_rows_batch(count, m, n, A, lda, ss.data(), seeds.data(), Xp.data(), st);
+    precond_batch(count, ss.data(), n, Xp.data(), count > 0 ? ov[0].rcond : 0.0, sp.data(), Pp.data(),
+                  prs.data(), st);
     Xpool.release();
     Spool.release();
     for (int32_t p = 0; p < count; ++p) {
@@ -920,8 +925,10 @@ lsrn_status lsrn_solve_batch(int32_t count, const int64_t *m, const int64_t *n,
     std::vector<const double *> lb;
     std::vector<double *> lx;
     std::vector<int32_t> idx;
+    std::vector<lsrn_options> lo;
     for (int32_t p = 0; p < count; ++p) {
         if (pbs[(size_t)p].r > 0) {
+            lo.push_back(ov[(size_t)p]);
             live.push_back(pbs[(size_t)p]);
             lb.push_back(bs[(size_t)p]);
             lx.push_back(xs[(size_t)p]);
@@ -930,7 +937,7 @@ lsrn_status lsrn_solve_batch(int32_t count, const int64_t *m, const int64_t *n,
             LSRN_HIP(hipMemsetAsync(x[p], 0, (size_t)n[p] * sizeof(double), st));
         }
     }
-    std::vector<IterResult> irs = iterate_batch_tall(live, lb, lx, opt, st);
+    std::vector<IterResult> irs = iterate_batch_tall(live, lb, lx, lo, st);
     tm.mark();
     bool all_conv = true;
     std::vector<IterResult> full((size_t)count);
@@ -955,6 +962,30 @@ lsrn_status lsrn_solve_batch(int32_t count, const int64_t *m, const int64_t *n,
         g_last_error = "LSQR reached max_iter for at least one problem";
         return LSRN_E_NOT_CONVERGED;
     }
+    return LSRN_OK;
+}
+
+lsrn_status lsrn_solve_batch(int32_t count, const int64_t *m, const int64_t *n,
+                             const double *const *A, const int64_t *lda, const double *const *b,
+                             double *const *x, const lsrn_options *opt_in, lsrn_info *infos,
+                             void *stream) {
+    LSRN_API_BEGIN
+    LSRN_REQUIRE(count >= 0, "count must be >= 0");
+    LSRN_REQUIRE(count == 0 || (m && n && A && lda && b && x), "NULL pointer");
+    const std::vector<lsrn_options> ov((size_t)count, opt_in ? *opt_in : defaults());
+    return solve_batch_body(count, m, n, A, lda, b, x, ov, infos, (hipStream_t)stream);
+    LSRN_API_END
+}
+
+lsrn_status lsrn_solve_batch_opts(int32_t count, const int64_t *m, const int64_t *n,
+                                  const double *const *A, const int64_t *lda, const double *const *b,
+                                  double *const *x, const lsrn_options *opts, lsrn_info *infos,
+                                  void *stream) {
+    LSRN_API_BEGIN
+    LSRN_REQUIRE(count >= 0, "count must be >= 0");
+    LSRN_REQUIRE(count == 0 || (m && n && A && lda && b && x && opts), "NULL pointer");
+    const std::vector<lsrn_options> ov(opts, opts + count);
+    return solve_batch_body(count, m, n, A, lda, b, x, ov, infos, (hipStream_t)stream);
     LSRN_API_END
 }
 

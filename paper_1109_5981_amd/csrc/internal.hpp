@@ -35,10 +35,11 @@ size_t sketch_slices_bytes(int64_t K, int64_t d, int64_t s);
 // synchronise; LSRN_E_NOMEM when the partial sums would not fit.
 void sketch_rows_noalloc(int64_t K, int64_t d, const double *T, int64_t ldt, double lambda,
                          int64_t s, uint64_t seed, double *X, hipStream_t st);
-// The sketches of `count` tall problems (T[p] row-major K[p] x d[p]) in one
-// launch per alignment class, no split of K.  Synchronises.
+// The sketches of `count` tall problems (T[p] row-major K[p] x d[p], G[p]
+// from key seeds[p]) in one launch per alignment class, no split of K.
+// Synchronises.
 void sketch_rows_batch(int count, const int64_t *K, const int64_t *d, const double *const *T,
-                       const int64_t *ldt, const int64_t *s, uint64_t seed, double *const *X,
+                       const int64_t *ldt, const int64_t *s, const uint64_t *seeds, double *const *X,
                        hipStream_t st);
 
 // The precision form's sketch: X = bf16(G) fl32(T) on the BF16 matrix
@@ -222,11 +223,13 @@ struct IterResult {
 IterResult iterate(const IterProblem &pb, const double *b, double *x, const lsrn_options &opt,
                    hipStream_t st);
 
-// LSQR for many tall dense FP64 problems (cols <= 512, no lambda) at once:
-// each kernel launch covers the whole batch.  No refinement.  Synchronises.
+// LSQR for many tall dense FP64 problems (cols <= 512, no lambda) at once,
+// then opts[p].refine refinement steps of each: each kernel launch covers
+// the whole batch.  opts[p] gives problem p's tol, max_iter, refine and
+// refine_tol.  Synchronises.
 std::vector<IterResult> iterate_batch_tall(const std::vector<IterProblem> &pbs,
                                            const std::vector<const double *> &bs,
-                                           const std::vector<double *> &xs, const lsrn_options &opt,
-                                           hipStream_t st);
+                                           const std::vector<double *> &xs,
+                                           const std::vector<lsrn_options> &opts, hipStream_t st);
 
 }  // namespace lsrn

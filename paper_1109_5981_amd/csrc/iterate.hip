@@ -2280,7 +2280,15 @@ void OpView::apply_t(int t, int64_t k, const double *in, int64_t ldin, double *o
 namespace {
 
 constexpr int BCPT = 2, BR = 8;          // the sweep variant for L <= 512
-constexpr int64_t B_ROWS_PER_BLOCK = 512;
+constexpr int B_RED_COLS = 64;           // columns of z per reduction workgroup
+
+// Rows per workgroup of a problem's batched sweeps, from its own row count
+// alone (so its bits do not depend on the rest of the batch): about 512
+// workgroups for a tall problem, 128 to 512 rows each (fewer rows left the
+// per-workgroup set-up dominant on problems of a few thousand rows).
+int64_t batch_rows_per_block(int64_t rows) {
+    return std::min<int64_t>(512, std::max<int64_t>(128, round_up(ceil_div(rows, 512), 64)));
+}
 
 struct BatchItem {
     SweepArgs sw;  // T, ldt, rows, L, nblocks, rows_per_block, w = wN, zpart, spart, y = u, st
@@ -2296,6 +2304,7 @@ struct BatchItem {
     const double *bvec;
     double *hhi, *hlo, *h, *c, *zc, *rc, *pc;
     double rtol;
+    int refine;  // this problem's refinement steps (its buffers exist only if > 0)
 };
 
 __device__ __forceinline__ int find_item(const int *__restrict__ off, int n, int g) {
@@ -2326,24 +2335,38 @@ batch_sweep_kernel(const BatchItem *__restrict__ it, const int *__restrict__ off
     }
 }
 
-// z_p = sum of the row-block partials, st_p->acc = sum of the scalar partials.
+// z_p = sum of the row-block partials, st_p->acc = sum of the scalar
+// partials.  A workgroup takes 64 columns: four groups of 64 threads sum
+// the partials k = g mod 4, then the four sums are added in order g = 0..3;
+// the first workgroup of a problem also sums the scalar partials (64
+// threads a scalar, k = q mod 64, added in order q = 0..63).
 __global__ void __launch_bounds__(256)
 batch_reduce_kernel(const BatchItem *__restrict__ it, const int *__restrict__ off, int n) {
+    __shared__ double red[4][B_RED_COLS];
+    __shared__ double sred[64][4];
     const int p = find_item(off, n, (int)blockIdx.x);
     const BatchItem &b = it[p];
     if (b.sw.st->done) return;
     const int chunk = (int)blockIdx.x - off[p];
-    const int col = chunk * 256 + threadIdx.x;
+    const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int col = chunk * B_RED_COLS + c;
     const int nb = b.sw.nblocks;
-    if (col < b.L) {
-        double t = 0.0;
-        for (int k = 0; k < nb; ++k) t += b.sw.zpart[(int64_t)k * b.L + col];
-        b.z[col] = t;
+    double t = 0.0;
+    if (col < b.L)
+        for (int k = g; k < nb; k += 4) t += b.sw.zpart[(int64_t)k * b.L + col];
+    red[g][c] = t;
+    if (chunk == 0) {
+        const int a = threadIdx.x & 3, q = threadIdx.x >> 2;
+        double u = 0.0;
+        for (int k = q; k < nb; k += 64) u += b.sw.spart[k * 4 + a];
+        sred[q][a] = u;
     }
+    __syncthreads();
+    if (g == 0 && col < b.L) b.z[col] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
     if (chunk == 0 && threadIdx.x < 4) {
-        double t = 0.0;
-        for (int k = 0; k < nb; ++k) t += b.sw.spart[k * 4 + threadIdx.x];
-        b.sw.st->acc[threadIdx.x] = t;
+        double u = 0.0;
+        for (int q = 0; q < 64; ++q) u += sred[q][threadIdx.x];
+        b.sw.st->acc[threadIdx.x] = u;
     }
 }
 
@@ -2351,10 +2374,12 @@ batch_reduce_kernel(const BatchItem *__restrict__ it, const int *__restrict__ of
 // 4: wN = P p (the CG direction); 5: x += P z (the CG solution).  2, 3 and
 // 5 run after the loops, whatever the done flags say.
 __global__ void __launch_bounds__(256)
-batch_gemv_kernel(const BatchItem *__restrict__ it, const int *__restrict__ off, int n, int which) {
+batch_gemv_kernel(const BatchItem *__restrict__ it, const int *__restrict__ off, int n, int which,
+                  int step = 0) {
     const int p = find_item(off, n, (int)blockIdx.x);
     const BatchItem &b = it[p];
     if ((which == 0 || which == 1 || which == 4) && b.sw.st->done) return;
+    if ((which == 3 || which == 5) && step >= b.refine) return;  // no refinement step `step` here
     const int64_t row = (int64_t)((int)blockIdx.x - off[p]) * 4 + (threadIdx.x >> 6);
     const double *M;
     int64_t ld, nrows, ncols;
@@ -2401,28 +2426,49 @@ batch_gemv_kernel(const BatchItem *__restrict__ it, const int *__restrict__ off,
 // h partials of the refinement: per row block of each problem, in double-
 // double (the single-problem kernel's body, the row blocks of the sweeps).
 __global__ void __launch_bounds__(NT)
-batch_resid_kernel(const BatchItem *__restrict__ it, const int *__restrict__ off, int n) {
+batch_resid_kernel(const BatchItem *__restrict__ it, const int *__restrict__ off, int n, int step) {
     const int p = find_item(off, n, (int)blockIdx.x);
     const BatchItem &b = it[p];
+    if (step >= b.refine) return;
     resid_dd_tall_body<BCPT, double>(b.sw.T, b.sw.ldt, b.sw.rows, b.sw.L, b.sw.nblocks, b.sw.rows_per_block,
                                      b.bvec, b.x, 0.0, b.hhi, b.hlo, (int)blockIdx.x - off[p]);
 }
 
 // h = the double-double sum of the row-block partials, rounded.
 __global__ void __launch_bounds__(256)
-batch_reduce_dd_kernel(const BatchItem *__restrict__ it, const int *__restrict__ off, int n) {
+batch_reduce_dd_kernel(const BatchItem *__restrict__ it, const int *__restrict__ off, int n, int step) {
     const int p = find_item(off, n, (int)blockIdx.x);
+    __shared__ double rhi[4][B_RED_COLS], rlo[4][B_RED_COLS];
     const BatchItem &b = it[p];
-    const int col = ((int)blockIdx.x - off[p]) * 256 + threadIdx.x;
-    if (col >= b.L) return;
+    if (step >= b.refine) return;
+    const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int col = ((int)blockIdx.x - off[p]) * B_RED_COLS + c;
     dd t = {0.0, 0.0};
-    for (int k = 0; k < b.sw.nblocks; ++k)
-        t = dd_add(t, dd{b.hhi[(int64_t)k * b.L + col], b.hlo[(int64_t)k * b.L + col]});
-    b.h[col] = t.hi;
+    if (col < b.L)
+        for (int k = g; k < b.sw.nblocks; k += 4)
+            t = dd_add(t, dd{b.hhi[(int64_t)k * b.L + col], b.hlo[(int64_t)k * b.L + col]});
+    rhi[g][c] = t.hi;
+    rlo[g][c] = t.lo;
+    __syncthreads();
+    if (g == 0 && col < b.L) {
+        dd u = {rhi[0][c], rlo[0][c]};
+        for (int q = 1; q < 4; ++q) u = dd_add(u, dd{rhi[q][c], rlo[q][c]});
+        b.h[col] = u.hi;
+    }
 }
 
-__global__ void __launch_bounds__(SNT) batch_cg_init_kernel(const BatchItem *__restrict__ it, int maxiter) {
+__global__ void __launch_bounds__(SNT) batch_cg_init_kernel(const BatchItem *__restrict__ it, int maxiter,
+                                                             int step) {
     const BatchItem &b = it[blockIdx.x];
+    if (step >= b.refine) {  // done: the CG launches of this step skip the problem
+        if (threadIdx.x == 0) {
+            State s0 = {};
+            s0.done = 1;
+            s0.converged = 1;
+            *b.sw.st = s0;
+        }
+        return;
+    }
     cg_init_body(b.c, b.r, b.zc, b.rc, b.pc, b.rtol, maxiter, b.sw.st);
 }
 
@@ -2451,9 +2497,12 @@ __global__ void batch_set_state_kernel(const BatchItem *__restrict__ it, const i
 
 std::vector<IterResult> iterate_batch_tall(const std::vector<IterProblem> &pbs,
                                            const std::vector<const double *> &bs,
-                                           const std::vector<double *> &xs, const lsrn_options &opt,
-                                           hipStream_t st) {
+                                           const std::vector<double *> &xs,
+                                           const std::vector<lsrn_options> &opts, hipStream_t st) {
     const int n = (int)pbs.size();
+    LSRN_REQUIRE(opts.size() == pbs.size(), "batched iterations: one option set per problem");
+    int nref = 0;  // refinement steps of the batch (the most any problem takes)
+    for (const lsrn_options &o : opts) nref = std::max(nref, (int)o.refine);
     std::vector<IterResult> res((size_t)n);
     if (n == 0) return res;
     for (const IterProblem &pb : pbs)
@@ -2464,12 +2513,13 @@ std::vector<IterResult> iterate_batch_tall(const std::vector<IterProblem> &pbs,
     std::vector<int> off_sw(n + 1), off_red(n + 1), off_gP(n + 1), off_gPt(n + 1), maxit(n);
     auto carve = [](size_t elems) { return (std::max<size_t>(elems, 1) + 31) & ~(size_t)31; };
     size_t pool_elems = 0;
-    for (const IterProblem &pb : pbs) {
+    for (int p = 0; p < n; ++p) {
+        const IterProblem &pb = pbs[(size_t)p];
         const size_t L = (size_t)pb.cols, r = (size_t)pb.r;
-        const size_t nb = (size_t)std::max<int64_t>(1, ceil_div(pb.rows, B_ROWS_PER_BLOCK));
+        const size_t nb = (size_t)std::max<int64_t>(1, ceil_div(pb.rows, batch_rows_per_block(pb.rows)));
         pool_elems += carve(nb * L) + carve(nb * 4) + carve((size_t)pb.rows) + carve(L) + carve(r * L) +
                       4 * carve(r) + carve(L);
-        if (opt.refine > 0) pool_elems += 2 * carve(nb * L) + carve(L) + 4 * carve(r);
+        if (opts[(size_t)p].refine > 0) pool_elems += 2 * carve(nb * L) + carve(L) + 4 * carve(r);
     }
     DevBuf pool(pool_elems * sizeof(double));
     size_t pool_used = 0;
@@ -2481,12 +2531,14 @@ std::vector<IterResult> iterate_batch_tall(const std::vector<IterProblem> &pbs,
     DevBuf states((size_t)n * sizeof(State));
     for (int p = 0; p < n; ++p) {
         const IterProblem &pb = pbs[(size_t)p];
+        const lsrn_options &opt = opts[(size_t)p];
         BatchItem &b = items[(size_t)p];
         const int64_t L = pb.cols, r = pb.r;
-        const int nblocks = (int)std::max<int64_t>(1, ceil_div(pb.rows, B_ROWS_PER_BLOCK));
+        const int64_t rpb = batch_rows_per_block(pb.rows);
+        const int nblocks = (int)std::max<int64_t>(1, ceil_div(pb.rows, rpb));
         std::memset(&b, 0, sizeof(b));
         b.sw.T = pb.T; b.sw.T32 = nullptr; b.sw.ldt = pb.ldt; b.sw.rows = pb.rows; b.sw.L = (int)L;
-        b.sw.nblocks = nblocks; b.sw.rows_per_block = B_ROWS_PER_BLOCK;
+        b.sw.nblocks = nblocks; b.sw.rows_per_block = rpb;
         b.sw.zpart = buf((size_t)nblocks * L);
         b.sw.spart = buf((size_t)nblocks * 4);
         b.sw.y = buf((size_t)pb.rows);
@@ -2503,6 +2555,7 @@ std::vector<IterResult> iterate_batch_tall(const std::vector<IterProblem> &pbs,
         b.tol = opt.tol;
         b.bvec = bs[(size_t)p];
         b.rtol = opt.refine_tol;
+        b.refine = (int)opt.refine;
         if (opt.refine > 0) {
             b.hhi = buf((size_t)nblocks * L); b.hlo = buf((size_t)nblocks * L);
             b.h = buf((size_t)L);
@@ -2519,7 +2572,7 @@ std::vector<IterResult> iterate_batch_tall(const std::vector<IterProblem> &pbs,
         res[(size_t)p].sigma_l = sl;
         res[(size_t)p].sigma_u = su;
         off_sw[(size_t)p + 1] = off_sw[(size_t)p] + nblocks;
-        off_red[(size_t)p + 1] = off_red[(size_t)p] + (int)ceil_div(L, 256);
+        off_red[(size_t)p + 1] = off_red[(size_t)p] + (int)ceil_div(L, (int64_t)B_RED_COLS);
         off_gP[(size_t)p + 1] = off_gP[(size_t)p] + (int)ceil_div(L, 4);
         off_gPt[(size_t)p + 1] = off_gPt[(size_t)p] + (int)ceil_div(r, 4);
     }
@@ -2617,15 +2670,15 @@ std::vector<IterResult> iterate_batch_tall(const std::vector<IterProblem> &pbs,
         LSRN_HIP(hipGetLastError());
         // refinement steps (as for one problem): h = A^T (b - A x) in
         // double-double, CG on (A N)^T (A N) z = N^T h to refine_tol, x += N z
-        for (int step = 0; step < opt.refine; ++step) {
-            batch_resid_kernel<<<off_sw[(size_t)n], NT, 0, st>>>(di, o_sw, n);
-            batch_reduce_dd_kernel<<<off_red[(size_t)n], 256, 0, st>>>(di, o_red, n);
-            batch_gemv_kernel<<<off_gPt[(size_t)n], 256, 0, st>>>(di, o_gPt, n, 3);
-            batch_cg_init_kernel<<<n, SNT, 0, st>>>(di, 200);
+        for (int step = 0; step < nref; ++step) {
+            batch_resid_kernel<<<off_sw[(size_t)n], NT, 0, st>>>(di, o_sw, n, step);
+            batch_reduce_dd_kernel<<<off_red[(size_t)n], 256, 0, st>>>(di, o_red, n, step);
+            batch_gemv_kernel<<<off_gPt[(size_t)n], 256, 0, st>>>(di, o_gPt, n, 3, step);
+            batch_cg_init_kernel<<<n, SNT, 0, st>>>(di, 200, step);
             LSRN_HIP(hipGetLastError());
             run_until_done(exec_cg, chunk_cg);
             for (int p = 0; p < n; ++p) refine_iters[(size_t)p] += hs[(size_t)p].iters;
-            batch_gemv_kernel<<<off_gP[(size_t)n], 256, 0, st>>>(di, o_gP, n, 5);
+            batch_gemv_kernel<<<off_gP[(size_t)n], 256, 0, st>>>(di, o_gP, n, 5, step);
             LSRN_HIP(hipGetLastError());
         }
     } catch (...) {
@@ -2645,7 +2698,7 @@ std::vector<IterResult> iterate_batch_tall(const std::vector<IterProblem> &pbs,
     for (int p = 0; p < n; ++p) {
         res[(size_t)p].iters = iters_main[(size_t)p];
         res[(size_t)p].converged = conv_main[(size_t)p];
-        res[(size_t)p].refine_steps = opt.refine;
+        res[(size_t)p].refine_steps = opts[(size_t)p].refine;
         res[(size_t)p].refine_iters = refine_iters[(size_t)p];
         res[(size_t)p].t_iter_ms = ms;
     }

@@ -12,8 +12,17 @@
 // up.  Every solve runs the same kernels in the same order as a call of
 // lsrn_solve_dense / lsrn_solve_csr on its own, so its result does not
 // depend on what else is running.
+//
+// Requests the batched path covers (dense row-major over-determined FP64
+// LSQR with n <= 512, lambda = 0 and the default rank cutoff) queue apart:
+// one batcher thread, on a stream of its own, takes all of them that are
+// waiting when it is free (up to kMaxBatch, within the budget) and solves
+// them together with lsrn_solve_batch_opts, so that the iterations of
+// requests that arrived close together advance in shared launches.  A
+// batched request's result equals the same request batched alone.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -40,6 +49,8 @@ struct lsrn_server {
         const double *b = nullptr;
         double *x = nullptr;
         lsrn_options opt{};
+        bool batch = false;  // solved by the batcher
+        int64_t batch_size = 0;
         size_t bytes = 0;
         double t_submit = 0.0, t_start = 0.0, t_done = 0.0;
         bool done = false;
@@ -56,9 +67,94 @@ struct lsrn_server {
     int64_t next_id = 1;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
-    std::deque<Request *> pending;
+    std::deque<Request *> pending, pending_batch;
     std::unordered_map<int64_t, std::unique_ptr<Request>> requests;
     std::vector<std::thread> workers;
+    static constexpr int kMaxBatch = 256;
+
+    static bool batchable(const Request &r) {
+        const lsrn_options &o = r.opt;
+        return !r.csr && r.layout == LSRN_ROW_MAJOR && r.m >= r.n && r.n <= 512 && r.lda >= r.n &&
+               o.method == LSRN_LSQR && o.lambda == 0.0 && o.precision == LSRN_PREC_FP64 &&
+               o.precond != LSRN_PRECOND_QR && o.rcond == 0.0;
+    }
+
+    void finish(Request *r, lsrn_status s, const lsrn_info &info, const std::string &err) {
+        r->status = s;
+        r->info = info;
+        if (s != LSRN_OK) r->error = err;
+        r->t_done = now_ms();
+        r->done = true;
+        in_use -= r->bytes;
+        --running;
+    }
+
+    // Takes every waiting batched request that fits (at least one when
+    // nothing runs), solves them together and completes them.
+    void batcher() {
+        (void)hipSetDevice(device);
+        hipStream_t st = nullptr;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return;
+        lsrn::set_alloc_stream(st);
+        // the batched iterations replay graph chunks, captured thread-local
+        // so that the workers' allocations stay legal meanwhile
+        std::vector<Request *> batch;
+        for (;;) {
+            batch.clear();
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv_work.wait(lk, [&] {
+                    if (stopping && pending_batch.empty()) return true;
+                    if (pending_batch.empty()) return false;
+                    return in_use + pending_batch.front()->bytes <= budget || running == 0;
+                });
+                if (pending_batch.empty()) break;
+                while (!pending_batch.empty() && (int)batch.size() < kMaxBatch) {
+                    Request *r = pending_batch.front();
+                    if (!(in_use + r->bytes <= budget || (batch.empty() && running == 0))) break;
+                    pending_batch.pop_front();
+                    in_use += r->bytes;
+                    ++running;
+                    r->t_start = now_ms();
+                    batch.push_back(r);
+                }
+                for (Request *r : batch) r->batch_size = (int64_t)batch.size();
+            }
+            const int n = (int)batch.size();
+            std::vector<int64_t> m(n), nn(n), lda(n);
+            std::vector<const double *> A(n), b(n);
+            std::vector<double *> x(n);
+            std::vector<lsrn_options> opts(n);
+            std::vector<lsrn_info> infos(n);
+            for (int k = 0; k < n; ++k) {
+                const Request &r = *batch[(size_t)k];
+                m[k] = r.m; nn[k] = r.n; lda[k] = r.lda; A[k] = r.A; b[k] = r.b; x[k] = r.x;
+                opts[k] = r.opt;
+            }
+            std::memset(infos.data(), 0, infos.size() * sizeof(lsrn_info));
+            lsrn_status s = lsrn_solve_batch_opts(n, m.data(), nn.data(), A.data(), lda.data(), b.data(),
+                                                  x.data(), opts.data(), infos.data(), st);
+            if (hipStreamSynchronize(st) != hipSuccess && (s == LSRN_OK || s == LSRN_E_NOT_CONVERGED))
+                s = LSRN_E_HIP;
+            const std::string err = s != LSRN_OK ? lsrn_last_error() : std::string();
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                for (int k = 0; k < n; ++k) {
+                    // not converged is per problem; any other failure is the batch's
+                    lsrn_status sk = s;
+                    if (s == LSRN_OK || s == LSRN_E_NOT_CONVERGED)
+                        sk = infos[(size_t)k].converged ? LSRN_OK : LSRN_E_NOT_CONVERGED;
+                    finish(batch[(size_t)k], sk, infos[(size_t)k],
+                           sk == LSRN_E_NOT_CONVERGED ? "LSQR reached max_iter" : err);
+                }
+            }
+            cv_work.notify_all();
+            cv_done.notify_all();
+        }
+        lsrn::set_alloc_stream(nullptr);
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+    }
 
     static double now_ms() {
         using namespace std::chrono;
@@ -100,13 +196,7 @@ struct lsrn_server {
             if (hipStreamSynchronize(st) != hipSuccess && s == LSRN_OK) s = LSRN_E_HIP;
             {
                 std::lock_guard<std::mutex> lk(mu);
-                r->status = s;
-                r->info = info;
-                if (s != LSRN_OK) r->error = lsrn_last_error();
-                r->t_done = now_ms();
-                r->done = true;
-                in_use -= r->bytes;
-                --running;
+                finish(r, s, info, s != LSRN_OK ? std::string(lsrn_last_error()) : std::string());
             }
             cv_work.notify_all();
             cv_done.notify_all();
@@ -140,6 +230,7 @@ lsrn_status lsrn_server_create(int64_t hbm_budget_bytes, int32_t streams, lsrn_s
         }
         srv->budget = (size_t)hbm_budget_bytes;
         for (int i = 0; i < streams; ++i) srv->workers.emplace_back([srv] { srv->worker(); });
+        srv->workers.emplace_back([srv] { srv->batcher(); });
         *out = srv;
         return LSRN_OK;
     } catch (...) {
@@ -153,7 +244,8 @@ static lsrn_status enqueue(lsrn_server *srv, std::unique_ptr<lsrn_server::Reques
     r->id = srv->next_id++;
     r->t_submit = lsrn_server::now_ms();
     *ticket = r->id;
-    srv->pending.push_back(r.get());
+    r->batch = lsrn_server::batchable(*r);
+    (r->batch ? srv->pending_batch : srv->pending).push_back(r.get());
     srv->requests.emplace(r->id, std::move(r));
     srv->cv_work.notify_one();
     return LSRN_OK;
@@ -208,6 +300,7 @@ lsrn_status lsrn_server_wait(lsrn_server *srv, int64_t ticket, lsrn_info *info,
         timing->run_ms = r->t_done - r->t_start;
         timing->latency_ms = r->t_done - r->t_submit;
         timing->footprint_bytes = (int64_t)r->bytes;
+        timing->batch_size = r->batch_size;
     }
     const lsrn_status s = r->status;
     if (s != LSRN_OK) g_server_error = r->error;
@@ -219,7 +312,7 @@ lsrn_status lsrn_server_stats(lsrn_server *srv, int64_t *pending, int64_t *runni
                               int64_t *bytes_in_use) {
     if (!srv) return server_fail(LSRN_E_INVALID, "NULL server");
     std::lock_guard<std::mutex> lk(srv->mu);
-    if (pending) *pending = (int64_t)srv->pending.size();
+    if (pending) *pending = (int64_t)(srv->pending.size() + srv->pending_batch.size());
     if (running) *running = srv->running;
     if (bytes_in_use) *bytes_in_use = (int64_t)srv->in_use;
     return LSRN_OK;

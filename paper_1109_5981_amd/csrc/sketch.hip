@@ -191,20 +191,24 @@ sketch_mfma_kernel(const TT *__restrict__ T, int64_t ldt, int64_t K, int64_t d, 
                               (int)blockIdx.y);
 }
 
-// One problem of a batched sketch (no split of K).
+// One problem of a batched sketch: tiles_m x tiles_n tiles of X, each over
+// nsplit slices of k_per_split rows of T (slice j's partial sums in
+// Xp + j s d when nsplit > 1, else in X itself).
 struct SkItem {
     const double *T;
     int64_t ldt, K, d, s;
     double *X;
-    int tiles_m;
+    int tiles_m, tiles, nsplit;
+    int64_t k_per_split;
+    double *Xp;
+    uint64_t seed;  // the problem's Philox key
 };
 
-// Every tile of every problem in one launch: workgroup g is tile
-// g - off[p] of problem p (off: prefix sums of the tile counts).
+// Every (tile, slice) of every problem in one launch: workgroup g is work
+// item g - off[p] of problem p (off: prefix sums of tiles x nsplit).
 template <bool VEC2>
 __global__ void __launch_bounds__((NT_<2, 2>), 2)
-sketch_batch_kernel(const SkItem *__restrict__ items, const int *__restrict__ off, int n,
-                    uint64_t seed) {
+sketch_batch_kernel(const SkItem *__restrict__ items, const int *__restrict__ off, int n) {
     const int g = (int)blockIdx.x;
     int lo = 0, hi = n - 1;
     while (lo < hi) {
@@ -213,8 +217,29 @@ sketch_batch_kernel(const SkItem *__restrict__ items, const int *__restrict__ of
         else hi = mid - 1;
     }
     const SkItem it = items[lo];
-    sketch_tile<2, 2, VEC2, double>(it.T, it.ldt, it.K, it.d, it.s, seed, it.K, it.tiles_m, it.X,
-                                 g - off[lo], 0);
+    const int w = g - off[lo];
+    sketch_tile<2, 2, VEC2, double>(it.T, it.ldt, it.K, it.d, it.s, it.seed, it.k_per_split, it.tiles_m,
+                                 it.nsplit > 1 ? it.Xp : it.X, w % it.tiles, w / it.tiles);
+}
+
+// X = the sum of a split problem's slices in ascending order, for every
+// split problem of a batch: workgroup g covers 256 entries of problem p.
+__global__ void __launch_bounds__(256)
+sum_slices_batch_kernel(const SkItem *__restrict__ items, const int *__restrict__ off, int n) {
+    const int g = (int)blockIdx.x;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    const SkItem &it = items[lo];
+    const int64_t count = it.s * it.d;
+    const int64_t t = (int64_t)(g - off[lo]) * 256 + threadIdx.x;
+    if (t >= count) return;
+    double acc = 0.0;
+    for (int sl = 0; sl < it.nsplit; ++sl) acc += it.Xp[(int64_t)sl * count + t];
+    it.X[t] = acc;
 }
 
 // X[idx] = sum over slices of Xp[slice][idx], slices in ascending order.
@@ -426,34 +451,70 @@ void sketch_rows(int64_t K, int64_t d, const float *T, int64_t ldt, double lambd
     sketch_rows_t(K, d, T, ldt, lambda, s, seed, X, st, kernel_ms);
 }
 
+// Slices of K for one problem of a batch, from its own sizes alone (so its
+// bits do not depend on the rest of the batch): slices of at least
+// kBatchSliceRows rows, and no more than about 256 work items a problem.
+constexpr int64_t kBatchSliceRows = 2048;
+
 void sketch_rows_batch(int count, const int64_t *K, const int64_t *d, const double *const *T,
-                       const int64_t *ldt, const int64_t *s, uint64_t seed, double *const *X,
+                       const int64_t *ldt, const int64_t *s, const uint64_t *seeds, double *const *X,
                        hipStream_t st) {
     for (int pass = 0; pass < 2; ++pass) {  // rows aligned for paired loads, then the rest
         std::vector<SkItem> items;
         std::vector<int> off(1, 0);
+        size_t slice_elems = 0;
         for (int p = 0; p < count; ++p) {
             const bool vec2 = (ldt[p] % 2 == 0) && ((reinterpret_cast<uintptr_t>(T[p]) & 15) == 0);
             if (vec2 != (pass == 0)) continue;
             const int tm = (int)ceil_div(s[p], BM_<2>), tn = (int)ceil_div(d[p], BN_<2>);
-            items.push_back(SkItem{T[p], ldt[p], K[p], d[p], s[p], X[p], tm});
-            off.push_back(off.back() + tm * tn);
+            const int tiles = tm * tn;
+            int nsplit = (int)std::min<int64_t>(K[p] / kBatchSliceRows, std::max(1, 256 / tiles));
+            nsplit = std::max(nsplit, 1);
+            int64_t kps = round_up(ceil_div(K[p], (int64_t)nsplit), (int64_t)KT);
+            nsplit = (int)ceil_div(K[p], kps);  // no empty slice
+            items.push_back(SkItem{T[p], ldt[p], K[p], d[p], s[p], X[p], tm, tiles, nsplit, kps, nullptr,
+                                   seeds[p]});
+            if (nsplit > 1) slice_elems += (size_t)nsplit * (size_t)s[p] * (size_t)d[p];
+            off.push_back(off.back() + tiles * nsplit);
         }
         if (items.empty()) continue;
         const int n = (int)items.size();
-        DevBuf ditems((size_t)n * sizeof(SkItem)), doff(off.size() * sizeof(int));
+        DevBuf slices(slice_elems * sizeof(double));
+        std::vector<SkItem> split_items;
+        std::vector<int> off_sum(1, 0);
+        size_t at = 0;
+        for (SkItem &it : items) {
+            if (it.nsplit <= 1) continue;
+            it.Xp = slices.as<double>() + at;
+            at += (size_t)it.nsplit * (size_t)it.s * (size_t)it.d;
+            split_items.push_back(it);
+            off_sum.push_back(off_sum.back() + (int)ceil_div(it.s * it.d, (int64_t)256));
+        }
+        const int ns = (int)split_items.size();
+        DevBuf ditems((size_t)(n + ns) * sizeof(SkItem)), doff((off.size() + off_sum.size()) * sizeof(int));
         LSRN_HIP(hipMemcpyAsync(ditems.as<SkItem>(), items.data(), (size_t)n * sizeof(SkItem),
                                 hipMemcpyHostToDevice, st));
         LSRN_HIP(hipMemcpyAsync(doff.as<int>(), off.data(), off.size() * sizeof(int),
                                 hipMemcpyHostToDevice, st));
+        if (ns > 0) {
+            LSRN_HIP(hipMemcpyAsync(ditems.as<SkItem>() + n, split_items.data(), (size_t)ns * sizeof(SkItem),
+                                    hipMemcpyHostToDevice, st));
+            LSRN_HIP(hipMemcpyAsync(doff.as<int>() + off.size(), off_sum.data(), off_sum.size() * sizeof(int),
+                                    hipMemcpyHostToDevice, st));
+        }
         if (pass == 0)
             sketch_batch_kernel<true><<<(unsigned)off.back(), NT_<2, 2>, 0, st>>>(ditems.as<SkItem>(),
-                                                                               doff.as<int>(), n, seed);
+                                                                               doff.as<int>(), n);
         else
             sketch_batch_kernel<false><<<(unsigned)off.back(), NT_<2, 2>, 0, st>>>(ditems.as<SkItem>(),
-                                                                                doff.as<int>(), n, seed);
+                                                                                doff.as<int>(), n);
         LSRN_HIP(hipGetLastError());
-        LSRN_HIP(hipStreamSynchronize(st));  // before the tables are freed
+        if (ns > 0) {
+            sum_slices_batch_kernel<<<(unsigned)off_sum.back(), 256, 0, st>>>(
+                ditems.as<SkItem>() + n, doff.as<int>() + off.size(), ns);
+            LSRN_HIP(hipGetLastError());
+        }
+        LSRN_HIP(hipStreamSynchronize(st));  // before the tables and slices are freed
     }
 }
 

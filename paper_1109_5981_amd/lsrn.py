@@ -60,7 +60,7 @@ EXPORTS = ["lsrn_default_options", "lsrn_status_string", "lsrn_last_error", "lsr
            "lsrn_philox_words", "lsrn_gauss_fill", "lsrn_sketch_dense", "lsrn_sketch_dense_bf16",
            "lsrn_sketch_csr",
            "lsrn_precond", "lsrn_precond_qr", "lsrn_iterate_dense", "lsrn_iterate_csr"]
-EXPORTS = EXPORTS + ["lsrn_solve_batch"]
+EXPORTS = EXPORTS + ["lsrn_solve_batch", "lsrn_solve_batch_opts"]
 SERVER_EXPORTS = ["lsrn_server_create", "lsrn_server_submit_dense", "lsrn_server_submit_csr",
                   "lsrn_server_wait", "lsrn_server_stats", "lsrn_server_last_error",
                   "lsrn_server_destroy"]
@@ -83,7 +83,7 @@ _SIZE_FNS = ("lsrn_default_options", "lsrn_status_string", "lsrn_last_error",
 
 class ServerTiming(C.Structure):
     _fields_ = [("queue_ms", C.c_double), ("run_ms", C.c_double), ("latency_ms", C.c_double),
-                ("footprint_bytes", C.c_int64)]
+                ("footprint_bytes", C.c_int64), ("batch_size", C.c_int64)]
 
 
 def lib():
@@ -119,6 +119,7 @@ def lib():
         L.lsrn_iterate_csr.argtypes = [I64, I64, I64, P, P, P, P, P, I64, I64, I64, P,
                                        C.POINTER(Options), C.POINTER(Info), P]
         L.lsrn_solve_batch.argtypes = [I32, P, P, P, P, P, P, C.POINTER(Options), P, P]
+        L.lsrn_solve_batch_opts.argtypes = [I32, P, P, P, P, P, P, P, P, P]
         L.lsrn_server_create.argtypes = [I64, I32, C.POINTER(C.c_void_p)]
         L.lsrn_server_submit_dense.argtypes = [P, I64, I64, P, I64, I32, P, P, C.POINTER(Options),
                                                C.POINTER(C.c_int64)]
@@ -615,7 +616,8 @@ class Server:
         out = info.as_dict()
         out["status"] = int(st)
         return x, out, {"queue_ms": tm.queue_ms, "run_ms": tm.run_ms,
-                        "latency_ms": tm.latency_ms, "footprint_bytes": tm.footprint_bytes}
+                        "latency_ms": tm.latency_ms, "footprint_bytes": tm.footprint_bytes,
+                        "batch_size": tm.batch_size}
 
     def stats(self):
         p, r, b = C.c_int64(), C.c_int64(), C.c_int64()
@@ -634,9 +636,11 @@ class Server:
         self.close()
 
 
-def solve_batch(As, bs, xs=None, allow_not_converged: bool = False, **opts):
-    """lsrn_solve_batch over lists of row-major tall A (n <= 512) and b.
-    Returns (list of x, list of info dicts)."""
+def solve_batch(As, bs, xs=None, allow_not_converged: bool = False, per_problem=None, **opts):
+    """lsrn_solve_batch over lists of row-major tall A (n <= 512) and b, or
+    with per_problem (a list of option dicts, one per problem, each merged
+    over **opts) lsrn_solve_batch_opts.  Returns (list of x, list of info
+    dicts)."""
     count = len(As)
     if len(bs) != count:
         raise ValueError("As and bs differ in length")
@@ -652,11 +656,17 @@ def solve_batch(As, bs, xs=None, allow_not_converged: bool = False, **opts):
         xs = [torch.empty(n, dtype=torch.float64, device=A.device) for A, n in zip(As, ns)]
     I64A = C.c_int64 * max(count, 1)
     PA = C.c_void_p * max(count, 1)
-    o = options(**opts)
     infos = (Info * max(count, 1))()
-    st = lib().lsrn_solve_batch(count, I64A(*ms), I64A(*ns), PA(*[A.data_ptr() for A in As]),
-                                I64A(*ldas), PA(*[b.data_ptr() for b in bs]),
-                                PA(*[x.data_ptr() for x in xs]), C.byref(o), infos, _stream())
+    args = (count, I64A(*ms), I64A(*ns), PA(*[A.data_ptr() for A in As]), I64A(*ldas),
+            PA(*[b.data_ptr() for b in bs]), PA(*[x.data_ptr() for x in xs]))
+    if per_problem is None:
+        o = options(**opts)
+        st = lib().lsrn_solve_batch(*args, C.byref(o), infos, _stream())
+    else:
+        if len(per_problem) != count:
+            raise ValueError("per_problem needs one option dict per problem")
+        oa = (Options * max(count, 1))(*[options(**dict(opts, **d)) for d in per_problem])
+        st = lib().lsrn_solve_batch_opts(*args, oa, infos, _stream())
     if not (allow_not_converged and st == 4):
         _check(st)
     return xs, [infos[i].as_dict() for i in range(count)]

@@ -85,6 +85,39 @@ def test_batch_refined_matches_oracle_1e10(L, orc):
         assert i1[0]["iters"] == infos[k]["iters"] and i1[0]["refine_iters"] == infos[k]["refine_iters"]
 
 
+def test_batch_per_problem_options(L, orc):
+    """lsrn_solve_batch_opts: every problem takes its own seed, tolerance,
+    iteration cap and refinement steps; each result equals that problem
+    batched alone with its options, bit for bit, and the refined ones are
+    within 1e-10 of the oracle.  A problem whose cap stops it early reports
+    not converged without holding the others back."""
+    rng = np.random.default_rng(31)
+    As, bs, opts, hosts = [], [], [], []
+    specs = [(24, dict(seed=3, tol=1e-14, refine=2)), (100, dict(seed=8, tol=1e-8)),
+             (257, dict(seed=1, tol=1e-12, refine=1)), (64, dict(seed=5, tol=1e-14, max_iter=3)),
+             (512, dict(seed=2, tol=1e-10, refine=3)), (9, dict(seed=4, tol=1e-14))]
+    for i, (n, o) in enumerate(specs):
+        m = int(rng.integers(2 * n + 300, 6000))
+        P = workloads.dense_problem(m, n, smin=10.0 ** -(2 + i % 4), seed=1200 + i)
+        b = workloads.rhs_gauss(m, 1200 + i)
+        As.append(dev(P.A)); bs.append(dev(b)); opts.append(o); hosts.append((P.A, b))
+    xs, infos = L.solve_batch(As, bs, allow_not_converged=True, per_problem=opts)
+    for k, o in enumerate(opts):
+        x1, i1 = L.solve_batch([As[k]], [bs[k]], allow_not_converged=True, per_problem=[o])
+        np.testing.assert_array_equal(host(x1[0]), host(xs[k]))
+        assert i1[0]["iters"] == infos[k]["iters"]
+        assert infos[k]["refine_steps"] == o.get("refine", 0)
+        if o.get("refine", 0) > 0:
+            A, b = hosts[k]
+            ref = orc.lsrn_solve(orc.Matrix.dense(A), b, seed=1, refine=3).x
+            assert rel(host(xs[k]), ref) <= 1e-10, (k, o)
+    assert not infos[3]["converged"] and infos[3]["iters"] == 3
+    assert all(infos[k]["converged"] for k in (0, 1, 2, 4, 5))
+    # a different seed changes the sketch, so the iterates differ
+    xo, _ = L.solve_batch([As[1]], [bs[1]], per_problem=[dict(opts[1], seed=9)])
+    assert not np.array_equal(host(xo[0]), host(xs[1]))
+
+
 def test_batch_padded_rows_equal_contiguous(L):
     """Problems given with an odd leading dimension (element loads in the
     batched sketch and sweeps) give bit for bit the batch result of the

@@ -1,6 +1,7 @@
 """The serving runtime: every request's result is the same alone and in a
-mix of concurrently running solves, admission respects the memory budget,
-and errors come back per request."""
+mix of concurrently running solves (batched requests: the same as batched
+alone), admission respects the memory budget, and errors come back per
+request."""
 import time
 
 import numpy as np
@@ -73,7 +74,20 @@ def oracle_ref(orc, spec, b, lam):
     return orc.lsrn_solve(M, b, seed=1, refine=3).x
 
 
+def batchable(kind, opts):
+    """The requests the server's batcher takes (the batched path's scope:
+    dense row-major over-determined FP64 LSQR, n <= 512, no lambda)."""
+    return (kind == "dense" and opts.get("layout", 0) == 0 and opts.get("precision", "fp64") == "fp64"
+            and opts.get("method", "lsqr") == "lsqr" and opts.get("lam", 0.0) == 0.0)
+
+
 def solve_alone(L, kind, A, b, opts):
+    """A request's result alone: the batched path with only this request for
+    those the batcher takes, the one-problem solve for the rest."""
+    if kind == "dense" and batchable(kind, opts) and A.shape[0] >= A.shape[1] and A.shape[1] <= 512:
+        o = {k: v for k, v in opts.items() if k != "layout"}
+        xs, infos = L.solve_batch([A], [b], allow_not_converged=True, per_problem=[o])
+        return host(xs[0]), infos[0]
     if kind == "dense":
         x, info = L.solve_dense(A, b, allow_not_converged=True, **opts)
     else:
@@ -87,6 +101,7 @@ def test_results_alone_equal_results_in_mix(L, orc):
     (FP64 requests refined three steps; precision-form requests refined to
     their FP64 answer)."""
     reqs = mix(L)
+    assert sum(batchable(kind, o) for kind, _, _, o, _ in reqs) == 3   # both queues are used
     L.tune_clear()
     alone = [solve_alone(L, kind, A, b, {k: v for k, v in o.items() if k != "autotune"})[0]
              for kind, A, b, o, _ in reqs]
@@ -102,10 +117,11 @@ def test_results_alone_equal_results_in_mix(L, orc):
                     tickets.append(srv.submit_dense(A, b, **opts))
                 else:
                     tickets.append(srv.submit_csr(A, b, **opts))
-            for t, ref in zip(tickets, alone):
+            for t, ref, (kind, _, _, opts, _) in zip(tickets, alone, reqs):
                 x, info, tm = srv.wait(t, allow_not_converged=True)
                 np.testing.assert_array_equal(host(x), ref)
                 assert tm["latency_ms"] >= tm["run_ms"] >= 0.0
+                assert (tm["batch_size"] >= 1) == batchable(kind, opts)
     assert L.tune_export() == ""     # no served request recorded a tuned shape
 
 
