@@ -350,8 +350,13 @@ lsrn_status lsrn_iterate_csr(int64_t m, int64_t n, int64_t nnz, const int64_t *r
  * dense FP64 row-major, m[p] >= n[p], n[p] <= 512, leading dimension
  * lda[p]; b[p] length m[p]; x[p] length n[p] (arrays of device pointers
  * held on the host).  The sketches of all problems run in one launch; the
- * QR of the sketches (up to 1024 rows) and the Jacobi sweeps (d <= 512)
- * run for all problems in shared launches; then the LSQR iterations of all
+ * QR of the sketches (up to 1024 rows) runs for all problems in shared
+ * launches; with LSRN_PRECOND_AUTO a problem takes N = R^-1 when
+ * |R|_F |R^-1|_F certifies that the SVD would keep every singular value
+ * (the rule of lsrn_solve_dense; the inverses of all problems in one
+ * launch; precond_used = LSRN_PRECOND_QR), and the other problems (and all
+ * with LSRN_PRECOND_SVD) take the Jacobi sweeps (d <= 512) in shared
+ * launches; then the LSQR iterations of all
  * problems advance together: every kernel launch covers the whole batch
  * (one work item per problem row block, column chunk or problem) and each
  * chunk of iterations is replayed as a HIP graph, so the number of
@@ -360,7 +365,7 @@ lsrn_status lsrn_iterate_csr(int64_t m, int64_t n, int64_t nnz, const int64_t *r
  * A^T (b - A x) of every problem, then CG on the preconditioned normal
  * equations to opt->refine_tol for all problems together, x += N z; as in
  * lsrn_solve_dense).  One option set for all problems; LSQR only,
- * lambda = 0, precision FP64, the SVD preconditioner (LSRN_E_UNSUPPORTED
+ * lambda = 0, precision FP64, precond AUTO or SVD (LSRN_E_UNSUPPORTED
  * otherwise).  infos (count entries, may be NULL) report per problem; the
  * stage times are those of the whole batch (t_iter_ms includes the
  * refinement).  LSRN_E_NOT_CONVERGED if any problem's LSQR reached

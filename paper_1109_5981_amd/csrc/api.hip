@@ -863,7 +863,7 @@ static lsrn_status solve_batch_body(int32_t count, const int64_t *m, const int64
         check_options(opt);
         if (opt.method != LSRN_LSQR || opt.lambda != 0.0 || opt.precision != LSRN_PREC_FP64 ||
             opt.precond == LSRN_PRECOND_QR)
-            fail(LSRN_E_UNSUPPORTED, "the batched path runs FP64 LSQR with the SVD preconditioner, "
+            fail(LSRN_E_UNSUPPORTED, "the batched path runs FP64 LSQR with the automatic or SVD preconditioner, "
                                      "without lambda");
         // the preconditioners of the batch are formed together with one cutoff
         LSRN_REQUIRE(opt.rcond == ov[0].rcond, "batched problems need the same rcond");
@@ -907,8 +907,10 @@ static lsrn_status solve_batch_body(int32_t count, const int64_t *m, const int64
     for (int32_t p = 0; p < count; ++p) seeds[(size_t)p] = ov[(size_t)p].seed;
     if (count > 0)
         sketch_rows_batch(count, m, n, A, lda, ss.data(), seeds.data(), Xp.data(), st);
+    std::vector<char> tfr((size_t)count);
+    for (int32_t p = 0; p < count; ++p) tfr[(size_t)p] = try_full_rank(ov[(size_t)p], n[p]) ? 1 : 0;
     precond_batch(count, ss.data(), n, Xp.data(), count > 0 ? ov[0].rcond : 0.0, sp.data(), Pp.data(),
-                  prs.data(), st);
+                  prs.data(), st, tfr.data());
     Xpool.release();
     Spool.release();
     for (int32_t p = 0; p < count; ++p) {
@@ -950,7 +952,7 @@ static lsrn_status solve_batch_body(int32_t count, const int64_t *m, const int64
         in.s = ss[(size_t)p]; in.d = n[p]; in.rank = prs[(size_t)p].rank;
         in.iters = full[(size_t)p].iters; in.sweeps = prs[(size_t)p].sweeps; in.tall = 1;
         in.refine_steps = full[(size_t)p].refine_steps; in.refine_iters = full[(size_t)p].refine_iters;
-        in.precond_used = LSRN_PRECOND_SVD;
+        in.precond_used = prs[(size_t)p].full_rank_inverse ? LSRN_PRECOND_QR : LSRN_PRECOND_SVD;
         in.converged = full[(size_t)p].converged;
         in.sigma_l = full[(size_t)p].sigma_l; in.sigma_u = full[(size_t)p].sigma_u;
         in.sigma_max = prs[(size_t)p].sigma_max; in.sigma_min_kept = prs[(size_t)p].sigma_min_kept;

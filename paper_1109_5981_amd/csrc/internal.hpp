@@ -121,11 +121,14 @@ struct PrecondResult {
 // descending).  Synchronises.
 PrecondResult precond(int64_t s, int64_t d, double *X, double rcond, double *sigma, double *P,
                       hipStream_t st, bool profile = false, bool try_full_rank = false);
-// precond for `count` sketches at once: the QR of each, then the Jacobi
-// sweeps of all problems with d <= 512 in shared launches (wider ones one
-// at a time).  X[p] is overwritten.
+// precond for `count` sketches at once: the QR of each; for the problems
+// with try_fr[p] (d <= 512; try_fr may be NULL) the certified P = R^-1 of
+// all of them in one launch; then the Jacobi sweeps of the rest with
+// d <= 512 in shared launches (wider ones one at a time).  X[p] is
+// overwritten.
 void precond_batch(int count, const int64_t *s, const int64_t *d, double *const *X, double rcond,
-                   double *const *sigma, double *const *P, PrecondResult *res, hipStream_t st);
+                   double *const *sigma, double *const *P, PrecondResult *res, hipStream_t st,
+                   const char *try_fr = nullptr);
 size_t precond_workspace_bytes(int64_t s, int64_t d);
 // Householder QR of X (s x d, column-major, in place; R in the upper
 // triangle).  Synchronises.

@@ -1379,8 +1379,140 @@ PrecondResult precond(int64_t s, int64_t d, double *X, double rcond, double *sig
     return res;
 }
 
+namespace {
+
+// One problem of a batched triangular inverse (d <= 512).
+struct TriInvItem {
+    const double *R;  // upper triangle, column-major, leading dimension ldr
+    int64_t ldr;
+    int d;
+    double *P;     // R^-1, row-major d x d
+    double *part;  // [0, d): |R(:, j)|^2; [d, 2d): |R^-1(:, j)|^2; [2d, 3d): |r_jj|
+};
+
+// Column j of R^-1 for every problem of a batch (workgroup g: column
+// g - off[p] of problem p): back substitution on R y = e_j, the right-hand
+// side in LDS, one row a step from j down to 0 (step k reads only x_k and
+// updates only x_i, i < k, so one barrier a step suffices).
+__global__ void __launch_bounds__(256)
+trinv_col_batch_kernel(const TriInvItem *__restrict__ items, const int *__restrict__ off, int n) {
+    __shared__ double xs[512], ys[512];
+    __shared__ double red[2][4];
+    const int g = (int)blockIdx.x;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    const TriInvItem it = items[lo];
+    const int j = g - off[lo], d = it.d, tid = (int)threadIdx.x;
+    const double *__restrict__ R = it.R;
+    for (int i = tid; i <= j; i += 256) xs[i] = i == j ? 1.0 : 0.0;
+    __syncthreads();
+    for (int k = j; k >= 0; --k) {
+        const double *__restrict__ rk = R + (int64_t)k * it.ldr;
+        const double yk = xs[k] / rk[k];
+        if (tid == 0) ys[k] = yk;
+        for (int i = tid; i < k; i += 256) xs[i] -= rk[i] * yk;
+        __syncthreads();
+    }
+    double sy = 0.0, sr = 0.0;
+    const double *__restrict__ rj = R + (int64_t)j * it.ldr;
+    for (int i = tid; i < d; i += 256) {
+        const double y = i <= j ? ys[i] : 0.0;
+        it.P[(int64_t)i * d + j] = y;
+        sy += y * y;
+        if (i <= j) sr += rj[i] * rj[i];
+    }
+    sy = wave_sum(sy);
+    sr = wave_sum(sr);
+    if ((tid & 63) == 0) {
+        red[0][tid >> 6] = sr;
+        red[1][tid >> 6] = sy;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        it.part[j] = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+        it.part[d + j] = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
+        it.part[2 * d + j] = fabs(rj[j]);
+    }
+}
+
+// The full-rank case of full_rank_inverse for the problems of a batch that
+// try it, in one launch and one read-back: P = R^-1 where |R|_F |R^-1|_F
+// <= 1 / (2 rc) certifies that the SVD would keep every singular value
+// (done[p] = 1; sigma = |diag R| descending; sigma_min_kept = 1 / |R^-1|_F,
+// a lower bound on sigma_d).  The others are left to the SVD.
+void certified_inverse_batch(int count, const int64_t *s, const int64_t *d, double *const *X, double rcond,
+                             double *const *sigma, double *const *P, PrecondResult *res,
+                             const char *try_fr, std::vector<char> &done, hipStream_t st) {
+    std::vector<TriInvItem> items;
+    std::vector<int> off(1, 0), ids;
+    std::vector<size_t> po;
+    size_t ptot = 0;
+    for (int p = 0; p < count; ++p) {
+        if (!try_fr[p]) continue;
+        LSRN_REQUIRE(d[p] <= 512, "batched certified inverse: d <= 512");
+        ids.push_back(p);
+        po.push_back(ptot);
+        ptot += (size_t)3 * (size_t)d[p];
+        off.push_back(off.back() + (int)d[p]);
+    }
+    if (ids.empty()) return;
+    const int n = (int)ids.size();
+    DevBuf part(ptot * sizeof(double));
+    for (int k = 0; k < n; ++k) {
+        const int p = ids[(size_t)k];
+        items.push_back(TriInvItem{X[p], s[p], (int)d[p], P[p], part.as<double>() + po[(size_t)k]});
+    }
+    DevBuf ditems((size_t)n * sizeof(TriInvItem)), doff(off.size() * sizeof(int));
+    LSRN_HIP(hipMemcpyAsync(ditems.as<TriInvItem>(), items.data(), (size_t)n * sizeof(TriInvItem),
+                            hipMemcpyHostToDevice, st));
+    LSRN_HIP(hipMemcpyAsync(doff.as<int>(), off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    trinv_col_batch_kernel<<<(unsigned)off.back(), 256, 0, st>>>(ditems.as<TriInvItem>(), doff.as<int>(), n);
+    LSRN_HIP(hipGetLastError());
+    std::vector<double> h(ptot);
+    LSRN_HIP(hipMemcpyAsync(h.data(), part.as<double>(), ptot * sizeof(double), hipMemcpyDeviceToHost, st));
+    LSRN_HIP(hipStreamSynchronize(st));
+    std::vector<double> sig(ptot);  // sorted |diag R| of each certified problem
+    for (int k = 0; k < n; ++k) {
+        const int p = ids[(size_t)k];
+        const int64_t dp = d[p];
+        const double *hp = h.data() + po[(size_t)k];
+        double sr = 0.0, si = 0.0, cmax = 0.0;
+        for (int64_t j = 0; j < dp; ++j) {
+            sr += hp[j];
+            si += hp[dp + j];
+            cmax = std::max(cmax, hp[j]);
+        }
+        const double rc = rcond > 0.0 ? rcond : (double)std::max(s[p], dp) * DBL_EPSILON;
+        const double nr = std::sqrt(sr), ni = std::sqrt(si);
+        if (!(nr > 0.0 && nr * ni <= 0.5 / rc)) continue;  // NaN / inf fail too
+        double *g = sig.data() + po[(size_t)k];
+        std::copy(hp + 2 * dp, hp + 3 * dp, g);
+        std::sort(g, g + dp, [](double a, double b) { return a > b; });
+        LSRN_HIP(hipMemcpyAsync(sigma[p], g, (size_t)dp * sizeof(double), hipMemcpyHostToDevice, st));
+        res[p] = PrecondResult();
+        res[p].rank = dp;
+        res[p].sweeps = 0;
+        res[p].sigma_max = std::sqrt(cmax);
+        res[p].sigma_min_kept = 1.0 / ni;
+        res[p].full_rank_inverse = true;
+        done[(size_t)p] = 1;
+    }
+    LSRN_HIP(hipStreamSynchronize(st));  // before sig and the buffers go
+}
+
+// Steps 4-5 after the QR for a batch: Jacobi on Y = R^T, sigma, rank, P.
+void svd_batch(int count, const int64_t *s, const int64_t *d, double *const *X, double rcond,
+               double *const *sigma, double *const *P, PrecondResult *res, hipStream_t st);
+
+}  // namespace
+
 void precond_batch(int count, const int64_t *s, const int64_t *d, double *const *X, double rcond,
-                   double *const *sigma, double *const *P, PrecondResult *res, hipStream_t st) {
+                   double *const *sigma, double *const *P, PrecondResult *res, hipStream_t st,
+                   const char *try_fr) {
     // ---- QR: sketches of up to 1024 rows factor together, one launch per
     // panel step for all of them; taller ones one at a time
     {
@@ -1420,6 +1552,32 @@ void precond_batch(int count, const int64_t *s, const int64_t *d, double *const 
             LSRN_HIP(hipStreamSynchronize(st));  // before the panel buffers are freed
         }
     }
+    std::vector<char> done((size_t)count, 0);
+    if (try_fr) certified_inverse_batch(count, s, d, X, rcond, sigma, P, res, try_fr, done, st);
+    std::vector<int> rest;
+    for (int p = 0; p < count; ++p)
+        if (!done[(size_t)p]) rest.push_back(p);
+    if (rest.empty()) return;
+    if ((int)rest.size() == count) {
+        svd_batch(count, s, d, X, rcond, sigma, P, res, st);
+        return;
+    }
+    const size_t nr = rest.size();
+    std::vector<int64_t> s2(nr), d2(nr);
+    std::vector<double *> X2(nr), sig2(nr), P2(nr);
+    std::vector<PrecondResult> r2(nr);
+    for (size_t k = 0; k < nr; ++k) {
+        const int p = rest[k];
+        s2[k] = s[p]; d2[k] = d[p]; X2[k] = X[p]; sig2[k] = sigma[p]; P2[k] = P[p];
+    }
+    svd_batch((int)nr, s2.data(), d2.data(), X2.data(), rcond, sig2.data(), P2.data(), r2.data(), st);
+    for (size_t k = 0; k < nr; ++k) res[rest[k]] = r2[k];
+}
+
+namespace {
+
+void svd_batch(int count, const int64_t *s, const int64_t *d, double *const *X, double rcond,
+               double *const *sigma, double *const *P, PrecondResult *res, hipStream_t st) {
     std::vector<JacobiPlan> pl((size_t)count);
     std::vector<double *> Yb((size_t)count);  // carved from one allocation
     std::vector<int> small_ids, gram_ids, other_ids;
@@ -1551,6 +1709,8 @@ void precond_batch(int count, const int64_t *s, const int64_t *d, double *const 
     }
     LSRN_HIP(hipStreamSynchronize(st));
 }
+
+}  // namespace
 
 PrecondResult precond_qr_inverse(int64_t s, int64_t d, double *X, double rcond, double *sigma,
                                  double *P, hipStream_t st) {

@@ -42,20 +42,35 @@ def test_batch_matches_single_solves_and_oracle(L, orc):
         As.append(dev(P.A)); bs.append(dev(b))
         if i % 4 == 0:
             refs.append((i, orc.lsrn_solve(orc.Matrix.dense(P.A), b, seed=1, refine=3).x))
-    # a zero matrix: rank 0, x = 0
+    # a rank-deficient problem (rank 150 of 200: the certified R^-1 must
+    # fail and the SVD cut the rank) and a zero matrix (rank 0, x = 0)
+    Pd = workloads.dense_problem(3000, 200, rank=150, smin=1e-3, seed=399)
+    As.append(dev(Pd.A)); bs.append(dev(workloads.rhs_gauss(3000, 399)))
+    refs.append((len(As) - 1, orc.lsrn_solve(orc.Matrix.dense(Pd.A), workloads.rhs_gauss(3000, 399),
+                                             seed=1, refine=3).x))
     As.append(torch.zeros(700, 30, dtype=torch.float64, device="cuda"))
     bs.append(dev(np.ones(700)))
     xs, infos = L.solve_batch(As, bs, seed=11)
+    xv, iv = L.solve_batch(As, bs, seed=11, precond="svd")
     for k, (A, b) in enumerate(zip(As[:-1], bs[:-1])):
-        # the batch forms the SVD preconditioner; the lone solve is asked for
-        # the same (its automatic choice would take R^-1 for a full-rank sketch)
-        x1, i1 = L.solve_dense(A, b, seed=11, precond="svd")
+        # the automatic choice (R^-1 where |R|_F |R^-1|_F certifies full
+        # rank, else the SVD), batched and alone: the same preconditioner
+        # up to rounding, the sweeps summed in other orders
+        x1, i1 = L.solve_dense(A, b, seed=11)
+        assert infos[k]["precond_used"] == i1["precond_used"], k
         assert infos[k]["rank"] == i1["rank"]
         assert abs(infos[k]["iters"] - i1["iters"]) <= 1
-        # same sketch and preconditioner; the sweeps sum in other orders
         assert rel(host(xs[k]), host(x1)) < 1e-11
+        # the SVD preconditioner, batched and alone
+        x2, i2 = L.solve_dense(A, b, seed=11, precond="svd")
+        assert iv[k]["precond_used"] == 1 and iv[k]["rank"] == i2["rank"]
+        assert abs(iv[k]["iters"] - i2["iters"]) <= 1
+        assert rel(host(xv[k]), host(x2)) < 1e-11
+    assert sum(i["precond_used"] == 2 for i in infos[:-2]) == 24   # every full-rank sketch certified
+    assert infos[-2]["precond_used"] == 1 and infos[-2]["rank"] == 150
     for i, xr in refs:
         assert rel(host(xs[i]), xr) < 1e-9
+        assert rel(host(xv[i]), xr) < 1e-9
     assert infos[-1]["rank"] == 0 and np.all(host(xs[-1]) == 0.0)
 
 
