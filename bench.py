@@ -280,6 +280,9 @@ def serve_main(args):
                             "median": float(np.median(checks)) if checks else None,
                             "max_by_category": worst},
         "precision_form_fp64_fallbacks": sum(1 for r in results.values() if r["fp64_steps"] > 0),
+        # precision-form requests the batcher took: the batched path computes in FP64
+        "precision_form_batched_in_fp64": sum(1 for r in results.values()
+                                              if r["precision"] == "mixed" and r["batch_size"] > 0),
     }
     print(json.dumps(line))
 

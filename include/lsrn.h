@@ -365,8 +365,11 @@ lsrn_status lsrn_iterate_csr(int64_t m, int64_t n, int64_t nnz, const int64_t *r
  * A^T (b - A x) of every problem, then CG on the preconditioned normal
  * equations to opt->refine_tol for all problems together, x += N z; as in
  * lsrn_solve_dense).  One option set for all problems; LSQR only,
- * lambda = 0, precision FP64, precond AUTO or SVD (LSRN_E_UNSUPPORTED
- * otherwise).  infos (count entries, may be NULL) report per problem; the
+ * lambda = 0, precond AUTO or SVD (LSRN_E_UNSUPPORTED otherwise).  The
+ * batched path computes in FP64 only: a problem that asks for
+ * LSRN_PREC_MIXED is solved exactly as with LSRN_PREC_FP64 (the precision
+ * form's result is the FP64 answer its refinement reaches; for problems
+ * this small FP32 sweeps save nothing).  infos (count entries, may be NULL) report per problem; the
  * stage times are those of the whole batch (t_iter_ms includes the
  * refinement).  LSRN_E_NOT_CONVERGED if any problem's LSQR reached
  * max_iter (its x holds the last iterate, refined).

@@ -861,9 +861,9 @@ static lsrn_status solve_batch_body(int32_t count, const int64_t *m, const int64
     for (int32_t p = 0; p < count; ++p) {
         const lsrn_options &opt = ov[(size_t)p];
         check_options(opt);
-        if (opt.method != LSRN_LSQR || opt.lambda != 0.0 || opt.precision != LSRN_PREC_FP64 ||
-            opt.precond == LSRN_PRECOND_QR)
-            fail(LSRN_E_UNSUPPORTED, "the batched path runs FP64 LSQR with the automatic or SVD preconditioner, "
+        // the precision form is accepted and runs in FP64 like the rest
+        if (opt.method != LSRN_LSQR || opt.lambda != 0.0 || opt.precond == LSRN_PRECOND_QR)
+            fail(LSRN_E_UNSUPPORTED, "the batched path runs LSQR with the automatic or SVD preconditioner, "
                                      "without lambda");
         // the preconditioners of the batch are formed together with one cutoff
         LSRN_REQUIRE(opt.rcond == ov[0].rcond, "batched problems need the same rcond");

@@ -2280,7 +2280,8 @@ void OpView::apply_t(int t, int64_t k, const double *in, int64_t ldin, double *o
 namespace {
 
 constexpr int BCPT = 2, BR = 8;          // the sweep variant for L <= 512
-constexpr int B_RED_COLS = 64;           // columns of z per reduction workgroup
+constexpr int B_RED_COLS = 32;           // columns of z per reduction workgroup
+constexpr int B_RED_GROUPS = 256 / B_RED_COLS;  // partial groups per reduction workgroup
 
 // Rows per workgroup of a problem's batched sweeps, from its own row count
 // alone (so its bits do not depend on the rest of the batch): about 512
@@ -2335,26 +2336,42 @@ batch_sweep_kernel(const BatchItem *__restrict__ it, const int *__restrict__ off
     }
 }
 
+// Sum over the partials k = g, g + 8, ... of column col: four independent
+// chains (k = g + 8 (4 q + u), u = 0..3), added as (c0 + c1) + (c2 + c3).
+__device__ __forceinline__ double batch_col_sum(const double *__restrict__ zp, int64_t L, int col, int nb,
+                                                int g) {
+    double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
+    constexpr int S = B_RED_GROUPS;
+    int k = g;
+    for (; k + 3 * S < nb; k += 4 * S) {
+        c0 += zp[(int64_t)k * L + col];
+        c1 += zp[(int64_t)(k + S) * L + col];
+        c2 += zp[(int64_t)(k + 2 * S) * L + col];
+        c3 += zp[(int64_t)(k + 3 * S) * L + col];
+    }
+    if (k < nb) c0 += zp[(int64_t)k * L + col];
+    if (k + S < nb) c1 += zp[(int64_t)(k + S) * L + col];
+    if (k + 2 * S < nb) c2 += zp[(int64_t)(k + 2 * S) * L + col];
+    return (c0 + c1) + (c2 + c3);
+}
+
 // z_p = sum of the row-block partials, st_p->acc = sum of the scalar
-// partials.  A workgroup takes 64 columns: four groups of 64 threads sum
-// the partials k = g mod 4, then the four sums are added in order g = 0..3;
-// the first workgroup of a problem also sums the scalar partials (64
-// threads a scalar, k = q mod 64, added in order q = 0..63).
+// partials.  A workgroup takes 32 columns: eight groups of 32 threads sum
+// the partials k = g mod 8 (batch_col_sum), then the eight sums are added
+// in order g = 0..7; the first workgroup of a problem also sums the scalar
+// partials (64 threads a scalar, k = q mod 64, added in order q = 0..63).
 __global__ void __launch_bounds__(256)
 batch_reduce_kernel(const BatchItem *__restrict__ it, const int *__restrict__ off, int n) {
-    __shared__ double red[4][B_RED_COLS];
+    __shared__ double red[B_RED_GROUPS][B_RED_COLS];
     __shared__ double sred[64][4];
     const int p = find_item(off, n, (int)blockIdx.x);
     const BatchItem &b = it[p];
     if (b.sw.st->done) return;
     const int chunk = (int)blockIdx.x - off[p];
-    const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int c = threadIdx.x % B_RED_COLS, g = threadIdx.x / B_RED_COLS;
     const int col = chunk * B_RED_COLS + c;
     const int nb = b.sw.nblocks;
-    double t = 0.0;
-    if (col < b.L)
-        for (int k = g; k < nb; k += 4) t += b.sw.zpart[(int64_t)k * b.L + col];
-    red[g][c] = t;
+    red[g][c] = col < b.L ? batch_col_sum(b.sw.zpart, b.L, col, nb, g) : 0.0;
     if (chunk == 0) {
         const int a = threadIdx.x & 3, q = threadIdx.x >> 2;
         double u = 0.0;
@@ -2362,7 +2379,11 @@ batch_reduce_kernel(const BatchItem *__restrict__ it, const int *__restrict__ of
         sred[q][a] = u;
     }
     __syncthreads();
-    if (g == 0 && col < b.L) b.z[col] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+    if (g == 0 && col < b.L) {
+        double t = red[0][c];
+        for (int q = 1; q < B_RED_GROUPS; ++q) t += red[q][c];
+        b.z[col] = t;
+    }
     if (chunk == 0 && threadIdx.x < 4) {
         double u = 0.0;
         for (int q = 0; q < 64; ++q) u += sred[q][threadIdx.x];
@@ -2438,21 +2459,21 @@ batch_resid_kernel(const BatchItem *__restrict__ it, const int *__restrict__ off
 __global__ void __launch_bounds__(256)
 batch_reduce_dd_kernel(const BatchItem *__restrict__ it, const int *__restrict__ off, int n, int step) {
     const int p = find_item(off, n, (int)blockIdx.x);
-    __shared__ double rhi[4][B_RED_COLS], rlo[4][B_RED_COLS];
+    __shared__ double rhi[B_RED_GROUPS][B_RED_COLS], rlo[B_RED_GROUPS][B_RED_COLS];
     const BatchItem &b = it[p];
     if (step >= b.refine) return;
-    const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int c = threadIdx.x % B_RED_COLS, g = threadIdx.x / B_RED_COLS;
     const int col = ((int)blockIdx.x - off[p]) * B_RED_COLS + c;
     dd t = {0.0, 0.0};
     if (col < b.L)
-        for (int k = g; k < b.sw.nblocks; k += 4)
+        for (int k = g; k < b.sw.nblocks; k += B_RED_GROUPS)
             t = dd_add(t, dd{b.hhi[(int64_t)k * b.L + col], b.hlo[(int64_t)k * b.L + col]});
     rhi[g][c] = t.hi;
     rlo[g][c] = t.lo;
     __syncthreads();
     if (g == 0 && col < b.L) {
         dd u = {rhi[0][c], rlo[0][c]};
-        for (int q = 1; q < 4; ++q) u = dd_add(u, dd{rhi[q][c], rlo[q][c]});
+        for (int q = 1; q < B_RED_GROUPS; ++q) u = dd_add(u, dd{rhi[q][c], rlo[q][c]});
         b.h[col] = u.hi;
     }
 }

@@ -13,8 +13,9 @@
 // lsrn_solve_dense / lsrn_solve_csr on its own, so its result does not
 // depend on what else is running.
 //
-// Requests the batched path covers (dense row-major over-determined FP64
-// LSQR with n <= 512, lambda = 0 and the default rank cutoff) queue apart:
+// Requests the batched path covers (dense row-major over-determined LSQR
+// with n <= 512, lambda = 0 and the default rank cutoff; the precision
+// form's requests among them run in FP64 there) queue apart:
 // one batcher thread, on a stream of its own, takes all of them that are
 // waiting when it is free (up to kMaxBatch, within the budget) and solves
 // them together with lsrn_solve_batch_opts, so that the iterations of
@@ -75,8 +76,7 @@ struct lsrn_server {
     static bool batchable(const Request &r) {
         const lsrn_options &o = r.opt;
         return !r.csr && r.layout == LSRN_ROW_MAJOR && r.m >= r.n && r.n <= 512 && r.lda >= r.n &&
-               o.method == LSRN_LSQR && o.lambda == 0.0 && o.precision == LSRN_PREC_FP64 &&
-               o.precond != LSRN_PRECOND_QR && o.rcond == 0.0;
+               o.method == LSRN_LSQR && o.lambda == 0.0 && o.precond != LSRN_PRECOND_QR && o.rcond == 0.0;
     }
 
     void finish(Request *r, lsrn_status s, const lsrn_info &info, const std::string &err) {

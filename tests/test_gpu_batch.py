@@ -158,10 +158,14 @@ def test_batch_padded_rows_equal_contiguous(L):
 def test_batch_rejections(L):
     P = workloads.dense_problem(500, 20, smin=1e-3, seed=6)
     A, b = dev(P.A), dev(workloads.rhs_gauss(500, 6))
-    for bad in (dict(method="chebyshev"), dict(lam=0.1), dict(precision="mixed")):
+    for bad in (dict(method="chebyshev"), dict(lam=0.1), dict(precond="qr")):
         with pytest.raises(L.LSRNError) as e:
             L.solve_batch([A], [b], **bad)
         assert e.value.status == 5
+    # the precision form is taken and computed in FP64: the same bits
+    x64, _ = L.solve_batch([A], [b], seed=3)
+    xmx, _ = L.solve_batch([A], [b], seed=3, precision="mixed")
+    np.testing.assert_array_equal(host(xmx[0]), host(x64[0]))
     Pw = workloads.dense_problem(2000, 600, smin=1e-3, seed=7)
     with pytest.raises(L.LSRNError) as e:
         L.solve_batch([dev(Pw.A)], [dev(workloads.rhs_gauss(2000, 7))])
