@@ -230,7 +230,7 @@ lsrn_status lsrn_server_create(int64_t hbm_budget_bytes, int32_t streams, lsrn_s
         }
         srv->budget = (size_t)hbm_budget_bytes;
         for (int i = 0; i < streams; ++i) srv->workers.emplace_back([srv] { srv->worker(); });
-        srv->workers.emplace_back([srv] { srv->batcher(); });
+        for (int i = 0; i < std::max(1, streams / 4); ++i) srv->workers.emplace_back([srv] { srv->batcher(); });
         *out = srv;
         return LSRN_OK;
     } catch (...) {
