@@ -423,6 +423,16 @@ lsrn_status solve_impl(bool tall, int64_t K, int64_t d, int64_t n, const TallVie
 }
 
 }  // namespace
+
+bool options_valid(const lsrn_options &o) {
+    try {
+        check_options(o);
+        return true;
+    } catch (const Error &) {
+        return false;
+    }
+}
+
 }  // namespace lsrn
 
 using namespace lsrn;

@@ -66,6 +66,8 @@ class DevBuf {
 // Stream for stream-ordered allocations of DevBufs made on this thread
 // (nullptr: plain hipMalloc / hipFree).
 void set_alloc_stream(hipStream_t s);
+// True when the options pass the checks every solve makes (no throw).
+bool options_valid(const lsrn_options &o);
 
 // Whether this thread may capture iteration chunks into HIP graphs (the
 // serving workers do not: a capture there can be invalidated by device-wide

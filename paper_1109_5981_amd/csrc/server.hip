@@ -73,9 +73,12 @@ struct lsrn_server {
     std::vector<std::thread> workers;
     static constexpr int kMaxBatch = 256;
 
+    // A request goes to the batcher only when the batched call would take
+    // it (valid options included): one bad request must not fail a batch.
     static bool batchable(const Request &r) {
         const lsrn_options &o = r.opt;
         return !r.csr && r.layout == LSRN_ROW_MAJOR && r.m >= r.n && r.n <= 512 && r.lda >= r.n &&
+               lsrn::options_valid(o) &&
                o.method == LSRN_LSQR && o.lambda == 0.0 && o.precond != LSRN_PRECOND_QR && o.rcond == 0.0;
     }
 
@@ -244,10 +247,10 @@ static lsrn_status enqueue(lsrn_server *srv, std::unique_ptr<lsrn_server::Reques
     r->id = srv->next_id++;
     r->t_submit = lsrn_server::now_ms();
     *ticket = r->id;
-    r->batch = lsrn_server::batchable(*r);
     (r->batch ? srv->pending_batch : srv->pending).push_back(r.get());
     srv->requests.emplace(r->id, std::move(r));
-    srv->cv_work.notify_one();
+    // workers and batchers wait on this condition for different queues
+    srv->cv_work.notify_all();
     return LSRN_OK;
 }
 
@@ -264,8 +267,10 @@ lsrn_status lsrn_server_submit_dense(lsrn_server *srv, int64_t m, int64_t n, con
     // share the device would be noise, and a new table entry would change
     // the summation order of later requests of the same shape
     r->opt.autotune = 0;
+    r->batch = lsrn_server::batchable(*r);
     r->bytes = lsrn_workspace_bytes(m, n, layout, &r->opt);
-    if (r->opt.precision == LSRN_PREC_MIXED) r->bytes += (size_t)m * (size_t)n * sizeof(float);
+    // the FP32 copy of A (the batched path computes in FP64 and makes none)
+    if (r->opt.precision == LSRN_PREC_MIXED && !r->batch) r->bytes += (size_t)m * (size_t)n * sizeof(float);
     return enqueue(srv, std::move(r), ticket);
 }
 

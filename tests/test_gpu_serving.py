@@ -152,8 +152,19 @@ def test_request_errors_are_per_request(L):
     with L.Server(hbm_budget_bytes=1 << 30, streams=2) as srv:
         good = srv.submit_dense(A, b)
         bad = srv.submit_dense(A, b, precision="mixed", method="chebyshev")
+        # an invalid request of the batcher's kind among valid ones: it
+        # fails alone, the others are batched and solved
+        goods = [srv.submit_dense(A, b, seed=s) for s in range(3)]
+        invalid = srv.submit_dense(A, b, tol=2.0)
+        goods += [srv.submit_dense(A, b, seed=s) for s in range(3, 6)]
         _, info, _ = srv.wait(good)
         assert info["rank"] == 20
         with pytest.raises(L.LSRNError) as e:
             srv.wait(bad)
         assert e.value.status == 5
+        with pytest.raises(L.LSRNError) as e:
+            srv.wait(invalid)
+        assert e.value.status == 1
+        for t in goods:
+            _, info, tm = srv.wait(t)
+            assert info["rank"] == 20 and tm["batch_size"] >= 1
