@@ -434,7 +434,7 @@ def batch_main(args):
     diff = max((torch.linalg.norm(a - c) / torch.linalg.norm(c)).item() for a, c in zip(xs, xs1))
     # the same batch with two refinement steps (double-double residuals, CG
     # corrections in shared launches), against the single solves refined
-    # the same way with the SVD preconditioner the batch forms
+    # the same way (the same automatic preconditioner choice)
     ropts = dict(opts, refine=2)
     lsrn.solve_batch(As, bs, allow_not_converged=True, **ropts)       # warm-up
     torch.cuda.synchronize()
@@ -442,7 +442,7 @@ def batch_main(args):
     xr, infos_r = lsrn.solve_batch(As, bs, allow_not_converged=True, **ropts)
     torch.cuda.synchronize()
     t_batch_r = time.perf_counter() - t0
-    xr1 = [lsrn.solve_dense(A, b, allow_not_converged=True, precond="svd", **ropts)[0]
+    xr1 = [lsrn.solve_dense(A, b, allow_not_converged=True, **ropts)[0]
            for A, b in zip(As, bs)]
     torch.cuda.synchronize()
     diff_r = max((torch.linalg.norm(a - c) / torch.linalg.norm(c)).item() for a, c in zip(xr, xr1))
