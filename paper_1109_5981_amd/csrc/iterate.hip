@@ -890,6 +890,80 @@ __device__ __forceinline__ void resid_dd_tall_body(const TT *__restrict__ T, int
     }
 }
 
+// h = T^T (b - T x) in double-double over the narrow-row layout of
+// sweep_narrow_body (LPR lanes a row, 8 columns a lane, L <= 8 LPR, lambda
+// = 0): a row's product T_j x is summed over its lanes in double-double
+// and taken from the row's first lane (so every lane uses the same bits),
+// each lane keeps the residual's contributions to its columns, and these
+// are summed over the rows of a wave (shuffles) and then over the waves in
+// wave order (LDS).  Offsets of T must fit in 31 bits, as for the sweep.
+template <int LPR>
+__device__ __forceinline__ void resid_dd_narrow_body(const double *__restrict__ T, int64_t ldt, int64_t rows,
+                                                     int L, int64_t rows_per_block,
+                                                     const double *__restrict__ b,
+                                                     const double *__restrict__ x,
+                                                     double *__restrict__ hpart_hi,
+                                                     double *__restrict__ hpart_lo, const int block,
+                                                     double (*__restrict__ rh)[8 * 64],
+                                                     double (*__restrict__ rl)[8 * 64]) {
+    constexpr int CPT = 8, RPW = 64 / LPR, NW = NT / 64, STEP = NW * RPW;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int sl = lane % LPR, rw = lane / LPR;
+    double xr[CPT];
+    dd zr[CPT];
+#pragma unroll
+    for (int e = 0; e < CPT; ++e) {
+        const int col = 2 * sl + 2 * LPR * (e >> 1) + (e & 1);
+        xr[e] = col < L ? x[col] : 0.0;
+        zr[e] = {0.0, 0.0};
+    }
+    const int64_t r0 = (int64_t)block * rows_per_block;
+    const int64_t r1 = min(rows, r0 + rows_per_block);
+    for (int64_t j0 = r0; j0 < r1; j0 += STEP) {
+        const int64_t row = j0 + wid * RPW + rw;
+        const bool valid = row < r1;
+        const double *__restrict__ trow = T + (valid ? row : r0) * ldt;
+        double av[CPT];
+        dd p = {0.0, 0.0};
+#pragma unroll
+        for (int e = 0; e < CPT; ++e) {
+            const int col = 2 * sl + 2 * LPR * (e >> 1) + (e & 1);
+            av[e] = (valid && col < L) ? trow[col] : 0.0;
+            p = dd_fma(p, av[e], xr[e]);
+        }
+#pragma unroll
+        for (int o = 1; o < LPR; o <<= 1) p = dd_add(p, dd{__shfl_xor(p.hi, o, 64), __shfl_xor(p.lo, o, 64)});
+        p.hi = __shfl(p.hi, rw * LPR, 64);
+        p.lo = __shfl(p.lo, rw * LPR, 64);
+        const dd res = valid ? dd_add(dd{b[row], 0.0}, dd{-p.hi, -p.lo}) : dd{0.0, 0.0};
+#pragma unroll
+        for (int e = 0; e < CPT; ++e) zr[e] = dd_fma_dd(zr[e], av[e], res);
+    }
+#pragma unroll
+    for (int o = LPR; o < 64; o <<= 1)
+#pragma unroll
+        for (int e = 0; e < CPT; ++e)
+            zr[e] = dd_add(zr[e], dd{__shfl_xor(zr[e].hi, o, 64), __shfl_xor(zr[e].lo, o, 64)});
+    if (rw == 0) {
+#pragma unroll
+        for (int e = 0; e < CPT; ++e) {
+            const int col = 2 * sl + 2 * LPR * (e >> 1) + (e & 1);
+            if (col < L) {
+                rh[wid][col] = zr[e].hi;
+                rl[wid][col] = zr[e].lo;
+            }
+        }
+    }
+    __syncthreads();
+    for (int col = tid; col < L; col += NT) {
+        dd t = {rh[0][col], rl[0][col]};
+#pragma unroll
+        for (int w = 1; w < NW; ++w) t = dd_add(t, dd{rh[w][col], rl[w][col]});
+        hpart_hi[(int64_t)block * L + col] = t.hi;
+        hpart_lo[(int64_t)block * L + col] = t.lo;
+    }
+}
+
 template <int CPT, typename TT>
 __global__ void __launch_bounds__(NT)
 resid_dd_tall_kernel(const TT *__restrict__ T, int64_t ldt, int64_t rows, int L, int nblocks,
@@ -2451,8 +2525,21 @@ batch_resid_kernel(const BatchItem *__restrict__ it, const int *__restrict__ off
     const int p = find_item(off, n, (int)blockIdx.x);
     const BatchItem &b = it[p];
     if (step >= b.refine) return;
-    resid_dd_tall_body<BCPT, double>(b.sw.T, b.sw.ldt, b.sw.rows, b.sw.L, b.sw.nblocks, b.sw.rows_per_block,
-                                     b.bvec, b.x, 0.0, b.hhi, b.hlo, (int)blockIdx.x - off[p]);
+    const int blk = (int)blockIdx.x - off[p];
+    const SweepArgs &a = b.sw;
+    __shared__ double rh[NT / 64][8 * 64], rl[NT / 64][8 * 64];  // the narrow bodies' wave sums
+    switch (b.lpr) {
+        case 2: resid_dd_narrow_body<2>(a.T, a.ldt, a.rows, a.L, a.rows_per_block, b.bvec, b.x, b.hhi, b.hlo, blk, rh, rl); break;
+        case 4: resid_dd_narrow_body<4>(a.T, a.ldt, a.rows, a.L, a.rows_per_block, b.bvec, b.x, b.hhi, b.hlo, blk, rh, rl); break;
+        case 8: resid_dd_narrow_body<8>(a.T, a.ldt, a.rows, a.L, a.rows_per_block, b.bvec, b.x, b.hhi, b.hlo, blk, rh, rl); break;
+        case 16: resid_dd_narrow_body<16>(a.T, a.ldt, a.rows, a.L, a.rows_per_block, b.bvec, b.x, b.hhi, b.hlo, blk, rh, rl); break;
+        case 32: resid_dd_narrow_body<32>(a.T, a.ldt, a.rows, a.L, a.rows_per_block, b.bvec, b.x, b.hhi, b.hlo, blk, rh, rl); break;
+        case 64: resid_dd_narrow_body<64>(a.T, a.ldt, a.rows, a.L, a.rows_per_block, b.bvec, b.x, b.hhi, b.hlo, blk, rh, rl); break;
+        default:
+            resid_dd_tall_body<BCPT, double>(a.T, a.ldt, a.rows, a.L, a.nblocks, a.rows_per_block, b.bvec, b.x, 0.0,
+                                             b.hhi, b.hlo, blk);
+            break;
+    }
 }
 
 // h = the double-double sum of the row-block partials, rounded.
