@@ -364,8 +364,14 @@ lsrn_status lsrn_iterate_csr(int64_t m, int64_t n, int64_t nnz, const int64_t *r
  * refinement steps follow the same way (the double-double residual
  * A^T (b - A x) of every problem, then CG on the preconditioned normal
  * equations to opt->refine_tol for all problems together, x += N z; as in
- * lsrn_solve_dense).  One option set for all problems; LSQR only,
- * lambda = 0, precond AUTO or SVD (LSRN_E_UNSUPPORTED otherwise).  The
+ * lsrn_solve_dense).  One option set for all problems.  Chebyshev
+ * problems (Alg. 3) run their steps for all of them in shared launches
+ * first (the LSQR problems waiting), each with its own schedule from its
+ * bounds, then the check of lsrn_solve_dense (cs_fallbacks = 1 and an LSQR
+ * restart where it fails), then the LSQR problems and the restarts
+ * together; LSRN_E_UNSUPPORTED for the whole call if a Chebyshev problem's
+ * bounds do not hold (sqrt(s) - sqrt(r) - t_margin <= 0).  lambda = 0,
+ * precond AUTO or SVD (LSRN_E_UNSUPPORTED otherwise).  The
  * batched path computes in FP64 only: a problem that asks for
  * LSRN_PREC_MIXED is solved exactly as with LSRN_PREC_FP64 (the precision
  * form's result is the FP64 answer its refinement reaches; for problems

@@ -872,8 +872,8 @@ static lsrn_status solve_batch_body(int32_t count, const int64_t *m, const int64
         const lsrn_options &opt = ov[(size_t)p];
         check_options(opt);
         // the precision form is accepted and runs in FP64 like the rest
-        if (opt.method != LSRN_LSQR || opt.lambda != 0.0 || opt.precond == LSRN_PRECOND_QR)
-            fail(LSRN_E_UNSUPPORTED, "the batched path runs LSQR with the automatic or SVD preconditioner, "
+        if (opt.lambda != 0.0 || opt.precond == LSRN_PRECOND_QR)
+            fail(LSRN_E_UNSUPPORTED, "the batched path runs with the automatic or SVD preconditioner, "
                                      "without lambda");
         // the preconditioners of the batch are formed together with one cutoff
         LSRN_REQUIRE(opt.rcond == ov[0].rcond, "batched problems need the same rcond");
@@ -962,6 +962,7 @@ static lsrn_status solve_batch_body(int32_t count, const int64_t *m, const int64
         in.s = ss[(size_t)p]; in.d = n[p]; in.rank = prs[(size_t)p].rank;
         in.iters = full[(size_t)p].iters; in.sweeps = prs[(size_t)p].sweeps; in.tall = 1;
         in.refine_steps = full[(size_t)p].refine_steps; in.refine_iters = full[(size_t)p].refine_iters;
+        in.cs_fallbacks = full[(size_t)p].cs_fallbacks;
         in.precond_used = prs[(size_t)p].full_rank_inverse ? LSRN_PRECOND_QR : LSRN_PRECOND_SVD;
         in.converged = full[(size_t)p].converged;
         in.sigma_l = full[(size_t)p].sigma_l; in.sigma_u = full[(size_t)p].sigma_u;

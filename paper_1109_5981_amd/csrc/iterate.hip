@@ -2380,6 +2380,12 @@ struct BatchItem {
     double *hhi, *hlo, *h, *c, *zc, *rc, *pc;
     double rtol;
     int refine;  // this problem's refinement steps (its buffers exist only if > 0)
+    // Chebyshev (Alg. 3): cs = 1, the run's ncs steps (alpha_k at sched[k],
+    // beta_k at sched[ncs + k]), the iterate kept for an LSQR restart, and
+    // csn = {|N^T A^T b|, |N^T A^T r| after the run, |b|} for the check
+    int cs, ncs;
+    const double *sched;
+    double *ycs, *csn;
 };
 
 __device__ __forceinline__ int find_item(const int *__restrict__ off, int n, int g) {
@@ -2587,7 +2593,106 @@ __global__ void __launch_bounds__(SNT) batch_cg_step_kernel(const BatchItem *__r
 
 __global__ void __launch_bounds__(SNT) batch_init_kernel(const BatchItem *__restrict__ it) {
     const BatchItem &b = it[blockIdx.x];
+    if (b.sw.st->done) return;  // parked: a Chebyshev run that passed its check
     lsqr_tall_init_body(b.t, b.r, b.v, b.wdir, b.yv, b.sw.st);
+}
+
+// Start of the Chebyshev phase (t = N^T A^T b already formed): for a
+// Chebyshev problem v = y = 0, csn[0] = |t|, csn[2] = |b|; an LSQR problem
+// is parked (done) until the LSQR phase.
+__global__ void __launch_bounds__(SNT) batch_cs_begin_kernel(const BatchItem *__restrict__ it) {
+    __shared__ double scratch[SNT / 64];
+    const BatchItem &b = it[blockIdx.x];
+    if (!b.cs) {
+        if (threadIdx.x == 0) b.sw.st->done = 1;
+        return;
+    }
+    double g = 0.0, q = 0.0;
+    for (int64_t i = threadIdx.x; i < b.r; i += SNT) {
+        b.v[i] = 0.0;
+        b.yv[i] = 0.0;
+        g += b.t[i] * b.t[i];
+    }
+    for (int64_t j = threadIdx.x; j < b.sw.rows; j += SNT) q += b.sw.y[j] * b.sw.y[j];
+    g = block_sum<SNT>(g, scratch);
+    q = block_sum<SNT>(q, scratch);
+    if (threadIdx.x == 0) {
+        b.csn[0] = sqrt(g);
+        b.csn[2] = sqrt(q);
+        b.sw.st->iters = 0;
+        b.sw.st->done = 0;
+    }
+}
+
+// Step k of a Chebyshev run (k = the steps done, from its state): v =
+// beta_k v + t, y += alpha_k v, and alpha_k handed to this step's sweep.
+__global__ void __launch_bounds__(SNT) batch_cs_short_kernel(const BatchItem *__restrict__ it) {
+    const BatchItem &b = it[blockIdx.x];
+    if (b.sw.st->done) return;
+    const int k = b.sw.st->iters;
+    const double al = b.sched[k], be = b.sched[b.ncs + k];
+    for (int64_t i = threadIdx.x; i < b.r; i += SNT) {
+        const double vi = be * b.v[i] + b.t[i];
+        b.v[i] = vi;
+        b.yv[i] += al * vi;
+    }
+    if (threadIdx.x == 0) const_cast<BatchItem *>(it)[blockIdx.x].sw.alpha = al;
+}
+
+// After a Chebyshev step's products: one more step done; the last one ends
+// the run (t then holds N^T A^T r for the check).
+__global__ void batch_cs_step_kernel(const BatchItem *__restrict__ it) {
+    const BatchItem &b = it[blockIdx.x];
+    State *s = b.sw.st;
+    if (s->done) return;
+    const int k = s->iters + 1;
+    s->iters = k;
+    if (k >= b.ncs) {
+        s->done = 1;
+        s->converged = 1;
+    }
+}
+
+// csn[1] = |t| = |N^T A^T r| after a Chebyshev run.
+__global__ void __launch_bounds__(SNT) batch_cs_norm_kernel(const BatchItem *__restrict__ it) {
+    __shared__ double scratch[SNT / 64];
+    const BatchItem &b = it[blockIdx.x];
+    if (!b.cs) return;
+    double g = 0.0;
+    for (int64_t i = threadIdx.x; i < b.r; i += SNT) g += b.t[i] * b.t[i];
+    g = block_sum<SNT>(g, scratch);
+    if (threadIdx.x == 0) b.csn[1] = sqrt(g);
+}
+
+// The LSQR phase's start for each problem, by mode: 0 parks it (a
+// Chebyshev run that passed its check), 1 starts LSQR on b (an LSQR
+// problem), 2 on the Chebyshev residual r (the long vector) after keeping
+// y, 3 on b again with the Chebyshev iterate dropped (a divergent run).
+__global__ void __launch_bounds__(SNT) batch_lsqr_phase_kernel(const BatchItem *__restrict__ it,
+                                                               const int *__restrict__ maxit,
+                                                               const int *__restrict__ mode) {
+    const BatchItem &b = it[blockIdx.x];
+    const int md = mode[blockIdx.x];
+    if (md == 0) return;
+    if (md == 2)
+        for (int64_t i = threadIdx.x; i < b.r; i += SNT) b.ycs[i] = b.yv[i];
+    if (md == 3) {
+        for (int64_t i = threadIdx.x; i < b.r; i += SNT) b.ycs[i] = 0.0;
+        for (int64_t j = threadIdx.x; j < b.sw.rows; j += SNT) b.sw.y[j] = b.bvec[j];
+    }
+    if (threadIdx.x == 0) {
+        State z = {};
+        z.maxiter = maxit[blockIdx.x];
+        *b.sw.st = z;
+    }
+}
+
+// y += the kept Chebyshev iterate, for the restarted problems (mode 2, 3).
+__global__ void __launch_bounds__(SNT) batch_cs_finish_kernel(const BatchItem *__restrict__ it,
+                                                              const int *__restrict__ mode) {
+    const BatchItem &b = it[blockIdx.x];
+    if (mode[blockIdx.x] < 2) return;
+    for (int64_t i = threadIdx.x; i < b.r; i += SNT) b.yv[i] += b.ycs[i];
 }
 
 __global__ void __launch_bounds__(SNT) batch_step_kernel(const BatchItem *__restrict__ it) {
@@ -2628,7 +2733,30 @@ std::vector<IterResult> iterate_batch_tall(const std::vector<IterProblem> &pbs,
         pool_elems += carve(nb * L) + carve(nb * 4) + carve((size_t)pb.rows) + carve(L) + carve(r * L) +
                       4 * carve(r) + carve(L);
         if (opts[(size_t)p].refine > 0) pool_elems += 2 * carve(nb * L) + carve(L) + 4 * carve(r);
+        if (opts[(size_t)p].method == LSRN_CHEBYSHEV) pool_elems += carve(r) + carve(3);
     }
+    // Chebyshev schedules (Alg. 3 from each problem's bounds, Theorem 3)
+    std::vector<double> sched_h;
+    std::vector<size_t> sched_off((size_t)n, 0);
+    std::vector<int> ncs((size_t)n, 0);
+    bool any_cs = false;
+    for (int p = 0; p < n; ++p) {
+        if (opts[(size_t)p].method != LSRN_CHEBYSHEV) continue;
+        double sl = 0.0, su = 0.0;
+        (void)default_maxiter(pbs[(size_t)p], opts[(size_t)p], sl, su);
+        if (su <= 0.0) fail(LSRN_E_UNSUPPORTED, "Chebyshev bounds need sqrt(s) - sqrt(r) - t > 0");
+        std::vector<double> al, be;
+        cs_schedule(sl, su, opts[(size_t)p].tol, al, be);
+        sched_off[(size_t)p] = sched_h.size();
+        ncs[(size_t)p] = (int)al.size();
+        sched_h.insert(sched_h.end(), al.begin(), al.end());
+        sched_h.insert(sched_h.end(), be.begin(), be.end());
+        any_cs = true;
+    }
+    DevBuf dsched(sched_h.size() * sizeof(double));
+    if (!sched_h.empty())
+        LSRN_HIP(hipMemcpyAsync(dsched.as<double>(), sched_h.data(), sched_h.size() * sizeof(double),
+                                hipMemcpyHostToDevice, st));
     DevBuf pool(pool_elems * sizeof(double));
     size_t pool_used = 0;
     auto buf = [&](size_t elems) {
@@ -2679,6 +2807,16 @@ std::vector<IterResult> iterate_batch_tall(const std::vector<IterProblem> &pbs,
         maxit[(size_t)p] = (int)default_maxiter(pb, opt, sl, su);
         res[(size_t)p].sigma_l = sl;
         res[(size_t)p].sigma_u = su;
+        if (opt.method == LSRN_CHEBYSHEV) {
+            // an LSQR restart after a failed check gets a cap not taken from
+            // the bounds the check found wrong (as in the one-problem solve)
+            maxit[(size_t)p] = (int)(opt.max_iter > 0 ? opt.max_iter : 4 * (int64_t)maxit[(size_t)p]);
+            b.cs = 1;
+            b.ncs = ncs[(size_t)p];
+            b.sched = dsched.as<double>() + sched_off[(size_t)p];
+            b.ycs = buf((size_t)r);
+            b.csn = buf(3);
+        }
         off_sw[(size_t)p + 1] = off_sw[(size_t)p] + nblocks;
         off_red[(size_t)p + 1] = off_red[(size_t)p] + (int)ceil_div(L, (int64_t)B_RED_COLS);
         off_gP[(size_t)p + 1] = off_gP[(size_t)p] + (int)ceil_div(L, 4);
@@ -2707,7 +2845,6 @@ std::vector<IterResult> iterate_batch_tall(const std::vector<IterProblem> &pbs,
     batch_sweep_kernel<OP_ATB><<<off_sw[(size_t)n], NT, 0, st>>>(di, o_sw, n);
     batch_reduce_kernel<<<off_red[(size_t)n], 256, 0, st>>>(di, o_red, n);
     batch_gemv_kernel<<<off_gPt[(size_t)n], 256, 0, st>>>(di, o_gPt, n, 1);
-    batch_init_kernel<<<n, SNT, 0, st>>>(di);
     LSRN_HIP(hipGetLastError());
     std::vector<State> hs((size_t)n);
     auto all_done = [&] {
@@ -2718,7 +2855,20 @@ std::vector<IterResult> iterate_batch_tall(const std::vector<IterProblem> &pbs,
             if (!h.done) return false;
         return true;
     };
-    hipGraphExec_t exec = nullptr, exec_cg = nullptr;
+    hipGraphExec_t exec = nullptr, exec_cg = nullptr, exec_cs = nullptr;
+    // Chebyshev steps (Alg. 3) for every Chebyshev problem, the LSQR ones
+    // parked; each problem's step index is its state's count
+    auto chunk_cs = [&] {
+        for (int k = 0; k < CHUNK; ++k) {
+            batch_cs_short_kernel<<<n, SNT, 0, st>>>(di);
+            batch_gemv_kernel<<<off_gP[(size_t)n], 256, 0, st>>>(di, o_gP, n, 0);
+            batch_sweep_kernel<OP_CS_TALL><<<off_sw[(size_t)n], NT, 0, st>>>(di, o_sw, n);
+            batch_reduce_kernel<<<off_red[(size_t)n], 256, 0, st>>>(di, o_red, n);
+            batch_gemv_kernel<<<off_gPt[(size_t)n], 256, 0, st>>>(di, o_gPt, n, 1);
+            batch_cs_step_kernel<<<n, 1, 0, st>>>(di);
+        }
+        LSRN_HIP(hipGetLastError());
+    };
     auto chunk = [&] {
         for (int k = 0; k < CHUNK; ++k) {
             batch_gemv_kernel<<<off_gP[(size_t)n], 256, 0, st>>>(di, o_gP, n, 0);
@@ -2766,13 +2916,72 @@ std::vector<IterResult> iterate_batch_tall(const std::vector<IterProblem> &pbs,
             }
         }
     };
-    std::vector<int64_t> iters_main((size_t)n), refine_iters((size_t)n, 0);
+    std::vector<int64_t> iters_main((size_t)n), refine_iters((size_t)n, 0), cs_iters((size_t)n, 0);
     std::vector<bool> conv_main((size_t)n);
+    // LSQR phase per problem: 0 parked (Chebyshev run passed its check), 1
+    // LSQR, 2 LSQR restart on the Chebyshev residual, 3 restart on b
+    std::vector<int> mode((size_t)n, 1);
+    DevBuf dmode((size_t)n * sizeof(int));
+    bool restarts = false;
     try {
+        if (any_cs) {
+            batch_cs_begin_kernel<<<n, SNT, 0, st>>>(di);
+            LSRN_HIP(hipGetLastError());
+            run_until_done(exec_cs, chunk_cs);
+            batch_cs_norm_kernel<<<n, SNT, 0, st>>>(di);
+            LSRN_HIP(hipGetLastError());
+            // the check of each run (as in the one-problem solve): |N^T A^T r|
+            // against |N^T A^T b|; a failed run restarts LSQR from its
+            // iterate, or from zero if its residual grew beyond |b|
+            std::vector<double> csn((size_t)3 * n, 0.0);
+            for (int p = 0; p < n; ++p)
+                if (items[(size_t)p].cs)
+                    LSRN_HIP(hipMemcpyAsync(csn.data() + 3 * p, items[(size_t)p].csn, 3 * sizeof(double),
+                                            hipMemcpyDeviceToHost, st));
+            LSRN_HIP(hipStreamSynchronize(st));
+            bool lsqr_left = false;
+            for (int p = 0; p < n; ++p) {
+                if (!items[(size_t)p].cs) {
+                    lsqr_left = true;
+                    continue;
+                }
+                cs_iters[(size_t)p] = hs[(size_t)p].iters;
+                const double g0 = csn[(size_t)3 * p], gn = csn[(size_t)3 * p + 1], bn = csn[(size_t)3 * p + 2];
+                if (cs_passes(gn, g0, opts[(size_t)p].tol)) {
+                    mode[(size_t)p] = 0;
+                    continue;
+                }
+                const double rn = std::sqrt(std::max(0.0, hs[(size_t)p].acc[0]));
+                mode[(size_t)p] = (std::isfinite(rn) && rn <= bn) ? 2 : 3;
+                res[(size_t)p].cs_fallbacks = 1;
+                restarts = lsqr_left = true;
+            }
+            LSRN_HIP(hipMemcpyAsync(dmode.as<int>(), mode.data(), (size_t)n * sizeof(int), hipMemcpyHostToDevice,
+                                    st));
+            batch_lsqr_phase_kernel<<<n, SNT, 0, st>>>(di, o_max, dmode.as<int>());
+            if (lsqr_left) {
+                // t = N^T A^T (the right-hand side) again for the problems
+                // that run LSQR (the same bits for an LSQR problem: its b is
+                // untouched), then their LSQR start
+                batch_sweep_kernel<OP_ATB><<<off_sw[(size_t)n], NT, 0, st>>>(di, o_sw, n);
+                batch_reduce_kernel<<<off_red[(size_t)n], 256, 0, st>>>(di, o_red, n);
+                batch_gemv_kernel<<<off_gPt[(size_t)n], 256, 0, st>>>(di, o_gPt, n, 1);
+                batch_init_kernel<<<n, SNT, 0, st>>>(di);
+            }
+            LSRN_HIP(hipGetLastError());
+        } else {
+            batch_init_kernel<<<n, SNT, 0, st>>>(di);
+            LSRN_HIP(hipGetLastError());
+        }
         run_until_done(exec, chunk);
         for (int p = 0; p < n; ++p) {
-            iters_main[(size_t)p] = hs[(size_t)p].iters;
-            conv_main[(size_t)p] = hs[(size_t)p].converged != 0;
+            const bool passed = mode[(size_t)p] == 0;
+            iters_main[(size_t)p] = cs_iters[(size_t)p] + (passed ? 0 : hs[(size_t)p].iters);
+            conv_main[(size_t)p] = passed || hs[(size_t)p].converged != 0;
+        }
+        if (restarts) {
+            batch_cs_finish_kernel<<<n, SNT, 0, st>>>(di, dmode.as<int>());
+            LSRN_HIP(hipGetLastError());
         }
         batch_gemv_kernel<<<off_gP[(size_t)n], 256, 0, st>>>(di, o_gP, n, 2);
         LSRN_HIP(hipGetLastError());
@@ -2792,11 +3001,13 @@ std::vector<IterResult> iterate_batch_tall(const std::vector<IterProblem> &pbs,
     } catch (...) {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (exec_cg) (void)hipGraphExecDestroy(exec_cg);
+        if (exec_cs) (void)hipGraphExecDestroy(exec_cs);
         (void)hipStreamSynchronize(st);
         throw;
     }
     if (exec) (void)hipGraphExecDestroy(exec);
     if (exec_cg) (void)hipGraphExecDestroy(exec_cg);
+    if (exec_cs) (void)hipGraphExecDestroy(exec_cs);
     LSRN_HIP(hipEventRecord(e1, st));
     LSRN_HIP(hipEventSynchronize(e1));
     float ms = 0.f;

@@ -14,10 +14,11 @@
 // depend on what else is running.
 //
 // Requests the batched path covers (dense row-major over-determined LSQR
-// with n <= 512, lambda = 0 and the default rank cutoff; the precision
-// form's requests among them run in FP64 there) queue apart:
-// one batcher thread, on a stream of its own, takes all of them that are
-// waiting when it is free (up to kMaxBatch, within the budget) and solves
+// or Chebyshev with n <= 512, lambda = 0 and the default rank cutoff; the
+// precision form's requests among them run in FP64 there) queue apart:
+// batcher threads (one per four worker streams), each on a stream of its
+// own, take all of them that are waiting when free (up to kMaxBatch,
+// within the budget) and solve
 // them together with lsrn_solve_batch_opts, so that the iterations of
 // requests that arrived close together advance in shared launches.  A
 // batched request's result equals the same request batched alone.
@@ -25,6 +26,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -77,9 +79,15 @@ struct lsrn_server {
     // it (valid options included): one bad request must not fail a batch.
     static bool batchable(const Request &r) {
         const lsrn_options &o = r.opt;
-        return !r.csr && r.layout == LSRN_ROW_MAJOR && r.m >= r.n && r.n <= 512 && r.lda >= r.n &&
-               lsrn::options_valid(o) &&
-               o.method == LSRN_LSQR && o.lambda == 0.0 && o.precond != LSRN_PRECOND_QR && o.rcond == 0.0;
+        if (r.csr || r.layout != LSRN_ROW_MAJOR || r.m < r.n || r.n > 512 || r.lda < r.n ||
+            !lsrn::options_valid(o) || o.lambda != 0.0 || o.precond == LSRN_PRECOND_QR || o.rcond != 0.0)
+            return false;
+        if (o.method == LSRN_CHEBYSHEV) {
+            // the bounds must hold at full rank (a failure would fail the batch)
+            const double s = std::ceil(o.gamma * (double)r.n);
+            return std::sqrt(s) - std::sqrt((double)r.n) - o.t_margin > 0.0;
+        }
+        return true;
     }
 
     void finish(Request *r, lsrn_status s, const lsrn_info &info, const std::string &err) {

@@ -133,6 +133,48 @@ def test_batch_per_problem_options(L, orc):
     assert not np.array_equal(host(xo[0]), host(xs[1]))
 
 
+def test_batch_chebyshev_with_lsqr(L, orc):
+    """Chebyshev problems (Alg. 3) batched with LSQR ones.  A Chebyshev
+    problem runs the schedule of the one-problem solve (same sketch, bounds
+    and step count) and agrees with it to rounding; forced bound failures
+    (t_margin = -4, as in the one-problem test) fail the check, restart LSQR
+    and still converge, as alone; refined ones are within 1e-10 of the
+    oracle.  Every problem gives the bits of itself batched alone, and the
+    LSQR problems the bits of an LSQR-only batch."""
+    rng = np.random.default_rng(41)
+    As, bs, hostA = [], [], []
+    for i, n in enumerate([24, 64, 130, 257, 512, 60, 200]):
+        m = int(rng.integers(3 * n + 300, 7000))
+        P = workloads.dense_problem(m, n, smin=10.0 ** -(2 + i % 4), seed=1400 + i)
+        b = workloads.rhs_gauss(m, 1400 + i)
+        As.append(dev(P.A)); bs.append(dev(b)); hostA.append((P.A, b))
+    opts = [dict(method="chebyshev", seed=3), dict(seed=4), dict(method="chebyshev", seed=5, refine=2),
+            dict(method="chebyshev", seed=6, tol=1e-10), dict(seed=7, refine=1),
+            dict(method="chebyshev", seed=8, t_margin=-4.0),
+            dict(method="chebyshev", seed=9, t_margin=-4.0, refine=2)]
+    xs, infos = L.solve_batch(As, bs, per_problem=opts)
+    for k, o in enumerate(opts):
+        cs = o.get("method") == "chebyshev"
+        x1, i1 = L.solve_batch([As[k]], [bs[k]], per_problem=[o])
+        np.testing.assert_array_equal(host(x1[0]), host(xs[k]))
+        assert i1[0]["iters"] == infos[k]["iters"] and infos[k]["converged"]
+        if cs:
+            xl, il = L.solve_dense(As[k], bs[k], **o)
+            assert infos[k]["cs_fallbacks"] == il["cs_fallbacks"], k
+            if not il["cs_fallbacks"]:
+                assert infos[k]["iters"] == il["iters"], k
+            assert rel(host(xs[k]), host(xl)) < 1e-9, k
+        if o.get("refine", 0):
+            A, b = hostA[k]
+            ref = orc.lsrn_solve(orc.Matrix.dense(A), b, seed=1, method=orc.CS if cs else orc.LSQR, refine=3).x
+            assert rel(host(xs[k]), ref) <= 1e-10, k
+    assert [i["cs_fallbacks"] for i in infos] == [0, 0, 0, 0, 0, 1, 1]
+    lq = [1, 4]
+    xq, _ = L.solve_batch([As[k] for k in lq], [bs[k] for k in lq], per_problem=[opts[k] for k in lq])
+    for j, k in enumerate(lq):
+        np.testing.assert_array_equal(host(xq[j]), host(xs[k]))
+
+
 def test_batch_padded_rows_equal_contiguous(L):
     """Problems given with an odd leading dimension (element loads in the
     batched sketch and sweeps) give bit for bit the batch result of the
@@ -158,10 +200,15 @@ def test_batch_padded_rows_equal_contiguous(L):
 def test_batch_rejections(L):
     P = workloads.dense_problem(500, 20, smin=1e-3, seed=6)
     A, b = dev(P.A), dev(workloads.rhs_gauss(500, 6))
-    for bad in (dict(method="chebyshev"), dict(lam=0.1), dict(precond="qr")):
+    for bad in (dict(lam=0.1), dict(precond="qr")):
         with pytest.raises(L.LSRNError) as e:
             L.solve_batch([A], [b], **bad)
         assert e.value.status == 5
+    # Chebyshev whose bounds cannot hold (n = 4: sqrt(8) - sqrt(4) - 1 < 0)
+    P4 = workloads.dense_problem(300, 4, smin=1e-2, seed=8)
+    with pytest.raises(L.LSRNError) as e:
+        L.solve_batch([dev(P4.A)], [dev(workloads.rhs_gauss(300, 8))], method="chebyshev")
+    assert e.value.status == 5
     # the precision form is taken and computed in FP64: the same bits
     x64, _ = L.solve_batch([A], [b], seed=3)
     xmx, _ = L.solve_batch([A], [b], seed=3, precision="mixed")

@@ -76,10 +76,10 @@ def oracle_ref(orc, spec, b, lam):
 
 def batchable(kind, opts):
     """The requests the server's batcher takes (the batched path's scope:
-    dense row-major over-determined LSQR, n <= 512, no lambda; precision-form
-    requests run in FP64 there)."""
-    return (kind == "dense" and opts.get("layout", 0) == 0 and opts.get("method", "lsqr") == "lsqr"
-            and opts.get("lam", 0.0) == 0.0)
+    dense row-major over-determined LSQR or Chebyshev, n <= 512, no lambda;
+    precision-form requests run in FP64 there; every request of the mix is
+    wide enough for the Chebyshev bounds)."""
+    return (kind == "dense" and opts.get("layout", 0) == 0 and opts.get("lam", 0.0) == 0.0)
 
 
 def solve_alone(L, kind, A, b, opts):
@@ -102,7 +102,7 @@ def test_results_alone_equal_results_in_mix(L, orc):
     (FP64 requests refined three steps; precision-form requests refined to
     their FP64 answer)."""
     reqs = mix(L)
-    assert sum(batchable(kind, o) for kind, _, _, o, _ in reqs) == 5   # both queues are used
+    assert sum(batchable(kind, o) for kind, _, _, o, _ in reqs) == 6   # both queues are used
     L.tune_clear()
     alone = [solve_alone(L, kind, A, b, {k: v for k, v in o.items() if k != "autotune"})[0]
              for kind, A, b, o, _ in reqs]
