@@ -120,10 +120,18 @@ struct lsrn_server {
                     return in_use + pending_batch.front()->bytes <= budget || running == 0;
                 });
                 if (pending_batch.empty()) break;
-                while (!pending_batch.empty() && (int)batch.size() < kMaxBatch) {
-                    Request *r = pending_batch.front();
+                // one method a batch: a batch runs its Chebyshev steps before
+                // its LSQR iterations, so mixing the two would hold the LSQR
+                // requests back; the others wait for the next batch (in order)
+                const int32_t method = pending_batch.front()->opt.method;
+                for (auto it = pending_batch.begin(); it != pending_batch.end() && (int)batch.size() < kMaxBatch;) {
+                    Request *r = *it;
+                    if (r->opt.method != method) {
+                        ++it;
+                        continue;
+                    }
                     if (!(in_use + r->bytes <= budget || (batch.empty() && running == 0))) break;
-                    pending_batch.pop_front();
+                    it = pending_batch.erase(it);
                     in_use += r->bytes;
                     ++running;
                     r->t_start = now_ms();
