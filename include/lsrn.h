@@ -524,7 +524,15 @@ void lsrn_plan_destroy(lsrn_plan *plan);
  * in `hbm_budget_bytes` next to the solves already running; a request
  * larger than the budget runs alone.  Admitted solves overlap on the device
  * and each runs exactly the kernels of lsrn_solve_dense / lsrn_solve_csr,
- * so its result equals that of the same call made alone.  Served requests
+ * so its result equals that of the same call made alone.  Requests that
+ * lsrn_solve_batch_opts covers (dense row-major, m >= n, n <= 512, valid
+ * options, lambda = 0, precond AUTO or SVD, rcond 0; Chebyshev ones only
+ * when their bounds hold at full rank) queue apart instead: max(1,
+ * streams / 4) batcher threads, each on a stream of its own, take the
+ * waiting ones of one method (up to 256, within the budget, without the
+ * FP32 copy: the batched path computes in FP64) and solve them in one
+ * lsrn_solve_batch_opts call, so each such result equals that of the same
+ * request batched alone (lsrn_server_timing.batch_size reports the batch).  Served requests
  * never tune launch shapes (opt.autotune is ignored; recorded shapes are
  * used): timings taken while other solves share the device are noise, and
  * a new table entry would change the summation order of later requests.
