@@ -528,7 +528,7 @@ void lsrn_plan_destroy(lsrn_plan *plan);
  * lsrn_solve_batch_opts covers (dense row-major, m >= n, n <= 512, valid
  * options, lambda = 0, precond AUTO or SVD, rcond 0; Chebyshev ones only
  * when their bounds hold at full rank) queue apart instead: max(1,
- * streams / 4) batcher threads, each on a stream of its own, take the
+ * streams / 2) batcher threads, each on a stream of its own, take the
  * waiting ones of one method (up to 256, within the budget, without the
  * FP32 copy: the batched path computes in FP64) and solve them in one
  * lsrn_solve_batch_opts call, so each such result equals that of the same

@@ -16,7 +16,7 @@
 // Requests the batched path covers (dense row-major over-determined LSQR
 // or Chebyshev with n <= 512, lambda = 0 and the default rank cutoff; the
 // precision form's requests among them run in FP64 there) queue apart:
-// batcher threads (one per four worker streams), each on a stream of its
+// batcher threads (one per two worker streams), each on a stream of its
 // own, take all of them that are waiting when free (up to kMaxBatch,
 // within the budget) and solve
 // them together with lsrn_solve_batch_opts, so that the iterations of
@@ -249,7 +249,7 @@ lsrn_status lsrn_server_create(int64_t hbm_budget_bytes, int32_t streams, lsrn_s
         }
         srv->budget = (size_t)hbm_budget_bytes;
         for (int i = 0; i < streams; ++i) srv->workers.emplace_back([srv] { srv->worker(); });
-        for (int i = 0; i < std::max(1, streams / 4); ++i) srv->workers.emplace_back([srv] { srv->batcher(); });
+        for (int i = 0; i < std::max(1, streams / 2); ++i) srv->workers.emplace_back([srv] { srv->batcher(); });
         *out = srv;
         return LSRN_OK;
     } catch (...) {
