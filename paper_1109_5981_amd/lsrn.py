@@ -360,17 +360,23 @@ class Csr:
                 self.val.data_ptr())
 
 
-def solve_csr(A: Csr, b: torch.Tensor, x: torch.Tensor | None = None, **opts):
-    """lsrn_solve_csr: min-length LS solution for CSR A.  Returns (x, info)."""
+def solve_csr(A: Csr, b: torch.Tensor, x: torch.Tensor | None = None, *,
+              allow_not_converged: bool = False, **opts):
+    """lsrn_solve_csr: min-length LS solution for CSR A.  Returns (x, info).
+    With allow_not_converged, LSRN_E_NOT_CONVERGED returns the last iterate
+    with info["status"] = 4 instead of raising."""
     _dev_f64(b, "b")
     if b.numel() != A.m or not b.is_contiguous():
         raise ValueError("b must be contiguous with m entries")
     if x is None:
         x = torch.empty(A.n, dtype=torch.float64, device=b.device)
     o, info = options(**opts), Info()
-    _check(lib().lsrn_solve_csr(*A.args(), b.data_ptr(), x.data_ptr(), C.byref(o), C.byref(info),
-                                _stream()))
-    return x, info.as_dict()
+    st = lib().lsrn_solve_csr(*A.args(), b.data_ptr(), x.data_ptr(), C.byref(o), C.byref(info), _stream())
+    if not (allow_not_converged and st == 4):
+        _check(st)
+    out = info.as_dict()
+    out["status"] = int(st)
+    return x, out
 
 
 def workspace_bytes_csr(m: int, n: int, nnz: int, **opts) -> int:

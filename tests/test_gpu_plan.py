@@ -63,11 +63,15 @@ def test_plan_csr_matches_solve_csr(L):
     opts = dict(seed=4, lam=1e-3, refine=1)
     plan = L.Plan.csr(A, **opts)
     rng = np.random.default_rng(8)
+    keys = ("status", "rank", "iters", "refine_iters", "precond_used", "sigma_max", "sigma_min_kept")
     for k in range(2):
         b = dev(rng.standard_normal(S.m))
-        x1, _ = plan.solve(b)
-        x2, _ = L.solve_csr(A, b, **opts)
-        assert np.array_equal(host(x1), host(x2))
+        x1, i1 = plan.solve(b, allow_not_converged=True)
+        x2, i2 = L.solve_csr(A, b, allow_not_converged=True, **opts)
+        # both infos in the message, so that a failure shows which stage differs
+        diag = {"plan": {q: i1.get(q) for q in keys}, "solve": {q: i2.get(q) for q in keys}}
+        assert i1["status"] == 0 and i2["status"] == 0, diag
+        assert np.array_equal(host(x1), host(x2)), diag
     plan.close()
 
 
