@@ -2356,6 +2356,7 @@ namespace {
 constexpr int BCPT = 2, BR = 8;          // the sweep variant for L <= 512
 constexpr int B_RED_COLS = 32;           // columns of z per reduction workgroup
 constexpr int B_RED_GROUPS = 256 / B_RED_COLS;  // partial groups per reduction workgroup
+constexpr int B_CHUNK = 16;  // batched iterations enqueued between done-flag checks
 
 // Rows per workgroup of a problem's batched sweeps, from its own row count
 // alone (so its bits do not depend on the rest of the batch): about 512
@@ -2859,7 +2860,7 @@ std::vector<IterResult> iterate_batch_tall(const std::vector<IterProblem> &pbs,
     // Chebyshev steps (Alg. 3) for every Chebyshev problem, the LSQR ones
     // parked; each problem's step index is its state's count
     auto chunk_cs = [&] {
-        for (int k = 0; k < CHUNK; ++k) {
+        for (int k = 0; k < B_CHUNK; ++k) {
             batch_cs_short_kernel<<<n, SNT, 0, st>>>(di);
             batch_gemv_kernel<<<off_gP[(size_t)n], 256, 0, st>>>(di, o_gP, n, 0);
             batch_sweep_kernel<OP_CS_TALL><<<off_sw[(size_t)n], NT, 0, st>>>(di, o_sw, n);
@@ -2870,7 +2871,7 @@ std::vector<IterResult> iterate_batch_tall(const std::vector<IterProblem> &pbs,
         LSRN_HIP(hipGetLastError());
     };
     auto chunk = [&] {
-        for (int k = 0; k < CHUNK; ++k) {
+        for (int k = 0; k < B_CHUNK; ++k) {
             batch_gemv_kernel<<<off_gP[(size_t)n], 256, 0, st>>>(di, o_gP, n, 0);
             batch_sweep_kernel<OP_LSQR_TALL><<<off_sw[(size_t)n], NT, 0, st>>>(di, o_sw, n);
             batch_reduce_kernel<<<off_red[(size_t)n], 256, 0, st>>>(di, o_red, n);
@@ -2881,7 +2882,7 @@ std::vector<IterResult> iterate_batch_tall(const std::vector<IterProblem> &pbs,
     };
     // CG on (A N)^T (A N) z = c for every problem (the refinement's inner solve)
     auto chunk_cg = [&] {
-        for (int k = 0; k < CHUNK; ++k) {
+        for (int k = 0; k < B_CHUNK; ++k) {
             batch_gemv_kernel<<<off_gP[(size_t)n], 256, 0, st>>>(di, o_gP, n, 4);
             batch_sweep_kernel<OP_NORMAL><<<off_sw[(size_t)n], NT, 0, st>>>(di, o_sw, n);
             batch_reduce_kernel<<<off_red[(size_t)n], 256, 0, st>>>(di, o_red, n);
